@@ -1,0 +1,99 @@
+"""Rate coefficients, mass-action right-hand side and Jacobian (oracle).
+
+TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
+
+State variable: fractional abundance x_i = n_i / n_H.  Dividing the paper's
+rate equation for n_i (Sec. 2) by the constant n_H turns every two-body term
+k n_a n_b into (k n_H) x_a x_b while one-body terms keep their coefficient, so
+two-body coefficients are multiplied by n_H here.
+"""
+from __future__ import annotations
+
+import numpy as np
+import scipy.sparse as sp
+
+TWO_BODY, COSMIC_RAY, PHOTO = 0, 1, 2
+
+
+def rate_coefficients(net, T, n_H, A_V, zeta, G0) -> np.ndarray:
+    """k_r for one cell.
+
+    two-body  (Sec. 2, Kooij-Arrhenius): alpha (T/300)^beta exp(-gamma/T), times n_H
+    cosmic ray (Sec. 2, direct ionisation): alpha zeta
+    photo     (App. B.1): alpha G0 exp(-gamma A_V), G0 being the UV field F_UV
+    """
+    k = np.empty(net.n_reactions)
+    for r in range(net.n_reactions):
+        a, b, g = net.alpha[r], net.beta[r], net.gamma[r]
+        t = net.rtype[r]
+        if t == TWO_BODY:
+            k[r] = a * (T / 300.0) ** b * np.exp(-g / T) * n_H
+        elif t == COSMIC_RAY:
+            k[r] = a * zeta
+        elif t == PHOTO:
+            k[r] = a * G0 * np.exp(-g * A_V)
+        else:
+            raise ValueError(f"unknown reaction type {t}")
+    return k
+
+
+def stoichiometry(net) -> sp.csr_matrix:
+    """nu (S x R): count of species i among products minus among reactants."""
+    S, R = net.n_species, net.n_reactions
+    nu = np.zeros((S, R))
+    for r in range(R):
+        for i in net.products[r]:
+            if i >= 0:
+                nu[i, r] += 1
+        for i in net.reactants[r]:
+            if i >= 0:
+                nu[i, r] -= 1
+    return sp.csr_matrix(nu)
+
+
+def reaction_rates(net, k, x) -> np.ndarray:
+    """rate_r = k_r times the product of its reactants' abundances (A + A gives x_A^2)."""
+    rate = k.copy()
+    for col in range(2):
+        idx = net.reactants[:, col]
+        has = idx >= 0
+        rate[has] = rate[has] * x[idx[has]]
+    return rate
+
+
+def rate_derivative(net, k, x) -> sp.csr_matrix:
+    """d rate_r / d x_j (R x S) for rates of mass-action form."""
+    rows, cols, vals = [], [], []
+    for r in range(net.n_reactions):
+        a, b = net.reactants[r]
+        if b < 0:
+            rows.append(r); cols.append(a); vals.append(k[r])
+        elif a == b:
+            rows.append(r); cols.append(a); vals.append(2.0 * k[r] * x[a])
+        else:
+            rows.append(r); cols.append(a); vals.append(k[r] * x[b])
+            rows.append(r); cols.append(b); vals.append(k[r] * x[a])
+    return sp.csr_matrix((vals, (rows, cols)), shape=(net.n_reactions, net.n_species))
+
+
+class Chemistry:
+    """f(x) = nu . rate(x) and J(x) = nu . d rate / dx for one cell's coefficients."""
+
+    def __init__(self, net, k):
+        self.net = net
+        self.k = np.asarray(k, dtype=float)
+        self.nu = stoichiometry(net)
+
+    def f(self, x) -> np.ndarray:
+        return self.nu @ reaction_rates(self.net, self.k, x)
+
+    def jac(self, x) -> np.ndarray:
+        return (self.nu @ rate_derivative(self.net, self.k, x)).toarray()
+
+    def df_dlogalpha(self, x) -> sp.csr_matrix:
+        """d f / d log alpha_r = nu[:, r] rate_r (S x R), since k_r is linear in alpha_r."""
+        return self.nu @ sp.diags(reaction_rates(self.net, self.k, x))
+
+
+def cell_chemistry(net, cell: dict) -> Chemistry:
+    return Chemistry(net, rate_coefficients(net, **cell))

@@ -1,0 +1,158 @@
+"""Pins for the oracle's BDF integrator (CPU only).
+
+Each pin comes from outside the oracle: backward differences of polynomials,
+implicit Euler, closed-form solutions of one-reaction systems, the matrix
+exponential of a linear network, and conservation laws.
+"""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import synth
+from oracle import bdf, chem
+from tests import tiny_nets
+
+YEAR = synth.YEAR_S
+CELL = dict(T=30.0, n_H=1e4, A_V=1.0, zeta=1.3e-17, G0=1.0)
+
+
+def _backward_differences(p, t, h, q):
+    """nabla^j p(t) on the grid t, t-h, ..., t-q*h for j = 0..q."""
+    vals = np.array([p(t - i * h) for i in range(q + 1)])
+    out = [vals[0]]
+    cur = vals
+    for _ in range(q):
+        cur = cur[:-1] - cur[1:]
+        out.append(cur[0])
+    return np.array(out)
+
+
+@pytest.mark.parametrize("q", [1, 2, 3, 4, 5])
+def test_rescale_is_regridding_of_the_interpolating_polynomial(q):
+    rng = np.random.default_rng(q)
+    coef = rng.normal(size=q + 1)
+    p = np.polynomial.Polynomial(coef)
+    t, h = 0.7, 0.13
+    for rho in (0.2, 0.5, 1.0, 1.7, 10.0):
+        D = np.zeros((bdf.MAX_ORDER + 3, 1))
+        D[: q + 1, 0] = _backward_differences(p, t, h, q)
+        bdf.rescale(D, q, rho)
+        want = _backward_differences(p, t, rho * h, q)
+        np.testing.assert_allclose(D[: q + 1, 0], want, rtol=1e-11, atol=1e-11 * np.abs(want).max())
+
+
+def test_harmonic_and_error_constants_make_bdf_exact_on_polynomials():
+    # sum_{j=1..q} (1/j) nabla^j y(t_{n+1}) = h y'(t_{n+1}) for deg y <= q is the BDF
+    # formula; gamma_q is the coefficient of the newest correction in it and
+    # E_q = 1/(q+1) is the coefficient of nabla^{q+1} y in its local error.
+    for q in range(1, 6):
+        gam = sum(1.0 / j for j in range(1, q + 1))
+        assert bdf.GAMMA[q] == pytest.approx(gam, rel=1e-15)
+        # exactness on t^q
+        h, t1 = 0.1, 1.0
+        y = lambda s: s ** q
+        dif = _backward_differences(y, t1, h, q)
+        lhs = sum(dif[j] / j for j in range(1, q + 1))
+        assert lhs == pytest.approx(h * q * t1 ** (q - 1), rel=1e-10)
+        # local error of the order-q formula on t^{q+1} is h^{q+1} (q+1)! / (q+1) ... scaled
+        y2 = lambda s: s ** (q + 1)
+        dif2 = _backward_differences(y2, t1, h, q + 1)
+        resid = sum(dif2[j] / j for j in range(1, q + 1)) - h * (q + 1) * t1 ** q
+        assert resid == pytest.approx(-bdf.ERRC[q] * dif2[q + 1], rel=1e-8)
+
+
+def test_first_step_is_implicit_euler():
+    net = tiny_nets.decay(2.0)
+    ch = chem.cell_chemistry(net, CELL)
+    k = ch.k[0]
+    res = bdf.solve(ch, np.array([1.0, 0.0]), 5.0 / k, 1e-6, 1e-20, record=True)
+    h, q, t, x = res.history[0]
+    assert q == 1
+    assert x[0] == pytest.approx(1.0 / (1.0 + h * k), rel=1e-14)
+    assert x[1] == pytest.approx(1.0 - 1.0 / (1.0 + h * k), rel=1e-12)
+
+
+def test_decay_matches_exponential():
+    net = tiny_nets.decay(2.0)
+    ch = chem.cell_chemistry(net, CELL)
+    k = ch.k[0]
+    # global relative error of x_A grows with the number of e-folds integrated
+    for kt, tol in ((0.3, 1e-8), (5.0, 1e-8), (20.0, 1e-7)):
+        res = bdf.solve(ch, np.array([1.0, 0.0]), kt / k, 1e-10, 1e-30)
+        assert res.status == bdf.OK
+        assert res.t == kt / k
+        want = np.array([np.exp(-kt), -np.expm1(-kt)])
+        np.testing.assert_allclose(res.x, want, rtol=tol)
+    # and at the production tolerance within the tolerance's reach
+    res = bdf.solve(ch, np.array([1.0, 0.0]), 5.0 / k, 1e-6, 1e-20)
+    np.testing.assert_allclose(res.x, [np.exp(-5.0), -np.expm1(-5.0)], rtol=1e-4)
+
+
+@pytest.mark.parametrize("a0,b0", [(3e-4, 1e-4), (1e-4, 1e-4), (1e-4, 5e-4)])
+def test_association_matches_closed_form(a0, b0):
+    net = tiny_nets.association(1e-9)
+    ch = chem.cell_chemistry(net, CELL)
+    kp = ch.k[0]          # already multiplied by n_H
+    t = 3.0 / (kp * max(a0, b0))
+    res = bdf.solve(ch, np.array([a0, b0, 0.0]), t, 1e-10, 1e-30)
+    d = a0 - b0
+    if d == 0:
+        a = a0 / (1 + kp * a0 * t)
+    else:
+        a = d / (1 - (b0 / a0) * np.exp(-kp * d * t))
+    want = np.array([a, a - d, a0 - a])
+    np.testing.assert_allclose(res.x, want, rtol=1e-8)
+
+
+def test_first_order_network_matches_matrix_exponential():
+    net = tiny_nets.first_order()
+    cell = dict(T=20.0, n_H=1e3, A_V=0.5, zeta=1e-16, G0=1.0)
+    ch = chem.cell_chemistry(net, cell)
+    K = ch.jac(np.zeros(net.n_species))     # constant: all reactions are one-body
+    x0 = np.zeros(net.n_species)
+    x0[net.index("H2")] = 0.5
+    x0[net.index("CO")] = 1e-4
+    t = 1e6 * YEAR
+    res = bdf.solve(ch, x0, t, 1e-10, 1e-30)
+    want = sla.expm(t * K) @ x0
+    m = want > 1e-12
+    np.testing.assert_allclose(res.x[m], want[m], rtol=1e-8)
+
+
+def test_small_network_conserves_elements_and_charge():
+    net = synth.network_for_config("small")
+    cells = synth.single_cell(net)
+    ch = chem.cell_chemistry(net, cells.cell(0))
+    res = bdf.solve(ch, cells.x0[0], cells.t_end[0], 1e-6, 1e-20, record=True)
+    assert res.status == bdf.OK
+    W = net.conservation_matrix().astype(float)
+    w0 = W @ cells.x0[0]
+    for (_h, _q, _t, x) in res.history[:: max(1, len(res.history) // 20)] + [res.history[-1]]:
+        # relative to the conserved quantity's own terms, with a rounding floor
+        # set by the whole state (the linear solves mix all species)
+        bound = 1e-12 * (np.abs(W) @ np.abs(x)) + 1e-15 * np.abs(x).sum()
+        assert np.all(np.abs(W @ x - w0) <= bound)
+
+
+def test_order_and_step_adapt_on_smooth_problem():
+    net = tiny_nets.decay(2.0)
+    ch = chem.cell_chemistry(net, CELL)
+    k = ch.k[0]
+    res = bdf.solve(ch, np.array([1.0, 0.0]), 30.0 / k, 1e-8, 1e-30, record=True)
+    orders = [q for (_h, q, _t, _x) in res.history]
+    assert max(orders) >= 4
+    assert res.stats.n_steps < 1000
+
+
+def test_status_codes():
+    net = synth.network_for_config("small")
+    cells = synth.single_cell(net)
+    ch = chem.cell_chemistry(net, cells.cell(0))
+    x0 = cells.x0[0]
+    assert bdf.solve(ch, x0, cells.t_end[0], max_steps=3).status == bdf.MAX_STEPS
+    assert bdf.solve(ch, x0, cells.t_end[0], rtol=0.0).status == bdf.BAD_INPUT
+    bad = x0.copy()
+    bad[1] = np.nan
+    assert bdf.solve(ch, bad, cells.t_end[0]).status == bdf.BAD_INPUT
+    r = bdf.solve(ch, x0, 0.0)
+    assert r.status == bdf.OK and np.array_equal(r.x, x0)

@@ -1,0 +1,150 @@
+"""Pins for the oracle's rate laws, right-hand side and Jacobian (CPU only)."""
+import numpy as np
+import pytest
+
+import synth
+from oracle import chem
+from tests import tiny_nets
+
+CELL = dict(T=50.0, n_H=1e4, A_V=2.0, zeta=1.3e-17, G0=1.0)
+
+
+def _one(rtype, alpha, beta, gamma):
+    if rtype == synth.TWO_BODY:
+        net = tiny_nets.association(alpha, beta, gamma)
+    else:
+        net = synth.make_network("one", [("A", {"C": 1, "O": 1}, 0), ("B", {"C": 1, "O": 1}, 0)],
+                                 [(rtype, ["A"], ["B"], alpha, beta, gamma)])
+    return net
+
+
+def k_of(net, **kw):
+    cell = dict(CELL)
+    cell.update(kw)
+    return chem.rate_coefficients(net, **cell)[0]
+
+
+def test_two_body_reduces_to_alpha_nH_without_temperature_terms():
+    # Sec. 2 Kooij-Arrhenius with beta = gamma = 0: the rate coefficient is alpha;
+    # in fractional-abundance units it is multiplied by n_H.
+    net = _one(synth.TWO_BODY, 3e-10, 0.0, 0.0)
+    for T in (10.0, 77.0, 300.0):
+        assert k_of(net, T=T, n_H=2e5) == pytest.approx(3e-10 * 2e5, rel=1e-15)
+
+
+def test_two_body_power_law_in_temperature():
+    # gamma = 0: log k is linear in log T with slope beta (the T/300 power law).
+    for beta in (-0.7, 0.4, 1.0):
+        net = _one(synth.TWO_BODY, 1e-10, beta, 0.0)
+        k1, k2 = k_of(net, T=20.0), k_of(net, T=180.0)
+        slope = (np.log(k2) - np.log(k1)) / (np.log(180.0) - np.log(20.0))
+        assert slope == pytest.approx(beta, abs=1e-12)
+
+
+def test_two_body_temperature_factor_is_one_at_300K():
+    a = k_of(_one(synth.TWO_BODY, 1e-10, 0.8, 0.0), T=300.0)
+    b = k_of(_one(synth.TWO_BODY, 1e-10, -0.3, 0.0), T=300.0)
+    assert a == pytest.approx(b, rel=1e-15)
+
+
+def test_two_body_arrhenius_slope_in_inverse_temperature():
+    # beta = 0: log k is linear in 1/T with slope -gamma.
+    for gamma in (5.0, 80.0, 200.0):
+        net = _one(synth.TWO_BODY, 1e-10, 0.0, gamma)
+        k1, k2 = k_of(net, T=40.0), k_of(net, T=250.0)
+        slope = (np.log(k2) - np.log(k1)) / (1 / 250.0 - 1 / 40.0)
+        assert slope == pytest.approx(-gamma, rel=1e-10)
+
+
+def test_cosmic_ray_rate_is_alpha_zeta_and_ignores_other_physics():
+    net = _one(synth.COSMIC_RAY, 2.5, 0.0, 0.0)
+    assert k_of(net, zeta=4e-16) == pytest.approx(2.5 * 4e-16, rel=1e-15)
+    base = k_of(net)
+    assert k_of(net, T=250.0, n_H=10.0, A_V=15.0, G0=3.0) == base
+
+
+def test_photo_rate_extinction_law():
+    net = _one(synth.PHOTO, 4e-10, 0.0, 2.2)
+    assert k_of(net, A_V=0.0, G0=1.0) == pytest.approx(4e-10, rel=1e-15)
+    assert k_of(net, A_V=0.0, G0=3.0) == pytest.approx(1.2e-9, rel=1e-15)
+    k1, k2 = k_of(net, A_V=1.0), k_of(net, A_V=7.0)
+    assert (np.log(k2) - np.log(k1)) / 6.0 == pytest.approx(-2.2, rel=1e-12)
+    assert k_of(net, T=250.0, n_H=10.0, zeta=1e-15) == k_of(net)
+
+
+def test_single_reaction_right_hand_sides():
+    # decay A -> B: A lost and B gained at rate k x_A
+    net = tiny_nets.decay(2.0)
+    k = chem.rate_coefficients(net, **CELL)
+    f = chem.Chemistry(net, k).f(np.array([0.3, 0.1]))
+    assert f[0] == pytest.approx(-k[0] * 0.3, rel=1e-15)
+    assert f[1] == pytest.approx(k[0] * 0.3, rel=1e-15)
+    # association A + B -> C
+    net = tiny_nets.association(1e-10)
+    k = chem.rate_coefficients(net, **CELL)
+    f = chem.Chemistry(net, k).f(np.array([0.2, 0.5, 0.0]))
+    r = k[0] * 0.2 * 0.5
+    np.testing.assert_allclose(f, [-r, -r, r], rtol=1e-15)
+    # identical reactants H + H -> H2: rate k x_H^2, H consumed twice
+    net = tiny_nets.dimer(alpha_d=0.0)
+    k = chem.rate_coefficients(net, **CELL)
+    f = chem.Chemistry(net, k).f(np.array([0.4, 0.3]))
+    r = k[0] * 0.4 * 0.4
+    np.testing.assert_allclose(f, [-2 * r, r], rtol=1e-15)
+
+
+@pytest.mark.parametrize("name", ["small", "net200", "net500"])
+def test_rhs_conserves_elements_and_charge(name):
+    net = synth.network_for_config(name)
+    W = net.conservation_matrix().astype(float)
+    rng = np.random.default_rng(3)
+    ch = chem.cell_chemistry(net, CELL)
+    nu = chem.stoichiometry(net)
+    for _ in range(3):
+        x = np.exp(rng.uniform(-30, 0, net.n_species))
+        f = ch.f(x)
+        rate = chem.reaction_rates(net, ch.k, x)
+        bound = 1e-15 * (np.abs(W) @ (abs(nu) @ rate)) + 1e-300
+        assert np.all(np.abs(W @ f) <= 4 * bound)
+
+
+@pytest.mark.parametrize("name", ["small", "net200", "net500"])
+def test_jacobian_matches_central_differences(name):
+    # f is at most quadratic in x, so central differences carry no truncation error.
+    net = synth.network_for_config(name)
+    ch = chem.cell_chemistry(net, CELL)
+    rng = np.random.default_rng(5)
+    x = np.exp(rng.uniform(-20, 0, net.n_species))
+    J = ch.jac(x)
+    absnu = abs(chem.stoichiometry(net))
+    eps = np.finfo(float).eps
+    cols = rng.choice(net.n_species, size=min(25, net.n_species), replace=False)
+    for j in cols:
+        dx = 0.1 * x[j]
+        e = np.zeros_like(x)
+        e[j] = dx
+        fp, fm = ch.f(x + e), ch.f(x - e)
+        fd = (fp - fm) / (2 * dx)
+        # rounding bound of the two sums, divided by the step
+        terms = absnu @ (chem.reaction_rates(net, ch.k, x + e) + chem.reaction_rates(net, ch.k, x - e))
+        bound = 1e-12 * np.abs(J[:, j]).max() + 8 * eps * terms / (2 * dx) + 1e-300
+        assert np.all(np.abs(fd - J[:, j]) <= bound)
+
+
+def test_df_dlogalpha_matches_finite_difference():
+    # f is linear in each k_r and d/dlog alpha_r = k_r d/dk_r, so a central
+    # difference in k_r with a finite relative step is exact up to rounding.
+    net = synth.network_for_config("small")
+    rng = np.random.default_rng(8)
+    x = np.exp(rng.uniform(-10, 0, net.n_species))
+    k = chem.rate_coefficients(net, **CELL)
+    G = chem.Chemistry(net, k).df_dlogalpha(x).toarray()
+    absnu = abs(chem.stoichiometry(net))
+    eps = np.finfo(float).eps
+    for r in rng.choice(net.n_reactions, 6, replace=False):
+        kp, km = k.copy(), k.copy()
+        kp[r] *= 1.5
+        km[r] *= 0.5
+        fd = (chem.Chemistry(net, kp).f(x) - chem.Chemistry(net, km).f(x)) / 1.0
+        terms = absnu @ (chem.reaction_rates(net, kp, x) + chem.reaction_rates(net, km, x))
+        assert np.all(np.abs(fd - G[:, r]) <= 8 * eps * terms + 1e-300)
