@@ -1,0 +1,218 @@
+"""Python binding of the astrobdf C-ABI (include/astrobdf.h).
+
+Every array argument is a torch tensor on the HIP device; this module only
+checks shapes and dtypes, passes raw pointers and the current stream, and
+raises on a non-OK status.  All arithmetic runs in the library's kernels.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib
+from ._lib import CellStats, LibraryMissing, Options  # noqa: F401
+
+PREC = {"fp64": 0, "fp32_lu": 1}
+CELL_STATUS = {0: "ok", 1: "step_too_small", 2: "max_steps", 3: "nonfinite", 4: "bad_input"}
+STATUS_NAMES = {0: "OK", 1: "E_ARG", 2: "E_PARSE", 3: "E_NONCONSERVING", 4: "E_IO", 5: "E_DEVICE",
+                6: "E_BUDGET", 7: "E_NOMEM", 8: "E_BUSY"}
+
+
+class AbdfError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{STATUS_NAMES.get(code, code)}: {msg}")
+        self.code = code
+
+
+def _check(rc):
+    if rc != 0:
+        msg = _lib.lib().abdf_last_error()
+        raise AbdfError(rc, msg.decode() if msg else "")
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream():
+    return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def _ptr(t, dtype, shape=None, name="array"):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a torch tensor on the HIP device")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError(f"{name} must have shape {tuple(shape)}, got {tuple(t.shape)}")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Network:
+    """A loaded, validated reaction network (host handle; tables reach the
+    device on first use)."""
+
+    def __init__(self, handle):
+        self._h = handle
+
+    @classmethod
+    def from_text(cls, text: str) -> "Network":
+        L = _lib.lib()
+        h = ctypes.c_void_p()
+        b = text.encode()
+        _check(L.abdf_network_load_mem(b, len(b), ctypes.byref(h)))
+        return cls(h)
+
+    @classmethod
+    def from_file(cls, path) -> "Network":
+        L = _lib.lib()
+        h = ctypes.c_void_p()
+        _check(L.abdf_network_load(str(path).encode(), ctypes.byref(h)))
+        return cls(h)
+
+    @property
+    def handle(self):
+        return self._h
+
+    @property
+    def n_species(self) -> int:
+        return _lib.lib().abdf_network_num_species(self._h)
+
+    @property
+    def n_reactions(self) -> int:
+        return _lib.lib().abdf_network_num_reactions(self._h)
+
+    @property
+    def n_elements(self) -> int:
+        return _lib.lib().abdf_network_num_elements(self._h)
+
+    def species_name(self, i: int):
+        v = _lib.lib().abdf_network_species_name(self._h, i)
+        return None if v is None else v.decode()
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            try:
+                _lib.lib().abdf_network_free(h)
+            except Exception:
+                pass
+            self._h = None
+
+
+def load_network(path_or_text) -> Network:
+    s = str(path_or_text)
+    if s.lstrip().startswith("astrobdf-network"):
+        return Network.from_text(s)
+    return Network.from_file(s)
+
+
+def default_options() -> Options:
+    o = Options()
+    _lib.lib().abdf_options_default(ctypes.byref(o))
+    return o
+
+
+def make_options(rtol=1e-6, atol=1e-20, max_steps=100000, precision="fp64", check_every=8,
+                 hbm_budget_bytes=0, newton_tol=0.0) -> Options:
+    o = default_options()
+    o.rtol, o.atol, o.max_steps = rtol, atol, max_steps
+    o.precision = PREC[precision] if isinstance(precision, str) else int(precision)
+    o.check_every, o.hbm_budget_bytes, o.newton_tol = check_every, hbm_budget_bytes, newton_tol
+    return o
+
+
+def stats_to_numpy(buf) -> np.ndarray:
+    """Device byte tensor of abdf_cell_stats -> numpy structured array."""
+    dt = np.dtype([("n_steps", "<i4"), ("n_attempts", "<i4"), ("n_err_reject", "<i4"),
+                   ("n_newton_fail", "<i4"), ("n_rhs", "<i4"), ("n_jac", "<i4"), ("n_lu", "<i4"),
+                   ("order", "<i4"), ("h", "<f8"), ("t", "<f8")])
+    return buf.cpu().numpy().view(dt)
+
+
+def solve(net: Network, T, n_H, A_V, zeta, G0, x0, t_end, *, options: Options | None = None,
+          with_stats=False, **opts):
+    """Integrates every cell to its t_end.  Returns (x_out, status[, stats])."""
+    torch = _torch()
+    C, S = x0.shape
+    f64 = torch.float64
+    args = [_ptr(v, f64, (C,), nm) for v, nm in
+            ((T, "T"), (n_H, "n_H"), (A_V, "A_V"), (zeta, "zeta"), (G0, "G0"))]
+    args.append(_ptr(x0, f64, (C, net.n_species), "x0"))
+    args.append(_ptr(t_end, f64, (C,), "t_end"))
+    o = options if options is not None else make_options(**opts)
+    x_out = torch.empty_like(x0)
+    status = torch.full((C,), -1, dtype=torch.int32, device=x0.device)
+    st = None
+    st_ptr = ctypes.c_void_p(None)
+    if with_stats:
+        st = torch.zeros((max(C, 1) * ctypes.sizeof(CellStats),), dtype=torch.uint8, device=x0.device)
+        st_ptr = ctypes.c_void_p(st.data_ptr())
+    _check(_lib.lib().abdf_solve(net.handle, C, *args, ctypes.byref(o),
+                                 ctypes.c_void_p(x_out.data_ptr()), ctypes.c_void_p(status.data_ptr()),
+                                 st_ptr, _stream()))
+    if with_stats:
+        return x_out, status, stats_to_numpy(st)[:C]
+    return x_out, status
+
+
+def rates(net: Network, T, n_H, A_V, zeta, G0):
+    torch = _torch()
+    C = T.shape[0]
+    args = [_ptr(v, torch.float64, (C,), nm) for v, nm in
+            ((T, "T"), (n_H, "n_H"), (A_V, "A_V"), (zeta, "zeta"), (G0, "G0"))]
+    k = torch.empty((C, net.n_reactions), dtype=torch.float64, device=T.device)
+    _check(_lib.lib().abdf_rates(net.handle, C, *args, ctypes.c_void_p(k.data_ptr()), _stream()))
+    return k
+
+
+def rhs(net: Network, k, x):
+    torch = _torch()
+    C = x.shape[0]
+    f = torch.empty_like(x)
+    _check(_lib.lib().abdf_rhs(net.handle, C, _ptr(k, torch.float64, (C, net.n_reactions), "k"),
+                               _ptr(x, torch.float64, (C, net.n_species), "x"),
+                               ctypes.c_void_p(f.data_ptr()), _stream()))
+    return f
+
+
+def newton_matrix(net: Network, k, x, c):
+    torch = _torch()
+    C, S = x.shape
+    M = torch.empty((C, S, S), dtype=torch.float64, device=x.device)
+    _check(_lib.lib().abdf_newton_matrix(net.handle, C, _ptr(k, torch.float64, (C, net.n_reactions), "k"),
+                                         _ptr(x, torch.float64, (C, S), "x"), _ptr(c, torch.float64, (C,), "c"),
+                                         ctypes.c_void_p(M.data_ptr()), _stream()))
+    return M
+
+
+def lu_factor(A, precision="fp64"):
+    """Batched P A = L U of A (B, n, n) FP64; returns (LU, perm, info)."""
+    torch = _torch()
+    B, n, n2 = A.shape
+    if n != n2:
+        raise ValueError("square matrices required")
+    LU = A.clone()
+    perm = torch.empty((B, n), dtype=torch.int32, device=A.device)
+    info = torch.empty((B,), dtype=torch.int32, device=A.device)
+    _check(_lib.lib().abdf_lu_factor(n, B, _ptr(LU, torch.float64, None, "A"), ctypes.c_void_p(perm.data_ptr()),
+                                     ctypes.c_void_p(info.data_ptr()), PREC[precision], _stream()))
+    return LU, perm, info
+
+
+def lu_solve(LU, perm, b):
+    torch = _torch()
+    B, n, _ = LU.shape
+    z = b.clone()
+    _check(_lib.lib().abdf_lu_solve(n, B, _ptr(LU, torch.float64, None, "LU"), _ptr(perm, torch.int32, (B, n), "perm"),
+                                    _ptr(z, torch.float64, (B, n), "b"), _stream()))
+    return z
+
+
+def selftest():
+    _check(_lib.lib().abdf_selftest(_stream()))

@@ -1,0 +1,84 @@
+"""ctypes declarations of the C-ABI in include/astrobdf.h (argument marshalling only)."""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libastrobdf.so")
+
+c_double_p = ctypes.c_void_p
+c_void_p = ctypes.c_void_p
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("rtol", ctypes.c_double),
+        ("atol", ctypes.c_double),
+        ("max_steps", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("check_every", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32),
+        ("hbm_budget_bytes", ctypes.c_uint64),
+        ("newton_tol", ctypes.c_double),
+    ]
+
+
+class CellStats(ctypes.Structure):
+    _fields_ = [
+        ("n_steps", ctypes.c_int32),
+        ("n_attempts", ctypes.c_int32),
+        ("n_err_reject", ctypes.c_int32),
+        ("n_newton_fail", ctypes.c_int32),
+        ("n_rhs", ctypes.c_int32),
+        ("n_jac", ctypes.c_int32),
+        ("n_lu", ctypes.c_int32),
+        ("order", ctypes.c_int32),
+        ("h", ctypes.c_double),
+        ("t", ctypes.c_double),
+    ]
+
+
+# name -> (restype, argtypes); mirrors include/astrobdf.h
+SIGNATURES = {
+    "abdf_options_default": (None, [ctypes.POINTER(Options)]),
+    "abdf_last_error": (ctypes.c_char_p, []),
+    "abdf_network_load": (ctypes.c_int, [ctypes.c_char_p, ctypes.POINTER(c_void_p)]),
+    "abdf_network_load_mem": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_size_t, ctypes.POINTER(c_void_p)]),
+    "abdf_network_free": (None, [c_void_p]),
+    "abdf_network_num_species": (ctypes.c_int32, [c_void_p]),
+    "abdf_network_num_reactions": (ctypes.c_int32, [c_void_p]),
+    "abdf_network_num_elements": (ctypes.c_int32, [c_void_p]),
+    "abdf_network_species_name": (ctypes.c_char_p, [c_void_p, ctypes.c_int32]),
+    "abdf_solve": (ctypes.c_int, [c_void_p, ctypes.c_int64] + [c_void_p] * 7 +
+                   [ctypes.POINTER(Options), c_void_p, c_void_p, c_void_p, c_void_p]),
+    "abdf_rates": (ctypes.c_int, [c_void_p, ctypes.c_int64] + [c_void_p] * 6 + [c_void_p]),
+    "abdf_rhs": (ctypes.c_int, [c_void_p, ctypes.c_int64, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "abdf_newton_matrix": (ctypes.c_int, [c_void_p, ctypes.c_int64, c_void_p, c_void_p, c_void_p, c_void_p,
+                                          c_void_p]),
+    "abdf_lu_factor": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, c_void_p, c_void_p, c_void_p,
+                                      ctypes.c_int32, c_void_p]),
+    "abdf_lu_solve": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, c_void_p, c_void_p, c_void_p, c_void_p]),
+    "abdf_selftest": (ctypes.c_int, [c_void_p]),
+}
+
+_LIB = None
+
+
+class LibraryMissing(RuntimeError):
+    pass
+
+
+def lib():
+    """The loaded library; raises LibraryMissing (never falls back) if it is not built."""
+    global _LIB
+    if _LIB is None:
+        if not os.path.exists(LIB_PATH):
+            raise LibraryMissing(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _LIB = L
+    return _LIB

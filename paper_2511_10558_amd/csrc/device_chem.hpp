@@ -1,0 +1,84 @@
+// Rate coefficients, right-hand side and Newton-matrix rows for one cell,
+// evaluated cooperatively by one workgroup.
+#pragma once
+
+#include "device_common.hpp"
+#include "network.hpp"
+
+namespace abdf {
+
+// k_r for one cell (paper Sec. 2 Kooij-Arrhenius and direct cosmic-ray forms,
+// App. B.1 photo form); two-body coefficients carry the factor n_H of the
+// fractional-abundance state.  Written to global memory, coalesced over r.
+__device__ inline void cell_rates(const DeviceNet &n, const double *phi, double *k) {
+    const double T = phi[0], nH = phi[1], Av = phi[2], zeta = phi[3], G0 = phi[4];
+    const double T300 = T / 300.0;
+    for (int r = threadIdx.x; r < n.R; r += kBlock) {
+        const int t = n.rx_type[r];
+        const double a = n.alpha[r];
+        double v;
+        if (t == kTwoBody) v = a * pow(T300, n.beta[r]) * exp(-n.gamma[r] / T) * nH;
+        else if (t == kCosmicRay) v = a * zeta;
+        else v = a * G0 * exp(-n.gamma[r] * Av);
+        k[r] = v;
+    }
+}
+
+// f = nu . rate(x) for one cell.  x in LDS; k in global memory (one coalesced
+// pass); rate[R] and part[n_seg] are LDS scratch; f may be LDS or global.
+// Deterministic: every sum runs in a fixed order.
+__device__ inline void cell_rhs(const DeviceNet &n, const double *__restrict__ k, const double *x,
+                                double *rate, double *part, double *f) {
+    for (int r = threadIdx.x; r < n.R; r += kBlock) {
+        const int ab = n.rx_ab[r];
+        const int a = ab & 0xffff, b = (ab >> 16) & 0xffff;
+        double v = k[r] * x[a];
+        if (b != 0xffff) v *= x[b];
+        rate[r] = v;
+    }
+    __syncthreads();
+    for (int s = threadIdx.x; s < n.n_seg; s += kBlock) {
+        const int e0 = n.seg_beg[s], e1 = n.seg_beg[s + 1];
+        double acc = 0.0;
+        for (int e = e0; e < e1; ++e) {
+            const int w = n.f_ent[e];
+            acc += double((w & 7) - 4) * rate[w >> 3];
+        }
+        part[s] = acc;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n.S; i += kBlock) {
+        double acc = 0.0;
+        for (int s = n.seg_ptr[i]; s < n.seg_ptr[i + 1]; ++s) acc += part[s];
+        f[i] = acc;
+    }
+    __syncthreads();
+}
+
+// One row i of M = I - c J(x) into rowbuf[NP] (LDS, owned by the calling wave),
+// then to the matrix row in global memory as T.  Rows i >= S are identity.
+template <typename T>
+__device__ inline void newton_matrix_row(const DeviceNet &n, const double *__restrict__ k, const double *x,
+                                         double c, int i, double *rowbuf, T *Mrow) {
+    const int lane = threadIdx.x & 63;
+    for (int j = lane; j < n.NP; j += 64) rowbuf[j] = 0.0;
+    __builtin_amdgcn_wave_barrier();
+    if (i < n.S) {
+        for (int e = n.jrow_ptr[i] + lane; e < n.jrow_ptr[i + 1]; e += 64) {
+            double v = 0.0;
+            for (int t = n.jterm_ptr[e]; t < n.jterm_ptr[e + 1]; ++t) {
+                const int w = n.jt_rx_other[t];
+                const int other = (w & 0xffff) - 1;
+                double term = n.jt_coef[t] * k[w >> 16];
+                if (other >= 0) term *= x[other];
+                v += term;
+            }
+            rowbuf[n.jcol[e]] = -c * v;
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    for (int j = lane; j < n.NP; j += 64) Mrow[j] = T((j == i ? 1.0 : 0.0) + rowbuf[j]);
+    __builtin_amdgcn_wave_barrier();
+}
+
+}  // namespace abdf

@@ -1,0 +1,70 @@
+// Device-side constants, per-slot state and block-wide reductions (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace abdf {
+
+constexpr int kBlock = 256;          // threads per workgroup in every per-cell kernel
+constexpr int kWaves = kBlock / 64;
+constexpr int kMaxOrder = 5;
+constexpr int kDRows = kMaxOrder + 3;  // difference rows 0..q+2 at q = 5
+constexpr int kNewtonMaxIter = 4;
+constexpr double kURound = 2.220446049250313e-16;  // 2^-52
+constexpr double kMinFactor = 0.2;
+constexpr double kMaxFactor = 10.0;
+
+// status values: >= 0 are the public ABDF_CELL_* codes
+constexpr int32_t kRunning = -1;
+
+// Newton phase of the current step attempt
+constexpr int32_t kIter = 0;
+constexpr int32_t kConverged = 1;
+constexpr int32_t kFailed = 2;
+
+struct SlotCtl {
+    double t, h, t_end, c, c_lu, eta_old, rtol, atol, newton_tol, err;
+    int32_t q, n_equal, status, phase, j_fresh, jac_refresh, landing, newton_iter;
+    int32_t lu_valid, cell, m_last, pad;
+    int32_t n_steps, n_attempts, n_err_reject, n_newton_fail, n_rhs, n_jac, n_lu, n_newton_iter;
+};
+
+// Device workspace for n slots of one network (all arrays slot-major).
+struct Slots {
+    int nslots, S, R, NP, prec, max_steps;
+    SlotCtl *ctl;
+    double *phi;      // [n][5]: T, n_H, A_V, zeta, G0
+    double *k;        // [n][R]
+    double *D;        // [n][kDRows][S]
+    double *x;        // [n][S] Newton iterate
+    double *d;        // [n][S] accumulated correction
+    double *psi;      // [n][S]
+    double *scl;      // [n][S] Newton weights atol + rtol |x_p|
+    double *xJ;       // [n][S] point of the current Jacobian
+    void *lu;         // [n][NP][NP] factors (double or float)
+    int32_t *perm;    // [n][NP]
+    int32_t *act;     // [3][n] active-slot lists (ring)
+    int32_t *lul;     // [3][n] slots needing a factorisation (ring)
+    int32_t *fin;     // [n] finished slots since the last harvest
+    int32_t *cnt;     // [0..2] active counts, [3..5] factor counts, [6] finished count
+};
+
+// Sum over the workgroup, identical on every thread; fixed reduction order.
+__device__ inline double block_sum(double v, double *red) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    for (int w = 0; w < kWaves; ++w) s += red[w];
+    return s;
+}
+
+// Logical OR over the workgroup.
+__device__ inline bool block_any(bool p, double *red) {
+    return block_sum(p ? 1.0 : 0.0, red) != 0.0;
+}
+
+}  // namespace abdf

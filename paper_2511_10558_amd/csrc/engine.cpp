@@ -1,0 +1,200 @@
+// Host orchestration: slot pool, admission, the step-attempt loop and harvest.
+//
+// Every loop iteration performs one step attempt for every running slot:
+//   k_factor   (slots whose Newton matrix is stale)
+//   k_newton   x 4 (slots still iterating)
+//   k_control  (accept / reject / order selection, next attempt queued)
+// The slot lists are compacted on the device every attempt.  The host reads
+// the running and finished counts back every `check_every` attempts, copies
+// finished results out, and refills freed slots with pending cells.
+#include "engine.hpp"
+
+#include <cstring>
+#include <cmath>
+
+#include "../../include/astrobdf.h"
+
+namespace abdf {
+
+namespace {
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+#define HIP_TRY(expr)                                                           \
+    do {                                                                        \
+        hipError_t e__ = (expr);                                                \
+        if (e__ != hipSuccess) {                                                \
+            err = std::string(#expr ": ") + hipGetErrorString(e__);            \
+            return ABDF_E_DEVICE;                                               \
+        }                                                                       \
+    } while (0)
+}  // namespace
+
+Engine::Engine(const HostNetwork &net, const DeviceNet &dn, int prec, int max_steps)
+    : net_(net), dn_(dn), prec_(prec), max_steps_(max_steps) {}
+
+Engine::~Engine() {
+    if (base_) (void)hipFree(base_);
+    if (h_cnt_) (void)hipHostFree(h_cnt_);
+    if (h_fin_) (void)hipHostFree(h_fin_);
+    if (h_admit_slots_) (void)hipHostFree(h_admit_slots_);
+    if (h_admit_cells_) (void)hipHostFree(h_admit_cells_);
+}
+
+size_t Engine::bytes_per_slot(const DeviceNet &dn, int prec) {
+    const size_t S = dn.S, R = dn.R, NP = dn.NP;
+    const size_t elt = prec == ABDF_PREC_FP32_LU ? sizeof(float) : sizeof(double);
+    return sizeof(SlotCtl) + 5 * sizeof(double) + R * sizeof(double) + kDRows * S * sizeof(double) +
+           5 * S * sizeof(double) + NP * NP * elt + NP * sizeof(int32_t) + 7 * sizeof(int32_t) +
+           sizeof(long long);
+}
+
+int Engine::init(int nslots, std::string &err) {
+    const size_t n = size_t(nslots), S = dn_.S, R = dn_.R, NP = dn_.NP;
+    const size_t elt = prec_ == ABDF_PREC_FP32_LU ? sizeof(float) : sizeof(double);
+    struct Part { void **dst; size_t bytes; };
+    void *ctl, *phi, *k, *D, *x, *d, *psi, *scl, *xJ, *lu, *perm, *act, *lul, *fin, *cnt, *aslots, *acells;
+    Part parts[] = {
+        {&ctl, n * sizeof(SlotCtl)}, {&phi, n * 5 * sizeof(double)}, {&k, n * R * sizeof(double)},
+        {&D, n * kDRows * S * sizeof(double)}, {&x, n * S * sizeof(double)}, {&d, n * S * sizeof(double)},
+        {&psi, n * S * sizeof(double)}, {&scl, n * S * sizeof(double)}, {&xJ, n * S * sizeof(double)},
+        {&lu, n * NP * NP * elt}, {&perm, n * NP * sizeof(int32_t)}, {&act, 3 * n * sizeof(int32_t)},
+        {&lul, 3 * n * sizeof(int32_t)}, {&fin, n * sizeof(int32_t)}, {&cnt, 8 * sizeof(int32_t)},
+        {&aslots, n * sizeof(int32_t)}, {&acells, n * sizeof(long long)},
+    };
+    size_t total = 0;
+    for (auto &p : parts) total += align256(p.bytes);
+    hipError_t e = hipMalloc(&base_, total);
+    if (e != hipSuccess) {
+        base_ = nullptr;
+        err = "device workspace of " + std::to_string(total) + " bytes: " + hipGetErrorString(e);
+        return ABDF_E_NOMEM;
+    }
+    size_t off = 0;
+    for (auto &p : parts) {
+        *p.dst = static_cast<char *>(base_) + off;
+        off += align256(p.bytes);
+    }
+    HIP_TRY(hipMemset(cnt, 0, 8 * sizeof(int32_t)));
+    s_.nslots = nslots;
+    s_.S = dn_.S;
+    s_.R = dn_.R;
+    s_.NP = dn_.NP;
+    s_.prec = prec_;
+    s_.max_steps = max_steps_;
+    s_.ctl = static_cast<SlotCtl *>(ctl);
+    s_.phi = static_cast<double *>(phi);
+    s_.k = static_cast<double *>(k);
+    s_.D = static_cast<double *>(D);
+    s_.x = static_cast<double *>(x);
+    s_.d = static_cast<double *>(d);
+    s_.psi = static_cast<double *>(psi);
+    s_.scl = static_cast<double *>(scl);
+    s_.xJ = static_cast<double *>(xJ);
+    s_.lu = lu;
+    s_.perm = static_cast<int32_t *>(perm);
+    s_.act = static_cast<int32_t *>(act);
+    s_.lul = static_cast<int32_t *>(lul);
+    s_.fin = static_cast<int32_t *>(fin);
+    s_.cnt = static_cast<int32_t *>(cnt);
+    d_admit_slots_ = static_cast<int32_t *>(aslots);
+    d_admit_cells_ = static_cast<long long *>(acells);
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&h_cnt_), 8 * sizeof(int32_t), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&h_fin_), n * sizeof(int32_t), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&h_admit_slots_), n * sizeof(int32_t), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&h_admit_cells_), n * sizeof(long long), hipHostMallocDefault));
+    lds_admit_ = admit_lds(dn_);
+    lds_factor_ = factor_lds(dn_, prec_);
+    lds_newton_ = newton_lds(dn_);
+    if (lds_admit_ > kMaxLds || lds_factor_ > kMaxLds || lds_newton_ > kMaxLds) {
+        err = "network too large for one workgroup's LDS";
+        return ABDF_E_ARG;
+    }
+    free_.clear();
+    for (int i = nslots - 1; i >= 0; --i) free_.push_back(i);
+    return ABDF_OK;
+}
+
+int Engine::admit(const BatchIO &io, const abdf_options &opt, long long &next, hipStream_t st, std::string &err) {
+    const long long want = std::min<long long>(static_cast<long long>(free_.size()), io.n_cells - next);
+    if (want <= 0) return ABDF_OK;
+    for (long long i = 0; i < want; ++i) {
+        h_admit_slots_[i] = free_.back();
+        free_.pop_back();
+        h_admit_cells_[i] = next + i;
+    }
+    HIP_TRY(hipMemcpyAsync(d_admit_slots_, h_admit_slots_, want * sizeof(int32_t), hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemcpyAsync(d_admit_cells_, h_admit_cells_, want * sizeof(long long), hipMemcpyHostToDevice, st));
+    AdmitArgs a;
+    a.count = int(want);
+    a.slots = d_admit_slots_;
+    a.cells = d_admit_cells_;
+    a.T = io.T;
+    a.nH = io.nH;
+    a.Av = io.Av;
+    a.zeta = io.zeta;
+    a.G0 = io.G0;
+    a.x0 = io.x0;
+    a.t_end = io.t_end;
+    a.rtol = opt.rtol;
+    a.atol = opt.atol;
+    a.newton_tol = opt.newton_tol > 0 ? opt.newton_tol
+                                      : std::max(10.0 * kURound / opt.rtol, std::min(0.03, std::sqrt(opt.rtol)));
+    HIP_TRY(launch_admit(s_, dn_, a, ring_, lds_admit_, st));
+    // the pinned admission buffers are rewritten only after the next poll's synchronisation
+    next += want;
+    bound_ += int(want);
+    return ABDF_OK;
+}
+
+int Engine::poll(hipStream_t st, std::string &err) {
+    HIP_TRY(hipMemcpyAsync(h_cnt_, s_.cnt, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const int nfin = h_cnt_[6];
+    bound_ = h_cnt_[ring_];
+    if (nfin > 0) {
+        HIP_TRY(hipMemcpyAsync(h_fin_, s_.fin, nfin * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HarvestArgs h;
+        h.count = nfin;
+        h.slots = s_.fin;
+        h.x_out = io_->x_out;
+        h.status = io_->status;
+        h.stats = io_->stats;
+        HIP_TRY(launch_harvest(s_, h, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        for (int i = 0; i < nfin; ++i) free_.push_back(h_fin_[i]);
+    }
+    return ABDF_OK;
+}
+
+int Engine::solve(const BatchIO &io, const abdf_options &opt, hipStream_t st, std::string &err) {
+    io_ = &io;
+    ring_ = 0;
+    bound_ = 0;
+    long long next = 0;
+    const int check_every = std::max(1, opt.check_every);
+    int rc = admit(io, opt, next, st, err);
+    if (rc != ABDF_OK) return rc;
+    int since_poll = 0;
+    while (true) {
+        if (bound_ > 0) {
+            HIP_TRY(launch_factor(s_, dn_, ring_, bound_, lds_factor_, st));
+            for (int m = 0; m < kNewtonMaxIter; ++m) HIP_TRY(launch_newton(s_, dn_, ring_, bound_, lds_newton_, st));
+            HIP_TRY(launch_control(s_, ring_, bound_, st));
+            ring_ = (ring_ + 1) % 3;
+            ++since_poll;
+        }
+        if (bound_ == 0 || since_poll >= check_every) {
+            since_poll = 0;
+            rc = poll(st, err);
+            if (rc != ABDF_OK) return rc;
+            rc = admit(io, opt, next, st, err);
+            if (rc != ABDF_OK) return rc;
+            if (bound_ == 0 && next >= io.n_cells) break;
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    io_ = nullptr;
+    return ABDF_OK;
+}
+
+}  // namespace abdf

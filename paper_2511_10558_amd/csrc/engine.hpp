@@ -1,0 +1,64 @@
+// Host orchestration of the batched BDF solver.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "kernels.hpp"
+#include "network.hpp"
+
+struct abdf_options;
+struct abdf_cell_stats;
+
+namespace abdf {
+
+// Device inputs/outputs of one batch solve (caller-owned device pointers).
+struct BatchIO {
+    long long n_cells;
+    const double *T, *nH, *Av, *zeta, *G0, *x0, *t_end;
+    double *x_out;
+    int32_t *status;
+    abdf_cell_stats *stats;
+};
+
+// A pool of device slots for one network.  Cells are admitted into free
+// slots, integrated by the step-attempt loop, and harvested when finished;
+// freed slots are refilled from the pending cells (continuous batching).
+class Engine {
+  public:
+    Engine(const HostNetwork &net, const DeviceNet &dn, int prec, int max_steps);
+    ~Engine();
+    // Allocates room for up to `nslots` slots; returns an abdf_status.
+    int init(int nslots, std::string &err);
+    // Bytes of device workspace per slot.
+    static size_t bytes_per_slot(const DeviceNet &dn, int prec);
+    // Solves every cell of io; returns an abdf_status.
+    int solve(const BatchIO &io, const abdf_options &opt, hipStream_t st, std::string &err);
+
+  private:
+    int poll(hipStream_t st, std::string &err);
+    int admit(const BatchIO &io, const abdf_options &opt, long long &next, hipStream_t st, std::string &err);
+
+    const HostNetwork &net_;
+    const DeviceNet &dn_;
+    int prec_, max_steps_;
+    Slots s_{};
+    void *base_ = nullptr;
+    int32_t *d_admit_slots_ = nullptr;
+    long long *d_admit_cells_ = nullptr;
+    int32_t *h_cnt_ = nullptr;          // pinned [8]
+    int32_t *h_fin_ = nullptr;          // pinned [nslots]
+    int32_t *h_admit_slots_ = nullptr;  // pinned [nslots]
+    long long *h_admit_cells_ = nullptr;
+    std::vector<int32_t> free_;
+    int ring_ = 0;
+    int bound_ = 0;
+    size_t lds_admit_ = 0, lds_factor_ = 0, lds_newton_ = 0;
+    // harvest target of the current solve
+    const BatchIO *io_ = nullptr;
+};
+
+}  // namespace abdf

@@ -1,0 +1,732 @@
+// Device kernels of the batched BDF solver and the component entry points.
+//
+// One workgroup handles one cell (slot) in every per-cell kernel; vectors are
+// slot-major so a workgroup's loads over species or reactions are coalesced.
+//
+// Integrator: variable-order, variable-step BDF in backward-difference form
+// (quasi-constant step size, orders 1..5; the BDF family of paper Sec. 1 in
+// the formulation of Shampine & Reichelt 1997, Sec. 2.1-2.3, kappa = 0).
+// Per step attempt of a cell:
+//   begin   clamp h to land on t_end, predictor x_p = sum_{j<=q} D_j,
+//           psi = sum_{j=1..q} gamma_j D_j / gamma_q, c = h / gamma_q,
+//           request a factorisation of M = I - c J when c changed
+//   factor  form M from J at x_J and factor it (k_factor)
+//   newton  <= 4 modified-Newton iterations d <- d + M^{-1}(c f(x) - psi - d)
+//   control error test ||d / (q+1)|| <= 1, accept (update differences) or
+//           reject (shrink h), order/step selection every q+1 equal steps,
+//           Jacobian refresh or h halving on corrector failure.
+#include "kernels.hpp"
+
+#include "device_chem.hpp"
+#include "device_common.hpp"
+#include "device_lu.hpp"
+
+#include "../../include/astrobdf.h"
+
+namespace abdf {
+
+// ------------------------------------------------------------ BDF helpers --
+
+__device__ inline double bdf_gamma(int q) {
+    double g = 0.0;
+    for (int j = 1; j <= q; ++j) g += 1.0 / j;
+    return g;
+}
+
+__device__ inline double growth(double err, int p) {
+    if (err == 0.0) return INFINITY;
+    if (!isfinite(err)) return 0.0;
+    return pow(err, -1.0 / p);
+}
+
+// RU = R(rho) R(1) with R(rho)[i][j] = prod_{m=1..i} (m - 1 - rho j) / m, i, j in 0..q.
+__device__ inline void interp_product(int q, double rho, double *RU) {
+    double Rr[6][6], R1[6][6];
+    for (int j = 0; j <= q; ++j) { Rr[0][j] = 1.0; R1[0][j] = 1.0; }
+    for (int i = 1; i <= q; ++i)
+        for (int j = 0; j <= q; ++j) {
+            Rr[i][j] = Rr[i - 1][j] * (i - 1 - rho * j) / i;
+            R1[i][j] = R1[i - 1][j] * (i - 1 - 1.0 * j) / i;
+        }
+    for (int i = 0; i <= q; ++i)
+        for (int j = 0; j <= q; ++j) {
+            double s = 0.0;
+            for (int m = 0; m <= q; ++m) s += Rr[i][m] * R1[m][j];
+            RU[i * 6 + j] = s;
+        }
+}
+
+// Rows 0..q of D (one slot) from spacing h to rho*h.  Cooperative.
+__device__ inline void rescale_D(double *D, int S, int q, double rho, double *RU) {
+    if (threadIdx.x == 0) interp_product(q, rho, RU);
+    __syncthreads();
+    for (int i = threadIdx.x; i < S; i += kBlock) {
+        double v[kMaxOrder + 1], w[kMaxOrder + 1];
+        for (int j = 0; j <= q; ++j) v[j] = D[j * S + i];
+        for (int a = 0; a <= q; ++a) {
+            double s = 0.0;
+            for (int b = 0; b <= q; ++b) s += RU[b * 6 + a] * v[b];
+            w[a] = s;
+        }
+        for (int j = 0; j <= q; ++j) D[j * S + i] = w[j];
+    }
+    __syncthreads();
+}
+
+__device__ inline void finish_slot(const Slots &s, int slot, SlotCtl &cs, int status) {
+    if (threadIdx.x == 0) {
+        cs.status = status;
+        const int p = atomicAdd(&s.cnt[6], 1);
+        s.fin[p] = slot;
+    }
+}
+
+// Starts the next step attempt of a running slot whose cs (LDS) is current:
+// checks limits, lands on t_end, forms the predictor and queues the slot.
+// Writes cs back to global memory.
+__device__ void begin_attempt(const Slots &s, int slot, SlotCtl &cs, int ring, double *RU, double *sh) {
+    const int S = s.S;
+    double *D = s.D + size_t(slot) * kDRows * S;
+    if (threadIdx.x == 0) {
+        int st = kRunning;
+        double rho = 0.0;
+        if (cs.n_attempts >= s.max_steps) {
+            st = ABDF_CELL_MAX_STEPS;
+        } else {
+            cs.n_attempts += 1;
+            if (cs.h < 10.0 * kURound * fabs(cs.t)) {
+                st = ABDF_CELL_STEP_TOO_SMALL;
+            } else {
+                cs.landing = 0;
+                if (cs.t + cs.h >= cs.t_end) {
+                    if (cs.t + cs.h > cs.t_end) {
+                        rho = (cs.t_end - cs.t) / cs.h;
+                        cs.h = cs.t_end - cs.t;
+                        cs.n_equal = 0;
+                    }
+                    cs.landing = 1;
+                }
+            }
+        }
+        cs.status = st;
+        sh[0] = rho;
+    }
+    __syncthreads();
+    if (cs.status != kRunning) {
+        finish_slot(s, slot, cs, cs.status);
+        __syncthreads();
+        if (threadIdx.x == 0) s.ctl[slot] = cs;
+        return;
+    }
+    const int q = cs.q;
+    if (sh[0] != 0.0) rescale_D(D, S, q, sh[0], RU);
+    const double gq = bdf_gamma(q);
+    double gam[kMaxOrder + 1];
+    for (int j = 1; j <= q; ++j) gam[j] = bdf_gamma(j);
+    const bool refresh = cs.jac_refresh != 0;
+    double *x = s.x + size_t(slot) * S, *d = s.d + size_t(slot) * S, *psi = s.psi + size_t(slot) * S;
+    double *scl = s.scl + size_t(slot) * S, *xJ = s.xJ + size_t(slot) * S;
+    for (int i = threadIdx.x; i < S; i += kBlock) {
+        double xp = D[i];
+        for (int j = 1; j <= q; ++j) xp = xp + D[j * S + i];
+        double ps = 0.0;
+        for (int j = 1; j <= q; ++j) ps = ps + gam[j] * D[j * S + i];
+        ps = ps / gq;
+        x[i] = xp;
+        d[i] = 0.0;
+        psi[i] = ps;
+        scl[i] = cs.atol + cs.rtol * fabs(xp);
+        if (refresh) xJ[i] = xp;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        if (refresh) { cs.jac_refresh = 0; cs.lu_valid = 0; }
+        cs.c = cs.h / gq;
+        cs.phase = kIter;
+        cs.newton_iter = 0;
+        cs.eta_old = 0.0;
+        const int p = atomicAdd(&s.cnt[ring], 1);
+        s.act[ring * s.nslots + p] = slot;
+        if (!cs.lu_valid || cs.c != cs.c_lu) {
+            const int pl = atomicAdd(&s.cnt[3 + ring], 1);
+            s.lul[ring * s.nslots + pl] = slot;
+        }
+        s.ctl[slot] = cs;
+    }
+}
+
+// --------------------------------------------------------------- kernels --
+
+// Admits cells into slots: copies inputs, rates, starting step, difference
+// table, then the first attempt.  One workgroup per (slot, cell) pair.
+__global__ void __launch_bounds__(kBlock) k_admit(Slots s, DeviceNet n, AdmitArgs a, int ring) {
+    extern __shared__ double smem[];
+    __shared__ SlotCtl cs;
+    __shared__ double RU[36], red[kWaves], sh[2];
+    const int idx = blockIdx.x;
+    if (idx >= a.count) return;
+    const int slot = a.slots[idx];
+    const long long cell = a.cells[idx];
+    const int S = s.S;
+    double *xs = smem;
+    double *f0 = xs + S;
+    double *rate = f0 + S;
+    double *part = rate + n.R;
+    double *f1 = part + n.n_seg;
+    double *phi = s.phi + size_t(slot) * 5;
+    double *k = s.k + size_t(slot) * n.R;
+    double *D = s.D + size_t(slot) * kDRows * S;
+    if (threadIdx.x == 0) {
+        phi[0] = a.T[cell]; phi[1] = a.nH[cell]; phi[2] = a.Av[cell]; phi[3] = a.zeta[cell]; phi[4] = a.G0[cell];
+        SlotCtl z = {};
+        z.t = 0.0;
+        z.t_end = a.t_end[cell];
+        z.rtol = a.rtol;
+        z.atol = a.atol;
+        z.newton_tol = a.newton_tol;
+        z.q = 1;
+        z.status = kRunning;
+        z.j_fresh = 1;
+        z.lu_valid = 0;
+        z.cell = int32_t(cell);
+        cs = z;
+    }
+    bool bad = false;
+    for (int i = threadIdx.x; i < S; i += kBlock) {
+        const double v = a.x0[size_t(cell) * S + i];
+        xs[i] = v;
+        D[i] = v;
+        for (int j = 1; j < kDRows; ++j) D[j * S + i] = 0.0;
+        s.xJ[size_t(slot) * S + i] = v;
+        bad |= !isfinite(v);
+    }
+    __syncthreads();
+    const double T = phi[0], nH = phi[1], Av = phi[2], zeta = phi[3], G0 = phi[4];
+    bad |= !(isfinite(T) && T > 0.0 && isfinite(nH) && nH > 0.0 && isfinite(Av) && isfinite(zeta) &&
+             zeta >= 0.0 && isfinite(G0) && G0 >= 0.0 && isfinite(cs.t_end) && cs.t_end >= 0.0);
+    bad = block_any(bad, red);
+    if (bad) {
+        finish_slot(s, slot, cs, ABDF_CELL_BAD_INPUT);
+        __syncthreads();
+        if (threadIdx.x == 0) s.ctl[slot] = cs;
+        return;
+    }
+    cell_rates(n, phi, k);
+    __syncthreads();
+    if (cs.t_end == 0.0) {
+        finish_slot(s, slot, cs, ABDF_CELL_OK);
+        __syncthreads();
+        if (threadIdx.x == 0) s.ctl[slot] = cs;
+        return;
+    }
+    // starting step (Hairer, Norsett & Wanner, Solving ODEs I, Sec. II.4), order 1
+    cell_rhs(n, k, xs, rate, part, f0);
+    const double rtol = cs.rtol, atol = cs.atol;
+    double s0 = 0.0, s1 = 0.0;
+    for (int i = threadIdx.x; i < S; i += kBlock) {
+        const double sc = atol + rtol * fabs(xs[i]);
+        s0 += (xs[i] / sc) * (xs[i] / sc);
+        s1 += (f0[i] / sc) * (f0[i] / sc);
+    }
+    const double d0 = sqrt(block_sum(s0, red) / S);
+    const double d1 = sqrt(block_sum(s1, red) / S);
+    double h0 = (d0 < 1e-5 || d1 < 1e-5) ? 1e-6 : 0.01 * d0 / d1;
+    h0 = fmin(h0, cs.t_end);
+    // x1 = x0 + h0 f0 (kept in f1 as scratch, then f1 = f(x1))
+    double *x1 = f1 + S;
+    for (int i = threadIdx.x; i < S; i += kBlock) x1[i] = xs[i] + h0 * f0[i];
+    __syncthreads();
+    cell_rhs(n, k, x1, rate, part, f1);
+    double s2 = 0.0;
+    for (int i = threadIdx.x; i < S; i += kBlock) {
+        const double sc = atol + rtol * fabs(xs[i]);
+        const double v = (f1[i] - f0[i]) / sc;
+        s2 += v * v;
+    }
+    const double d2 = sqrt(block_sum(s2, red) / S) / h0;
+    const double mx = fmax(d1, d2);
+    const double h1 = mx <= 1e-15 ? fmax(1e-6, h0 * 1e-3) : sqrt(0.01 / mx);
+    const double h = fmin(fmin(100.0 * h0, h1), cs.t_end);
+    for (int i = threadIdx.x; i < S; i += kBlock) D[S + i] = h * f0[i];
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        cs.h = h;
+        cs.n_rhs = 2;
+        cs.n_jac = 1;
+    }
+    __syncthreads();
+    begin_attempt(s, slot, cs, ring, RU, sh);
+}
+
+// Forms M = I - c J(x_J) for every queued slot and factors it.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_factor(Slots s, DeviceNet n, int ring) {
+    extern __shared__ double smem[];
+    const int idx = blockIdx.x;
+    if (idx >= s.cnt[3 + ring]) return;
+    const int slot = s.lul[ring * s.nslots + idx];
+    const int S = s.S, NP = s.NP;
+    const double c = s.ctl[slot].c;
+    double *xs = smem;
+    double *rowbuf = xs + S;
+    const double *k = s.k + size_t(slot) * n.R;
+    for (int i = threadIdx.x; i < S; i += kBlock) xs[i] = s.xJ[size_t(slot) * S + i];
+    __syncthreads();
+    T *A = reinterpret_cast<T *>(s.lu) + size_t(slot) * NP * NP;
+    const int wave = threadIdx.x >> 6;
+    for (int i = wave; i < NP; i += kWaves) newton_matrix_row<T>(n, k, xs, c, i, rowbuf + wave * NP, A + size_t(i) * NP);
+    __syncthreads();
+    lu_factor_wg<T>(A, NP, s.perm + size_t(slot) * NP, nullptr, reinterpret_cast<unsigned char *>(smem));
+    if (threadIdx.x == 0) {
+        s.ctl[slot].c_lu = c;
+        s.ctl[slot].lu_valid = 1;
+        s.ctl[slot].n_lu += 1;
+    }
+}
+
+// One modified-Newton iteration for every active slot still iterating.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_newton(Slots s, DeviceNet n, int ring) {
+    extern __shared__ double smem[];
+    __shared__ double red[16 + kWaves];
+    __shared__ int decision;
+    const int idx = blockIdx.x;
+    if (idx >= s.cnt[ring]) return;
+    const int slot = s.act[ring * s.nslots + idx];
+    if (s.ctl[slot].phase != kIter) return;
+    const int S = s.S, NP = s.NP;
+    double *xs = smem;
+    double *rate = xs + S;
+    double *part = rate + n.R;
+    double *b = part + n.n_seg;
+    double *y = b + NP;
+    double *x = s.x + size_t(slot) * S, *d = s.d + size_t(slot) * S;
+    const double *psi = s.psi + size_t(slot) * S, *scl = s.scl + size_t(slot) * S;
+    const double c = s.ctl[slot].c;
+    for (int i = threadIdx.x; i < S; i += kBlock) xs[i] = x[i];
+    __syncthreads();
+    cell_rhs(n, s.k + size_t(slot) * n.R, xs, rate, part, b);
+    bool nonfinite = false;
+    for (int i = threadIdx.x; i < NP; i += kBlock) {
+        if (i < S) {
+            nonfinite |= !isfinite(b[i]);
+            b[i] = c * b[i] - psi[i] - d[i];
+        } else {
+            b[i] = 0.0;
+        }
+    }
+    nonfinite = block_any(nonfinite, red + 16);
+    SlotCtl &g = s.ctl[slot];
+    if (nonfinite) {
+        if (threadIdx.x == 0) {
+            g.n_rhs += 1;
+            g.n_newton_iter += 1;
+            g.newton_iter += 1;
+            g.m_last = g.newton_iter;
+            g.phase = kFailed;
+        }
+        return;
+    }
+    lu_solve_wg<T>(reinterpret_cast<const T *>(s.lu) + size_t(slot) * NP * NP, s.perm + size_t(slot) * NP, NP, b,
+                   y, red);
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < S; i += kBlock) {
+        const double v = y[i] / scl[i];
+        acc += v * v;
+    }
+    const double eta = sqrt(block_sum(acc, red + 16) / S);
+    if (threadIdx.x == 0) {
+        const int m = g.newton_iter + 1;
+        const double tol = g.newton_tol;
+        bool fail = false, conv = false;
+        double theta = -1.0;
+        if (m > 1) {
+            theta = eta / g.eta_old;
+            fail = theta >= 1.0 || pow(theta, double(kNewtonMaxIter - m)) / (1.0 - theta) * eta > tol;
+        }
+        if (!fail) conv = eta == 0.0 || (m > 1 && theta / (1.0 - theta) * eta < tol);
+        if (!fail && !conv && m == kNewtonMaxIter) fail = true;
+        g.n_rhs += 1;
+        g.n_newton_iter += 1;
+        g.newton_iter = m;
+        g.m_last = m;
+        g.eta_old = eta;
+        decision = fail ? kFailed : (conv ? kConverged : kIter);
+        g.phase = decision;
+    }
+    __syncthreads();
+    // a failed attempt discards x and d, so they are only updated otherwise
+    if (decision != kFailed) {
+        for (int i = threadIdx.x; i < S; i += kBlock) {
+            x[i] = xs[i] + y[i];
+            d[i] = d[i] + y[i];
+        }
+    }
+}
+
+// Acts on the outcome of every active slot's attempt and starts its next one.
+__global__ void __launch_bounds__(kBlock) k_control(Slots s, int ring) {
+    __shared__ SlotCtl cs;
+    __shared__ double RU[36], red[kWaves], sh[4];
+    const int next = (ring + 1) % 3;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const int old = (ring + 2) % 3;
+        s.cnt[old] = 0;
+        s.cnt[3 + old] = 0;
+    }
+    const int idx = blockIdx.x;
+    if (idx >= s.cnt[ring]) return;
+    const int slot = s.act[ring * s.nslots + idx];
+    const int S = s.S;
+    if (threadIdx.x == 0) cs = s.ctl[slot];
+    __syncthreads();
+    double *D = s.D + size_t(slot) * kDRows * S;
+    const double *x = s.x + size_t(slot) * S, *d = s.d + size_t(slot) * S;
+    if (cs.phase == kFailed) {
+        if (threadIdx.x == 0) {
+            cs.n_newton_fail += 1;
+            if (!cs.j_fresh) {
+                cs.j_fresh = 1;
+                cs.jac_refresh = 1;
+                cs.n_jac += 1;
+                sh[0] = 0.0;
+            } else {
+                cs.h = 0.5 * cs.h;
+                cs.n_equal = 0;
+                cs.lu_valid = 0;
+                sh[0] = 0.5;
+            }
+        }
+        __syncthreads();
+        if (sh[0] != 0.0) rescale_D(D, S, cs.q, 0.5, RU);
+        begin_attempt(s, slot, cs, next, RU, sh + 2);
+        return;
+    }
+    // converged: local error test
+    const int q = cs.q;
+    const double rtol = cs.rtol, atol = cs.atol;
+    const double eq = 1.0 / (q + 1);
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < S; i += kBlock) {
+        const double sc = atol + rtol * fmax(fabs(D[i]), fabs(x[i]));
+        const double v = eq * d[i] / sc;
+        acc += v * v;
+    }
+    const double err = sqrt(block_sum(acc, red) / S);
+    const int m = cs.m_last;
+    const double safety = 0.9 * (2 * kNewtonMaxIter + 1) / (2 * kNewtonMaxIter + m);
+    if (!isfinite(err)) {
+        finish_slot(s, slot, cs, ABDF_CELL_NONFINITE);
+        __syncthreads();
+        if (threadIdx.x == 0) s.ctl[slot] = cs;
+        return;
+    }
+    if (err > 1.0) {
+        const double rho = fmax(kMinFactor, safety * growth(err, q + 1));
+        if (threadIdx.x == 0) {
+            cs.n_err_reject += 1;
+            cs.h = cs.h * rho;
+            cs.n_equal = 0;
+            cs.lu_valid = 0;
+        }
+        rescale_D(D, S, q, rho, RU);
+        begin_attempt(s, slot, cs, next, RU, sh + 2);
+        return;
+    }
+    // accept: update the differences, collect the order-selection norms
+    const double em_c = q > 1 ? 1.0 / q : 0.0;
+    const double ep_c = 1.0 / (q + 2);
+    double am = 0.0, ap = 0.0;
+    bool nonfinite = false;
+    for (int i = threadIdx.x; i < S; i += kBlock) {
+        const double sc = atol + rtol * fmax(fabs(D[i]), fabs(x[i]));
+        double v[kDRows];
+        for (int j = 0; j <= q + 1; ++j) v[j] = D[j * S + i];
+        const double di = d[i];
+        v[q + 2] = di - v[q + 1];
+        v[q + 1] = di;
+        for (int j = q; j >= 0; --j) v[j] = v[j] + v[j + 1];
+        for (int j = 0; j <= q + 2; ++j) D[j * S + i] = v[j];
+        const double a1 = em_c * v[q] / sc, a2 = ep_c * v[q + 2] / sc;
+        am += a1 * a1;
+        ap += a2 * a2;
+        nonfinite |= !isfinite(v[0]);
+    }
+    const double sm = block_sum(am, red);
+    const double sp = block_sum(ap, red);
+    nonfinite = block_any(nonfinite, red);
+    if (threadIdx.x == 0) {
+        cs.t = cs.landing ? cs.t_end : cs.t + cs.h;
+        cs.n_steps += 1;
+        cs.n_equal += 1;
+        cs.j_fresh = 0;
+    }
+    __syncthreads();
+    if (nonfinite) {
+        finish_slot(s, slot, cs, ABDF_CELL_NONFINITE);
+        __syncthreads();
+        if (threadIdx.x == 0) s.ctl[slot] = cs;
+        return;
+    }
+    if (cs.landing) {
+        finish_slot(s, slot, cs, ABDF_CELL_OK);
+        __syncthreads();
+        if (threadIdx.x == 0) s.ctl[slot] = cs;
+        return;
+    }
+    if (cs.n_equal >= q + 1) {
+        if (threadIdx.x == 0) {
+            const double e_m = q > 1 ? sqrt(sm / S) : INFINITY;
+            const double e_p = q < kMaxOrder ? sqrt(sp / S) : INFINITY;
+            const double r0 = growth(e_m, q), r1 = growth(err, q + 1), r2 = growth(e_p, q + 2);
+            int best = 1;
+            double rb = r1;
+            if (r0 > rb) { best = 0; rb = r0; }
+            if (r2 > rb) { best = 2; rb = r2; }
+            cs.q = q + best - 1;
+            const double rho = fmin(kMaxFactor, safety * rb);
+            cs.h = cs.h * rho;
+            cs.n_equal = 0;
+            cs.lu_valid = 0;
+            sh[0] = rho;
+        }
+        __syncthreads();
+        rescale_D(D, S, cs.q, sh[0], RU);
+    }
+    begin_attempt(s, slot, cs, next, RU, sh + 2);
+}
+
+// Copies results of finished slots to the caller's arrays.
+__global__ void __launch_bounds__(kBlock) k_harvest(Slots s, HarvestArgs h) {
+    const int idx = blockIdx.x;
+    if (idx == 0 && threadIdx.x == 0) s.cnt[6] = 0;
+    if (idx >= h.count) return;
+    const int slot = h.slots[idx];
+    const SlotCtl &c = s.ctl[slot];
+    const long long cell = c.cell;
+    const int S = s.S;
+    for (int i = threadIdx.x; i < S; i += kBlock) h.x_out[size_t(cell) * S + i] = s.D[size_t(slot) * kDRows * S + i];
+    if (threadIdx.x == 0) {
+        h.status[cell] = c.status;
+        if (h.stats) {
+            abdf_cell_stats st;
+            st.n_steps = c.n_steps;
+            st.n_attempts = c.n_attempts;
+            st.n_err_reject = c.n_err_reject;
+            st.n_newton_fail = c.n_newton_fail;
+            st.n_rhs = c.n_rhs;
+            st.n_jac = c.n_jac;
+            st.n_lu = c.n_lu;
+            st.order = c.q;
+            st.h = c.h;
+            st.t = c.t;
+            h.stats[cell] = st;
+        }
+    }
+}
+
+// ------------------------------------------------- component entry kernels --
+
+__global__ void __launch_bounds__(kBlock) k_rates_only(DeviceNet n, PhysArgs p, double *k_out) {
+    __shared__ double phi[5];
+    const long long c = blockIdx.x;
+    if (threadIdx.x == 0) {
+        phi[0] = p.T[c]; phi[1] = p.nH[c]; phi[2] = p.Av[c]; phi[3] = p.zeta[c]; phi[4] = p.G0[c];
+    }
+    __syncthreads();
+    cell_rates(n, phi, k_out + size_t(c) * n.R);
+}
+
+__global__ void __launch_bounds__(kBlock) k_rhs_only(DeviceNet n, const double *k, const double *x, double *f) {
+    extern __shared__ double smem[];
+    const long long c = blockIdx.x;
+    double *xs = smem, *rate = xs + n.S, *part = rate + n.R;
+    for (int i = threadIdx.x; i < n.S; i += kBlock) xs[i] = x[size_t(c) * n.S + i];
+    __syncthreads();
+    cell_rhs(n, k + size_t(c) * n.R, xs, rate, part, f + size_t(c) * n.S);
+}
+
+// Writes the unpadded S x S Newton matrix of each cell.
+__global__ void __launch_bounds__(kBlock) k_newton_matrix_only(DeviceNet n, const double *k, const double *x,
+                                                               const double *cvec, double *M) {
+    extern __shared__ double smem[];
+    const long long c = blockIdx.x;
+    double *xs = smem, *rowbuf = xs + n.S, *rowout = rowbuf + kWaves * n.NP;
+    for (int i = threadIdx.x; i < n.S; i += kBlock) xs[i] = x[size_t(c) * n.S + i];
+    __syncthreads();
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int i = wave; i < n.S; i += kWaves) {
+        double *ro = rowout + wave * n.NP;
+        newton_matrix_row<double>(n, k + size_t(c) * n.R, xs, cvec[c], i, rowbuf + wave * n.NP, ro);
+        for (int j = lane; j < n.S; j += 64) M[(size_t(c) * n.S + i) * n.S + j] = ro[j];
+        __builtin_amdgcn_wave_barrier();
+    }
+}
+
+// Copies an n x n matrix into the padded NP x NP work matrix (identity padding) and back.
+template <typename T>
+__global__ void k_pad_in(int n, int NP, const double *A, T *W) {
+    const long long b = blockIdx.y;
+    for (long long e = blockIdx.x * blockDim.x + threadIdx.x; e < (long long)NP * NP; e += gridDim.x * blockDim.x) {
+        const int i = int(e / NP), j = int(e % NP);
+        double v = (i < n && j < n) ? A[(b * n + i) * n + j] : (i == j ? 1.0 : 0.0);
+        W[b * NP * NP + e] = T(v);
+    }
+}
+
+template <typename T>
+__global__ void k_pad_out(int n, int NP, const T *W, double *A, const int32_t *permW, int32_t *perm) {
+    const long long b = blockIdx.y;
+    for (long long e = blockIdx.x * blockDim.x + threadIdx.x; e < (long long)n * n; e += gridDim.x * blockDim.x) {
+        const int i = int(e / n), j = int(e % n);
+        A[(b * n + i) * n + j] = double(W[b * NP * NP + (long long)i * NP + j]);
+    }
+    if (blockIdx.x == 0)
+        for (int i = threadIdx.x; i < n; i += blockDim.x) perm[b * n + i] = permW[b * NP + i];
+}
+
+__global__ void k_copy_perm(int n, int NP, const int32_t *perm, int32_t *permW) {
+    const long long b = blockIdx.x;
+    for (int i = threadIdx.x; i < NP; i += blockDim.x) permW[b * NP + i] = i < n ? perm[b * n + i] : i;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_lu_factor_only(int NP, T *W, int32_t *permW, int32_t *info) {
+    extern __shared__ double smem[];
+    const long long b = blockIdx.x;
+    lu_factor_wg<T>(W + b * NP * NP, NP, permW + b * NP, info ? info + b : nullptr,
+                    reinterpret_cast<unsigned char *>(smem));
+}
+
+__global__ void __launch_bounds__(kBlock) k_lu_solve_only(int NP, int n, const double *W, const int32_t *permW,
+                                                          double *bvec) {
+    extern __shared__ double smem[];
+    __shared__ double red[16];
+    const long long bi = blockIdx.x;
+    double *b = smem, *y = b + NP;
+    for (int i = threadIdx.x; i < NP; i += kBlock) b[i] = i < n ? bvec[bi * n + i] : 0.0;
+    __syncthreads();
+    lu_solve_wg<double>(W + bi * NP * NP, permW + bi * NP, NP, b, y, red);
+    for (int i = threadIdx.x; i < n; i += kBlock) bvec[bi * n + i] = y[i];
+}
+
+// Matrix-core lane-layout check: D = A B for integer-valued A (16x4), B (4x16).
+__global__ void k_selftest(int *bad) {
+    const int l = threadIdx.x;
+    auto Aval = [](int i, int k) { return double((i * 7 + k * 3) % 11 - 5); };
+    auto Bval = [](int k, int j) { return double((k * 5 + j * 2) % 13 - 6); };
+    f64x4 cd = {0, 0, 0, 0};
+    cd = Mfma<double>::mma(Aval(l & 15, l >> 4), Bval(l >> 4, l & 15), cd);
+    f32x4 cf = {0, 0, 0, 0};
+    cf = Mfma<float>::mma(float(Aval(l & 15, l >> 4)), float(Bval(l >> 4, l & 15)), cf);
+    int nb = 0;
+    for (int v = 0; v < 4; ++v) {
+        const int j = l & 15;
+        double ref_d = 0.0, ref_f = 0.0;
+        const int id = Mfma<double>::row(l, v), jf = Mfma<float>::row(l, v);
+        for (int k = 0; k < 4; ++k) {
+            ref_d += Aval(id, k) * Bval(k, j);
+            ref_f += Aval(jf, k) * Bval(k, j);
+        }
+        nb += (cd[v] != ref_d) + (double(cf[v]) != ref_f);
+    }
+    atomicAdd(bad, nb);
+}
+
+// ------------------------------------------------------------- launchers --
+
+size_t lu_work_lds(int NP, int prec) {
+    return prec == ABDF_PREC_FP32_LU ? lu_lds_bytes<float>(NP) : lu_lds_bytes<double>(NP);
+}
+
+size_t factor_lds(const DeviceNet &n, int prec) {
+    return std::max(sizeof(double) * (size_t(n.S) + kWaves * size_t(n.NP)), lu_work_lds(n.NP, prec));
+}
+
+#define LAUNCH_CHECK() hipGetLastError()
+
+hipError_t launch_admit(const Slots &s, const DeviceNet &n, const AdmitArgs &a, int ring, size_t lds, hipStream_t st) {
+    if (a.count == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_admit, dim3(a.count), dim3(kBlock), lds, st, s, n, a, ring);
+    return LAUNCH_CHECK();
+}
+
+hipError_t launch_factor(const Slots &s, const DeviceNet &n, int ring, int grid, size_t lds, hipStream_t st) {
+    if (grid == 0) return hipSuccess;
+    if (s.prec == ABDF_PREC_FP32_LU)
+        hipLaunchKernelGGL(k_factor<float>, dim3(grid), dim3(kBlock), lds, st, s, n, ring);
+    else
+        hipLaunchKernelGGL(k_factor<double>, dim3(grid), dim3(kBlock), lds, st, s, n, ring);
+    return LAUNCH_CHECK();
+}
+
+hipError_t launch_newton(const Slots &s, const DeviceNet &n, int ring, int grid, size_t lds, hipStream_t st) {
+    if (grid == 0) return hipSuccess;
+    if (s.prec == ABDF_PREC_FP32_LU)
+        hipLaunchKernelGGL(k_newton<float>, dim3(grid), dim3(kBlock), lds, st, s, n, ring);
+    else
+        hipLaunchKernelGGL(k_newton<double>, dim3(grid), dim3(kBlock), lds, st, s, n, ring);
+    return LAUNCH_CHECK();
+}
+
+hipError_t launch_control(const Slots &s, int ring, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_control, dim3(grid > 0 ? grid : 1), dim3(kBlock), 0, st, s, ring);
+    return LAUNCH_CHECK();
+}
+
+hipError_t launch_harvest(const Slots &s, const HarvestArgs &h, hipStream_t st) {
+    hipLaunchKernelGGL(k_harvest, dim3(h.count > 0 ? h.count : 1), dim3(kBlock), 0, st, s, h);
+    return LAUNCH_CHECK();
+}
+
+hipError_t launch_rates(const DeviceNet &n, const PhysArgs &p, long long cells, double *k, hipStream_t st) {
+    hipLaunchKernelGGL(k_rates_only, dim3(cells), dim3(kBlock), 0, st, n, p, k);
+    return LAUNCH_CHECK();
+}
+
+hipError_t launch_rhs(const DeviceNet &n, long long cells, const double *k, const double *x, double *f, hipStream_t st) {
+    const size_t lds = sizeof(double) * (size_t(n.S) + n.R + n.n_seg);
+    hipLaunchKernelGGL(k_rhs_only, dim3(cells), dim3(kBlock), lds, st, n, k, x, f);
+    return LAUNCH_CHECK();
+}
+
+hipError_t launch_newton_matrix(const DeviceNet &n, long long cells, const double *k, const double *x,
+                                const double *c, double *M, hipStream_t st) {
+    const size_t lds = sizeof(double) * (size_t(n.S) + 2 * kWaves * size_t(n.NP));
+    hipLaunchKernelGGL(k_newton_matrix_only, dim3(cells), dim3(kBlock), lds, st, n, k, x, c, M);
+    return LAUNCH_CHECK();
+}
+
+hipError_t launch_lu_factor(int n, int NP, long long batch, double *A, void *W, int32_t *permW, int32_t *perm,
+                            int32_t *info, int prec, hipStream_t st) {
+    dim3 g(std::max(1, std::min(64, (NP * NP + 255) / 256)), unsigned(batch));
+    if (prec == ABDF_PREC_FP32_LU) {
+        hipLaunchKernelGGL(k_pad_in<float>, g, dim3(256), 0, st, n, NP, A, (float *)W);
+        hipLaunchKernelGGL(k_lu_factor_only<float>, dim3(batch), dim3(kBlock), lu_lds_bytes<float>(NP), st, NP,
+                           (float *)W, permW, info);
+        hipLaunchKernelGGL(k_pad_out<float>, g, dim3(256), 0, st, n, NP, (const float *)W, A, permW, perm);
+    } else {
+        hipLaunchKernelGGL(k_pad_in<double>, g, dim3(256), 0, st, n, NP, A, (double *)W);
+        hipLaunchKernelGGL(k_lu_factor_only<double>, dim3(batch), dim3(kBlock), lu_lds_bytes<double>(NP), st, NP,
+                           (double *)W, permW, info);
+        hipLaunchKernelGGL(k_pad_out<double>, g, dim3(256), 0, st, n, NP, (const double *)W, A, permW, perm);
+    }
+    return LAUNCH_CHECK();
+}
+
+hipError_t launch_lu_solve(int n, int NP, long long batch, const double *LU, const int32_t *perm, double *b,
+                           void *W, int32_t *permW, hipStream_t st) {
+    dim3 g(std::max(1, std::min(64, (NP * NP + 255) / 256)), unsigned(batch));
+    hipLaunchKernelGGL(k_pad_in<double>, g, dim3(256), 0, st, n, NP, LU, (double *)W);
+    hipLaunchKernelGGL(k_copy_perm, dim3(unsigned(batch)), dim3(256), 0, st, n, NP, perm, permW);
+    hipLaunchKernelGGL(k_lu_solve_only, dim3(batch), dim3(kBlock), sizeof(double) * 2 * NP, st, NP, n,
+                       (const double *)W, permW, b);
+    return LAUNCH_CHECK();
+}
+
+hipError_t launch_selftest(int *bad, hipStream_t st) {
+    hipLaunchKernelGGL(k_selftest, dim3(1), dim3(64), 0, st, bad);
+    return LAUNCH_CHECK();
+}
+
+}  // namespace abdf

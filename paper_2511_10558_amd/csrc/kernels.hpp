@@ -1,0 +1,63 @@
+// Kernel launchers shared by the host engine and the C-ABI layer.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdint>
+
+#include "device_common.hpp"
+#include "network.hpp"
+
+struct abdf_cell_stats;
+
+namespace abdf {
+
+struct AdmitArgs {
+    int count;
+    const int32_t *slots;       // [count] target slots
+    const long long *cells;     // [count] source cell indices
+    const double *T, *nH, *Av, *zeta, *G0, *x0, *t_end;
+    double rtol, atol, newton_tol;
+};
+
+struct HarvestArgs {
+    int count;
+    const int32_t *slots;       // [count] finished slots
+    double *x_out;
+    int32_t *status;
+    abdf_cell_stats *stats;
+};
+
+struct PhysArgs {
+    const double *T, *nH, *Av, *zeta, *G0;
+};
+
+// LDS bytes per kernel for a network
+inline size_t admit_lds(const DeviceNet &n) { return sizeof(double) * (4 * size_t(n.S) + n.R + n.n_seg); }
+inline size_t newton_lds(const DeviceNet &n) {
+    return sizeof(double) * (size_t(n.S) + n.R + n.n_seg + 2 * size_t(n.NP));
+}
+size_t factor_lds(const DeviceNet &n, int prec);
+
+hipError_t launch_admit(const Slots &s, const DeviceNet &n, const AdmitArgs &a, int ring, size_t lds, hipStream_t st);
+hipError_t launch_factor(const Slots &s, const DeviceNet &n, int ring, int grid, size_t lds, hipStream_t st);
+hipError_t launch_newton(const Slots &s, const DeviceNet &n, int ring, int grid, size_t lds, hipStream_t st);
+hipError_t launch_control(const Slots &s, int ring, int grid, hipStream_t st);
+hipError_t launch_harvest(const Slots &s, const HarvestArgs &h, hipStream_t st);
+
+hipError_t launch_rates(const DeviceNet &n, const PhysArgs &p, long long cells, double *k, hipStream_t st);
+hipError_t launch_rhs(const DeviceNet &n, long long cells, const double *k, const double *x, double *f, hipStream_t st);
+hipError_t launch_newton_matrix(const DeviceNet &n, long long cells, const double *k, const double *x,
+                                const double *c, double *M, hipStream_t st);
+hipError_t launch_lu_factor(int n, int NP, long long batch, double *A, void *W, int32_t *permW, int32_t *perm,
+                            int32_t *info, int prec, hipStream_t st);
+hipError_t launch_lu_solve(int n, int NP, long long batch, const double *LU, const int32_t *perm, double *b,
+                           void *W, int32_t *permW, hipStream_t st);
+hipError_t launch_selftest(int *bad, hipStream_t st);
+size_t lu_work_lds(int NP, int prec);
+
+// Largest dynamic LDS one workgroup may use on the device.
+constexpr size_t kMaxLds = 160 * 1024;
+
+}  // namespace abdf

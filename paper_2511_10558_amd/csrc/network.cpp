@@ -1,0 +1,275 @@
+// Network text parser, integer conservation check and gather-table builder.
+//
+// The tables restate the mass-action model of the paper (Sec. 2): the
+// stoichiometric (incidence) matrix nu_ir = (count of i among products) -
+// (count of i among reactants), the right-hand side f_i = sum_r nu_ir rate_r
+// and its Jacobian J_ij = sum_r nu_ir d rate_r / d x_j.
+#include "network.hpp"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <sstream>
+
+#include "../../include/astrobdf.h"
+
+namespace abdf {
+
+namespace {
+
+struct Tok {
+    std::istringstream in;
+    explicit Tok(const std::string &s) : in(s) {}
+    template <typename T>
+    bool get(T &v) { return static_cast<bool>(in >> v); }
+};
+
+bool expect_word(Tok &t, const char *w) {
+    std::string s;
+    return t.get(s) && s == w;
+}
+
+}  // namespace
+
+HostNetwork::~HostNetwork() {
+    for (DeviceNet *d : dev) {
+        if (!d) continue;
+        int prev = 0;
+        if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(d->device) == hipSuccess) {
+            void *ptrs[] = {d->rx_ab, d->rx_type, d->alpha, d->beta, d->gamma, d->seg_ptr, d->seg_beg,
+                            d->f_ent, d->jrow_ptr, d->jcol, d->jterm_ptr, d->jt_rx_other, d->jt_coef};
+            for (void *p : ptrs)
+                if (p) (void)hipFree(p);
+            (void)hipSetDevice(prev);
+        }
+        delete d;
+    }
+}
+
+int HostNetwork::parse(const char *text, size_t len, std::string &err) {
+    Tok t(std::string(text, len));
+    int version = 0;
+    if (!expect_word(t, "astrobdf-network") || !t.get(version) || version != 1) {
+        err = "not an astrobdf-network version 1 text";
+        return ABDF_E_PARSE;
+    }
+    if (!expect_word(t, "name") || !t.get(name)) { err = "missing name"; return ABDF_E_PARSE; }
+    if (!expect_word(t, "elements") || !t.get(E) || E < 1 || E > 32) { err = "bad elements line"; return ABDF_E_PARSE; }
+    elements.resize(E);
+    for (int e = 0; e < E; ++e)
+        if (!t.get(elements[e])) { err = "bad elements line"; return ABDF_E_PARSE; }
+    if (!expect_word(t, "species") || !t.get(S) || S < 1 || S > 32000) { err = "bad species count"; return ABDF_E_PARSE; }
+    species.resize(S);
+    charge.resize(S);
+    comp.resize(size_t(S) * E);
+    for (int i = 0; i < S; ++i) {
+        int idx = -1;
+        if (!t.get(idx) || idx != i || !t.get(species[i]) || !t.get(charge[i])) {
+            err = "bad species record " + std::to_string(i);
+            return ABDF_E_PARSE;
+        }
+        for (int e = 0; e < E; ++e)
+            if (!t.get(comp[size_t(i) * E + e]) || comp[size_t(i) * E + e] < 0) {
+                err = "bad species record " + std::to_string(i);
+                return ABDF_E_PARSE;
+            }
+    }
+    if (!expect_word(t, "reactions") || !t.get(R) || R < 1 || R > (1 << 24)) { err = "bad reaction count"; return ABDF_E_PARSE; }
+    rtype.resize(R);
+    react.assign(size_t(R) * 2, -1);
+    prod.assign(size_t(R) * 3, -1);
+    alpha.resize(R);
+    beta.resize(R);
+    gamma.resize(R);
+    for (int r = 0; r < R; ++r) {
+        int idx = -1, nr = 0, np = 0;
+        int32_t a[2], p[3];
+        bool ok = t.get(idx) && idx == r && t.get(rtype[r]) && t.get(nr) && t.get(a[0]) && t.get(a[1]) &&
+                  t.get(np) && t.get(p[0]) && t.get(p[1]) && t.get(p[2]) && t.get(alpha[r]) &&
+                  t.get(beta[r]) && t.get(gamma[r]);
+        if (!ok || nr < 1 || nr > 2 || np < 1 || np > 3 || rtype[r] < 0 || rtype[r] > 2) {
+            err = "bad reaction record " + std::to_string(r);
+            return ABDF_E_PARSE;
+        }
+        if ((rtype[r] != kTwoBody && nr != 1) || (rtype[r] == kTwoBody && nr != 2)) {
+            err = "reaction " + std::to_string(r) + ": two-body needs 2 reactants, cosmic-ray/photo 1";
+            return ABDF_E_PARSE;
+        }
+        for (int j = 0; j < 2; ++j) {
+            bool used = j < nr;
+            if ((used && (a[j] < 0 || a[j] >= S)) || (!used && a[j] != -1)) {
+                err = "reaction " + std::to_string(r) + ": reactant index out of range";
+                return ABDF_E_PARSE;
+            }
+            react[size_t(r) * 2 + j] = a[j];
+        }
+        for (int j = 0; j < 3; ++j) {
+            bool used = j < np;
+            if ((used && (p[j] < 0 || p[j] >= S)) || (!used && p[j] != -1)) {
+                err = "reaction " + std::to_string(r) + ": product index out of range";
+                return ABDF_E_PARSE;
+            }
+            prod[size_t(r) * 3 + j] = p[j];
+        }
+        // integer conservation of every element and the charge
+        for (int e = 0; e <= E; ++e) {
+            long long lhs = 0, rhs = 0;
+            for (int j = 0; j < nr; ++j) lhs += e < E ? comp[size_t(a[j]) * E + e] : charge[a[j]];
+            for (int j = 0; j < np; ++j) rhs += e < E ? comp[size_t(p[j]) * E + e] : charge[p[j]];
+            if (lhs != rhs) {
+                err = "reaction " + std::to_string(r) + " does not conserve " +
+                      (e < E ? "element " + elements[e] : std::string("charge"));
+                return ABDF_E_NONCONSERVING;
+            }
+        }
+        if (!std::isfinite(alpha[r]) || !std::isfinite(beta[r]) || !std::isfinite(gamma[r])) {
+            err = "reaction " + std::to_string(r) + ": non-finite parameter";
+            return ABDF_E_PARSE;
+        }
+    }
+    if (!expect_word(t, "end")) { err = "missing end"; return ABDF_E_PARSE; }
+    finalize();
+    return ABDF_OK;
+}
+
+void HostNetwork::finalize() {
+    NP = (S + 15) / 16 * 16;
+    // nu as a sparse map per species: (reaction, coefficient)
+    std::vector<std::map<int, int>> nu(S);
+    for (int r = 0; r < R; ++r) {
+        for (int j = 0; j < 3; ++j)
+            if (prod[size_t(r) * 3 + j] >= 0) nu[prod[size_t(r) * 3 + j]][r] += 1;
+        for (int j = 0; j < 2; ++j)
+            if (react[size_t(r) * 2 + j] >= 0) nu[react[size_t(r) * 2 + j]][r] -= 1;
+    }
+    // right-hand side entries, each species' row cut into segments
+    seg_ptr.assign(S + 1, 0);
+    seg_beg.clear();
+    f_ent.clear();
+    for (int i = 0; i < S; ++i) {
+        seg_ptr[i] = int32_t(seg_beg.size());
+        int in_seg = kRhsSegment;
+        for (auto &kv : nu[i]) {
+            if (kv.second == 0) continue;
+            if (in_seg == kRhsSegment) {
+                seg_beg.push_back(int32_t(f_ent.size()));
+                in_seg = 0;
+            }
+            f_ent.push_back((kv.first << 3) | (kv.second + 4));
+            ++in_seg;
+        }
+    }
+    seg_ptr[S] = int32_t(seg_beg.size());
+    seg_beg.push_back(int32_t(f_ent.size()));
+
+    // Jacobian terms: d rate_r / d x_j of a mass-action rate
+    struct Term { int j, r, other; double coef; };
+    std::vector<std::vector<Term>> rows(S);
+    for (int r = 0; r < R; ++r) {
+        int a = react[size_t(r) * 2], b = react[size_t(r) * 2 + 1];
+        Term d[2];
+        int nd = 0;
+        if (b < 0) d[nd++] = {a, r, -1, 1.0};
+        else if (a == b) d[nd++] = {a, r, a, 2.0};
+        else { d[nd++] = {a, r, b, 1.0}; d[nd++] = {b, r, a, 1.0}; }
+        std::map<int, int> nur;
+        for (int j = 0; j < 3; ++j)
+            if (prod[size_t(r) * 3 + j] >= 0) nur[prod[size_t(r) * 3 + j]] += 1;
+        for (int j = 0; j < 2; ++j)
+            if (react[size_t(r) * 2 + j] >= 0) nur[react[size_t(r) * 2 + j]] -= 1;
+        for (auto &kv : nur) {
+            if (kv.second == 0) continue;
+            for (int q = 0; q < nd; ++q)
+                rows[kv.first].push_back({d[q].j, r, d[q].other, kv.second * d[q].coef});
+        }
+    }
+    jrow_ptr.assign(S + 1, 0);
+    jcol.clear();
+    jterm_ptr.clear();
+    jt_rx_other.clear();
+    jt_coef.clear();
+    for (int i = 0; i < S; ++i) {
+        auto &v = rows[i];
+        std::stable_sort(v.begin(), v.end(), [](const Term &x, const Term &y) {
+            return x.j != y.j ? x.j < y.j : x.r < y.r;
+        });
+        jrow_ptr[i] = int32_t(jcol.size());
+        int last = -1;
+        for (auto &tm : v) {
+            if (tm.j != last) {
+                jcol.push_back(tm.j);
+                jterm_ptr.push_back(int32_t(jt_coef.size()));
+                last = tm.j;
+            }
+            jt_rx_other.push_back((tm.r << 16) | (tm.other + 1));
+            jt_coef.push_back(tm.coef);
+        }
+    }
+    jrow_ptr[S] = int32_t(jcol.size());
+    jterm_ptr.push_back(int32_t(jt_coef.size()));
+}
+
+namespace {
+template <typename T>
+hipError_t upload(T **dst, const std::vector<T> &src) {
+    size_t n = std::max<size_t>(src.size(), 1) * sizeof(T);
+    hipError_t e = hipMalloc(reinterpret_cast<void **>(dst), n);
+    if (e != hipSuccess) return e;
+    if (!src.empty()) e = hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice);
+    return e;
+}
+}  // namespace
+
+const DeviceNet *HostNetwork::device_tables(std::string &err) const {
+    int devid = 0;
+    if (hipGetDevice(&devid) != hipSuccess) {
+        err = "no HIP device";
+        return nullptr;
+    }
+    std::lock_guard<std::mutex> lock(mu);
+    if (int(dev.size()) <= devid) dev.resize(devid + 1, nullptr);
+    if (dev[devid]) return dev[devid];
+    if (R >= (1 << 15) || S >= 0xffff) {
+        err = "network too large for the packed device tables";
+        return nullptr;
+    }
+    auto *d = new DeviceNet();
+    d->device = devid;
+    d->S = S;
+    d->R = R;
+    d->NP = NP;
+    std::vector<int32_t> ab(R);
+    for (int r = 0; r < R; ++r) {
+        int a = react[size_t(r) * 2], b = react[size_t(r) * 2 + 1];
+        ab[r] = (a & 0xffff) | ((b < 0 ? 0xffff : b) << 16);
+    }
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
+    chk(upload(&d->rx_ab, ab));
+    chk(upload(&d->rx_type, rtype));
+    chk(upload(&d->alpha, alpha));
+    chk(upload(&d->beta, beta));
+    chk(upload(&d->gamma, gamma));
+    chk(upload(&d->seg_ptr, seg_ptr));
+    chk(upload(&d->seg_beg, seg_beg));
+    chk(upload(&d->f_ent, f_ent));
+    chk(upload(&d->jrow_ptr, jrow_ptr));
+    chk(upload(&d->jcol, jcol));
+    chk(upload(&d->jterm_ptr, jterm_ptr));
+    chk(upload(&d->jt_rx_other, jt_rx_other));
+    chk(upload(&d->jt_coef, jt_coef));
+    d->n_seg = int32_t(seg_beg.size()) - 1;
+    d->nnzJ = int32_t(jcol.size());
+    d->nterm = int32_t(jt_coef.size());
+    if (e != hipSuccess) {
+        err = std::string("uploading network tables: ") + hipGetErrorString(e);
+        return nullptr;  // the partial upload is leaked rather than reused
+    }
+    dev[devid] = d;
+    return d;
+}
+
+}  // namespace abdf

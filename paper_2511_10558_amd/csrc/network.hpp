@@ -1,0 +1,69 @@
+// Host-side reaction network: parsing, validation and the derived tables the
+// device kernels read.  No HIP calls here except in DeviceNet::upload.
+#pragma once
+
+#include <cstdint>
+#include <mutex>
+#include <string>
+#include <vector>
+
+namespace abdf {
+
+constexpr int kTwoBody = 0;
+constexpr int kCosmicRay = 1;
+constexpr int kPhoto = 2;
+constexpr int kRhsSegment = 32;   // CSR entries summed by one thread before the per-species pass
+
+// Device copies of the network tables (one per HIP device).
+struct DeviceNet {
+    int device = -1;
+    int S = 0, R = 0, NP = 0;
+    // per reaction
+    int32_t *rx_ab = nullptr;      // reactant a in low 16 bits, b in high 16 bits (0xffff: none)
+    int32_t *rx_type = nullptr;
+    double *alpha = nullptr, *beta = nullptr, *gamma = nullptr;
+    // right-hand side: species rows split into segments of <= kRhsSegment entries
+    int32_t n_seg = 0;
+    int32_t *seg_ptr = nullptr;    // [S+1] first segment of each species
+    int32_t *seg_beg = nullptr;    // [n_seg+1] first entry of each segment (entries are contiguous)
+    int32_t *f_ent = nullptr;      // packed entry: reaction index << 3 | (nu + 4)
+    // Jacobian: nonzeros of J grouped by row, each with its list of terms
+    int32_t *jrow_ptr = nullptr;   // [S+1]
+    int32_t *jcol = nullptr;       // [nnzJ]
+    int32_t *jterm_ptr = nullptr;  // [nnzJ+1]
+    int32_t *jt_rx_other = nullptr;  // reaction << 16 | (other species + 1), 0 in the low half = none
+    double *jt_coef = nullptr;     // [nterm] nu_ir * multiplicity
+    int32_t nnzJ = 0, nterm = 0;
+};
+
+struct HostNetwork {
+    std::string name;
+    std::vector<std::string> elements;
+    std::vector<std::string> species;
+    std::vector<int32_t> charge;          // [S]
+    std::vector<int32_t> comp;            // [S * E]
+    std::vector<int32_t> rtype;           // [R]
+    std::vector<int32_t> react;           // [R * 2], -1 padded
+    std::vector<int32_t> prod;            // [R * 3], -1 padded
+    std::vector<double> alpha, beta, gamma;
+
+    // derived (built by finalize())
+    int S = 0, R = 0, E = 0, NP = 0;
+    std::vector<int32_t> seg_ptr, seg_beg, f_ent;
+    std::vector<int32_t> jrow_ptr, jcol, jterm_ptr, jt_rx_other;
+    std::vector<double> jt_coef;
+
+    // per-device uploads, created on first use
+    mutable std::mutex mu;
+    mutable std::vector<DeviceNet *> dev;
+
+    ~HostNetwork();
+    // Parses the text format; on failure returns an abdf_status code and sets err.
+    int parse(const char *text, size_t len, std::string &err);
+    // Builds the gather tables; called by parse.
+    void finalize();
+    // Device tables for the current HIP device (uploaded once); nullptr + err on failure.
+    const DeviceNet *device_tables(std::string &err) const;
+};
+
+}  // namespace abdf

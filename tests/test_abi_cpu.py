@@ -1,0 +1,117 @@
+"""C-ABI surface on the CPU: the library loads, exports every declared symbol,
+and validates network text without touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "astrobdf.h")
+
+ab = pytest.importorskip("paper_2511_10558_amd")
+
+
+def _declared():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(abdf_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_header_declares_the_boundary():
+    names = _declared()
+    for must in ("abdf_network_load", "abdf_solve", "abdf_rates", "abdf_rhs", "abdf_newton_matrix",
+                 "abdf_lu_factor", "abdf_lu_solve", "abdf_last_error", "abdf_options_default"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    L = ab._lib.lib()
+    for name in _declared():
+        assert hasattr(L, name), name
+    assert set(_declared()) <= set(ab._lib.SIGNATURES)
+
+
+def test_options_default_values():
+    o = ab.default_options()
+    assert o.rtol == 1e-6 and o.atol == 1e-20 and o.max_steps == 100000
+    assert o.precision == 0 and o.check_every == 8 and o.hbm_budget_bytes == 0
+
+
+@pytest.mark.parametrize("name", ["small", "net200", "net500"])
+def test_generated_networks_load(name):
+    net = synth.network_for_config(name)
+    g = ab.Network.from_text(net.to_text())
+    assert g.n_species == net.n_species
+    assert g.n_reactions == net.n_reactions
+    assert g.n_elements == len(synth.ELEMENTS)
+    assert [g.species_name(i) for i in range(net.n_species)] == net.species
+    assert g.species_name(-1) is None and g.species_name(net.n_species) is None
+
+
+def test_network_file_load_and_missing_file(tmp_path):
+    net = synth.network_for_config("small")
+    p = tmp_path / "n.txt"
+    synth.write_network(net, p)
+    assert ab.Network.from_file(p).n_species == 12
+    with pytest.raises(ab.AbdfError) as e:
+        ab.Network.from_file(tmp_path / "missing.txt")
+    assert e.value.code == 4
+
+
+def _mutate(text, line_prefix, new_line):
+    lines = text.splitlines()
+    for i, l in enumerate(lines):
+        if l.startswith(line_prefix):
+            lines[i] = new_line
+            break
+    return "\n".join(lines) + "\n"
+
+
+def test_nonconserving_reaction_is_rejected_with_its_index():
+    net = synth.network_for_config("small")
+    text = net.to_text()
+    start = text.splitlines().index("reactions 40") + 1
+    line = text.splitlines()[start + 3].split()
+    line[6] = str((int(line[6]) + 1) % 12)      # change the first product
+    bad = _mutate(text, " ".join(text.splitlines()[start + 3].split()[:2]) + " ", " ".join(line))
+    with pytest.raises(ab.AbdfError) as e:
+        ab.Network.from_text(bad)
+    assert e.value.code == 3
+    assert "reaction 3" in str(e.value)
+
+
+@pytest.mark.parametrize("edit", [
+    lambda t: t.replace("astrobdf-network 1", "astrobdf-network 2"),
+    lambda t: t.replace("\nend\n", "\n"),
+    lambda t: t.replace("species 12", "species 13"),
+    lambda t: _mutate(t, "0 0 2 ", "0 7 2 3 6 3 4 7 11 1e-10 0 0"),
+    lambda t: _mutate(t, "0 0 2 ", "0 0 2 3 99 2 4 7 -1 1e-10 0 0"),
+    lambda t: _mutate(t, "0 0 2 ", "0 0 2 3 6 2 4 7 -1 nan 0 0"),
+])
+def test_malformed_network_text_is_a_parse_error(edit):
+    text = synth.network_for_config("small").to_text()
+    bad = edit(text)
+    assert bad != text
+    with pytest.raises(ab.AbdfError) as e:
+        ab.Network.from_text(bad)
+    assert e.value.code in (2, 3)
+
+
+def test_null_and_invalid_arguments_without_gpu():
+    L = ab._lib.lib()
+    h = ctypes.c_void_p()
+    assert L.abdf_network_load(None, ctypes.byref(h)) == 1
+    assert L.abdf_network_num_species(None) == -1
+    g = ab.Network.from_text(synth.network_for_config("small").to_text())
+    o = ab.make_options(rtol=0.0)
+    rc = L.abdf_solve(g.handle, 1, *([None] * 7), ctypes.byref(o), None, None, None, None)
+    assert rc == 1 and b"rtol" in L.abdf_last_error()
+    o = ab.make_options(precision=7)
+    assert L.abdf_solve(g.handle, 1, *([None] * 7), ctypes.byref(o), None, None, None, None) == 1
+    o = ab.make_options()
+    assert L.abdf_solve(g.handle, 0, *([None] * 7), ctypes.byref(o), None, None, None, None) == 0
+    assert L.abdf_solve(g.handle, -1, *([None] * 7), ctypes.byref(o), None, None, None, None) == 1
+    assert L.abdf_lu_factor(0, 1, None, None, None, 0, None) == 1

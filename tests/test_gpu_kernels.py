@@ -1,0 +1,135 @@
+"""Kernel-level parity of the HIP path against the oracle (GPU)."""
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import synth
+from oracle import chem
+from tests.gpu_util import device, t
+
+pytestmark = pytest.mark.gpu
+EPS = np.finfo(float).eps
+
+
+@pytest.fixture(scope="module")
+def ab():
+    import paper_2511_10558_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return device()
+
+
+def test_matrix_core_layouts(ab, dev):
+    ab.selftest()
+
+
+@pytest.mark.parametrize("name", ["small", "net200", "net500"])
+def test_rates_match_oracle(ab, dev, name):
+    net = synth.network_for_config(name)
+    g = ab.Network.from_text(net.to_text())
+    cells = synth.sample_cells(net, 37, seed=11)
+    k = ab.rates(g, t(cells.T, dev), t(cells.n_H, dev), t(cells.A_V, dev), t(cells.zeta, dev),
+                 t(cells.G0, dev)).cpu().numpy()
+    for c in range(cells.n):
+        ref = chem.rate_coefficients(net, **cells.cell(c))
+        np.testing.assert_allclose(k[c], ref, rtol=1e-13, atol=0)
+
+
+@pytest.mark.parametrize("name", ["small", "net200", "net500"])
+def test_rhs_matches_oracle(ab, dev, name):
+    net = synth.network_for_config(name)
+    g = ab.Network.from_text(net.to_text())
+    cells = synth.sample_cells(net, 19, seed=12)
+    rng = np.random.default_rng(13)
+    x = np.exp(rng.uniform(np.log(1e-20), 0.0, (cells.n, net.n_species)))
+    x[:, 0] = 0.0                       # an exactly-zero species
+    K = np.array([chem.rate_coefficients(net, **cells.cell(c)) for c in range(cells.n)])
+    f = ab.rhs(g, t(K, dev), t(x, dev)).cpu().numpy()
+    absnu = abs(chem.stoichiometry(net))
+    for c in range(cells.n):
+        ch = chem.Chemistry(net, K[c])
+        ref = ch.f(x[c])
+        bound = 16 * EPS * (absnu @ chem.reaction_rates(net, K[c], x[c]))
+        assert np.all(np.abs(f[c] - ref) <= bound + 1e-300)
+
+
+@pytest.mark.parametrize("name", ["small", "net200", "net500"])
+def test_newton_matrix_matches_oracle(ab, dev, name):
+    net = synth.network_for_config(name)
+    g = ab.Network.from_text(net.to_text())
+    cells = synth.sample_cells(net, 5, seed=14)
+    rng = np.random.default_rng(15)
+    x = np.exp(rng.uniform(np.log(1e-20), 0.0, (cells.n, net.n_species)))
+    K = np.array([chem.rate_coefficients(net, **cells.cell(c)) for c in range(cells.n)])
+    cvec = np.exp(rng.uniform(np.log(1e2), np.log(1e13), cells.n))
+    M = ab.newton_matrix(g, t(K, dev), t(x, dev), t(cvec, dev)).cpu().numpy()
+    absnu = abs(chem.stoichiometry(net))
+    for c in range(cells.n):
+        ch = chem.Chemistry(net, K[c])
+        ref = np.eye(net.n_species) - cvec[c] * ch.jac(x[c])
+        absJ = (absnu @ abs(chem.rate_derivative(net, K[c], x[c]))).toarray()
+        bound = 16 * EPS * (cvec[c] * absJ + np.abs(ref))
+        assert np.all(np.abs(M[c] - ref) <= bound + 1e-300)
+
+
+def _newton_like_matrices(n, batch, seed):
+    """Diagonally heavy, badly scaled matrices like I - cJ, plus plain random ones."""
+    rng = np.random.default_rng(seed)
+    A = rng.normal(size=(batch, n, n))
+    for b in range(0, batch, 2):
+        scale = np.exp(rng.uniform(-8, 8, n))
+        A[b] = np.eye(n) + (A[b] * (rng.random((n, n)) < 0.2)) * scale[None, :]
+    return A
+
+
+@pytest.mark.parametrize("n", [1, 12, 37, 200, 500])
+@pytest.mark.parametrize("prec", ["fp64", "fp32_lu"])
+def test_lu_factor_backward_error(ab, dev, n, prec):
+    import torch
+    batch = 6
+    A = _newton_like_matrices(n, batch, seed=n)
+    LU, perm, info = ab.lu_factor(t(A, dev), precision=prec)
+    LU, perm, info = LU.cpu().numpy(), perm.cpu().numpy(), info.cpu().numpy()
+    u = EPS / 2 if prec == "fp64" else np.finfo(np.float32).eps / 2
+    for b in range(batch):
+        L = np.tril(LU[b], -1) + np.eye(n)
+        U = np.triu(LU[b])
+        assert sorted(perm[b]) == list(range(n))
+        PA = A[b][perm[b]]
+        err = np.abs(PA - L @ U).max() / np.abs(A[b]).max()
+        assert err <= 30 * n * u, err
+        assert info[b] == 0
+        if prec == "fp64":
+            # same pivots as LAPACK's partial pivoting (no near-ties in these inputs)
+            lu_ref, piv = sla.lu_factor(A[b])
+            p_ref = np.arange(n)
+            for i, p in enumerate(piv):
+                p_ref[[i, p]] = p_ref[[p, i]]
+            assert np.array_equal(p_ref, perm[b])
+            np.testing.assert_allclose(LU[b], lu_ref, rtol=1e-9, atol=1e-9 * np.abs(lu_ref).max())
+
+
+def test_lu_factor_reports_zero_pivot(ab, dev):
+    A = np.eye(20)[None].repeat(2, 0)
+    A[1, :, 7] = 0.0
+    _, _, info = ab.lu_factor(t(A, dev))
+    assert list(info.cpu().numpy()) == [0, 8]
+
+
+@pytest.mark.parametrize("n", [12, 200, 500])
+def test_lu_solve_matches_linalg(ab, dev, n):
+    batch = 4
+    A = _newton_like_matrices(n, batch, seed=100 + n)
+    rng = np.random.default_rng(n)
+    bvec = rng.normal(size=(batch, n))
+    LU, perm, _ = ab.lu_factor(t(A, dev))
+    z = ab.lu_solve(LU, perm, t(bvec, dev)).cpu().numpy()
+    for b in range(batch):
+        ref = np.linalg.solve(A[b], bvec[b])
+        res = np.abs(A[b] @ z[b] - bvec[b]).max() / (np.abs(A[b]).max() * np.abs(z[b]).max())
+        assert res <= 30 * n * EPS
+        cond = np.linalg.cond(A[b])
+        assert np.abs(z[b] - ref).max() <= 100 * n * EPS * cond * np.abs(ref).max()

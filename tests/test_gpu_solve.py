@@ -1,0 +1,116 @@
+"""End-to-end parity of the batched GPU BDF against the oracle (GPU).
+
+Parity measure: max |x_gpu - x_oracle| / x_oracle over species with
+x_oracle > 1e-12 (fraction of H nuclei) at t_end, both at rtol 1e-6,
+atol 1e-20; bar 1e-4.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import bdf, chem
+from tests.gpu_util import device, rel_err_above, solve_cells, t
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-4
+
+
+@pytest.fixture(scope="module")
+def ab():
+    import paper_2511_10558_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return device()
+
+
+def oracle_cells(net, cells, rtol=1e-6, atol=1e-20):
+    out = []
+    for c in range(cells.n):
+        ch = chem.cell_chemistry(net, cells.cell(c))
+        out.append(bdf.solve(ch, cells.x0[c], cells.t_end[c], rtol, atol))
+    return out
+
+
+def test_single_dense_cloud_cell(ab, dev):
+    net = synth.network_for_config("small")
+    cells = synth.single_cell(net)
+    g = ab.Network.from_text(net.to_text())
+    x, status, stats = solve_cells(ab, g, cells, dev)
+    ref = oracle_cells(net, cells)[0]
+    assert status[0] == 0
+    assert stats["t"][0] == cells.t_end[0]
+    assert rel_err_above(x[0], ref.x) <= TOL
+    # the same algorithm: step counts agree closely
+    assert abs(int(stats["n_steps"][0]) - ref.stats.n_steps) <= 0.05 * ref.stats.n_steps + 2
+
+
+@pytest.mark.parametrize("name,n,seed", [("net200", 6, 2001), ("net500", 3, 3001)])
+def test_batched_cells_match_oracle(ab, dev, name, n, seed):
+    net = synth.network_for_config(name)
+    cells = synth.sample_cells(net, n, seed=seed)
+    g = ab.Network.from_text(net.to_text())
+    x, status, stats = solve_cells(ab, g, cells, dev)
+    refs = oracle_cells(net, cells)
+    W = net.conservation_matrix().astype(float)
+    for c in range(n):
+        assert status[c] == 0
+        err = rel_err_above(x[c], refs[c].x)
+        assert err <= TOL, (c, err, int(stats["n_steps"][c]), refs[c].stats.n_steps)
+        w0 = W @ cells.x0[c]
+        bound = 1e-12 * (np.abs(W) @ np.abs(x[c])) + 1e-15 * np.abs(x[c]).sum()
+        assert np.all(np.abs(W @ x[c] - w0) <= bound)
+
+
+def test_mixed_horizons_and_edge_cases(ab, dev):
+    net = synth.network_for_config("net200")
+    cells = synth.sample_cells(net, 7, seed=77)
+    cells.t_end[:] = np.array([0.0, 1e3, 1e4, 1e5, 1e6, 1e7, 3e2]) * synth.YEAR_S
+    cells.T[6] = -5.0                     # non-physical temperature
+    g = ab.Network.from_text(net.to_text())
+    x, status, stats = solve_cells(ab, g, cells, dev)
+    assert status[0] == 0 and np.array_equal(x[0], cells.x0[0]) and stats["n_steps"][0] == 0
+    assert status[6] == 4
+    refs = oracle_cells(net, cells.subset([1, 2, 3, 4, 5]))
+    for j, c in enumerate([1, 2, 3, 4, 5]):
+        assert status[c] == 0
+        assert stats["t"][c] == cells.t_end[c]
+        assert rel_err_above(x[c], refs[j].x) <= TOL
+
+
+def test_nonfinite_input_and_step_limit(ab, dev):
+    net = synth.network_for_config("small")
+    cells = synth.Cells.concat([synth.single_cell(net)] * 3)
+    cells.x0[1, 2] = np.nan
+    g = ab.Network.from_text(net.to_text())
+    x, status, stats = solve_cells(ab, g, cells, dev, max_steps=5)
+    assert status[1] == 4
+    assert status[0] == 2 and status[2] == 2
+    assert stats["n_attempts"][0] == 5
+
+
+def test_empty_batch(ab, dev):
+    import torch
+    net = synth.network_for_config("small")
+    g = ab.Network.from_text(net.to_text())
+    z = torch.zeros((0,), dtype=torch.float64, device=dev)
+    x, status = ab.solve(g, z, z, z, z, z, torch.zeros((0, 12), dtype=torch.float64, device=dev), z)
+    assert x.shape == (0, 12) and status.shape == (0,)
+
+
+def test_deterministic_and_independent_of_batch_composition(ab, dev):
+    """A cell's result is bitwise the same alone, in a batch, and when the
+    workspace budget forces slots to be refilled (continuous batching)."""
+    net = synth.network_for_config("net200")
+    cells = synth.sample_cells(net, 9, seed=5)
+    g = ab.Network.from_text(net.to_text())
+    x1, s1, _ = solve_cells(ab, g, cells, dev)
+    x2, s2, _ = solve_cells(ab, g, cells, dev)
+    assert np.array_equal(x1, x2) and np.array_equal(s1, s2)
+    per_slot = 8 * (net.n_reactions + 13 * net.n_species + 208 * 208) + 4096
+    x3, s3, _ = solve_cells(ab, g, cells, dev, hbm_budget_bytes=2 * per_slot)
+    assert np.array_equal(x1, x3)
+    alone, _, _ = solve_cells(ab, g, cells.subset([4]), dev)
+    assert np.array_equal(alone[0], x1[4])
