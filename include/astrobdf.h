@@ -182,6 +182,30 @@ abdf_status abdf_lu_factor(int32_t n, int64_t batch, double *A, int32_t *perm,
 abdf_status abdf_lu_solve(int32_t n, int64_t batch, const double *LU, const int32_t *perm,
                           double *b, void *stream);
 
+/* ------------------------------------------------------------- profiling --
+ * Process-wide kernel timers: while enabled, the solver brackets each of its
+ * kernel launches with HIP events on the launch stream and accumulates the
+ * durations per kernel family when it next synchronises.
+ */
+enum {
+    ABDF_PROF_ADMIT = 0,    /* admission: rates, starting step, first attempt */
+    ABDF_PROF_FACTOR = 1,   /* Newton-matrix assembly + LU factorisation */
+    ABDF_PROF_NEWTON = 2,   /* one Newton iteration: RHS, residual, triangular solves */
+    ABDF_PROF_CONTROL = 3,  /* error test, step/order control, next predictor */
+    ABDF_PROF_HARVEST = 4,  /* copy-out of finished cells */
+    ABDF_PROF_KINDS = 5
+};
+
+typedef struct abdf_profile {
+    int64_t launches[8];    /* kernel launches per family */
+    double ms[8];           /* summed launch durations [ms] per family */
+} abdf_profile;
+
+/* Turns the timers on (nonzero) or off. */
+void abdf_profile_enable(int32_t on);
+/* Copies the accumulated timers; clears them when reset is nonzero. */
+void abdf_profile_read(abdf_profile *out, int32_t reset);
+
 /* Checks on the device that the matrix-core lane layouts the kernels assume
  * hold (FP64 and FP32).  ABDF_OK if they do, ABDF_E_DEVICE otherwise. */
 abdf_status abdf_selftest(void *stream);

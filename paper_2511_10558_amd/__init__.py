@@ -214,5 +214,17 @@ def lu_solve(LU, perm, b):
     return z
 
 
+def profile_enable(on: bool = True):
+    """Turns the library's per-kernel-family HIP-event timers on or off."""
+    _lib.lib().abdf_profile_enable(1 if on else 0)
+
+
+def profile_read(reset: bool = False) -> dict:
+    """{family: (launches, total_ms)} accumulated by the kernel timers."""
+    p = _lib.Profile()
+    _lib.lib().abdf_profile_read(ctypes.byref(p), 1 if reset else 0)
+    return {k: (int(p.launches[i]), float(p.ms[i])) for i, k in enumerate(_lib.PROFILE_KINDS)}
+
+
 def selftest():
     _check(_lib.lib().abdf_selftest(_stream()))

@@ -39,6 +39,12 @@ class CellStats(ctypes.Structure):
     ]
 
 
+class Profile(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_int64 * 8), ("ms", ctypes.c_double * 8)]
+
+
+PROFILE_KINDS = ("admit", "factor", "newton", "control", "harvest")
+
 # name -> (restype, argtypes); mirrors include/astrobdf.h
 SIGNATURES = {
     "abdf_options_default": (None, [ctypes.POINTER(Options)]),
@@ -60,6 +66,8 @@ SIGNATURES = {
                                       ctypes.c_int32, c_void_p]),
     "abdf_lu_solve": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, c_void_p, c_void_p, c_void_p, c_void_p]),
     "abdf_selftest": (ctypes.c_int, [c_void_p]),
+    "abdf_profile_enable": (None, [ctypes.c_int32]),
+    "abdf_profile_read": (None, [ctypes.POINTER(Profile), ctypes.c_int32]),
 }
 
 _LIB = None

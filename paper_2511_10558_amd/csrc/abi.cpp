@@ -273,6 +273,13 @@ abdf_status abdf_lu_solve(int32_t n, int64_t batch, const double *LU, const int3
     return ok();
 }
 
+void abdf_profile_enable(int32_t on) { abdf::Profiler::enable(on != 0); }
+
+void abdf_profile_read(abdf_profile *out, int32_t reset) {
+    if (!out) return;
+    abdf::Profiler::read(out->launches, out->ms, reset != 0);
+}
+
 abdf_status abdf_selftest(void *stream) {
     int *bad = nullptr;
     HIP_OR_FAIL(hipMalloc(reinterpret_cast<void **>(&bad), sizeof(int)));

@@ -9,8 +9,10 @@
 // finished results out, and refills freed slots with pending cells.
 #include "engine.hpp"
 
-#include <cstring>
+#include <atomic>
 #include <cmath>
+#include <cstring>
+#include <mutex>
 
 #include "../../include/astrobdf.h"
 
@@ -29,10 +31,79 @@ size_t align256(size_t b) { return (b + 255) / 256 * 256; }
     } while (0)
 }  // namespace
 
+namespace {
+std::atomic<bool> g_prof_on{false};
+std::mutex g_prof_mu;
+int64_t g_prof_launches[8];
+double g_prof_ms[8];
+}  // namespace
+
+bool Profiler::on() { return g_prof_on.load(std::memory_order_relaxed); }
+void Profiler::enable(bool v) { g_prof_on.store(v); }
+void Profiler::add(int kind, double ms) {
+    std::lock_guard<std::mutex> l(g_prof_mu);
+    g_prof_launches[kind] += 1;
+    g_prof_ms[kind] += ms;
+}
+void Profiler::read(int64_t *launches, double *ms, bool reset) {
+    std::lock_guard<std::mutex> l(g_prof_mu);
+    for (int i = 0; i < 8; ++i) {
+        launches[i] = g_prof_launches[i];
+        ms[i] = g_prof_ms[i];
+        if (reset) { g_prof_launches[i] = 0; g_prof_ms[i] = 0.0; }
+    }
+}
+
+hipEvent_t Engine::timer_begin(hipStream_t st) {
+    if (!Profiler::on()) return nullptr;
+    hipEvent_t e = nullptr;
+    if (!event_pool_.empty()) {
+        e = event_pool_.back();
+        event_pool_.pop_back();
+    } else if (hipEventCreate(&e) != hipSuccess) {
+        return nullptr;
+    }
+    if (hipEventRecord(e, st) != hipSuccess) {
+        event_pool_.push_back(e);
+        return nullptr;
+    }
+    return e;
+}
+
+void Engine::timer_end(int kind, hipEvent_t a, hipStream_t st) {
+    if (!a) return;
+    hipEvent_t b = nullptr;
+    if (!event_pool_.empty()) {
+        b = event_pool_.back();
+        event_pool_.pop_back();
+    } else if (hipEventCreate(&b) != hipSuccess) {
+        event_pool_.push_back(a);
+        return;
+    }
+    (void)hipEventRecord(b, st);
+    pending_.push_back({kind, a, b});
+}
+
+// Called after the stream has been synchronised.
+void Engine::flush_timers() {
+    for (auto &p : pending_) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) Profiler::add(p.kind, double(ms));
+        event_pool_.push_back(p.a);
+        event_pool_.push_back(p.b);
+    }
+    pending_.clear();
+}
+
 Engine::Engine(const HostNetwork &net, const DeviceNet &dn, int prec, int max_steps)
     : net_(net), dn_(dn), prec_(prec), max_steps_(max_steps) {}
 
 Engine::~Engine() {
+    for (auto &p : pending_) {
+        event_pool_.push_back(p.a);
+        event_pool_.push_back(p.b);
+    }
+    for (hipEvent_t e : event_pool_) (void)hipEventDestroy(e);
     if (base_) (void)hipFree(base_);
     if (h_cnt_) (void)hipHostFree(h_cnt_);
     if (h_fin_) (void)hipHostFree(h_fin_);
@@ -139,7 +210,9 @@ int Engine::admit(const BatchIO &io, const abdf_options &opt, long long &next, h
     a.atol = opt.atol;
     a.newton_tol = opt.newton_tol > 0 ? opt.newton_tol
                                       : std::max(10.0 * kURound / opt.rtol, std::min(0.03, std::sqrt(opt.rtol)));
+    hipEvent_t t0 = timer_begin(st);
     HIP_TRY(launch_admit(s_, dn_, a, ring_, lds_admit_, st));
+    timer_end(0, t0, st);
     // the pinned admission buffers are rewritten only after the next poll's synchronisation
     next += want;
     bound_ += int(want);
@@ -149,6 +222,7 @@ int Engine::admit(const BatchIO &io, const abdf_options &opt, long long &next, h
 int Engine::poll(hipStream_t st, std::string &err) {
     HIP_TRY(hipMemcpyAsync(h_cnt_, s_.cnt, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    flush_timers();
     const int nfin = h_cnt_[6];
     bound_ = h_cnt_[ring_];
     if (nfin > 0) {
@@ -159,7 +233,9 @@ int Engine::poll(hipStream_t st, std::string &err) {
         h.x_out = io_->x_out;
         h.status = io_->status;
         h.stats = io_->stats;
+        hipEvent_t t0 = timer_begin(st);
         HIP_TRY(launch_harvest(s_, h, st));
+        timer_end(4, t0, st);
         HIP_TRY(hipStreamSynchronize(st));
         for (int i = 0; i < nfin; ++i) free_.push_back(h_fin_[i]);
     }
@@ -177,9 +253,17 @@ int Engine::solve(const BatchIO &io, const abdf_options &opt, hipStream_t st, st
     int since_poll = 0;
     while (true) {
         if (bound_ > 0) {
+            hipEvent_t t0 = timer_begin(st);
             HIP_TRY(launch_factor(s_, dn_, ring_, bound_, lds_factor_, st));
-            for (int m = 0; m < kNewtonMaxIter; ++m) HIP_TRY(launch_newton(s_, dn_, ring_, bound_, lds_newton_, st));
+            timer_end(1, t0, st);
+            for (int m = 0; m < kNewtonMaxIter; ++m) {
+                t0 = timer_begin(st);
+                HIP_TRY(launch_newton(s_, dn_, ring_, bound_, lds_newton_, st));
+                timer_end(2, t0, st);
+            }
+            t0 = timer_begin(st);
             HIP_TRY(launch_control(s_, ring_, bound_, st));
+            timer_end(3, t0, st);
             ring_ = (ring_ + 1) % 3;
             ++since_poll;
         }
@@ -193,6 +277,7 @@ int Engine::solve(const BatchIO &io, const abdf_options &opt, hipStream_t st, st
         }
     }
     HIP_TRY(hipStreamSynchronize(st));
+    flush_timers();
     io_ = nullptr;
     return ABDF_OK;
 }

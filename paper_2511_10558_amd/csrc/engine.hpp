@@ -24,6 +24,14 @@ struct BatchIO {
     abdf_cell_stats *stats;
 };
 
+// Process-wide kernel timers (abdf_profile_*).
+struct Profiler {
+    static bool on();
+    static void enable(bool v);
+    static void add(int kind, double ms);
+    static void read(int64_t *launches, double *ms, bool reset);
+};
+
 // A pool of device slots for one network.  Cells are admitted into free
 // slots, integrated by the step-attempt loop, and harvested when finished;
 // freed slots are refilled from the pending cells (continuous batching).
@@ -40,6 +48,10 @@ class Engine {
 
   private:
     int poll(hipStream_t st, std::string &err);
+    // kernel timers: an event before a launch, and after it with its family
+    hipEvent_t timer_begin(hipStream_t st);
+    void timer_end(int kind, hipEvent_t a, hipStream_t st);
+    void flush_timers();
     int admit(const BatchIO &io, const abdf_options &opt, long long &next, hipStream_t st, std::string &err);
 
     const HostNetwork &net_;
@@ -59,6 +71,10 @@ class Engine {
     size_t lds_admit_ = 0, lds_factor_ = 0, lds_newton_ = 0;
     // harvest target of the current solve
     const BatchIO *io_ = nullptr;
+    // kernel timers of launches not yet read back
+    struct Pending { int kind; hipEvent_t a, b; };
+    std::vector<Pending> pending_;
+    std::vector<hipEvent_t> event_pool_;
 };
 
 }  // namespace abdf
