@@ -228,47 +228,47 @@ abdf_status abdf_newton_matrix(const abdf_network *net, int64_t n_cells, const d
 
 abdf_status abdf_lu_factor(int32_t n, int64_t batch, double *A, int32_t *perm, int32_t *info, int32_t precision,
                            void *stream) {
-    if (n < 1 || n > 4096 || batch < 0 || batch > 65535) return fail(ABDF_E_ARG, "n or batch out of range");
+    if (n < 1 || n > 512 || batch < 0 || batch > 65535) return fail(ABDF_E_ARG, "n or batch out of range");
     if (precision != ABDF_PREC_FP64 && precision != ABDF_PREC_FP32_LU) return fail(ABDF_E_ARG, "unknown precision");
     if (batch == 0) return ok();
     CHECK_DEV(A, "A");
     CHECK_DEV(perm, "perm");
     if (info) CHECK_DEV(info, "info");
     const int NP = (n + 15) / 16 * 16;
-    if (abdf::lu_work_lds(NP, precision) > abdf::kMaxLds) return fail(ABDF_E_ARG, "n too large");
     const size_t elt = precision == ABDF_PREC_FP32_LU ? sizeof(float) : sizeof(double);
-    void *W = nullptr;
+    void *W = nullptr, *dinv = nullptr;
     int32_t *permW = nullptr;
-    HIP_OR_FAIL(hipMalloc(&W, size_t(batch) * NP * NP * elt));
-    hipError_t e = hipMalloc(reinterpret_cast<void **>(&permW), size_t(batch) * NP * sizeof(int32_t));
-    if (e != hipSuccess) { (void)hipFree(W); return fail(ABDF_E_NOMEM, hipGetErrorString(e)); }
+    hipError_t e = hipMalloc(&W, size_t(batch) * NP * NP * elt);
+    if (e == hipSuccess) e = hipMalloc(&dinv, size_t(batch) * abdf::dinv_bytes(NP, precision));
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&permW), size_t(batch) * NP * sizeof(int32_t));
     hipStream_t st = static_cast<hipStream_t>(stream);
-    e = abdf::launch_lu_factor(n, NP, batch, A, W, permW, perm, info, precision, st);
+    if (e == hipSuccess) e = abdf::launch_lu_factor(n, NP, batch, A, W, permW, perm, dinv, info, precision, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    (void)hipFree(W);
-    (void)hipFree(permW);
+    if (W) (void)hipFree(W);
+    if (dinv) (void)hipFree(dinv);
+    if (permW) (void)hipFree(permW);
     if (e != hipSuccess) return fail(ABDF_E_DEVICE, hipGetErrorString(e));
     return ok();
 }
 
 abdf_status abdf_lu_solve(int32_t n, int64_t batch, const double *LU, const int32_t *perm, double *b, void *stream) {
-    if (n < 1 || n > 4096 || batch < 0 || batch > 65535) return fail(ABDF_E_ARG, "n or batch out of range");
+    if (n < 1 || n > 512 || batch < 0 || batch > 65535) return fail(ABDF_E_ARG, "n or batch out of range");
     if (batch == 0) return ok();
     CHECK_DEV(LU, "LU");
     CHECK_DEV(perm, "perm");
     CHECK_DEV(b, "b");
     const int NP = (n + 15) / 16 * 16;
-    if (2 * NP * sizeof(double) > abdf::kMaxLds) return fail(ABDF_E_ARG, "n too large");
-    void *W = nullptr;
+    void *W = nullptr, *dinv = nullptr;
     int32_t *permW = nullptr;
-    HIP_OR_FAIL(hipMalloc(&W, size_t(batch) * NP * NP * sizeof(double)));
-    hipError_t e = hipMalloc(reinterpret_cast<void **>(&permW), size_t(batch) * NP * sizeof(int32_t));
-    if (e != hipSuccess) { (void)hipFree(W); return fail(ABDF_E_NOMEM, hipGetErrorString(e)); }
+    hipError_t e = hipMalloc(&W, size_t(batch) * NP * NP * sizeof(double));
+    if (e == hipSuccess) e = hipMalloc(&dinv, size_t(batch) * abdf::dinv_bytes(NP, ABDF_PREC_FP64));
+    if (e == hipSuccess) e = hipMalloc(reinterpret_cast<void **>(&permW), size_t(batch) * NP * sizeof(int32_t));
     hipStream_t st = static_cast<hipStream_t>(stream);
-    e = abdf::launch_lu_solve(n, NP, batch, LU, perm, b, W, permW, st);
+    if (e == hipSuccess) e = abdf::launch_lu_solve(n, NP, batch, LU, perm, b, W, permW, dinv, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    (void)hipFree(W);
-    (void)hipFree(permW);
+    if (W) (void)hipFree(W);
+    if (dinv) (void)hipFree(dinv);
+    if (permW) (void)hipFree(permW);
     if (e != hipSuccess) return fail(ABDF_E_DEVICE, hipGetErrorString(e));
     return ok();
 }

@@ -27,7 +27,7 @@ __device__ inline void cell_rates(const DeviceNet &n, const double *phi, double 
 // f = nu . rate(x) for one cell.  x in LDS; k in global memory (one coalesced
 // pass); rate[R] and part[n_seg] are LDS scratch; f may be LDS or global.
 // Deterministic: every sum runs in a fixed order.
-__device__ inline void cell_rhs(const DeviceNet &n, const double *__restrict__ k, const double *x,
+__device__ __forceinline__ void cell_rhs(const DeviceNet &n, const double *__restrict__ k, const double *x,
                                 double *rate, double *part, double *f) {
     for (int r = threadIdx.x; r < n.R; r += kBlock) {
         const int ab = n.rx_ab[r];
@@ -58,7 +58,7 @@ __device__ inline void cell_rhs(const DeviceNet &n, const double *__restrict__ k
 // One row i of M = I - c J(x) into rowbuf[NP] (LDS, owned by the calling wave),
 // then to the matrix row in global memory as T.  Rows i >= S are identity.
 template <typename T>
-__device__ inline void newton_matrix_row(const DeviceNet &n, const double *__restrict__ k, const double *x,
+__device__ __forceinline__ void newton_matrix_row(const DeviceNet &n, const double *__restrict__ k, const double *x,
                                          double c, int i, double *rowbuf, T *Mrow) {
     const int lane = threadIdx.x & 63;
     for (int j = lane; j < n.NP; j += 64) rowbuf[j] = 0.0;

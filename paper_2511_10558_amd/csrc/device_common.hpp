@@ -43,7 +43,8 @@ struct Slots {
     double *psi;      // [n][S]
     double *scl;      // [n][S] Newton weights atol + rtol |x_p|
     double *xJ;       // [n][S] point of the current Jacobian
-    void *lu;         // [n][NP][NP] factors (double or float)
+    void *lu;         // [n][NP][NP] factors (double or float), rows in storage order
+    void *dinv;       // [n][NB][2][64][64] inverses of the diagonal blocks' triangles
     int32_t *perm;    // [n][NP]
     int32_t *act;     // [3][n] active-slot lists (ring)
     int32_t *lul;     // [3][n] slots needing a factorisation (ring)

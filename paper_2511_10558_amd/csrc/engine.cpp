@@ -115,20 +115,20 @@ size_t Engine::bytes_per_slot(const DeviceNet &dn, int prec) {
     const size_t S = dn.S, R = dn.R, NP = dn.NP;
     const size_t elt = prec == ABDF_PREC_FP32_LU ? sizeof(float) : sizeof(double);
     return sizeof(SlotCtl) + 5 * sizeof(double) + R * sizeof(double) + kDRows * S * sizeof(double) +
-           5 * S * sizeof(double) + NP * NP * elt + NP * sizeof(int32_t) + 7 * sizeof(int32_t) +
-           sizeof(long long);
+           5 * S * sizeof(double) + NP * NP * elt + dinv_bytes(int(NP), prec) + NP * sizeof(int32_t) +
+           7 * sizeof(int32_t) + sizeof(long long);
 }
 
 int Engine::init(int nslots, std::string &err) {
     const size_t n = size_t(nslots), S = dn_.S, R = dn_.R, NP = dn_.NP;
     const size_t elt = prec_ == ABDF_PREC_FP32_LU ? sizeof(float) : sizeof(double);
     struct Part { void **dst; size_t bytes; };
-    void *ctl, *phi, *k, *D, *x, *d, *psi, *scl, *xJ, *lu, *perm, *act, *lul, *fin, *cnt, *aslots, *acells;
+    void *ctl, *phi, *k, *D, *x, *d, *psi, *scl, *xJ, *lu, *dinv, *perm, *act, *lul, *fin, *cnt, *aslots, *acells;
     Part parts[] = {
         {&ctl, n * sizeof(SlotCtl)}, {&phi, n * 5 * sizeof(double)}, {&k, n * R * sizeof(double)},
         {&D, n * kDRows * S * sizeof(double)}, {&x, n * S * sizeof(double)}, {&d, n * S * sizeof(double)},
         {&psi, n * S * sizeof(double)}, {&scl, n * S * sizeof(double)}, {&xJ, n * S * sizeof(double)},
-        {&lu, n * NP * NP * elt}, {&perm, n * NP * sizeof(int32_t)}, {&act, 3 * n * sizeof(int32_t)},
+        {&lu, n * NP * NP * elt}, {&dinv, n * dinv_bytes(int(NP), prec_)}, {&perm, n * NP * sizeof(int32_t)}, {&act, 3 * n * sizeof(int32_t)},
         {&lul, 3 * n * sizeof(int32_t)}, {&fin, n * sizeof(int32_t)}, {&cnt, 8 * sizeof(int32_t)},
         {&aslots, n * sizeof(int32_t)}, {&acells, n * sizeof(long long)},
     };
@@ -162,6 +162,7 @@ int Engine::init(int nslots, std::string &err) {
     s_.scl = static_cast<double *>(scl);
     s_.xJ = static_cast<double *>(xJ);
     s_.lu = lu;
+    s_.dinv = dinv;
     s_.perm = static_cast<int32_t *>(perm);
     s_.act = static_cast<int32_t *>(act);
     s_.lul = static_cast<int32_t *>(lul);
@@ -176,7 +177,7 @@ int Engine::init(int nslots, std::string &err) {
     lds_admit_ = admit_lds(dn_);
     lds_factor_ = factor_lds(dn_, prec_);
     lds_newton_ = newton_lds(dn_);
-    if (lds_admit_ > kMaxLds || lds_factor_ > kMaxLds || lds_newton_ > kMaxLds) {
+    if (dn_.NP > 512 || lds_admit_ > kMaxLds || lds_factor_ > kMaxLds || lds_newton_ > kMaxLds) {
         err = "network too large for one workgroup's LDS";
         return ABDF_E_ARG;
     }

@@ -20,6 +20,7 @@
 #include "device_chem.hpp"
 #include "device_common.hpp"
 #include "device_lu.hpp"
+#include "device_lu2.hpp"
 
 #include "../../include/astrobdf.h"
 
@@ -57,7 +58,7 @@ __device__ inline void interp_product(int q, double rho, double *RU) {
 }
 
 // Rows 0..q of D (one slot) from spacing h to rho*h.  Cooperative.
-__device__ inline void rescale_D(double *D, int S, int q, double rho, double *RU) {
+__device__ __forceinline__ void rescale_D(double *D, int S, int q, double rho, double *RU) {
     if (threadIdx.x == 0) interp_product(q, rho, RU);
     __syncthreads();
     for (int i = threadIdx.x; i < S; i += kBlock) {
@@ -84,7 +85,7 @@ __device__ inline void finish_slot(const Slots &s, int slot, SlotCtl &cs, int st
 // Starts the next step attempt of a running slot whose cs (LDS) is current:
 // checks limits, lands on t_end, forms the predictor and queues the slot.
 // Writes cs back to global memory.
-__device__ void begin_attempt(const Slots &s, int slot, SlotCtl &cs, int ring, double *RU, double *sh) {
+__device__ __forceinline__ void begin_attempt(const Slots &s, int slot, SlotCtl &cs, int ring, double *RU, double *sh) {
     const int S = s.S;
     double *D = s.D + size_t(slot) * kDRows * S;
     if (threadIdx.x == 0) {
@@ -258,9 +259,10 @@ __global__ void __launch_bounds__(kBlock) k_admit(Slots s, DeviceNet n, AdmitArg
     begin_attempt(s, slot, cs, ring, RU, sh);
 }
 
-// Forms M = I - c J(x_J) for every queued slot and factors it.
+// Forms M = I - c J(x_J) for every queued slot and factors it (one
+// 1024-thread workgroup per matrix).
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_factor(Slots s, DeviceNet n, int ring) {
+__global__ void __launch_bounds__(kLuThreads) k_factor(Slots s, DeviceNet n, int ring) {
     extern __shared__ double smem[];
     const int idx = blockIdx.x;
     if (idx >= s.cnt[3 + ring]) return;
@@ -270,13 +272,16 @@ __global__ void __launch_bounds__(kBlock) k_factor(Slots s, DeviceNet n, int rin
     double *xs = smem;
     double *rowbuf = xs + S;
     const double *k = s.k + size_t(slot) * n.R;
-    for (int i = threadIdx.x; i < S; i += kBlock) xs[i] = s.xJ[size_t(slot) * S + i];
+    for (int i = threadIdx.x; i < S; i += kLuThreads) xs[i] = s.xJ[size_t(slot) * S + i];
     __syncthreads();
     T *A = reinterpret_cast<T *>(s.lu) + size_t(slot) * NP * NP;
     const int wave = threadIdx.x >> 6;
-    for (int i = wave; i < NP; i += kWaves) newton_matrix_row<T>(n, k, xs, c, i, rowbuf + wave * NP, A + size_t(i) * NP);
+    for (int i = wave; i < NP; i += kLuWaves)
+        newton_matrix_row<T>(n, k, xs, c, i, rowbuf + wave * NP, A + size_t(i) * NP);
     __syncthreads();
-    lu_factor_wg<T>(A, NP, s.perm + size_t(slot) * NP, nullptr, reinterpret_cast<unsigned char *>(smem));
+    lu_factor_left<T>(A, NP, s.perm + size_t(slot) * NP,
+                      reinterpret_cast<T *>(s.dinv) + size_t(slot) * lu2_dinv_elems<T>(NP), nullptr,
+                      reinterpret_cast<unsigned char *>(smem));
     if (threadIdx.x == 0) {
         s.ctl[slot].c_lu = c;
         s.ctl[slot].lu_valid = 1;
@@ -288,7 +293,7 @@ __global__ void __launch_bounds__(kBlock) k_factor(Slots s, DeviceNet n, int rin
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_newton(Slots s, DeviceNet n, int ring) {
     extern __shared__ double smem[];
-    __shared__ double red[16 + kWaves];
+    __shared__ double red[kLuW + kWaves];
     __shared__ int decision;
     const int idx = blockIdx.x;
     if (idx >= s.cnt[ring]) return;
@@ -315,7 +320,7 @@ __global__ void __launch_bounds__(kBlock) k_newton(Slots s, DeviceNet n, int rin
             b[i] = 0.0;
         }
     }
-    nonfinite = block_any(nonfinite, red + 16);
+    nonfinite = block_any(nonfinite, red + kLuW);
     SlotCtl &g = s.ctl[slot];
     if (nonfinite) {
         if (threadIdx.x == 0) {
@@ -327,14 +332,16 @@ __global__ void __launch_bounds__(kBlock) k_newton(Slots s, DeviceNet n, int rin
         }
         return;
     }
-    lu_solve_wg<T>(reinterpret_cast<const T *>(s.lu) + size_t(slot) * NP * NP, s.perm + size_t(slot) * NP, NP, b,
-                   y, red);
+    const int32_t *perm = s.perm + size_t(slot) * NP;
+    lu_solve_left<T>(reinterpret_cast<const T *>(s.lu) + size_t(slot) * NP * NP,
+                     reinterpret_cast<const T *>(s.dinv) + size_t(slot) * lu2_dinv_elems<T>(NP), perm, perm, NP, b,
+                     y, red);
     double acc = 0.0;
     for (int i = threadIdx.x; i < S; i += kBlock) {
         const double v = y[i] / scl[i];
         acc += v * v;
     }
-    const double eta = sqrt(block_sum(acc, red + 16) / S);
+    const double eta = sqrt(block_sum(acc, red + kLuW) / S);
     if (threadIdx.x == 0) {
         const int m = g.newton_iter + 1;
         const double tol = g.newton_tol;
@@ -574,12 +581,14 @@ __global__ void k_pad_in(int n, int NP, const double *A, T *W) {
     }
 }
 
+// Factors (rows in storage order, row i of P A at storage row permW[i]) back
+// to the LAPACK layout: row i of the output is row i of P A.
 template <typename T>
 __global__ void k_pad_out(int n, int NP, const T *W, double *A, const int32_t *permW, int32_t *perm) {
     const long long b = blockIdx.y;
     for (long long e = blockIdx.x * blockDim.x + threadIdx.x; e < (long long)n * n; e += gridDim.x * blockDim.x) {
         const int i = int(e / n), j = int(e % n);
-        A[(b * n + i) * n + j] = double(W[b * NP * NP + (long long)i * NP + j]);
+        A[(b * n + i) * n + j] = double(W[b * NP * NP + (long long)permW[b * NP + i] * NP + j]);
     }
     if (blockIdx.x == 0)
         for (int i = threadIdx.x; i < n; i += blockDim.x) perm[b * n + i] = permW[b * NP + i];
@@ -591,22 +600,41 @@ __global__ void k_copy_perm(int n, int NP, const int32_t *perm, int32_t *permW) 
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_lu_factor_only(int NP, T *W, int32_t *permW, int32_t *info) {
+__global__ void __launch_bounds__(kLuThreads) k_lu_factor_only(int NP, T *W, int32_t *permW, T *dinv,
+                                                              int32_t *info) {
     extern __shared__ double smem[];
     const long long b = blockIdx.x;
-    lu_factor_wg<T>(W + b * NP * NP, NP, permW + b * NP, info ? info + b : nullptr,
-                    reinterpret_cast<unsigned char *>(smem));
+    lu_factor_left<T>(W + b * NP * NP, NP, permW + b * NP, dinv + b * lu2_dinv_elems<T>(NP),
+                      info ? info + b : nullptr, reinterpret_cast<unsigned char *>(smem));
 }
 
-__global__ void __launch_bounds__(kBlock) k_lu_solve_only(int NP, int n, const double *W, const int32_t *permW,
-                                                          double *bvec) {
+// Inverse diagonal blocks of LAPACK-layout factors (rows already in P A order).
+__global__ void __launch_bounds__(kBlock) k_dinv_only(int NP, const double *W, double *dinv) {
     extern __shared__ double smem[];
-    __shared__ double red[16];
+    const long long b = blockIdx.x;
+    double *Cb = smem, *Xb = Cb + kLuW * kLdb, *Yb = Xb + kLuW * kLdb;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int j = 0; j * kLuW < NP; ++j) {
+        const int r0 = j * kLuW, Wj = min(kLuW, NP - r0);
+        for (int e = threadIdx.x; e < Wj * Wj; e += kBlock)
+            Cb[(e / Wj) * kLdb + e % Wj] = W[b * NP * NP + size_t(r0 + e / Wj) * NP + r0 + e % Wj];
+        __syncthreads();
+        diag_inverses<double>(Cb, Wj, dinv + b * lu2_dinv_elems<double>(NP) + size_t(j) * 2 * kLuW * kLuW, Xb, Yb,
+                              wave, lane);
+        __syncthreads();
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_lu_solve_only(int NP, int n, const double *W, const double *dinv,
+                                                          const int32_t *permW, double *bvec) {
+    extern __shared__ double smem[];
+    __shared__ double t[kLuW];
     const long long bi = blockIdx.x;
     double *b = smem, *y = b + NP;
     for (int i = threadIdx.x; i < NP; i += kBlock) b[i] = i < n ? bvec[bi * n + i] : 0.0;
     __syncthreads();
-    lu_solve_wg<double>(W + bi * NP * NP, permW + bi * NP, NP, b, y, red);
+    lu_solve_left<double>(W + bi * NP * NP, dinv + bi * lu2_dinv_elems<double>(NP), nullptr, permW + bi * NP, NP, b,
+                          y, t);
     for (int i = threadIdx.x; i < n; i += kBlock) bvec[bi * n + i] = y[i];
 }
 
@@ -636,11 +664,16 @@ __global__ void k_selftest(int *bad) {
 // ------------------------------------------------------------- launchers --
 
 size_t lu_work_lds(int NP, int prec) {
-    return prec == ABDF_PREC_FP32_LU ? lu_lds_bytes<float>(NP) : lu_lds_bytes<double>(NP);
+    return prec == ABDF_PREC_FP32_LU ? lu2_lds_bytes<float>(NP) : lu2_lds_bytes<double>(NP);
 }
 
 size_t factor_lds(const DeviceNet &n, int prec) {
-    return std::max(sizeof(double) * (size_t(n.S) + kWaves * size_t(n.NP)), lu_work_lds(n.NP, prec));
+    return std::max(sizeof(double) * (size_t(n.S) + kLuWaves * size_t(n.NP)), lu_work_lds(n.NP, prec));
+}
+
+size_t dinv_bytes(int NP, int prec) {
+    return prec == ABDF_PREC_FP32_LU ? lu2_dinv_elems<float>(NP) * sizeof(float)
+                                     : lu2_dinv_elems<double>(NP) * sizeof(double);
 }
 
 #define LAUNCH_CHECK() hipGetLastError()
@@ -654,9 +687,9 @@ hipError_t launch_admit(const Slots &s, const DeviceNet &n, const AdmitArgs &a, 
 hipError_t launch_factor(const Slots &s, const DeviceNet &n, int ring, int grid, size_t lds, hipStream_t st) {
     if (grid == 0) return hipSuccess;
     if (s.prec == ABDF_PREC_FP32_LU)
-        hipLaunchKernelGGL(k_factor<float>, dim3(grid), dim3(kBlock), lds, st, s, n, ring);
+        hipLaunchKernelGGL(k_factor<float>, dim3(grid), dim3(kLuThreads), lds, st, s, n, ring);
     else
-        hipLaunchKernelGGL(k_factor<double>, dim3(grid), dim3(kBlock), lds, st, s, n, ring);
+        hipLaunchKernelGGL(k_factor<double>, dim3(grid), dim3(kLuThreads), lds, st, s, n, ring);
     return LAUNCH_CHECK();
 }
 
@@ -698,29 +731,31 @@ hipError_t launch_newton_matrix(const DeviceNet &n, long long cells, const doubl
 }
 
 hipError_t launch_lu_factor(int n, int NP, long long batch, double *A, void *W, int32_t *permW, int32_t *perm,
-                            int32_t *info, int prec, hipStream_t st) {
+                            void *dinv, int32_t *info, int prec, hipStream_t st) {
     dim3 g(std::max(1, std::min(64, (NP * NP + 255) / 256)), unsigned(batch));
     if (prec == ABDF_PREC_FP32_LU) {
         hipLaunchKernelGGL(k_pad_in<float>, g, dim3(256), 0, st, n, NP, A, (float *)W);
-        hipLaunchKernelGGL(k_lu_factor_only<float>, dim3(batch), dim3(kBlock), lu_lds_bytes<float>(NP), st, NP,
-                           (float *)W, permW, info);
+        hipLaunchKernelGGL(k_lu_factor_only<float>, dim3(batch), dim3(kLuThreads), lu2_lds_bytes<float>(NP), st, NP,
+                           (float *)W, permW, (float *)dinv, info);
         hipLaunchKernelGGL(k_pad_out<float>, g, dim3(256), 0, st, n, NP, (const float *)W, A, permW, perm);
     } else {
         hipLaunchKernelGGL(k_pad_in<double>, g, dim3(256), 0, st, n, NP, A, (double *)W);
-        hipLaunchKernelGGL(k_lu_factor_only<double>, dim3(batch), dim3(kBlock), lu_lds_bytes<double>(NP), st, NP,
-                           (double *)W, permW, info);
+        hipLaunchKernelGGL(k_lu_factor_only<double>, dim3(batch), dim3(kLuThreads), lu2_lds_bytes<double>(NP), st,
+                           NP, (double *)W, permW, (double *)dinv, info);
         hipLaunchKernelGGL(k_pad_out<double>, g, dim3(256), 0, st, n, NP, (const double *)W, A, permW, perm);
     }
     return LAUNCH_CHECK();
 }
 
 hipError_t launch_lu_solve(int n, int NP, long long batch, const double *LU, const int32_t *perm, double *b,
-                           void *W, int32_t *permW, hipStream_t st) {
+                           void *W, int32_t *permW, void *dinv, hipStream_t st) {
     dim3 g(std::max(1, std::min(64, (NP * NP + 255) / 256)), unsigned(batch));
     hipLaunchKernelGGL(k_pad_in<double>, g, dim3(256), 0, st, n, NP, LU, (double *)W);
     hipLaunchKernelGGL(k_copy_perm, dim3(unsigned(batch)), dim3(256), 0, st, n, NP, perm, permW);
+    hipLaunchKernelGGL(k_dinv_only, dim3(batch), dim3(kBlock), sizeof(double) * 3 * kLuW * kLdb, st, NP,
+                       (const double *)W, (double *)dinv);
     hipLaunchKernelGGL(k_lu_solve_only, dim3(batch), dim3(kBlock), sizeof(double) * 2 * NP, st, NP, n,
-                       (const double *)W, permW, b);
+                       (const double *)W, (const double *)dinv, permW, b);
     return LAUNCH_CHECK();
 }
 

@@ -51,9 +51,10 @@ hipError_t launch_rhs(const DeviceNet &n, long long cells, const double *k, cons
 hipError_t launch_newton_matrix(const DeviceNet &n, long long cells, const double *k, const double *x,
                                 const double *c, double *M, hipStream_t st);
 hipError_t launch_lu_factor(int n, int NP, long long batch, double *A, void *W, int32_t *permW, int32_t *perm,
-                            int32_t *info, int prec, hipStream_t st);
+                            void *dinv, int32_t *info, int prec, hipStream_t st);
 hipError_t launch_lu_solve(int n, int NP, long long batch, const double *LU, const int32_t *perm, double *b,
-                           void *W, int32_t *permW, hipStream_t st);
+                           void *W, int32_t *permW, void *dinv, hipStream_t st);
+size_t dinv_bytes(int NP, int prec);
 hipError_t launch_selftest(int *bad, hipStream_t st);
 size_t lu_work_lds(int NP, int prec);
 
