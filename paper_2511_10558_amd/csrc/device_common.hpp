@@ -52,6 +52,34 @@ struct Slots {
     int32_t *cnt;     // [0..2] active counts, [3..5] factor counts, [6] finished count
 };
 
+// One step of a wave-wide arg-max (value descending, key ascending on ties)
+// through a DPP lane permutation; lanes outside the pattern keep their pair.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ void dpp_argmax_step(double &v, int &k) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    const int olo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROW_MASK, 0xf, false);
+    const int ohi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROW_MASK, 0xf, false);
+    const int ok = __builtin_amdgcn_update_dpp(k, k, CTRL, ROW_MASK, 0xf, false);
+    const double ov = __hiloint2double(ohi, olo);
+    if (ov > v || (ov == v && ok < k)) { v = ov; k = ok; }
+}
+
+// Arg-max over the 64 lanes of a wave, returned uniformly to every lane:
+// swaps within quads, half-row and row mirrors, then the row broadcasts
+// that leave the wave's result in lane 63.
+__device__ __forceinline__ void wave_argmax(double &v, int &k) {
+    dpp_argmax_step<0xB1, 0xf>(v, k);    // quad_perm [1,0,3,2]
+    dpp_argmax_step<0x4E, 0xf>(v, k);    // quad_perm [2,3,0,1]
+    dpp_argmax_step<0x141, 0xf>(v, k);   // row_half_mirror
+    dpp_argmax_step<0x140, 0xf>(v, k);   // row_mirror
+    dpp_argmax_step<0x142, 0xa>(v, k);   // row_bcast:15
+    dpp_argmax_step<0x143, 0xc>(v, k);   // row_bcast:31
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), 63);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
+    k = __builtin_amdgcn_readlane(k, 63);
+    v = __hiloint2double(hi, lo);
+}
+
 // Sum over the workgroup, identical on every thread; fixed reduction order.
 __device__ inline double block_sum(double v, double *red) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);

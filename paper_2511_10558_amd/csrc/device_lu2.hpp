@@ -1,4 +1,4 @@
-// Left-looking blocked LU with partial pivoting, one 1024-thread workgroup per
+// Left-looking blocked LU with partial pivoting, one 512-thread workgroup per
 // matrix, and the matching triangular solves.
 //
 // Storage.  The matrix keeps its rows where they are: row r of P A (the
@@ -12,14 +12,16 @@
 //
 // Factorisation of block column j (columns 64j .. 64j + Wj - 1):
 //  1. the block column is gathered (rows through perm) into MFMA accumulator
-//     registers: 16 waves, wave w owns row tiles w and w + 16, all 4 column
-//     tiles of 16;
+//     registers: 8 waves, wave w owns row tiles w, w + 8, w + 16, w + 24, and
+//     all 4 column tiles of 16;
 //  2. for every earlier block i: U_ij = inv(L_ii) C_i (rows 64i..64i+63 of the
 //     block column, staged through LDS), then the rows below block i are
 //     updated C -= L_{:,i} U_ij on the matrix cores, L read from memory;
-//  3. the panel (rows >= 64j) is factored in registers, one column at a time:
-//     arg-max pivot search (ties to the smaller row, as LAPACK), row exchange
-//     through LDS, scaling, rank-1 update;
+//  3. the panel (rows >= 64j) is factored in 16-column sub-panels, one thread
+//     per row: arg-max pivot search (ties to the smaller logical row, as
+//     LAPACK's idamax), scaling and rank-1 update; rows keep their positions
+//     and only their logical labels change; after each sub-panel the rest of
+//     the block column is updated on the matrix cores;
 //  4. the inverses of the diagonal block's triangles are formed and stored,
 //     and the block column is written back through perm.
 #pragma once
@@ -29,10 +31,11 @@
 
 namespace abdf {
 
-constexpr int kLuWaves = 16;
+constexpr int kLuWaves = 8;
 constexpr int kLuThreads = kLuWaves * 64;
 constexpr int kLuW = 64;          // block-column width
-constexpr int kLuMaxNP = 512;     // two row tiles per wave
+constexpr int kLuMaxNP = 512;     // one thread per row in the panel; four row tiles per wave
+constexpr int kSlots = kLuMaxNP / 16 / kLuWaves;
 constexpr int kLdb = 65;          // LDS leading dimension of 64-wide staging buffers
 
 template <typename T>
@@ -56,15 +59,25 @@ __device__ inline int tile_row_reg<double>(int t) { return t >> 2; }
 template <>
 __device__ inline int tile_row_reg<float>(int t) { return t & 3; }
 
+// LDS layout of lu_factor_left (element type T for the staging region).
+constexpr int kPanLd = 17;        // row stride of the 16-column sub-panel buffer
+constexpr int kU12Ld = 49;        // row stride of the 16 x 48 sub-panel U block
+template <typename T>
+__host__ __device__ constexpr size_t lu2_work_elems(int NP) {
+    return size_t(NP) * kPanLd + 16 * kU12Ld > 3 * size_t(kLuW) * kLdb + 1536
+               ? size_t(NP) * kPanLd + 16 * kU12Ld
+               : 3 * size_t(kLuW) * kLdb + 1536;
+}
 template <typename T>
 __host__ __device__ constexpr size_t lu2_lds_bytes(int NP) {
-    return size_t(NP) * sizeof(int32_t)                   // perm
-           + kLuWaves * (sizeof(double) + sizeof(int32_t)) // arg-max partials
-           + 2 * 2 * kLuW * sizeof(T)                     // pivot row / displaced row, double-buffered
-           + 3 * size_t(kLuW) * kLdb * sizeof(T) + 64;    // C_i, U_ij and inverse staging
+    return 5 * size_t(NP) * sizeof(int32_t)                        // perm, sto, pos_log, log_pos, pidx
+           + kLuW * sizeof(int32_t)                                // piv_pos
+           + 2 * kLuWaves * (sizeof(double) + sizeof(int32_t))     // arg-max partials, double-buffered
+           + 2 * kLuWaves * 16 * sizeof(T) + 16                    // candidate pivot rows, double-buffered
+           + lu2_work_elems<T>(NP) * sizeof(T) + 64;
 }
 
-// Bytes of the per-matrix inverse diagonal blocks.
+// Elements of the per-matrix inverse diagonal blocks.
 template <typename T>
 __host__ __device__ constexpr size_t lu2_dinv_elems(int NP) {
     return size_t((NP + kLuW - 1) / kLuW) * 2 * kLuW * kLuW;
@@ -72,37 +85,90 @@ __host__ __device__ constexpr size_t lu2_dinv_elems(int NP) {
 
 // Inverses of the unit-lower and the upper triangle of the W x W diagonal block
 // held in LDS (leading dimension kLdb), written to D[0] and D[1] (64 x 64
-// row-major, global).  Wave 0 forms inv(L) by columns, wave 1 inv(U); Xb and
-// Yb are LDS scratch of 64 x kLdb.
+// row-major, global).  The first half of the threads forms inv(L), the second
+// inv(U), block-recursively on 16 x 16 blocks: the diagonal blocks by
+// substitution (4 lanes per column), then the off-diagonal blocks level by level,
+// X_ij = -X_ii sum_k L_ik X_kj (lower) and Y_ij = -Y_ii sum_k U_ik Y_kj (upper).
+// Xb, Yb: 64 x kLdb LDS outputs; Tb: 2 x 768 LDS scratch.  Every thread of
+// the workgroup must call this (it contains barriers).
 template <typename T>
-__device__ __forceinline__ void diag_inverses(const T *Cb, int W, T *D, T *Xb, T *Yb, int wave, int lane) {
-    if (wave == 0 && lane < W) {
-        const int k = lane;
-        for (int i = 0; i < W; ++i) {
-            double acc2 = 0.0;
-            for (int m = 0; m < i; ++m)
-                if (m >= k) acc2 += double(Cb[i * kLdb + m]) * double(Xb[m * kLdb + k]);
-            const double xv = i < k ? 0.0 : (i == k ? 1.0 : -acc2);
-            Xb[i * kLdb + k] = T(xv);
-            D[i * kLuW + k] = T(xv);
-        }
-    } else if (wave == 1 && lane < W) {
-        const int k = lane;
-        for (int i = W - 1; i >= 0; --i) {
-            double acc2 = 0.0;
-            for (int m = i + 1; m < W; ++m)
-                if (m <= k) acc2 += double(Cb[i * kLdb + m]) * double(Yb[m * kLdb + k]);
-            const double d = double(Cb[i * kLdb + i]);
-            const double yv = i > k ? 0.0 : (i == k ? 1.0 / d : -acc2 / d);
-            Yb[i * kLdb + k] = T(yv);
-            D[kLuW * kLuW + i * kLuW + k] = T(yv);
+__device__ __forceinline__ void diag_inverses(const T *Cb, int W, T *D, T *Xb, T *Yb, T *Tb) {
+    constexpr int HALF = kLuThreads / 2;
+    const int tid = threadIdx.x;
+    const bool upper = tid >= HALF;
+    const int h = tid % HALF;
+    const int nb = W / 16;
+    T *Z = upper ? Yb : Xb;
+    T *Tz = Tb + (upper ? 768 : 0);
+    // zero the outputs
+    for (int e = h; e < 64 * 64; e += HALF) Z[(e >> 6) * kLdb + (e & 63)] = T(0);
+    __syncthreads();
+    // diagonal 16 x 16 blocks
+    {
+        const int ct = h >> 2, t = h & 3;
+        const int b = ct >> 4, kk = 16 * b + (ct & 15);
+        if (b < nb) {
+            if (!upper) {
+                for (int i = 16 * b; i < 16 * b + 16; ++i) {
+                    double acc = 0.0;
+                    for (int m = kk + t; m < i; m += 4) acc += double(Cb[i * kLdb + m]) * double(Z[m * kLdb + kk]);
+                    acc += __shfl_xor(acc, 1);
+                    acc += __shfl_xor(acc, 2);
+                    if (t == 0 && i >= kk) Z[i * kLdb + kk] = T(i == kk ? 1.0 : -acc);
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                }
+            } else {
+                for (int i = 16 * b + 15; i >= 16 * b; --i) {
+                    double acc = 0.0;
+                    for (int m = i + 1 + t; m <= kk; m += 4) acc += double(Cb[i * kLdb + m]) * double(Z[m * kLdb + kk]);
+                    acc += __shfl_xor(acc, 1);
+                    acc += __shfl_xor(acc, 2);
+                    const double d = double(Cb[i * kLdb + i]);
+                    if (t == 0 && i <= kk) Z[i * kLdb + kk] = T(i == kk ? 1.0 / d : -acc / d);
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                }
+            }
         }
     }
+    __syncthreads();
+    // off-diagonal blocks, by distance from the diagonal
+    for (int d = 1; d < nb; ++d) {
+        const int cnt = (nb - d) * 256;
+        for (int e = h; e < cnt; e += HALF) {
+            const int bi = e >> 8, r = (e >> 4) & 15, c = e & 15;
+            double acc = 0.0;
+            if (!upper) {
+                const int i = bi + d, jb = bi;   // block (i, jb), i > jb
+                for (int m = 16 * jb; m < 16 * i; ++m)
+                    acc += double(Cb[(16 * i + r) * kLdb + m]) * double(Z[m * kLdb + 16 * jb + c]);
+            } else {
+                const int i = bi, jb = bi + d;   // block (i, jb), i < jb
+                for (int m = 16 * (i + 1); m < 16 * jb + 16; ++m)
+                    acc += double(Cb[(16 * i + r) * kLdb + m]) * double(Z[m * kLdb + 16 * jb + c]);
+            }
+            Tz[e] = T(acc);
+        }
+        __syncthreads();
+        for (int e = h; e < cnt; e += HALF) {
+            const int bi = e >> 8, r = (e >> 4) & 15, c = e & 15;
+            const int i = upper ? bi : bi + d, jb = upper ? bi + d : bi;
+            double acc = 0.0;
+            for (int m = 0; m < 16; ++m)
+                acc += double(Z[(16 * i + r) * kLdb + 16 * i + m]) * double(Tz[(bi << 8) + (m << 4) + c]);
+            Z[(16 * i + r) * kLdb + 16 * jb + c] = T(-acc);
+        }
+        __syncthreads();
+    }
+    for (int e = h; e < 64 * 64; e += HALF) D[(upper ? kLuW * kLuW : 0) + e] = Z[(e >> 6) * kLdb + (e & 63)];
 }
 
 template <typename T>
-__device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_t *__restrict__ perm_out, T *__restrict__ dinv,
-                               int32_t *info, unsigned char *smem) {
+__device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_t *__restrict__ perm_out,
+                                               T *__restrict__ dinv, int32_t *info, unsigned char *smem) {
     using M = Mfma<T>;
     using acc_t = typename M::acc_t;
     using v4 = typename V4<T>::type;
@@ -111,13 +177,22 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
     const int RT = NP / 16;
     const int NB = (NP + kLuW - 1) / kLuW;
 
-    int32_t *perm = reinterpret_cast<int32_t *>(smem);
-    double *redv = reinterpret_cast<double *>(perm + NP + (NP & 1));
-    int32_t *redi = reinterpret_cast<int32_t *>(redv + kLuWaves);
-    T *rowb = reinterpret_cast<T *>(redi + kLuWaves);           // [2 buffers][2 rows][64]
-    T *Cb = rowb + 2 * 2 * kLuW;                                  // [64][kLdb]
-    T *Ub = Cb + kLuW * kLdb;                                     // [64][kLdb]
-    T *Xb = Ub + kLuW * kLdb;                                     // [64][kLdb] inverse output
+    int32_t *perm = reinterpret_cast<int32_t *>(smem);    // logical row -> storage row
+    int32_t *sto = perm + NP;                              // position -> storage row (this block column)
+    int32_t *pos_log = sto + NP;                           // position -> logical row
+    int32_t *log_pos = pos_log + NP;                       // logical row -> position
+    int32_t *pidx = log_pos + NP;                          // position -> pivot column in this block, or -1
+    int32_t *piv_pos = pidx + NP;                          // pivot column -> position
+    double *redv = reinterpret_cast<double *>(piv_pos + kLuW);   // [2][waves]
+    int32_t *redi = reinterpret_cast<int32_t *>(redv + 2 * kLuWaves);
+    int32_t *rwave = redi + 2 * kLuWaves;                        // [2] wave holding logical row r
+    T *crow = reinterpret_cast<T *>(rwave + 4);                  // [2][waves][16] candidate rows
+    T *work = crow + 2 * kLuWaves * 16;
+    T *Cb = work;                                          // [64][kLdb]   (left-looking, inverses)
+    T *Ub = Cb + kLuW * kLdb;                              // [64][kLdb]
+    T *Xb = Ub + kLuW * kLdb;                              // [64][kLdb]
+    T *P = work;                                           // [NP][kPanLd] (panel)
+    T *U12 = P + size_t(NP) * kPanLd;                      // [16][kU12Ld]
 
     for (int i = tid; i < NP; i += kLuThreads) perm[i] = i;
     int first_zero = 0;
@@ -127,11 +202,17 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
         const int c0 = j * kLuW;
         const int Wj = min(kLuW, NP - c0);
         const int CTj = Wj / 16;
-        acc_t acc[2][4];
-        // 1. gather the block column
+        for (int q = tid; q < NP; q += kLuThreads) {
+            sto[q] = perm[q];
+            pos_log[q] = q;
+            log_pos[q] = q;
+            pidx[q] = -1;
+        }
+        acc_t acc[kSlots][4];
+        // 1. gather the block column (positions = logical rows at this point)
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const int rt = wave + 16 * s;
+        for (int s = 0; s < kSlots; ++s) {
+            const int rt = wave + kLuWaves * s;
 #pragma unroll
             for (int ct = 0; ct < 4; ++ct) {
 #pragma unroll
@@ -149,8 +230,8 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
         for (int i = 0; i < j; ++i) {
             const int r0 = i * kLuW;
 #pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                const int rt = wave + 16 * s;
+            for (int s = 0; s < kSlots; ++s) {
+                const int rt = wave + kLuWaves * s;
                 if (rt >= 4 * i && rt < 4 * i + 4) {
 #pragma unroll
                     for (int ct = 0; ct < 4; ++ct)
@@ -163,22 +244,23 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
             __syncthreads();
             const T *Li = dinv + size_t(i) * 2 * kLuW * kLuW;   // inverse of the unit-lower block i
 #pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                const int rt = wave + 16 * s;
+            for (int s = 0; s < kSlots; ++s) {
+                const int rt = wave + kLuWaves * s;
                 if (rt >= 4 * i && rt < 4 * i + 4) {
                     const int tr = rt - 4 * i;
+                    v4 a[4];
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk)
+                        a[kk] = *reinterpret_cast<const v4 *>(Li + (16 * tr + lc) * kLuW + 16 * kk + 4 * g);
 #pragma unroll
                     for (int ct = 0; ct < 4; ++ct) {
                         if (ct < CTj) {
                             acc_t u = acc_t{0, 0, 0, 0};
 #pragma unroll
-                            for (int kk = 0; kk < 4; ++kk) {
-                                const v4 a =
-                                    *reinterpret_cast<const v4 *>(Li + (16 * tr + lc) * kLuW + 16 * kk + 4 * g);
+                            for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
                                 for (int e = 0; e < 4; ++e)
-                                    u = M::mma(a[e], Cb[(16 * kk + 4 * g + e) * kLdb + 16 * ct + lc], u);
-                            }
+                                    u = M::mma(a[kk][e], Cb[(16 * kk + 4 * g + e) * kLdb + 16 * ct + lc], u);
                             acc[s][ct] = u;
 #pragma unroll
                             for (int v = 0; v < 4; ++v) Ub[(16 * tr + M::row(lane, v)) * kLdb + 16 * ct + lc] = u[v];
@@ -188,171 +270,212 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
             }
             __syncthreads();
 #pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                const int rt = wave + 16 * s;
+            for (int s = 0; s < kSlots; ++s) {
+                const int rt = wave + kLuWaves * s;
                 if (rt >= 4 * (i + 1) && rt < RT) {
                     const T *Lrow = A + size_t(perm[16 * rt + lc]) * NP + r0;
+                    v4 a[4];
 #pragma unroll
-                    for (int kk = 0; kk < 4; ++kk) {
-                        const v4 a = *reinterpret_cast<const v4 *>(Lrow + 16 * kk + 4 * g);
+                    for (int kk = 0; kk < 4; ++kk) a[kk] = *reinterpret_cast<const v4 *>(Lrow + 16 * kk + 4 * g);
+#pragma unroll
+                    for (int kk = 0; kk < 4; ++kk)
 #pragma unroll
                         for (int e = 0; e < 4; ++e)
 #pragma unroll
                             for (int ct = 0; ct < 4; ++ct)
                                 if (ct < CTj)
-                                    acc[s][ct] = M::mma(-a[e], Ub[(16 * kk + 4 * g + e) * kLdb + 16 * ct + lc],
+                                    acc[s][ct] = M::mma(-a[kk][e], Ub[(16 * kk + 4 * g + e) * kLdb + 16 * ct + lc],
                                                         acc[s][ct]);
-                    }
                 }
             }
             __syncthreads();
         }
-        // 3. panel factorisation in registers
-        for (int c = 0; c < Wj; ++c) {
-            const int r = c0 + c;
-            const int ctc = c >> 4;
-            const int buf = c & 1;
-            double bv = -1.0;
-            int bi = 0x7fffffff;
+        // 3. panel factorisation, 16-column sub-panels.  Rows stay at their
+        //    positions; pivoting assigns logical rows to positions.
+#pragma unroll 1
+        for (int sp = 0; sp < CTj; ++sp) {
+            // (a) the sub-panel's column tile to LDS, one row per position
 #pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                const int rt = wave + 16 * s;
-                if (rt < RT && lc == (c & 15)) {
+            for (int s = 0; s < kSlots; ++s) {
+                const int rt = wave + kLuWaves * s;
+                if (rt >= 4 * j && rt < RT)
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        const int row = 16 * rt + M::row(lane, v);
-                        T x = T(0);
+                        T val = acc[s][0][v];
 #pragma unroll
-                        for (int ct = 0; ct < 4; ++ct)
-                            if (ct == ctc) x = acc[s][ct][v];
-                        const double a = fabs(double(x));
-                        if (row >= r && a > bv) { bv = a; bi = row; }
+                        for (int ct = 1; ct < 4; ++ct)
+                            if (ct == sp) val = acc[s][ct][v];
+                        P[(16 * rt + M::row(lane, v)) * kPanLd + lc] = val;
+                    }
+            }
+            __syncthreads();
+            // (b) one thread per position factors the 16 columns.  Each
+            //     thread knows the logical row of its position (mylog); the
+            //     winner of the pivot search among a wave's lanes publishes
+            //     its row, so one barrier per column suffices.
+            const int q = tid;
+            bool active = q >= c0 && q < NP && pidx[q] < 0;
+            const bool participated = active;
+            int mylog = active ? pos_log[q] : 0x7fffffff;
+            T x[16];
+#pragma unroll
+            for (int c = 0; c < 16; ++c) x[c] = active ? P[q * kPanLd + c] : T(0);
+#pragma unroll
+            for (int c = 0; c < 16; ++c) {
+                const int gc = 16 * sp + c;
+                const int r = c0 + gc;
+                const int buf = c & 1;
+                {
+                    const double ax = fabs(double(x[c]));
+                    double bv = (active && ax == ax) ? ax : -1.0;   // NaN never wins
+                    int bl = active ? mylog : 0x7fffffff;
+                    wave_argmax(bv, bl);
+                    if (lane == 0) { redv[buf * kLuWaves + wave] = bv; redi[buf * kLuWaves + wave] = bl; }
+                    if (active && mylog == r) rwave[buf] = wave;
+                    // the wave's candidate row (or row r, kept when nothing is finite)
+                    if (active && mylog == (bv < 0.0 ? r : bl)) {
+#pragma unroll
+                        for (int cc = c; cc < 16; ++cc) crow[(buf * kLuWaves + wave) * 16 + cc] = x[cc];
+                    }
+                }
+                __syncthreads();
+                // cross-wave arg-max: one partial per lane, key = logical row * 8 + wave
+                double fv = lane < kLuWaves ? redv[buf * kLuWaves + lane] : -2.0;
+                int fk = 0x7fffffff;
+                if (lane < kLuWaves && redi[buf * kLuWaves + lane] != 0x7fffffff)
+                    fk = redi[buf * kLuWaves + lane] * 8 + lane;
+                wave_argmax(fv, fk);
+                int lp = fk >> 3, wv = fk & 7;
+                if (fv < 0.0) {          // no finite candidate: keep logical row r
+                    lp = r;
+                    wv = rwave[buf];
+                }
+                const T *urow = crow + (buf * kLuWaves + wv) * 16;
+                const T piv = urow[c];
+                if (tid == 0 && piv == T(0) && first_zero == 0) first_zero = r + 1;
+                if (active) {
+                    if (mylog == lp) {               // this position becomes logical row r
+                        mylog = r;
+                        active = false;
+                        pidx[q] = gc;
+                        piv_pos[gc] = q;
+                    } else {
+                        if (mylog == r) mylog = lp;  // row r moves to the pivot's old logical index
+                        const T l = piv != T(0) ? x[c] / piv : x[c];
+                        x[c] = l;
+#pragma unroll
+                        for (int cc = c + 1; cc < 16; ++cc) x[cc] -= l * urow[cc];
                     }
                 }
             }
-            for (int o = 32; o > 0; o >>= 1) {
-                const double ov = __shfl_xor(bv, o);
-                const int oi = __shfl_xor(bi, o);
-                if (ov > bv || (ov == bv && oi < bi)) { bv = ov; bi = oi; }
-            }
-            if (lane == 0) { redv[wave] = bv; redi[wave] = bi; }
-            __syncthreads();
-            double fv = redv[0];
-            int p = redi[0];
-            for (int w = 1; w < kLuWaves; ++w)
-                if (redv[w] > fv || (redv[w] == fv && redi[w] < p)) { fv = redv[w]; p = redi[w]; }
-            if (fv < 0.0) p = r;   // no finite candidate: keep the row
-            T *urow = rowb + buf * 2 * kLuW;
-            T *rrow = urow + kLuW;
-            // the pivot row and (if it moves) row r, to LDS
-            const int tp = p & 15, tr_ = r & 15;
+            if (participated) {
 #pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                const int rt = wave + 16 * s;
-                if (rt == (p >> 4) && g == tile_row_group<T>(tp)) {
-                    const int vr = tile_row_reg<T>(tp);
-#pragma unroll
-                    for (int ct = 0; ct < 4; ++ct)
-                        if (ct < CTj) {
-                            T x = T(0);
-#pragma unroll
-                            for (int v = 0; v < 4; ++v)
-                                if (v == vr) x = acc[s][ct][v];
-                            urow[16 * ct + lc] = x;
-                        }
-                }
-                if (p != r && rt == (r >> 4) && g == tile_row_group<T>(tr_)) {
-                    const int vr = tile_row_reg<T>(tr_);
-#pragma unroll
-                    for (int ct = 0; ct < 4; ++ct)
-                        if (ct < CTj) {
-                            T x = T(0);
-#pragma unroll
-                            for (int v = 0; v < 4; ++v)
-                                if (v == vr) x = acc[s][ct][v];
-                            rrow[16 * ct + lc] = x;
-                        }
-                }
+                for (int c = 0; c < 16; ++c) P[q * kPanLd + c] = x[c];
+                pos_log[q] = mylog;
             }
             __syncthreads();
-            if (tid == 0 && p != r) {
-                const int t = perm[r];
-                perm[r] = perm[p];
-                perm[p] = t;
-            }
-            const T piv = urow[c];
-            if (tid == 0 && piv == T(0) && first_zero == 0) first_zero = r + 1;
-            T u[4];
+            // (c) back to the accumulators
 #pragma unroll
-            for (int ct = 0; ct < 4; ++ct) u[ct] = ct < CTj ? urow[16 * ct + lc] : T(0);
-#pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                const int rt = wave + 16 * s;
-                if (rt < RT && 16 * rt + 15 >= r) {
-                    // exchange of rows r and p
-                    if (p != r) {
-#pragma unroll
-                        for (int v = 0; v < 4; ++v) {
-                            const int row = 16 * rt + M::row(lane, v);
-                            if (row == r || row == p) {
-#pragma unroll
-                                for (int ct = 0; ct < 4; ++ct)
-                                    if (ct < CTj) acc[s][ct][v] = row == r ? u[ct] : rrow[16 * ct + lc];
-                            }
-                        }
-                    }
-                    // multipliers of column c and the rank-1 update of the rows below r
+            for (int s = 0; s < kSlots; ++s) {
+                const int rt = wave + kLuWaves * s;
+                if (rt >= 4 * j && rt < RT)
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        T x = T(0);
+                        const T val = P[(16 * rt + M::row(lane, v)) * kPanLd + lc];
 #pragma unroll
                         for (int ct = 0; ct < 4; ++ct)
-                            if (ct == ctc) x = acc[s][ct][v];
-                        x = __shfl(x, (lane & 48) | (c & 15));
-                        const int row = 16 * rt + M::row(lane, v);
-                        if (row > r) {
-                            const T l = piv != T(0) ? x / piv : x;
+                            if (ct == sp) acc[s][ct][v] = val;
+                    }
+            }
+            // (d) the remaining column tiles of the block: U12 of this
+            //     sub-panel's pivot rows, then the update of unused rows
+            if (sp + 1 < CTj) {
+                const int nct = CTj - sp - 1;
 #pragma unroll
-                            for (int ct = 0; ct < 4; ++ct) {
-                                const int col = 16 * ct + lc;
-                                if (ct < CTj) {
-                                    if (col == c) acc[s][ct][v] = l;
-                                    else if (col > c) acc[s][ct][v] -= l * u[ct];
+                for (int s = 0; s < kSlots; ++s) {
+                    const int rt = wave + kLuWaves * s;
+                    if (rt >= 4 * j && rt < RT)
+#pragma unroll
+                        for (int ct = 1; ct < 4; ++ct)
+                            if (ct > sp && ct < CTj)
+#pragma unroll
+                                for (int v = 0; v < 4; ++v) {
+                                    const int pi = pidx[16 * rt + M::row(lane, v)] - 16 * sp;
+                                    if (pi >= 0 && pi < 16)
+                                        U12[pi * kU12Ld + 16 * (ct - sp - 1) + lc] = acc[s][ct][v];
+                                }
+                }
+                __syncthreads();
+                if (tid < 16 * nct) {
+                    T u[16];
+#pragma unroll
+                    for (int i2 = 0; i2 < 16; ++i2) u[i2] = U12[i2 * kU12Ld + tid];
+#pragma unroll
+                    for (int i2 = 1; i2 < 16; ++i2) {
+                        const T *Lr = P + piv_pos[16 * sp + i2] * kPanLd;
+#pragma unroll
+                        for (int m = 0; m < i2; ++m) u[i2] -= Lr[m] * u[m];
+                    }
+#pragma unroll
+                    for (int i2 = 0; i2 < 16; ++i2) U12[i2 * kU12Ld + tid] = u[i2];
+                }
+                __syncthreads();
+#pragma unroll
+                for (int s = 0; s < kSlots; ++s) {
+                    const int rt = wave + kLuWaves * s;
+                    if (rt >= 4 * j && rt < RT) {
+                        const bool unused = pidx[16 * rt + lc] < 0;
+                        T a[4];
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) a[e] = unused ? -P[(16 * rt + lc) * kPanLd + 4 * e + g] : T(0);
+#pragma unroll
+                        for (int ct = 1; ct < 4; ++ct) {
+                            if (ct > sp && ct < CTj) {
+#pragma unroll
+                                for (int e = 0; e < 4; ++e)
+                                    acc[s][ct] = M::mma(a[e], U12[(4 * e + g) * kU12Ld + 16 * (ct - sp - 1) + lc],
+                                                        acc[s][ct]);
+#pragma unroll
+                                for (int v = 0; v < 4; ++v) {
+                                    const int pi = pidx[16 * rt + M::row(lane, v)] - 16 * sp;
+                                    if (pi >= 0 && pi < 16) acc[s][ct][v] = U12[pi * kU12Ld + 16 * (ct - sp - 1) + lc];
                                 }
                             }
                         }
                     }
                 }
+                __syncthreads();
             }
         }
-        // 4. diagonal-block inverses and write-back
+        for (int q2 = tid; q2 < NP; q2 += kLuThreads)
+            if (q2 >= c0) perm[pos_log[q2]] = sto[q2];
+        // 4. diagonal block (logical rows c0 .. c0 + Wj - 1) to LDS, its
+        //    triangles' inverses, and the block column back to its storage rows
 #pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const int rt = wave + 16 * s;
-            if (rt >= 4 * j && rt < 4 * j + CTj) {
-#pragma unroll
-                for (int ct = 0; ct < 4; ++ct)
-                    if (ct < CTj)
-#pragma unroll
-                        for (int v = 0; v < 4; ++v)
-                            Cb[(16 * (rt - 4 * j) + M::row(lane, v)) * kLdb + 16 * ct + lc] = acc[s][ct][v];
-            }
-        }
-        __syncthreads();
-        diag_inverses<T>(Cb, Wj, dinv + size_t(j) * 2 * kLuW * kLuW, Xb, Ub, wave, lane);
-#pragma unroll
-        for (int s = 0; s < 2; ++s) {
-            const int rt = wave + 16 * s;
-            if (rt < RT) {
+        for (int s = 0; s < kSlots; ++s) {
+            const int rt = wave + kLuWaves * s;
+            if (rt >= 4 * j && rt < RT)
 #pragma unroll
                 for (int ct = 0; ct < 4; ++ct)
                     if (ct < CTj)
 #pragma unroll
                         for (int v = 0; v < 4; ++v) {
-                            const int row = 16 * rt + M::row(lane, v);
-                            A[size_t(perm[row]) * NP + c0 + 16 * ct + lc] = acc[s][ct][v];
+                            const int lr = pos_log[16 * rt + M::row(lane, v)] - c0;
+                            if (lr >= 0 && lr < Wj) Cb[lr * kLdb + 16 * ct + lc] = acc[s][ct][v];
                         }
-            }
+        }
+        __syncthreads();
+        diag_inverses<T>(Cb, Wj, dinv + size_t(j) * 2 * kLuW * kLuW, Xb, Ub, Xb + kLuW * kLdb);
+#pragma unroll
+        for (int s = 0; s < kSlots; ++s) {
+            const int rt = wave + kLuWaves * s;
+            if (rt < RT)
+#pragma unroll
+                for (int ct = 0; ct < 4; ++ct)
+                    if (ct < CTj)
+#pragma unroll
+                        for (int v = 0; v < 4; ++v)
+                            A[size_t(sto[16 * rt + M::row(lane, v)]) * NP + c0 + 16 * ct + lc] = acc[s][ct][v];
         }
         __syncthreads();
     }

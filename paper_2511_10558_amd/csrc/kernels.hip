@@ -609,18 +609,17 @@ __global__ void __launch_bounds__(kLuThreads) k_lu_factor_only(int NP, T *W, int
 }
 
 // Inverse diagonal blocks of LAPACK-layout factors (rows already in P A order).
-__global__ void __launch_bounds__(kBlock) k_dinv_only(int NP, const double *W, double *dinv) {
+__global__ void __launch_bounds__(kLuThreads) k_dinv_only(int NP, const double *W, double *dinv) {
     extern __shared__ double smem[];
     const long long b = blockIdx.x;
-    double *Cb = smem, *Xb = Cb + kLuW * kLdb, *Yb = Xb + kLuW * kLdb;
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double *Cb = smem, *Xb = Cb + kLuW * kLdb, *Yb = Xb + kLuW * kLdb, *Tb = Yb + kLuW * kLdb;
     for (int j = 0; j * kLuW < NP; ++j) {
         const int r0 = j * kLuW, Wj = min(kLuW, NP - r0);
-        for (int e = threadIdx.x; e < Wj * Wj; e += kBlock)
+        for (int e = threadIdx.x; e < Wj * Wj; e += kLuThreads)
             Cb[(e / Wj) * kLdb + e % Wj] = W[b * NP * NP + size_t(r0 + e / Wj) * NP + r0 + e % Wj];
         __syncthreads();
         diag_inverses<double>(Cb, Wj, dinv + b * lu2_dinv_elems<double>(NP) + size_t(j) * 2 * kLuW * kLuW, Xb, Yb,
-                              wave, lane);
+                              Tb);
         __syncthreads();
     }
 }
@@ -657,6 +656,23 @@ __global__ void k_selftest(int *bad) {
             ref_f += Aval(jf, k) * Bval(k, j);
         }
         nb += (cd[v] != ref_d) + (double(cf[v]) != ref_f);
+    }
+    // wave arg-max: several value patterns with ties, checked against brute force
+    for (int pat = 0; pat < 4; ++pat) {
+        auto val = [pat](int i) {
+            return pat == 0 ? double((i * 37) % 64) : pat == 1 ? double((i * 13) % 7) : pat == 2 ? 1.0 : double(i % 5 == 3 ? 9 : -1);
+        };
+        double v = val(l);
+        int k = (l * 29 + pat) % 64;
+        double bv = val(0);
+        int bk = (pat) % 64;
+        for (int i = 1; i < 64; ++i) {
+            const double vi = val(i);
+            const int ki = (i * 29 + pat) % 64;
+            if (vi > bv || (vi == bv && ki < bk)) { bv = vi; bk = ki; }
+        }
+        wave_argmax(v, k);
+        nb += (v != bv) + (k != bk);
     }
     atomicAdd(bad, nb);
 }
@@ -752,8 +768,8 @@ hipError_t launch_lu_solve(int n, int NP, long long batch, const double *LU, con
     dim3 g(std::max(1, std::min(64, (NP * NP + 255) / 256)), unsigned(batch));
     hipLaunchKernelGGL(k_pad_in<double>, g, dim3(256), 0, st, n, NP, LU, (double *)W);
     hipLaunchKernelGGL(k_copy_perm, dim3(unsigned(batch)), dim3(256), 0, st, n, NP, perm, permW);
-    hipLaunchKernelGGL(k_dinv_only, dim3(batch), dim3(kBlock), sizeof(double) * 3 * kLuW * kLdb, st, NP,
-                       (const double *)W, (double *)dinv);
+    hipLaunchKernelGGL(k_dinv_only, dim3(batch), dim3(kLuThreads), sizeof(double) * (3 * kLuW * kLdb + 1536), st,
+                       NP, (const double *)W, (double *)dinv);
     hipLaunchKernelGGL(k_lu_solve_only, dim3(batch), dim3(kBlock), sizeof(double) * 2 * NP, st, NP, n,
                        (const double *)W, (const double *)dinv, permW, b);
     return LAUNCH_CHECK();
