@@ -190,10 +190,11 @@ abdf_status abdf_lu_solve(int32_t n, int64_t batch, const double *LU, const int3
 enum {
     ABDF_PROF_ADMIT = 0,    /* admission: rates, starting step, first attempt */
     ABDF_PROF_FACTOR = 1,   /* Newton-matrix assembly + LU factorisation */
-    ABDF_PROF_NEWTON = 2,   /* one Newton iteration: RHS, residual, triangular solves */
+    ABDF_PROF_NEWTON = 2,   /* Newton correction: triangular solves, norm, tests, update */
     ABDF_PROF_CONTROL = 3,  /* error test, step/order control, next predictor */
     ABDF_PROF_HARVEST = 4,  /* copy-out of finished cells */
-    ABDF_PROF_KINDS = 5
+    ABDF_PROF_RHS = 5,      /* Newton residual: rates times abundances, species sums */
+    ABDF_PROF_KINDS = 6
 };
 
 typedef struct abdf_profile {

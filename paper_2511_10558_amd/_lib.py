@@ -43,7 +43,7 @@ class Profile(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64 * 8), ("ms", ctypes.c_double * 8)]
 
 
-PROFILE_KINDS = ("admit", "factor", "newton", "control", "harvest")
+PROFILE_KINDS = ("admit", "factor", "newton", "control", "harvest", "rhs")
 
 # name -> (restype, argtypes); mirrors include/astrobdf.h
 SIGNATURES = {

@@ -221,8 +221,12 @@ abdf_status abdf_newton_matrix(const abdf_network *net, int64_t n_cells, const d
     const abdf::DeviceNet *dn = net->host.device_tables(err);
     if (!dn) return fail(ABDF_E_DEVICE, err);
     hipStream_t st = static_cast<hipStream_t>(stream);
-    HIP_OR_FAIL(abdf::launch_newton_matrix(*dn, n_cells, k, x, c, M_out, st));
-    HIP_OR_FAIL(hipStreamSynchronize(st));
+    double *W = nullptr;
+    HIP_OR_FAIL(hipMalloc(reinterpret_cast<void **>(&W), size_t(n_cells) * dn->NP * dn->NP * sizeof(double)));
+    hipError_t e = abdf::launch_newton_matrix(*dn, n_cells, k, x, c, M_out, W, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    (void)hipFree(W);
+    if (e != hipSuccess) return fail(ABDF_E_DEVICE, hipGetErrorString(e));
     return ok();
 }
 

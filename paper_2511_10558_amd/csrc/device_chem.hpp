@@ -81,4 +81,30 @@ __device__ __forceinline__ void newton_matrix_row(const DeviceNet &n, const doub
     __builtin_amdgcn_wave_barrier();
 }
 
+// M = I - c J(x) for one cell into the NP x NP row-major matrix A (global, T),
+// by all NT threads of the workgroup: an identity pass over the whole matrix,
+// then one independent gather per nonzero of J.  x in LDS.  Contains a
+// workgroup barrier between the passes.
+template <typename T, int NT>
+__device__ __forceinline__ void assemble_newton_matrix(const DeviceNet &n, const double *__restrict__ k,
+                                                       const double *x, double c, T *A) {
+    const int NP = n.NP;
+    const size_t total = size_t(NP) * NP;
+    for (size_t e = threadIdx.x; e < total; e += NT) A[e] = T((e / NP) == (e % NP) ? 1.0 : 0.0);
+    __syncthreads();
+    for (int e = threadIdx.x; e < n.nnzJ; e += NT) {
+        double v = 0.0;
+        for (int t = n.jterm_ptr[e]; t < n.jterm_ptr[e + 1]; ++t) {
+            const int w = n.jt_rx_other[t];
+            const int other = (w & 0xffff) - 1;
+            double term = n.jt_coef[t] * k[w >> 16];
+            if (other >= 0) term *= x[other];
+            v += term;
+        }
+        const int i = n.jrow[e], j = n.jcol[e];
+        A[size_t(i) * NP + j] = T((i == j ? 1.0 : 0.0) + (-c * v));
+    }
+    __syncthreads();
+}
+
 }  // namespace abdf

@@ -43,6 +43,7 @@ struct Slots {
     double *psi;      // [n][S]
     double *scl;      // [n][S] Newton weights atol + rtol |x_p|
     double *xJ;       // [n][S] point of the current Jacobian
+    double *rb;       // [n][S] Newton residual c f(x) - psi - d
     void *lu;         // [n][NP][NP] factors (double or float), rows in storage order
     void *dinv;       // [n][NB][2][64][64] inverses of the diagonal blocks' triangles
     int32_t *perm;    // [n][NP]

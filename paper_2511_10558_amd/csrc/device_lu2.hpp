@@ -497,24 +497,47 @@ __device__ __forceinline__ void lu_solve_left(const T *__restrict__ A, const T *
     for (int i = tid; i < NP; i += kBlock) y[i] = b[bperm[i]];
     __syncthreads();
     const int NB = (NP + kLuW - 1) / kLuW;
-    // y_rows -= A_rows[c_begin, c_end) . vec (rows through perm), result to t[0..W)
+    // t[rr] = y[r0 + rr] - A_row(r0 + rr)[c_begin, c_end) . vec for rr < W (rows through
+    // rowmap); 16 lanes per row, each thread carries 4 rows so that 8 loads
+    // per column pair are in flight.
     auto gemv_off = [&](int r0, int W, int c_begin, int c_end, const double *vec) {
-        for (int rr = row16; rr < W; rr += 16) {
-            const T *row = A + size_t(rowmap ? rowmap[r0 + rr] : r0 + rr) * NP;
-            double acc = 0.0;
-            for (int c = c_begin + 2 * lane16; c < c_end; c += 32)
-                acc += double(row[c]) * vec[c] + double(row[c + 1]) * vec[c + 1];
-            for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-            if (lane16 == 0) t[rr] = y[r0 + rr] - acc;
+        const T *rows[4];
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            const int rr = row16 + 16 * p;
+            rows[p] = rr < W ? A + size_t(rowmap ? rowmap[r0 + rr] : r0 + rr) * NP : nullptr;
+        }
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int c = c_begin + 2 * lane16; c < c_end; c += 32) {
+            const double y0 = vec[c], y1 = vec[c + 1];
+#pragma unroll
+            for (int p = 0; p < 4; ++p)
+                if (rows[p]) acc[p] += double(rows[p][c]) * y0 + double(rows[p][c + 1]) * y1;
+        }
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            double a = acc[p];
+            for (int o = 8; o > 0; o >>= 1) a += __shfl_xor(a, o);
+            const int rr = row16 + 16 * p;
+            if (lane16 == 0 && rr < W) t[rr] = y[r0 + rr] - a;
         }
     };
     auto gemv_diag = [&](int r0, int W, const T *D) {
-        for (int rr = row16; rr < W; rr += 16) {
-            const T *row = D + rr * kLuW;
-            double acc = 0.0;
-            for (int c = 2 * lane16; c < W; c += 32) acc += double(row[c]) * t[c] + double(row[c + 1]) * t[c + 1];
-            for (int o = 8; o > 0; o >>= 1) acc += __shfl_xor(acc, o);
-            if (lane16 == 0) y[r0 + rr] = acc;
+        double acc[4] = {0.0, 0.0, 0.0, 0.0};
+        for (int c = 2 * lane16; c < W; c += 32) {
+            const double t0 = t[c], t1 = t[c + 1];
+#pragma unroll
+            for (int p = 0; p < 4; ++p) {
+                const int rr = row16 + 16 * p;
+                if (rr < W) acc[p] += double(D[rr * kLuW + c]) * t0 + double(D[rr * kLuW + c + 1]) * t1;
+            }
+        }
+#pragma unroll
+        for (int p = 0; p < 4; ++p) {
+            double a = acc[p];
+            for (int o = 8; o > 0; o >>= 1) a += __shfl_xor(a, o);
+            const int rr = row16 + 16 * p;
+            if (lane16 == 0 && rr < W) y[r0 + rr] = a;
         }
     };
     for (int ib = 0; ib < NB; ++ib) {

@@ -115,7 +115,7 @@ size_t Engine::bytes_per_slot(const DeviceNet &dn, int prec) {
     const size_t S = dn.S, R = dn.R, NP = dn.NP;
     const size_t elt = prec == ABDF_PREC_FP32_LU ? sizeof(float) : sizeof(double);
     return sizeof(SlotCtl) + 5 * sizeof(double) + R * sizeof(double) + kDRows * S * sizeof(double) +
-           5 * S * sizeof(double) + NP * NP * elt + dinv_bytes(int(NP), prec) + NP * sizeof(int32_t) +
+           6 * S * sizeof(double) + NP * NP * elt + dinv_bytes(int(NP), prec) + NP * sizeof(int32_t) +
            7 * sizeof(int32_t) + sizeof(long long);
 }
 
@@ -123,11 +123,12 @@ int Engine::init(int nslots, std::string &err) {
     const size_t n = size_t(nslots), S = dn_.S, R = dn_.R, NP = dn_.NP;
     const size_t elt = prec_ == ABDF_PREC_FP32_LU ? sizeof(float) : sizeof(double);
     struct Part { void **dst; size_t bytes; };
-    void *ctl, *phi, *k, *D, *x, *d, *psi, *scl, *xJ, *lu, *dinv, *perm, *act, *lul, *fin, *cnt, *aslots, *acells;
+    void *ctl, *phi, *k, *D, *x, *d, *psi, *scl, *xJ, *rb, *lu, *dinv, *perm, *act, *lul, *fin, *cnt, *aslots, *acells;
     Part parts[] = {
         {&ctl, n * sizeof(SlotCtl)}, {&phi, n * 5 * sizeof(double)}, {&k, n * R * sizeof(double)},
         {&D, n * kDRows * S * sizeof(double)}, {&x, n * S * sizeof(double)}, {&d, n * S * sizeof(double)},
         {&psi, n * S * sizeof(double)}, {&scl, n * S * sizeof(double)}, {&xJ, n * S * sizeof(double)},
+        {&rb, n * S * sizeof(double)},
         {&lu, n * NP * NP * elt}, {&dinv, n * dinv_bytes(int(NP), prec_)}, {&perm, n * NP * sizeof(int32_t)}, {&act, 3 * n * sizeof(int32_t)},
         {&lul, 3 * n * sizeof(int32_t)}, {&fin, n * sizeof(int32_t)}, {&cnt, 8 * sizeof(int32_t)},
         {&aslots, n * sizeof(int32_t)}, {&acells, n * sizeof(long long)},
@@ -161,6 +162,7 @@ int Engine::init(int nslots, std::string &err) {
     s_.psi = static_cast<double *>(psi);
     s_.scl = static_cast<double *>(scl);
     s_.xJ = static_cast<double *>(xJ);
+    s_.rb = static_cast<double *>(rb);
     s_.lu = lu;
     s_.dinv = dinv;
     s_.perm = static_cast<int32_t *>(perm);
@@ -177,10 +179,18 @@ int Engine::init(int nslots, std::string &err) {
     lds_admit_ = admit_lds(dn_);
     lds_factor_ = factor_lds(dn_, prec_);
     lds_newton_ = newton_lds(dn_);
+    lds_solve_ = solve_lds(dn_);
     if (dn_.NP > 512 || lds_admit_ > kMaxLds || lds_factor_ > kMaxLds || lds_newton_ > kMaxLds) {
         err = "network too large for one workgroup's LDS";
         return ABDF_E_ARG;
     }
+    int dev = 0, cus = 256;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
+        cus = prop.multiProcessorCount;
+    grid_factor_max_ = cus * resident_per_cu(0, prec_, lds_factor_);
+    grid_newton_max_ = cus * resident_per_cu(1, prec_, lds_newton_);
+    grid_solve_max_ = cus * resident_per_cu(2, prec_, lds_solve_);
     free_.clear();
     for (int i = nslots - 1; i >= 0; --i) free_.push_back(i);
     return ABDF_OK;
@@ -255,11 +265,14 @@ int Engine::solve(const BatchIO &io, const abdf_options &opt, hipStream_t st, st
     while (true) {
         if (bound_ > 0) {
             hipEvent_t t0 = timer_begin(st);
-            HIP_TRY(launch_factor(s_, dn_, ring_, bound_, lds_factor_, st));
+            HIP_TRY(launch_factor(s_, dn_, ring_, std::min(bound_, grid_factor_max_), lds_factor_, st));
             timer_end(1, t0, st);
             for (int m = 0; m < kNewtonMaxIter; ++m) {
                 t0 = timer_begin(st);
-                HIP_TRY(launch_newton(s_, dn_, ring_, bound_, lds_newton_, st));
+                HIP_TRY(launch_newton_rhs(s_, dn_, ring_, std::min(bound_, grid_newton_max_), lds_newton_, st));
+                timer_end(5, t0, st);
+                t0 = timer_begin(st);
+                HIP_TRY(launch_newton_solve(s_, ring_, std::min(bound_, grid_solve_max_), lds_solve_, st));
                 timer_end(2, t0, st);
             }
             t0 = timer_begin(st);

@@ -68,7 +68,8 @@ class Engine {
     std::vector<int32_t> free_;
     int ring_ = 0;
     int bound_ = 0;
-    size_t lds_admit_ = 0, lds_factor_ = 0, lds_newton_ = 0;
+    size_t lds_admit_ = 0, lds_factor_ = 0, lds_newton_ = 0, lds_solve_ = 0;
+    int grid_factor_max_ = 256, grid_newton_max_ = 512, grid_solve_max_ = 1024;   // persistent grid sizes
     // harvest target of the current solve
     const BatchIO *io_ = nullptr;
     // kernel timers of launches not yet read back

@@ -264,110 +264,126 @@ __global__ void __launch_bounds__(kBlock) k_admit(Slots s, DeviceNet n, AdmitArg
 template <typename T>
 __global__ void __launch_bounds__(kLuThreads) k_factor(Slots s, DeviceNet n, int ring) {
     extern __shared__ double smem[];
-    const int idx = blockIdx.x;
-    if (idx >= s.cnt[3 + ring]) return;
-    const int slot = s.lul[ring * s.nslots + idx];
+    const int count = s.cnt[3 + ring];
     const int S = s.S, NP = s.NP;
-    const double c = s.ctl[slot].c;
-    double *xs = smem;
-    double *rowbuf = xs + S;
-    const double *k = s.k + size_t(slot) * n.R;
-    for (int i = threadIdx.x; i < S; i += kLuThreads) xs[i] = s.xJ[size_t(slot) * S + i];
-    __syncthreads();
-    T *A = reinterpret_cast<T *>(s.lu) + size_t(slot) * NP * NP;
-    const int wave = threadIdx.x >> 6;
-    for (int i = wave; i < NP; i += kLuWaves)
-        newton_matrix_row<T>(n, k, xs, c, i, rowbuf + wave * NP, A + size_t(i) * NP);
-    __syncthreads();
-    lu_factor_left<T>(A, NP, s.perm + size_t(slot) * NP,
-                      reinterpret_cast<T *>(s.dinv) + size_t(slot) * lu2_dinv_elems<T>(NP), nullptr,
-                      reinterpret_cast<unsigned char *>(smem));
-    if (threadIdx.x == 0) {
-        s.ctl[slot].c_lu = c;
-        s.ctl[slot].lu_valid = 1;
-        s.ctl[slot].n_lu += 1;
+    // persistent: each workgroup takes every gridDim.x-th queued slot
+    for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
+        const int slot = s.lul[ring * s.nslots + idx];
+        const double c = s.ctl[slot].c;
+        double *xs = smem;
+        const double *k = s.k + size_t(slot) * n.R;
+        for (int i = threadIdx.x; i < S; i += kLuThreads) xs[i] = s.xJ[size_t(slot) * S + i];
+        __syncthreads();
+        T *A = reinterpret_cast<T *>(s.lu) + size_t(slot) * NP * NP;
+        assemble_newton_matrix<T, kLuThreads>(n, k, xs, c, A);
+        lu_factor_left<T>(A, NP, s.perm + size_t(slot) * NP,
+                          reinterpret_cast<T *>(s.dinv) + size_t(slot) * lu2_dinv_elems<T>(NP), nullptr,
+                          reinterpret_cast<unsigned char *>(smem));
+        if (threadIdx.x == 0) {
+            s.ctl[slot].c_lu = c;
+            s.ctl[slot].lu_valid = 1;
+            s.ctl[slot].n_lu += 1;
+        }
+        __syncthreads();
     }
 }
 
-// One modified-Newton iteration for every active slot still iterating.
+// Newton residual r = c f(x) - psi - d of every active slot still iterating
+// (persistent).  A non-finite f ends the attempt as a corrector failure.
+__global__ void __launch_bounds__(kBlock) k_newton_rhs(Slots s, DeviceNet n, int ring) {
+    extern __shared__ double smem[];
+    __shared__ double red[kWaves];
+    const int count = s.cnt[ring];
+    const int S = s.S;
+    for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
+        const int slot = s.act[ring * s.nslots + idx];
+        if (s.ctl[slot].phase != kIter) continue;
+        double *xs = smem;
+        double *rate = xs + S;
+        double *part = rate + n.R;
+        double *f = part + n.n_seg;
+        const double *x = s.x + size_t(slot) * S, *d = s.d + size_t(slot) * S, *psi = s.psi + size_t(slot) * S;
+        double *rb = s.rb + size_t(slot) * S;
+        const double c = s.ctl[slot].c;
+        for (int i = threadIdx.x; i < S; i += kBlock) xs[i] = x[i];
+        __syncthreads();
+        cell_rhs(n, s.k + size_t(slot) * n.R, xs, rate, part, f);
+        bool nonfinite = false;
+        for (int i = threadIdx.x; i < S; i += kBlock) {
+            nonfinite |= !isfinite(f[i]);
+            rb[i] = c * f[i] - psi[i] - d[i];
+        }
+        nonfinite = block_any(nonfinite, red);
+        if (threadIdx.x == 0) {
+            SlotCtl &g = s.ctl[slot];
+            g.n_rhs += 1;
+            if (nonfinite) {
+                g.n_newton_iter += 1;
+                g.newton_iter += 1;
+                g.m_last = g.newton_iter;
+                g.phase = kFailed;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Newton correction Delta = M^{-1} r, its weighted norm, the convergence and
+// divergence tests, and the update x += Delta, d += Delta (persistent).
 template <typename T>
-__global__ void __launch_bounds__(kBlock) k_newton(Slots s, DeviceNet n, int ring) {
+__global__ void __launch_bounds__(kBlock) k_newton_solve(Slots s, int ring) {
     extern __shared__ double smem[];
     __shared__ double red[kLuW + kWaves];
     __shared__ int decision;
-    const int idx = blockIdx.x;
-    if (idx >= s.cnt[ring]) return;
-    const int slot = s.act[ring * s.nslots + idx];
-    if (s.ctl[slot].phase != kIter) return;
+    const int count = s.cnt[ring];
     const int S = s.S, NP = s.NP;
-    double *xs = smem;
-    double *rate = xs + S;
-    double *part = rate + n.R;
-    double *b = part + n.n_seg;
-    double *y = b + NP;
-    double *x = s.x + size_t(slot) * S, *d = s.d + size_t(slot) * S;
-    const double *psi = s.psi + size_t(slot) * S, *scl = s.scl + size_t(slot) * S;
-    const double c = s.ctl[slot].c;
-    for (int i = threadIdx.x; i < S; i += kBlock) xs[i] = x[i];
-    __syncthreads();
-    cell_rhs(n, s.k + size_t(slot) * n.R, xs, rate, part, b);
-    bool nonfinite = false;
-    for (int i = threadIdx.x; i < NP; i += kBlock) {
-        if (i < S) {
-            nonfinite |= !isfinite(b[i]);
-            b[i] = c * b[i] - psi[i] - d[i];
-        } else {
-            b[i] = 0.0;
-        }
-    }
-    nonfinite = block_any(nonfinite, red + kLuW);
-    SlotCtl &g = s.ctl[slot];
-    if (nonfinite) {
-        if (threadIdx.x == 0) {
-            g.n_rhs += 1;
-            g.n_newton_iter += 1;
-            g.newton_iter += 1;
-            g.m_last = g.newton_iter;
-            g.phase = kFailed;
-        }
-        return;
-    }
-    const int32_t *perm = s.perm + size_t(slot) * NP;
-    lu_solve_left<T>(reinterpret_cast<const T *>(s.lu) + size_t(slot) * NP * NP,
-                     reinterpret_cast<const T *>(s.dinv) + size_t(slot) * lu2_dinv_elems<T>(NP), perm, perm, NP, b,
-                     y, red);
-    double acc = 0.0;
-    for (int i = threadIdx.x; i < S; i += kBlock) {
-        const double v = y[i] / scl[i];
-        acc += v * v;
-    }
-    const double eta = sqrt(block_sum(acc, red + kLuW) / S);
-    if (threadIdx.x == 0) {
-        const int m = g.newton_iter + 1;
-        const double tol = g.newton_tol;
-        bool fail = false, conv = false;
-        double theta = -1.0;
-        if (m > 1) {
-            theta = eta / g.eta_old;
-            fail = theta >= 1.0 || pow(theta, double(kNewtonMaxIter - m)) / (1.0 - theta) * eta > tol;
-        }
-        if (!fail) conv = eta == 0.0 || (m > 1 && theta / (1.0 - theta) * eta < tol);
-        if (!fail && !conv && m == kNewtonMaxIter) fail = true;
-        g.n_rhs += 1;
-        g.n_newton_iter += 1;
-        g.newton_iter = m;
-        g.m_last = m;
-        g.eta_old = eta;
-        decision = fail ? kFailed : (conv ? kConverged : kIter);
-        g.phase = decision;
-    }
-    __syncthreads();
-    // a failed attempt discards x and d, so they are only updated otherwise
-    if (decision != kFailed) {
+    for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
+        const int slot = s.act[ring * s.nslots + idx];
+        if (s.ctl[slot].phase != kIter) continue;
+        double *b = smem;
+        double *y = b + NP;
+        double *x = s.x + size_t(slot) * S, *d = s.d + size_t(slot) * S;
+        const double *scl = s.scl + size_t(slot) * S, *rb = s.rb + size_t(slot) * S;
+        for (int i = threadIdx.x; i < NP; i += kBlock) b[i] = i < S ? rb[i] : 0.0;
+        __syncthreads();
+        const int32_t *perm = s.perm + size_t(slot) * NP;
+        lu_solve_left<T>(reinterpret_cast<const T *>(s.lu) + size_t(slot) * NP * NP,
+                         reinterpret_cast<const T *>(s.dinv) + size_t(slot) * lu2_dinv_elems<T>(NP), perm, perm,
+                         NP, b, y, red);
+        double acc = 0.0;
         for (int i = threadIdx.x; i < S; i += kBlock) {
-            x[i] = xs[i] + y[i];
-            d[i] = d[i] + y[i];
+            const double v = y[i] / scl[i];
+            acc += v * v;
         }
+        const double eta = sqrt(block_sum(acc, red + kLuW) / S);
+        if (threadIdx.x == 0) {
+            SlotCtl &g = s.ctl[slot];
+            const int m = g.newton_iter + 1;
+            const double tol = g.newton_tol;
+            bool fail = false, conv = false;
+            double theta = -1.0;
+            if (m > 1) {
+                theta = eta / g.eta_old;
+                fail = theta >= 1.0 || pow(theta, double(kNewtonMaxIter - m)) / (1.0 - theta) * eta > tol;
+            }
+            if (!fail) conv = eta == 0.0 || (m > 1 && theta / (1.0 - theta) * eta < tol);
+            if (!fail && !conv && m == kNewtonMaxIter) fail = true;
+            g.n_newton_iter += 1;
+            g.newton_iter = m;
+            g.m_last = m;
+            g.eta_old = eta;
+            decision = fail ? kFailed : (conv ? kConverged : kIter);
+            g.phase = decision;
+        }
+        __syncthreads();
+        // a failed attempt discards x and d, so they are only updated otherwise
+        if (decision != kFailed) {
+            for (int i = threadIdx.x; i < S; i += kBlock) {
+                x[i] = x[i] + y[i];
+                d[i] = d[i] + y[i];
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -553,21 +569,19 @@ __global__ void __launch_bounds__(kBlock) k_rhs_only(DeviceNet n, const double *
     cell_rhs(n, k + size_t(c) * n.R, xs, rate, part, f + size_t(c) * n.S);
 }
 
-// Writes the unpadded S x S Newton matrix of each cell.
-__global__ void __launch_bounds__(kBlock) k_newton_matrix_only(DeviceNet n, const double *k, const double *x,
-                                                               const double *cvec, double *M) {
+// Writes the unpadded S x S Newton matrix of each cell, assembled by the same
+// code as the solver's factor kernel (into a padded work matrix W).
+__global__ void __launch_bounds__(kLuThreads) k_newton_matrix_only(DeviceNet n, const double *k, const double *x,
+                                                                  const double *cvec, double *W, double *M) {
     extern __shared__ double smem[];
     const long long c = blockIdx.x;
-    double *xs = smem, *rowbuf = xs + n.S, *rowout = rowbuf + kWaves * n.NP;
-    for (int i = threadIdx.x; i < n.S; i += kBlock) xs[i] = x[size_t(c) * n.S + i];
+    double *xs = smem;
+    for (int i = threadIdx.x; i < n.S; i += kLuThreads) xs[i] = x[size_t(c) * n.S + i];
     __syncthreads();
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int i = wave; i < n.S; i += kWaves) {
-        double *ro = rowout + wave * n.NP;
-        newton_matrix_row<double>(n, k + size_t(c) * n.R, xs, cvec[c], i, rowbuf + wave * n.NP, ro);
-        for (int j = lane; j < n.S; j += 64) M[(size_t(c) * n.S + i) * n.S + j] = ro[j];
-        __builtin_amdgcn_wave_barrier();
-    }
+    double *Wc = W + size_t(c) * n.NP * n.NP;
+    assemble_newton_matrix<double, kLuThreads>(n, k + size_t(c) * n.R, xs, cvec[c], Wc);
+    for (size_t e = threadIdx.x; e < size_t(n.S) * n.S; e += kLuThreads)
+        M[size_t(c) * n.S * n.S + e] = Wc[(e / n.S) * n.NP + e % n.S];
 }
 
 // Copies an n x n matrix into the padded NP x NP work matrix (identity padding) and back.
@@ -684,7 +698,23 @@ size_t lu_work_lds(int NP, int prec) {
 }
 
 size_t factor_lds(const DeviceNet &n, int prec) {
-    return std::max(sizeof(double) * (size_t(n.S) + kLuWaves * size_t(n.NP)), lu_work_lds(n.NP, prec));
+    return std::max(sizeof(double) * size_t(n.S), lu_work_lds(n.NP, prec));
+}
+
+int resident_per_cu(int which, int prec, size_t lds) {
+    int nb = 0;
+    hipError_t e;
+    if (which == 0)
+        e = prec == ABDF_PREC_FP32_LU
+                ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_factor<float>, kLuThreads, lds)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_factor<double>, kLuThreads, lds);
+    else if (which == 1)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_newton_rhs, kBlock, lds);
+    else
+        e = prec == ABDF_PREC_FP32_LU
+                ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_newton_solve<float>, kBlock, lds)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_newton_solve<double>, kBlock, lds);
+    return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
 size_t dinv_bytes(int NP, int prec) {
@@ -709,12 +739,18 @@ hipError_t launch_factor(const Slots &s, const DeviceNet &n, int ring, int grid,
     return LAUNCH_CHECK();
 }
 
-hipError_t launch_newton(const Slots &s, const DeviceNet &n, int ring, int grid, size_t lds, hipStream_t st) {
+hipError_t launch_newton_rhs(const Slots &s, const DeviceNet &n, int ring, int grid, size_t lds, hipStream_t st) {
+    if (grid == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_newton_rhs, dim3(grid), dim3(kBlock), lds, st, s, n, ring);
+    return LAUNCH_CHECK();
+}
+
+hipError_t launch_newton_solve(const Slots &s, int ring, int grid, size_t lds, hipStream_t st) {
     if (grid == 0) return hipSuccess;
     if (s.prec == ABDF_PREC_FP32_LU)
-        hipLaunchKernelGGL(k_newton<float>, dim3(grid), dim3(kBlock), lds, st, s, n, ring);
+        hipLaunchKernelGGL(k_newton_solve<float>, dim3(grid), dim3(kBlock), lds, st, s, ring);
     else
-        hipLaunchKernelGGL(k_newton<double>, dim3(grid), dim3(kBlock), lds, st, s, n, ring);
+        hipLaunchKernelGGL(k_newton_solve<double>, dim3(grid), dim3(kBlock), lds, st, s, ring);
     return LAUNCH_CHECK();
 }
 
@@ -740,9 +776,9 @@ hipError_t launch_rhs(const DeviceNet &n, long long cells, const double *k, cons
 }
 
 hipError_t launch_newton_matrix(const DeviceNet &n, long long cells, const double *k, const double *x,
-                                const double *c, double *M, hipStream_t st) {
-    const size_t lds = sizeof(double) * (size_t(n.S) + 2 * kWaves * size_t(n.NP));
-    hipLaunchKernelGGL(k_newton_matrix_only, dim3(cells), dim3(kBlock), lds, st, n, k, x, c, M);
+                                const double *c, double *M, double *W, hipStream_t st) {
+    const size_t lds = sizeof(double) * size_t(n.S);
+    hipLaunchKernelGGL(k_newton_matrix_only, dim3(cells), dim3(kLuThreads), lds, st, n, k, x, c, W, M);
     return LAUNCH_CHECK();
 }
 

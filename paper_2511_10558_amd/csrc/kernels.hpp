@@ -36,25 +36,30 @@ struct PhysArgs {
 // LDS bytes per kernel for a network
 inline size_t admit_lds(const DeviceNet &n) { return sizeof(double) * (4 * size_t(n.S) + n.R + n.n_seg); }
 inline size_t newton_lds(const DeviceNet &n) {
-    return sizeof(double) * (size_t(n.S) + n.R + n.n_seg + 2 * size_t(n.NP));
+    return sizeof(double) * (2 * size_t(n.S) + n.R + n.n_seg);
 }
+inline size_t solve_lds(const DeviceNet &n) { return sizeof(double) * 2 * size_t(n.NP); }
 size_t factor_lds(const DeviceNet &n, int prec);
 
 hipError_t launch_admit(const Slots &s, const DeviceNet &n, const AdmitArgs &a, int ring, size_t lds, hipStream_t st);
 hipError_t launch_factor(const Slots &s, const DeviceNet &n, int ring, int grid, size_t lds, hipStream_t st);
-hipError_t launch_newton(const Slots &s, const DeviceNet &n, int ring, int grid, size_t lds, hipStream_t st);
+hipError_t launch_newton_rhs(const Slots &s, const DeviceNet &n, int ring, int grid, size_t lds, hipStream_t st);
+hipError_t launch_newton_solve(const Slots &s, int ring, int grid, size_t lds, hipStream_t st);
 hipError_t launch_control(const Slots &s, int ring, int grid, hipStream_t st);
 hipError_t launch_harvest(const Slots &s, const HarvestArgs &h, hipStream_t st);
 
 hipError_t launch_rates(const DeviceNet &n, const PhysArgs &p, long long cells, double *k, hipStream_t st);
 hipError_t launch_rhs(const DeviceNet &n, long long cells, const double *k, const double *x, double *f, hipStream_t st);
 hipError_t launch_newton_matrix(const DeviceNet &n, long long cells, const double *k, const double *x,
-                                const double *c, double *M, hipStream_t st);
+                                const double *c, double *M, double *W, hipStream_t st);
 hipError_t launch_lu_factor(int n, int NP, long long batch, double *A, void *W, int32_t *permW, int32_t *perm,
                             void *dinv, int32_t *info, int prec, hipStream_t st);
 hipError_t launch_lu_solve(int n, int NP, long long batch, const double *LU, const int32_t *perm, double *b,
                            void *W, int32_t *permW, void *dinv, hipStream_t st);
 size_t dinv_bytes(int NP, int prec);
+// Workgroups resident per CU of the factor (which = 0), Newton residual (1) or
+// Newton solve (2) kernel.
+int resident_per_cu(int which, int prec, size_t lds);
 hipError_t launch_selftest(int *bad, hipStream_t st);
 size_t lu_work_lds(int NP, int prec);
 

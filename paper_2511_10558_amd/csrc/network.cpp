@@ -40,7 +40,7 @@ HostNetwork::~HostNetwork() {
         int prev = 0;
         if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(d->device) == hipSuccess) {
             void *ptrs[] = {d->rx_ab, d->rx_type, d->alpha, d->beta, d->gamma, d->seg_ptr, d->seg_beg,
-                            d->f_ent, d->jrow_ptr, d->jcol, d->jterm_ptr, d->jt_rx_other, d->jt_coef};
+                            d->f_ent, d->jrow_ptr, d->jcol, d->jrow, d->jterm_ptr, d->jt_rx_other, d->jt_coef};
             for (void *p : ptrs)
                 if (p) (void)hipFree(p);
             (void)hipSetDevice(prev);
@@ -188,6 +188,7 @@ void HostNetwork::finalize() {
     }
     jrow_ptr.assign(S + 1, 0);
     jcol.clear();
+    jrow.clear();
     jterm_ptr.clear();
     jt_rx_other.clear();
     jt_coef.clear();
@@ -201,6 +202,7 @@ void HostNetwork::finalize() {
         for (auto &tm : v) {
             if (tm.j != last) {
                 jcol.push_back(tm.j);
+                jrow.push_back(i);
                 jterm_ptr.push_back(int32_t(jt_coef.size()));
                 last = tm.j;
             }
@@ -258,6 +260,7 @@ const DeviceNet *HostNetwork::device_tables(std::string &err) const {
     chk(upload(&d->f_ent, f_ent));
     chk(upload(&d->jrow_ptr, jrow_ptr));
     chk(upload(&d->jcol, jcol));
+    chk(upload(&d->jrow, jrow));
     chk(upload(&d->jterm_ptr, jterm_ptr));
     chk(upload(&d->jt_rx_other, jt_rx_other));
     chk(upload(&d->jt_coef, jt_coef));

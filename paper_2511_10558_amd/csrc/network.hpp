@@ -30,6 +30,7 @@ struct DeviceNet {
     // Jacobian: nonzeros of J grouped by row, each with its list of terms
     int32_t *jrow_ptr = nullptr;   // [S+1]
     int32_t *jcol = nullptr;       // [nnzJ]
+    int32_t *jrow = nullptr;       // [nnzJ] row of each nonzero
     int32_t *jterm_ptr = nullptr;  // [nnzJ+1]
     int32_t *jt_rx_other = nullptr;  // reaction << 16 | (other species + 1), 0 in the low half = none
     double *jt_coef = nullptr;     // [nterm] nu_ir * multiplicity
@@ -50,7 +51,7 @@ struct HostNetwork {
     // derived (built by finalize())
     int S = 0, R = 0, E = 0, NP = 0;
     std::vector<int32_t> seg_ptr, seg_beg, f_ent;
-    std::vector<int32_t> jrow_ptr, jcol, jterm_ptr, jt_rx_other;
+    std::vector<int32_t> jrow_ptr, jcol, jrow, jterm_ptr, jt_rx_other;
     std::vector<double> jt_coef;
 
     // per-device uploads, created on first use
