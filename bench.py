@@ -56,6 +56,18 @@ def _single_thread_blas():
     os.environ["OMP_NUM_THREADS"] = "1"
 
 
+def recorded_traffic():
+    """Per-unit HBM bytes from the last rocprofv3 counter passes (profiles/traffic.json),
+    or None when the kernel sources have changed since they were taken."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    sys.path.insert(0, os.path.join(ROOT, "profiles"))
+    import summarize
+    rec = json.load(open(path))
+    return rec if rec.get("source_hash") == summarize.source_hash() else None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -68,6 +80,9 @@ def main():
     ap.add_argument("--seed", type=int, default=3001)
     ap.add_argument("--cpu-sample", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="first run one elementwise kernel reading and writing 256 MiB "
+                         "(a reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: the cells are independent and this build runs on one "
@@ -86,6 +101,12 @@ def main():
     inp = [t(cells.T), t(cells.n_H), t(cells.A_V), t(cells.zeta), t(cells.G0), t(cells.x0), t(cells.t_end)]
     opts = ab.make_options(rtol=1e-6, atol=1e-20, precision=args.precision)
 
+    if args.calibrate_copy:
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.mul(src, 2.0, out=dst)     # elementwise kernel: 256 MiB read, 256 MiB written
+        torch.cuda.synchronize()
+        del src, dst
     for _ in range(args.warmup):
         ab.solve(g, *inp, options=opts)
     torch.cuda.synchronize()
@@ -137,6 +158,13 @@ def main():
         ach = n_att * control_bytes / (prof["control"][1] * 1e-3) / 1e9
         roof = {"kernel": "k_control", "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
+    rec = recorded_traffic()
+    if rec is not None and args.precision == "fp64":
+        if roof["kernel"] == "k_factor":
+            roof["traffic"] = round(rec["k_factor_bytes_per_lu"] * n_lu / max(1, prof["factor"][0]))
+        elif roof["kernel"] == "k_newton_solve":
+            roof["traffic"] = round(rec["k_newton_solve_bytes_per_iteration"] * n_newton / max(1, prof["newton"][0]))
+        roof["traffic_unit"] = "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"
     # secondary figures for the other two hot kernels
     if prof["factor"][1] > 0:
         kern["factor"]["tflops"] = round(n_lu * lu_flop / (prof["factor"][1] * 1e-3) / 1e12, 3)

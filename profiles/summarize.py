@@ -1,0 +1,100 @@
+"""Turns rocprofv3 CSV output into the short summaries kept in this folder.
+
+    python profiles/summarize.py TRACE_DIR FETCH_DIR WRITE_DIR FETCH_LOG
+
+TRACE_DIR holds run_kernel_stats.csv of a --kernel-trace --stats run;
+FETCH_DIR / WRITE_DIR hold run_counter_collection.csv of the FETCH_SIZE and
+WRITE_SIZE passes of a bench run started with --calibrate-copy (one
+elementwise multiply of 32 Mi doubles: 256 MiB read, 256 MiB written);
+FETCH_LOG is that bench run's
+output line (for the number of factorisations).  Writes
+profiles/kernel_stats_net500.md and profiles/traffic.json.
+"""
+import csv
+import hashlib
+import json
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(HERE)
+KERNEL_SOURCES = ["paper_2511_10558_amd/csrc/device_lu2.hpp", "paper_2511_10558_amd/csrc/device_lu.hpp",
+                  "paper_2511_10558_amd/csrc/device_chem.hpp", "paper_2511_10558_amd/csrc/kernels.hip",
+                  "paper_2511_10558_amd/csrc/device_common.hpp"]
+COPY_BYTES = 256 * 1024 * 1024
+
+
+def source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def short(name):
+    for key in ("k_factor<double>", "k_factor<float>", "k_newton_solve<double>", "k_newton_solve<float>",
+                "k_newton_rhs", "k_control", "k_admit", "k_harvest"):
+        if key in name:
+            return key
+    if "MulFunctor" in name:
+        return "reference multiply"
+    return name[:40]
+
+
+def counters(path):
+    per = {}
+    with open(os.path.join(path, "run_counter_collection.csv")) as fh:
+        for row in csv.DictReader(fh):
+            k = short(row["Kernel_Name"])
+            v = float(row["Counter_Value"])
+            n, s = per.get(k, (0, 0.0))
+            per[k] = (n + 1, s + v)
+    return per
+
+
+def main():
+    trace, fetch, write, flog = sys.argv[1:5]
+    rows = list(csv.DictReader(open(os.path.join(trace, "run_kernel_stats.csv"))))
+    out = ["# rocprofv3 kernel statistics: 500-species / 6000-reaction network, 4096 cells, FP64", "",
+           "Command (repo root, on the GPU box):", "",
+           "    rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o run -- "
+           "python3 bench.py --cells 4096 --steps 1 --warmup 0 --no-cpu-baseline", "",
+           "| kernel | calls | total ms | average us | % |", "|---|---|---|---|---|"]
+    for r in rows:
+        if float(r["Percentage"]) < 0.01:
+            continue
+        out.append(f"| {short(r['Name'])} | {r['Calls']} | {float(r['TotalDurationNs'])/1e6:.1f} | "
+                   f"{float(r['AverageNs'])/1e3:.1f} | {float(r['Percentage']):.2f} |")
+    f = counters(fetch)
+    w = counters(write)
+    cf = COPY_BYTES / (f["reference multiply"][1] * 1024.0)
+    cw = COPY_BYTES / (w["reference multiply"][1] * 1024.0)
+    line = [l for l in open(flog) if l.startswith("{")][-1]
+    work = json.loads(line)["work"]
+    out += ["", "## HBM traffic (FETCH_SIZE, WRITE_SIZE; 512 cells, one solve)", "",
+            "Commands: the bench command above with --cells 512 --calibrate-copy under "
+            "`rocprofv3 --pmc FETCH_SIZE` and, separately, `rocprofv3 --pmc WRITE_SIZE`.", "",
+            f"Calibration: an elementwise multiply reading and writing 256 MiB reads "
+            f"{f['reference multiply'][1]/1024:.1f} MiB by FETCH_SIZE (scale {cf:.3f}) and writes "
+            f"{w['reference multiply'][1]/1024:.1f} MiB by WRITE_SIZE (scale {cw:.3f}).", "",
+            "| kernel | dispatches | fetched MiB (scaled) | written MiB (scaled) |", "|---|---|---|---|"]
+    traffic = {}
+    for k in sorted(set(f) | set(w)):
+        fb = f.get(k, (0, 0.0))[1] * 1024 * cf
+        wb = w.get(k, (0, 0.0))[1] * 1024 * cw
+        out.append(f"| {k} | {f.get(k, (0, 0))[0]} | {fb/2**20:.1f} | {wb/2**20:.1f} |")
+        traffic[k] = fb + wb
+    per_lu = traffic.get("k_factor<double>", 0.0) / max(1, work["factorisations"])
+    per_it = traffic.get("k_newton_solve<double>", 0.0) / max(1, work["newton_iterations"])
+    out += ["", f"Per factorisation (k_factor, assembly + LU): {per_lu/2**20:.2f} MiB of HBM traffic; "
+                f"per Newton solve (k_newton_solve): {per_it/2**20:.3f} MiB."]
+    open(os.path.join(HERE, "kernel_stats_net500.md"), "w").write("\n".join(out) + "\n")
+    json.dump({"source_hash": source_hash(), "k_factor_bytes_per_lu": per_lu,
+               "k_newton_solve_bytes_per_iteration": per_it}, open(os.path.join(HERE, "traffic.json"), "w"),
+              indent=1)
+    print("\n".join(out))
+
+
+if __name__ == "__main__":
+    main()
