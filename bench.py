@@ -73,7 +73,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--cells", type=int, default=1024)
+    ap.add_argument("--cells", type=int, default=4096)
     ap.add_argument("--network", default="net500", choices=["small", "net200", "net500"])
     ap.add_argument("--t-end-yr", type=float, default=1e6)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_lu"])

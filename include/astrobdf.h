@@ -58,7 +58,8 @@ enum {
     ABDF_CELL_STEP_TOO_SMALL = 1,  /* h fell below 10 u |t| */
     ABDF_CELL_MAX_STEPS = 2,       /* more than max_steps step attempts */
     ABDF_CELL_NONFINITE = 3,       /* a non-finite abundance or error norm */
-    ABDF_CELL_BAD_INPUT = 4        /* non-finite or non-physical phi, x0, t_end or tolerances */
+    ABDF_CELL_BAD_INPUT = 4,       /* non-finite or non-physical phi, x0, t_end or tolerances */
+    ABDF_CELL_TAPE_FULL = 5        /* more accepted steps than the step tape holds (recording solves) */
 };
 
 /* Precision of the Newton-matrix factorisation.  Residuals, error norms,
@@ -147,6 +148,151 @@ abdf_status abdf_solve(const abdf_network *net, int64_t n_cells,
                        double *x_out, int32_t *cell_status, abdf_cell_stats *stats,
                        void *stream);
 
+/* ---------------------------------------------------------------- serving --
+ * A request server with continuous batching (one per network and device).
+ * Requests of any number of cells, each with its own horizon, are queued on
+ * submission; a worker thread admits cells of the oldest requests into device
+ * slots whenever slots are free (the slot pool is sized by hbm_budget_bytes),
+ * keeps each cell's BDF history (difference table, step, order, Newton
+ * factor) on the device between step attempts, and refills slots as cells
+ * finish, so requests that arrive while others run share the step loop.
+ * Each cell's arithmetic does not depend on which other cells run beside it:
+ * a request's results are bitwise the same alone and in any mix, and equal
+ * those of abdf_solve at the same tolerances.
+ *
+ * Inputs are HOST arrays copied at submission (the caller may reuse them at
+ * once).  Outputs are written to the caller's HOST buffers named in the
+ * request, which must stay valid until the request's completion has been
+ * returned by abdf_server_poll (or the server is destroyed).  The network
+ * must outlive the server.  All functions are safe to call from any thread.
+ */
+typedef struct abdf_server abdf_server;
+
+typedef struct abdf_server_options {
+    abdf_options solve;        /* default tolerances, max_steps, precision, check_every, hbm_budget_bytes */
+    int64_t max_slots;         /* cells resident at once; 0 = as many as the budget and free memory allow */
+    int64_t max_queued_cells;  /* submit returns ABDF_E_BUSY beyond this many waiting cells; 0 = no bound */
+} abdf_server_options;
+
+typedef struct abdf_request {
+    int64_t n_cells;
+    const double *T, *n_H, *A_V, *zeta, *G0;  /* HOST [n_cells] */
+    const double *x0;                         /* HOST [n_cells][S] */
+    const double *t_end;                      /* HOST [n_cells], seconds */
+    double rtol;                              /* <= 0: the server's default */
+    double atol;                              /* < 0: the server's default */
+    double *x_out;                            /* HOST [n_cells][S] */
+    int32_t *cell_status;                     /* HOST [n_cells] */
+    abdf_cell_stats *stats;                   /* HOST [n_cells], or NULL */
+} abdf_request;
+
+typedef struct abdf_completion {
+    uint64_t id;
+    int64_t n_cells;
+    int64_t n_failed;       /* cells whose status is not ABDF_CELL_OK */
+    int32_t cancelled;      /* 1: cancelled; the output buffers hold no result */
+    int32_t reserved;
+    double t_submit;        /* seconds on the server clock (abdf_server_clock) */
+    double t_first_admit;   /* first cell placed in a slot, -1 if none */
+    double t_done;          /* last cell's result written to the caller's buffers */
+} abdf_completion;
+
+typedef struct abdf_server_info {
+    int64_t slots;              /* size of the slot pool */
+    int64_t occupied;           /* slots holding a cell */
+    int64_t queued_cells;       /* submitted, not yet admitted */
+    int64_t completed_requests;
+    int64_t completed_cells;
+    double busy_slot_seconds;   /* integral of occupied slots over time */
+    double uptime;              /* seconds since creation */
+} abdf_server_info;
+
+void abdf_server_options_default(abdf_server_options *opt);
+/* Creates a server on the current HIP device.  Errors: ABDF_E_ARG,
+ * ABDF_E_BUDGET (not one slot fits), ABDF_E_NOMEM, ABDF_E_DEVICE. */
+abdf_status abdf_server_create(const abdf_network *net, const abdf_server_options *opt, abdf_server **out);
+/* Queues a request and returns its id (ids start at 1 and increase).
+ * Errors: ABDF_E_ARG (null pointers, n_cells < 0, non-finite tolerances),
+ * ABDF_E_BUSY (queue bound reached), ABDF_E_DEVICE (the worker stopped on a
+ * device error; abdf_last_error names it). */
+abdf_status abdf_server_submit(abdf_server *srv, const abdf_request *req, uint64_t *id);
+/* Returns up to `max` completions in completion order.  timeout_ms = 0 does
+ * not wait; > 0 waits up to that long for the first one; < 0 waits until one
+ * is available.  *n_out may be 0.  After a device error in the worker the
+ * completions already made are still returned, then ABDF_E_DEVICE. */
+abdf_status abdf_server_poll(abdf_server *srv, abdf_completion *out, int32_t max, int32_t *n_out,
+                             int32_t timeout_ms);
+/* Cancels a request: its cells not yet admitted are dropped, running ones are
+ * discarded when they finish, and a completion with cancelled = 1 follows.
+ * ABDF_E_ARG if the id was never issued; a request already complete is not
+ * affected. */
+abdf_status abdf_server_cancel(abdf_server *srv, uint64_t id);
+/* Seconds since the server was created (monotonic clock). */
+double abdf_server_clock(const abdf_server *srv);
+abdf_status abdf_server_info_get(abdf_server *srv, abdf_server_info *out);
+/* Stops the worker after its current step attempt, drops queued and running
+ * requests (their buffers are no longer written) and frees the server. */
+void abdf_server_destroy(abdf_server *srv);
+
+/* ---------------------------------------------------------------- adjoint --
+ * Gradients of a loss L(x(t_end)) with respect to the log rate prefactors,
+ * dL/dlog alpha_r for every reaction (the sensitivities to the chemical
+ * parameters of paper Sec. 2 and its differentiable-solver motivation), and
+ * with respect to the initial abundances.
+ *
+ * The gradient is that of the discrete map the forward solve followed: its
+ * accepted (h, q) sequence held fixed and each corrector equation taken as
+ * solved exactly.  A recording solve keeps, per cell, that sequence and the
+ * abundances after every accepted step (the checkpoint); the reverse sweep
+ * walks it backwards with one fresh factorisation of I - c J(x_{n+1}) and
+ * one transposed solve per step.  Factorisations are FP64.
+ */
+typedef struct abdf_tape abdf_tape;
+
+/* Solves like abdf_solve and records the step tape.
+ *   alpha          : DEVICE [R] rate prefactors to use, or NULL for the network's
+ *   max_tape_steps : accepted steps recorded per cell (0 = 2048); a cell that
+ *                    needs more ends with ABDF_CELL_TAPE_FULL
+ *   tape           : receives the tape, owned by the caller (abdf_tape_free);
+ *                    it holds its own copies of the inputs and of alpha
+ * Device memory: n_cells * (max_tape_steps * (S + 2) + S + 8) doubles for the
+ * tape, counted against opt->hbm_budget_bytes before the solver's slots.
+ * Errors: as abdf_solve; ABDF_E_ARG also for precision other than FP64 or
+ * max_tape_steps < 0; ABDF_E_BUDGET when the tape alone exceeds the budget.
+ * The network must outlive the tape. */
+abdf_status abdf_solve_record(const abdf_network *net, int64_t n_cells,
+                              const double *T, const double *n_H, const double *A_V,
+                              const double *zeta, const double *G0,
+                              const double *x0, const double *t_end, const double *alpha,
+                              const abdf_options *opt, int32_t max_tape_steps,
+                              double *x_out, int32_t *cell_status, abdf_cell_stats *stats,
+                              abdf_tape **tape, void *stream);
+
+/* Reverse sweep of a tape for dL_dx = dL/dx(t_end) (DEVICE [n_cells][S]).
+ * Outputs (DEVICE, each may be NULL):
+ *   dL_dlog_alpha      [R]          summed over cells, in cell order
+ *   dL_dlog_alpha_cell [n_cells][R] per cell
+ *   dL_dx0             [n_cells][S]
+ * Cells whose forward status was not ABDF_CELL_OK contribute zeros.  A tape
+ * may be swept any number of times.  Errors: ABDF_E_ARG, ABDF_E_NOMEM,
+ * ABDF_E_DEVICE. */
+abdf_status abdf_tape_adjoint(abdf_tape *tape, const double *dL_dx, double *dL_dlog_alpha,
+                              double *dL_dlog_alpha_cell, double *dL_dx0, void *stream);
+
+/* Device bytes held by the tape's checkpoint (inputs, alpha, steps). */
+int64_t abdf_tape_bytes(const abdf_tape *tape);
+void abdf_tape_free(abdf_tape *tape);
+
+/* Record, sweep and free in one call. */
+abdf_status abdf_solve_adjoint(const abdf_network *net, int64_t n_cells,
+                               const double *T, const double *n_H, const double *A_V,
+                               const double *zeta, const double *G0,
+                               const double *x0, const double *t_end, const double *alpha,
+                               const abdf_options *opt, const double *dL_dx,
+                               double *x_out, int32_t *cell_status,
+                               double *dL_dlog_alpha, double *dL_dlog_alpha_cell, double *dL_dx0,
+                               abdf_cell_stats *stats, void *stream);
+
 /* -------------------------------------------------- component entry points --
  * The steps of one BDF step on their own, for kernel-level checks and timing.
  */
@@ -194,7 +340,9 @@ enum {
     ABDF_PROF_CONTROL = 3,  /* error test, step/order control, next predictor */
     ABDF_PROF_HARVEST = 4,  /* copy-out of finished cells */
     ABDF_PROF_RHS = 5,      /* Newton residual: rates times abundances, species sums */
-    ABDF_PROF_KINDS = 6
+    ABDF_PROF_ADJ_SOLVE = 6,  /* reverse sweep: transposed triangular solves */
+    ABDF_PROF_ADJ_STEP = 7,   /* reverse sweep: adjoint step update and parameter gradient */
+    ABDF_PROF_KINDS = 8
 };
 
 typedef struct abdf_profile {

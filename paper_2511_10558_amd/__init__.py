@@ -127,12 +127,14 @@ def make_options(rtol=1e-6, atol=1e-20, max_steps=100000, precision="fp64", chec
     return o
 
 
+_STATS_DTYPE = np.dtype([("n_steps", "<i4"), ("n_attempts", "<i4"), ("n_err_reject", "<i4"),
+                         ("n_newton_fail", "<i4"), ("n_rhs", "<i4"), ("n_jac", "<i4"), ("n_lu", "<i4"),
+                         ("order", "<i4"), ("h", "<f8"), ("t", "<f8")])
+
+
 def stats_to_numpy(buf) -> np.ndarray:
     """Device byte tensor of abdf_cell_stats -> numpy structured array."""
-    dt = np.dtype([("n_steps", "<i4"), ("n_attempts", "<i4"), ("n_err_reject", "<i4"),
-                   ("n_newton_fail", "<i4"), ("n_rhs", "<i4"), ("n_jac", "<i4"), ("n_lu", "<i4"),
-                   ("order", "<i4"), ("h", "<f8"), ("t", "<f8")])
-    return buf.cpu().numpy().view(dt)
+    return buf.cpu().numpy().view(_STATS_DTYPE)
 
 
 def solve(net: Network, T, n_H, A_V, zeta, G0, x0, t_end, *, options: Options | None = None,
@@ -224,6 +226,99 @@ def profile_read(reset: bool = False) -> dict:
     p = _lib.Profile()
     _lib.lib().abdf_profile_read(ctypes.byref(p), 1 if reset else 0)
     return {k: (int(p.launches[i]), float(p.ms[i])) for i, k in enumerate(_lib.PROFILE_KINDS)}
+
+
+class Server:
+    """Continuous-batching request server (abdf_server_*).  Inputs are host
+    numpy arrays copied at submission; each request's outputs are host numpy
+    arrays owned here until its completion is returned by poll()."""
+
+    def __init__(self, net: Network, *, max_slots=0, max_queued_cells=0, options: Options | None = None, **opts):
+        L = _lib.lib()
+        so = _lib.ServerOptions()
+        L.abdf_server_options_default(ctypes.byref(so))
+        if options is not None:
+            so.solve = options
+        else:
+            o = so.solve
+            for k, v in opts.items():
+                if k == "precision":
+                    v = PREC[v] if isinstance(v, str) else int(v)
+                setattr(o, k, v)
+        so.max_slots, so.max_queued_cells = max_slots, max_queued_cells
+        self._net = net           # the network must outlive the server
+        self._S = net.n_species
+        h = ctypes.c_void_p()
+        _check(L.abdf_server_create(net.handle, ctypes.byref(so), ctypes.byref(h)))
+        self._h = h
+        self._live = {}
+
+    def submit(self, T, n_H, A_V, zeta, G0, x0, t_end, rtol=0.0, atol=-1.0) -> int:
+        f = lambda a: np.ascontiguousarray(a, dtype=np.float64)
+        T, n_H, A_V, zeta, G0, t_end = (f(v).reshape(-1) for v in (T, n_H, A_V, zeta, G0, t_end))
+        x0 = f(x0)
+        C = T.shape[0]
+        if x0.shape != (C, self._S) or any(v.shape != (C,) for v in (n_H, A_V, zeta, G0, t_end)):
+            raise ValueError("inconsistent request shapes")
+        x_out = np.empty((C, self._S), dtype=np.float64)
+        status = np.full((C,), -1, dtype=np.int32)
+        stats = np.zeros((C,), dtype=_STATS_DTYPE)
+        r = _lib.Request()
+        r.n_cells = C
+        for name, v in (("T", T), ("n_H", n_H), ("A_V", A_V), ("zeta", zeta), ("G0", G0), ("x0", x0),
+                        ("t_end", t_end)):
+            setattr(r, name, v.ctypes.data)
+        r.rtol, r.atol = rtol, atol
+        r.x_out, r.cell_status, r.stats = x_out.ctypes.data, status.ctypes.data, stats.ctypes.data
+        rid = ctypes.c_uint64()
+        _check(_lib.lib().abdf_server_submit(self._h, ctypes.byref(r), ctypes.byref(rid)))
+        self._live[rid.value] = (x_out, status, stats)
+        return rid.value
+
+    def poll(self, max_n=256, timeout_ms=0) -> list:
+        """Completed requests: dicts with id, x, status, stats, t_submit,
+        t_first_admit, t_done, cancelled."""
+        buf = (_lib.Completion * max_n)()
+        n = ctypes.c_int32()
+        _check(_lib.lib().abdf_server_poll(self._h, buf, max_n, ctypes.byref(n), timeout_ms))
+        out = []
+        for i in range(n.value):
+            c = buf[i]
+            x, st, sts = self._live.pop(c.id, (None, None, None))
+            out.append({"id": c.id, "x": x, "status": st, "stats": sts, "n_cells": c.n_cells,
+                        "n_failed": c.n_failed, "cancelled": bool(c.cancelled), "t_submit": c.t_submit,
+                        "t_first_admit": c.t_first_admit, "t_done": c.t_done})
+        return out
+
+    def cancel(self, rid: int):
+        _check(_lib.lib().abdf_server_cancel(self._h, rid))
+
+    def clock(self) -> float:
+        return _lib.lib().abdf_server_clock(self._h)
+
+    def info(self) -> dict:
+        i = _lib.ServerInfo()
+        _check(_lib.lib().abdf_server_info_get(self._h, ctypes.byref(i)))
+        return {k: getattr(i, k) for k, _ in _lib.ServerInfo._fields_}
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.lib().abdf_server_destroy(h)
+        self._h = None
+        self._live = {}
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def selftest():

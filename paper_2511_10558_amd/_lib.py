@@ -39,11 +39,34 @@ class CellStats(ctypes.Structure):
     ]
 
 
+class ServerOptions(ctypes.Structure):
+    _fields_ = [("solve", Options), ("max_slots", ctypes.c_int64), ("max_queued_cells", ctypes.c_int64)]
+
+
+class Request(ctypes.Structure):
+    _fields_ = [("n_cells", ctypes.c_int64)] + [(n, c_void_p) for n in ("T", "n_H", "A_V", "zeta", "G0", "x0",
+                                                                       "t_end")] + [
+        ("rtol", ctypes.c_double), ("atol", ctypes.c_double),
+        ("x_out", c_void_p), ("cell_status", c_void_p), ("stats", c_void_p)]
+
+
+class Completion(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("n_cells", ctypes.c_int64), ("n_failed", ctypes.c_int64),
+                ("cancelled", ctypes.c_int32), ("reserved", ctypes.c_int32), ("t_submit", ctypes.c_double),
+                ("t_first_admit", ctypes.c_double), ("t_done", ctypes.c_double)]
+
+
+class ServerInfo(ctypes.Structure):
+    _fields_ = [("slots", ctypes.c_int64), ("occupied", ctypes.c_int64), ("queued_cells", ctypes.c_int64),
+                ("completed_requests", ctypes.c_int64), ("completed_cells", ctypes.c_int64),
+                ("busy_slot_seconds", ctypes.c_double), ("uptime", ctypes.c_double)]
+
+
 class Profile(ctypes.Structure):
     _fields_ = [("launches", ctypes.c_int64 * 8), ("ms", ctypes.c_double * 8)]
 
 
-PROFILE_KINDS = ("admit", "factor", "newton", "control", "harvest", "rhs")
+PROFILE_KINDS = ("admit", "factor", "newton", "control", "harvest", "rhs", "adj_solve", "adj_step")
 
 # name -> (restype, argtypes); mirrors include/astrobdf.h
 SIGNATURES = {
@@ -67,6 +90,15 @@ SIGNATURES = {
     "abdf_lu_solve": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, c_void_p, c_void_p, c_void_p, c_void_p]),
     "abdf_selftest": (ctypes.c_int, [c_void_p]),
     "abdf_profile_enable": (None, [ctypes.c_int32]),
+    "abdf_server_options_default": (None, [ctypes.POINTER(ServerOptions)]),
+    "abdf_server_create": (ctypes.c_int, [c_void_p, ctypes.POINTER(ServerOptions), ctypes.POINTER(c_void_p)]),
+    "abdf_server_submit": (ctypes.c_int, [c_void_p, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),
+    "abdf_server_poll": (ctypes.c_int, [c_void_p, ctypes.POINTER(Completion), ctypes.c_int32,
+                                        ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]),
+    "abdf_server_cancel": (ctypes.c_int, [c_void_p, ctypes.c_uint64]),
+    "abdf_server_clock": (ctypes.c_double, [c_void_p]),
+    "abdf_server_info_get": (ctypes.c_int, [c_void_p, ctypes.POINTER(ServerInfo)]),
+    "abdf_server_destroy": (None, [c_void_p]),
     "abdf_profile_read": (None, [ctypes.POINTER(Profile), ctypes.c_int32]),
 }
 

@@ -1,25 +1,39 @@
-"""Builds libastrobdf.so in-tree for gfx950 with hipcc."""
+"""Builds libastrobdf.so in-tree for gfx950 with hipcc (sources compiled in parallel, then linked)."""
 from __future__ import annotations
 
 import os
 import subprocess
+from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["csrc/kernels.hip", "csrc/engine.cpp", "csrc/network.cpp", "csrc/abi.cpp"]
+SOURCES = ["csrc/kernels.hip", "csrc/engine.cpp", "csrc/network.cpp", "csrc/server.cpp", "csrc/adjoint.cpp",
+           "csrc/abi.cpp"]
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-pthread",
     # keep the compiler from forming packed FP32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]
 
 
-def build(verbose: bool = False) -> str:
-    out = os.path.join(HERE, "libastrobdf.so")
-    tmp = out + ".tmp"
-    cmd = ["hipcc", *FLAGS, *[os.path.join(HERE, s) for s in SOURCES], "-o", tmp]
+def _compile(src: str, obj: str) -> None:
+    cmd = ["hipcc", *FLAGS, "-c", os.path.join(HERE, src), "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + res.stderr[-4000:])
+        raise RuntimeError(f"hipcc failed on {src}:\n" + res.stderr[-4000:])
+
+
+def build(verbose: bool = False) -> str:
+    out = os.path.join(HERE, "libastrobdf.so")
+    objdir = os.path.join(HERE, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    objs = [os.path.join(objdir, os.path.basename(s) + ".o") for s in SOURCES]
+    with ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+        list(ex.map(_compile, SOURCES, objs))
+    tmp = out + ".tmp"
+    cmd = ["hipcc", "--offload-arch=gfx950", "-shared", "-fPIC", "-pthread", *objs, "-o", tmp]
+    res = subprocess.run(cmd, capture_output=True, text=True)
+    if res.returncode != 0:
+        raise RuntimeError("link failed:\n" + res.stderr[-4000:])
     if verbose and res.stderr:
         print(res.stderr[-2000:])
     os.replace(tmp, out)

@@ -16,9 +16,19 @@
 #include "engine.hpp"
 #include "kernels.hpp"
 #include "network.hpp"
+#include "server.hpp"
+#include "adjoint.hpp"
 
 struct abdf_network {
     abdf::HostNetwork host;
+};
+
+struct abdf_tape {
+    std::unique_ptr<abdf::Tape> impl;
+};
+
+struct abdf_server {
+    std::unique_ptr<abdf::Server> impl;
 };
 
 namespace {
@@ -64,6 +74,17 @@ abdf_status check_opts(const abdf_options &o) {
         return fail(ABDF_E_ARG, "unknown precision");
     if (o.newton_tol < 0.0 || !std::isfinite(o.newton_tol)) return fail(ABDF_E_ARG, "newton_tol must be >= 0");
     return ABDF_OK;
+}
+
+// Slots that fit in the budget and in 85% of the free device memory (at most `want`).
+long long slot_count(const abdf::DeviceNet &dn, const abdf_options &o, long long want, size_t extra_per_slot = 0) {
+    const size_t per = abdf::Engine::bytes_per_slot(dn, o.precision) + extra_per_slot;
+    long long n = want;
+    if (o.hbm_budget_bytes > 0) n = std::min<long long>(n, (long long)(o.hbm_budget_bytes / per));
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b > 0)
+        n = std::min<long long>(n, (long long)(0.85 * double(free_b) / double(per)));
+    return n;
 }
 
 }  // namespace
@@ -148,12 +169,7 @@ abdf_status abdf_solve(const abdf_network *net, int64_t n_cells, const double *T
         std::string err;
         const abdf::DeviceNet *dn = net->host.device_tables(err);
         if (!dn) return fail(ABDF_E_DEVICE, err);
-        const size_t per = abdf::Engine::bytes_per_slot(*dn, o.precision);
-        long long nslots = n_cells;
-        if (o.hbm_budget_bytes > 0) nslots = std::min<long long>(nslots, (long long)(o.hbm_budget_bytes / per));
-        size_t free_b = 0, total_b = 0;
-        if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b > 0)
-            nslots = std::min<long long>(nslots, (long long)(0.85 * double(free_b) / double(per)));
+        const long long nslots = slot_count(*dn, o, n_cells);
         if (nslots < 1) return fail(ABDF_E_BUDGET, "not even one cell fits in the workspace budget");
         abdf::Engine eng(net->host, *dn, o.precision, o.max_steps);
         int r = eng.init(int(nslots), err);
@@ -168,6 +184,179 @@ abdf_status abdf_solve(const abdf_network *net, int64_t n_cells, const double *T
         return fail(ABDF_E_DEVICE, e.what());
     }
 }
+
+namespace {
+abdf_status check_solve_args(const abdf_network *net, int64_t n_cells, const double *T, const double *n_H,
+                             const double *A_V, const double *zeta, const double *G0, const double *x0,
+                             const double *t_end, const double *x_out, const int32_t *cell_status,
+                             const abdf_cell_stats *stats) {
+    if (!net) return fail(ABDF_E_ARG, "null network");
+    if (n_cells < 0 || n_cells > INT32_MAX) return fail(ABDF_E_ARG, "n_cells out of range");
+    if (n_cells == 0) return ABDF_OK;
+    CHECK_DEV(T, "T");
+    CHECK_DEV(n_H, "n_H");
+    CHECK_DEV(A_V, "A_V");
+    CHECK_DEV(zeta, "zeta");
+    CHECK_DEV(G0, "G0");
+    CHECK_DEV(x0, "x0");
+    CHECK_DEV(t_end, "t_end");
+    CHECK_DEV(x_out, "x_out");
+    CHECK_DEV(cell_status, "cell_status");
+    if (stats) CHECK_DEV(stats, "stats");
+    return ABDF_OK;
+}
+}  // namespace
+
+abdf_status abdf_solve_record(const abdf_network *net, int64_t n_cells, const double *T, const double *n_H,
+                              const double *A_V, const double *zeta, const double *G0, const double *x0,
+                              const double *t_end, const double *alpha, const abdf_options *opt,
+                              int32_t max_tape_steps, double *x_out, int32_t *cell_status, abdf_cell_stats *stats,
+                              abdf_tape **tape, void *stream) {
+    if (!tape) return fail(ABDF_E_ARG, "null tape pointer");
+    *tape = nullptr;
+    abdf_status rc = check_solve_args(net, n_cells, T, n_H, A_V, zeta, G0, x0, t_end, x_out, cell_status, stats);
+    if (rc != ABDF_OK) return rc;
+    if (n_cells == 0) return fail(ABDF_E_ARG, "a tape needs at least one cell");
+    abdf_options o;
+    if (opt) o = *opt; else abdf_options_default(&o);
+    rc = check_opts(o);
+    if (rc != ABDF_OK) return rc;
+    if (o.precision != ABDF_PREC_FP64) return fail(ABDF_E_ARG, "recording solves use FP64 factorisations");
+    if (max_tape_steps < 0) return fail(ABDF_E_ARG, "max_tape_steps must be >= 0");
+    if (alpha) CHECK_DEV(alpha, "alpha");
+    try {
+        std::string err;
+        const abdf::DeviceNet *dn = net->host.device_tables(err);
+        if (!dn) return fail(ABDF_E_DEVICE, err);
+        auto t = std::make_unique<abdf_tape>();
+        t->impl = std::make_unique<abdf::Tape>(net->host, *dn);
+        abdf::BatchIO io{n_cells, T, n_H, A_V, zeta, G0, x0, t_end, x_out, cell_status, stats};
+        int r = t->impl->record(io, alpha, o, max_tape_steps > 0 ? max_tape_steps : 2048,
+                                static_cast<hipStream_t>(stream), err);
+        if (r != ABDF_OK) return fail(static_cast<abdf_status>(r), err);
+        *tape = t.release();
+        return ok();
+    } catch (const std::bad_alloc &) {
+        return fail(ABDF_E_NOMEM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return fail(ABDF_E_DEVICE, e.what());
+    }
+}
+
+abdf_status abdf_tape_adjoint(abdf_tape *tape, const double *dL_dx, double *dL_dlog_alpha,
+                              double *dL_dlog_alpha_cell, double *dL_dx0, void *stream) {
+    if (!tape) return fail(ABDF_E_ARG, "null tape");
+    CHECK_DEV(dL_dx, "dL_dx");
+    if (dL_dlog_alpha) CHECK_DEV(dL_dlog_alpha, "dL_dlog_alpha");
+    if (dL_dlog_alpha_cell) CHECK_DEV(dL_dlog_alpha_cell, "dL_dlog_alpha_cell");
+    if (dL_dx0) CHECK_DEV(dL_dx0, "dL_dx0");
+    try {
+        std::string err;
+        int r = tape->impl->adjoint(dL_dx, dL_dlog_alpha, dL_dlog_alpha_cell, dL_dx0,
+                                    static_cast<hipStream_t>(stream), err);
+        if (r != ABDF_OK) return fail(static_cast<abdf_status>(r), err);
+        return ok();
+    } catch (const std::bad_alloc &) {
+        return fail(ABDF_E_NOMEM, "host allocation failed");
+    }
+}
+
+int64_t abdf_tape_bytes(const abdf_tape *tape) { return tape ? int64_t(tape->impl->bytes()) : 0; }
+
+void abdf_tape_free(abdf_tape *tape) { delete tape; }
+
+abdf_status abdf_solve_adjoint(const abdf_network *net, int64_t n_cells, const double *T, const double *n_H,
+                               const double *A_V, const double *zeta, const double *G0, const double *x0,
+                               const double *t_end, const double *alpha, const abdf_options *opt,
+                               const double *dL_dx, double *x_out, int32_t *cell_status, double *dL_dlog_alpha,
+                               double *dL_dlog_alpha_cell, double *dL_dx0, abdf_cell_stats *stats, void *stream) {
+    abdf_tape *tape = nullptr;
+    abdf_status rc = abdf_solve_record(net, n_cells, T, n_H, A_V, zeta, G0, x0, t_end, alpha, opt, 0, x_out,
+                                       cell_status, stats, &tape, stream);
+    if (rc != ABDF_OK) return rc;
+    rc = abdf_tape_adjoint(tape, dL_dx, dL_dlog_alpha, dL_dlog_alpha_cell, dL_dx0, stream);
+    abdf_tape_free(tape);
+    return rc;
+}
+
+void abdf_server_options_default(abdf_server_options *opt) {
+    if (!opt) return;
+    std::memset(opt, 0, sizeof(*opt));
+    abdf_options_default(&opt->solve);
+    opt->solve.check_every = 4;
+}
+
+abdf_status abdf_server_create(const abdf_network *net, const abdf_server_options *opt, abdf_server **out) {
+    if (!net || !out) return fail(ABDF_E_ARG, "null argument");
+    *out = nullptr;
+    abdf_server_options o;
+    if (opt) o = *opt; else abdf_server_options_default(&o);
+    abdf_status rc = check_opts(o.solve);
+    if (rc != ABDF_OK) return rc;
+    if (o.max_slots < 0 || o.max_slots > INT32_MAX || o.max_queued_cells < 0)
+        return fail(ABDF_E_ARG, "max_slots or max_queued_cells out of range");
+    try {
+        std::string err;
+        const abdf::DeviceNet *dn = net->host.device_tables(err);
+        if (!dn) return fail(ABDF_E_DEVICE, err);
+        // staging per slot: admission inputs (8 + S doubles), outputs (S doubles, status, stats)
+        const size_t staging = (8 + 2 * size_t(dn->S)) * sizeof(double) + 16 + sizeof(abdf_cell_stats);
+        long long nslots = slot_count(*dn, o.solve, o.max_slots > 0 ? o.max_slots : INT32_MAX, staging);
+        if (nslots < 1) return fail(ABDF_E_BUDGET, "not even one cell fits in the workspace budget");
+        int dev = 0;
+        HIP_OR_FAIL(hipGetDevice(&dev));
+        auto s = std::make_unique<abdf_server>();
+        s->impl = std::make_unique<abdf::Server>(net->host, *dn, o, dev);
+        int r = s->impl->start(int(nslots), err);
+        if (r != ABDF_OK) return fail(static_cast<abdf_status>(r), err);
+        *out = s.release();
+        return ok();
+    } catch (const std::bad_alloc &) {
+        return fail(ABDF_E_NOMEM, "host allocation failed");
+    } catch (const std::exception &e) {
+        return fail(ABDF_E_DEVICE, e.what());
+    }
+}
+
+abdf_status abdf_server_submit(abdf_server *srv, const abdf_request *req, uint64_t *id) {
+    if (!srv || !req || !id) return fail(ABDF_E_ARG, "null argument");
+    try {
+        std::string err;
+        int r = srv->impl->submit(*req, id, err);
+        if (r != ABDF_OK) return fail(static_cast<abdf_status>(r), err);
+        return ok();
+    } catch (const std::bad_alloc &) {
+        return fail(ABDF_E_NOMEM, "host allocation failed");
+    }
+}
+
+abdf_status abdf_server_poll(abdf_server *srv, abdf_completion *out, int32_t max, int32_t *n_out, int32_t timeout_ms) {
+    if (!srv || !n_out || (max > 0 && !out) || max < 0) return fail(ABDF_E_ARG, "bad argument");
+    std::string err;
+    int n = 0;
+    int r = srv->impl->poll(out, max, &n, timeout_ms, err);
+    *n_out = n;
+    if (r != ABDF_OK) return fail(static_cast<abdf_status>(r), err);
+    return ok();
+}
+
+abdf_status abdf_server_cancel(abdf_server *srv, uint64_t id) {
+    if (!srv) return fail(ABDF_E_ARG, "null server");
+    std::string err;
+    int r = srv->impl->cancel(id, err);
+    if (r != ABDF_OK) return fail(static_cast<abdf_status>(r), err);
+    return ok();
+}
+
+double abdf_server_clock(const abdf_server *srv) { return srv ? srv->impl->now() : 0.0; }
+
+abdf_status abdf_server_info_get(abdf_server *srv, abdf_server_info *out) {
+    if (!srv || !out) return fail(ABDF_E_ARG, "null argument");
+    srv->impl->info(out);
+    return ok();
+}
+
+void abdf_server_destroy(abdf_server *srv) { delete srv; }
 
 abdf_status abdf_rates(const abdf_network *net, int64_t n_cells, const double *T, const double *n_H,
                        const double *A_V, const double *zeta, const double *G0, double *k_out, void *stream) {

@@ -51,6 +51,14 @@ struct Slots {
     int32_t *lul;     // [3][n] slots needing a factorisation (ring)
     int32_t *fin;     // [n] finished slots since the last harvest
     int32_t *cnt;     // [0..2] active counts, [3..5] factor counts, [6] finished count
+    // step tape of the discrete adjoint (null when not recording), indexed by cell
+    int tape_cap;     // accepted steps recorded per cell
+    double *tape_x;   // [cells][tape_cap][S] x after each accepted step
+    double *tape_h;   // [cells][tape_cap] its step size
+    int32_t *tape_q;  // [cells][tape_cap] its order
+    int32_t *tape_len;  // [cells] accepted steps recorded
+    const double *tape_x0;   // [cells][S] initial abundances
+    double *g;        // [n][R] reverse sweep: per-slot gradient with respect to log alpha
 };
 
 // One step of a wave-wide arg-max (value descending, key ascending on ties)

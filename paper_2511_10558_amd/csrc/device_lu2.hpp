@@ -556,4 +556,62 @@ __device__ __forceinline__ void lu_solve_left(const T *__restrict__ A, const T *
     }
 }
 
+
+// Solves M^T z = b from the factors of P M = L U (M^T = U^T L^T P): forward
+// substitution with U^T, back substitution with L^T, then z[rowmap[i]] = v[i].
+// b, z and t (>= 5 * kLuW doubles) are in LDS; b is consumed.  256 threads:
+// lane i & 63 owns column i of the current 64-column block, the four waves
+// split the rows, so each wave reads 64 consecutive entries of a row.
+template <typename T>
+__device__ __forceinline__ void lu_solve_left_T(const T *__restrict__ A, const T *__restrict__ dinv,
+                                                const int32_t *__restrict__ rowmap, int NP, double *b, double *z,
+                                                double *t) {
+    const int tid = threadIdx.x;
+    const int col = tid & 63, grp = tid >> 6;
+    const int NB = (NP + kLuW - 1) / kLuW;
+    // t[col] = b[r0 + col] - sum_{r in [rb, re)} A_logical[r][r0 + col] vec[r]
+    auto colgemv = [&](int r0, int W, int rb, int re, const double *vec) {
+        double acc = 0.0;
+        if (col < W) {
+            int r = rb + grp;
+            for (; r + 12 < re; r += 16) {
+                const double a0 = double(A[size_t(rowmap[r]) * NP + r0 + col]);
+                const double a1 = double(A[size_t(rowmap[r + 4]) * NP + r0 + col]);
+                const double a2 = double(A[size_t(rowmap[r + 8]) * NP + r0 + col]);
+                const double a3 = double(A[size_t(rowmap[r + 12]) * NP + r0 + col]);
+                acc += a0 * vec[r] + a1 * vec[r + 4] + a2 * vec[r + 8] + a3 * vec[r + 12];
+            }
+            for (; r < re; r += 4) acc += double(A[size_t(rowmap[r]) * NP + r0 + col]) * vec[r];
+        }
+        t[kLuW + grp * kLuW + col] = acc;
+        __syncthreads();
+        if (tid < W) t[tid] = b[r0 + tid] - ((t[kLuW + tid] + t[2 * kLuW + tid]) + (t[3 * kLuW + tid] + t[4 * kLuW + tid]));
+        __syncthreads();
+    };
+    // out[r0 + col] = sum_c Dm[c][col] t[c] (transpose of a stored 64 x 64 inverse)
+    auto diagT = [&](int r0, int W, const T *Dm, double *out) {
+        double acc = 0.0;
+        if (col < W)
+            for (int c = grp; c < W; c += 4) acc += double(Dm[c * kLuW + col]) * t[c];
+        t[kLuW + grp * kLuW + col] = acc;
+        __syncthreads();
+        if (tid < W) out[r0 + tid] = (t[kLuW + tid] + t[2 * kLuW + tid]) + (t[3 * kLuW + tid] + t[4 * kLuW + tid]);
+        __syncthreads();
+    };
+    // U^T w = b  (w kept in b)
+    for (int ib = 0; ib < NB; ++ib) {
+        const int r0 = ib * kLuW, W = min(kLuW, NP - r0);
+        colgemv(r0, W, 0, r0, b);
+        diagT(r0, W, dinv + size_t(ib) * 2 * kLuW * kLuW + kLuW * kLuW, b);
+    }
+    // L^T v = w  (v kept in b)
+    for (int ib = NB - 1; ib >= 0; --ib) {
+        const int r0 = ib * kLuW, W = min(kLuW, NP - r0);
+        colgemv(r0, W, r0 + W, NP, b);
+        diagT(r0, W, dinv + size_t(ib) * 2 * kLuW * kLuW, b);
+    }
+    for (int i = tid; i < NP; i += blockDim.x) z[rowmap[i]] = b[i];
+    __syncthreads();
+}
+
 }  // namespace abdf

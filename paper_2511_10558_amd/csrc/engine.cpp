@@ -191,8 +191,23 @@ int Engine::init(int nslots, std::string &err) {
     grid_factor_max_ = cus * resident_per_cu(0, prec_, lds_factor_);
     grid_newton_max_ = cus * resident_per_cu(1, prec_, lds_newton_);
     grid_solve_max_ = cus * resident_per_cu(2, prec_, lds_solve_);
+    grid_adj_solve_max_ = cus * resident_per_cu(3, prec_, adj_solve_lds(dn_));
     free_.clear();
     for (int i = nslots - 1; i >= 0; --i) free_.push_back(i);
+    return ABDF_OK;
+}
+
+double Engine::newton_tolerance(const abdf_options &opt) {
+    return opt.newton_tol > 0 ? opt.newton_tol
+                              : std::max(10.0 * kURound / opt.rtol, std::min(0.03, std::sqrt(opt.rtol)));
+}
+
+int Engine::admit_cells(const AdmitArgs &a, hipStream_t st, std::string &err) {
+    if (a.count <= 0) return ABDF_OK;
+    hipEvent_t t0 = timer_begin(st);
+    HIP_TRY(launch_admit(s_, dn_, a, ring_, lds_admit_, st));
+    timer_end(ABDF_PROF_ADMIT, t0, st);
+    bound_ += a.count;
     return ABDF_OK;
 }
 
@@ -200,13 +215,12 @@ int Engine::admit(const BatchIO &io, const abdf_options &opt, long long &next, h
     const long long want = std::min<long long>(static_cast<long long>(free_.size()), io.n_cells - next);
     if (want <= 0) return ABDF_OK;
     for (long long i = 0; i < want; ++i) {
-        h_admit_slots_[i] = free_.back();
-        free_.pop_back();
+        h_admit_slots_[i] = take_slot();
         h_admit_cells_[i] = next + i;
     }
     HIP_TRY(hipMemcpyAsync(d_admit_slots_, h_admit_slots_, want * sizeof(int32_t), hipMemcpyHostToDevice, st));
     HIP_TRY(hipMemcpyAsync(d_admit_cells_, h_admit_cells_, want * sizeof(long long), hipMemcpyHostToDevice, st));
-    AdmitArgs a;
+    AdmitArgs a{};
     a.count = int(want);
     a.slots = d_admit_slots_;
     a.cells = d_admit_cells_;
@@ -219,42 +233,55 @@ int Engine::admit(const BatchIO &io, const abdf_options &opt, long long &next, h
     a.t_end = io.t_end;
     a.rtol = opt.rtol;
     a.atol = opt.atol;
-    a.newton_tol = opt.newton_tol > 0 ? opt.newton_tol
-                                      : std::max(10.0 * kURound / opt.rtol, std::min(0.03, std::sqrt(opt.rtol)));
-    hipEvent_t t0 = timer_begin(st);
-    HIP_TRY(launch_admit(s_, dn_, a, ring_, lds_admit_, st));
-    timer_end(0, t0, st);
+    a.newton_tol = newton_tolerance(opt);
     // the pinned admission buffers are rewritten only after the next poll's synchronisation
     next += want;
-    bound_ += int(want);
+    return admit_cells(a, st, err);
+}
+
+int Engine::attempt(hipStream_t st, std::string &err) {
+    if (bound_ <= 0) return ABDF_OK;
+    hipEvent_t t0 = timer_begin(st);
+    HIP_TRY(launch_factor(s_, dn_, ring_, std::min(bound_, grid_factor_max_), lds_factor_, st));
+    timer_end(ABDF_PROF_FACTOR, t0, st);
+    for (int m = 0; m < kNewtonMaxIter; ++m) {
+        t0 = timer_begin(st);
+        HIP_TRY(launch_newton_rhs(s_, dn_, ring_, std::min(bound_, grid_newton_max_), lds_newton_, st));
+        timer_end(ABDF_PROF_RHS, t0, st);
+        t0 = timer_begin(st);
+        HIP_TRY(launch_newton_solve(s_, ring_, std::min(bound_, grid_solve_max_), lds_solve_, st));
+        timer_end(ABDF_PROF_NEWTON, t0, st);
+    }
+    t0 = timer_begin(st);
+    HIP_TRY(launch_control(s_, ring_, bound_, st));
+    timer_end(ABDF_PROF_CONTROL, t0, st);
+    ring_ = (ring_ + 1) % 3;
     return ABDF_OK;
 }
 
-int Engine::poll(hipStream_t st, std::string &err) {
+int Engine::sync_counts(hipStream_t st, int &nfin, std::string &err) {
     HIP_TRY(hipMemcpyAsync(h_cnt_, s_.cnt, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     flush_timers();
-    const int nfin = h_cnt_[6];
+    nfin = h_cnt_[6];
     bound_ = h_cnt_[ring_];
-    if (nfin > 0) {
-        HIP_TRY(hipMemcpyAsync(h_fin_, s_.fin, nfin * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        HarvestArgs h;
-        h.count = nfin;
-        h.slots = s_.fin;
-        h.x_out = io_->x_out;
-        h.status = io_->status;
-        h.stats = io_->stats;
-        hipEvent_t t0 = timer_begin(st);
-        HIP_TRY(launch_harvest(s_, h, st));
-        timer_end(4, t0, st);
-        HIP_TRY(hipStreamSynchronize(st));
-        for (int i = 0; i < nfin; ++i) free_.push_back(h_fin_[i]);
-    }
+    return ABDF_OK;
+}
+
+int Engine::harvest(HarvestArgs h, hipStream_t st, std::string &err) {
+    const int nfin = h.count;
+    if (nfin <= 0) return ABDF_OK;
+    HIP_TRY(hipMemcpyAsync(h_fin_, s_.fin, nfin * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    h.slots = s_.fin;
+    hipEvent_t t0 = timer_begin(st);
+    HIP_TRY(launch_harvest(s_, h, st));
+    timer_end(ABDF_PROF_HARVEST, t0, st);
+    HIP_TRY(hipStreamSynchronize(st));
+    for (int i = 0; i < nfin; ++i) free_.push_back(h_fin_[i]);
     return ABDF_OK;
 }
 
 int Engine::solve(const BatchIO &io, const abdf_options &opt, hipStream_t st, std::string &err) {
-    io_ = &io;
     ring_ = 0;
     bound_ = 0;
     long long next = 0;
@@ -264,26 +291,21 @@ int Engine::solve(const BatchIO &io, const abdf_options &opt, hipStream_t st, st
     int since_poll = 0;
     while (true) {
         if (bound_ > 0) {
-            hipEvent_t t0 = timer_begin(st);
-            HIP_TRY(launch_factor(s_, dn_, ring_, std::min(bound_, grid_factor_max_), lds_factor_, st));
-            timer_end(1, t0, st);
-            for (int m = 0; m < kNewtonMaxIter; ++m) {
-                t0 = timer_begin(st);
-                HIP_TRY(launch_newton_rhs(s_, dn_, ring_, std::min(bound_, grid_newton_max_), lds_newton_, st));
-                timer_end(5, t0, st);
-                t0 = timer_begin(st);
-                HIP_TRY(launch_newton_solve(s_, ring_, std::min(bound_, grid_solve_max_), lds_solve_, st));
-                timer_end(2, t0, st);
-            }
-            t0 = timer_begin(st);
-            HIP_TRY(launch_control(s_, ring_, bound_, st));
-            timer_end(3, t0, st);
-            ring_ = (ring_ + 1) % 3;
+            rc = attempt(st, err);
+            if (rc != ABDF_OK) return rc;
             ++since_poll;
         }
         if (bound_ == 0 || since_poll >= check_every) {
             since_poll = 0;
-            rc = poll(st, err);
+            int nfin = 0;
+            rc = sync_counts(st, nfin, err);
+            if (rc != ABDF_OK) return rc;
+            HarvestArgs h{};
+            h.count = nfin;
+            h.x_out = io.x_out;
+            h.status = io.status;
+            h.stats = io.stats;
+            rc = harvest(h, st, err);
             if (rc != ABDF_OK) return rc;
             rc = admit(io, opt, next, st, err);
             if (rc != ABDF_OK) return rc;
@@ -292,7 +314,75 @@ int Engine::solve(const BatchIO &io, const abdf_options &opt, hipStream_t st, st
     }
     HIP_TRY(hipStreamSynchronize(st));
     flush_timers();
-    io_ = nullptr;
+    return ABDF_OK;
+}
+
+int Engine::reverse(const AdjIO &io, int check_every, hipStream_t st, std::string &err) {
+    ring_ = 0;
+    bound_ = 0;
+    HIP_TRY(hipMemsetAsync(s_.cnt, 0, 8 * sizeof(int32_t), st));
+    const size_t lds_adj = adj_lds(dn_), lds_adj_solve = adj_solve_lds(dn_);
+    if (lds_adj > kMaxLds || lds_adj_solve > kMaxLds) {
+        err = "network too large for one workgroup's LDS";
+        return ABDF_E_ARG;
+    }
+    check_every = std::max(1, check_every);
+    long long next = 0;
+    auto admit_rev = [&]() -> int {
+        const long long want = std::min<long long>(static_cast<long long>(free_.size()), io.n_cells - next);
+        if (want <= 0) return ABDF_OK;
+        for (long long i = 0; i < want; ++i) {
+            h_admit_slots_[i] = take_slot();
+            h_admit_cells_[i] = next + i;
+        }
+        HIP_TRY(hipMemcpyAsync(d_admit_slots_, h_admit_slots_, want * sizeof(int32_t), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(d_admit_cells_, h_admit_cells_, want * sizeof(long long), hipMemcpyHostToDevice, st));
+        AdjArgs a{int(want), d_admit_slots_, d_admit_cells_, io.phi, io.dLdx, io.status};
+        hipEvent_t t0 = timer_begin(st);
+        HIP_TRY(launch_adj_admit(s_, dn_, a, ring_, lds_adj, st));
+        timer_end(ABDF_PROF_ADMIT, t0, st);
+        next += want;
+        bound_ += int(want);
+        return ABDF_OK;
+    };
+    int rc = admit_rev();
+    if (rc != ABDF_OK) return rc;
+    int since = 0;
+    while (true) {
+        if (bound_ > 0) {
+            hipEvent_t t0 = timer_begin(st);
+            HIP_TRY(launch_factor(s_, dn_, ring_, std::min(bound_, grid_factor_max_), lds_factor_, st));
+            timer_end(ABDF_PROF_FACTOR, t0, st);
+            t0 = timer_begin(st);
+            HIP_TRY(launch_adj_solve(s_, ring_, std::min(bound_, grid_adj_solve_max_), lds_adj_solve, st));
+            timer_end(ABDF_PROF_ADJ_SOLVE, t0, st);
+            t0 = timer_begin(st);
+            HIP_TRY(launch_adj_step(s_, dn_, ring_, bound_, lds_adj, st));
+            timer_end(ABDF_PROF_ADJ_STEP, t0, st);
+            ring_ = (ring_ + 1) % 3;
+            ++since;
+        }
+        if (bound_ == 0 || since >= check_every) {
+            since = 0;
+            int nfin = 0;
+            rc = sync_counts(st, nfin, err);
+            if (rc != ABDF_OK) return rc;
+            if (nfin > 0) {
+                HIP_TRY(hipMemcpyAsync(h_fin_, s_.fin, nfin * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+                AdjHarvestArgs h{nfin, s_.fin, io.g_cell, io.dx0};
+                hipEvent_t t0 = timer_begin(st);
+                HIP_TRY(launch_adj_harvest(s_, h, st));
+                timer_end(ABDF_PROF_HARVEST, t0, st);
+                HIP_TRY(hipStreamSynchronize(st));
+                for (int i = 0; i < nfin; ++i) free_.push_back(h_fin_[i]);
+            }
+            rc = admit_rev();
+            if (rc != ABDF_OK) return rc;
+            if (bound_ == 0 && next >= io.n_cells) break;
+        }
+    }
+    HIP_TRY(hipStreamSynchronize(st));
+    flush_timers();
     return ABDF_OK;
 }
 

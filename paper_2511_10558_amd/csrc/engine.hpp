@@ -24,6 +24,16 @@ struct BatchIO {
     abdf_cell_stats *stats;
 };
 
+// Device inputs/outputs of one reverse sweep (tape-owned or caller-owned device pointers).
+struct AdjIO {
+    long long n_cells;
+    const double *phi;        // [n][5]
+    const double *dLdx;       // [n][S]
+    const int32_t *status;    // [n] forward outcome
+    double *g_cell;           // [n][R] gradient with respect to log alpha per cell
+    double *dx0;              // [n][S] or null
+};
+
 // Process-wide kernel timers (abdf_profile_*).
 struct Profiler {
     static bool on();
@@ -46,12 +56,42 @@ class Engine {
     // Solves every cell of io; returns an abdf_status.
     int solve(const BatchIO &io, const abdf_options &opt, hipStream_t st, std::string &err);
 
-  private:
-    int poll(hipStream_t st, std::string &err);
+    // Reverse sweep of the recorded steps (the slots' tape pointers must be set).
+    int reverse(const AdjIO &io, int check_every, hipStream_t st, std::string &err);
+
+    // Building blocks of a driver loop (batch solve, server, adjoint).
+    int nslots() const { return s_.nslots; }
+    int free_count() const { return int(free_.size()); }
+    // Slots on the current attempt list (an upper bound until the next sync_counts).
+    int running() const { return bound_; }
+    int take_slot() {
+        const int v = free_.back();
+        free_.pop_back();
+        return v;
+    }
+    // Admits a.count cells into the slots a.slots (taken with take_slot).
+    int admit_cells(const AdmitArgs &a, hipStream_t st, std::string &err);
+    // One step attempt of every running slot.
+    int attempt(hipStream_t st, std::string &err);
+    // Waits for the stream and reads the running and finished counts.
+    int sync_counts(hipStream_t st, int &nfin, std::string &err);
+    // Copies the nfin finished slots out (h.count = nfin, h.slots = the finished
+    // list), waits, and returns the slots to the free list; their ids stay
+    // readable in finished_slots() until the next harvest.
+    int harvest(HarvestArgs h, hipStream_t st, std::string &err);
+    const int32_t *finished_slots() const { return h_fin_; }
+    const int32_t *device_finished_list() const { return s_.fin; }
+    Slots &slots() { return s_; }
+    const DeviceNet &net() const { return dn_; }
+    int ring() const { return ring_; }
     // kernel timers: an event before a launch, and after it with its family
     hipEvent_t timer_begin(hipStream_t st);
     void timer_end(int kind, hipEvent_t a, hipStream_t st);
     void flush_timers();
+    // Newton tolerance for a relative tolerance (option value if positive).
+    static double newton_tolerance(const abdf_options &opt);
+
+  private:
     int admit(const BatchIO &io, const abdf_options &opt, long long &next, hipStream_t st, std::string &err);
 
     const HostNetwork &net_;
@@ -70,8 +110,7 @@ class Engine {
     int bound_ = 0;
     size_t lds_admit_ = 0, lds_factor_ = 0, lds_newton_ = 0, lds_solve_ = 0;
     int grid_factor_max_ = 256, grid_newton_max_ = 512, grid_solve_max_ = 1024;   // persistent grid sizes
-    // harvest target of the current solve
-    const BatchIO *io_ = nullptr;
+    int grid_adj_solve_max_ = 1024;
     // kernel timers of launches not yet read back
     struct Pending { int kind; hipEvent_t a, b; };
     std::vector<Pending> pending_;

@@ -182,9 +182,10 @@ __global__ void __launch_bounds__(kBlock) k_admit(Slots s, DeviceNet n, AdmitArg
         SlotCtl z = {};
         z.t = 0.0;
         z.t_end = a.t_end[cell];
-        z.rtol = a.rtol;
-        z.atol = a.atol;
-        z.newton_tol = a.newton_tol;
+        z.rtol = a.rtol_c ? a.rtol_c[cell] : a.rtol;
+        z.atol = a.atol_c ? a.atol_c[cell] : a.atol;
+        z.newton_tol = a.newton_tol > 0.0 ? a.newton_tol
+                                          : fmax(10.0 * kURound / z.rtol, fmin(0.03, sqrt(z.rtol)));
         z.q = 1;
         z.status = kRunning;
         z.j_fresh = 1;
@@ -204,7 +205,8 @@ __global__ void __launch_bounds__(kBlock) k_admit(Slots s, DeviceNet n, AdmitArg
     __syncthreads();
     const double T = phi[0], nH = phi[1], Av = phi[2], zeta = phi[3], G0 = phi[4];
     bad |= !(isfinite(T) && T > 0.0 && isfinite(nH) && nH > 0.0 && isfinite(Av) && isfinite(zeta) &&
-             zeta >= 0.0 && isfinite(G0) && G0 >= 0.0 && isfinite(cs.t_end) && cs.t_end >= 0.0);
+             zeta >= 0.0 && isfinite(G0) && G0 >= 0.0 && isfinite(cs.t_end) && cs.t_end >= 0.0 &&
+             isfinite(cs.rtol) && cs.rtol > 0.0 && isfinite(cs.atol) && cs.atol >= 0.0);
     bad = block_any(bad, red);
     if (bad) {
         finish_slot(s, slot, cs, ABDF_CELL_BAD_INPUT);
@@ -456,7 +458,15 @@ __global__ void __launch_bounds__(kBlock) k_control(Slots s, int ring) {
         begin_attempt(s, slot, cs, next, RU, sh + 2);
         return;
     }
-    // accept: update the differences, collect the order-selection norms
+    // accept: update the differences, collect the order-selection norms, and
+    // record the step when a tape is attached
+    if (s.tape_x && cs.n_steps >= s.tape_cap) {
+        finish_slot(s, slot, cs, ABDF_CELL_TAPE_FULL);
+        __syncthreads();
+        if (threadIdx.x == 0) s.ctl[slot] = cs;
+        return;
+    }
+    double *tx = s.tape_x ? s.tape_x + (size_t(cs.cell) * s.tape_cap + cs.n_steps) * S : nullptr;
     const double em_c = q > 1 ? 1.0 / q : 0.0;
     const double ep_c = 1.0 / (q + 2);
     double am = 0.0, ap = 0.0;
@@ -470,6 +480,7 @@ __global__ void __launch_bounds__(kBlock) k_control(Slots s, int ring) {
         v[q + 1] = di;
         for (int j = q; j >= 0; --j) v[j] = v[j] + v[j + 1];
         for (int j = 0; j <= q + 2; ++j) D[j * S + i] = v[j];
+        if (tx) tx[i] = v[0];
         const double a1 = em_c * v[q] / sc, a2 = ep_c * v[q + 2] / sc;
         am += a1 * a1;
         ap += a2 * a2;
@@ -479,6 +490,10 @@ __global__ void __launch_bounds__(kBlock) k_control(Slots s, int ring) {
     const double sp = block_sum(ap, red);
     nonfinite = block_any(nonfinite, red);
     if (threadIdx.x == 0) {
+        if (tx) {
+            s.tape_h[size_t(cs.cell) * s.tape_cap + cs.n_steps] = cs.h;
+            s.tape_q[size_t(cs.cell) * s.tape_cap + cs.n_steps] = q;
+        }
         cs.t = cs.landing ? cs.t_end : cs.t + cs.h;
         cs.n_steps += 1;
         cs.n_equal += 1;
@@ -526,10 +541,11 @@ __global__ void __launch_bounds__(kBlock) k_harvest(Slots s, HarvestArgs h) {
     if (idx >= h.count) return;
     const int slot = h.slots[idx];
     const SlotCtl &c = s.ctl[slot];
-    const long long cell = c.cell;
+    const long long cell = h.compact ? idx : c.cell;
     const int S = s.S;
     for (int i = threadIdx.x; i < S; i += kBlock) h.x_out[size_t(cell) * S + i] = s.D[size_t(slot) * kDRows * S + i];
     if (threadIdx.x == 0) {
+        if (s.tape_len) s.tape_len[c.cell] = c.n_steps;
         h.status[cell] = c.status;
         if (h.stats) {
             abdf_cell_stats st;
@@ -546,6 +562,269 @@ __global__ void __launch_bounds__(kBlock) k_harvest(Slots s, HarvestArgs h) {
             h.stats[cell] = st;
         }
     }
+}
+
+// ---------------------------------------------------------------- adjoint --
+//
+// Reverse sweep of the frozen-sequence BDF map: the accepted (h_n, q_n) of a
+// recorded solve, each corrector equation c f(x_{n+1}) - psi - d = 0 taken as
+// solved exactly.  lambda_j (stored in D) is the adjoint of difference row j.
+// Step n, in reverse:
+//   difference update   lambda_{j+1} += lambda_j (j = 0..q), lambda_d =
+//                       lambda_{q+1} + lambda_{q+2}, lambda_{q+1} = -lambda_{q+2},
+//                       lambda_{q+2} = 0
+//   corrector           mu = M^{-T} lambda_d with M = I - c J(x_{n+1}) factored afresh
+//   predictor           lambda_j += mu - lambda_d (j <= q), lambda_j -= gamma_j / gamma_q mu (1 <= j <= q)
+//   parameters          dL/dlog alpha_r += c rate_r(x_{n+1}) (nu_r . mu)
+//   step-size change    lambda_{0..q} <- (R(rho) U) lambda when (h, q) changed from step n-1
+// and finally, for D_0 = x_0 and D_1 = h_0 f(x_0):
+//   dL/dlog alpha_r += h_0 rate_r(x_0) (nu_r . lambda_1),  dL/dx_0 = lambda_0 + h_0 J(x_0)^T lambda_1.
+
+// rate_r(x) = k_r x_a (x_b) from the packed reactant pair
+__device__ __forceinline__ double mass_action(const DeviceNet &n, const double *k, const double *xs, int r) {
+    const int ab = n.rx_ab[r];
+    const int a = ab & 0xffff, b = (ab >> 16) & 0xffff;
+    double v = k[r] * xs[a];
+    if (b != 0xffff) v *= xs[b];
+    return v;
+}
+
+// nu_r . v over the reaction's net stoichiometry
+__device__ __forceinline__ double nu_dot(const DeviceNet &n, const double *v, int r) {
+    double w = 0.0;
+    for (int e = n.rnu_ptr[r]; e < n.rnu_ptr[r + 1]; ++e) {
+        const int ent = n.rnu_ent[e];
+        w += double((ent & 7) - 4) * v[ent >> 3];
+    }
+    return w;
+}
+
+// Reverse of rescale_D: lambda_old[b] = sum_a RU[b][a] lambda_new[a], rows 0..q.
+__device__ __forceinline__ void rescale_adjoint(double *L, int S, int q, double rho, double *RU) {
+    if (threadIdx.x == 0) interp_product(q, rho, RU);
+    __syncthreads();
+    for (int i = threadIdx.x; i < S; i += kBlock) {
+        double v[kMaxOrder + 1], w[kMaxOrder + 1];
+        for (int j = 0; j <= q; ++j) v[j] = L[j * S + i];
+        for (int b = 0; b <= q; ++b) {
+            double acc = 0.0;
+            for (int a = 0; a <= q; ++a) acc += RU[b * 6 + a] * v[a];
+            w[b] = acc;
+        }
+        for (int j = 0; j <= q; ++j) L[j * S + i] = w[j];
+    }
+    __syncthreads();
+}
+
+// Queues reverse step cs.n_steps - 1 of a slot: the reverse of its difference
+// update, the corrector point and c for a fresh factorisation.
+__device__ __forceinline__ void adj_begin(const Slots &s, int slot, SlotCtl &cs, int ring) {
+    const int S = s.S;
+    const size_t te = size_t(cs.cell) * s.tape_cap + (cs.n_steps - 1);
+    const int q = s.tape_q[te];
+    const double h = s.tape_h[te];
+    double *L = s.D + size_t(slot) * kDRows * S;
+    double *rb = s.rb + size_t(slot) * S, *xJ = s.xJ + size_t(slot) * S;
+    const double *xt = s.tape_x + te * S;
+    for (int i = threadIdx.x; i < S; i += kBlock) {
+        double v[kDRows];
+        for (int j = 0; j <= q + 2; ++j) v[j] = L[j * S + i];
+        for (int j = 0; j <= q; ++j) v[j + 1] = v[j + 1] + v[j];
+        const double ld = v[q + 1] + v[q + 2];
+        v[q + 1] = -v[q + 2];
+        v[q + 2] = 0.0;
+        for (int j = 0; j <= q + 2; ++j) L[j * S + i] = v[j];
+        rb[i] = ld;
+        xJ[i] = xt[i];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        cs.h = h;
+        cs.q = q;
+        cs.c = h / bdf_gamma(q);
+        const int p = atomicAdd(&s.cnt[ring], 1);
+        s.act[ring * s.nslots + p] = slot;
+        const int pl = atomicAdd(&s.cnt[3 + ring], 1);
+        s.lul[ring * s.nslots + pl] = slot;
+        s.ctl[slot] = cs;
+    }
+}
+
+// Contributions of the starting differences and dL/dx_0 (into s.x); ends the slot.
+// LDS: xs [S], l1 [S], w [R].
+__device__ __forceinline__ void adj_finish(const Slots &s, const DeviceNet &n, int slot, SlotCtl &cs, int len,
+                                           double *smem) {
+    const int S = s.S, R = n.R;
+    double *L = s.D + size_t(slot) * kDRows * S;
+    double *dx0 = s.x + size_t(slot) * S;
+    if (len > 0) {
+        double *xs = smem, *l1 = xs + S, *w = l1 + S;
+        const double h0 = s.tape_h[size_t(cs.cell) * s.tape_cap];
+        const double *x0 = s.tape_x0 + size_t(cs.cell) * S;
+        const double *k = s.k + size_t(slot) * R;
+        double *g = s.g + size_t(slot) * R;
+        for (int i = threadIdx.x; i < S; i += kBlock) {
+            xs[i] = x0[i];
+            l1[i] = L[S + i];
+        }
+        __syncthreads();
+        for (int r = threadIdx.x; r < R; r += kBlock) {
+            const double wr = nu_dot(n, l1, r);
+            w[r] = wr;
+            g[r] += h0 * mass_action(n, k, xs, r) * wr;
+        }
+        __syncthreads();
+        for (int j = threadIdx.x; j < S; j += kBlock) {
+            double jt = 0.0;
+            for (int e = n.dcol_ptr[j]; e < n.dcol_ptr[j + 1]; ++e) {
+                const int ent = n.dcol_ent[e];
+                const int r = ent >> 16, o = (ent & 0xffff) - 1;
+                double d = n.dcol_coef[e] * k[r];
+                if (o >= 0) d *= xs[o];
+                jt += d * w[r];
+            }
+            dx0[j] = L[j] + h0 * jt;
+        }
+    } else {
+        for (int i = threadIdx.x; i < S; i += kBlock) dx0[i] = L[i];
+    }
+    __syncthreads();
+    finish_slot(s, slot, cs, cs.status == kRunning ? ABDF_CELL_OK : cs.status);
+    __syncthreads();
+    if (threadIdx.x == 0) s.ctl[slot] = cs;
+}
+
+// Places cells in slots for the reverse sweep: lambda_0 = dL/dx(t_end), rate
+// coefficients, zero gradient, and the last recorded step queued.
+__global__ void __launch_bounds__(kBlock) k_adj_admit(Slots s, DeviceNet n, AdjArgs a, int ring) {
+    extern __shared__ double smem[];
+    __shared__ SlotCtl cs;
+    const int idx = blockIdx.x;
+    if (idx >= a.count) return;
+    const int slot = a.slots[idx];
+    const long long cell = a.cells[idx];
+    const int S = s.S, R = n.R;
+    const bool ok = a.status[cell] == ABDF_CELL_OK;
+    double *phi = s.phi + size_t(slot) * 5;
+    if (threadIdx.x == 0) {
+        for (int j = 0; j < 5; ++j) phi[j] = a.phi[cell * 5 + j];
+        SlotCtl z = {};
+        z.cell = int32_t(cell);
+        z.n_steps = ok ? s.tape_len[cell] : 0;
+        z.status = ok ? kRunning : a.status[cell];
+        z.q = 1;
+        cs = z;
+    }
+    double *L = s.D + size_t(slot) * kDRows * S;
+    for (int i = threadIdx.x; i < S; i += kBlock) {
+        L[i] = ok ? a.dLdx[cell * S + i] : 0.0;
+        for (int j = 1; j < kDRows; ++j) L[j * S + i] = 0.0;
+    }
+    double *g = s.g + size_t(slot) * R;
+    for (int r = threadIdx.x; r < R; r += kBlock) g[r] = 0.0;
+    __syncthreads();
+    cell_rates(n, phi, s.k + size_t(slot) * R);
+    __syncthreads();
+    if (cs.n_steps == 0)
+        adj_finish(s, n, slot, cs, 0, smem);
+    else
+        adj_begin(s, slot, cs, ring);
+}
+
+// mu = M^{-T} lambda_d for every queued slot (persistent).
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_adj_solve(Slots s, int ring) {
+    extern __shared__ double smem[];
+    const int count = s.cnt[ring];
+    const int S = s.S, NP = s.NP;
+    for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
+        const int slot = s.act[ring * s.nslots + idx];
+        double *b = smem, *z = b + NP, *t = z + NP;
+        const double *rb = s.rb + size_t(slot) * S;
+        for (int i = threadIdx.x; i < NP; i += kBlock) b[i] = i < S ? rb[i] : 0.0;
+        __syncthreads();
+        lu_solve_left_T<T>(reinterpret_cast<const T *>(s.lu) + size_t(slot) * NP * NP,
+                           reinterpret_cast<const T *>(s.dinv) + size_t(slot) * lu2_dinv_elems<T>(NP),
+                           s.perm + size_t(slot) * NP, NP, b, z, t);
+        double *d = s.d + size_t(slot) * S;
+        for (int i = threadIdx.x; i < S; i += kBlock) d[i] = z[i];
+        __syncthreads();
+    }
+}
+
+// Completes the current reverse step of every queued slot and queues the
+// previous one (or finishes the slot).  One workgroup per slot.
+__global__ void __launch_bounds__(kBlock) k_adj_step(Slots s, DeviceNet n, int ring) {
+    extern __shared__ double smem[];
+    __shared__ SlotCtl cs;
+    __shared__ double RU[36];
+    const int next = (ring + 1) % 3;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const int old = (ring + 2) % 3;
+        s.cnt[old] = 0;
+        s.cnt[3 + old] = 0;
+    }
+    const int idx = blockIdx.x;
+    if (idx >= s.cnt[ring]) return;
+    const int slot = s.act[ring * s.nslots + idx];
+    const int S = s.S, R = n.R;
+    if (threadIdx.x == 0) cs = s.ctl[slot];
+    __syncthreads();
+    const int q = cs.q;
+    const double c = cs.c, gq = bdf_gamma(q);
+    double *L = s.D + size_t(slot) * kDRows * S;
+    const double *rb = s.rb + size_t(slot) * S, *mu = s.d + size_t(slot) * S, *xJ = s.xJ + size_t(slot) * S;
+    double *xs = smem, *ms = xs + S;
+    double gr[kMaxOrder + 1];
+    for (int j = 1; j <= q; ++j) gr[j] = bdf_gamma(j) / gq;
+    for (int i = threadIdx.x; i < S; i += kBlock) {
+        const double m = mu[i];
+        xs[i] = xJ[i];
+        ms[i] = m;
+        const double lxp = m - rb[i];
+        L[i] = L[i] + lxp;
+        for (int j = 1; j <= q; ++j) L[j * S + i] = L[j * S + i] + (lxp - gr[j] * m);
+    }
+    __syncthreads();
+    const double *k = s.k + size_t(slot) * R;
+    double *g = s.g + size_t(slot) * R;
+    for (int r = threadIdx.x; r < R; r += kBlock) g[r] += c * mass_action(n, k, xs, r) * nu_dot(n, ms, r);
+    __syncthreads();
+    const int m = cs.n_steps - 1;
+    if (m > 0) {
+        const size_t te = size_t(cs.cell) * s.tape_cap + m;
+        const double hp = s.tape_h[te - 1];
+        const int qp = s.tape_q[te - 1];
+        if (cs.h != hp || q != qp) rescale_adjoint(L, S, q, cs.h / hp, RU);
+    }
+    if (threadIdx.x == 0) cs.n_steps = m;
+    __syncthreads();
+    if (m > 0)
+        adj_begin(s, slot, cs, next);
+    else
+        adj_finish(s, n, slot, cs, 1, smem);
+}
+
+// Copies the gradients of finished reverse slots to per-cell arrays.
+__global__ void __launch_bounds__(kBlock) k_adj_harvest(Slots s, AdjHarvestArgs h) {
+    const int idx = blockIdx.x;
+    if (idx == 0 && threadIdx.x == 0) s.cnt[6] = 0;
+    if (idx >= h.count) return;
+    const int slot = h.slots[idx];
+    const long long cell = s.ctl[slot].cell;
+    const int S = s.S, R = s.R;
+    for (int r = threadIdx.x; r < R; r += kBlock) h.g_cell[size_t(cell) * R + r] = s.g[size_t(slot) * R + r];
+    if (h.dx0)
+        for (int i = threadIdx.x; i < S; i += kBlock) h.dx0[size_t(cell) * S + i] = s.x[size_t(slot) * S + i];
+}
+
+// out[r] = sum over cells of g_cell[c][r], cells in order.
+__global__ void k_grad_sum(const double *g_cell, long long cells, int R, double *out) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    double acc = 0.0;
+    for (long long c = 0; c < cells; ++c) acc += g_cell[size_t(c) * R + r];
+    out[r] = acc;
 }
 
 // ------------------------------------------------- component entry kernels --
@@ -710,10 +989,14 @@ int resident_per_cu(int which, int prec, size_t lds) {
                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_factor<double>, kLuThreads, lds);
     else if (which == 1)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_newton_rhs, kBlock, lds);
-    else
+    else if (which == 2)
         e = prec == ABDF_PREC_FP32_LU
                 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_newton_solve<float>, kBlock, lds)
                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_newton_solve<double>, kBlock, lds);
+    else
+        e = prec == ABDF_PREC_FP32_LU
+                ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adj_solve<float>, kBlock, lds)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adj_solve<double>, kBlock, lds);
     return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
@@ -761,6 +1044,36 @@ hipError_t launch_control(const Slots &s, int ring, int grid, hipStream_t st) {
 
 hipError_t launch_harvest(const Slots &s, const HarvestArgs &h, hipStream_t st) {
     hipLaunchKernelGGL(k_harvest, dim3(h.count > 0 ? h.count : 1), dim3(kBlock), 0, st, s, h);
+    return LAUNCH_CHECK();
+}
+
+hipError_t launch_adj_admit(const Slots &s, const DeviceNet &n, const AdjArgs &a, int ring, size_t lds, hipStream_t st) {
+    if (a.count == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_adj_admit, dim3(a.count), dim3(kBlock), lds, st, s, n, a, ring);
+    return LAUNCH_CHECK();
+}
+
+hipError_t launch_adj_solve(const Slots &s, int ring, int grid, size_t lds, hipStream_t st) {
+    if (grid == 0) return hipSuccess;
+    if (s.prec == ABDF_PREC_FP32_LU)
+        hipLaunchKernelGGL(k_adj_solve<float>, dim3(grid), dim3(kBlock), lds, st, s, ring);
+    else
+        hipLaunchKernelGGL(k_adj_solve<double>, dim3(grid), dim3(kBlock), lds, st, s, ring);
+    return LAUNCH_CHECK();
+}
+
+hipError_t launch_adj_step(const Slots &s, const DeviceNet &n, int ring, int grid, size_t lds, hipStream_t st) {
+    hipLaunchKernelGGL(k_adj_step, dim3(grid > 0 ? grid : 1), dim3(kBlock), lds, st, s, n, ring);
+    return LAUNCH_CHECK();
+}
+
+hipError_t launch_adj_harvest(const Slots &s, const AdjHarvestArgs &h, hipStream_t st) {
+    hipLaunchKernelGGL(k_adj_harvest, dim3(h.count > 0 ? h.count : 1), dim3(kBlock), 0, st, s, h);
+    return LAUNCH_CHECK();
+}
+
+hipError_t launch_grad_sum(const double *g_cell, long long cells, int R, double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_grad_sum, dim3((R + 255) / 256), dim3(256), 0, st, g_cell, cells, R, out);
     return LAUNCH_CHECK();
 }
 

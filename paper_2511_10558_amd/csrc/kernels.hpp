@@ -18,7 +18,9 @@ struct AdmitArgs {
     const int32_t *slots;       // [count] target slots
     const long long *cells;     // [count] source cell indices
     const double *T, *nH, *Av, *zeta, *G0, *x0, *t_end;
-    double rtol, atol, newton_tol;
+    const double *rtol_c, *atol_c;  // per-cell tolerances [cells], or null for rtol / atol
+    double rtol, atol;
+    double newton_tol;          // > 0: used as is; 0: from each cell's rtol
 };
 
 struct HarvestArgs {
@@ -27,6 +29,24 @@ struct HarvestArgs {
     double *x_out;
     int32_t *status;
     abdf_cell_stats *stats;
+    int compact;                // 1: results of the i-th finished slot go to index i, else to its cell
+};
+
+// Reverse-sweep admission: cells into slots with their loss gradients.
+struct AdjArgs {
+    int count;
+    const int32_t *slots;
+    const long long *cells;
+    const double *phi;          // [cells][5] T, n_H, A_V, zeta, G0
+    const double *dLdx;         // [cells][S] gradient of the loss with respect to x(t_end)
+    const int32_t *status;      // [cells] forward outcome; only ABDF_CELL_OK cells are differentiated
+};
+
+struct AdjHarvestArgs {
+    int count;
+    const int32_t *slots;
+    double *g_cell;             // [cells][R]
+    double *dx0;                // [cells][S] or null
 };
 
 struct PhysArgs {
@@ -48,6 +68,14 @@ hipError_t launch_newton_solve(const Slots &s, int ring, int grid, size_t lds, h
 hipError_t launch_control(const Slots &s, int ring, int grid, hipStream_t st);
 hipError_t launch_harvest(const Slots &s, const HarvestArgs &h, hipStream_t st);
 
+hipError_t launch_adj_admit(const Slots &s, const DeviceNet &n, const AdjArgs &a, int ring, size_t lds, hipStream_t st);
+hipError_t launch_adj_solve(const Slots &s, int ring, int grid, size_t lds, hipStream_t st);
+hipError_t launch_adj_step(const Slots &s, const DeviceNet &n, int ring, int grid, size_t lds, hipStream_t st);
+hipError_t launch_adj_harvest(const Slots &s, const AdjHarvestArgs &h, hipStream_t st);
+hipError_t launch_grad_sum(const double *g_cell, long long cells, int R, double *out, hipStream_t st);
+inline size_t adj_lds(const DeviceNet &n) { return sizeof(double) * (2 * size_t(n.S) + n.R); }
+inline size_t adj_solve_lds(const DeviceNet &n) { return sizeof(double) * (2 * size_t(n.NP) + 5 * 64); }
+
 hipError_t launch_rates(const DeviceNet &n, const PhysArgs &p, long long cells, double *k, hipStream_t st);
 hipError_t launch_rhs(const DeviceNet &n, long long cells, const double *k, const double *x, double *f, hipStream_t st);
 hipError_t launch_newton_matrix(const DeviceNet &n, long long cells, const double *k, const double *x,
@@ -57,8 +85,8 @@ hipError_t launch_lu_factor(int n, int NP, long long batch, double *A, void *W, 
 hipError_t launch_lu_solve(int n, int NP, long long batch, const double *LU, const int32_t *perm, double *b,
                            void *W, int32_t *permW, void *dinv, hipStream_t st);
 size_t dinv_bytes(int NP, int prec);
-// Workgroups resident per CU of the factor (which = 0), Newton residual (1) or
-// Newton solve (2) kernel.
+// Workgroups resident per CU of the factor (which = 0), Newton residual (1),
+// Newton solve (2) or transposed adjoint solve (3) kernel.
 int resident_per_cu(int which, int prec, size_t lds);
 hipError_t launch_selftest(int *bad, hipStream_t st);
 size_t lu_work_lds(int NP, int prec);

@@ -40,7 +40,8 @@ HostNetwork::~HostNetwork() {
         int prev = 0;
         if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(d->device) == hipSuccess) {
             void *ptrs[] = {d->rx_ab, d->rx_type, d->alpha, d->beta, d->gamma, d->seg_ptr, d->seg_beg,
-                            d->f_ent, d->jrow_ptr, d->jcol, d->jrow, d->jterm_ptr, d->jt_rx_other, d->jt_coef};
+                            d->f_ent, d->jrow_ptr, d->jcol, d->jrow, d->jterm_ptr, d->jt_rx_other, d->jt_coef,
+                            d->rnu_ptr, d->rnu_ent, d->dcol_ptr, d->dcol_ent, d->dcol_coef};
             for (void *p : ptrs)
                 if (p) (void)hipFree(p);
             (void)hipSetDevice(prev);
@@ -168,6 +169,9 @@ void HostNetwork::finalize() {
     // Jacobian terms: d rate_r / d x_j of a mass-action rate
     struct Term { int j, r, other; double coef; };
     std::vector<std::vector<Term>> rows(S);
+    rnu_ptr.assign(R + 1, 0);
+    rnu_ent.clear();
+    std::vector<std::vector<Term>> dcols(S);
     for (int r = 0; r < R; ++r) {
         int a = react[size_t(r) * 2], b = react[size_t(r) * 2 + 1];
         Term d[2];
@@ -175,11 +179,15 @@ void HostNetwork::finalize() {
         if (b < 0) d[nd++] = {a, r, -1, 1.0};
         else if (a == b) d[nd++] = {a, r, a, 2.0};
         else { d[nd++] = {a, r, b, 1.0}; d[nd++] = {b, r, a, 1.0}; }
+        for (int q = 0; q < nd; ++q) dcols[d[q].j].push_back(d[q]);
         std::map<int, int> nur;
         for (int j = 0; j < 3; ++j)
             if (prod[size_t(r) * 3 + j] >= 0) nur[prod[size_t(r) * 3 + j]] += 1;
         for (int j = 0; j < 2; ++j)
             if (react[size_t(r) * 2 + j] >= 0) nur[react[size_t(r) * 2 + j]] -= 1;
+        rnu_ptr[r] = int32_t(rnu_ent.size());
+        for (auto &kv : nur)
+            if (kv.second != 0) rnu_ent.push_back((kv.first << 3) | (kv.second + 4));
         for (auto &kv : nur) {
             if (kv.second == 0) continue;
             for (int q = 0; q < nd; ++q)
@@ -212,6 +220,18 @@ void HostNetwork::finalize() {
     }
     jrow_ptr[S] = int32_t(jcol.size());
     jterm_ptr.push_back(int32_t(jt_coef.size()));
+    rnu_ptr[R] = int32_t(rnu_ent.size());
+    dcol_ptr.assign(S + 1, 0);
+    dcol_ent.clear();
+    dcol_coef.clear();
+    for (int j = 0; j < S; ++j) {
+        dcol_ptr[j] = int32_t(dcol_ent.size());
+        for (auto &tm : dcols[j]) {
+            dcol_ent.push_back((tm.r << 16) | (tm.other + 1));
+            dcol_coef.push_back(tm.coef);
+        }
+    }
+    dcol_ptr[S] = int32_t(dcol_ent.size());
 }
 
 namespace {
@@ -264,6 +284,11 @@ const DeviceNet *HostNetwork::device_tables(std::string &err) const {
     chk(upload(&d->jterm_ptr, jterm_ptr));
     chk(upload(&d->jt_rx_other, jt_rx_other));
     chk(upload(&d->jt_coef, jt_coef));
+    chk(upload(&d->rnu_ptr, rnu_ptr));
+    chk(upload(&d->rnu_ent, rnu_ent));
+    chk(upload(&d->dcol_ptr, dcol_ptr));
+    chk(upload(&d->dcol_ent, dcol_ent));
+    chk(upload(&d->dcol_coef, dcol_coef));
     d->n_seg = int32_t(seg_beg.size()) - 1;
     d->nnzJ = int32_t(jcol.size());
     d->nterm = int32_t(jt_coef.size());

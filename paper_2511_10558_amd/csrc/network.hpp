@@ -35,6 +35,13 @@ struct DeviceNet {
     int32_t *jt_rx_other = nullptr;  // reaction << 16 | (other species + 1), 0 in the low half = none
     double *jt_coef = nullptr;     // [nterm] nu_ir * multiplicity
     int32_t nnzJ = 0, nterm = 0;
+    // reaction-major stoichiometry: the species of reaction r with nu != 0
+    int32_t *rnu_ptr = nullptr;    // [R+1]
+    int32_t *rnu_ent = nullptr;    // species << 3 | (nu + 4)
+    // d rate_r / d x_j grouped by species j: reaction << 16 | (other reactant + 1), multiplicity
+    int32_t *dcol_ptr = nullptr;   // [S+1]
+    int32_t *dcol_ent = nullptr;
+    double *dcol_coef = nullptr;
 };
 
 struct HostNetwork {
@@ -53,6 +60,8 @@ struct HostNetwork {
     std::vector<int32_t> seg_ptr, seg_beg, f_ent;
     std::vector<int32_t> jrow_ptr, jcol, jrow, jterm_ptr, jt_rx_other;
     std::vector<double> jt_coef;
+    std::vector<int32_t> rnu_ptr, rnu_ent, dcol_ptr, dcol_ent;
+    std::vector<double> dcol_coef;
 
     // per-device uploads, created on first use
     mutable std::mutex mu;

@@ -115,3 +115,22 @@ def test_null_and_invalid_arguments_without_gpu():
     assert L.abdf_solve(g.handle, 0, *([None] * 7), ctypes.byref(o), None, None, None, None) == 0
     assert L.abdf_solve(g.handle, -1, *([None] * 7), ctypes.byref(o), None, None, None, None) == 1
     assert L.abdf_lu_factor(0, 1, None, None, None, 0, None) == 1
+
+
+def test_server_without_device_fails_cleanly():
+    net = synth.network_for_config("small")
+    g = ab.Network.from_text(net.to_text())
+    import torch
+    if torch.cuda.is_available():
+        pytest.skip("a HIP device is present")
+    with pytest.raises(ab.AbdfError) as e:
+        ab.Server(g)
+    assert e.value.code == 5
+
+
+def test_server_options_defaults():
+    import ctypes
+    so = ab._lib.ServerOptions()
+    ab._lib.lib().abdf_server_options_default(ctypes.byref(so))
+    assert so.solve.rtol == 1e-6 and so.solve.check_every == 4
+    assert so.max_slots == 0 and so.max_queued_cells == 0
