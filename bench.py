@@ -33,27 +33,35 @@ def _oracle_cell(args):
     net = synth.network_for_config(net_name)
     ch = chem.cell_chemistry(net, cells.cell(i))
     r = bdf.solve(ch, cells.x0[i], cells.t_end[i], 1e-6, 1e-20)
-    return r.status
+    return r.status, r.x
 
 
 def cpu_baseline(net_name, cells, n_sample):
-    """The oracle, untuned, one cell per process on the host cores."""
+    """The oracle, untuned, one cell per process on the host cores.  Returns the
+    baseline record and the oracle's abundances of the sampled cells."""
     procs = max(1, min(os.cpu_count() or 1, 16, n_sample))
     import synth  # noqa: F401  (warm the network cache before forking)
     synth.network_for_config(net_name)
     sample = cells.subset(np.arange(n_sample))
     t0 = time.perf_counter()
     with mp.get_context("fork").Pool(procs, initializer=_single_thread_blas) as pool:
-        st = pool.map(_oracle_cell, [(net_name, sample, i) for i in range(n_sample)])
+        res = pool.map(_oracle_cell, [(net_name, sample, i) for i in range(n_sample)])
     wall = time.perf_counter() - t0
-    ok = sum(1 for s in st if s == 0)
-    return {"value": ok / wall, "unit": "cell-solves/s", "cores": procs, "kind": "oracle",
-            "sample": f"first {n_sample} cells of the timed batch, one process per cell, wall {wall:.1f} s"}
+    ok = sum(1 for s, _ in res if s == 0)
+    rec = {"value": ok / wall, "unit": "cell-solves/s", "cores": procs, "kind": "oracle",
+           "sample": f"first {n_sample} cells of the timed batch, one process per cell, wall {wall:.1f} s"}
+    return rec, np.array([x for _, x in res])
+
+
+def max_rel_err(x, ref, floor=1e-12):
+    """max |x - ref| / ref over entries with ref > floor (the abundance parity measure)."""
+    m = ref > floor
+    return float(np.max(np.abs(x[m] - ref[m]) / ref[m])) if m.any() else 0.0
 
 
 def _single_thread_blas():
-    os.environ["OPENBLAS_NUM_THREADS"] = "1"
-    os.environ["OMP_NUM_THREADS"] = "1"
+    from threadpoolctl import threadpool_limits
+    threadpool_limits(1)          # one BLAS thread per worker process
 
 
 def recorded_traffic():
@@ -68,8 +76,156 @@ def recorded_traffic():
     return rec if rec.get("source_hash") == summarize.source_hash() else None
 
 
+def run_serve(args):
+    """Serving workload: Poisson arrivals of requests of 1..1024 cells with
+    horizons log-uniform in 1e3..1e7 yr on one server.  A closed-loop pass
+    (every request queued at once) gives the saturated throughput; the
+    open-loop pass offers 0.8 of it (unless --rate is given) and yields the
+    latency percentiles."""
+    import paper_2511_10558_amd as ab
+    import synth
+    net = synth.network_for_config(args.network)
+    g = ab.Network.from_text(net.to_text())
+    reqs = synth.request_stream(net, args.requests, seed=args.seed, rate_per_s=1.0)
+    warm = synth.request_stream(net, 16, seed=args.seed + 1, rate_per_s=1.0)
+    unit_arrivals = np.array([r.arrival_s for r in reqs])
+    n_cells = sum(r.cells.n for r in reqs)
+    mean_cells = n_cells / len(reqs)
+
+    def submit(srv, cells):
+        return srv.submit(cells.T, cells.n_H, cells.A_V, cells.zeta, cells.G0, cells.x0, cells.t_end)
+
+    def one_pass(precision, arrivals):
+        with ab.Server(g, precision=precision, check_every=args.check_every) as srv:
+            wid = [submit(srv, r.cells) for r in warm]
+            got = 0
+            while got < len(wid):
+                got += len(srv.poll(timeout_ms=500))
+            info0 = srv.info()
+            t0 = srv.clock()
+            ids, done, i = {}, {}, 0
+            while len(done) < len(reqs):
+                now = srv.clock() - t0
+                while i < len(reqs) and arrivals[i] <= now:
+                    ids[submit(srv, reqs[i].cells)] = i
+                    i += 1
+                wait = 200 if i >= len(reqs) else max(0, min(200, int((arrivals[i] - now) * 1e3)))
+                for c in srv.poll(max_n=512, timeout_ms=wait):
+                    done[ids[c["id"]]] = c
+            info1 = srv.info()
+        t_end = max(c["t_done"] for c in done.values()) - t0
+        lat = np.array([done[j]["t_done"] - (t0 + arrivals[j]) for j in range(len(reqs))])
+        failed = sum(c["n_failed"] for c in done.values())
+        busy = info1["busy_slot_seconds"] - info0["busy_slot_seconds"]
+        return {"cell_solves_per_s": round((n_cells - failed) / t_end, 3), "window_s": round(t_end, 3),
+                "p50_latency_s": round(float(np.percentile(lat, 50)), 4),
+                "p99_latency_s": round(float(np.percentile(lat, 99)), 4),
+                "mean_latency_s": round(float(lat.mean()), 4), "failed_cells": int(failed),
+                "slots": int(info1["slots"]), "mean_occupied_slots": round(busy / t_end, 1)}
+
+    out = {"metric": "served cell-solves/sec (Poisson request stream, 500-sp net) with p50/p99 latency",
+           "unit": "cell-solves/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
+           "config": {"workload": f"{args.network} serving: {len(reqs)} requests after 16 warm-up requests, "
+                                  f"{n_cells} cells (1..1024 per request, mean {mean_cells:.1f}), t_end log-uniform "
+                                  "1e3..1e7 yr, rtol 1e-6 atol 1e-20", "requests": len(reqs), "cells": n_cells,
+                      "seed": args.seed}, "passes": {}}
+    for prec in args.serve_precisions.split(","):
+        res = {}
+        if args.rate > 0:
+            rate = args.rate
+        else:
+            closed = one_pass(prec, np.zeros(len(reqs)))
+            res["closed_loop"] = closed
+            rate = 0.8 * closed["cell_solves_per_s"] / mean_cells
+        res["open_loop"] = one_pass(prec, unit_arrivals / rate)
+        res["arrival_rate_req_per_s"] = round(rate, 4)
+        out["passes"][prec] = res
+        print(f"[serve] {prec}: {json.dumps(res)}", file=sys.stderr, flush=True)
+    first = out["passes"][args.serve_precisions.split(",")[0]]["open_loop"]
+    out["value"] = first["cell_solves_per_s"]
+    out["p50_latency_s"], out["p99_latency_s"] = first["p50_latency_s"], first["p99_latency_s"]
+    if "fp64" in out["passes"] and "fp32_lu" in out["passes"]:
+        a, b = out["passes"]["fp64"], out["passes"]["fp32_lu"]
+        key = "closed_loop" if "closed_loop" in a else "open_loop"
+        out["fp32_lu_speedup_saturated"] = round(b[key]["cell_solves_per_s"] / a[key]["cell_solves_per_s"], 4)
+    print(json.dumps(out))
+
+
+def run_adjoint(args):
+    """Differentiation workload: record 256 cells of the 500-species network to
+    1e6 yr, then the discrete adjoint of the loss sum of log x over 10 seeded
+    target species with respect to log alpha of every reaction."""
+    import torch
+    import paper_2511_10558_amd as ab
+    import synth
+    dev = torch.device("cuda:0")
+    net = synth.network_for_config("net500")
+    g = ab.Network.from_text(net.to_text())
+    cells = synth.sample_cells(net, args.adj_cells, seed=5001, t_end_yr=1e6)
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    inp = [t(cells.T), t(cells.n_H), t(cells.A_V), t(cells.zeta), t(cells.G0), t(cells.x0), t(cells.t_end)]
+    # targets: 10 seeded species above 1e-12 in every cell at t_end
+    x_plain, st_plain = ab.solve(g, *inp)
+    xp = x_plain.cpu().numpy()
+    eligible = np.flatnonzero((xp > 1e-12).all(axis=0))
+    targets = np.sort(np.random.default_rng(5002).choice(eligible, 10, replace=False))
+    torch.cuda.synchronize()
+    ab.profile_read(reset=True)
+    ab.profile_enable(True)
+    t0 = time.perf_counter()
+    x, status, tape = ab.solve_record(g, *inp)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    dLdx = torch.zeros_like(x)
+    dLdx[:, targets] = 1.0 / x[:, targets]
+    gsum, gcell, _ = tape.adjoint(dLdx, per_cell=True)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    ab.profile_enable(False)
+    prof = ab.profile_read(reset=True)
+    ok = int((status == 0).sum().item())
+    out = {"metric": "gradient cell-solves/sec (forward with step tape + discrete adjoint), 500-sp net",
+           "value": round(ok / (t2 - t0), 3), "unit": "cell-solves/s", "n_gpus": 1, "higher_is_better": True,
+           "data": "synthetic", "dtype": "f64",
+           "config": {"workload": f"net500 differentiation: {args.adj_cells} cells, t_end 1e6 yr, rtol 1e-6 "
+                                  "atol 1e-20, d(sum of log x over 10 targets)/d log alpha for all 6000 reactions",
+                      "cells": args.adj_cells, "targets": targets.tolist()},
+           "forward_record_s": round(t1 - t0, 3), "reverse_s": round(t2 - t1, 3),
+           "checkpoint_bytes": tape.nbytes, "cells_ok": ok,
+           "forward_equals_plain_solve": bool(torch.equal(x, x_plain)),
+           "kernels": {k: {"launches": v[0], "ms": round(v[1], 3)} for k, v in prof.items()}}
+    tape.free()
+    gold_path = os.path.join(ROOT, "tests", "golden", "adjoint_net500.json")
+    if os.path.exists(gold_path):
+        gold = json.load(open(gold_path))
+        n = len(gold["cells"])
+        gt, gr = np.array(gold["targets"]), np.array(gold["reactions"])
+        sub = [v[:n].contiguous() for v in inp]
+        xs, _ = ab.solve(g, *sub)
+        d = torch.zeros_like(xs)
+        d[:, gt] = 1.0 / xs[:, gt]
+        _, _, _, gc, _ = ab.solve_adjoint(g, *sub, d, per_cell=True)
+        gc = gc.cpu().numpy()
+
+        def err(gv, ref):
+            ref = np.asarray(ref)
+            return float(np.max(np.abs(gv - ref) / np.maximum(np.abs(ref), 1e-3 * np.abs(ref).max())))
+        out["check"] = {"cells": n, "reactions": len(gr),
+                        "max_err_vs_oracle_forward_sensitivities": max(err(gc[c, gr], r["sens"])
+                                                                       for c, r in enumerate(gold["cells"])),
+                        "max_err_vs_central_differences": max(err(gc[c, np.array(gold["fd_reactions"])], r["fd"])
+                                                              for c, r in enumerate(gold["cells"]))}
+    print(json.dumps(out))
+
+
 def main():
     ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="batch", choices=["batch", "serve", "adjoint"])
+    ap.add_argument("--requests", type=int, default=256, help="serve: requests after the warm-up")
+    ap.add_argument("--rate", type=float, default=0.0, help="serve: arrival rate [requests/s]; 0 = 0.8 x saturation")
+    ap.add_argument("--serve-precisions", default="fp64,fp32_lu")
+    ap.add_argument("--check-every", type=int, default=4)
+    ap.add_argument("--adj-cells", type=int, default=256)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
@@ -80,6 +236,8 @@ def main():
     ap.add_argument("--seed", type=int, default=3001)
     ap.add_argument("--cpu-sample", type=int, default=32)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-compare-fp32", dest="compare_fp32", action="store_false",
+                    help="skip the FP32-LU run of the same batch")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="first run one elementwise kernel reading and writing 256 MiB "
                          "(a reference for HBM byte counters)")
@@ -89,6 +247,10 @@ def main():
               "MI355X; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
+    if args.workload == "serve":
+        return run_serve(args)
+    if args.workload == "adjoint":
+        return run_adjoint(args)
     import torch
     import paper_2511_10558_amd as ab
     import synth
@@ -195,9 +357,26 @@ def main():
         "kernels": kern,
         "roofline": roof,
     }
+    x64 = x.cpu().numpy()
+    if args.compare_fp32 and args.precision == "fp64":
+        # the same batch with the Newton-matrix LU in FP32 (residuals, norms, control in FP64)
+        o32 = ab.make_options(rtol=1e-6, atol=1e-20, precision="fp32_lu")
+        ab.solve(g, *inp, options=o32)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x32, st32 = ab.solve(g, *inp, options=o32)
+        torch.cuda.synchronize()
+        w32 = time.perf_counter() - t0
+        ok32 = int((st32 == 0).sum().item())
+        out["fp32_lu"] = {"value": round(ok32 / w32, 3), "unit": "cell-solves/s", "cells_ok": ok32,
+                          "speedup_vs_fp64": round((ok32 / w32) / value, 4),
+                          "max_rel_dev_from_fp64_gpu": max_rel_err(x32.cpu().numpy(), x64)}
     if not args.no_cpu_baseline:
         n = min(args.cpu_sample, args.cells)
-        out["cpu_baseline"] = cpu_baseline(args.network, cells, n)
+        out["cpu_baseline"], xo = cpu_baseline(args.network, cells, n)
+        out["parity_vs_oracle"] = {"cells": n, "max_rel_err_fp64": max_rel_err(x64[:n], xo)}
+        if "fp32_lu" in out:
+            out["parity_vs_oracle"]["max_rel_err_fp32_lu"] = max_rel_err(x32.cpu().numpy()[:n], xo)
     print(json.dumps(out))
 
 

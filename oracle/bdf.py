@@ -257,7 +257,7 @@ def solve(chem, x0, t_end, rtol=1e-6, atol=1e-20, max_steps=100000,
         t = t_end if landing else t + h
         stats.n_steps += 1
         if record:
-            hist.append((h, q, t, D[0] + d))
+            hist.append((h, q, t, x_new.copy()))
         D[q + 2] = d - D[q + 1]
         D[q + 1] = d
         for j in range(q, -1, -1):

@@ -14,7 +14,7 @@ from . import _lib
 from ._lib import CellStats, LibraryMissing, Options  # noqa: F401
 
 PREC = {"fp64": 0, "fp32_lu": 1}
-CELL_STATUS = {0: "ok", 1: "step_too_small", 2: "max_steps", 3: "nonfinite", 4: "bad_input"}
+CELL_STATUS = {0: "ok", 1: "step_too_small", 2: "max_steps", 3: "nonfinite", 4: "bad_input", 5: "tape_full"}
 STATUS_NAMES = {0: "OK", 1: "E_ARG", 2: "E_PARSE", 3: "E_NONCONSERVING", 4: "E_IO", 5: "E_DEVICE",
                 6: "E_BUDGET", 7: "E_NOMEM", 8: "E_BUSY"}
 
@@ -161,6 +161,132 @@ def solve(net: Network, T, n_H, A_V, zeta, G0, x0, t_end, *, options: Options | 
     if with_stats:
         return x_out, status, stats_to_numpy(st)[:C]
     return x_out, status
+
+
+def _cell_args(net, T, n_H, A_V, zeta, G0, x0, t_end):
+    torch = _torch()
+    C = x0.shape[0]
+    f64 = torch.float64
+    args = [_ptr(v, f64, (C,), nm) for v, nm in
+            ((T, "T"), (n_H, "n_H"), (A_V, "A_V"), (zeta, "zeta"), (G0, "G0"))]
+    args.append(_ptr(x0, f64, (C, net.n_species), "x0"))
+    args.append(_ptr(t_end, f64, (C,), "t_end"))
+    return C, args
+
+
+class Tape:
+    """Step tape of a recording solve (abdf_solve_record); reverse sweeps with adjoint()."""
+
+    def __init__(self, handle, net, n_cells, device):
+        self._h, self._net, self.n_cells, self._dev = handle, net, n_cells, device
+
+    @property
+    def nbytes(self) -> int:
+        return int(_lib.lib().abdf_tape_bytes(self._h))
+
+    def adjoint(self, dL_dx, per_cell=False, x0_grad=False):
+        """(dL/dlog alpha [R], dL/dlog alpha per cell [C, R] or None, dL/dx0 [C, S] or None)."""
+        torch = _torch()
+        C, S, R = self.n_cells, self._net.n_species, self._net.n_reactions
+        g = torch.empty((R,), dtype=torch.float64, device=self._dev)
+        gc = torch.empty((C, R), dtype=torch.float64, device=self._dev) if per_cell else None
+        dx0 = torch.empty((C, S), dtype=torch.float64, device=self._dev) if x0_grad else None
+        p = lambda t: ctypes.c_void_p(t.data_ptr() if t is not None else None)
+        _check(_lib.lib().abdf_tape_adjoint(self._h, _ptr(dL_dx.contiguous(), torch.float64, (C, S), "dL_dx"),
+                                            p(g), p(gc), p(dx0), _stream()))
+        return g, gc, dx0
+
+    def free(self):
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            _lib.lib().abdf_tape_free(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def solve_record(net: Network, T, n_H, A_V, zeta, G0, x0, t_end, *, alpha=None, max_tape_steps=0,
+                 options: Options | None = None, with_stats=False, **opts):
+    """Solve and record the step tape.  Returns (x_out, status, tape[, stats])."""
+    torch = _torch()
+    C, args = _cell_args(net, T, n_H, A_V, zeta, G0, x0, t_end)
+    a = ctypes.c_void_p(None) if alpha is None else _ptr(alpha, torch.float64, (net.n_reactions,), "alpha")
+    o = options if options is not None else make_options(**opts)
+    x_out = torch.empty_like(x0)
+    status = torch.full((C,), -1, dtype=torch.int32, device=x0.device)
+    st = torch.zeros((max(C, 1) * ctypes.sizeof(CellStats),), dtype=torch.uint8, device=x0.device) \
+        if with_stats else None
+    h = ctypes.c_void_p()
+    _check(_lib.lib().abdf_solve_record(net.handle, C, *args, a, ctypes.byref(o), int(max_tape_steps),
+                                        ctypes.c_void_p(x_out.data_ptr()), ctypes.c_void_p(status.data_ptr()),
+                                        ctypes.c_void_p(st.data_ptr() if st is not None else None),
+                                        ctypes.byref(h), _stream()))
+    tape = Tape(h, net, C, x0.device)
+    if with_stats:
+        return x_out, status, tape, stats_to_numpy(st)[:C]
+    return x_out, status, tape
+
+
+def solve_adjoint(net: Network, T, n_H, A_V, zeta, G0, x0, t_end, dL_dx, *, alpha=None,
+                  options: Options | None = None, per_cell=False, x0_grad=False, **opts):
+    """One call: (x_out, status, dL/dlog alpha [R], per cell [C, R] or None, dL/dx0 or None)."""
+    torch = _torch()
+    C, args = _cell_args(net, T, n_H, A_V, zeta, G0, x0, t_end)
+    S, R = net.n_species, net.n_reactions
+    a = ctypes.c_void_p(None) if alpha is None else _ptr(alpha, torch.float64, (R,), "alpha")
+    o = options if options is not None else make_options(**opts)
+    x_out = torch.empty_like(x0)
+    status = torch.full((C,), -1, dtype=torch.int32, device=x0.device)
+    g = torch.empty((R,), dtype=torch.float64, device=x0.device)
+    gc = torch.empty((C, R), dtype=torch.float64, device=x0.device) if per_cell else None
+    dx0 = torch.empty((C, S), dtype=torch.float64, device=x0.device) if x0_grad else None
+    p = lambda t: ctypes.c_void_p(t.data_ptr() if t is not None else None)
+    _check(_lib.lib().abdf_solve_adjoint(net.handle, C, *args, a, ctypes.byref(o),
+                                         _ptr(dL_dx.contiguous(), torch.float64, (C, S), "dL_dx"),
+                                         p(x_out), p(status), p(g), p(gc), p(dx0), ctypes.c_void_p(None),
+                                         _stream()))
+    return x_out, status, g, gc, dx0
+
+
+def _autograd_function():
+    torch = _torch()
+
+    class SolveFunction(torch.autograd.Function):
+        """x(t_end) as a differentiable function of log alpha [R] and x0 [C, S];
+        the backward pass is the discrete adjoint of the recorded solve."""
+
+        @staticmethod
+        def forward(ctx, log_alpha, x0, net, T, n_H, A_V, zeta, G0, t_end, options, max_tape_steps):
+            alpha = torch.exp(log_alpha.detach()).contiguous()
+            x, status, tape = solve_record(net, T, n_H, A_V, zeta, G0, x0.detach().contiguous(), t_end,
+                                           alpha=alpha, options=options, max_tape_steps=max_tape_steps)
+            ctx.tape = tape
+            ctx.mark_non_differentiable(status)
+            return x, status
+
+        @staticmethod
+        def backward(ctx, gx, _gstatus):
+            g, _, dx0 = ctx.tape.adjoint(gx.contiguous(), x0_grad=ctx.needs_input_grad[1])
+            return g, dx0, None, None, None, None, None, None, None, None, None
+
+    return SolveFunction
+
+
+_SOLVE_FN = None
+
+
+def solve_diff(net: Network, T, n_H, A_V, zeta, G0, x0, t_end, log_alpha, *, max_tape_steps=0,
+               options: Options | None = None, **opts):
+    """Differentiable solve: (x_out, status); gradients flow to log_alpha [R] and x0."""
+    global _SOLVE_FN
+    if _SOLVE_FN is None:
+        _SOLVE_FN = _autograd_function()
+    o = options if options is not None else make_options(**opts)
+    return _SOLVE_FN.apply(log_alpha, x0, net, T, n_H, A_V, zeta, G0, t_end, o, max_tape_steps)
 
 
 def rates(net: Network, T, n_H, A_V, zeta, G0):

@@ -90,6 +90,14 @@ SIGNATURES = {
     "abdf_lu_solve": (ctypes.c_int, [ctypes.c_int32, ctypes.c_int64, c_void_p, c_void_p, c_void_p, c_void_p]),
     "abdf_selftest": (ctypes.c_int, [c_void_p]),
     "abdf_profile_enable": (None, [ctypes.c_int32]),
+    "abdf_solve_record": (ctypes.c_int, [c_void_p, ctypes.c_int64] + [c_void_p] * 8 +
+                          [ctypes.POINTER(Options), ctypes.c_int32, c_void_p, c_void_p, c_void_p,
+                           ctypes.POINTER(c_void_p), c_void_p]),
+    "abdf_tape_adjoint": (ctypes.c_int, [c_void_p] * 6),
+    "abdf_tape_bytes": (ctypes.c_int64, [c_void_p]),
+    "abdf_tape_free": (None, [c_void_p]),
+    "abdf_solve_adjoint": (ctypes.c_int, [c_void_p, ctypes.c_int64] + [c_void_p] * 8 +
+                           [ctypes.POINTER(Options)] + [c_void_p] * 8),
     "abdf_server_options_default": (None, [ctypes.POINTER(ServerOptions)]),
     "abdf_server_create": (ctypes.c_int, [c_void_p, ctypes.POINTER(ServerOptions), ctypes.POINTER(c_void_p)]),
     "abdf_server_submit": (ctypes.c_int, [c_void_p, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),

@@ -559,13 +559,17 @@ __device__ __forceinline__ void lu_solve_left(const T *__restrict__ A, const T *
 
 // Solves M^T z = b from the factors of P M = L U (M^T = U^T L^T P): forward
 // substitution with U^T, back substitution with L^T, then z[rowmap[i]] = v[i].
-// b, z and t (>= 5 * kLuW doubles) are in LDS; b is consumed.  256 threads:
-// lane i & 63 owns column i of the current 64-column block, the four waves
-// split the rows, so each wave reads 64 consecutive entries of a row.
+// The off-diagonal blocks enter as column products (lane i & 63 owns column
+// i of the current 64-column block, the four waves split the rows, so each
+// wave reads 64 consecutive entries of a row); the diagonal blocks are solved
+// by substitution (one wave, column by column, the block staged in LDS)
+// rather than by their stored inverses: the reverse sweep of the BDF map
+// amplifies solve errors strongly, and substitution keeps them at the level
+// of a backward-stable solver.  b, z, t (>= 5 * kLuW doubles) and Db
+// (kLuW * kLdb doubles) are in LDS; b is consumed.  256 threads.
 template <typename T>
-__device__ __forceinline__ void lu_solve_left_T(const T *__restrict__ A, const T *__restrict__ dinv,
-                                                const int32_t *__restrict__ rowmap, int NP, double *b, double *z,
-                                                double *t) {
+__device__ __forceinline__ void lu_solve_left_T(const T *__restrict__ A, const int32_t *__restrict__ rowmap, int NP,
+                                                double *b, double *z, double *t, double *Db) {
     const int tid = threadIdx.x;
     const int col = tid & 63, grp = tid >> 6;
     const int NB = (NP + kLuW - 1) / kLuW;
@@ -588,27 +592,49 @@ __device__ __forceinline__ void lu_solve_left_T(const T *__restrict__ A, const T
         if (tid < W) t[tid] = b[r0 + tid] - ((t[kLuW + tid] + t[2 * kLuW + tid]) + (t[3 * kLuW + tid] + t[4 * kLuW + tid]));
         __syncthreads();
     };
-    // out[r0 + col] = sum_c Dm[c][col] t[c] (transpose of a stored 64 x 64 inverse)
-    auto diagT = [&](int r0, int W, const T *Dm, double *out) {
-        double acc = 0.0;
-        if (col < W)
-            for (int c = grp; c < W; c += 4) acc += double(Dm[c * kLuW + col]) * t[c];
-        t[kLuW + grp * kLuW + col] = acc;
-        __syncthreads();
-        if (tid < W) out[r0 + tid] = (t[kLuW + tid] + t[2 * kLuW + tid]) + (t[3 * kLuW + tid] + t[4 * kLuW + tid]);
+    // the W x W diagonal block of logical rows r0.. into Db (row-major, ld kLdb)
+    auto stage = [&](int r0, int W) {
+        for (int e = tid; e < W * kLuW; e += blockDim.x) {
+            const int rr = e >> 6, cc = e & 63;
+            if (cc < W) Db[rr * kLdb + cc] = double(A[size_t(rowmap[r0 + rr]) * NP + r0 + cc]);
+        }
         __syncthreads();
     };
-    // U^T w = b  (w kept in b)
+    auto bcast = [](double v, int k) {
+        const int lo = __builtin_amdgcn_readlane(__double2loint(v), k);
+        const int hi = __builtin_amdgcn_readlane(__double2hiint(v), k);
+        return __hiloint2double(hi, lo);
+    };
+    // U^T w = b: w_k = t_k / U_kk, then t_i -= U_ki w_k for i > k  (w kept in b)
     for (int ib = 0; ib < NB; ++ib) {
         const int r0 = ib * kLuW, W = min(kLuW, NP - r0);
         colgemv(r0, W, 0, r0, b);
-        diagT(r0, W, dinv + size_t(ib) * 2 * kLuW * kLuW + kLuW * kLuW, b);
+        stage(r0, W);
+        if (tid < 64) {
+            double tv = col < W ? t[col] : 0.0;
+            for (int k = 0; k < W; ++k) {
+                const double wk = bcast(tv, k) / Db[k * kLdb + k];
+                if (col == k) tv = wk;
+                else if (col > k && col < W) tv -= Db[k * kLdb + col] * wk;
+            }
+            if (col < W) b[r0 + col] = tv;
+        }
+        __syncthreads();
     }
-    // L^T v = w  (v kept in b)
+    // L^T v = w (unit diagonal): v_k = t_k, then t_i -= L_ki v_k for i < k  (v kept in b)
     for (int ib = NB - 1; ib >= 0; --ib) {
         const int r0 = ib * kLuW, W = min(kLuW, NP - r0);
         colgemv(r0, W, r0 + W, NP, b);
-        diagT(r0, W, dinv + size_t(ib) * 2 * kLuW * kLuW, b);
+        stage(r0, W);
+        if (tid < 64) {
+            double tv = col < W ? t[col] : 0.0;
+            for (int k = W - 1; k > 0; --k) {
+                const double vk = bcast(tv, k);
+                if (col < k) tv -= Db[k * kLdb + col] * vk;
+            }
+            if (col < W) b[r0 + col] = tv;
+        }
+        __syncthreads();
     }
     for (int i = tid; i < NP; i += blockDim.x) z[rowmap[i]] = b[i];
     __syncthreads();

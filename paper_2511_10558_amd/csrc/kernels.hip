@@ -573,8 +573,9 @@ __global__ void __launch_bounds__(kBlock) k_harvest(Slots s, HarvestArgs h) {
 //   difference update   lambda_{j+1} += lambda_j (j = 0..q), lambda_d =
 //                       lambda_{q+1} + lambda_{q+2}, lambda_{q+1} = -lambda_{q+2},
 //                       lambda_{q+2} = 0
-//   corrector           mu = M^{-T} lambda_d with M = I - c J(x_{n+1}) factored afresh
-//   predictor           lambda_j += mu - lambda_d (j <= q), lambda_j -= gamma_j / gamma_q mu (1 <= j <= q)
+//   corrector           mu = M^{-T} lambda_d with M = I - c J(x_{n+1}) factored afresh,
+//                       solved as lambda_xp = mu - lambda_d = M^{-T} c J^T lambda_d
+//   predictor           lambda_j += lambda_xp (j <= q), lambda_j -= gamma_j / gamma_q mu (1 <= j <= q)
 //   parameters          dL/dlog alpha_r += c rate_r(x_{n+1}) (nu_r . mu)
 //   step-size change    lambda_{0..q} <- (R(rho) U) lambda when (h, q) changed from step n-1
 // and finally, for D_0 = x_0 and D_1 = h_0 f(x_0):
@@ -616,16 +617,45 @@ __device__ __forceinline__ void rescale_adjoint(double *L, int S, int q, double 
     __syncthreads();
 }
 
+// c J(x)^T v (into out, global) for one slot: w_r = nu_r . v, then
+// (J^T v)_j = sum over reactions r with reactant j of d rate_r / d x_j w_r.
+// xs, v in LDS; w: LDS scratch [R].
+__device__ __forceinline__ void jac_transpose_apply(const DeviceNet &n, const double *k, const double *xs,
+                                                    const double *v, double *w, double c, double *out, int S) {
+    for (int r = threadIdx.x; r < n.R; r += kBlock) w[r] = nu_dot(n, v, r);
+    __syncthreads();
+    for (int j = threadIdx.x; j < S; j += kBlock) {
+        double jt = 0.0;
+        for (int e = n.dcol_ptr[j]; e < n.dcol_ptr[j + 1]; ++e) {
+            const int ent = n.dcol_ent[e];
+            const int r = ent >> 16, o = (ent & 0xffff) - 1;
+            double d = n.dcol_coef[e] * k[r];
+            if (o >= 0) d *= xs[o];
+            jt += d * w[r];
+        }
+        out[j] = c * jt;
+    }
+    __syncthreads();
+}
+
 // Queues reverse step cs.n_steps - 1 of a slot: the reverse of its difference
-// update, the corrector point and c for a fresh factorisation.
-__device__ __forceinline__ void adj_begin(const Slots &s, int slot, SlotCtl &cs, int ring) {
+// update (lambda_d kept in psi), the corrector point, c, and the right-hand
+// side c J(x_{n+1})^T lambda_d of the transposed solve.  The solve then
+// yields lambda_xp = mu - lambda_d = M^{-T} c J^T lambda_d directly: the
+// adjoint rows can be many orders of magnitude larger than lambda_xp, and
+// forming mu first and subtracting lambda_d would lose it to cancellation.
+// LDS: xs [S], ls [S], w [R].
+__device__ __forceinline__ void adj_begin(const Slots &s, const DeviceNet &n, int slot, SlotCtl &cs, int ring,
+                                          double *smem) {
     const int S = s.S;
     const size_t te = size_t(cs.cell) * s.tape_cap + (cs.n_steps - 1);
     const int q = s.tape_q[te];
     const double h = s.tape_h[te];
+    const double c = h / bdf_gamma(q);
     double *L = s.D + size_t(slot) * kDRows * S;
-    double *rb = s.rb + size_t(slot) * S, *xJ = s.xJ + size_t(slot) * S;
+    double *rb = s.rb + size_t(slot) * S, *xJ = s.xJ + size_t(slot) * S, *lam_d = s.psi + size_t(slot) * S;
     const double *xt = s.tape_x + te * S;
+    double *xs = smem, *ls = xs + S, *w = ls + S;
     for (int i = threadIdx.x; i < S; i += kBlock) {
         double v[kDRows];
         for (int j = 0; j <= q + 2; ++j) v[j] = L[j * S + i];
@@ -634,14 +664,18 @@ __device__ __forceinline__ void adj_begin(const Slots &s, int slot, SlotCtl &cs,
         v[q + 1] = -v[q + 2];
         v[q + 2] = 0.0;
         for (int j = 0; j <= q + 2; ++j) L[j * S + i] = v[j];
-        rb[i] = ld;
-        xJ[i] = xt[i];
+        ls[i] = ld;
+        lam_d[i] = ld;
+        const double xv = xt[i];
+        xs[i] = xv;
+        xJ[i] = xv;
     }
     __syncthreads();
+    jac_transpose_apply(n, s.k + size_t(slot) * n.R, xs, ls, w, c, rb, S);
     if (threadIdx.x == 0) {
         cs.h = h;
         cs.q = q;
-        cs.c = h / bdf_gamma(q);
+        cs.c = c;
         const int p = atomicAdd(&s.cnt[ring], 1);
         s.act[ring * s.nslots + p] = slot;
         const int pl = atomicAdd(&s.cnt[3 + ring], 1);
@@ -668,23 +702,11 @@ __device__ __forceinline__ void adj_finish(const Slots &s, const DeviceNet &n, i
             l1[i] = L[S + i];
         }
         __syncthreads();
-        for (int r = threadIdx.x; r < R; r += kBlock) {
-            const double wr = nu_dot(n, l1, r);
-            w[r] = wr;
-            g[r] += h0 * mass_action(n, k, xs, r) * wr;
-        }
+        for (int r = threadIdx.x; r < R; r += kBlock) g[r] += h0 * mass_action(n, k, xs, r) * nu_dot(n, l1, r);
         __syncthreads();
-        for (int j = threadIdx.x; j < S; j += kBlock) {
-            double jt = 0.0;
-            for (int e = n.dcol_ptr[j]; e < n.dcol_ptr[j + 1]; ++e) {
-                const int ent = n.dcol_ent[e];
-                const int r = ent >> 16, o = (ent & 0xffff) - 1;
-                double d = n.dcol_coef[e] * k[r];
-                if (o >= 0) d *= xs[o];
-                jt += d * w[r];
-            }
-            dx0[j] = L[j] + h0 * jt;
-        }
+        // dL/dx0 = lambda_0 + h0 J(x0)^T lambda_1 (dx0 first holds the second term)
+        jac_transpose_apply(n, k, xs, l1, w, h0, dx0, S);
+        for (int i = threadIdx.x; i < S; i += kBlock) dx0[i] = L[i] + dx0[i];
     } else {
         for (int i = threadIdx.x; i < S; i += kBlock) dx0[i] = L[i];
     }
@@ -728,10 +750,10 @@ __global__ void __launch_bounds__(kBlock) k_adj_admit(Slots s, DeviceNet n, AdjA
     if (cs.n_steps == 0)
         adj_finish(s, n, slot, cs, 0, smem);
     else
-        adj_begin(s, slot, cs, ring);
+        adj_begin(s, n, slot, cs, ring, smem);
 }
 
-// mu = M^{-T} lambda_d for every queued slot (persistent).
+// lambda_xp = M^{-T} (c J^T lambda_d) for every queued slot (persistent).
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_adj_solve(Slots s, int ring) {
     extern __shared__ double smem[];
@@ -739,13 +761,12 @@ __global__ void __launch_bounds__(kBlock) k_adj_solve(Slots s, int ring) {
     const int S = s.S, NP = s.NP;
     for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
         const int slot = s.act[ring * s.nslots + idx];
-        double *b = smem, *z = b + NP, *t = z + NP;
+        double *b = smem, *z = b + NP, *t = z + NP, *Db = t + 5 * kLuW;
         const double *rb = s.rb + size_t(slot) * S;
         for (int i = threadIdx.x; i < NP; i += kBlock) b[i] = i < S ? rb[i] : 0.0;
         __syncthreads();
-        lu_solve_left_T<T>(reinterpret_cast<const T *>(s.lu) + size_t(slot) * NP * NP,
-                           reinterpret_cast<const T *>(s.dinv) + size_t(slot) * lu2_dinv_elems<T>(NP),
-                           s.perm + size_t(slot) * NP, NP, b, z, t);
+        lu_solve_left_T<T>(reinterpret_cast<const T *>(s.lu) + size_t(slot) * NP * NP, s.perm + size_t(slot) * NP,
+                           NP, b, z, t, Db);
         double *d = s.d + size_t(slot) * S;
         for (int i = threadIdx.x; i < S; i += kBlock) d[i] = z[i];
         __syncthreads();
@@ -773,15 +794,15 @@ __global__ void __launch_bounds__(kBlock) k_adj_step(Slots s, DeviceNet n, int r
     const int q = cs.q;
     const double c = cs.c, gq = bdf_gamma(q);
     double *L = s.D + size_t(slot) * kDRows * S;
-    const double *rb = s.rb + size_t(slot) * S, *mu = s.d + size_t(slot) * S, *xJ = s.xJ + size_t(slot) * S;
+    const double *lam_d = s.psi + size_t(slot) * S, *lxp_g = s.d + size_t(slot) * S, *xJ = s.xJ + size_t(slot) * S;
     double *xs = smem, *ms = xs + S;
     double gr[kMaxOrder + 1];
     for (int j = 1; j <= q; ++j) gr[j] = bdf_gamma(j) / gq;
     for (int i = threadIdx.x; i < S; i += kBlock) {
-        const double m = mu[i];
+        const double lxp = lxp_g[i];
+        const double m = lam_d[i] + lxp;
         xs[i] = xJ[i];
         ms[i] = m;
-        const double lxp = m - rb[i];
         L[i] = L[i] + lxp;
         for (int j = 1; j <= q; ++j) L[j * S + i] = L[j * S + i] + (lxp - gr[j] * m);
     }
@@ -800,7 +821,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_step(Slots s, DeviceNet n, int r
     if (threadIdx.x == 0) cs.n_steps = m;
     __syncthreads();
     if (m > 0)
-        adj_begin(s, slot, cs, next);
+        adj_begin(s, n, slot, cs, next, smem);
     else
         adj_finish(s, n, slot, cs, 1, smem);
 }

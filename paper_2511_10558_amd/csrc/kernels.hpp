@@ -74,7 +74,7 @@ hipError_t launch_adj_step(const Slots &s, const DeviceNet &n, int ring, int gri
 hipError_t launch_adj_harvest(const Slots &s, const AdjHarvestArgs &h, hipStream_t st);
 hipError_t launch_grad_sum(const double *g_cell, long long cells, int R, double *out, hipStream_t st);
 inline size_t adj_lds(const DeviceNet &n) { return sizeof(double) * (2 * size_t(n.S) + n.R); }
-inline size_t adj_solve_lds(const DeviceNet &n) { return sizeof(double) * (2 * size_t(n.NP) + 5 * 64); }
+inline size_t adj_solve_lds(const DeviceNet &n) { return sizeof(double) * (2 * size_t(n.NP) + 5 * 64 + 64 * 65); }
 
 hipError_t launch_rates(const DeviceNet &n, const PhysArgs &p, long long cells, double *k, hipStream_t st);
 hipError_t launch_rhs(const DeviceNet &n, long long cells, const double *k, const double *x, double *f, hipStream_t st);

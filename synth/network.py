@@ -25,6 +25,7 @@ from __future__ import annotations
 
 import dataclasses
 import io
+import collections
 import itertools
 
 import numpy as np
@@ -196,18 +197,37 @@ class _Builder:
         self.rows.append((rtype, key[0], key[1], float(alpha), float(beta), float(gamma)))
         return True
 
+    def two_body(self, a, b):
+        """One two-body reaction of the pair (a, b) with products drawn uniformly among
+        the conserving multisets; False if none exists or it duplicates a reaction."""
+        cands = self.conserving_products((a, b))
+        if not cands:
+            return False
+        prod = cands[self.rng.integers(len(cands))]
+        alpha = _loguniform(self.rng, 1e-12, 1e-9)
+        beta = self.rng.uniform(-1.0, 1.0)
+        gamma = self.rng.uniform(0.0, 200.0)
+        return self.add(TWO_BODY, (a, b), prod, alpha, beta, gamma)
+
+    def single(self, rtype, a, need_electron, e_idx):
+        cands = self.conserving_products((a,))
+        if need_electron:
+            cands = [p for p in cands if e_idx in p]
+        if not cands:
+            return False
+        prod = cands[self.rng.integers(len(cands))]
+        if rtype == COSMIC_RAY:
+            alpha, beta, gamma = _loguniform(self.rng, 0.1, 10.0), 0.0, 0.0
+        else:
+            alpha = _loguniform(self.rng, 1e-11, 1e-9)
+            beta, gamma = 0.0, self.rng.uniform(0.5, 3.5)
+        return self.add(rtype, (a,), prod, alpha, beta, gamma)
+
     def draw_two_body(self, pairs, count):
         made = 0
         while made < count:
             a, b = pairs[self.rng.integers(len(pairs))]
-            cands = self.conserving_products((a, b))
-            if not cands:
-                continue
-            prod = cands[self.rng.integers(len(cands))]
-            alpha = _loguniform(self.rng, 1e-12, 1e-9)
-            beta = self.rng.uniform(-1.0, 1.0)
-            gamma = self.rng.uniform(0.0, 200.0)
-            if self.add(TWO_BODY, (a, b), prod, alpha, beta, gamma):
+            if self.two_body(a, b):
                 made += 1
 
     def draw_single(self, rtype, reactant_pool, count, need_electron, e_idx):
@@ -231,6 +251,49 @@ class _Builder:
                 beta, gamma = 0.0, self.rng.uniform(0.5, 3.5)
             if self.add(rtype, (a,), prod, alpha, beta, gamma):
                 made += 1
+
+    def grow(self, reach, kinds, allowed_pair, single_ok, e_idx):
+        """Draws reactions of the given kinds, in order, with every reactant taken
+        from the species already reachable from the initial state (`reach`,
+        updated in place with each reaction's products), so that the network is
+        connected to the initial abundances as a real chemical network is.
+        Two-body pairs are uniform over the allowed unordered pairs of reachable
+        species; single-reactant reactions take a uniform reachable species.
+        kinds: sequence of TWO_BODY / COSMIC_RAY / PHOTO."""
+        n = len(self.species)
+        queue = collections.deque(kinds)
+        stalled = 0
+        while queue:
+            kind = queue.popleft()
+            for _ in range(3000 if not reach.all() else 300000):
+                pool = np.flatnonzero(reach)
+                if kind == TWO_BODY:
+                    a, b = sorted(int(v) for v in pool[self.rng.integers(len(pool), size=2)])
+                    # uniform over unordered pairs: a distinct pair arises from two orders
+                    if a != b and self.rng.random() < 0.5:
+                        continue
+                    if not allowed_pair(a, b) or not self.two_body(a, b):
+                        continue
+                else:
+                    a = int(pool[self.rng.integers(len(pool))])
+                    if not single_ok(kind, a) or not self.single(kind, a, kind == COSMIC_RAY, e_idx):
+                        continue
+                for p in self.rows[-1][2]:
+                    reach[p] = True
+                stalled = 0
+                break
+            else:
+                # nothing new of this kind among the reachable species yet: later
+                queue.append(kind)
+                stalled += 1
+                if stalled > len(queue):
+                    if reach.all():
+                        raise RuntimeError("could not draw the remaining reactions")
+                    # the reachable part is exhausted: the rest of the reactions
+                    # are drawn among all species
+                    reach[:] = True
+                    stalled = 0
+        return int(reach[:n].sum())
 
     def build(self) -> Network:
         R = len(self.rows)
@@ -279,12 +342,6 @@ def small_network(seed: int = 1, n_two_body: int = 30, n_cr: int = 10) -> Networ
     bld = _Builder(f"small-{seed}", names, comp, charge, rng)
     e = 0
     non_e = [i for i in range(len(names)) if i != e]
-    pairs = [
-        (a, b)
-        for a, b in itertools.combinations_with_replacement(non_e, 2)
-        if not (bld.charge[a] != 0 and bld.charge[b] != 0)
-    ]
-    bld.draw_two_body(pairs, n_two_body)
     singles = []
     for a in non_e:
         for p in bld.conserving_products((a,)):
@@ -297,6 +354,19 @@ def small_network(seed: int = 1, n_two_body: int = 30, n_cr: int = 10) -> Networ
         chosen += [others[i] for i in sorted(pick)]
     for a, p in chosen[:n_cr]:
         bld.add(COSMIC_RAY, (a,), p, _loguniform(rng, 0.1, 10.0), 0.0, 0.0)
+    # two-body reactions grown from the atomic start: the initial atoms and
+    # whatever the cosmic-ray set makes from reachable species
+    reach = np.zeros(len(names), bool)
+    reach[[names.index(a) for a in ("H", "C", "O")]] = True
+    changed = True
+    while changed:
+        changed = False
+        for t_, rs, ps, *_ in bld.rows:
+            if all(reach[r] for r in rs) and not all(reach[p] for p in ps):
+                reach[list(ps)] = True
+                changed = True
+    ion_neutral = lambda a, b: a != e and b != e and not (bld.charge[a] != 0 and bld.charge[b] != 0)
+    bld.grow(reach, [TWO_BODY] * n_two_body, ion_neutral, None, e)
     return bld.build()
 
 
@@ -344,18 +414,28 @@ def large_network(n_species: int, n_reactions: int, seed: int,
     charge = [q for _, q in chosen]
     bld = _Builder(f"large-{n_species}-{n_reactions}-{seed}", names, comp, charge, rng)
     e = 0
-    neutrals = [i for i in range(1, n_species) if bld.charge[i] == 0]
-    cations = [i for i in range(1, n_species) if bld.charge[i] > 0]
-    pairs = [(a, b) for a, b in itertools.combinations_with_replacement(neutrals, 2)]
-    pairs += [(min(a, b), max(a, b)) for a in neutrals for b in cations]
-    pairs += [(e, b) for b in cations]
     n_cr = int(round(mix[1] * n_reactions))
     n_ph = int(round(mix[2] * n_reactions))
     n_2b = n_reactions - n_cr - n_ph
-    bld.draw_two_body(pairs, n_2b)
-    non_e = list(range(1, n_species))
-    bld.draw_single(COSMIC_RAY, non_e, n_cr, need_electron=True, e_idx=e)
-    bld.draw_single(PHOTO, non_e, n_ph, need_electron=False, e_idx=e)
+    # neutral-neutral, neutral-cation and electron-cation pairs; no ion-ion pair
+    q = bld.charge
+
+    def allowed(a, b):
+        if a == e:
+            return b != e and q[b] > 0
+        return (q[a] == 0 and q[b] >= 0) or (q[a] > 0 and q[b] == 0)
+
+    def single_ok(kind, a):
+        return a != e
+    # reactions grown from the atomic start, types in a seeded order with exact counts
+    kinds = np.array([TWO_BODY] * n_2b + [COSMIC_RAY] * n_cr + [PHOTO] * n_ph)
+    kinds = kinds[rng.permutation(len(kinds))]
+    # the first reactions ionise: the atoms alone allow neutral-neutral and
+    # cosmic-ray chemistry, the rest follows from what they make
+    reach = np.zeros(n_species, bool)
+    for atom in ("H", "He", "C", "N", "O", "S"):
+        reach[names.index(atom)] = True
+    bld.grow(reach, list(kinds), allowed, single_ok, e)
     return bld.build()
 
 

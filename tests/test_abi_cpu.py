@@ -83,13 +83,22 @@ def test_nonconserving_reaction_is_rejected_with_its_index():
     assert "reaction 3" in str(e.value)
 
 
+def _first_reaction(text, new_line):
+    """Replaces the line of reaction 0."""
+    lines = text.splitlines()
+    i = next(k for k, l in enumerate(lines) if l.startswith("reactions ")) + 1
+    assert lines[i].startswith("0 ")
+    lines[i] = new_line
+    return "\n".join(lines) + "\n"
+
+
 @pytest.mark.parametrize("edit", [
     lambda t: t.replace("astrobdf-network 1", "astrobdf-network 2"),
     lambda t: t.replace("\nend\n", "\n"),
     lambda t: t.replace("species 12", "species 13"),
-    lambda t: _mutate(t, "0 0 2 ", "0 7 2 3 6 3 4 7 11 1e-10 0 0"),
-    lambda t: _mutate(t, "0 0 2 ", "0 0 2 3 99 2 4 7 -1 1e-10 0 0"),
-    lambda t: _mutate(t, "0 0 2 ", "0 0 2 3 6 2 4 7 -1 nan 0 0"),
+    lambda t: _first_reaction(t, "0 7 2 3 6 3 4 7 11 1e-10 0 0"),
+    lambda t: _first_reaction(t, "0 0 2 3 99 2 4 7 -1 1e-10 0 0"),
+    lambda t: _first_reaction(t, "0 0 2 3 6 2 4 7 -1 nan 0 0"),
 ])
 def test_malformed_network_text_is_a_parse_error(edit):
     text = synth.network_for_config("small").to_text()
@@ -134,3 +143,24 @@ def test_server_options_defaults():
     ab._lib.lib().abdf_server_options_default(ctypes.byref(so))
     assert so.solve.rtol == 1e-6 and so.solve.check_every == 4
     assert so.max_slots == 0 and so.max_queued_cells == 0
+
+
+def test_adjoint_entry_points_reject_null_arguments():
+    L = ab._lib.lib()
+    import ctypes
+    net = synth.network_for_config("small")
+    g = ab.Network.from_text(net.to_text())
+    o = ab.default_options()
+    nul = ctypes.c_void_p(None)
+    # no tape pointer
+    rc = L.abdf_solve_record(g.handle, 1, *([nul] * 8), ctypes.byref(o), 0, nul, nul, nul, None, nul)
+    assert rc == 1
+    assert L.abdf_tape_adjoint(nul, nul, nul, nul, nul, nul) == 1
+    assert L.abdf_tape_bytes(nul) == 0
+    L.abdf_tape_free(nul)
+    # host pointers are not device pointers
+    tape = ctypes.c_void_p()
+    x = (ctypes.c_double * 64)()
+    rc = L.abdf_solve_record(g.handle, 1, *([ctypes.cast(x, ctypes.c_void_p)] * 8), ctypes.byref(o), 0,
+                             nul, nul, nul, ctypes.byref(tape), nul)
+    assert rc == 1 and not tape.value

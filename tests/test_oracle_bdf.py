@@ -156,3 +156,18 @@ def test_status_codes():
     assert bdf.solve(ch, bad, cells.t_end[0]).status == bdf.BAD_INPUT
     r = bdf.solve(ch, x0, 0.0)
     assert r.status == bdf.OK and np.array_equal(r.x, x0)
+
+
+def test_recorded_history_holds_the_accepted_states():
+    # each record is (h, q, t, x) after the accepted step: the last equals the result,
+    # and the times advance by the recorded steps to t_end
+    net = tiny_nets.decay(2.0)
+    ch = chem.cell_chemistry(net, CELL)
+    t_end = 4.0 / ch.k[0]
+    res = bdf.solve(ch, np.array([1.0, 0.0]), t_end, 1e-6, 1e-20, record=True)
+    assert np.allclose(res.history[-1][3], res.x, rtol=1e-14, atol=0)
+    assert res.history[-1][2] == t_end
+    t = 0.0
+    for h, q, t_rec, _x in res.history[:-1]:
+        t += h
+        assert t_rec == pytest.approx(t, rel=1e-12)
