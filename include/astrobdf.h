@@ -63,7 +63,11 @@ enum {
 };
 
 /* Precision of the Newton-matrix factorisation.  Residuals, error norms,
- * step control and Newton updates are FP64 in both forms. */
+ * step control and Newton updates are FP64 in both forms.  In the FP32-LU
+ * form a cell whose corrector fails with a fresh Jacobian retries the step
+ * with each FP32 solve refined once against an FP64 residual of the linear
+ * system, and after a second such failure continues with FP64 factors
+ * (counted in n_lu_fp64). */
 enum {
     ABDF_PREC_FP64 = 0,
     ABDF_PREC_FP32_LU = 1
@@ -94,6 +98,8 @@ typedef struct abdf_cell_stats {
     int32_t order;          /* BDF order at the end */
     double h;               /* step size at the end [s] */
     double t;               /* time reached [s] */
+    int32_t n_lu_fp64;      /* factorisations in FP64 (FP32-LU form: those after a fallback) */
+    int32_t reserved;
 } abdf_cell_stats;
 
 /* Fills `opt` with the defaults listed in abdf_options. */

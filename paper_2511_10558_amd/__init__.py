@@ -129,7 +129,8 @@ def make_options(rtol=1e-6, atol=1e-20, max_steps=100000, precision="fp64", chec
 
 _STATS_DTYPE = np.dtype([("n_steps", "<i4"), ("n_attempts", "<i4"), ("n_err_reject", "<i4"),
                          ("n_newton_fail", "<i4"), ("n_rhs", "<i4"), ("n_jac", "<i4"), ("n_lu", "<i4"),
-                         ("order", "<i4"), ("h", "<f8"), ("t", "<f8")])
+                         ("order", "<i4"), ("h", "<f8"), ("t", "<f8"), ("n_lu_fp64", "<i4"),
+                         ("reserved", "<i4")])
 
 
 def stats_to_numpy(buf) -> np.ndarray:

@@ -36,6 +36,8 @@ class CellStats(ctypes.Structure):
         ("order", ctypes.c_int32),
         ("h", ctypes.c_double),
         ("t", ctypes.c_double),
+        ("n_lu_fp64", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 

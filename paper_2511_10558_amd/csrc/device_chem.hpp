@@ -24,6 +24,28 @@ __device__ inline void cell_rates(const DeviceNet &n, const double *phi, double 
     }
 }
 
+// out_i = sum_r nu_ir v_r for per-reaction values v (LDS): each species' row of
+// the stoichiometry in segments of up to 32 entries (part[n_seg], LDS), then
+// the segments of a species in order.  Deterministic.
+__device__ __forceinline__ void species_gather(const DeviceNet &n, const double *v, double *part, double *out) {
+    for (int s = threadIdx.x; s < n.n_seg; s += kBlock) {
+        const int e0 = n.seg_beg[s], e1 = n.seg_beg[s + 1];
+        double acc = 0.0;
+        for (int e = e0; e < e1; ++e) {
+            const int w = n.f_ent[e];
+            acc += double((w & 7) - 4) * v[w >> 3];
+        }
+        part[s] = acc;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < n.S; i += kBlock) {
+        double acc = 0.0;
+        for (int s = n.seg_ptr[i]; s < n.seg_ptr[i + 1]; ++s) acc += part[s];
+        out[i] = acc;
+    }
+    __syncthreads();
+}
+
 // f = nu . rate(x) for one cell.  x in LDS; k in global memory (one coalesced
 // pass); rate[R] and part[n_seg] are LDS scratch; f may be LDS or global.
 // Deterministic: every sum runs in a fixed order.
@@ -37,23 +59,61 @@ __device__ __forceinline__ void cell_rhs(const DeviceNet &n, const double *__res
         rate[r] = v;
     }
     __syncthreads();
-    for (int s = threadIdx.x; s < n.n_seg; s += kBlock) {
-        const int e0 = n.seg_beg[s], e1 = n.seg_beg[s + 1];
-        double acc = 0.0;
-        for (int e = e0; e < e1; ++e) {
-            const int w = n.f_ent[e];
-            acc += double((w & 7) - 4) * rate[w >> 3];
-        }
-        part[s] = acc;
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < n.S; i += kBlock) {
-        double acc = 0.0;
-        for (int s = n.seg_ptr[i]; s < n.seg_ptr[i + 1]; ++s) acc += part[s];
-        f[i] = acc;
-    }
-    __syncthreads();
+    species_gather(n, rate, part, f);
 }
+
+// J(x) y = nu . (d rate / dx) y for one cell: per reaction
+// k_r (y_a x_b + x_a y_b) (k_r y_a for one reactant; the same expression gives
+// 2 k_r x_a y_a for A + A), then the species sums of cell_rhs.  x, y in LDS;
+// drate[R], part[n_seg] LDS scratch.
+__device__ __forceinline__ void cell_jvp(const DeviceNet &n, const double *__restrict__ k, const double *x,
+                                         const double *y, double *drate, double *part, double *out) {
+    for (int r = threadIdx.x; r < n.R; r += kBlock) {
+        const int ab = n.rx_ab[r];
+        const int a = ab & 0xffff, b = (ab >> 16) & 0xffff;
+        drate[r] = b == 0xffff ? k[r] * y[a] : k[r] * (y[a] * x[b] + x[a] * y[b]);
+    }
+    __syncthreads();
+    species_gather(n, drate, part, out);
+}
+
+// The Jacobian nonzeros J_e(x) of one cell into jv[nnzJ] (global, written
+// coalesced): the terms of each nonzero summed in the order of
+// assemble_newton_matrix.  x in LDS, k in global memory.  Cooperative.
+template <int NT>
+__device__ __forceinline__ void jacobian_values(const DeviceNet &n, const double *__restrict__ k, const double *x,
+                                                double *jv) {
+    for (int e = threadIdx.x; e < n.nnzJ; e += NT) {
+        double v = 0.0;
+        for (int t = n.jterm_ptr[e]; t < n.jterm_ptr[e + 1]; ++t) {
+            const int w = n.jt_rx_other[t];
+            const int other = (w & 0xffff) - 1;
+            double term = n.jt_coef[t] * k[w >> 16];
+            if (other >= 0) term *= x[other];
+            v += term;
+        }
+        jv[e] = v;
+    }
+}
+
+// Entries of M = I - c J of one cell where the factorisation gathers them:
+// the dense map gives the nonzero of (i, j) (same value as
+// assemble_newton_matrix stores); rows and columns beyond S are the identity's.
+template <typename T>
+struct NewtonMatrixSource {
+    const int32_t *jidx;
+    const double *jv;
+    int S, NP;
+    double c;
+    __device__ __forceinline__ T operator()(int i, int j) const {
+        double v = i == j ? 1.0 : 0.0;
+        if (i < S && j < S) {
+            const int e = jidx[size_t(i) * NP + j];
+            if (e >= 0) v = v + (-c * jv[e]);
+        }
+        return T(v);
+    }
+};
 
 // One row i of M = I - c J(x) into rowbuf[NP] (LDS, owned by the calling wave),
 // then to the matrix row in global memory as T.  Rows i >= S are identity.

@@ -24,11 +24,20 @@ constexpr int32_t kIter = 0;
 constexpr int32_t kConverged = 1;
 constexpr int32_t kFailed = 2;
 
+// Factor modes of a cell in an FP32-LU engine: FP32 factors with one solve
+// per Newton iteration, FP32 factors with one FP64 refinement of each solve,
+// FP64 factors.  A cell whose corrector fails with a fresh Jacobian moves to
+// the next mode.  FP64 engines use FP64 factors throughout.
+constexpr int32_t kLuPlain32 = 0;
+constexpr int32_t kLuRefined32 = 1;
+constexpr int32_t kLu64 = 2;
+
 struct SlotCtl {
     double t, h, t_end, c, c_lu, eta_old, rtol, atol, newton_tol, err;
     int32_t q, n_equal, status, phase, j_fresh, jac_refresh, landing, newton_iter;
-    int32_t lu_valid, cell, m_last, pad;
+    int32_t lu_valid, cell, m_last, lu_mode;   // FP32-LU engines: kLuPlain32, kLuRefined32 or kLu64
     int32_t n_steps, n_attempts, n_err_reject, n_newton_fail, n_rhs, n_jac, n_lu, n_newton_iter;
+    int32_t n_lu64, pad;                   // FP32-LU engines: factorisations done in FP64 after a fallback
 };
 
 // Device workspace for n slots of one network (all arrays slot-major).
@@ -44,8 +53,10 @@ struct Slots {
     double *scl;      // [n][S] Newton weights atol + rtol |x_p|
     double *xJ;       // [n][S] point of the current Jacobian
     double *rb;       // [n][S] Newton residual c f(x) - psi - d
-    void *lu;         // [n][NP][NP] factors (double or float), rows in storage order
-    void *dinv;       // [n][NB][2][64][64] inverses of the diagonal blocks' triangles
+    double *jval;     // [n][nnzJ] Jacobian nonzeros at x_J (the factor kernel's input)
+    void *lu;         // [n] factors (double or float, NP x NP), rows in storage order, lu_stride bytes apart
+    void *dinv;       // [n] inverses of the diagonal blocks' triangles [NB][2][64][64], dinv_stride bytes apart
+    size_t lu_stride, dinv_stride;
     int32_t *perm;    // [n][NP]
     int32_t *act;     // [3][n] active-slot lists (ring)
     int32_t *lul;     // [3][n] slots needing a factorisation (ring)
@@ -60,6 +71,16 @@ struct Slots {
     const double *tape_x0;   // [cells][S] initial abundances
     double *g;        // [n][R] reverse sweep: per-slot gradient with respect to log alpha
 };
+
+// The factor storage of a slot in element type T.
+template <typename T>
+__device__ __forceinline__ T *slot_lu(const Slots &s, int slot) {
+    return reinterpret_cast<T *>(static_cast<char *>(s.lu) + size_t(slot) * s.lu_stride);
+}
+template <typename T>
+__device__ __forceinline__ T *slot_dinv(const Slots &s, int slot) {
+    return reinterpret_cast<T *>(static_cast<char *>(s.dinv) + size_t(slot) * s.dinv_stride);
+}
 
 // One step of a wave-wide arg-max (value descending, key ascending on ties)
 // through a DPP lane permutation; lanes outside the pattern keep their pair.

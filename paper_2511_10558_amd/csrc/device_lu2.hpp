@@ -1,5 +1,7 @@
 // Left-looking blocked LU with partial pivoting, one 512-thread workgroup per
-// matrix, and the matching triangular solves.
+// matrix, and the matching triangular solves.  The matrix is read through a
+// source functor when each block column is first gathered, so it can be
+// formed on the fly (the Newton matrix) instead of being stored first.
 //
 // Storage.  The matrix keeps its rows where they are: row r of P A (the
 // "logical" row r) is storage row perm[r].  Pivoting only swaps entries of
@@ -166,9 +168,20 @@ __device__ __forceinline__ void diag_inverses(const T *Cb, int W, T *D, T *Xb, T
     for (int e = h; e < 64 * 64; e += HALF) D[(upper ? kLuW * kLuW : 0) + e] = Z[(e >> 6) * kLdb + (e & 63)];
 }
 
+// Entries of the matrix to factor as stored in A (storage row, column).
 template <typename T>
+struct DenseSource {
+    const T *A;
+    int NP;
+    __device__ __forceinline__ T operator()(int row, int col) const { return A[size_t(row) * NP + col]; }
+};
+
+// Factors the matrix whose entries src(row, col) yields (read once, when its
+// block column is gathered) into A: A needs no initial contents.
+template <typename T, typename Src>
 __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_t *__restrict__ perm_out,
-                                               T *__restrict__ dinv, int32_t *info, unsigned char *smem) {
+                                               T *__restrict__ dinv, int32_t *info, unsigned char *smem,
+                                               const Src &src) {
     using M = Mfma<T>;
     using acc_t = typename M::acc_t;
     using v4 = typename V4<T>::type;
@@ -220,7 +233,7 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
                     T val = T(0);
                     if (rt < RT && ct < CTj) {
                         const int row = 16 * rt + M::row(lane, v);
-                        val = A[size_t(perm[row]) * NP + c0 + 16 * ct + lc];
+                        val = src(perm[row], c0 + 16 * ct + lc);
                     }
                     acc[s][ct][v] = val;
                 }

@@ -111,25 +111,29 @@ Engine::~Engine() {
     if (h_admit_cells_) (void)hipHostFree(h_admit_cells_);
 }
 
+// Factor storage per slot: FP64-sized in both forms, since an FP32-LU cell can
+// fall back to FP64 factors.
 size_t Engine::bytes_per_slot(const DeviceNet &dn, int prec) {
+    (void)prec;
     const size_t S = dn.S, R = dn.R, NP = dn.NP;
-    const size_t elt = prec == ABDF_PREC_FP32_LU ? sizeof(float) : sizeof(double);
     return sizeof(SlotCtl) + 5 * sizeof(double) + R * sizeof(double) + kDRows * S * sizeof(double) +
-           6 * S * sizeof(double) + NP * NP * elt + dinv_bytes(int(NP), prec) + NP * sizeof(int32_t) +
-           7 * sizeof(int32_t) + sizeof(long long);
+           6 * S * sizeof(double) + size_t(dn.nnzJ) * sizeof(double) + lu_bytes(int(NP), ABDF_PREC_FP64) +
+           dinv_bytes(int(NP), ABDF_PREC_FP64) +
+           NP * sizeof(int32_t) + 7 * sizeof(int32_t) + sizeof(long long);
 }
 
 int Engine::init(int nslots, std::string &err) {
     const size_t n = size_t(nslots), S = dn_.S, R = dn_.R, NP = dn_.NP;
-    const size_t elt = prec_ == ABDF_PREC_FP32_LU ? sizeof(float) : sizeof(double);
+    const size_t lu_stride = lu_bytes(int(NP), ABDF_PREC_FP64), dinv_stride = dinv_bytes(int(NP), ABDF_PREC_FP64);
     struct Part { void **dst; size_t bytes; };
-    void *ctl, *phi, *k, *D, *x, *d, *psi, *scl, *xJ, *rb, *lu, *dinv, *perm, *act, *lul, *fin, *cnt, *aslots, *acells;
+    void *ctl, *phi, *k, *D, *x, *d, *psi, *scl, *xJ, *rb, *jval, *lu, *dinv, *perm, *act, *lul, *fin, *cnt, *aslots,
+        *acells;
     Part parts[] = {
         {&ctl, n * sizeof(SlotCtl)}, {&phi, n * 5 * sizeof(double)}, {&k, n * R * sizeof(double)},
         {&D, n * kDRows * S * sizeof(double)}, {&x, n * S * sizeof(double)}, {&d, n * S * sizeof(double)},
         {&psi, n * S * sizeof(double)}, {&scl, n * S * sizeof(double)}, {&xJ, n * S * sizeof(double)},
-        {&rb, n * S * sizeof(double)},
-        {&lu, n * NP * NP * elt}, {&dinv, n * dinv_bytes(int(NP), prec_)}, {&perm, n * NP * sizeof(int32_t)}, {&act, 3 * n * sizeof(int32_t)},
+        {&rb, n * S * sizeof(double)}, {&jval, n * size_t(dn_.nnzJ) * sizeof(double)},
+        {&lu, n * lu_stride}, {&dinv, n * dinv_stride}, {&perm, n * NP * sizeof(int32_t)}, {&act, 3 * n * sizeof(int32_t)},
         {&lul, 3 * n * sizeof(int32_t)}, {&fin, n * sizeof(int32_t)}, {&cnt, 8 * sizeof(int32_t)},
         {&aslots, n * sizeof(int32_t)}, {&acells, n * sizeof(long long)},
     };
@@ -163,8 +167,11 @@ int Engine::init(int nslots, std::string &err) {
     s_.scl = static_cast<double *>(scl);
     s_.xJ = static_cast<double *>(xJ);
     s_.rb = static_cast<double *>(rb);
+    s_.jval = static_cast<double *>(jval);
     s_.lu = lu;
     s_.dinv = dinv;
+    s_.lu_stride = lu_stride;
+    s_.dinv_stride = dinv_stride;
     s_.perm = static_cast<int32_t *>(perm);
     s_.act = static_cast<int32_t *>(act);
     s_.lul = static_cast<int32_t *>(lul);
@@ -177,10 +184,13 @@ int Engine::init(int nslots, std::string &err) {
     HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&h_admit_slots_), n * sizeof(int32_t), hipHostMallocDefault));
     HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&h_admit_cells_), n * sizeof(long long), hipHostMallocDefault));
     lds_admit_ = admit_lds(dn_);
-    lds_factor_ = factor_lds(dn_, prec_);
+    lds_factor_ = factor_lds(dn_, ABDF_PREC_FP64);
+    lds_factor32_ = factor_lds(dn_, ABDF_PREC_FP32_LU);
     lds_newton_ = newton_lds(dn_);
     lds_solve_ = solve_lds(dn_);
-    if (dn_.NP > 512 || lds_admit_ > kMaxLds || lds_factor_ > kMaxLds || lds_newton_ > kMaxLds) {
+    lds_solve32_ = solve_lds32(dn_);
+    if (dn_.NP > 512 || lds_admit_ > kMaxLds || lds_factor_ > kMaxLds || lds_newton_ > kMaxLds ||
+        lds_solve32_ > kMaxLds) {
         err = "network too large for one workgroup's LDS";
         return ABDF_E_ARG;
     }
@@ -188,9 +198,13 @@ int Engine::init(int nslots, std::string &err) {
     hipDeviceProp_t prop;
     if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess && prop.multiProcessorCount > 0)
         cus = prop.multiProcessorCount;
-    grid_factor_max_ = cus * resident_per_cu(0, prec_, lds_factor_);
+    const bool f32 = prec_ == ABDF_PREC_FP32_LU;
+    grid_factor64_max_ = cus * resident_per_cu(0, ABDF_PREC_FP64, lds_factor_);
+    grid_solve64_max_ = cus * resident_per_cu(2, ABDF_PREC_FP64, lds_solve_);
+    grid_factor_max_ = f32 ? cus * resident_per_cu(0, prec_, lds_factor32_) : grid_factor64_max_;
     grid_newton_max_ = cus * resident_per_cu(1, prec_, lds_newton_);
-    grid_solve_max_ = cus * resident_per_cu(2, prec_, lds_solve_);
+    grid_solve_max_ = f32 ? cus * resident_per_cu(2, prec_, lds_solve_) : grid_solve64_max_;
+    grid_solve_ref_max_ = cus * resident_per_cu(4, prec_, lds_solve32_);
     grid_adj_solve_max_ = cus * resident_per_cu(3, prec_, adj_solve_lds(dn_));
     free_.clear();
     for (int i = nslots - 1; i >= 0; --i) free_.push_back(i);
@@ -242,14 +256,17 @@ int Engine::admit(const BatchIO &io, const abdf_options &opt, long long &next, h
 int Engine::attempt(hipStream_t st, std::string &err) {
     if (bound_ <= 0) return ABDF_OK;
     hipEvent_t t0 = timer_begin(st);
-    HIP_TRY(launch_factor(s_, dn_, ring_, std::min(bound_, grid_factor_max_), lds_factor_, st));
+    HIP_TRY(launch_factor(s_, dn_, ring_, std::min(bound_, grid_factor_max_), std::min(bound_, grid_factor64_max_),
+                          lds_factor_, lds_factor32_, st));
     timer_end(ABDF_PROF_FACTOR, t0, st);
     for (int m = 0; m < kNewtonMaxIter; ++m) {
         t0 = timer_begin(st);
         HIP_TRY(launch_newton_rhs(s_, dn_, ring_, std::min(bound_, grid_newton_max_), lds_newton_, st));
         timer_end(ABDF_PROF_RHS, t0, st);
         t0 = timer_begin(st);
-        HIP_TRY(launch_newton_solve(s_, ring_, std::min(bound_, grid_solve_max_), lds_solve_, st));
+        HIP_TRY(launch_newton_solve(s_, dn_, ring_, std::min(bound_, grid_solve_max_),
+                                    std::min(bound_, grid_solve_ref_max_), std::min(bound_, grid_solve64_max_),
+                                    lds_solve_, lds_solve32_, st));
         timer_end(ABDF_PROF_NEWTON, t0, st);
     }
     t0 = timer_begin(st);
@@ -351,7 +368,8 @@ int Engine::reverse(const AdjIO &io, int check_every, hipStream_t st, std::strin
     while (true) {
         if (bound_ > 0) {
             hipEvent_t t0 = timer_begin(st);
-            HIP_TRY(launch_factor(s_, dn_, ring_, std::min(bound_, grid_factor_max_), lds_factor_, st));
+            HIP_TRY(launch_factor(s_, dn_, ring_, std::min(bound_, grid_factor_max_),
+                                  std::min(bound_, grid_factor64_max_), lds_factor_, lds_factor32_, st));
             timer_end(ABDF_PROF_FACTOR, t0, st);
             t0 = timer_begin(st);
             HIP_TRY(launch_adj_solve(s_, ring_, std::min(bound_, grid_adj_solve_max_), lds_adj_solve, st));

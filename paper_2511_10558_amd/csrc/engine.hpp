@@ -108,9 +108,11 @@ class Engine {
     std::vector<int32_t> free_;
     int ring_ = 0;
     int bound_ = 0;
-    size_t lds_admit_ = 0, lds_factor_ = 0, lds_newton_ = 0, lds_solve_ = 0;
-    int grid_factor_max_ = 256, grid_newton_max_ = 512, grid_solve_max_ = 1024;   // persistent grid sizes
-    int grid_adj_solve_max_ = 1024;
+    // LDS and persistent grid sizes; the *64 / unsuffixed FP64 values serve the
+    // FP64 variants, *32 / the main grids the FP32 ones in FP32-LU engines
+    size_t lds_admit_ = 0, lds_factor_ = 0, lds_factor32_ = 0, lds_newton_ = 0, lds_solve_ = 0, lds_solve32_ = 0;
+    int grid_factor_max_ = 256, grid_newton_max_ = 512, grid_solve_max_ = 1024;
+    int grid_factor64_max_ = 256, grid_solve64_max_ = 1024, grid_solve_ref_max_ = 512, grid_adj_solve_max_ = 1024;
     // kernel timers of launches not yet read back
     struct Pending { int kind; hipEvent_t a, b; };
     std::vector<Pending> pending_;

@@ -271,20 +271,26 @@ __global__ void __launch_bounds__(kLuThreads) k_factor(Slots s, DeviceNet n, int
     // persistent: each workgroup takes every gridDim.x-th queued slot
     for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
         const int slot = s.lul[ring * s.nslots + idx];
+        // FP32-LU engines run both variants: each takes the slots of its precision
+        if (s.prec == ABDF_PREC_FP32_LU && (sizeof(T) == sizeof(double)) != (s.ctl[slot].lu_mode == kLu64)) continue;
         const double c = s.ctl[slot].c;
-        double *xs = smem;
-        const double *k = s.k + size_t(slot) * n.R;
+        // x_J after the factorisation's own LDS; the Jacobian nonzeros go to the
+        // slot's compact array and M = I - c J(x_J) is formed block column by
+        // block column as the factorisation gathers it
+        double *xs = reinterpret_cast<double *>(reinterpret_cast<unsigned char *>(smem) + lu2_lds_bytes<T>(NP));
         for (int i = threadIdx.x; i < S; i += kLuThreads) xs[i] = s.xJ[size_t(slot) * S + i];
         __syncthreads();
-        T *A = reinterpret_cast<T *>(s.lu) + size_t(slot) * NP * NP;
-        assemble_newton_matrix<T, kLuThreads>(n, k, xs, c, A);
-        lu_factor_left<T>(A, NP, s.perm + size_t(slot) * NP,
-                          reinterpret_cast<T *>(s.dinv) + size_t(slot) * lu2_dinv_elems<T>(NP), nullptr,
-                          reinterpret_cast<unsigned char *>(smem));
+        double *jv = s.jval + size_t(slot) * n.nnzJ;
+        jacobian_values<kLuThreads>(n, s.k + size_t(slot) * n.R, xs, jv);
+        __syncthreads();
+        NewtonMatrixSource<T> src{n.jidx, jv, S, NP, c};
+        lu_factor_left<T>(slot_lu<T>(s, slot), NP, s.perm + size_t(slot) * NP, slot_dinv<T>(s, slot), nullptr,
+                          reinterpret_cast<unsigned char *>(smem), src);
         if (threadIdx.x == 0) {
             s.ctl[slot].c_lu = c;
             s.ctl[slot].lu_valid = 1;
             s.ctl[slot].n_lu += 1;
+            if (s.prec == ABDF_PREC_FP32_LU && sizeof(T) == sizeof(double)) s.ctl[slot].n_lu64 += 1;
         }
         __syncthreads();
     }
@@ -332,16 +338,22 @@ __global__ void __launch_bounds__(kBlock) k_newton_rhs(Slots s, DeviceNet n, int
 
 // Newton correction Delta = M^{-1} r, its weighted norm, the convergence and
 // divergence tests, and the update x += Delta, d += Delta (persistent).
-template <typename T>
-__global__ void __launch_bounds__(kBlock) k_newton_solve(Slots s, int ring) {
+// The refining variant (FP32 factors after a corrector failure) refines once in FP64:
+// Delta += M^{-1} (r - (Delta - c J(x_J) Delta)), J applied through the
+// network's Jacobian term lists.
+template <typename T, bool kRefine>
+__global__ void __launch_bounds__(kBlock) k_newton_solve(Slots s, DeviceNet n, int ring) {
     extern __shared__ double smem[];
     __shared__ double red[kLuW + kWaves];
     __shared__ int decision;
+    // the factor mode this variant serves in an FP32-LU engine
+    constexpr int32_t kMode = sizeof(T) == sizeof(double) ? kLu64 : (kRefine ? kLuRefined32 : kLuPlain32);
     const int count = s.cnt[ring];
     const int S = s.S, NP = s.NP;
     for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
         const int slot = s.act[ring * s.nslots + idx];
         if (s.ctl[slot].phase != kIter) continue;
+        if (s.prec == ABDF_PREC_FP32_LU && s.ctl[slot].lu_mode != kMode) continue;
         double *b = smem;
         double *y = b + NP;
         double *x = s.x + size_t(slot) * S, *d = s.d + size_t(slot) * S;
@@ -349,9 +361,21 @@ __global__ void __launch_bounds__(kBlock) k_newton_solve(Slots s, int ring) {
         for (int i = threadIdx.x; i < NP; i += kBlock) b[i] = i < S ? rb[i] : 0.0;
         __syncthreads();
         const int32_t *perm = s.perm + size_t(slot) * NP;
-        lu_solve_left<T>(reinterpret_cast<const T *>(s.lu) + size_t(slot) * NP * NP,
-                         reinterpret_cast<const T *>(s.dinv) + size_t(slot) * lu2_dinv_elems<T>(NP), perm, perm,
-                         NP, b, y, red);
+        const T *A = slot_lu<T>(s, slot);
+        const T *Di = slot_dinv<T>(s, slot);
+        lu_solve_left<T>(A, Di, perm, perm, NP, b, y, red);
+        if (kRefine) {
+            double *y2 = y + NP, *xs = y2 + NP, *drate = xs + S, *part = drate + n.R;
+            const double c = s.ctl[slot].c_lu;
+            for (int i = threadIdx.x; i < S; i += kBlock) xs[i] = s.xJ[size_t(slot) * S + i];
+            __syncthreads();
+            cell_jvp(n, s.k + size_t(slot) * n.R, xs, y, drate, part, y2);   // y2 = J(x_J) y
+            for (int i = threadIdx.x; i < NP; i += kBlock) b[i] = i < S ? rb[i] - (y[i] - c * y2[i]) : 0.0;
+            __syncthreads();
+            lu_solve_left<T>(A, Di, perm, perm, NP, b, y2, red);
+            for (int i = threadIdx.x; i < NP; i += kBlock) y[i] = y[i] + y2[i];
+            __syncthreads();
+        }
         double acc = 0.0;
         for (int i = threadIdx.x; i < S; i += kBlock) {
             const double v = y[i] / scl[i];
@@ -414,6 +438,13 @@ __global__ void __launch_bounds__(kBlock) k_control(Slots s, int ring) {
                 cs.j_fresh = 1;
                 cs.jac_refresh = 1;
                 cs.n_jac += 1;
+                sh[0] = 0.0;
+            } else if (s.prec == ABDF_PREC_FP32_LU && cs.lu_mode != kLu64) {
+                // the corrector failed with a fresh Jacobian and FP32 factors:
+                // the cell retries the same step with refined solves, then
+                // with FP64 factors
+                cs.lu_mode += 1;
+                if (cs.lu_mode == kLu64) cs.lu_valid = 0;
                 sh[0] = 0.0;
             } else {
                 cs.h = 0.5 * cs.h;
@@ -559,6 +590,8 @@ __global__ void __launch_bounds__(kBlock) k_harvest(Slots s, HarvestArgs h) {
             st.order = c.q;
             st.h = c.h;
             st.t = c.t;
+            st.n_lu_fp64 = s.prec == ABDF_PREC_FP32_LU ? c.n_lu64 : c.n_lu;
+            st.reserved = 0;
             h.stats[cell] = st;
         }
     }
@@ -765,7 +798,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_solve(Slots s, int ring) {
         const double *rb = s.rb + size_t(slot) * S;
         for (int i = threadIdx.x; i < NP; i += kBlock) b[i] = i < S ? rb[i] : 0.0;
         __syncthreads();
-        lu_solve_left_T<T>(reinterpret_cast<const T *>(s.lu) + size_t(slot) * NP * NP, s.perm + size_t(slot) * NP,
+        lu_solve_left_T<T>(slot_lu<T>(s, slot), s.perm + size_t(slot) * NP,
                            NP, b, z, t, Db);
         double *d = s.d + size_t(slot) * S;
         for (int i = threadIdx.x; i < S; i += kBlock) d[i] = z[i];
@@ -918,8 +951,9 @@ __global__ void __launch_bounds__(kLuThreads) k_lu_factor_only(int NP, T *W, int
                                                               int32_t *info) {
     extern __shared__ double smem[];
     const long long b = blockIdx.x;
-    lu_factor_left<T>(W + b * NP * NP, NP, permW + b * NP, dinv + b * lu2_dinv_elems<T>(NP),
-                      info ? info + b : nullptr, reinterpret_cast<unsigned char *>(smem));
+    T *A = W + b * NP * NP;
+    lu_factor_left<T>(A, NP, permW + b * NP, dinv + b * lu2_dinv_elems<T>(NP), info ? info + b : nullptr,
+                      reinterpret_cast<unsigned char *>(smem), DenseSource<T>{A, NP});
 }
 
 // Inverse diagonal blocks of LAPACK-layout factors (rows already in P A order).
@@ -998,7 +1032,7 @@ size_t lu_work_lds(int NP, int prec) {
 }
 
 size_t factor_lds(const DeviceNet &n, int prec) {
-    return std::max(sizeof(double) * size_t(n.S), lu_work_lds(n.NP, prec));
+    return lu_work_lds(n.NP, prec) + sizeof(double) * size_t(n.S);   // factorisation, then x_J
 }
 
 int resident_per_cu(int which, int prec, size_t lds) {
@@ -1012,13 +1046,19 @@ int resident_per_cu(int which, int prec, size_t lds) {
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_newton_rhs, kBlock, lds);
     else if (which == 2)
         e = prec == ABDF_PREC_FP32_LU
-                ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_newton_solve<float>, kBlock, lds)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_newton_solve<double>, kBlock, lds);
+                ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_newton_solve<float, false>, kBlock, lds)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_newton_solve<double, false>, kBlock, lds);
+    else if (which == 4)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_newton_solve<float, true>, kBlock, lds);
     else
         e = prec == ABDF_PREC_FP32_LU
                 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adj_solve<float>, kBlock, lds)
                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_adj_solve<double>, kBlock, lds);
     return (e == hipSuccess && nb > 0) ? nb : 1;
+}
+
+size_t lu_bytes(int NP, int prec) {
+    return size_t(NP) * NP * (prec == ABDF_PREC_FP32_LU ? sizeof(float) : sizeof(double));
 }
 
 size_t dinv_bytes(int NP, int prec) {
@@ -1034,12 +1074,16 @@ hipError_t launch_admit(const Slots &s, const DeviceNet &n, const AdmitArgs &a, 
     return LAUNCH_CHECK();
 }
 
-hipError_t launch_factor(const Slots &s, const DeviceNet &n, int ring, int grid, size_t lds, hipStream_t st) {
+hipError_t launch_factor(const Slots &s, const DeviceNet &n, int ring, int grid, int grid64, size_t lds,
+                         size_t lds32, hipStream_t st) {
     if (grid == 0) return hipSuccess;
-    if (s.prec == ABDF_PREC_FP32_LU)
-        hipLaunchKernelGGL(k_factor<float>, dim3(grid), dim3(kLuThreads), lds, st, s, n, ring);
-    else
-        hipLaunchKernelGGL(k_factor<double>, dim3(grid), dim3(kLuThreads), lds, st, s, n, ring);
+    if (s.prec == ABDF_PREC_FP32_LU) {
+        hipLaunchKernelGGL(k_factor<float>, dim3(grid), dim3(kLuThreads), lds32, st, s, n, ring);
+        hipError_t e = LAUNCH_CHECK();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_factor<double>, dim3(s.prec == ABDF_PREC_FP32_LU ? grid64 : grid), dim3(kLuThreads), lds,
+                       st, s, n, ring);
     return LAUNCH_CHECK();
 }
 
@@ -1049,12 +1093,19 @@ hipError_t launch_newton_rhs(const Slots &s, const DeviceNet &n, int ring, int g
     return LAUNCH_CHECK();
 }
 
-hipError_t launch_newton_solve(const Slots &s, int ring, int grid, size_t lds, hipStream_t st) {
+hipError_t launch_newton_solve(const Slots &s, const DeviceNet &n, int ring, int grid, int grid_ref, int grid64,
+                               size_t lds, size_t lds_ref, hipStream_t st) {
     if (grid == 0) return hipSuccess;
-    if (s.prec == ABDF_PREC_FP32_LU)
-        hipLaunchKernelGGL(k_newton_solve<float>, dim3(grid), dim3(kBlock), lds, st, s, ring);
-    else
-        hipLaunchKernelGGL(k_newton_solve<double>, dim3(grid), dim3(kBlock), lds, st, s, ring);
+    if (s.prec == ABDF_PREC_FP32_LU) {
+        hipLaunchKernelGGL((k_newton_solve<float, false>), dim3(grid), dim3(kBlock), lds, st, s, n, ring);
+        hipError_t e = LAUNCH_CHECK();
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL((k_newton_solve<float, true>), dim3(grid_ref), dim3(kBlock), lds_ref, st, s, n, ring);
+        e = LAUNCH_CHECK();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL((k_newton_solve<double, false>), dim3(s.prec == ABDF_PREC_FP32_LU ? grid64 : grid),
+                       dim3(kBlock), lds, st, s, n, ring);
     return LAUNCH_CHECK();
 }
 

@@ -59,12 +59,23 @@ inline size_t newton_lds(const DeviceNet &n) {
     return sizeof(double) * (2 * size_t(n.S) + n.R + n.n_seg);
 }
 inline size_t solve_lds(const DeviceNet &n) { return sizeof(double) * 2 * size_t(n.NP); }
+// the refining FP32 variant also holds the second solution, x_J and the
+// scratch of the Jacobian-vector product
+inline size_t solve_lds32(const DeviceNet &n) {
+    return sizeof(double) * (3 * size_t(n.NP) + n.S + n.R + n.n_seg);
+}
 size_t factor_lds(const DeviceNet &n, int prec);
 
 hipError_t launch_admit(const Slots &s, const DeviceNet &n, const AdmitArgs &a, int ring, size_t lds, hipStream_t st);
-hipError_t launch_factor(const Slots &s, const DeviceNet &n, int ring, int grid, size_t lds, hipStream_t st);
+// FP32-LU engines launch the FP32 variant (grid, lds32) and then the FP64 one
+// for the slots that fell back (grid64, lds); FP64 engines only the latter (grid).
+hipError_t launch_factor(const Slots &s, const DeviceNet &n, int ring, int grid, int grid64, size_t lds,
+                         size_t lds32, hipStream_t st);
 hipError_t launch_newton_rhs(const Slots &s, const DeviceNet &n, int ring, int grid, size_t lds, hipStream_t st);
-hipError_t launch_newton_solve(const Slots &s, int ring, int grid, size_t lds, hipStream_t st);
+// FP32-LU engines launch the plain FP32 (grid), the refining FP32 (grid_ref,
+// lds_ref) and the FP64 (grid64) variants; FP64 engines only the last (grid).
+hipError_t launch_newton_solve(const Slots &s, const DeviceNet &n, int ring, int grid, int grid_ref, int grid64,
+                               size_t lds, size_t lds_ref, hipStream_t st);
 hipError_t launch_control(const Slots &s, int ring, int grid, hipStream_t st);
 hipError_t launch_harvest(const Slots &s, const HarvestArgs &h, hipStream_t st);
 
@@ -85,8 +96,10 @@ hipError_t launch_lu_factor(int n, int NP, long long batch, double *A, void *W, 
 hipError_t launch_lu_solve(int n, int NP, long long batch, const double *LU, const int32_t *perm, double *b,
                            void *W, int32_t *permW, void *dinv, hipStream_t st);
 size_t dinv_bytes(int NP, int prec);
+size_t lu_bytes(int NP, int prec);
 // Workgroups resident per CU of the factor (which = 0), Newton residual (1),
-// Newton solve (2) or transposed adjoint solve (3) kernel.
+// Newton solve (2), transposed adjoint solve (3) or refining FP32 Newton
+// solve (4) kernel.
 int resident_per_cu(int which, int prec, size_t lds);
 hipError_t launch_selftest(int *bad, hipStream_t st);
 size_t lu_work_lds(int NP, int prec);

@@ -41,7 +41,7 @@ HostNetwork::~HostNetwork() {
         if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(d->device) == hipSuccess) {
             void *ptrs[] = {d->rx_ab, d->rx_type, d->alpha, d->beta, d->gamma, d->seg_ptr, d->seg_beg,
                             d->f_ent, d->jrow_ptr, d->jcol, d->jrow, d->jterm_ptr, d->jt_rx_other, d->jt_coef,
-                            d->rnu_ptr, d->rnu_ent, d->dcol_ptr, d->dcol_ent, d->dcol_coef};
+                            d->rnu_ptr, d->rnu_ent, d->dcol_ptr, d->dcol_ent, d->dcol_coef, d->jidx};
             for (void *p : ptrs)
                 if (p) (void)hipFree(p);
             (void)hipSetDevice(prev);
@@ -232,6 +232,8 @@ void HostNetwork::finalize() {
         }
     }
     dcol_ptr[S] = int32_t(dcol_ent.size());
+    jidx.assign(size_t(NP) * NP, -1);
+    for (size_t e = 0; e < jcol.size(); ++e) jidx[size_t(jrow[e]) * NP + jcol[e]] = int32_t(e);
 }
 
 namespace {
@@ -289,6 +291,7 @@ const DeviceNet *HostNetwork::device_tables(std::string &err) const {
     chk(upload(&d->dcol_ptr, dcol_ptr));
     chk(upload(&d->dcol_ent, dcol_ent));
     chk(upload(&d->dcol_coef, dcol_coef));
+    chk(upload(&d->jidx, jidx));
     d->n_seg = int32_t(seg_beg.size()) - 1;
     d->nnzJ = int32_t(jcol.size());
     d->nterm = int32_t(jt_coef.size());

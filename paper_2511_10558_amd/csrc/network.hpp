@@ -42,6 +42,8 @@ struct DeviceNet {
     int32_t *dcol_ptr = nullptr;   // [S+1]
     int32_t *dcol_ent = nullptr;
     double *dcol_coef = nullptr;
+    // dense map (i, j) -> index of the Jacobian nonzero, -1 where J_ij = 0 structurally [NP][NP]
+    int32_t *jidx = nullptr;
 };
 
 struct HostNetwork {
@@ -60,7 +62,7 @@ struct HostNetwork {
     std::vector<int32_t> seg_ptr, seg_beg, f_ent;
     std::vector<int32_t> jrow_ptr, jcol, jrow, jterm_ptr, jt_rx_other;
     std::vector<double> jt_coef;
-    std::vector<int32_t> rnu_ptr, rnu_ent, dcol_ptr, dcol_ent;
+    std::vector<int32_t> rnu_ptr, rnu_ent, dcol_ptr, dcol_ent, jidx;
     std::vector<double> dcol_coef;
 
     // per-device uploads, created on first use

@@ -117,3 +117,20 @@ def test_deterministic_and_independent_of_batch_composition(ab, dev):
     assert np.array_equal(x1, x3)
     alone, _, _ = solve_cells(ab, g, cells.subset([4]), dev)
     assert np.array_equal(alone[0], x1[4])
+
+
+def test_fp32_lu_form_matches_oracle(ab, dev):
+    # FP32 factors with one FP64 refinement per Newton solve and FP64 fallback;
+    # parity against the FP64 oracle (the FP32 form has no exact reference of
+    # its own: parity unpinned beyond this tolerance)
+    net = synth.network_for_config("net500")
+    cells = synth.sample_cells(net, 3, seed=3001)
+    g = ab.Network.from_text(net.to_text())
+    x, status, stats = solve_cells(ab, g, cells, dev, precision="fp32_lu")
+    refs = oracle_cells(net, cells)
+    for c in range(cells.n):
+        assert status[c] == 0
+        assert rel_err_above(x[c], refs[c].x) <= TOL
+        assert stats["n_lu_fp64"][c] <= stats["n_lu"][c]
+    x64, _, st64 = solve_cells(ab, g, cells, dev)
+    assert np.all(st64["n_lu_fp64"] == st64["n_lu"])
