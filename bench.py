@@ -104,8 +104,13 @@ def run_serve(args):
             info0 = srv.info()
             t0 = srv.clock()
             ids, done, i = {}, {}, 0
+            last_note = 0.0
             while len(done) < len(reqs):
                 now = srv.clock() - t0
+                if now - last_note > 20.0:
+                    last_note = now
+                    print(f"[serve] {precision}: {now:.0f} s, {i} submitted, {len(done)} complete",
+                          file=sys.stderr, flush=True)
                 while i < len(reqs) and arrivals[i] <= now:
                     ids[submit(srv, reqs[i].cells)] = i
                     i += 1

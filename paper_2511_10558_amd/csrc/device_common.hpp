@@ -60,8 +60,9 @@ struct Slots {
     int32_t *perm;    // [n][NP]
     int32_t *act;     // [3][n] active-slot lists (ring)
     int32_t *lul;     // [3][n] slots needing a factorisation (ring)
+    int32_t *nol;     // [3][n] active slots whose factorisation is current (ring)
     int32_t *fin;     // [n] finished slots since the last harvest
-    int32_t *cnt;     // [0..2] active counts, [3..5] factor counts, [6] finished count
+    int32_t *cnt;     // [0..2] active counts, [3..5] factor counts, [6] finished count, [7..9] no-factor counts
     // step tape of the discrete adjoint (null when not recording), indexed by cell
     int tape_cap;     // accepted steps recorded per cell
     double *tape_x;   // [cells][tape_cap][S] x after each accepted step
@@ -82,6 +83,26 @@ __device__ __forceinline__ T *slot_dinv(const Slots &s, int slot) {
     return reinterpret_cast<T *>(static_cast<char *>(s.dinv) + size_t(slot) * s.dinv_stride);
 }
 
+// Slot lists of the step-attempt loop: every active slot, those that factor
+// this attempt, those that do not.
+constexpr int kListAll = 0;
+constexpr int kListFactor = 1;
+constexpr int kListNoFactor = 2;
+constexpr int kCountSlots = 16;   // ints in Slots::cnt
+
+__device__ __forceinline__ const int32_t *slot_list(const Slots &s, int which, int ring, int &count) {
+    if (which == kListFactor) {
+        count = s.cnt[3 + ring];
+        return s.lul + ring * s.nslots;
+    }
+    if (which == kListNoFactor) {
+        count = s.cnt[7 + ring];
+        return s.nol + ring * s.nslots;
+    }
+    count = s.cnt[ring];
+    return s.act + ring * s.nslots;
+}
+
 // One step of a wave-wide arg-max (value descending, key ascending on ties)
 // through a DPP lane permutation; lanes outside the pattern keep their pair.
 template <int CTRL, int ROW_MASK>
@@ -91,7 +112,10 @@ __device__ __forceinline__ void dpp_argmax_step(double &v, int &k) {
     const int ohi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROW_MASK, 0xf, false);
     const int ok = __builtin_amdgcn_update_dpp(k, k, CTRL, ROW_MASK, 0xf, false);
     const double ov = __hiloint2double(ohi, olo);
-    if (ov > v || (ov == v && ok < k)) { v = ov; k = ok; }
+    // selects, not a branch: keeps the reduction free of exec-mask changes
+    const bool take = (ov > v) | ((ov == v) & (ok < k));
+    v = take ? ov : v;
+    k = take ? ok : k;
 }
 
 // Arg-max over the 64 lanes of a wave, returned uniformly to every lane:

@@ -352,12 +352,21 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
                     }
                 }
                 __syncthreads();
-                // cross-wave arg-max: one partial per lane, key = logical row * 8 + wave
+                // cross-wave arg-max: lane w < 8 holds wave w's partial, key =
+                // logical row * 8 + wave; three DPP steps reduce lanes 0..7
                 double fv = lane < kLuWaves ? redv[buf * kLuWaves + lane] : -2.0;
                 int fk = 0x7fffffff;
                 if (lane < kLuWaves && redi[buf * kLuWaves + lane] != 0x7fffffff)
                     fk = redi[buf * kLuWaves + lane] * 8 + lane;
-                wave_argmax(fv, fk);
+                dpp_argmax_step<0xB1, 0xf>(fv, fk);    // quad_perm [1,0,3,2]
+                dpp_argmax_step<0x4E, 0xf>(fv, fk);    // quad_perm [2,3,0,1]
+                dpp_argmax_step<0x141, 0xf>(fv, fk);   // row_half_mirror
+                {
+                    const int lo = __builtin_amdgcn_readlane(__double2loint(fv), 0);
+                    const int hi = __builtin_amdgcn_readlane(__double2hiint(fv), 0);
+                    fk = __builtin_amdgcn_readlane(fk, 0);
+                    fv = __hiloint2double(hi, lo);
+                }
                 int lp = fk >> 3, wv = fk & 7;
                 if (fv < 0.0) {          // no finite candidate: keep logical row r
                     lp = r;
@@ -514,18 +523,25 @@ __device__ __forceinline__ void lu_solve_left(const T *__restrict__ A, const T *
     // rowmap); 16 lanes per row, each thread carries 4 rows so that 8 loads
     // per column pair are in flight.
     auto gemv_off = [&](int r0, int W, int c_begin, int c_end, const double *vec) {
+        // rows past W (last block) read row W - 1 again; their sums are not stored.
+        // No load sits behind a condition, so all of them are in flight together.
         const T *rows[4];
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
-            const int rr = row16 + 16 * p;
-            rows[p] = rr < W ? A + size_t(rowmap ? rowmap[r0 + rr] : r0 + rr) * NP : nullptr;
+            const int rr = min(row16 + 16 * p, W - 1);
+            rows[p] = A + size_t(rowmap ? rowmap[r0 + rr] : r0 + rr) * NP;
         }
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
         for (int c = c_begin + 2 * lane16; c < c_end; c += 32) {
             const double y0 = vec[c], y1 = vec[c + 1];
+            T a0[4], a1[4];
 #pragma unroll
-            for (int p = 0; p < 4; ++p)
-                if (rows[p]) acc[p] += double(rows[p][c]) * y0 + double(rows[p][c + 1]) * y1;
+            for (int p = 0; p < 4; ++p) {
+                a0[p] = rows[p][c];
+                a1[p] = rows[p][c + 1];
+            }
+#pragma unroll
+            for (int p = 0; p < 4; ++p) acc[p] += double(a0[p]) * y0 + double(a1[p]) * y1;
         }
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
@@ -536,14 +552,19 @@ __device__ __forceinline__ void lu_solve_left(const T *__restrict__ A, const T *
         }
     };
     auto gemv_diag = [&](int r0, int W, const T *D) {
+        // D is a full 64 x 64 block: rows past W are read but not stored
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
         for (int c = 2 * lane16; c < W; c += 32) {
             const double t0 = t[c], t1 = t[c + 1];
+            T a0[4], a1[4];
 #pragma unroll
             for (int p = 0; p < 4; ++p) {
                 const int rr = row16 + 16 * p;
-                if (rr < W) acc[p] += double(D[rr * kLuW + c]) * t0 + double(D[rr * kLuW + c + 1]) * t1;
+                a0[p] = D[rr * kLuW + c];
+                a1[p] = D[rr * kLuW + c + 1];
             }
+#pragma unroll
+            for (int p = 0; p < 4; ++p) acc[p] += double(a0[p]) * t0 + double(a1[p]) * t1;
         }
 #pragma unroll
         for (int p = 0; p < 4; ++p) {

@@ -109,6 +109,9 @@ Engine::~Engine() {
     if (h_fin_) (void)hipHostFree(h_fin_);
     if (h_admit_slots_) (void)hipHostFree(h_admit_slots_);
     if (h_admit_cells_) (void)hipHostFree(h_admit_cells_);
+    if (ev_lists_) (void)hipEventDestroy(ev_lists_);
+    if (ev_side_) (void)hipEventDestroy(ev_side_);
+    if (side_) (void)hipStreamDestroy(side_);
 }
 
 // Factor storage per slot: FP64-sized in both forms, since an FP32-LU cell can
@@ -126,15 +129,16 @@ int Engine::init(int nslots, std::string &err) {
     const size_t n = size_t(nslots), S = dn_.S, R = dn_.R, NP = dn_.NP;
     const size_t lu_stride = lu_bytes(int(NP), ABDF_PREC_FP64), dinv_stride = dinv_bytes(int(NP), ABDF_PREC_FP64);
     struct Part { void **dst; size_t bytes; };
-    void *ctl, *phi, *k, *D, *x, *d, *psi, *scl, *xJ, *rb, *jval, *lu, *dinv, *perm, *act, *lul, *fin, *cnt, *aslots,
-        *acells;
+    void *ctl, *phi, *k, *D, *x, *d, *psi, *scl, *xJ, *rb, *jval, *lu, *dinv, *perm, *act, *lul, *nol, *fin, *cnt,
+        *aslots, *acells;
     Part parts[] = {
         {&ctl, n * sizeof(SlotCtl)}, {&phi, n * 5 * sizeof(double)}, {&k, n * R * sizeof(double)},
         {&D, n * kDRows * S * sizeof(double)}, {&x, n * S * sizeof(double)}, {&d, n * S * sizeof(double)},
         {&psi, n * S * sizeof(double)}, {&scl, n * S * sizeof(double)}, {&xJ, n * S * sizeof(double)},
         {&rb, n * S * sizeof(double)}, {&jval, n * size_t(dn_.nnzJ) * sizeof(double)},
         {&lu, n * lu_stride}, {&dinv, n * dinv_stride}, {&perm, n * NP * sizeof(int32_t)}, {&act, 3 * n * sizeof(int32_t)},
-        {&lul, 3 * n * sizeof(int32_t)}, {&fin, n * sizeof(int32_t)}, {&cnt, 8 * sizeof(int32_t)},
+        {&lul, 3 * n * sizeof(int32_t)}, {&nol, 3 * n * sizeof(int32_t)}, {&fin, n * sizeof(int32_t)},
+        {&cnt, kCountSlots * sizeof(int32_t)},
         {&aslots, n * sizeof(int32_t)}, {&acells, n * sizeof(long long)},
     };
     size_t total = 0;
@@ -150,7 +154,7 @@ int Engine::init(int nslots, std::string &err) {
         *p.dst = static_cast<char *>(base_) + off;
         off += align256(p.bytes);
     }
-    HIP_TRY(hipMemset(cnt, 0, 8 * sizeof(int32_t)));
+    HIP_TRY(hipMemset(cnt, 0, kCountSlots * sizeof(int32_t)));
     s_.nslots = nslots;
     s_.S = dn_.S;
     s_.R = dn_.R;
@@ -175,11 +179,15 @@ int Engine::init(int nslots, std::string &err) {
     s_.perm = static_cast<int32_t *>(perm);
     s_.act = static_cast<int32_t *>(act);
     s_.lul = static_cast<int32_t *>(lul);
+    s_.nol = static_cast<int32_t *>(nol);
     s_.fin = static_cast<int32_t *>(fin);
     s_.cnt = static_cast<int32_t *>(cnt);
     d_admit_slots_ = static_cast<int32_t *>(aslots);
     d_admit_cells_ = static_cast<long long *>(acells);
-    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&h_cnt_), 8 * sizeof(int32_t), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&h_cnt_), kCountSlots * sizeof(int32_t), hipHostMallocDefault));
+    HIP_TRY(hipStreamCreateWithFlags(&side_, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&ev_lists_, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&ev_side_, hipEventDisableTiming));
     HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&h_fin_), n * sizeof(int32_t), hipHostMallocDefault));
     HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&h_admit_slots_), n * sizeof(int32_t), hipHostMallocDefault));
     HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&h_admit_cells_), n * sizeof(long long), hipHostMallocDefault));
@@ -253,22 +261,38 @@ int Engine::admit(const BatchIO &io, const abdf_options &opt, long long &next, h
     return admit_cells(a, st, err);
 }
 
-int Engine::attempt(hipStream_t st, std::string &err) {
-    if (bound_ <= 0) return ABDF_OK;
-    hipEvent_t t0 = timer_begin(st);
-    HIP_TRY(launch_factor(s_, dn_, ring_, std::min(bound_, grid_factor_max_), std::min(bound_, grid_factor64_max_),
-                          lds_factor_, lds_factor32_, st));
-    timer_end(ABDF_PROF_FACTOR, t0, st);
+int Engine::newton_iterations(int which, hipStream_t st, std::string &err) {
     for (int m = 0; m < kNewtonMaxIter; ++m) {
-        t0 = timer_begin(st);
-        HIP_TRY(launch_newton_rhs(s_, dn_, ring_, std::min(bound_, grid_newton_max_), lds_newton_, st));
+        hipEvent_t t0 = timer_begin(st);
+        HIP_TRY(launch_newton_rhs(s_, dn_, ring_, which, std::min(bound_, grid_newton_max_), lds_newton_, st));
         timer_end(ABDF_PROF_RHS, t0, st);
         t0 = timer_begin(st);
-        HIP_TRY(launch_newton_solve(s_, dn_, ring_, std::min(bound_, grid_solve_max_),
+        HIP_TRY(launch_newton_solve(s_, dn_, ring_, which, std::min(bound_, grid_solve_max_),
                                     std::min(bound_, grid_solve_ref_max_), std::min(bound_, grid_solve64_max_),
                                     lds_solve_, lds_solve32_, st));
         timer_end(ABDF_PROF_NEWTON, t0, st);
     }
+    return ABDF_OK;
+}
+
+// One step attempt.  The slots whose factorisation is current iterate on the
+// side stream while the others are factored on st: the factorisation kernel is
+// LDS-bound at a few workgroups per CU and leaves CUs idle in its last round,
+// which the side stream's kernels fill.  Control waits for both streams.
+int Engine::attempt(hipStream_t st, std::string &err) {
+    if (bound_ <= 0) return ABDF_OK;
+    HIP_TRY(hipEventRecord(ev_lists_, st));
+    hipEvent_t t0 = timer_begin(st);
+    HIP_TRY(launch_factor(s_, dn_, ring_, std::min(bound_, grid_factor_max_), std::min(bound_, grid_factor64_max_),
+                          lds_factor_, lds_factor32_, st));
+    timer_end(ABDF_PROF_FACTOR, t0, st);
+    HIP_TRY(hipStreamWaitEvent(side_, ev_lists_, 0));
+    int rc = newton_iterations(kListNoFactor, side_, err);
+    if (rc != ABDF_OK) return rc;
+    HIP_TRY(hipEventRecord(ev_side_, side_));
+    rc = newton_iterations(kListFactor, st, err);
+    if (rc != ABDF_OK) return rc;
+    HIP_TRY(hipStreamWaitEvent(st, ev_side_, 0));
     t0 = timer_begin(st);
     HIP_TRY(launch_control(s_, ring_, bound_, st));
     timer_end(ABDF_PROF_CONTROL, t0, st);
@@ -277,7 +301,7 @@ int Engine::attempt(hipStream_t st, std::string &err) {
 }
 
 int Engine::sync_counts(hipStream_t st, int &nfin, std::string &err) {
-    HIP_TRY(hipMemcpyAsync(h_cnt_, s_.cnt, 8 * sizeof(int32_t), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(h_cnt_, s_.cnt, kCountSlots * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     flush_timers();
     nfin = h_cnt_[6];
@@ -337,7 +361,7 @@ int Engine::solve(const BatchIO &io, const abdf_options &opt, hipStream_t st, st
 int Engine::reverse(const AdjIO &io, int check_every, hipStream_t st, std::string &err) {
     ring_ = 0;
     bound_ = 0;
-    HIP_TRY(hipMemsetAsync(s_.cnt, 0, 8 * sizeof(int32_t), st));
+    HIP_TRY(hipMemsetAsync(s_.cnt, 0, kCountSlots * sizeof(int32_t), st));
     const size_t lds_adj = adj_lds(dn_), lds_adj_solve = adj_solve_lds(dn_);
     if (lds_adj > kMaxLds || lds_adj_solve > kMaxLds) {
         err = "network too large for one workgroup's LDS";

@@ -93,6 +93,7 @@ class Engine {
 
   private:
     int admit(const BatchIO &io, const abdf_options &opt, long long &next, hipStream_t st, std::string &err);
+    int newton_iterations(int which, hipStream_t st, std::string &err);
 
     const HostNetwork &net_;
     const DeviceNet &dn_;
@@ -101,7 +102,9 @@ class Engine {
     void *base_ = nullptr;
     int32_t *d_admit_slots_ = nullptr;
     long long *d_admit_cells_ = nullptr;
-    int32_t *h_cnt_ = nullptr;          // pinned [8]
+    int32_t *h_cnt_ = nullptr;          // pinned [kCountSlots]
+    hipStream_t side_ = nullptr;        // Newton iterations of slots that do not factor (default priority)
+    hipEvent_t ev_lists_ = nullptr, ev_side_ = nullptr;
     int32_t *h_fin_ = nullptr;          // pinned [nslots]
     int32_t *h_admit_slots_ = nullptr;  // pinned [nslots]
     long long *h_admit_cells_ = nullptr;

@@ -151,6 +151,9 @@ __device__ __forceinline__ void begin_attempt(const Slots &s, int slot, SlotCtl 
         if (!cs.lu_valid || cs.c != cs.c_lu) {
             const int pl = atomicAdd(&s.cnt[3 + ring], 1);
             s.lul[ring * s.nslots + pl] = slot;
+        } else {
+            const int pn = atomicAdd(&s.cnt[7 + ring], 1);
+            s.nol[ring * s.nslots + pn] = slot;
         }
         s.ctl[slot] = cs;
     }
@@ -298,13 +301,14 @@ __global__ void __launch_bounds__(kLuThreads) k_factor(Slots s, DeviceNet n, int
 
 // Newton residual r = c f(x) - psi - d of every active slot still iterating
 // (persistent).  A non-finite f ends the attempt as a corrector failure.
-__global__ void __launch_bounds__(kBlock) k_newton_rhs(Slots s, DeviceNet n, int ring) {
+__global__ void __launch_bounds__(kBlock) k_newton_rhs(Slots s, DeviceNet n, int ring, int which) {
     extern __shared__ double smem[];
     __shared__ double red[kWaves];
-    const int count = s.cnt[ring];
+    int count;
+    const int32_t *list = slot_list(s, which, ring, count);
     const int S = s.S;
     for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
-        const int slot = s.act[ring * s.nslots + idx];
+        const int slot = list[idx];
         if (s.ctl[slot].phase != kIter) continue;
         double *xs = smem;
         double *rate = xs + S;
@@ -342,16 +346,17 @@ __global__ void __launch_bounds__(kBlock) k_newton_rhs(Slots s, DeviceNet n, int
 // Delta += M^{-1} (r - (Delta - c J(x_J) Delta)), J applied through the
 // network's Jacobian term lists.
 template <typename T, bool kRefine>
-__global__ void __launch_bounds__(kBlock) k_newton_solve(Slots s, DeviceNet n, int ring) {
+__global__ void __launch_bounds__(kBlock) k_newton_solve(Slots s, DeviceNet n, int ring, int which) {
     extern __shared__ double smem[];
     __shared__ double red[kLuW + kWaves];
     __shared__ int decision;
     // the factor mode this variant serves in an FP32-LU engine
     constexpr int32_t kMode = sizeof(T) == sizeof(double) ? kLu64 : (kRefine ? kLuRefined32 : kLuPlain32);
-    const int count = s.cnt[ring];
+    int count;
+    const int32_t *list = slot_list(s, which, ring, count);
     const int S = s.S, NP = s.NP;
     for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
-        const int slot = s.act[ring * s.nslots + idx];
+        const int slot = list[idx];
         if (s.ctl[slot].phase != kIter) continue;
         if (s.prec == ABDF_PREC_FP32_LU && s.ctl[slot].lu_mode != kMode) continue;
         double *b = smem;
@@ -422,6 +427,7 @@ __global__ void __launch_bounds__(kBlock) k_control(Slots s, int ring) {
         const int old = (ring + 2) % 3;
         s.cnt[old] = 0;
         s.cnt[3 + old] = 0;
+        s.cnt[7 + old] = 0;
     }
     const int idx = blockIdx.x;
     if (idx >= s.cnt[ring]) return;
@@ -817,6 +823,7 @@ __global__ void __launch_bounds__(kBlock) k_adj_step(Slots s, DeviceNet n, int r
         const int old = (ring + 2) % 3;
         s.cnt[old] = 0;
         s.cnt[3 + old] = 0;
+        s.cnt[7 + old] = 0;
     }
     const int idx = blockIdx.x;
     if (idx >= s.cnt[ring]) return;
@@ -1087,25 +1094,27 @@ hipError_t launch_factor(const Slots &s, const DeviceNet &n, int ring, int grid,
     return LAUNCH_CHECK();
 }
 
-hipError_t launch_newton_rhs(const Slots &s, const DeviceNet &n, int ring, int grid, size_t lds, hipStream_t st) {
+hipError_t launch_newton_rhs(const Slots &s, const DeviceNet &n, int ring, int which, int grid, size_t lds,
+                             hipStream_t st) {
     if (grid == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_newton_rhs, dim3(grid), dim3(kBlock), lds, st, s, n, ring);
+    hipLaunchKernelGGL(k_newton_rhs, dim3(grid), dim3(kBlock), lds, st, s, n, ring, which);
     return LAUNCH_CHECK();
 }
 
-hipError_t launch_newton_solve(const Slots &s, const DeviceNet &n, int ring, int grid, int grid_ref, int grid64,
-                               size_t lds, size_t lds_ref, hipStream_t st) {
+hipError_t launch_newton_solve(const Slots &s, const DeviceNet &n, int ring, int which, int grid, int grid_ref,
+                               int grid64, size_t lds, size_t lds_ref, hipStream_t st) {
     if (grid == 0) return hipSuccess;
     if (s.prec == ABDF_PREC_FP32_LU) {
-        hipLaunchKernelGGL((k_newton_solve<float, false>), dim3(grid), dim3(kBlock), lds, st, s, n, ring);
+        hipLaunchKernelGGL((k_newton_solve<float, false>), dim3(grid), dim3(kBlock), lds, st, s, n, ring, which);
         hipError_t e = LAUNCH_CHECK();
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL((k_newton_solve<float, true>), dim3(grid_ref), dim3(kBlock), lds_ref, st, s, n, ring);
+        hipLaunchKernelGGL((k_newton_solve<float, true>), dim3(grid_ref), dim3(kBlock), lds_ref, st, s, n, ring,
+                           which);
         e = LAUNCH_CHECK();
         if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL((k_newton_solve<double, false>), dim3(s.prec == ABDF_PREC_FP32_LU ? grid64 : grid),
-                       dim3(kBlock), lds, st, s, n, ring);
+                       dim3(kBlock), lds, st, s, n, ring, which);
     return LAUNCH_CHECK();
 }
 

@@ -71,11 +71,13 @@ hipError_t launch_admit(const Slots &s, const DeviceNet &n, const AdmitArgs &a, 
 // for the slots that fell back (grid64, lds); FP64 engines only the latter (grid).
 hipError_t launch_factor(const Slots &s, const DeviceNet &n, int ring, int grid, int grid64, size_t lds,
                          size_t lds32, hipStream_t st);
-hipError_t launch_newton_rhs(const Slots &s, const DeviceNet &n, int ring, int grid, size_t lds, hipStream_t st);
+// Newton kernels take the slot list to work on (kListAll / kListFactor / kListNoFactor).
+hipError_t launch_newton_rhs(const Slots &s, const DeviceNet &n, int ring, int which, int grid, size_t lds,
+                             hipStream_t st);
 // FP32-LU engines launch the plain FP32 (grid), the refining FP32 (grid_ref,
 // lds_ref) and the FP64 (grid64) variants; FP64 engines only the last (grid).
-hipError_t launch_newton_solve(const Slots &s, const DeviceNet &n, int ring, int grid, int grid_ref, int grid64,
-                               size_t lds, size_t lds_ref, hipStream_t st);
+hipError_t launch_newton_solve(const Slots &s, const DeviceNet &n, int ring, int which, int grid, int grid_ref,
+                               int grid64, size_t lds, size_t lds_ref, hipStream_t st);
 hipError_t launch_control(const Slots &s, int ring, int grid, hipStream_t st);
 hipError_t launch_harvest(const Slots &s, const HarvestArgs &h, hipStream_t st);
 
