@@ -348,12 +348,17 @@ enum {
     ABDF_PROF_RHS = 5,      /* Newton residual: rates times abundances, species sums */
     ABDF_PROF_ADJ_SOLVE = 6,  /* reverse sweep: transposed triangular solves */
     ABDF_PROF_ADJ_STEP = 7,   /* reverse sweep: adjoint step update and parameter gradient */
-    ABDF_PROF_KINDS = 8
+    /* Newton residual and correction of the cells that keep their factorisation,
+     * launched on a second stream beside the factorisation kernel; their event
+     * spans include the time spent waiting for compute units it holds. */
+    ABDF_PROF_RHS_SIDE = 8,
+    ABDF_PROF_NEWTON_SIDE = 9,
+    ABDF_PROF_KINDS = 10
 };
 
 typedef struct abdf_profile {
-    int64_t launches[8];    /* kernel launches per family */
-    double ms[8];           /* summed launch durations [ms] per family */
+    int64_t launches[10];   /* kernel launches per family */
+    double ms[10];          /* summed launch durations [ms] per family */
 } abdf_profile;
 
 /* Turns the timers on (nonzero) or off. */

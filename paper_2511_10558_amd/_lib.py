@@ -65,10 +65,11 @@ class ServerInfo(ctypes.Structure):
 
 
 class Profile(ctypes.Structure):
-    _fields_ = [("launches", ctypes.c_int64 * 8), ("ms", ctypes.c_double * 8)]
+    _fields_ = [("launches", ctypes.c_int64 * 10), ("ms", ctypes.c_double * 10)]
 
 
-PROFILE_KINDS = ("admit", "factor", "newton", "control", "harvest", "rhs", "adj_solve", "adj_step")
+PROFILE_KINDS = ("admit", "factor", "newton", "control", "harvest", "rhs", "adj_solve", "adj_step", "rhs_side",
+                 "newton_side")
 
 # name -> (restype, argtypes); mirrors include/astrobdf.h
 SIGNATURES = {

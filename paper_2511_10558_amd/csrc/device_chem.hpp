@@ -101,17 +101,16 @@ __device__ __forceinline__ void jacobian_values(const DeviceNet &n, const double
 // assemble_newton_matrix stores); rows and columns beyond S are the identity's.
 template <typename T>
 struct NewtonMatrixSource {
-    const int32_t *jidx;
-    const double *jv;
+    const int32_t *jidx;   // [NP][NP] entry of J at (i, j), -1 where J is structurally zero
+    const double *jv;      // the entries' values (at least one)
     int S, NP;
     double c;
-    __device__ __forceinline__ T operator()(int i, int j) const {
-        double v = i == j ? 1.0 : 0.0;
-        if (i < S && j < S) {
-            const int e = jidx[size_t(i) * NP + j];
-            if (e >= 0) v = v + (-c * jv[e]);
-        }
-        return T(v);
+    // Entries are read in two passes, every index first and then every value,
+    // so that no load waits behind a condition on an earlier one.
+    __device__ __forceinline__ int32_t handle(int i, int j) const { return jidx[size_t(i) * NP + j]; }
+    __device__ __forceinline__ T value(int32_t e, int i, int j) const {
+        const double jvv = jv[e < 0 ? 0 : e];
+        return T((i == j ? 1.0 : 0.0) + (e >= 0 ? -c * jvv : 0.0));
     }
 };
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <limits>
 
 namespace abdf {
 
@@ -132,6 +133,47 @@ __device__ __forceinline__ void wave_argmax(double &v, int &k) {
     const int hi = __builtin_amdgcn_readlane(__double2hiint(v), 63);
     k = __builtin_amdgcn_readlane(k, 63);
     v = __hiloint2double(hi, lo);
+}
+
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_max_step(double v) {
+    const int lo = __double2loint(v), hi = __double2hiint(v);
+    const int olo = __builtin_amdgcn_update_dpp(lo, lo, CTRL, ROW_MASK, 0xf, false);
+    const int ohi = __builtin_amdgcn_update_dpp(hi, hi, CTRL, ROW_MASK, 0xf, false);
+    return fmax(v, __hiloint2double(ohi, olo));
+}
+
+// Arg-max with the result of wave_argmax for values v >= 0 (v < 0 marks a lane
+// without a candidate; if no lane has one, v < 0 is returned and k is
+// unspecified).  The maximum is reduced alone; the lanes holding it are found
+// by a ballot, and only a tie among several of them reduces the keys.
+__device__ __forceinline__ void wave_argmax_ballot(double &v, int &k) {
+    double m = v;
+    m = dpp_max_step<0xB1, 0xf>(m);
+    m = dpp_max_step<0x4E, 0xf>(m);
+    m = dpp_max_step<0x141, 0xf>(m);
+    m = dpp_max_step<0x140, 0xf>(m);
+    m = dpp_max_step<0x142, 0xa>(m);
+    m = dpp_max_step<0x143, 0xc>(m);
+    {
+        const int lo = __builtin_amdgcn_readlane(__double2loint(m), 63);
+        const int hi = __builtin_amdgcn_readlane(__double2hiint(m), 63);
+        m = __hiloint2double(hi, lo);
+    }
+    if (m < 0.0) {
+        v = m;
+        return;
+    }
+    const unsigned long long hit = __ballot(v == m);
+    if (__popcll(hit) == 1) {
+        k = __builtin_amdgcn_readlane(k, __ffsll(static_cast<unsigned long long>(hit)) - 1);
+    } else {
+        double tv = v == m ? 1.0 : -1.0;
+        int tk = v == m ? k : 0x7fffffff;
+        wave_argmax(tv, tk);
+        k = tk;
+    }
+    v = m;
 }
 
 // Sum over the workgroup, identical on every thread; fixed reduction order.

@@ -64,6 +64,7 @@ __device__ inline int tile_row_reg<float>(int t) { return t & 3; }
 // LDS layout of lu_factor_left (element type T for the staging region).
 constexpr int kPanLd = 17;        // row stride of the 16-column sub-panel buffer
 constexpr int kU12Ld = 49;        // row stride of the 16 x 48 sub-panel U block
+constexpr int kCrowLd = 17;       // candidate pivot row: 16 entries and the pivot's reciprocal
 template <typename T>
 __host__ __device__ constexpr size_t lu2_work_elems(int NP) {
     return size_t(NP) * kPanLd + 16 * kU12Ld > 3 * size_t(kLuW) * kLdb + 1536
@@ -75,7 +76,7 @@ __host__ __device__ constexpr size_t lu2_lds_bytes(int NP) {
     return 5 * size_t(NP) * sizeof(int32_t)                        // perm, sto, pos_log, log_pos, pidx
            + kLuW * sizeof(int32_t)                                // piv_pos
            + 2 * kLuWaves * (sizeof(double) + sizeof(int32_t))     // arg-max partials, double-buffered
-           + 2 * kLuWaves * 16 * sizeof(T) + 16                    // candidate pivot rows, double-buffered
+           + 2 * kLuWaves * kCrowLd * sizeof(T) + 16               // candidate pivot rows, double-buffered
            + lu2_work_elems<T>(NP) * sizeof(T) + 64;
 }
 
@@ -168,16 +169,20 @@ __device__ __forceinline__ void diag_inverses(const T *Cb, int W, T *D, T *Xb, T
     for (int e = h; e < 64 * 64; e += HALF) D[(upper ? kLuW * kLuW : 0) + e] = Z[(e >> 6) * kLdb + (e & 63)];
 }
 
-// Entries of the matrix to factor as stored in A (storage row, column).
+// Entries of the matrix to factor as stored in A (storage row, column).  A
+// source yields an entry in two steps, handle(row, col) and then
+// value(handle, row, col), so that the gather can issue every handle load of a
+// tile before the value loads that depend on them.
 template <typename T>
 struct DenseSource {
     const T *A;
     int NP;
-    __device__ __forceinline__ T operator()(int row, int col) const { return A[size_t(row) * NP + col]; }
+    __device__ __forceinline__ int32_t handle(int row, int col) const { return row * NP + col; }
+    __device__ __forceinline__ T value(int32_t h, int, int) const { return A[h]; }
 };
 
-// Factors the matrix whose entries src(row, col) yields (read once, when its
-// block column is gathered) into A: A needs no initial contents.
+// Factors the matrix whose entries src yields (read once, when its block
+// column is gathered) into A: A needs no initial contents.
 template <typename T, typename Src>
 __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_t *__restrict__ perm_out,
                                                T *__restrict__ dinv, int32_t *info, unsigned char *smem,
@@ -198,9 +203,10 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
     int32_t *piv_pos = pidx + NP;                          // pivot column -> position
     double *redv = reinterpret_cast<double *>(piv_pos + kLuW);   // [2][waves]
     int32_t *redi = reinterpret_cast<int32_t *>(redv + 2 * kLuWaves);
-    int32_t *rwave = redi + 2 * kLuWaves;                        // [2] wave holding logical row r
-    T *crow = reinterpret_cast<T *>(rwave + 4);                  // [2][waves][16] candidate rows
-    T *work = crow + 2 * kLuWaves * 16;
+    int32_t *rwave = redi + 2 * kLuWaves;                        // [2] wave holding logical row r;
+                                                                 // [2] first zero pivot (1-based) or INT_MAX
+    T *crow = reinterpret_cast<T *>(rwave + 4);                  // [2][waves][kCrowLd] candidate rows
+    T *work = crow + 2 * kLuWaves * kCrowLd;
     T *Cb = work;                                          // [64][kLdb]   (left-looking, inverses)
     T *Ub = Cb + kLuW * kLdb;                              // [64][kLdb]
     T *Xb = Ub + kLuW * kLdb;                              // [64][kLdb]
@@ -208,7 +214,7 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
     T *U12 = P + size_t(NP) * kPanLd;                      // [16][kU12Ld]
 
     for (int i = tid; i < NP; i += kLuThreads) perm[i] = i;
-    int first_zero = 0;
+    if (tid == 0) rwave[2] = 0x7fffffff;
     __syncthreads();
 
     for (int j = 0; j < NB; ++j) {
@@ -222,22 +228,28 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
             pidx[q] = -1;
         }
         acc_t acc[kSlots][4];
-        // 1. gather the block column (positions = logical rows at this point)
+        // 1. gather the block column (positions = logical rows at this point),
+        //    a row tile at a time: its 16 handles, then its 16 values.  Tiles
+        //    outside the matrix read column c0 + lc of row 0 and are zeroed.
 #pragma unroll
         for (int s = 0; s < kSlots; ++s) {
             const int rt = wave + kLuWaves * s;
+            int32_t hnd[4][4];
+            int srow[4];
 #pragma unroll
-            for (int ct = 0; ct < 4; ++ct) {
+            for (int v = 0; v < 4; ++v) srow[v] = rt < RT ? perm[16 * rt + M::row(lane, v)] : 0;
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+                for (int v = 0; v < 4; ++v)
+                    hnd[ct][v] = src.handle(srow[v], c0 + 16 * (ct < CTj ? ct : 0) + lc);
+#pragma unroll
+            for (int ct = 0; ct < 4; ++ct)
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
-                    T val = T(0);
-                    if (rt < RT && ct < CTj) {
-                        const int row = 16 * rt + M::row(lane, v);
-                        val = src(perm[row], c0 + 16 * ct + lc);
-                    }
-                    acc[s][ct][v] = val;
+                    const T val = src.value(hnd[ct][v], srow[v], c0 + 16 * ct + lc);
+                    acc[s][ct][v] = (rt < RT && ct < CTj) ? val : T(0);
                 }
-            }
         }
         // 2. updates from the earlier block columns
         for (int i = 0; i < j; ++i) {
@@ -329,6 +341,12 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
             const int q = tid;
             bool active = q >= c0 && q < NP && pidx[q] < 0;
             const bool participated = active;
+            // a wave without unpivoted rows only takes part in the barriers
+            const bool busy = __ballot(active) != 0;
+            if (!busy && lane == 0) {
+                redv[wave] = -1.0;
+                redv[kLuWaves + wave] = -1.0;
+            }
             int mylog = active ? pos_log[q] : 0x7fffffff;
             T x[16];
 #pragma unroll
@@ -338,43 +356,61 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
                 const int gc = 16 * sp + c;
                 const int r = c0 + gc;
                 const int buf = c & 1;
-                {
+                if (busy) {
                     const double ax = fabs(double(x[c]));
                     double bv = (active && ax == ax) ? ax : -1.0;   // NaN never wins
-                    int bl = active ? mylog : 0x7fffffff;
-                    wave_argmax(bv, bl);
+                    int bl = mylog;
+                    wave_argmax_ballot(bv, bl);
                     if (lane == 0) { redv[buf * kLuWaves + wave] = bv; redi[buf * kLuWaves + wave] = bl; }
                     if (active && mylog == r) rwave[buf] = wave;
-                    // the wave's candidate row (or row r, kept when nothing is finite)
+                    // the wave's candidate row (or row r, kept when nothing is
+                    // finite) with the reciprocal of its entry in column c, or 0
+                    // where that is below the smallest normal number (then the
+                    // multipliers are formed by division, as LAPACK does)
                     if (active && mylog == (bv < 0.0 ? r : bl)) {
+                        T *cr = crow + (buf * kLuWaves + wave) * kCrowLd;
 #pragma unroll
-                        for (int cc = c; cc < 16; ++cc) crow[(buf * kLuWaves + wave) * 16 + cc] = x[cc];
+                        for (int cc = c; cc < 16; ++cc) cr[cc] = x[cc];
+                        cr[16] = fabs(x[c]) >= std::numeric_limits<T>::min() ? T(1) / x[c] : T(0);
                     }
                 }
                 __syncthreads();
-                // cross-wave arg-max: lane w < 8 holds wave w's partial, key =
-                // logical row * 8 + wave; three DPP steps reduce lanes 0..7
-                double fv = lane < kLuWaves ? redv[buf * kLuWaves + lane] : -2.0;
-                int fk = 0x7fffffff;
-                if (lane < kLuWaves && redi[buf * kLuWaves + lane] != 0x7fffffff)
-                    fk = redi[buf * kLuWaves + lane] * 8 + lane;
-                dpp_argmax_step<0xB1, 0xf>(fv, fk);    // quad_perm [1,0,3,2]
-                dpp_argmax_step<0x4E, 0xf>(fv, fk);    // quad_perm [2,3,0,1]
-                dpp_argmax_step<0x141, 0xf>(fv, fk);   // row_half_mirror
+                if (!busy) continue;
+                // cross-wave arg-max: lane w < 8 holds wave w's partial; ties go
+                // to the smaller logical row
+                int lp, wv;
                 {
-                    const int lo = __builtin_amdgcn_readlane(__double2loint(fv), 0);
-                    const int hi = __builtin_amdgcn_readlane(__double2hiint(fv), 0);
-                    fk = __builtin_amdgcn_readlane(fk, 0);
-                    fv = __hiloint2double(hi, lo);
+                    const double fv = lane < kLuWaves ? redv[buf * kLuWaves + lane] : -2.0;
+                    const int fi = lane < kLuWaves ? redi[buf * kLuWaves + lane] : 0x7fffffff;
+                    double m = dpp_max_step<0xB1, 0xf>(fv);    // quad_perm [1,0,3,2]
+                    m = dpp_max_step<0x4E, 0xf>(m);            // quad_perm [2,3,0,1]
+                    m = dpp_max_step<0x141, 0xf>(m);           // row_half_mirror: lanes 0..7 hold the max
+                    {
+                        const int lo = __builtin_amdgcn_readlane(__double2loint(m), 0);
+                        const int hi = __builtin_amdgcn_readlane(__double2hiint(m), 0);
+                        m = __hiloint2double(hi, lo);
+                    }
+                    if (m < 0.0) {          // no finite candidate: keep logical row r
+                        lp = r;
+                        wv = rwave[buf];
+                    } else {
+                        const unsigned long long hit = __ballot(lane < kLuWaves && fv == m);
+                        if (__popcll(hit) == 1) {
+                            wv = __ffsll(static_cast<unsigned long long>(hit)) - 1;
+                            lp = __builtin_amdgcn_readlane(fi, wv);
+                        } else {
+                            double tv = (lane < kLuWaves && fv == m) ? 1.0 : -1.0;
+                            int tk = (lane < kLuWaves && fv == m) ? fi * 8 + lane : 0x7fffffff;
+                            wave_argmax(tv, tk);
+                            lp = tk >> 3;
+                            wv = tk & 7;
+                        }
+                    }
                 }
-                int lp = fk >> 3, wv = fk & 7;
-                if (fv < 0.0) {          // no finite candidate: keep logical row r
-                    lp = r;
-                    wv = rwave[buf];
-                }
-                const T *urow = crow + (buf * kLuWaves + wv) * 16;
+                const T *urow = crow + (buf * kLuWaves + wv) * kCrowLd;
                 const T piv = urow[c];
-                if (tid == 0 && piv == T(0) && first_zero == 0) first_zero = r + 1;
+                const T rinv = urow[16];
+                if (lane == 0 && piv == T(0)) atomicMin(&rwave[2], r + 1);
                 if (active) {
                     if (mylog == lp) {               // this position becomes logical row r
                         mylog = r;
@@ -383,7 +419,11 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
                         piv_pos[gc] = q;
                     } else {
                         if (mylog == r) mylog = lp;  // row r moves to the pivot's old logical index
-                        const T l = piv != T(0) ? x[c] / piv : x[c];
+                        T l;
+                        if (rinv != T(0))
+                            l = x[c] * rinv;
+                        else
+                            l = piv != T(0) ? x[c] / piv : x[c];
                         x[c] = l;
 #pragma unroll
                         for (int cc = c + 1; cc < 16; ++cc) x[cc] -= l * urow[cc];
@@ -502,7 +542,7 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
         __syncthreads();
     }
     for (int i = tid; i < NP; i += kLuThreads) perm_out[i] = perm[i];
-    if (tid == 0 && info) *info = first_zero;
+    if (tid == 0 && info) *info = rwave[2] == 0x7fffffff ? 0 : rwave[2];
 }
 
 // Solves (P^T L U) z = b for one matrix factored by lu_factor_left, with the

@@ -34,8 +34,8 @@ size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 namespace {
 std::atomic<bool> g_prof_on{false};
 std::mutex g_prof_mu;
-int64_t g_prof_launches[8];
-double g_prof_ms[8];
+int64_t g_prof_launches[ABDF_PROF_KINDS];
+double g_prof_ms[ABDF_PROF_KINDS];
 }  // namespace
 
 bool Profiler::on() { return g_prof_on.load(std::memory_order_relaxed); }
@@ -47,7 +47,7 @@ void Profiler::add(int kind, double ms) {
 }
 void Profiler::read(int64_t *launches, double *ms, bool reset) {
     std::lock_guard<std::mutex> l(g_prof_mu);
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < ABDF_PROF_KINDS; ++i) {
         launches[i] = g_prof_launches[i];
         ms[i] = g_prof_ms[i];
         if (reset) { g_prof_launches[i] = 0; g_prof_ms[i] = 0.0; }
@@ -120,7 +120,7 @@ size_t Engine::bytes_per_slot(const DeviceNet &dn, int prec) {
     (void)prec;
     const size_t S = dn.S, R = dn.R, NP = dn.NP;
     return sizeof(SlotCtl) + 5 * sizeof(double) + R * sizeof(double) + kDRows * S * sizeof(double) +
-           6 * S * sizeof(double) + size_t(dn.nnzJ) * sizeof(double) + lu_bytes(int(NP), ABDF_PREC_FP64) +
+           6 * S * sizeof(double) + size_t(std::max(dn.nnzJ, 1)) * sizeof(double) + lu_bytes(int(NP), ABDF_PREC_FP64) +
            dinv_bytes(int(NP), ABDF_PREC_FP64) +
            NP * sizeof(int32_t) + 7 * sizeof(int32_t) + sizeof(long long);
 }
@@ -135,7 +135,7 @@ int Engine::init(int nslots, std::string &err) {
         {&ctl, n * sizeof(SlotCtl)}, {&phi, n * 5 * sizeof(double)}, {&k, n * R * sizeof(double)},
         {&D, n * kDRows * S * sizeof(double)}, {&x, n * S * sizeof(double)}, {&d, n * S * sizeof(double)},
         {&psi, n * S * sizeof(double)}, {&scl, n * S * sizeof(double)}, {&xJ, n * S * sizeof(double)},
-        {&rb, n * S * sizeof(double)}, {&jval, n * size_t(dn_.nnzJ) * sizeof(double)},
+        {&rb, n * S * sizeof(double)}, {&jval, n * size_t(std::max(dn_.nnzJ, 1)) * sizeof(double)},
         {&lu, n * lu_stride}, {&dinv, n * dinv_stride}, {&perm, n * NP * sizeof(int32_t)}, {&act, 3 * n * sizeof(int32_t)},
         {&lul, 3 * n * sizeof(int32_t)}, {&nol, 3 * n * sizeof(int32_t)}, {&fin, n * sizeof(int32_t)},
         {&cnt, kCountSlots * sizeof(int32_t)},
@@ -265,12 +265,12 @@ int Engine::newton_iterations(int which, hipStream_t st, std::string &err) {
     for (int m = 0; m < kNewtonMaxIter; ++m) {
         hipEvent_t t0 = timer_begin(st);
         HIP_TRY(launch_newton_rhs(s_, dn_, ring_, which, std::min(bound_, grid_newton_max_), lds_newton_, st));
-        timer_end(ABDF_PROF_RHS, t0, st);
+        timer_end(which == kListNoFactor ? ABDF_PROF_RHS_SIDE : ABDF_PROF_RHS, t0, st);
         t0 = timer_begin(st);
         HIP_TRY(launch_newton_solve(s_, dn_, ring_, which, std::min(bound_, grid_solve_max_),
                                     std::min(bound_, grid_solve_ref_max_), std::min(bound_, grid_solve64_max_),
                                     lds_solve_, lds_solve32_, st));
-        timer_end(ABDF_PROF_NEWTON, t0, st);
+        timer_end(which == kListNoFactor ? ABDF_PROF_NEWTON_SIDE : ABDF_PROF_NEWTON, t0, st);
     }
     return ABDF_OK;
 }

@@ -1026,8 +1026,18 @@ __global__ void k_selftest(int *bad) {
             const int ki = (i * 29 + pat) % 64;
             if (vi > bv || (vi == bv && ki < bk)) { bv = vi; bk = ki; }
         }
+        double v2 = v;
+        int k2 = k;
         wave_argmax(v, k);
         nb += (v != bv) + (k != bk);
+        wave_argmax_ballot(v2, k2);
+        nb += (v2 != bv) + (k2 != bk);
+    }
+    {
+        double v = -1.0;     // no lane with a candidate
+        int k = l;
+        wave_argmax_ballot(v, k);
+        nb += !(v < 0.0);
     }
     atomicAdd(bad, nb);
 }

@@ -33,13 +33,14 @@ def source_hash():
 
 
 def short(name):
-    for key in ("k_factor<double>", "k_factor<float>", "k_newton_solve<double>", "k_newton_solve<float>",
-                "k_newton_rhs", "k_control", "k_admit", "k_harvest"):
-        if key in name:
-            return key
+    """Kernel name without return type, namespace and argument list."""
     if "MulFunctor" in name:
         return "reference multiply"
-    return name[:40]
+    base = name.split("(")[0].strip()
+    if base.startswith("void "):
+        base = base[5:]
+    base = base.replace("abdf::", "")
+    return base[:48]
 
 
 def counters(path):
@@ -86,7 +87,8 @@ def main():
         out.append(f"| {k} | {f.get(k, (0, 0))[0]} | {fb/2**20:.1f} | {wb/2**20:.1f} |")
         traffic[k] = fb + wb
     per_lu = traffic.get("k_factor<double>", 0.0) / max(1, work["factorisations"])
-    per_it = traffic.get("k_newton_solve<double>", 0.0) / max(1, work["newton_iterations"])
+    per_it = sum(v for k, v in traffic.items() if k.startswith("k_newton_solve<double")) / \
+        max(1, work["newton_iterations"])
     out += ["", f"Per factorisation (k_factor, assembly + LU): {per_lu/2**20:.2f} MiB of HBM traffic; "
                 f"per Newton solve (k_newton_solve): {per_it/2**20:.3f} MiB."]
     open(os.path.join(HERE, "kernel_stats_net500.md"), "w").write("\n".join(out) + "\n")
