@@ -90,7 +90,7 @@ __host__ __device__ constexpr size_t lu2_dinv_elems(int NP) {
 // held in LDS (leading dimension kLdb), written to D[0] and D[1] (64 x 64
 // row-major, global).  The first half of the threads forms inv(L), the second
 // inv(U), block-recursively on 16 x 16 blocks: the diagonal blocks by
-// substitution (4 lanes per column), then the off-diagonal blocks level by level,
+// substitution (one lane per column), then the off-diagonal blocks level by level,
 // X_ij = -X_ii sum_k L_ik X_kj (lower) and Y_ij = -Y_ii sum_k U_ik Y_kj (upper).
 // Xb, Yb: 64 x kLdb LDS outputs; Tb: 2 x 768 LDS scratch.  Every thread of
 // the workgroup must call this (it contains barriers).
@@ -106,35 +106,40 @@ __device__ __forceinline__ void diag_inverses(const T *Cb, int W, T *D, T *Xb, T
     // zero the outputs
     for (int e = h; e < 64 * 64; e += HALF) Z[(e >> 6) * kLdb + (e & 63)] = T(0);
     __syncthreads();
-    // diagonal 16 x 16 blocks
-    {
-        const int ct = h >> 2, t = h & 3;
-        const int b = ct >> 4, kk = 16 * b + (ct & 15);
+    // diagonal 16 x 16 blocks: one lane per column, the column's entries in
+    // registers, by substitution (no barrier, no shuffle); lanes h < 64 of
+    // each half, lane h holding column h of the 64 x 64 block
+    if (h < 64) {
+        const int b = h >> 4, kc = h & 15;
         if (b < nb) {
+            const T *Bd = Cb + 16 * b * kLdb + 16 * b;     // the diagonal block, leading dimension kLdb
+            double xs[16];
             if (!upper) {
-                for (int i = 16 * b; i < 16 * b + 16; ++i) {
+#pragma unroll
+                for (int t = 0; t < 16; ++t) {
                     double acc = 0.0;
-                    for (int m = kk + t; m < i; m += 4) acc += double(Cb[i * kLdb + m]) * double(Z[m * kLdb + kk]);
-                    acc += __shfl_xor(acc, 1);
-                    acc += __shfl_xor(acc, 2);
-                    if (t == 0 && i >= kk) Z[i * kLdb + kk] = T(i == kk ? 1.0 : -acc);
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+                    for (int m = 0; m < t; ++m) {
+                        const double p = double(Bd[t * kLdb + m]) * xs[m];
+                        acc = m >= kc ? acc + p : acc;
+                    }
+                    xs[t] = t < kc ? 0.0 : (t == kc ? 1.0 : -acc);
                 }
             } else {
-                for (int i = 16 * b + 15; i >= 16 * b; --i) {
+#pragma unroll
+                for (int t = 15; t >= 0; --t) {
                     double acc = 0.0;
-                    for (int m = i + 1 + t; m <= kk; m += 4) acc += double(Cb[i * kLdb + m]) * double(Z[m * kLdb + kk]);
-                    acc += __shfl_xor(acc, 1);
-                    acc += __shfl_xor(acc, 2);
-                    const double d = double(Cb[i * kLdb + i]);
-                    if (t == 0 && i <= kk) Z[i * kLdb + kk] = T(i == kk ? 1.0 / d : -acc / d);
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+                    for (int m = t + 1; m < 16; ++m) {
+                        const double p = double(Bd[t * kLdb + m]) * xs[m];
+                        acc = m <= kc ? acc + p : acc;
+                    }
+                    const double d = double(Bd[t * kLdb + t]);
+                    xs[t] = t > kc ? 0.0 : (t == kc ? 1.0 / d : -acc / d);
                 }
             }
+#pragma unroll
+            for (int t = 0; t < 16; ++t) Z[(16 * b + t) * kLdb + 16 * b + kc] = T(xs[t]);
         }
     }
     __syncthreads();
@@ -143,15 +148,24 @@ __device__ __forceinline__ void diag_inverses(const T *Cb, int W, T *D, T *Xb, T
         const int cnt = (nb - d) * 256;
         for (int e = h; e < cnt; e += HALF) {
             const int bi = e >> 8, r = (e >> 4) & 15, c = e & 15;
+            // lower: block (bi + d, bi), sum over columns 16 bi .. 16 (bi + d) - 1;
+            // upper: block (bi, bi + d), sum over columns 16 (bi + 1) .. 16 (bi + d) + 15;
+            // d blocks of 16 terms either way, in ascending order
+            const int i = upper ? bi : bi + d, jb = upper ? bi + d : bi;
+            const int mb = upper ? 16 * (bi + 1) : 16 * bi;
+            const T *crow_i = Cb + (16 * i + r) * kLdb;
+            const T *zcol = Z + 16 * jb + c;
             double acc = 0.0;
-            if (!upper) {
-                const int i = bi + d, jb = bi;   // block (i, jb), i > jb
-                for (int m = 16 * jb; m < 16 * i; ++m)
-                    acc += double(Cb[(16 * i + r) * kLdb + m]) * double(Z[m * kLdb + 16 * jb + c]);
-            } else {
-                const int i = bi, jb = bi + d;   // block (i, jb), i < jb
-                for (int m = 16 * (i + 1); m < 16 * jb + 16; ++m)
-                    acc += double(Cb[(16 * i + r) * kLdb + m]) * double(Z[m * kLdb + 16 * jb + c]);
+            for (int kb = 0; kb < d; ++kb) {
+                const int m0 = mb + 16 * kb;
+                T cv[16], zv[16];
+#pragma unroll
+                for (int mm = 0; mm < 16; ++mm) {
+                    cv[mm] = crow_i[m0 + mm];
+                    zv[mm] = zcol[(m0 + mm) * kLdb];
+                }
+#pragma unroll
+                for (int mm = 0; mm < 16; ++mm) acc += double(cv[mm]) * double(zv[mm]);
             }
             Tz[e] = T(acc);
         }
@@ -159,9 +173,15 @@ __device__ __forceinline__ void diag_inverses(const T *Cb, int W, T *D, T *Xb, T
         for (int e = h; e < cnt; e += HALF) {
             const int bi = e >> 8, r = (e >> 4) & 15, c = e & 15;
             const int i = upper ? bi : bi + d, jb = upper ? bi + d : bi;
+            T zv[16], tv[16];
+#pragma unroll
+            for (int m = 0; m < 16; ++m) {
+                zv[m] = Z[(16 * i + r) * kLdb + 16 * i + m];
+                tv[m] = Tz[(bi << 8) + (m << 4) + c];
+            }
             double acc = 0.0;
-            for (int m = 0; m < 16; ++m)
-                acc += double(Z[(16 * i + r) * kLdb + 16 * i + m]) * double(Tz[(bi << 8) + (m << 4) + c]);
+#pragma unroll
+            for (int m = 0; m < 16; ++m) acc += double(zv[m]) * double(tv[m]);
             Z[(16 * i + r) * kLdb + 16 * jb + c] = T(-acc);
         }
         __syncthreads();
@@ -526,8 +546,8 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
                             if (lr >= 0 && lr < Wj) Cb[lr * kLdb + 16 * ct + lc] = acc[s][ct][v];
                         }
         }
-        __syncthreads();
-        diag_inverses<T>(Cb, Wj, dinv + size_t(j) * 2 * kLuW * kLuW, Xb, Ub, Xb + kLuW * kLdb);
+        // the block column goes back first, so that the accumulators are free
+        // while the inverses are formed
 #pragma unroll
         for (int s = 0; s < kSlots; ++s) {
             const int rt = wave + kLuWaves * s;
@@ -539,6 +559,8 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
                         for (int v = 0; v < 4; ++v)
                             A[size_t(sto[16 * rt + M::row(lane, v)]) * NP + c0 + 16 * ct + lc] = acc[s][ct][v];
         }
+        __syncthreads();
+        diag_inverses<T>(Cb, Wj, dinv + size_t(j) * 2 * kLuW * kLuW, Xb, Ub, Xb + kLuW * kLdb);
         __syncthreads();
     }
     for (int i = tid; i < NP; i += kLuThreads) perm_out[i] = perm[i];
