@@ -60,13 +60,47 @@ def main():
     out = ["# rocprofv3 kernel statistics: 500-species / 6000-reaction network, 4096 cells, FP64", "",
            "Command (repo root, on the GPU box):", "",
            "    rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o run -- "
-           "python3 bench.py --cells 4096 --steps 1 --warmup 0 --no-cpu-baseline", "",
+           "python3 bench.py --cells 4096 --steps 1 --warmup 0 --no-cpu-baseline --no-compare-fp32", "",
            "| kernel | calls | total ms | average us | % |", "|---|---|---|---|---|"]
     for r in rows:
         if float(r["Percentage"]) < 0.01:
             continue
         out.append(f"| {short(r['Name'])} | {r['Calls']} | {float(r['TotalDurationNs'])/1e6:.1f} | "
                    f"{float(r['AverageNs'])/1e3:.1f} | {float(r['Percentage']):.2f} |")
+    # per hardware queue: the solver's stream and the side stream of the
+    # Newton iterations that run beside the factorisation
+    trace_rows = list(csv.DictReader(open(os.path.join(trace, "run_kernel_trace.csv"))))
+    perq = {}
+    spans = []
+    for r in trace_rows:
+        k = short(r["Kernel_Name"])
+        t0, t1 = int(r["Start_Timestamp"]), int(r["End_Timestamp"])
+        spans.append((t0, t1))
+        key = (k, r["Queue_Id"])
+        n, tot = perq.get(key, (0, 0))
+        perq[key] = (n + 1, tot + (t1 - t0))
+    spans.sort()
+    busy, cs, ce = 0, None, None
+    for a, b in spans:
+        if ce is None or a > ce:
+            if ce is not None:
+                busy += ce - cs
+            cs, ce = a, b
+        else:
+            ce = max(ce, b)
+    if ce is not None:
+        busy += ce - cs
+    out += ["", "Per hardware queue (kernel trace).  Kernels on the second queue are the Newton "
+            "iterations of cells whose factorisation is current; they are launched beside k_factor "
+            "and their spans include the time their workgroups wait for compute units that "
+            "k_factor holds, so their totals overlap the factorisation's.", "",
+            "| kernel | queue | calls | total ms | average us |", "|---|---|---|---|---|"]
+    for (k, q), (n, tot) in sorted(perq.items(), key=lambda kv: -kv[1][1]):
+        if tot < 1e6:
+            continue
+        out.append(f"| {k} | {q} | {n} | {tot / 1e6:.1f} | {tot / n / 1e3:.1f} |")
+    out += ["", f"GPU busy (union of all kernel spans): {busy / 1e6:.1f} ms, of which k_factor "
+                f"{sum(t for (k, q), (n, t) in perq.items() if k.startswith('k_factor')) / 1e6:.1f} ms."]
     f = counters(fetch)
     w = counters(write)
     cf = COPY_BYTES / (f["reference multiply"][1] * 1024.0)
