@@ -27,13 +27,22 @@ __device__ inline void cell_rates(const DeviceNet &n, const double *phi, double 
 // out_i = sum_r nu_ir v_r for per-reaction values v (LDS): each species' row of
 // the stoichiometry in segments of up to 32 entries (part[n_seg], LDS), then
 // the segments of a species in order.  Deterministic.
+// A segment's entries are loaded eight at a time before any is used, so the
+// loads are in flight together; the sum still runs entry by entry in order.
 __device__ __forceinline__ void species_gather(const DeviceNet &n, const double *v, double *part, double *out) {
     for (int s = threadIdx.x; s < n.n_seg; s += kBlock) {
         const int e0 = n.seg_beg[s], e1 = n.seg_beg[s + 1];
         double acc = 0.0;
-        for (int e = e0; e < e1; ++e) {
-            const int w = n.f_ent[e];
-            acc += double((w & 7) - 4) * v[w >> 3];
+        for (int eb = e0; eb < e1; eb += 8) {
+            int w[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) w[u] = eb + u < e1 ? n.f_ent[eb + u] : 4;   // 4: coefficient 0, entry 0
+            double vv[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) vv[u] = v[w[u] >> 3];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (eb + u < e1) acc += double((w[u] & 7) - 4) * vv[u];
         }
         part[s] = acc;
     }
@@ -51,12 +60,24 @@ __device__ __forceinline__ void species_gather(const DeviceNet &n, const double 
 // Deterministic: every sum runs in a fixed order.
 __device__ __forceinline__ void cell_rhs(const DeviceNet &n, const double *__restrict__ k, const double *x,
                                 double *rate, double *part, double *f) {
-    for (int r = threadIdx.x; r < n.R; r += kBlock) {
-        const int ab = n.rx_ab[r];
-        const int a = ab & 0xffff, b = (ab >> 16) & 0xffff;
-        double v = k[r] * x[a];
-        if (b != 0xffff) v *= x[b];
-        rate[r] = v;
+    // four reactions per thread per pass, their loads issued before any use
+    for (int r0 = threadIdx.x; r0 < n.R; r0 += 4 * kBlock) {
+        int ab[4];
+        double kr[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int r = r0 + u * kBlock;
+            ab[u] = r < n.R ? n.rx_ab[r] : 0;
+            kr[u] = r < n.R ? k[r] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int r = r0 + u * kBlock;
+            const int a = ab[u] & 0xffff, b = (ab[u] >> 16) & 0xffff;
+            double v = kr[u] * x[a];
+            if (b != 0xffff) v *= x[b];
+            if (r < n.R) rate[r] = v;
+        }
     }
     __syncthreads();
     species_gather(n, rate, part, f);
@@ -68,10 +89,22 @@ __device__ __forceinline__ void cell_rhs(const DeviceNet &n, const double *__res
 // drate[R], part[n_seg] LDS scratch.
 __device__ __forceinline__ void cell_jvp(const DeviceNet &n, const double *__restrict__ k, const double *x,
                                          const double *y, double *drate, double *part, double *out) {
-    for (int r = threadIdx.x; r < n.R; r += kBlock) {
-        const int ab = n.rx_ab[r];
-        const int a = ab & 0xffff, b = (ab >> 16) & 0xffff;
-        drate[r] = b == 0xffff ? k[r] * y[a] : k[r] * (y[a] * x[b] + x[a] * y[b]);
+    for (int r0 = threadIdx.x; r0 < n.R; r0 += 4 * kBlock) {
+        int ab[4];
+        double kr[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int r = r0 + u * kBlock;
+            ab[u] = r < n.R ? n.rx_ab[r] : 0;
+            kr[u] = r < n.R ? k[r] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int r = r0 + u * kBlock;
+            const int a = ab[u] & 0xffff, b = (ab[u] >> 16) & 0xffff;
+            const double v = b == 0xffff ? kr[u] * y[a] : kr[u] * (y[a] * x[b] + x[a] * y[b]);
+            if (r < n.R) drate[r] = v;
+        }
     }
     __syncthreads();
     species_gather(n, drate, part, out);
@@ -83,14 +116,35 @@ __device__ __forceinline__ void cell_jvp(const DeviceNet &n, const double *__res
 template <int NT>
 __device__ __forceinline__ void jacobian_values(const DeviceNet &n, const double *__restrict__ k, const double *x,
                                                 double *jv) {
+    // a nonzero's terms are loaded four at a time before any is used; the sum
+    // still runs term by term in order
     for (int e = threadIdx.x; e < n.nnzJ; e += NT) {
         double v = 0.0;
-        for (int t = n.jterm_ptr[e]; t < n.jterm_ptr[e + 1]; ++t) {
-            const int w = n.jt_rx_other[t];
-            const int other = (w & 0xffff) - 1;
-            double term = n.jt_coef[t] * k[w >> 16];
-            if (other >= 0) term *= x[other];
-            v += term;
+        const int t0 = n.jterm_ptr[e], t1 = n.jterm_ptr[e + 1];
+        for (int tb = t0; tb < t1; tb += 4) {
+            int w[4];
+            double cf[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const bool in = tb + u < t1;
+                w[u] = in ? n.jt_rx_other[tb + u] : 0;
+                cf[u] = in ? n.jt_coef[tb + u] : 0.0;
+            }
+            double kv[4], xv[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int other = (w[u] & 0xffff) - 1;
+                kv[u] = k[w[u] >> 16];
+                xv[u] = x[other >= 0 ? other : 0];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (tb + u < t1) {
+                    double term = cf[u] * kv[u];
+                    if ((w[u] & 0xffff) != 0) term *= xv[u];
+                    v += term;
+                }
+            }
         }
         jv[e] = v;
     }
