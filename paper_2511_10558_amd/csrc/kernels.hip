@@ -41,35 +41,52 @@ __device__ inline double growth(double err, int p) {
 }
 
 // RU = R(rho) R(1) with R(rho)[i][j] = prod_{m=1..i} (m - 1 - rho j) / m, i, j in 0..q.
+// Thread i * 6 + j (< 36) forms entry (i, j): the factors of R(rho)[i][m] and
+// R(1)[m][j] in the order of the recurrence R[i][.] = R[i - 1][.] (i - 1 - rho .) / i,
+// then the sum over m in order.  Static loop bounds keep everything in registers.
 __device__ inline void interp_product(int q, double rho, double *RU) {
-    double Rr[6][6], R1[6][6];
-    for (int j = 0; j <= q; ++j) { Rr[0][j] = 1.0; R1[0][j] = 1.0; }
-    for (int i = 1; i <= q; ++i)
-        for (int j = 0; j <= q; ++j) {
-            Rr[i][j] = Rr[i - 1][j] * (i - 1 - rho * j) / i;
-            R1[i][j] = R1[i - 1][j] * (i - 1 - 1.0 * j) / i;
+    const int t = threadIdx.x;
+    if (t >= 36) return;
+    const int i = t / 6, j = t % 6;
+    if (i > q || j > q) return;
+    double s = 0.0;
+#pragma unroll
+    for (int m = 0; m <= kMaxOrder; ++m) {
+        if (m <= q) {
+            double rr = 1.0, r1 = 1.0;
+#pragma unroll
+            for (int k = 1; k <= kMaxOrder; ++k) {
+                if (k <= i) rr = rr * (k - 1 - rho * m) / k;
+                if (k <= m) r1 = r1 * (k - 1 - 1.0 * j) / k;
+            }
+            s += rr * r1;
         }
-    for (int i = 0; i <= q; ++i)
-        for (int j = 0; j <= q; ++j) {
-            double s = 0.0;
-            for (int m = 0; m <= q; ++m) s += Rr[i][m] * R1[m][j];
-            RU[i * 6 + j] = s;
-        }
+    }
+    RU[i * 6 + j] = s;
 }
 
 // Rows 0..q of D (one slot) from spacing h to rho*h.  Cooperative.
 __device__ __forceinline__ void rescale_D(double *D, int S, int q, double rho, double *RU) {
-    if (threadIdx.x == 0) interp_product(q, rho, RU);
+    interp_product(q, rho, RU);
     __syncthreads();
+    // loops over all kMaxOrder + 1 rows with the rows above q masked, so that
+    // the per-thread arrays stay in registers (a dynamic index would put them
+    // in scratch memory); the sums run in the same order
     for (int i = threadIdx.x; i < S; i += kBlock) {
         double v[kMaxOrder + 1], w[kMaxOrder + 1];
-        for (int j = 0; j <= q; ++j) v[j] = D[j * S + i];
-        for (int a = 0; a <= q; ++a) {
+#pragma unroll
+        for (int j = 0; j <= kMaxOrder; ++j) v[j] = j <= q ? D[j * S + i] : 0.0;
+#pragma unroll
+        for (int a = 0; a <= kMaxOrder; ++a) {
             double s = 0.0;
-            for (int b = 0; b <= q; ++b) s += RU[b * 6 + a] * v[b];
+#pragma unroll
+            for (int b = 0; b <= kMaxOrder; ++b)
+                if (b <= q) s += RU[b * 6 + a] * v[b];
             w[a] = s;
         }
-        for (int j = 0; j <= q; ++j) D[j * S + i] = w[j];
+#pragma unroll
+        for (int j = 0; j <= kMaxOrder; ++j)
+            if (j <= q) D[j * S + i] = w[j];
     }
     __syncthreads();
 }
@@ -123,15 +140,23 @@ __device__ __forceinline__ void begin_attempt(const Slots &s, int slot, SlotCtl 
     if (sh[0] != 0.0) rescale_D(D, S, q, sh[0], RU);
     const double gq = bdf_gamma(q);
     double gam[kMaxOrder + 1];
-    for (int j = 1; j <= q; ++j) gam[j] = bdf_gamma(j);
+#pragma unroll
+    for (int j = 1; j <= kMaxOrder; ++j) gam[j] = bdf_gamma(j);
     const bool refresh = cs.jac_refresh != 0;
     double *x = s.x + size_t(slot) * S, *d = s.d + size_t(slot) * S, *psi = s.psi + size_t(slot) * S;
     double *scl = s.scl + size_t(slot) * S, *xJ = s.xJ + size_t(slot) * S;
     for (int i = threadIdx.x; i < S; i += kBlock) {
-        double xp = D[i];
-        for (int j = 1; j <= q; ++j) xp = xp + D[j * S + i];
+        double dj[kMaxOrder + 1];
+#pragma unroll
+        for (int j = 0; j <= kMaxOrder; ++j) dj[j] = j <= q ? D[j * S + i] : 0.0;
+        double xp = dj[0];
+#pragma unroll
+        for (int j = 1; j <= kMaxOrder; ++j)
+            if (j <= q) xp = xp + dj[j];
         double ps = 0.0;
-        for (int j = 1; j <= q; ++j) ps = ps + gam[j] * D[j * S + i];
+#pragma unroll
+        for (int j = 1; j <= kMaxOrder; ++j)
+            if (j <= q) ps = ps + gam[j] * dj[j];
         ps = ps / gq;
         x[i] = xp;
         d[i] = 0.0;
@@ -510,15 +535,34 @@ __global__ void __launch_bounds__(kBlock) k_control(Slots s, int ring) {
     bool nonfinite = false;
     for (int i = threadIdx.x; i < S; i += kBlock) {
         const double sc = atol + rtol * fmax(fabs(D[i]), fabs(x[i]));
+        // rows 0..q+2 of the difference table, with every index static (masks
+        // and selects instead of v[q + 1] etc.) so that v stays in registers
         double v[kDRows];
-        for (int j = 0; j <= q + 1; ++j) v[j] = D[j * S + i];
+#pragma unroll
+        for (int j = 0; j < kDRows; ++j) v[j] = j <= q + 1 ? D[j * S + i] : 0.0;
         const double di = d[i];
-        v[q + 2] = di - v[q + 1];
-        v[q + 1] = di;
-        for (int j = q; j >= 0; --j) v[j] = v[j] + v[j + 1];
-        for (int j = 0; j <= q + 2; ++j) D[j * S + i] = v[j];
+        double vq1 = 0.0;
+#pragma unroll
+        for (int j = 0; j < kDRows; ++j) vq1 = j == q + 1 ? v[j] : vq1;
+#pragma unroll
+        for (int j = 0; j < kDRows; ++j) {
+            if (j == q + 2) v[j] = di - vq1;
+            if (j == q + 1) v[j] = di;
+        }
+#pragma unroll
+        for (int j = kDRows - 2; j >= 0; --j)
+            if (j <= q) v[j] = v[j] + v[j + 1];
+#pragma unroll
+        for (int j = 0; j < kDRows; ++j)
+            if (j <= q + 2) D[j * S + i] = v[j];
         if (tx) tx[i] = v[0];
-        const double a1 = em_c * v[q] / sc, a2 = ep_c * v[q + 2] / sc;
+        double vq = 0.0, vq2 = 0.0;
+#pragma unroll
+        for (int j = 0; j < kDRows; ++j) {
+            vq = j == q ? v[j] : vq;
+            vq2 = j == q + 2 ? v[j] : vq2;
+        }
+        const double a1 = em_c * vq / sc, a2 = ep_c * vq2 / sc;
         am += a1 * a1;
         ap += a2 * a2;
         nonfinite |= !isfinite(v[0]);
@@ -641,17 +685,23 @@ __device__ __forceinline__ double nu_dot(const DeviceNet &n, const double *v, in
 
 // Reverse of rescale_D: lambda_old[b] = sum_a RU[b][a] lambda_new[a], rows 0..q.
 __device__ __forceinline__ void rescale_adjoint(double *L, int S, int q, double rho, double *RU) {
-    if (threadIdx.x == 0) interp_product(q, rho, RU);
+    interp_product(q, rho, RU);
     __syncthreads();
     for (int i = threadIdx.x; i < S; i += kBlock) {
         double v[kMaxOrder + 1], w[kMaxOrder + 1];
-        for (int j = 0; j <= q; ++j) v[j] = L[j * S + i];
-        for (int b = 0; b <= q; ++b) {
+#pragma unroll
+        for (int j = 0; j <= kMaxOrder; ++j) v[j] = j <= q ? L[j * S + i] : 0.0;
+#pragma unroll
+        for (int b = 0; b <= kMaxOrder; ++b) {
             double acc = 0.0;
-            for (int a = 0; a <= q; ++a) acc += RU[b * 6 + a] * v[a];
+#pragma unroll
+            for (int a = 0; a <= kMaxOrder; ++a)
+                if (a <= q) acc += RU[b * 6 + a] * v[a];
             w[b] = acc;
         }
-        for (int j = 0; j <= q; ++j) L[j * S + i] = w[j];
+#pragma unroll
+        for (int j = 0; j <= kMaxOrder; ++j)
+            if (j <= q) L[j * S + i] = w[j];
     }
     __syncthreads();
 }
