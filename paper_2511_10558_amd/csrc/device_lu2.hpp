@@ -445,8 +445,20 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
                         else
                             l = piv != T(0) ? x[c] / piv : x[c];
                         x[c] = l;
+                        // the pivot row in groups of four entries, each group's
+                        // loads issued together before its updates
 #pragma unroll
-                        for (int cc = c + 1; cc < 16; ++cc) x[cc] -= l * urow[cc];
+                        for (int cb = c + 1; cb < 16; cb += 4) {
+                            T uv[4];
+#pragma unroll
+                            for (int u = 0; u < 4; ++u)
+                                if (cb + u < 16) uv[u] = urow[cb + u];
+                            __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);   // the group's LDS reads
+                            __builtin_amdgcn_sched_group_barrier(0x002, 8, 0);   // then VALU
+#pragma unroll
+                            for (int u = 0; u < 4; ++u)
+                                if (cb + u < 16) x[cb + u] -= l * uv[u];
+                        }
                     }
                 }
             }
