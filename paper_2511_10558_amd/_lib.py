@@ -126,6 +126,10 @@ def lib():
     if _LIB is None:
         if not os.path.exists(LIB_PATH):
             raise LibraryMissing(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+        # torch first: its HIP runtime (soname libamdhip64.so.7) is then the one
+        # this library binds to.  Loaded the other way round, torch would bring a
+        # second runtime to which this library's device pointers are unknown.
+        import torch  # noqa: F401
         L = ctypes.CDLL(LIB_PATH)
         for name, (res, args) in SIGNATURES.items():
             fn = getattr(L, name)
