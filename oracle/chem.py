@@ -37,6 +37,43 @@ def rate_coefficients(net, T, n_H, A_V, zeta, G0) -> np.ndarray:
     return k
 
 
+PHYS_PARAMS = ("T", "n_H", "A_V", "zeta", "G0")
+
+
+def log_rate_derivatives(net, T, n_H, A_V, zeta, G0) -> np.ndarray:
+    """d log k_r / d phi_j (R x 5) for phi = (T, n_H, A_V, zeta, G0), from the
+    rate laws of rate_coefficients:
+
+    two-body:   log k = log alpha + beta log(T/300) - gamma/T + log n_H
+                -> d/dT = beta/T + gamma/T^2, d/dn_H = 1/n_H
+    cosmic ray: log k = log alpha + log zeta -> d/dzeta = 1/zeta
+    photo:      log k = log alpha + log G0 - gamma A_V
+                -> d/dA_V = -gamma, d/dG0 = 1/G0
+    """
+    D = np.zeros((net.n_reactions, 5))
+    for r in range(net.n_reactions):
+        b, g = net.beta[r], net.gamma[r]
+        t = net.rtype[r]
+        if t == TWO_BODY:
+            D[r, 0] = b / T + g / T ** 2
+            D[r, 1] = 1.0 / n_H
+        elif t == COSMIC_RAY:
+            D[r, 3] = 1.0 / zeta
+        elif t == PHOTO:
+            D[r, 2] = -g
+            D[r, 4] = 1.0 / G0
+        else:
+            raise ValueError(f"unknown reaction type {t}")
+    return D
+
+
+def phys_gradient(net, cell: dict, g_log_alpha) -> np.ndarray:
+    """dL/dphi (5) of one cell from its dL/dlog alpha (R).  The parameters enter
+    the rate equations only through the coefficients k_r = alpha_r h_r(phi), so
+    dL/dlog k_r = dL/dlog alpha_r and dL/dphi_j = sum_r dL/dlog k_r d log k_r / d phi_j."""
+    return log_rate_derivatives(net, **cell).T @ np.asarray(g_log_alpha, dtype=float)
+
+
 def stoichiometry(net) -> sp.csr_matrix:
     """nu (S x R): count of species i among products minus among reactants."""
     S, R = net.n_species, net.n_reactions

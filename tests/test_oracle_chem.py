@@ -148,3 +148,22 @@ def test_df_dlogalpha_matches_finite_difference():
         fd = (chem.Chemistry(net, kp).f(x) - chem.Chemistry(net, km).f(x)) / 1.0
         terms = absnu @ (chem.reaction_rates(net, kp, x) + chem.reaction_rates(net, km, x))
         assert np.all(np.abs(fd - G[:, r]) <= 8 * eps * terms + 1e-300)
+
+
+def test_log_rate_derivatives_match_central_differences():
+    # every rate law is smooth in each parameter: a central difference of log k
+    # with relative step 1e-5 agrees with the analytic derivative to ~1e-9
+    net = synth.network_for_config("net200")
+    D = chem.log_rate_derivatives(net, **CELL)
+    for j, name in enumerate(chem.PHYS_PARAMS):
+        step = 1e-5 * (abs(CELL[name]) if CELL[name] != 0 else 1.0)
+        up, dn = dict(CELL), dict(CELL)
+        up[name] += step
+        dn[name] -= step
+        fd = (np.log(chem.rate_coefficients(net, **up)) - np.log(chem.rate_coefficients(net, **dn))) / (2 * step)
+        scale = np.abs(D[:, j]).max()
+        assert np.all(np.abs(fd - D[:, j]) <= 1e-7 * scale + 1e-12 * np.abs(fd)), name
+    # each law depends only on its own parameters
+    two, cr, ph = (net.rtype == t for t in (synth.TWO_BODY, synth.COSMIC_RAY, synth.PHOTO))
+    assert np.all(D[cr][:, [0, 1, 2, 4]] == 0) and np.all(D[ph][:, [0, 1, 3]] == 0)
+    assert np.all(D[two][:, 2:] == 0)

@@ -125,3 +125,71 @@ def test_sensitivity_is_exact_derivative_of_frozen_map():
         xm = bdf.replay(chem.Chemistry(net, km), x0, res.history)
         fd = (np.log(xp[m]) - np.log(xm[m])) / (2 * delta)
         assert np.max(np.abs(fd - G[:, r])) <= 1e-5 * gscale
+
+
+def test_phys_gradient_decay_closed_form():
+    # A -> B by cosmic rays, k = alpha zeta: d log x_A / d zeta = -alpha t, and
+    # no other parameter enters
+    net = tiny_nets.decay(2.0)
+    cell = dict(T=30.0, n_H=1e4, A_V=1.0, zeta=1.3e-17, G0=1.0)
+    ch = chem.cell_chemistry(net, cell)
+    t = 3.0 / ch.k[0]
+    res = bdf.solve(ch, np.array([1.0, 0.0]), t, 1e-10, 1e-30, record=True)
+    x, Sx = bdf.replay(ch, np.array([1.0, 0.0]), res.history,
+                       sens_dfdp=lambda y: ch.df_dlogalpha(y).toarray())
+    gphi = chem.phys_gradient(net, cell, Sx[0] / x[0])
+    assert gphi[3] == pytest.approx(-2.0 * t, rel=1e-6)
+    assert np.all(gphi[[0, 1, 2, 4]] == 0)
+
+
+def test_phys_gradient_first_order_matches_expm_frechet():
+    # x(t) = expm(tK) x0 with K linear in every k_r: for a parameter phi,
+    # dK/dphi = sum_r (d log k_r / d phi) dK/dlog alpha_r and dx/dphi is the
+    # Frechet derivative of expm along t dK/dphi applied to x0
+    net = tiny_nets.first_order()
+    cell = dict(T=20.0, n_H=1e3, A_V=0.5, zeta=1e-16, G0=1.0)
+    ch = chem.cell_chemistry(net, cell)
+    S = net.n_species
+    K = ch.jac(np.zeros(S))
+    x0 = np.zeros(S)
+    x0[net.index("H2")] = 0.5
+    x0[net.index("CO")] = 1e-4
+    t = 3e4 * YEAR
+    w = np.random.default_rng(11).uniform(-1, 1, S)
+    res = bdf.solve(ch, x0, t, 1e-9, 1e-30, record=True)
+    x, Sx = bdf.replay(ch, x0, res.history, sens_dfdp=lambda y: ch.df_dlogalpha(y).toarray())
+    gphi = chem.phys_gradient(net, cell, w @ Sx)
+    D = chem.log_rate_derivatives(net, **cell)
+    nu = chem.stoichiometry(net).toarray()
+    drate = chem.rate_derivative(net, ch.k, np.zeros(S)).toarray()
+    for j in (2, 3, 4):      # A_V, zeta, G0 (no two-body reaction: T, n_H do not enter)
+        dK = sum(D[r, j] * np.outer(nu[:, r], drate[r]) for r in range(net.n_reactions))
+        _, L = sla.expm_frechet(t * K, t * dK)
+        want = w @ (L @ x0)
+        assert gphi[j] == pytest.approx(want, rel=1e-6, abs=1e-12 * abs(want))
+    assert gphi[0] == 0 and gphi[1] == 0
+
+
+def test_phys_gradient_is_derivative_of_frozen_map():
+    # every parameter of the 12-species cell against central differences of the
+    # frozen-sequence map in that parameter (the rates are recomputed)
+    net = synth.network_for_config("small")
+    cells = synth.single_cell(net, t_end_yr=1e5)
+    cell = cells.cell(0)
+    ch = chem.cell_chemistry(net, cell)
+    x0, t_end = cells.x0[0], cells.t_end[0]
+    res = bdf.solve(ch, x0, t_end, 1e-6, 1e-20, record=True)
+    x, Sx = bdf.replay(ch, x0, res.history, sens_dfdp=lambda y: ch.df_dlogalpha(y).toarray())
+    m = np.flatnonzero(x > 1e-12)
+    gphi = chem.phys_gradient(net, cell, (Sx[m] / x[m, None]).sum(axis=0))
+    for j, name in enumerate(chem.PHYS_PARAMS):
+        if name == "A_V":
+            continue     # no photo reaction in this network: A_V and G0 do not enter
+        d = 1e-4 * cell[name]
+        up, dn = dict(cell), dict(cell)
+        up[name] += d
+        dn[name] -= d
+        xp = bdf.replay(chem.cell_chemistry(net, up), x0, res.history)
+        xm = bdf.replay(chem.cell_chemistry(net, dn), x0, res.history)
+        fd = (np.log(xp[m]).sum() - np.log(xm[m]).sum()) / (2 * d)
+        assert gphi[j] == pytest.approx(fd, rel=1e-5, abs=1e-9 * abs(gphi[j]) + 1e-300), name
