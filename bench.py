@@ -199,16 +199,19 @@ def run_adjoint(args):
     dLdx = torch.zeros_like(x)
     dLdx[:, targets] = 1.0 / x[:, targets]
     gsum, gcell, _ = tape.adjoint(dLdx, per_cell=True)
+    gphi = ab.phys_gradient(g, *inp[:5], gcell)      # dL/d(T, n_H, A_V, zeta, G0) per cell
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     ab.profile_enable(False)
     prof = ab.profile_read(reset=True)
     ok = int((status == 0).sum().item())
     out = {"metric": "gradient cell-solves/sec (forward with step tape + discrete adjoint), 500-sp net",
+           "phys_gradient_abs_mean": [float(v) for v in gphi.abs().mean(dim=0).cpu()],
            "value": round(ok / (t2 - t0), 3), "unit": "cell-solves/s", "n_gpus": 1, "higher_is_better": True,
            "data": "synthetic", "dtype": "f64",
            "config": {"workload": f"net500 differentiation: {args.adj_cells} cells, t_end 1e6 yr, rtol 1e-6 "
-                                  "atol 1e-20, d(sum of log x over 10 targets)/d log alpha for all 6000 reactions",
+                                  "atol 1e-20, d(sum of log x over 10 targets)/d log alpha for all 6000 reactions "
+                                  "and d/d(T, n_H, A_V, zeta, G0) per cell",
                       "cells": args.adj_cells, "targets": targets.tolist()},
            "forward_record_s": round(t1 - t0, 3), "reverse_s": round(t2 - t1, 3),
            "checkpoint_bytes": tape.nbytes, "cells_ok": ok,
@@ -246,12 +249,109 @@ def run_adjoint(args):
                         "max_rel_err_vs_oracle_forward_sensitivities": max(e_sens),
                         "max_abs_err_vs_central_differences_over_max_gradient": max(e_fd),
                         "oracle_sensitivities_vs_central_differences_over_max_gradient": max(e_own)}
+        phys_path = os.path.join(ROOT, "tests", "golden", "phys_net500.json")
+        pg = json.load(open(phys_path)) if os.path.exists(phys_path) else None
+        if pg is not None and pg["targets"] == gold["targets"]:
+            m = len(pg["cells"])
+            gp = ab.phys_gradient(g, *[v[:m] for v in sub[:5]], torch.as_tensor(gc[:m], device=dev)).cpu().numpy()
+            e_ps, e_pf, e_po = [], [], []
+            for c, r in enumerate(pg["cells"]):
+                # phi_j dL/dphi_j (dL/dA_V for the extinction): one dimensionless scale
+                cl = cells.cell(c)
+                w = np.array([cl["T"], cl["n_H"], 1.0, cl["zeta"], cl["G0"]])
+                sens, fd, gv = np.array(r["sens"]) * w, np.array(r["fd"]) * w, gp[c] * w
+                top = np.abs(sens).max()
+                e_ps.append(err(gv, sens, top))
+                e_pf.append(float(np.max(np.abs(gv - fd)) / top))
+                e_po.append(float(np.max(np.abs(sens - fd)) / top))
+            out["check_phys"] = {"cells": m, "params": pg["params"],
+                                 "max_rel_err_vs_oracle_forward_sensitivities": max(e_ps),
+                                 "max_abs_err_vs_central_differences_over_max_gradient": max(e_pf),
+                                 "oracle_sensitivities_vs_central_differences_over_max_gradient": max(e_po)}
+    print(json.dumps(out))
+
+
+def run_single(args):
+    """One cell of the 12-species network (n_H 1e4, T 10 K, A_V 0, t_end 1e6 yr):
+    the latency of a whole solve, its steps, and its error against the oracle."""
+    import torch
+    import paper_2511_10558_amd as ab
+    import synth
+    from oracle import bdf, chem
+    net = synth.network_for_config("small")
+    cells = synth.single_cell(net)
+    ref = bdf.solve(chem.cell_chemistry(net, cells.cell(0)), cells.x0[0], cells.t_end[0], 1e-6, 1e-20)
+    dev = torch.device("cuda:0")
+    g = ab.Network.from_text(net.to_text())
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
+    inp = [t(cells.T), t(cells.n_H), t(cells.A_V), t(cells.zeta), t(cells.G0), t(cells.x0), t(cells.t_end)]
+    opts = ab.make_options(rtol=1e-6, atol=1e-20)
+    for _ in range(max(1, args.warmup)):
+        ab.solve(g, *inp, options=opts)
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(max(1, args.steps) * 10):
+        t0 = time.perf_counter()
+        x, st, stats = ab.solve(g, *inp, options=opts, with_stats=True)
+        torch.cuda.synchronize()
+        times.append(time.perf_counter() - t0)
+    xg = x[0].cpu().numpy()
+    m = ref.x > 1e-12
+    out = {"metric": "single-cell solve latency, 12-species network", "value": round(float(np.median(times)) * 1e6, 1),
+           "unit": "us", "n_gpus": 1, "higher_is_better": False, "data": "synthetic", "dtype": "f64",
+           "config": {"workload": "12 species / 40 reactions, one cell n_H 1e4 T 10 K A_V 0, t_end 1e6 yr, "
+                                  "rtol 1e-6 atol 1e-20", "repeats": len(times)},
+           "steps": int(stats["n_steps"][0]), "oracle_steps": int(ref.stats.n_steps),
+           "max_rel_err_vs_oracle": float(np.max(np.abs(xg[m] - ref.x[m]) / ref.x[m])),
+           "status": int(st[0])}
+    print(json.dumps(out))
+
+
+def run_ceilings(args):
+    """Measured ceilings of this GPU for the roofline denominators: a plain
+    device copy (HBM) and a large FP64 / FP32 matrix product (rocBLAS through
+    torch), next to the vendor peaks used in the roofline."""
+    import torch
+    dev = torch.device("cuda:0")
+    res = {}
+    n = 1 << 28                              # 2 GiB of doubles
+    a = torch.ones(n, dtype=torch.float64, device=dev)
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(10):
+        b.copy_(a)
+    e1.record()
+    torch.cuda.synchronize()
+    res["copy_GBs"] = round(2 * 8 * n * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+    del a, b
+    for name, dt in (("dgemm_TFLOPs", torch.float64), ("sgemm_TFLOPs", torch.float32)):
+        m = 8192
+        x = torch.randn(m, m, dtype=dt, device=dev)
+        y = torch.randn(m, m, dtype=dt, device=dev)
+        for _ in range(3):
+            torch.matmul(x, y)
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(10):
+            torch.matmul(x, y)
+        e1.record()
+        torch.cuda.synchronize()
+        res[name] = round(2 * m ** 3 * 10 / (e0.elapsed_time(e1) * 1e-3) / 1e12, 2)
+        del x, y
+    out = {"metric": "measured ceilings (copy, FP64 and FP32 GEMM)", "n_gpus": 1, "data": "synthetic",
+           "config": {"workload": "2 GiB device copy; 8192^3 torch.matmul in FP64 and FP32"},
+           "vendor_peaks": {"hbm_GBs": HBM_PEAK_GBS, "fp64_mfma_TFLOPs": FP64_MFMA_PEAK_TFLOPS,
+                            "fp32_mfma_TFLOPs": FP32_MFMA_PEAK_TFLOPS}, **res}
     print(json.dumps(out))
 
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", default="batch", choices=["batch", "serve", "adjoint"])
+    ap.add_argument("--workload", default="batch", choices=["batch", "serve", "adjoint", "single", "ceilings"])
     ap.add_argument("--requests", type=int, default=256, help="serve: requests after the warm-up")
     ap.add_argument("--rate", type=float, default=0.0, help="serve: arrival rate [requests/s]; 0 = 0.8 x saturation")
     ap.add_argument("--serve-precisions", default="fp64,fp32_lu")
@@ -282,6 +382,10 @@ def main():
         return run_serve(args)
     if args.workload == "adjoint":
         return run_adjoint(args)
+    if args.workload == "single":
+        return run_single(args)
+    if args.workload == "ceilings":
+        return run_ceilings(args)
     import synth
     net = synth.network_for_config(args.network)
     cells = synth.sample_cells(net, args.cells, seed=args.seed, t_end_yr=args.t_end_yr)
@@ -379,7 +483,7 @@ def main():
     # the Newton kernels come from the rocprofv3 summary, not from these spans.
 
     out = {
-        "metric": "cell-solves/sec to t_end at rtol 1e-6, 500-sp net",
+        "metric": f"cell-solves/sec to t_end at rtol 1e-6, {S}-sp net",
         "value": round(value, 3),
         "unit": "cell-solves/s",
         "n_gpus": 1,

@@ -299,6 +299,26 @@ abdf_status abdf_solve_adjoint(const abdf_network *net, int64_t n_cells,
                                double *dL_dlog_alpha, double *dL_dlog_alpha_cell, double *dL_dx0,
                                abdf_cell_stats *stats, void *stream);
 
+/* Gradients with respect to each cell's physical parameters, from the per-cell
+ * gradients with respect to log alpha (dL_dlog_alpha_cell of
+ * abdf_tape_adjoint / abdf_solve_adjoint; DEVICE [n_cells][R]).  Every rate
+ * coefficient is alpha_r times a function of the cell's parameters (paper
+ * Sec. 2 two-body and cosmic-ray laws, App. B.1 photo law) and the parameters
+ * enter the rate equations only through the coefficients, so per cell
+ *   dL/dphi_j = sum_r dL/dlog alpha_r * d log k_r / d phi_j,
+ * with d log k_r/dT = (beta + gamma/T)/T and d log k_r/dn_H = 1/n_H (two-body),
+ * d log k_r/dzeta = 1/zeta (cosmic ray), d log k_r/dA_V = -gamma and
+ * d log k_r/dG0 = 1/G0 (photo).  T, n_H, A_V, zeta, G0: DEVICE [n_cells], the
+ * solve's inputs.  dL_dphi: DEVICE [n_cells][5], columns T, n_H, A_V, zeta,
+ * G0; the sums over reactions run in reaction order per thread, then in a
+ * fixed tree, so results are deterministic.  Asynchronous on the stream.
+ * Errors: ABDF_E_ARG (null or non-device pointers, n_cells out of range),
+ * ABDF_E_DEVICE. */
+abdf_status abdf_phys_gradient(const abdf_network *net, int64_t n_cells,
+                               const double *T, const double *n_H, const double *A_V,
+                               const double *zeta, const double *G0,
+                               const double *dL_dlog_alpha_cell, double *dL_dphi, void *stream);
+
 /* -------------------------------------------------- component entry points --
  * The steps of one BDF step on their own, for kernel-level checks and timing.
  */

@@ -253,26 +253,50 @@ def solve_adjoint(net: Network, T, n_H, A_V, zeta, G0, x0, t_end, dL_dx, *, alph
     return x_out, status, g, gc, dx0
 
 
+PHYS_PARAMS = ("T", "n_H", "A_V", "zeta", "G0")
+
+
+def phys_gradient(net: Network, T, n_H, A_V, zeta, G0, dL_dlog_alpha_cell):
+    """dL/dphi [C, 5] (columns T, n_H, A_V, zeta, G0) from the per-cell
+    gradients with respect to log alpha [C, R] (abdf_phys_gradient)."""
+    torch = _torch()
+    C = T.shape[0]
+    args = [_ptr(v, torch.float64, (C,), nm) for v, nm in
+            ((T, "T"), (n_H, "n_H"), (A_V, "A_V"), (zeta, "zeta"), (G0, "G0"))]
+    g = _ptr(dL_dlog_alpha_cell.contiguous(), torch.float64, (C, net.n_reactions), "dL_dlog_alpha_cell")
+    out = torch.empty((C, 5), dtype=torch.float64, device=T.device)
+    _check(_lib.lib().abdf_phys_gradient(net.handle, C, *args, g, ctypes.c_void_p(out.data_ptr()), _stream()))
+    return out
+
+
 def _autograd_function():
     torch = _torch()
 
     class SolveFunction(torch.autograd.Function):
-        """x(t_end) as a differentiable function of log alpha [R] and x0 [C, S];
-        the backward pass is the discrete adjoint of the recorded solve."""
+        """x(t_end) as a differentiable function of log alpha [R], x0 [C, S] and
+        the cells' physical parameters T, n_H, A_V, zeta, G0 [C]; the backward
+        pass is the discrete adjoint of the recorded solve (parameters through
+        abdf_phys_gradient)."""
 
         @staticmethod
         def forward(ctx, log_alpha, x0, net, T, n_H, A_V, zeta, G0, t_end, options, max_tape_steps):
             alpha = torch.exp(log_alpha.detach()).contiguous()
-            x, status, tape = solve_record(net, T, n_H, A_V, zeta, G0, x0.detach().contiguous(), t_end,
+            phys = [v.detach().contiguous() for v in (T, n_H, A_V, zeta, G0)]
+            x, status, tape = solve_record(net, *phys, x0.detach().contiguous(), t_end,
                                            alpha=alpha, options=options, max_tape_steps=max_tape_steps)
-            ctx.tape = tape
+            ctx.tape, ctx.net, ctx.phys = tape, net, phys
             ctx.mark_non_differentiable(status)
             return x, status
 
         @staticmethod
         def backward(ctx, gx, _gstatus):
-            g, _, dx0 = ctx.tape.adjoint(gx.contiguous(), x0_grad=ctx.needs_input_grad[1])
-            return g, dx0, None, None, None, None, None, None, None, None, None
+            need_phys = any(ctx.needs_input_grad[3:8])
+            g, gc, dx0 = ctx.tape.adjoint(gx.contiguous(), per_cell=need_phys, x0_grad=ctx.needs_input_grad[1])
+            gp = [None] * 5
+            if need_phys:
+                gphi = phys_gradient(ctx.net, *ctx.phys, gc)
+                gp = [gphi[:, j].clone() if ctx.needs_input_grad[3 + j] else None for j in range(5)]
+            return (g, dx0, None, *gp, None, None, None)
 
     return SolveFunction
 
@@ -282,7 +306,8 @@ _SOLVE_FN = None
 
 def solve_diff(net: Network, T, n_H, A_V, zeta, G0, x0, t_end, log_alpha, *, max_tape_steps=0,
                options: Options | None = None, **opts):
-    """Differentiable solve: (x_out, status); gradients flow to log_alpha [R] and x0."""
+    """Differentiable solve: (x_out, status); gradients flow to log_alpha [R],
+    x0 [C, S] and the physical parameters T, n_H, A_V, zeta, G0 [C]."""
     global _SOLVE_FN
     if _SOLVE_FN is None:
         _SOLVE_FN = _autograd_function()

@@ -85,6 +85,7 @@ SIGNATURES = {
     "abdf_solve": (ctypes.c_int, [c_void_p, ctypes.c_int64] + [c_void_p] * 7 +
                    [ctypes.POINTER(Options), c_void_p, c_void_p, c_void_p, c_void_p]),
     "abdf_rates": (ctypes.c_int, [c_void_p, ctypes.c_int64] + [c_void_p] * 6 + [c_void_p]),
+    "abdf_phys_gradient": (ctypes.c_int, [c_void_p, ctypes.c_int64] + [c_void_p] * 7 + [c_void_p]),
     "abdf_rhs": (ctypes.c_int, [c_void_p, ctypes.c_int64, c_void_p, c_void_p, c_void_p, c_void_p]),
     "abdf_newton_matrix": (ctypes.c_int, [c_void_p, ctypes.c_int64, c_void_p, c_void_p, c_void_p, c_void_p,
                                           c_void_p]),

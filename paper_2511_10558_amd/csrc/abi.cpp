@@ -378,6 +378,28 @@ abdf_status abdf_rates(const abdf_network *net, int64_t n_cells, const double *T
     return ok();
 }
 
+abdf_status abdf_phys_gradient(const abdf_network *net, int64_t n_cells, const double *T, const double *n_H,
+                               const double *A_V, const double *zeta, const double *G0,
+                               const double *dL_dlog_alpha_cell, double *dL_dphi, void *stream) {
+    if (!net) return fail(ABDF_E_ARG, "null network");
+    if (n_cells < 0 || n_cells > INT32_MAX) return fail(ABDF_E_ARG, "n_cells out of range");
+    if (n_cells == 0) return ok();
+    CHECK_DEV(T, "T");
+    CHECK_DEV(n_H, "n_H");
+    CHECK_DEV(A_V, "A_V");
+    CHECK_DEV(zeta, "zeta");
+    CHECK_DEV(G0, "G0");
+    CHECK_DEV(dL_dlog_alpha_cell, "dL_dlog_alpha_cell");
+    CHECK_DEV(dL_dphi, "dL_dphi");
+    std::string err;
+    const abdf::DeviceNet *dn = net->host.device_tables(err);
+    if (!dn) return fail(ABDF_E_DEVICE, err);
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    HIP_OR_FAIL(abdf::launch_phys_grad(*dn, abdf::PhysArgs{T, n_H, A_V, zeta, G0}, n_cells, dL_dlog_alpha_cell,
+                                       dL_dphi, st));
+    return ok();
+}
+
 abdf_status abdf_rhs(const abdf_network *net, int64_t n_cells, const double *k, const double *x, double *f_out,
                      void *stream) {
     if (!net) return fail(ABDF_E_ARG, "null network");

@@ -938,6 +938,42 @@ __global__ void k_grad_sum(const double *g_cell, long long cells, int R, double 
     out[r] = acc;
 }
 
+// dL/dphi of one cell (one workgroup) from its dL/dlog alpha: five sums over
+// reactions of g_r d log k_r / d phi_j (paper Sec. 2, App. B.1 rate laws).
+__global__ void __launch_bounds__(kBlock) k_phys_grad(DeviceNet n, PhysArgs p, const double *g_cell, double *out) {
+    __shared__ double red[kWaves];
+    const long long c = blockIdx.x;
+    const double T = p.T[c], nH = p.nH[c], zeta = p.zeta[c], G0 = p.G0[c];
+    const double *g = g_cell + size_t(c) * n.R;
+    double sT = 0.0, sN = 0.0, sA = 0.0, sZ = 0.0, sG = 0.0;
+    for (int r = threadIdx.x; r < n.R; r += kBlock) {
+        const int t = n.rx_type[r];
+        const double gr = g[r];
+        if (t == kTwoBody) {
+            sT += gr * (n.beta[r] + n.gamma[r] / T) / T;
+            sN += gr / nH;
+        } else if (t == kCosmicRay) {
+            sZ += gr / zeta;
+        } else {
+            sA += -n.gamma[r] * gr;
+            sG += gr / G0;
+        }
+    }
+    sT = block_sum(sT, red);
+    sN = block_sum(sN, red);
+    sA = block_sum(sA, red);
+    sZ = block_sum(sZ, red);
+    sG = block_sum(sG, red);
+    if (threadIdx.x == 0) {
+        double *o = out + size_t(c) * 5;
+        o[0] = sT;
+        o[1] = sN;
+        o[2] = sA;
+        o[3] = sZ;
+        o[4] = sG;
+    }
+}
+
 // ------------------------------------------------- component entry kernels --
 
 __global__ void __launch_bounds__(kBlock) k_rates_only(DeviceNet n, PhysArgs p, double *k_out) {
@@ -1215,6 +1251,12 @@ hipError_t launch_adj_harvest(const Slots &s, const AdjHarvestArgs &h, hipStream
 
 hipError_t launch_grad_sum(const double *g_cell, long long cells, int R, double *out, hipStream_t st) {
     hipLaunchKernelGGL(k_grad_sum, dim3((R + 255) / 256), dim3(256), 0, st, g_cell, cells, R, out);
+    return LAUNCH_CHECK();
+}
+
+hipError_t launch_phys_grad(const DeviceNet &n, const PhysArgs &p, long long cells, const double *g_cell,
+                            double *out, hipStream_t st) {
+    hipLaunchKernelGGL(k_phys_grad, dim3(cells), dim3(kBlock), 0, st, n, p, g_cell, out);
     return LAUNCH_CHECK();
 }
 

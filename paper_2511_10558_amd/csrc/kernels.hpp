@@ -86,6 +86,9 @@ hipError_t launch_adj_solve(const Slots &s, int ring, int grid, size_t lds, hipS
 hipError_t launch_adj_step(const Slots &s, const DeviceNet &n, int ring, int grid, size_t lds, hipStream_t st);
 hipError_t launch_adj_harvest(const Slots &s, const AdjHarvestArgs &h, hipStream_t st);
 hipError_t launch_grad_sum(const double *g_cell, long long cells, int R, double *out, hipStream_t st);
+// dL/dphi [cells][5] (T, n_H, A_V, zeta, G0) from per-cell dL/dlog alpha [cells][R].
+hipError_t launch_phys_grad(const DeviceNet &n, const PhysArgs &p, long long cells, const double *g_cell,
+                            double *out, hipStream_t st);
 inline size_t adj_lds(const DeviceNet &n) { return sizeof(double) * (2 * size_t(n.S) + n.R); }
 inline size_t adj_solve_lds(const DeviceNet &n) { return sizeof(double) * (2 * size_t(n.NP) + 5 * 64 + 64 * 65); }
 

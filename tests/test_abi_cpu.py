@@ -164,3 +164,9 @@ def test_adjoint_entry_points_reject_null_arguments():
     rc = L.abdf_solve_record(g.handle, 1, *([ctypes.cast(x, ctypes.c_void_p)] * 8), ctypes.byref(o), 0,
                              nul, nul, nul, ctypes.byref(tape), nul)
     assert rc == 1 and not tape.value
+    # physical-parameter gradient: null network, count out of range, host pointers; empty is fine
+    hp = ctypes.cast(x, ctypes.c_void_p)
+    assert L.abdf_phys_gradient(nul, 1, *([nul] * 7), nul) == 1
+    assert L.abdf_phys_gradient(g.handle, -1, *([nul] * 7), nul) == 1
+    assert L.abdf_phys_gradient(g.handle, 1, *([hp] * 7), nul) == 1
+    assert L.abdf_phys_gradient(g.handle, 0, *([nul] * 7), nul) == 0

@@ -1,0 +1,157 @@
+"""Gradients with respect to each cell's physical parameters (GPU).
+
+dL/dphi is the per-cell log-alpha gradient of the discrete adjoint contracted
+with d log k / d phi.  Checked against closed forms and expm Frechet
+derivatives where the map is known exactly, and against the oracle's forward
+sensitivities contracted the same way (bar as for the log-alpha gradients:
+|g - g_ref| <= 1e-3 max(|g_ref|, 1e-3 max |g_ref|)).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+
+import synth
+from oracle import chem
+from tests import tiny_nets
+from tests.gpu_util import device, solve_cells, t
+from tests.test_gpu_adjoint import adjoint, cells_for, grad_ok, log_loss_grad, oracle_log_gradient
+
+pytestmark = pytest.mark.gpu
+YEAR = synth.YEAR_S
+
+
+@pytest.fixture(scope="module")
+def ab():
+    import paper_2511_10558_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def dev():
+    return device()
+
+
+def log_scaled(gphi, cell):
+    """phi_j dL/dphi_j (dL/dA_V for the extinction): dimensionless, so that the
+    five entries can be compared on one scale."""
+    return np.asarray(gphi) * np.array([cell["T"], cell["n_H"], 1.0, cell["zeta"], cell["G0"]])
+
+
+def phys_grad(ab, g, cells, gc, dev):
+    phys = [t(v, dev) for v in (cells.T, cells.n_H, cells.A_V, cells.zeta, cells.G0)]
+    return ab.phys_gradient(g, *phys, t(gc, dev)).cpu().numpy()
+
+
+def test_decay_zeta_gradient_closed_form(ab, dev):
+    # A -> B by cosmic rays, k = alpha zeta: d log x_A / d zeta = -alpha t
+    net = tiny_nets.decay(2.0)
+    g = ab.Network.from_text(net.to_text())
+    cell = dict(T=30.0, n_H=1e4, A_V=1.0, zeta=1.3e-17, G0=1.0)
+    tt = 3.0 / chem.cell_chemistry(net, cell).k[0]
+    cells = cells_for(net, cell, [1.0, 0.0], tt)
+    x, st, _, gc, _ = adjoint(ab, g, cells, np.array([[1.0, 0.0]]), dev, rtol=1e-10, atol=1e-30)
+    assert st[0] == 0
+    gphi = phys_grad(ab, g, cells, gc, dev)[0] / x[0, 0]
+    assert gphi[3] == pytest.approx(-2.0 * tt, rel=1e-6)
+    assert np.all(gphi[[0, 1, 2, 4]] == 0)
+
+
+def test_first_order_network_matches_expm_frechet(ab, dev):
+    net = tiny_nets.first_order()
+    g = ab.Network.from_text(net.to_text())
+    cell = dict(T=20.0, n_H=1e3, A_V=0.5, zeta=1e-16, G0=1.0)
+    ch = chem.cell_chemistry(net, cell)
+    S = net.n_species
+    K = ch.jac(np.zeros(S))
+    x0 = np.zeros(S)
+    x0[net.index("H2")] = 0.5
+    x0[net.index("CO")] = 1e-4
+    tt = 3e4 * YEAR
+    w = np.random.default_rng(7).uniform(-1, 1, S)
+    cells = cells_for(net, cell, x0, tt)
+    _, st, _, gc, _ = adjoint(ab, g, cells, w[None, :], dev, rtol=1e-9, atol=1e-30)
+    assert st[0] == 0
+    gphi = phys_grad(ab, g, cells, gc, dev)[0]
+    D = chem.log_rate_derivatives(net, **cell)
+    nu = chem.stoichiometry(net).toarray()
+    drate = chem.rate_derivative(net, ch.k, np.zeros(S)).toarray()
+    want = np.zeros(5)
+    for j in (2, 3, 4):
+        dK = sum(D[r, j] * np.outer(nu[:, r], drate[r]) for r in range(net.n_reactions))
+        want[j] = w @ (sla.expm_frechet(tt * K, tt * dK)[1] @ x0)
+    assert np.max(np.abs(gphi - want)) <= 1e-6 * np.abs(want).max()
+    assert gphi[0] == 0 and gphi[1] == 0
+
+
+def test_small_network_matches_oracle_sensitivities(ab, dev):
+    net = synth.network_for_config("small")
+    g = ab.Network.from_text(net.to_text())
+    cells = synth.sample_cells(net, 3, seed=121, t_end_yr=1e5)
+    xg, st, _ = solve_cells(ab, g, cells, dev)
+    assert (st == 0).all()
+    targets = np.flatnonzero((xg > 1e-12).all(axis=0))
+    _, st, _, gc, _ = adjoint(ab, g, cells, log_loss_grad(xg, targets), dev)
+    gphi = phys_grad(ab, g, cells, gc, dev)
+    for c in range(cells.n):
+        # the contraction itself, against the oracle's derivative table on the GPU's gradient
+        D = chem.log_rate_derivatives(net, **cells.cell(c))
+        terms = np.abs(D) * np.abs(gc[c])[:, None]
+        assert np.all(np.abs(gphi[c] - D.T @ gc[c]) <= 1e-13 * terms.sum(axis=0) + 1e-300)
+        # end to end against the oracle's forward sensitivities
+        ref_a, _ = oracle_log_gradient(net, cells, c, targets, np.arange(net.n_reactions))
+        ref = chem.phys_gradient(net, cells.cell(c), ref_a)
+        assert grad_ok(log_scaled(gphi[c], cells.cell(c)), log_scaled(ref, cells.cell(c))) <= 1e-3
+
+
+def test_autograd_reaches_the_physical_parameters(ab, dev):
+    import torch
+    net = synth.network_for_config("small")
+    g = ab.Network.from_text(net.to_text())
+    cells = synth.sample_cells(net, 3, seed=131, t_end_yr=3e4)
+    log_alpha = torch.tensor(np.log(net.alpha), dtype=torch.float64, device=dev)
+    phys = [t(v, dev).requires_grad_(True) for v in (cells.T, cells.n_H, cells.A_V, cells.zeta, cells.G0)]
+    x, st = ab.solve_diff(g, *phys, t(cells.x0, dev), t(cells.t_end, dev), log_alpha)
+    targets = [i for i in range(net.n_species) if (x[:, i] > 1e-12).all()]
+    torch.log(x[:, targets]).sum().backward()
+    assert (st == 0).all()
+    dLdx = torch.zeros_like(x)
+    dLdx[:, targets] = 1.0 / x.detach()[:, targets]
+    plain = [p.detach() for p in phys]
+    # the same solve through the one-call entry point, with alpha = exp(log alpha) as the function uses
+    _, _, _, gc, _ = ab.solve_adjoint(g, *plain, t(cells.x0, dev), t(cells.t_end, dev), dLdx,
+                                      alpha=torch.exp(log_alpha), per_cell=True)
+    want = ab.phys_gradient(g, *plain, gc)
+    for j, p in enumerate(phys):
+        assert torch.equal(p.grad, want[:, j])
+
+
+PHYS_GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "phys_net500.json")
+
+
+@pytest.mark.skipif(not os.path.exists(PHYS_GOLDEN),
+                    reason="oracle physical-parameter gradients of the 500-species workload not generated")
+def test_net500_matches_oracle_sensitivities_and_central_differences(ab, dev):
+    gold = json.load(open(PHYS_GOLDEN))
+    net = synth.network_for_config("net500")
+    g = ab.Network.from_text(net.to_text())
+    n = len(gold["cells"])
+    cells = synth.sample_cells(net, gold["batch_cells"], seed=gold["seeds"]["cells"], t_end_yr=1e6)
+    cells = cells.subset(np.arange(n))
+    targets = np.array(gold["targets"])
+    xg, _, _ = solve_cells(ab, g, cells, dev)
+    _, st, _, gc, _ = adjoint(ab, g, cells, log_loss_grad(xg, targets), dev)
+    assert (st == 0).all()
+    gphi = phys_grad(ab, g, cells, gc, dev)
+    for c, rec in enumerate(gold["cells"]):
+        cell = cells.cell(c)
+        gv = log_scaled(gphi[c], cell)
+        sens, fd = log_scaled(rec["sens"], cell), log_scaled(rec["fd"], cell)
+        assert grad_ok(gv, sens) <= 1e-3
+        # central differences carry the frozen map's rounding amplification: the
+        # bar is the larger of 1e-3 and twice the oracle's own disagreement
+        scale = np.maximum(np.abs(fd), 1e-3 * np.abs(sens).max())
+        own = np.abs(sens - fd) / scale
+        assert np.all(np.abs(gv - fd) / scale <= np.maximum(1e-3, 2.0 * own))
