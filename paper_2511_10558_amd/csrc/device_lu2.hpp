@@ -1,5 +1,5 @@
-// Left-looking blocked LU with partial pivoting, one 512-thread workgroup per
-// matrix, and the matching triangular solves.  The matrix is read through a
+// Left-looking blocked LU with partial pivoting, one workgroup per matrix
+// (shape per element type: LuShape), and the matching triangular solves.  The matrix is read through a
 // source functor when each block column is first gathered, so it can be
 // formed on the fly (the Newton matrix) instead of being stored first.
 //
@@ -14,8 +14,8 @@
 //
 // Factorisation of block column j (columns 64j .. 64j + Wj - 1):
 //  1. the block column is gathered (rows through perm) into MFMA accumulator
-//     registers: 8 waves, wave w owns row tiles w, w + 8, w + 16, w + 24, and
-//     all 4 column tiles of 16;
+//     registers: with W waves, wave w owns row tiles w, w + W, ..., and all 4
+//     column tiles of 16;
 //  2. for every earlier block i: U_ij = inv(L_ii) C_i (rows 64i..64i+63 of the
 //     block column, staged through LDS), then the rows below block i are
 //     updated C -= L_{:,i} U_ij on the matrix cores, L read from memory;
@@ -33,11 +33,25 @@
 
 namespace abdf {
 
-constexpr int kLuWaves = 8;
-constexpr int kLuThreads = kLuWaves * 64;
 constexpr int kLuW = 64;          // block-column width
-constexpr int kLuMaxNP = 512;     // one thread per row in the panel; four row tiles per wave
-constexpr int kSlots = kLuMaxNP / 16 / kLuWaves;
+constexpr int kLuMaxNP = 512;     // one thread per row in the panel
+
+// Workgroup shape of the factorisation per element type.  FP64: 8 waves of
+// 256 VGPRs, each wave holding four row tiles of the block column.  FP32: 16
+// waves of 128 VGPRs with two row tiles each (its accumulators are half the
+// size), twice the waves to hide latency with.
+template <typename T>
+struct LuShape;
+template <>
+struct LuShape<double> { static constexpr int waves = 8, wave_bits = 3; };
+template <>
+struct LuShape<float> { static constexpr int waves = 16, wave_bits = 4; };
+template <typename T>
+constexpr int lu_waves = LuShape<T>::waves;
+template <typename T>
+constexpr int lu_threads = LuShape<T>::waves * 64;
+template <typename T>
+constexpr int lu_slots = kLuMaxNP / 16 / LuShape<T>::waves;   // row tiles per wave
 constexpr int kLdb = 65;          // LDS leading dimension of 64-wide staging buffers
 
 template <typename T>
@@ -75,8 +89,8 @@ template <typename T>
 __host__ __device__ constexpr size_t lu2_lds_bytes(int NP) {
     return 5 * size_t(NP) * sizeof(int32_t)                        // perm, sto, pos_log, log_pos, pidx
            + kLuW * sizeof(int32_t)                                // piv_pos
-           + 2 * kLuWaves * (sizeof(double) + sizeof(int32_t))     // arg-max partials, double-buffered
-           + 2 * kLuWaves * kCrowLd * sizeof(T) + 16               // candidate pivot rows, double-buffered
+           + 2 * lu_waves<T> * (sizeof(double) + sizeof(int32_t))     // arg-max partials, double-buffered
+           + 2 * lu_waves<T> * kCrowLd * sizeof(T) + 16               // candidate pivot rows, double-buffered
            + lu2_work_elems<T>(NP) * sizeof(T) + 64;
 }
 
@@ -96,7 +110,7 @@ __host__ __device__ constexpr size_t lu2_dinv_elems(int NP) {
 // the workgroup must call this (it contains barriers).
 template <typename T>
 __device__ __forceinline__ void diag_inverses(const T *Cb, int W, T *D, T *Xb, T *Yb, T *Tb) {
-    constexpr int HALF = kLuThreads / 2;
+    constexpr int HALF = lu_threads<T> / 2;
     const int tid = threadIdx.x;
     const bool upper = tid >= HALF;
     const int h = tid % HALF;
@@ -222,18 +236,18 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
     int32_t *pidx = log_pos + NP;                          // position -> pivot column in this block, or -1
     int32_t *piv_pos = pidx + NP;                          // pivot column -> position
     double *redv = reinterpret_cast<double *>(piv_pos + kLuW);   // [2][waves]
-    int32_t *redi = reinterpret_cast<int32_t *>(redv + 2 * kLuWaves);
-    int32_t *rwave = redi + 2 * kLuWaves;                        // [2] wave holding logical row r;
+    int32_t *redi = reinterpret_cast<int32_t *>(redv + 2 * lu_waves<T>);
+    int32_t *rwave = redi + 2 * lu_waves<T>;                        // [2] wave holding logical row r;
                                                                  // [2] first zero pivot (1-based) or INT_MAX
     T *crow = reinterpret_cast<T *>(rwave + 4);                  // [2][waves][kCrowLd] candidate rows
-    T *work = crow + 2 * kLuWaves * kCrowLd;
+    T *work = crow + 2 * lu_waves<T> * kCrowLd;
     T *Cb = work;                                          // [64][kLdb]   (left-looking, inverses)
     T *Ub = Cb + kLuW * kLdb;                              // [64][kLdb]
     T *Xb = Ub + kLuW * kLdb;                              // [64][kLdb]
     T *P = work;                                           // [NP][kPanLd] (panel)
     T *U12 = P + size_t(NP) * kPanLd;                      // [16][kU12Ld]
 
-    for (int i = tid; i < NP; i += kLuThreads) perm[i] = i;
+    for (int i = tid; i < NP; i += lu_threads<T>) perm[i] = i;
     if (tid == 0) rwave[2] = 0x7fffffff;
     __syncthreads();
 
@@ -241,19 +255,19 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
         const int c0 = j * kLuW;
         const int Wj = min(kLuW, NP - c0);
         const int CTj = Wj / 16;
-        for (int q = tid; q < NP; q += kLuThreads) {
+        for (int q = tid; q < NP; q += lu_threads<T>) {
             sto[q] = perm[q];
             pos_log[q] = q;
             log_pos[q] = q;
             pidx[q] = -1;
         }
-        acc_t acc[kSlots][4];
+        acc_t acc[lu_slots<T>][4];
         // 1. gather the block column (positions = logical rows at this point),
         //    a row tile at a time: its 16 handles, then its 16 values.  Tiles
         //    outside the matrix read column c0 + lc of row 0 and are zeroed.
 #pragma unroll
-        for (int s = 0; s < kSlots; ++s) {
-            const int rt = wave + kLuWaves * s;
+        for (int s = 0; s < lu_slots<T>; ++s) {
+            const int rt = wave + lu_waves<T> * s;
             int32_t hnd[4][4];
             int srow[4];
 #pragma unroll
@@ -275,8 +289,8 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
         for (int i = 0; i < j; ++i) {
             const int r0 = i * kLuW;
 #pragma unroll
-            for (int s = 0; s < kSlots; ++s) {
-                const int rt = wave + kLuWaves * s;
+            for (int s = 0; s < lu_slots<T>; ++s) {
+                const int rt = wave + lu_waves<T> * s;
                 if (rt >= 4 * i && rt < 4 * i + 4) {
 #pragma unroll
                     for (int ct = 0; ct < 4; ++ct)
@@ -289,8 +303,8 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
             __syncthreads();
             const T *Li = dinv + size_t(i) * 2 * kLuW * kLuW;   // inverse of the unit-lower block i
 #pragma unroll
-            for (int s = 0; s < kSlots; ++s) {
-                const int rt = wave + kLuWaves * s;
+            for (int s = 0; s < lu_slots<T>; ++s) {
+                const int rt = wave + lu_waves<T> * s;
                 if (rt >= 4 * i && rt < 4 * i + 4) {
                     const int tr = rt - 4 * i;
                     v4 a[4];
@@ -315,8 +329,8 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
             }
             __syncthreads();
 #pragma unroll
-            for (int s = 0; s < kSlots; ++s) {
-                const int rt = wave + kLuWaves * s;
+            for (int s = 0; s < lu_slots<T>; ++s) {
+                const int rt = wave + lu_waves<T> * s;
                 if (rt >= 4 * (i + 1) && rt < RT) {
                     const T *Lrow = A + size_t(perm[16 * rt + lc]) * NP + r0;
                     v4 a[4];
@@ -341,8 +355,8 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
         for (int sp = 0; sp < CTj; ++sp) {
             // (a) the sub-panel's column tile to LDS, one row per position
 #pragma unroll
-            for (int s = 0; s < kSlots; ++s) {
-                const int rt = wave + kLuWaves * s;
+            for (int s = 0; s < lu_slots<T>; ++s) {
+                const int rt = wave + lu_waves<T> * s;
                 if (rt >= 4 * j && rt < RT)
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
@@ -365,7 +379,7 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
             const bool busy = __ballot(active) != 0;
             if (!busy && lane == 0) {
                 redv[wave] = -1.0;
-                redv[kLuWaves + wave] = -1.0;
+                redv[lu_waves<T> + wave] = -1.0;
             }
             int mylog = active ? pos_log[q] : 0x7fffffff;
             T x[16];
@@ -381,14 +395,14 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
                     double bv = (active && ax == ax) ? ax : -1.0;   // NaN never wins
                     int bl = mylog;
                     wave_argmax_ballot(bv, bl);
-                    if (lane == 0) { redv[buf * kLuWaves + wave] = bv; redi[buf * kLuWaves + wave] = bl; }
+                    if (lane == 0) { redv[buf * lu_waves<T> + wave] = bv; redi[buf * lu_waves<T> + wave] = bl; }
                     if (active && mylog == r) rwave[buf] = wave;
                     // the wave's candidate row (or row r, kept when nothing is
                     // finite) with the reciprocal of its entry in column c, or 0
                     // where that is below the smallest normal number (then the
                     // multipliers are formed by division, as LAPACK does)
                     if (active && mylog == (bv < 0.0 ? r : bl)) {
-                        T *cr = crow + (buf * kLuWaves + wave) * kCrowLd;
+                        T *cr = crow + (buf * lu_waves<T> + wave) * kCrowLd;
 #pragma unroll
                         for (int cc = c; cc < 16; ++cc) cr[cc] = x[cc];
                         cr[16] = fabs(x[c]) >= std::numeric_limits<T>::min() ? T(1) / x[c] : T(0);
@@ -400,11 +414,12 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
                 // to the smaller logical row
                 int lp, wv;
                 {
-                    const double fv = lane < kLuWaves ? redv[buf * kLuWaves + lane] : -2.0;
-                    const int fi = lane < kLuWaves ? redi[buf * kLuWaves + lane] : 0x7fffffff;
+                    const double fv = lane < lu_waves<T> ? redv[buf * lu_waves<T> + lane] : -2.0;
+                    const int fi = lane < lu_waves<T> ? redi[buf * lu_waves<T> + lane] : 0x7fffffff;
                     double m = dpp_max_step<0xB1, 0xf>(fv);    // quad_perm [1,0,3,2]
                     m = dpp_max_step<0x4E, 0xf>(m);            // quad_perm [2,3,0,1]
-                    m = dpp_max_step<0x141, 0xf>(m);           // row_half_mirror: lanes 0..7 hold the max
+                    m = dpp_max_step<0x141, 0xf>(m);           // row_half_mirror: lanes 0..7 hold their max
+                    if (lu_waves<T> > 8) m = dpp_max_step<0x140, 0xf>(m);   // row_mirror: lanes 0..15
                     {
                         const int lo = __builtin_amdgcn_readlane(__double2loint(m), 0);
                         const int hi = __builtin_amdgcn_readlane(__double2hiint(m), 0);
@@ -414,20 +429,20 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
                         lp = r;
                         wv = rwave[buf];
                     } else {
-                        const unsigned long long hit = __ballot(lane < kLuWaves && fv == m);
+                        const unsigned long long hit = __ballot(lane < lu_waves<T> && fv == m);
                         if (__popcll(hit) == 1) {
                             wv = __ffsll(static_cast<unsigned long long>(hit)) - 1;
                             lp = __builtin_amdgcn_readlane(fi, wv);
                         } else {
-                            double tv = (lane < kLuWaves && fv == m) ? 1.0 : -1.0;
-                            int tk = (lane < kLuWaves && fv == m) ? fi * 8 + lane : 0x7fffffff;
+                            double tv = (lane < lu_waves<T> && fv == m) ? 1.0 : -1.0;
+                            int tk = (lane < lu_waves<T> && fv == m) ? (fi << LuShape<T>::wave_bits) + lane : 0x7fffffff;
                             wave_argmax(tv, tk);
-                            lp = tk >> 3;
-                            wv = tk & 7;
+                            lp = tk >> LuShape<T>::wave_bits;
+                            wv = tk & (lu_waves<T> - 1);
                         }
                     }
                 }
-                const T *urow = crow + (buf * kLuWaves + wv) * kCrowLd;
+                const T *urow = crow + (buf * lu_waves<T> + wv) * kCrowLd;
                 const T piv = urow[c];
                 const T rinv = urow[16];
                 if (lane == 0 && piv == T(0)) atomicMin(&rwave[2], r + 1);
@@ -470,8 +485,8 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
             __syncthreads();
             // (c) back to the accumulators
 #pragma unroll
-            for (int s = 0; s < kSlots; ++s) {
-                const int rt = wave + kLuWaves * s;
+            for (int s = 0; s < lu_slots<T>; ++s) {
+                const int rt = wave + lu_waves<T> * s;
                 if (rt >= 4 * j && rt < RT)
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
@@ -486,8 +501,8 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
             if (sp + 1 < CTj) {
                 const int nct = CTj - sp - 1;
 #pragma unroll
-                for (int s = 0; s < kSlots; ++s) {
-                    const int rt = wave + kLuWaves * s;
+                for (int s = 0; s < lu_slots<T>; ++s) {
+                    const int rt = wave + lu_waves<T> * s;
                     if (rt >= 4 * j && rt < RT)
 #pragma unroll
                         for (int ct = 1; ct < 4; ++ct)
@@ -515,8 +530,8 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
                 }
                 __syncthreads();
 #pragma unroll
-                for (int s = 0; s < kSlots; ++s) {
-                    const int rt = wave + kLuWaves * s;
+                for (int s = 0; s < lu_slots<T>; ++s) {
+                    const int rt = wave + lu_waves<T> * s;
                     if (rt >= 4 * j && rt < RT) {
                         const bool unused = pidx[16 * rt + lc] < 0;
                         T a[4];
@@ -541,13 +556,13 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
                 __syncthreads();
             }
         }
-        for (int q2 = tid; q2 < NP; q2 += kLuThreads)
+        for (int q2 = tid; q2 < NP; q2 += lu_threads<T>)
             if (q2 >= c0) perm[pos_log[q2]] = sto[q2];
         // 4. diagonal block (logical rows c0 .. c0 + Wj - 1) to LDS, its
         //    triangles' inverses, and the block column back to its storage rows
 #pragma unroll
-        for (int s = 0; s < kSlots; ++s) {
-            const int rt = wave + kLuWaves * s;
+        for (int s = 0; s < lu_slots<T>; ++s) {
+            const int rt = wave + lu_waves<T> * s;
             if (rt >= 4 * j && rt < RT)
 #pragma unroll
                 for (int ct = 0; ct < 4; ++ct)
@@ -561,8 +576,8 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
         // the block column goes back first, so that the accumulators are free
         // while the inverses are formed
 #pragma unroll
-        for (int s = 0; s < kSlots; ++s) {
-            const int rt = wave + kLuWaves * s;
+        for (int s = 0; s < lu_slots<T>; ++s) {
+            const int rt = wave + lu_waves<T> * s;
             if (rt < RT)
 #pragma unroll
                 for (int ct = 0; ct < 4; ++ct)
@@ -575,7 +590,7 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
         diag_inverses<T>(Cb, Wj, dinv + size_t(j) * 2 * kLuW * kLuW, Xb, Ub, Xb + kLuW * kLdb);
         __syncthreads();
     }
-    for (int i = tid; i < NP; i += kLuThreads) perm_out[i] = perm[i];
+    for (int i = tid; i < NP; i += lu_threads<T>) perm_out[i] = perm[i];
     if (tid == 0 && info) *info = rwave[2] == 0x7fffffff ? 0 : rwave[2];
 }
 

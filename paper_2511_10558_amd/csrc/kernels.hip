@@ -289,10 +289,10 @@ __global__ void __launch_bounds__(kBlock) k_admit(Slots s, DeviceNet n, AdmitArg
     begin_attempt(s, slot, cs, ring, RU, sh);
 }
 
-// Forms M = I - c J(x_J) for every queued slot and factors it (one
-// 1024-thread workgroup per matrix).
+// Forms M = I - c J(x_J) for every queued slot and factors it (one workgroup
+// per matrix: 512 threads in FP64, 1024 in FP32).
 template <typename T>
-__global__ void __launch_bounds__(kLuThreads) k_factor(Slots s, DeviceNet n, int ring) {
+__global__ void __launch_bounds__(lu_threads<T>) k_factor(Slots s, DeviceNet n, int ring) {
     extern __shared__ double smem[];
     const int count = s.cnt[3 + ring];
     const int S = s.S, NP = s.NP;
@@ -306,10 +306,10 @@ __global__ void __launch_bounds__(kLuThreads) k_factor(Slots s, DeviceNet n, int
         // slot's compact array and M = I - c J(x_J) is formed block column by
         // block column as the factorisation gathers it
         double *xs = reinterpret_cast<double *>(reinterpret_cast<unsigned char *>(smem) + lu2_lds_bytes<T>(NP));
-        for (int i = threadIdx.x; i < S; i += kLuThreads) xs[i] = s.xJ[size_t(slot) * S + i];
+        for (int i = threadIdx.x; i < S; i += lu_threads<T>) xs[i] = s.xJ[size_t(slot) * S + i];
         __syncthreads();
         double *jv = s.jval + size_t(slot) * n.nnzJ;
-        jacobian_values<kLuThreads>(n, s.k + size_t(slot) * n.R, xs, jv);
+        jacobian_values<lu_threads<T>>(n, s.k + size_t(slot) * n.R, xs, jv);
         __syncthreads();
         NewtonMatrixSource<T> src{n.jidx, jv, S, NP, c};
         lu_factor_left<T>(slot_lu<T>(s, slot), NP, s.perm + size_t(slot) * NP, slot_dinv<T>(s, slot), nullptr,
@@ -938,6 +938,8 @@ __global__ void k_grad_sum(const double *g_cell, long long cells, int R, double 
     out[r] = acc;
 }
 
+constexpr int kAsmThreads = 512;   // workgroup of the stand-alone Newton-matrix assembly
+
 // dL/dphi of one cell (one workgroup) from its dL/dlog alpha: five sums over
 // reactions of g_r d log k_r / d phi_j (paper Sec. 2, App. B.1 rate laws).
 __global__ void __launch_bounds__(kBlock) k_phys_grad(DeviceNet n, PhysArgs p, const double *g_cell, double *out) {
@@ -997,16 +999,16 @@ __global__ void __launch_bounds__(kBlock) k_rhs_only(DeviceNet n, const double *
 
 // Writes the unpadded S x S Newton matrix of each cell, assembled by the same
 // code as the solver's factor kernel (into a padded work matrix W).
-__global__ void __launch_bounds__(kLuThreads) k_newton_matrix_only(DeviceNet n, const double *k, const double *x,
+__global__ void __launch_bounds__(kAsmThreads) k_newton_matrix_only(DeviceNet n, const double *k, const double *x,
                                                                   const double *cvec, double *W, double *M) {
     extern __shared__ double smem[];
     const long long c = blockIdx.x;
     double *xs = smem;
-    for (int i = threadIdx.x; i < n.S; i += kLuThreads) xs[i] = x[size_t(c) * n.S + i];
+    for (int i = threadIdx.x; i < n.S; i += kAsmThreads) xs[i] = x[size_t(c) * n.S + i];
     __syncthreads();
     double *Wc = W + size_t(c) * n.NP * n.NP;
-    assemble_newton_matrix<double, kLuThreads>(n, k + size_t(c) * n.R, xs, cvec[c], Wc);
-    for (size_t e = threadIdx.x; e < size_t(n.S) * n.S; e += kLuThreads)
+    assemble_newton_matrix<double, kAsmThreads>(n, k + size_t(c) * n.R, xs, cvec[c], Wc);
+    for (size_t e = threadIdx.x; e < size_t(n.S) * n.S; e += kAsmThreads)
         M[size_t(c) * n.S * n.S + e] = Wc[(e / n.S) * n.NP + e % n.S];
 }
 
@@ -1040,7 +1042,7 @@ __global__ void k_copy_perm(int n, int NP, const int32_t *perm, int32_t *permW) 
 }
 
 template <typename T>
-__global__ void __launch_bounds__(kLuThreads) k_lu_factor_only(int NP, T *W, int32_t *permW, T *dinv,
+__global__ void __launch_bounds__(lu_threads<T>) k_lu_factor_only(int NP, T *W, int32_t *permW, T *dinv,
                                                               int32_t *info) {
     extern __shared__ double smem[];
     const long long b = blockIdx.x;
@@ -1050,13 +1052,13 @@ __global__ void __launch_bounds__(kLuThreads) k_lu_factor_only(int NP, T *W, int
 }
 
 // Inverse diagonal blocks of LAPACK-layout factors (rows already in P A order).
-__global__ void __launch_bounds__(kLuThreads) k_dinv_only(int NP, const double *W, double *dinv) {
+__global__ void __launch_bounds__(lu_threads<double>) k_dinv_only(int NP, const double *W, double *dinv) {
     extern __shared__ double smem[];
     const long long b = blockIdx.x;
     double *Cb = smem, *Xb = Cb + kLuW * kLdb, *Yb = Xb + kLuW * kLdb, *Tb = Yb + kLuW * kLdb;
     for (int j = 0; j * kLuW < NP; ++j) {
         const int r0 = j * kLuW, Wj = min(kLuW, NP - r0);
-        for (int e = threadIdx.x; e < Wj * Wj; e += kLuThreads)
+        for (int e = threadIdx.x; e < Wj * Wj; e += lu_threads<double>)
             Cb[(e / Wj) * kLdb + e % Wj] = W[b * NP * NP + size_t(r0 + e / Wj) * NP + r0 + e % Wj];
         __syncthreads();
         diag_inverses<double>(Cb, Wj, dinv + b * lu2_dinv_elems<double>(NP) + size_t(j) * 2 * kLuW * kLuW, Xb, Yb,
@@ -1143,8 +1145,8 @@ int resident_per_cu(int which, int prec, size_t lds) {
     hipError_t e;
     if (which == 0)
         e = prec == ABDF_PREC_FP32_LU
-                ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_factor<float>, kLuThreads, lds)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_factor<double>, kLuThreads, lds);
+                ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_factor<float>, lu_threads<float>, lds)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_factor<double>, lu_threads<double>, lds);
     else if (which == 1)
         e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_newton_rhs, kBlock, lds);
     else if (which == 2)
@@ -1181,11 +1183,11 @@ hipError_t launch_factor(const Slots &s, const DeviceNet &n, int ring, int grid,
                          size_t lds32, hipStream_t st) {
     if (grid == 0) return hipSuccess;
     if (s.prec == ABDF_PREC_FP32_LU) {
-        hipLaunchKernelGGL(k_factor<float>, dim3(grid), dim3(kLuThreads), lds32, st, s, n, ring);
+        hipLaunchKernelGGL(k_factor<float>, dim3(grid), dim3(lu_threads<float>), lds32, st, s, n, ring);
         hipError_t e = LAUNCH_CHECK();
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL(k_factor<double>, dim3(s.prec == ABDF_PREC_FP32_LU ? grid64 : grid), dim3(kLuThreads), lds,
+    hipLaunchKernelGGL(k_factor<double>, dim3(s.prec == ABDF_PREC_FP32_LU ? grid64 : grid), dim3(lu_threads<double>), lds,
                        st, s, n, ring);
     return LAUNCH_CHECK();
 }
@@ -1274,7 +1276,7 @@ hipError_t launch_rhs(const DeviceNet &n, long long cells, const double *k, cons
 hipError_t launch_newton_matrix(const DeviceNet &n, long long cells, const double *k, const double *x,
                                 const double *c, double *M, double *W, hipStream_t st) {
     const size_t lds = sizeof(double) * size_t(n.S);
-    hipLaunchKernelGGL(k_newton_matrix_only, dim3(cells), dim3(kLuThreads), lds, st, n, k, x, c, W, M);
+    hipLaunchKernelGGL(k_newton_matrix_only, dim3(cells), dim3(kAsmThreads), lds, st, n, k, x, c, W, M);
     return LAUNCH_CHECK();
 }
 
@@ -1283,12 +1285,12 @@ hipError_t launch_lu_factor(int n, int NP, long long batch, double *A, void *W, 
     dim3 g(std::max(1, std::min(64, (NP * NP + 255) / 256)), unsigned(batch));
     if (prec == ABDF_PREC_FP32_LU) {
         hipLaunchKernelGGL(k_pad_in<float>, g, dim3(256), 0, st, n, NP, A, (float *)W);
-        hipLaunchKernelGGL(k_lu_factor_only<float>, dim3(batch), dim3(kLuThreads), lu2_lds_bytes<float>(NP), st, NP,
+        hipLaunchKernelGGL(k_lu_factor_only<float>, dim3(batch), dim3(lu_threads<float>), lu2_lds_bytes<float>(NP), st, NP,
                            (float *)W, permW, (float *)dinv, info);
         hipLaunchKernelGGL(k_pad_out<float>, g, dim3(256), 0, st, n, NP, (const float *)W, A, permW, perm);
     } else {
         hipLaunchKernelGGL(k_pad_in<double>, g, dim3(256), 0, st, n, NP, A, (double *)W);
-        hipLaunchKernelGGL(k_lu_factor_only<double>, dim3(batch), dim3(kLuThreads), lu2_lds_bytes<double>(NP), st,
+        hipLaunchKernelGGL(k_lu_factor_only<double>, dim3(batch), dim3(lu_threads<double>), lu2_lds_bytes<double>(NP), st,
                            NP, (double *)W, permW, (double *)dinv, info);
         hipLaunchKernelGGL(k_pad_out<double>, g, dim3(256), 0, st, n, NP, (const double *)W, A, permW, perm);
     }
@@ -1300,7 +1302,7 @@ hipError_t launch_lu_solve(int n, int NP, long long batch, const double *LU, con
     dim3 g(std::max(1, std::min(64, (NP * NP + 255) / 256)), unsigned(batch));
     hipLaunchKernelGGL(k_pad_in<double>, g, dim3(256), 0, st, n, NP, LU, (double *)W);
     hipLaunchKernelGGL(k_copy_perm, dim3(unsigned(batch)), dim3(256), 0, st, n, NP, perm, permW);
-    hipLaunchKernelGGL(k_dinv_only, dim3(batch), dim3(kLuThreads), sizeof(double) * (3 * kLuW * kLdb + 1536), st,
+    hipLaunchKernelGGL(k_dinv_only, dim3(batch), dim3(lu_threads<double>), sizeof(double) * (3 * kLuW * kLdb + 1536), st,
                        NP, (const double *)W, (double *)dinv);
     hipLaunchKernelGGL(k_lu_solve_only, dim3(batch), dim3(kBlock), sizeof(double) * 2 * NP, st, NP, n,
                        (const double *)W, (const double *)dinv, permW, b);
