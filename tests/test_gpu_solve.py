@@ -134,3 +134,25 @@ def test_fp32_lu_form_matches_oracle(ab, dev):
         assert stats["n_lu_fp64"][c] <= stats["n_lu"][c]
     x64, _, st64 = solve_cells(ab, g, cells, dev)
     assert np.all(st64["n_lu_fp64"] == st64["n_lu"])
+
+
+@pytest.mark.parametrize("name,seed", [("net500", 3001), ("net200", 2001)])
+def test_full_batch_sampled_against_oracle(ab, dev, name, seed):
+    # the 4096-cell batch the benchmark times, in its launch configuration: every
+    # cell finishes and conserves elements and charge; seeded cells spread over
+    # the batch match the oracle, in FP64 and in the FP32-LU form
+    net = synth.network_for_config(name)
+    cells = synth.sample_cells(net, 4096, seed=seed, t_end_yr=1e6)
+    g = ab.Network.from_text(net.to_text())
+    x, status, _ = solve_cells(ab, g, cells, dev)
+    x32, status32, _ = solve_cells(ab, g, cells, dev, precision="fp32_lu")
+    assert (status == 0).all() and (status32 == 0).all()
+    W = net.conservation_matrix().astype(float)
+    w0 = cells.x0 @ W.T
+    bound = 1e-12 * (np.abs(x) @ np.abs(W).T) + 1e-8 * np.abs(x).sum(axis=1, keepdims=True)
+    assert np.all(np.abs(x @ W.T - w0) <= bound)
+    sample = np.sort(np.random.default_rng(seed + 7).choice(4096, 3, replace=False))
+    refs = oracle_cells(net, cells.subset(sample))
+    for j, c in enumerate(sample):
+        assert rel_err_above(x[c], refs[j].x) <= TOL, (c, rel_err_above(x[c], refs[j].x))
+        assert rel_err_above(x32[c], refs[j].x) <= TOL, (c, rel_err_above(x32[c], refs[j].x))
