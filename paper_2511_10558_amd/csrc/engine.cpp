@@ -275,12 +275,29 @@ int Engine::newton_iterations(int which, hipStream_t st, std::string &err) {
     return ABDF_OK;
 }
 
+// Below this many occupied slots an attempt runs on one stream.
+constexpr int kSplitMinSlots = 32;
+
 // One step attempt.  The slots whose factorisation is current iterate on the
 // side stream while the others are factored on st: the factorisation kernel is
 // LDS-bound at a few workgroups per CU and leaves CUs idle in its last round,
 // which the side stream's kernels fill.  Control waits for both streams.
 int Engine::attempt(hipStream_t st, std::string &err) {
     if (bound_ <= 0) return ABDF_OK;
+    if (bound_ < kSplitMinSlots) {
+        // a handful of cells: launch latency dominates, one stream
+        hipEvent_t t0 = timer_begin(st);
+        HIP_TRY(launch_factor(s_, dn_, ring_, std::min(bound_, grid_factor_max_),
+                              std::min(bound_, grid_factor64_max_), lds_factor_, lds_factor32_, st));
+        timer_end(ABDF_PROF_FACTOR, t0, st);
+        int rc = newton_iterations(kListAll, st, err);
+        if (rc != ABDF_OK) return rc;
+        t0 = timer_begin(st);
+        HIP_TRY(launch_control(s_, ring_, bound_, st));
+        timer_end(ABDF_PROF_CONTROL, t0, st);
+        ring_ = (ring_ + 1) % 3;
+        return ABDF_OK;
+    }
     HIP_TRY(hipEventRecord(ev_lists_, st));
     hipEvent_t t0 = timer_begin(st);
     HIP_TRY(launch_factor(s_, dn_, ring_, std::min(bound_, grid_factor_max_), std::min(bound_, grid_factor64_max_),
