@@ -290,8 +290,14 @@ int Engine::attempt(hipStream_t st, std::string &err) {
         HIP_TRY(launch_factor(s_, dn_, ring_, std::min(bound_, grid_factor_max_),
                               std::min(bound_, grid_factor64_max_), lds_factor_, lds_factor32_, st));
         timer_end(ABDF_PROF_FACTOR, t0, st);
-        int rc = newton_iterations(kListAll, st, err);
-        if (rc != ABDF_OK) return rc;
+        if (prec_ == ABDF_PREC_FP64) {
+            t0 = timer_begin(st);
+            HIP_TRY(launch_newton_fused(s_, dn_, ring_, kListAll, bound_, std::max(lds_newton_, lds_solve_), st));
+            timer_end(ABDF_PROF_NEWTON, t0, st);
+        } else {
+            int rc = newton_iterations(kListAll, st, err);
+            if (rc != ABDF_OK) return rc;
+        }
         t0 = timer_begin(st);
         HIP_TRY(launch_control(s_, ring_, bound_, st));
         timer_end(ABDF_PROF_CONTROL, t0, st);

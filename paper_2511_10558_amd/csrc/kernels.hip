@@ -324,122 +324,158 @@ __global__ void __launch_bounds__(lu_threads<T>) k_factor(Slots s, DeviceNet n, 
     }
 }
 
-// Newton residual r = c f(x) - psi - d of every active slot still iterating
-// (persistent).  A non-finite f ends the attempt as a corrector failure.
+// Newton residual r = c f(x) - psi - d of one slot still iterating.  A
+// non-finite f ends the attempt as a corrector failure.  Cooperative; ends with
+// a barrier.  LDS: xs [S], rate [R], part [n_seg], f [S]; red [kWaves].
+__device__ __forceinline__ void newton_rhs_cell(const Slots &s, const DeviceNet &n, int slot, double *smem,
+                                                double *red) {
+    const int S = s.S;
+    double *xs = smem;
+    double *rate = xs + S;
+    double *part = rate + n.R;
+    double *f = part + n.n_seg;
+    const double *x = s.x + size_t(slot) * S, *d = s.d + size_t(slot) * S, *psi = s.psi + size_t(slot) * S;
+    double *rb = s.rb + size_t(slot) * S;
+    const double c = s.ctl[slot].c;
+    for (int i = threadIdx.x; i < S; i += kBlock) xs[i] = x[i];
+    __syncthreads();
+    cell_rhs(n, s.k + size_t(slot) * n.R, xs, rate, part, f);
+    bool nonfinite = false;
+    for (int i = threadIdx.x; i < S; i += kBlock) {
+        nonfinite |= !isfinite(f[i]);
+        rb[i] = c * f[i] - psi[i] - d[i];
+    }
+    nonfinite = block_any(nonfinite, red);
+    if (threadIdx.x == 0) {
+        SlotCtl &g = s.ctl[slot];
+        g.n_rhs += 1;
+        if (nonfinite) {
+            g.n_newton_iter += 1;
+            g.newton_iter += 1;
+            g.m_last = g.newton_iter;
+            g.phase = kFailed;
+        }
+    }
+    __syncthreads();
+}
+
+// Newton correction Delta = M^{-1} r of one slot, its weighted norm, the
+// convergence and divergence tests, and the update x += Delta, d += Delta.
+// The refining variant (FP32 factors after a corrector failure) refines once in FP64:
+// Delta += M^{-1} (r - (Delta - c J(x_J) Delta)), J applied through the
+// network's Jacobian term lists.  Cooperative; ends with a barrier.
+// LDS: b, y [NP] (refining: y2 [NP], xs [S], drate [R], part [n_seg]);
+// red [kLuW + kWaves]; decision: one shared int.
+template <typename T, bool kRefine>
+__device__ __forceinline__ void newton_solve_cell(const Slots &s, const DeviceNet &n, int slot, double *smem,
+                                                  double *red, int *decision) {
+    const int S = s.S, NP = s.NP;
+    double *b = smem;
+    double *y = b + NP;
+    double *x = s.x + size_t(slot) * S, *d = s.d + size_t(slot) * S;
+    const double *scl = s.scl + size_t(slot) * S, *rb = s.rb + size_t(slot) * S;
+    for (int i = threadIdx.x; i < NP; i += kBlock) b[i] = i < S ? rb[i] : 0.0;
+    __syncthreads();
+    const int32_t *perm = s.perm + size_t(slot) * NP;
+    const T *A = slot_lu<T>(s, slot);
+    const T *Di = slot_dinv<T>(s, slot);
+    lu_solve_left<T>(A, Di, perm, perm, NP, b, y, red);
+    if (kRefine) {
+        double *y2 = y + NP, *xs = y2 + NP, *drate = xs + S, *part = drate + n.R;
+        const double c = s.ctl[slot].c_lu;
+        for (int i = threadIdx.x; i < S; i += kBlock) xs[i] = s.xJ[size_t(slot) * S + i];
+        __syncthreads();
+        cell_jvp(n, s.k + size_t(slot) * n.R, xs, y, drate, part, y2);   // y2 = J(x_J) y
+        for (int i = threadIdx.x; i < NP; i += kBlock) b[i] = i < S ? rb[i] - (y[i] - c * y2[i]) : 0.0;
+        __syncthreads();
+        lu_solve_left<T>(A, Di, perm, perm, NP, b, y2, red);
+        for (int i = threadIdx.x; i < NP; i += kBlock) y[i] = y[i] + y2[i];
+        __syncthreads();
+    }
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < S; i += kBlock) {
+        const double v = y[i] / scl[i];
+        acc += v * v;
+    }
+    const double eta = sqrt(block_sum(acc, red + kLuW) / S);
+    if (threadIdx.x == 0) {
+        SlotCtl &g = s.ctl[slot];
+        const int m = g.newton_iter + 1;
+        const double tol = g.newton_tol;
+        bool fail = false, conv = false;
+        double theta = -1.0;
+        if (m > 1) {
+            theta = eta / g.eta_old;
+            fail = theta >= 1.0 || pow(theta, double(kNewtonMaxIter - m)) / (1.0 - theta) * eta > tol;
+        }
+        if (!fail) conv = eta == 0.0 || (m > 1 && theta / (1.0 - theta) * eta < tol);
+        if (!fail && !conv && m == kNewtonMaxIter) fail = true;
+        g.n_newton_iter += 1;
+        g.newton_iter = m;
+        g.m_last = m;
+        g.eta_old = eta;
+        *decision = fail ? kFailed : (conv ? kConverged : kIter);
+        g.phase = *decision;
+    }
+    __syncthreads();
+    // a failed attempt discards x and d, so they are only updated otherwise
+    if (*decision != kFailed) {
+        for (int i = threadIdx.x; i < S; i += kBlock) {
+            x[i] = x[i] + y[i];
+            d[i] = d[i] + y[i];
+        }
+    }
+    __syncthreads();
+}
+
+// Newton residuals of every listed slot still iterating (persistent).
 __global__ void __launch_bounds__(kBlock) k_newton_rhs(Slots s, DeviceNet n, int ring, int which) {
     extern __shared__ double smem[];
     __shared__ double red[kWaves];
     int count;
     const int32_t *list = slot_list(s, which, ring, count);
-    const int S = s.S;
     for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
         const int slot = list[idx];
         if (s.ctl[slot].phase != kIter) continue;
-        double *xs = smem;
-        double *rate = xs + S;
-        double *part = rate + n.R;
-        double *f = part + n.n_seg;
-        const double *x = s.x + size_t(slot) * S, *d = s.d + size_t(slot) * S, *psi = s.psi + size_t(slot) * S;
-        double *rb = s.rb + size_t(slot) * S;
-        const double c = s.ctl[slot].c;
-        for (int i = threadIdx.x; i < S; i += kBlock) xs[i] = x[i];
-        __syncthreads();
-        cell_rhs(n, s.k + size_t(slot) * n.R, xs, rate, part, f);
-        bool nonfinite = false;
-        for (int i = threadIdx.x; i < S; i += kBlock) {
-            nonfinite |= !isfinite(f[i]);
-            rb[i] = c * f[i] - psi[i] - d[i];
-        }
-        nonfinite = block_any(nonfinite, red);
-        if (threadIdx.x == 0) {
-            SlotCtl &g = s.ctl[slot];
-            g.n_rhs += 1;
-            if (nonfinite) {
-                g.n_newton_iter += 1;
-                g.newton_iter += 1;
-                g.m_last = g.newton_iter;
-                g.phase = kFailed;
-            }
-        }
-        __syncthreads();
+        newton_rhs_cell(s, n, slot, smem, red);
     }
 }
 
-// Newton correction Delta = M^{-1} r, its weighted norm, the convergence and
-// divergence tests, and the update x += Delta, d += Delta (persistent).
-// The refining variant (FP32 factors after a corrector failure) refines once in FP64:
-// Delta += M^{-1} (r - (Delta - c J(x_J) Delta)), J applied through the
-// network's Jacobian term lists.
+// Newton corrections of every listed slot still iterating (persistent); in an
+// FP32-LU engine each variant takes the slots of its factor mode.
 template <typename T, bool kRefine>
 __global__ void __launch_bounds__(kBlock) k_newton_solve(Slots s, DeviceNet n, int ring, int which) {
     extern __shared__ double smem[];
     __shared__ double red[kLuW + kWaves];
     __shared__ int decision;
-    // the factor mode this variant serves in an FP32-LU engine
     constexpr int32_t kMode = sizeof(T) == sizeof(double) ? kLu64 : (kRefine ? kLuRefined32 : kLuPlain32);
     int count;
     const int32_t *list = slot_list(s, which, ring, count);
-    const int S = s.S, NP = s.NP;
     for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
         const int slot = list[idx];
         if (s.ctl[slot].phase != kIter) continue;
         if (s.prec == ABDF_PREC_FP32_LU && s.ctl[slot].lu_mode != kMode) continue;
-        double *b = smem;
-        double *y = b + NP;
-        double *x = s.x + size_t(slot) * S, *d = s.d + size_t(slot) * S;
-        const double *scl = s.scl + size_t(slot) * S, *rb = s.rb + size_t(slot) * S;
-        for (int i = threadIdx.x; i < NP; i += kBlock) b[i] = i < S ? rb[i] : 0.0;
-        __syncthreads();
-        const int32_t *perm = s.perm + size_t(slot) * NP;
-        const T *A = slot_lu<T>(s, slot);
-        const T *Di = slot_dinv<T>(s, slot);
-        lu_solve_left<T>(A, Di, perm, perm, NP, b, y, red);
-        if (kRefine) {
-            double *y2 = y + NP, *xs = y2 + NP, *drate = xs + S, *part = drate + n.R;
-            const double c = s.ctl[slot].c_lu;
-            for (int i = threadIdx.x; i < S; i += kBlock) xs[i] = s.xJ[size_t(slot) * S + i];
-            __syncthreads();
-            cell_jvp(n, s.k + size_t(slot) * n.R, xs, y, drate, part, y2);   // y2 = J(x_J) y
-            for (int i = threadIdx.x; i < NP; i += kBlock) b[i] = i < S ? rb[i] - (y[i] - c * y2[i]) : 0.0;
-            __syncthreads();
-            lu_solve_left<T>(A, Di, perm, perm, NP, b, y2, red);
-            for (int i = threadIdx.x; i < NP; i += kBlock) y[i] = y[i] + y2[i];
-            __syncthreads();
+        newton_solve_cell<T, kRefine>(s, n, slot, smem, red, &decision);
+    }
+}
+
+// Every Newton iteration of each listed slot in one launch (FP64 factors), for
+// attempts of a few cells where launches dominate: per slot, the same sequence
+// of residuals and corrections as the separate kernels.
+__global__ void __launch_bounds__(kBlock) k_newton_fused(Slots s, DeviceNet n, int ring, int which) {
+    extern __shared__ double smem[];
+    __shared__ double red[kLuW + kWaves];
+    __shared__ int decision;
+    int count;
+    const int32_t *list = slot_list(s, which, ring, count);
+    for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
+        const int slot = list[idx];
+        for (int m = 0; m < kNewtonMaxIter; ++m) {
+            if (s.ctl[slot].phase != kIter) break;
+            newton_rhs_cell(s, n, slot, smem, red);
+            if (s.ctl[slot].phase != kIter) break;
+            newton_solve_cell<double, false>(s, n, slot, smem, red, &decision);
         }
-        double acc = 0.0;
-        for (int i = threadIdx.x; i < S; i += kBlock) {
-            const double v = y[i] / scl[i];
-            acc += v * v;
-        }
-        const double eta = sqrt(block_sum(acc, red + kLuW) / S);
-        if (threadIdx.x == 0) {
-            SlotCtl &g = s.ctl[slot];
-            const int m = g.newton_iter + 1;
-            const double tol = g.newton_tol;
-            bool fail = false, conv = false;
-            double theta = -1.0;
-            if (m > 1) {
-                theta = eta / g.eta_old;
-                fail = theta >= 1.0 || pow(theta, double(kNewtonMaxIter - m)) / (1.0 - theta) * eta > tol;
-            }
-            if (!fail) conv = eta == 0.0 || (m > 1 && theta / (1.0 - theta) * eta < tol);
-            if (!fail && !conv && m == kNewtonMaxIter) fail = true;
-            g.n_newton_iter += 1;
-            g.newton_iter = m;
-            g.m_last = m;
-            g.eta_old = eta;
-            decision = fail ? kFailed : (conv ? kConverged : kIter);
-            g.phase = decision;
-        }
-        __syncthreads();
-        // a failed attempt discards x and d, so they are only updated otherwise
-        if (decision != kFailed) {
-            for (int i = threadIdx.x; i < S; i += kBlock) {
-                x[i] = x[i] + y[i];
-                d[i] = d[i] + y[i];
-            }
-        }
-        __syncthreads();
     }
 }
 
@@ -1196,6 +1232,13 @@ hipError_t launch_newton_rhs(const Slots &s, const DeviceNet &n, int ring, int w
                              hipStream_t st) {
     if (grid == 0) return hipSuccess;
     hipLaunchKernelGGL(k_newton_rhs, dim3(grid), dim3(kBlock), lds, st, s, n, ring, which);
+    return LAUNCH_CHECK();
+}
+
+hipError_t launch_newton_fused(const Slots &s, const DeviceNet &n, int ring, int which, int grid, size_t lds,
+                               hipStream_t st) {
+    if (grid == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_newton_fused, dim3(grid), dim3(kBlock), lds, st, s, n, ring, which);
     return LAUNCH_CHECK();
 }
 

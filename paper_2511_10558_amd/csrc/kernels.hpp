@@ -76,6 +76,10 @@ hipError_t launch_newton_rhs(const Slots &s, const DeviceNet &n, int ring, int w
                              hipStream_t st);
 // FP32-LU engines launch the plain FP32 (grid), the refining FP32 (grid_ref,
 // lds_ref) and the FP64 (grid64) variants; FP64 engines only the last (grid).
+// All Newton iterations of the listed slots in one launch (FP64 engines; LDS:
+// the larger of newton_lds and solve_lds).
+hipError_t launch_newton_fused(const Slots &s, const DeviceNet &n, int ring, int which, int grid, size_t lds,
+                               hipStream_t st);
 hipError_t launch_newton_solve(const Slots &s, const DeviceNet &n, int ring, int which, int grid, int grid_ref,
                                int grid64, size_t lds, size_t lds_ref, hipStream_t st);
 hipError_t launch_control(const Slots &s, int ring, int grid, hipStream_t st);
