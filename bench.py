@@ -374,7 +374,7 @@ def main():
                          "(a reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py measures one GPU: the cells are independent and this build runs on one "
+        print("bench.py measures one GPU: the cells are independent and this benchmark runs on one "
               "MI355X; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 

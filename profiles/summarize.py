@@ -58,7 +58,7 @@ def main():
     trace, fetch, write, flog = sys.argv[1:5]
     rows = list(csv.DictReader(open(os.path.join(trace, "run_kernel_stats.csv"))))
     out = ["# rocprofv3 kernel statistics: 500-species / 6000-reaction network, 4096 cells, FP64", "",
-           "Command (repo root, on the GPU box):", "",
+           "Command (repo root, on one MI355X):", "",
            "    rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o run -- "
            "python3 bench.py --cells 4096 --steps 1 --warmup 0 --no-cpu-baseline --no-compare-fp32", "",
            "| kernel | calls | total ms | average us | % |", "|---|---|---|---|---|"]
