@@ -280,7 +280,11 @@ def run_single(args):
     from oracle import bdf, chem
     net = synth.network_for_config("small")
     cells = synth.single_cell(net)
+    # CPU baseline: the oracle on the same cell, one thread (its result also
+    # gives the error of the GPU solve)
+    t0 = time.perf_counter()
     ref = bdf.solve(chem.cell_chemistry(net, cells.cell(0)), cells.x0[0], cells.t_end[0], 1e-6, 1e-20)
+    cpu_us = (time.perf_counter() - t0) * 1e6
     dev = torch.device("cuda:0")
     g = ab.Network.from_text(net.to_text())
     t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
@@ -303,7 +307,9 @@ def run_single(args):
                                   "rtol 1e-6 atol 1e-20", "repeats": len(times)},
            "steps": int(stats["n_steps"][0]), "oracle_steps": int(ref.stats.n_steps),
            "max_rel_err_vs_oracle": float(np.max(np.abs(xg[m] - ref.x[m]) / ref.x[m])),
-           "status": int(st[0])}
+           "status": int(st[0]),
+           "cpu_baseline": {"value": round(cpu_us, 1), "unit": "us", "cores": 1, "kind": "oracle",
+                            "sample": "the same cell, one solve"}}
     print(json.dumps(out))
 
 
