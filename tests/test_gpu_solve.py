@@ -156,3 +156,20 @@ def test_full_batch_sampled_against_oracle(ab, dev, name, seed):
     for j, c in enumerate(sample):
         assert rel_err_above(x[c], refs[j].x) <= TOL, (c, rel_err_above(x[c], refs[j].x))
         assert rel_err_above(x32[c], refs[j].x) <= TOL, (c, rel_err_above(x32[c], refs[j].x))
+
+
+def test_largest_and_too_large_networks(ab, dev):
+    # 512 species fill the factorisation's 512 x 512 tile exactly; 513 do not fit
+    net = synth.large_network(512, 6000, seed=512)
+    g = ab.Network.from_text(net.to_text())
+    cells = synth.sample_cells(net, 2, seed=5121, t_end_yr=1e5)
+    x, status, _ = solve_cells(ab, g, cells, dev)
+    refs = oracle_cells(net, cells)
+    for c in range(2):
+        assert status[c] == 0
+        assert rel_err_above(x[c], refs[c].x) <= TOL
+    big = synth.large_network(513, 6000, seed=513)
+    gb = ab.Network.from_text(big.to_text())
+    with pytest.raises(ab.AbdfError) as e:
+        solve_cells(ab, gb, synth.sample_cells(big, 1, seed=1), dev)
+    assert e.value.code == 1 and "too large" in str(e.value)
