@@ -373,6 +373,10 @@ def main():
     ap.add_argument("--seed", type=int, default=3001)
     ap.add_argument("--cpu-sample", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--lu-reuse", type=float, default=0.0,
+                    help="keep a factorisation while |c/c_lu - 1| <= this (0: refactor whenever c changes)")
+    ap.add_argument("--compare-reuse", type=float, default=0.3,
+                    help="also time the batch with this factorisation-reuse threshold (0: skip)")
     ap.add_argument("--no-compare-fp32", dest="compare_fp32", action="store_false",
                     help="skip the FP32-LU run of the same batch")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -408,7 +412,7 @@ def main():
     g = ab.Network.from_text(net.to_text())
     t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
     inp = [t(cells.T), t(cells.n_H), t(cells.A_V), t(cells.zeta), t(cells.G0), t(cells.x0), t(cells.t_end)]
-    opts = ab.make_options(rtol=1e-6, atol=1e-20, precision=args.precision)
+    opts = ab.make_options(rtol=1e-6, atol=1e-20, precision=args.precision, lu_reuse=args.lu_reuse)
 
     if args.calibrate_copy:
         src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
@@ -502,7 +506,8 @@ def main():
         "dtype": "f64" if args.precision == "fp64" else "f64 (f32 LU)",
         "data": "synthetic",
         "config": {"workload": f"{args.network}: {S} species / {R} reactions, batch of {args.cells} cells, "
-                               f"t_end {args.t_end_yr:g} yr, rtol 1e-6 atol 1e-20, {args.precision} Newton LU",
+                               f"t_end {args.t_end_yr:g} yr, rtol 1e-6 atol 1e-20, {args.precision} Newton LU"
+                               + (f", factorisation kept while |c/c_lu - 1| <= {args.lu_reuse:g}" if args.lu_reuse else ""),
                    "cells": args.cells, "species": S, "reactions": R, "precision": args.precision,
                    "parallelism": "one GPU, cells across workgroups"},
         "work": {"cells_ok": ok, "factorisations": int(n_lu), "newton_iterations": int(n_newton),
@@ -525,12 +530,28 @@ def main():
         out["fp32_lu"] = {"value": round(ok32 / w32, 3), "unit": "cell-solves/s", "cells_ok": ok32,
                           "speedup_vs_fp64": round((ok32 / w32) / value, 4),
                           "max_rel_dev_from_fp64_gpu": max_rel_err(x32.cpu().numpy(), x64)}
+    if args.compare_reuse > 0 and args.lu_reuse == 0:
+        # the same batch keeping factorisations across small changes of c
+        o_r = ab.make_options(rtol=1e-6, atol=1e-20, precision=args.precision, lu_reuse=args.compare_reuse)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        xr, str_, sr = ab.solve(g, *inp, options=o_r, with_stats=True)
+        torch.cuda.synchronize()
+        wr = time.perf_counter() - t0
+        okr = int((str_ == 0).sum().item())
+        progress(f"lu_reuse {args.compare_reuse} solve: {wr:.1f} s")
+        out["lu_reuse"] = {"lu_reuse": args.compare_reuse, "value": round(okr / wr, 3), "unit": "cell-solves/s",
+                           "cells_ok": okr, "speedup_vs_default": round((okr / wr) / value, 4),
+                           "factorisations": int(sr["n_lu"].sum()),
+                           "max_rel_dev_from_default_gpu": max_rel_err(xr.cpu().numpy(), x64)}
     if cpu_rec is not None:
         n = len(xo)
         out["cpu_baseline"] = cpu_rec
         out["parity_vs_oracle"] = {"cells": n, "max_rel_err_fp64": max_rel_err(x64[:n], xo)}
         if "fp32_lu" in out:
             out["parity_vs_oracle"]["max_rel_err_fp32_lu"] = max_rel_err(x32.cpu().numpy()[:n], xo)
+        if "lu_reuse" in out:
+            out["parity_vs_oracle"]["max_rel_err_lu_reuse"] = max_rel_err(xr.cpu().numpy()[:n], xo)
     print(json.dumps(out))
 
 

@@ -84,6 +84,11 @@ typedef struct abdf_options {
     int32_t reserved0;
     uint64_t hbm_budget_bytes; /* bound on the library's device workspace, 0 = no bound */
     double newton_tol;         /* 0 = max(10 u / rtol, min(0.03, sqrt(rtol))) */
+    double lu_reuse;           /* keep a cell's Newton-matrix factorisation while
+                                * |c / c_lu - 1| <= lu_reuse, c = h / gamma_q and
+                                * c_lu the value it was formed at, scaling each
+                                * correction by 2 / (1 + c / c_lu); 0 (default) =
+                                * refactor whenever c changes.  In [0, 1). */
 } abdf_options;
 
 /* Per-cell counters (written to a DEVICE array of n_cells structs). */

@@ -21,6 +21,7 @@ class Options(ctypes.Structure):
         ("reserved0", ctypes.c_int32),
         ("hbm_budget_bytes", ctypes.c_uint64),
         ("newton_tol", ctypes.c_double),
+        ("lu_reuse", ctypes.c_double),
     ]
 
 

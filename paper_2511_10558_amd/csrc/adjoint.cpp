@@ -84,6 +84,7 @@ int Tape::record(const BatchIO &io, const double *alpha, const abdf_options &opt
         return ABDF_E_NOMEM;
     }
     eng_ = std::make_unique<Engine>(net_, dn_, opt.precision, opt.max_steps);
+    eng_->set_lu_reuse(opt.lu_reuse);
     int rc = eng_->init(int(nslots), err);
     if (rc != ABDF_OK) return rc;
     Slots &s = eng_->slots();

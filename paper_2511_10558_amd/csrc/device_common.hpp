@@ -44,6 +44,7 @@ struct SlotCtl {
 // Device workspace for n slots of one network (all arrays slot-major).
 struct Slots {
     int nslots, S, R, NP, prec, max_steps;
+    double lu_reuse;  // keep the factorisation while |c / c_lu - 1| <= lu_reuse (0: while c == c_lu)
     SlotCtl *ctl;
     double *phi;      // [n][5]: T, n_H, A_V, zeta, G0
     double *k;        // [n][R]

@@ -51,6 +51,8 @@ class Engine {
     ~Engine();
     // Allocates room for up to `nslots` slots; returns an abdf_status.
     int init(int nslots, std::string &err);
+    // relative change of c within which a slot keeps its factorisation (0: none)
+    void set_lu_reuse(double v) { lu_reuse_ = v; s_.lu_reuse = v; }
     // Bytes of device workspace per slot.
     static size_t bytes_per_slot(const DeviceNet &dn, int prec);
     // Solves every cell of io; returns an abdf_status.
@@ -98,6 +100,7 @@ class Engine {
     const HostNetwork &net_;
     const DeviceNet &dn_;
     int prec_, max_steps_;
+    double lu_reuse_ = 0.0;
     Slots s_{};
     void *base_ = nullptr;
     int32_t *d_admit_slots_ = nullptr;

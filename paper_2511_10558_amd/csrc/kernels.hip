@@ -173,7 +173,8 @@ __device__ __forceinline__ void begin_attempt(const Slots &s, int slot, SlotCtl 
         cs.eta_old = 0.0;
         const int p = atomicAdd(&s.cnt[ring], 1);
         s.act[ring * s.nslots + p] = slot;
-        if (!cs.lu_valid || cs.c != cs.c_lu) {
+        const bool stale = s.lu_reuse > 0.0 ? !(fabs(cs.c - cs.c_lu) <= s.lu_reuse * cs.c_lu) : cs.c != cs.c_lu;
+        if (!cs.lu_valid || stale) {
             const int pl = atomicAdd(&s.cnt[3 + ring], 1);
             s.lul[ring * s.nslots + pl] = slot;
         } else {
@@ -392,6 +393,16 @@ __device__ __forceinline__ void newton_solve_cell(const Slots &s, const DeviceNe
         for (int i = threadIdx.x; i < NP; i += kBlock) y[i] = y[i] + y2[i];
         __syncthreads();
     }
+    {
+        // a factorisation kept from c_lu != c: the correction is scaled by
+        // 2 / (1 + c / c_lu), the usual remedy for the lagged leading coefficient
+        const double c = s.ctl[slot].c, c_lu = s.ctl[slot].c_lu;
+        if (c != c_lu) {
+            const double sc = 2.0 / (1.0 + c / c_lu);
+            for (int i = threadIdx.x; i < S; i += kBlock) y[i] = y[i] * sc;
+            __syncthreads();
+        }
+    }
     double acc = 0.0;
     for (int i = threadIdx.x; i < S; i += kBlock) {
         const double v = y[i] / scl[i];
@@ -516,7 +527,7 @@ __global__ void __launch_bounds__(kBlock) k_control(Slots s, int ring) {
             } else {
                 cs.h = 0.5 * cs.h;
                 cs.n_equal = 0;
-                cs.lu_valid = 0;
+                if (s.lu_reuse == 0.0) cs.lu_valid = 0;   // else the change of c decides
                 sh[0] = 0.5;
             }
         }
@@ -550,7 +561,7 @@ __global__ void __launch_bounds__(kBlock) k_control(Slots s, int ring) {
             cs.n_err_reject += 1;
             cs.h = cs.h * rho;
             cs.n_equal = 0;
-            cs.lu_valid = 0;
+            if (s.lu_reuse == 0.0) cs.lu_valid = 0;   // else the change of c decides
         }
         rescale_D(D, S, q, rho, RU);
         begin_attempt(s, slot, cs, next, RU, sh + 2);
@@ -642,7 +653,7 @@ __global__ void __launch_bounds__(kBlock) k_control(Slots s, int ring) {
             const double rho = fmin(kMaxFactor, safety * rb);
             cs.h = cs.h * rho;
             cs.n_equal = 0;
-            cs.lu_valid = 0;
+            if (s.lu_reuse == 0.0) cs.lu_valid = 0;   // else the change of c decides
             sh[0] = rho;
         }
         __syncthreads();

@@ -47,6 +47,7 @@ int Server::start(int nslots, std::string &err) {
     HIP_TRY(hipStreamCreateWithFlags(&st_, hipStreamNonBlocking));
     HIP_TRY(hipEventCreateWithFlags(&admit_done_, hipEventDisableTiming));
     eng_ = std::make_unique<Engine>(net_, dn_, opt_.solve.precision, opt_.solve.max_steps);
+    eng_->set_lu_reuse(opt_.solve.lu_reuse);
     int rc = eng_->init(nslots, err);
     if (rc != ABDF_OK) return rc;
     const size_t n = size_t(nslots), S = size_t(dn_.S);

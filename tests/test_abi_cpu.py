@@ -37,7 +37,7 @@ def test_library_exports_every_declared_symbol():
 def test_options_default_values():
     o = ab.default_options()
     assert o.rtol == 1e-6 and o.atol == 1e-20 and o.max_steps == 100000
-    assert o.precision == 0 and o.check_every == 8 and o.hbm_budget_bytes == 0
+    assert o.precision == 0 and o.check_every == 8 and o.hbm_budget_bytes == 0 and o.lu_reuse == 0.0
 
 
 @pytest.mark.parametrize("name", ["small", "net200", "net500"])
@@ -120,6 +120,10 @@ def test_null_and_invalid_arguments_without_gpu():
     assert rc == 1 and b"rtol" in L.abdf_last_error()
     o = ab.make_options(precision=7)
     assert L.abdf_solve(g.handle, 1, *([None] * 7), ctypes.byref(o), None, None, None, None) == 1
+    for bad in (-0.1, 1.0, float("nan")):
+        o = ab.make_options(lu_reuse=bad)
+        assert L.abdf_solve(g.handle, 1, *([None] * 7), ctypes.byref(o), None, None, None, None) == 1
+        assert b"lu_reuse" in L.abdf_last_error()
     o = ab.make_options()
     assert L.abdf_solve(g.handle, 0, *([None] * 7), ctypes.byref(o), None, None, None, None) == 0
     assert L.abdf_solve(g.handle, -1, *([None] * 7), ctypes.byref(o), None, None, None, None) == 1

@@ -173,3 +173,21 @@ def test_largest_and_too_large_networks(ab, dev):
     with pytest.raises(ab.AbdfError) as e:
         solve_cells(ab, gb, synth.sample_cells(big, 1, seed=1), dev)
     assert e.value.code == 1 and "too large" in str(e.value)
+
+
+def test_factorisation_reuse_across_small_c_changes(ab, dev):
+    # keeping a factorisation while |c / c_lu - 1| <= 0.3 (corrections scaled by
+    # 2 / (1 + c / c_lu)) changes the Newton iteration, not its fixed point: the
+    # results stay within the parity bar of the oracle with fewer factorisations
+    net = synth.network_for_config("net500")
+    cells = synth.sample_cells(net, 3, seed=3001)
+    g = ab.Network.from_text(net.to_text())
+    x0, st0, stats0 = solve_cells(ab, g, cells, dev)
+    x1, st1, stats1 = solve_cells(ab, g, cells, dev, lu_reuse=0.3)
+    assert (st0 == 0).all() and (st1 == 0).all()
+    assert stats1["n_lu"].sum() < stats0["n_lu"].sum()
+    refs = oracle_cells(net, cells)
+    for c in range(cells.n):
+        assert rel_err_above(x1[c], refs[c].x) <= TOL
+    with pytest.raises(ab.AbdfError):
+        solve_cells(ab, g, cells, dev, lu_reuse=1.0)
