@@ -29,8 +29,9 @@ __device__ inline void cell_rates(const DeviceNet &n, const double *phi, double 
 // the segments of a species in order.  Deterministic.
 // A segment's entries are loaded eight at a time before any is used, so the
 // loads are in flight together; the sum still runs entry by entry in order.
+template <int NT = kBlock>
 __device__ __forceinline__ void species_gather(const DeviceNet &n, const double *v, double *part, double *out) {
-    for (int s = threadIdx.x; s < n.n_seg; s += kBlock) {
+    for (int s = threadIdx.x; s < n.n_seg; s += NT) {
         const int e0 = n.seg_beg[s], e1 = n.seg_beg[s + 1];
         double acc = 0.0;
         for (int eb = e0; eb < e1; eb += 8) {
@@ -47,7 +48,7 @@ __device__ __forceinline__ void species_gather(const DeviceNet &n, const double 
         part[s] = acc;
     }
     __syncthreads();
-    for (int i = threadIdx.x; i < n.S; i += kBlock) {
+    for (int i = threadIdx.x; i < n.S; i += NT) {
         double acc = 0.0;
         for (int s = n.seg_ptr[i]; s < n.seg_ptr[i + 1]; ++s) acc += part[s];
         out[i] = acc;
@@ -58,21 +59,22 @@ __device__ __forceinline__ void species_gather(const DeviceNet &n, const double 
 // f = nu . rate(x) for one cell.  x in LDS; k in global memory (one coalesced
 // pass); rate[R] and part[n_seg] are LDS scratch; f may be LDS or global.
 // Deterministic: every sum runs in a fixed order.
+template <int NT = kBlock>
 __device__ __forceinline__ void cell_rhs(const DeviceNet &n, const double *__restrict__ k, const double *x,
                                 double *rate, double *part, double *f) {
     // four reactions per thread per pass, their loads issued before any use
-    for (int r0 = threadIdx.x; r0 < n.R; r0 += 4 * kBlock) {
+    for (int r0 = threadIdx.x; r0 < n.R; r0 += 4 * NT) {
         int ab[4];
         double kr[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const int r = r0 + u * kBlock;
+            const int r = r0 + u * NT;
             ab[u] = r < n.R ? n.rx_ab[r] : 0;
             kr[u] = r < n.R ? k[r] : 0.0;
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
-            const int r = r0 + u * kBlock;
+            const int r = r0 + u * NT;
             const int a = ab[u] & 0xffff, b = (ab[u] >> 16) & 0xffff;
             double v = kr[u] * x[a];
             if (b != 0xffff) v *= x[b];
@@ -80,7 +82,7 @@ __device__ __forceinline__ void cell_rhs(const DeviceNet &n, const double *__res
         }
     }
     __syncthreads();
-    species_gather(n, rate, part, f);
+    species_gather<NT>(n, rate, part, f);
 }
 
 // J(x) y = nu . (d rate / dx) y for one cell: per reaction

@@ -178,15 +178,20 @@ __device__ __forceinline__ void wave_argmax_ballot(double &v, int &k) {
 }
 
 // Sum over the workgroup, identical on every thread; fixed reduction order.
-__device__ inline double block_sum(double v, double *red) {
+// Sum over a workgroup of NT threads (red: NT / 64 doubles), identical on every
+// thread; fixed reduction order.
+template <int NT>
+__device__ inline double block_sum_nt(double v, double *red) {
     for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
     __syncthreads();
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
     double s = 0.0;
-    for (int w = 0; w < kWaves; ++w) s += red[w];
+    for (int w = 0; w < NT / 64; ++w) s += red[w];
     return s;
 }
+
+__device__ inline double block_sum(double v, double *red) { return block_sum_nt<kBlock>(v, red); }
 
 // Logical OR over the workgroup.
 __device__ inline bool block_any(bool p, double *red) {

@@ -328,6 +328,7 @@ __global__ void __launch_bounds__(lu_threads<T>) k_factor(Slots s, DeviceNet n, 
 // Newton residual r = c f(x) - psi - d of one slot still iterating.  A
 // non-finite f ends the attempt as a corrector failure.  Cooperative; ends with
 // a barrier.  LDS: xs [S], rate [R], part [n_seg], f [S]; red [kWaves].
+template <int NT>
 __device__ __forceinline__ void newton_rhs_cell(const Slots &s, const DeviceNet &n, int slot, double *smem,
                                                 double *red) {
     const int S = s.S;
@@ -338,15 +339,15 @@ __device__ __forceinline__ void newton_rhs_cell(const Slots &s, const DeviceNet 
     const double *x = s.x + size_t(slot) * S, *d = s.d + size_t(slot) * S, *psi = s.psi + size_t(slot) * S;
     double *rb = s.rb + size_t(slot) * S;
     const double c = s.ctl[slot].c;
-    for (int i = threadIdx.x; i < S; i += kBlock) xs[i] = x[i];
+    for (int i = threadIdx.x; i < S; i += NT) xs[i] = x[i];
     __syncthreads();
-    cell_rhs(n, s.k + size_t(slot) * n.R, xs, rate, part, f);
+    cell_rhs<NT>(n, s.k + size_t(slot) * n.R, xs, rate, part, f);
     bool nonfinite = false;
-    for (int i = threadIdx.x; i < S; i += kBlock) {
+    for (int i = threadIdx.x; i < S; i += NT) {
         nonfinite |= !isfinite(f[i]);
         rb[i] = c * f[i] - psi[i] - d[i];
     }
-    nonfinite = block_any(nonfinite, red);
+    nonfinite = block_sum_nt<NT>(nonfinite ? 1.0 : 0.0, red) != 0.0;
     if (threadIdx.x == 0) {
         SlotCtl &g = s.ctl[slot];
         g.n_rhs += 1;
@@ -439,16 +440,19 @@ __device__ __forceinline__ void newton_solve_cell(const Slots &s, const DeviceNe
     __syncthreads();
 }
 
-// Newton residuals of every listed slot still iterating (persistent).
-__global__ void __launch_bounds__(kBlock) k_newton_rhs(Slots s, DeviceNet n, int ring, int which) {
+// Newton residuals of every listed slot still iterating (persistent), with
+// kRhsThreads per slot: the residual's LDS (the rates) allows two workgroups per
+// CU, so each takes more waves.
+constexpr int kRhsThreads = 512;
+__global__ void __launch_bounds__(kRhsThreads) k_newton_rhs(Slots s, DeviceNet n, int ring, int which) {
     extern __shared__ double smem[];
-    __shared__ double red[kWaves];
+    __shared__ double red[kRhsThreads / 64];
     int count;
     const int32_t *list = slot_list(s, which, ring, count);
     for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
         const int slot = list[idx];
         if (s.ctl[slot].phase != kIter) continue;
-        newton_rhs_cell(s, n, slot, smem, red);
+        newton_rhs_cell<kRhsThreads>(s, n, slot, smem, red);
     }
 }
 
@@ -483,7 +487,7 @@ __global__ void __launch_bounds__(kBlock) k_newton_fused(Slots s, DeviceNet n, i
         const int slot = list[idx];
         for (int m = 0; m < kNewtonMaxIter; ++m) {
             if (s.ctl[slot].phase != kIter) break;
-            newton_rhs_cell(s, n, slot, smem, red);
+            newton_rhs_cell<kBlock>(s, n, slot, smem, red);
             if (s.ctl[slot].phase != kIter) break;
             newton_solve_cell<double, false>(s, n, slot, smem, red, &decision);
         }
@@ -1195,7 +1199,7 @@ int resident_per_cu(int which, int prec, size_t lds) {
                 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_factor<float>, lu_threads<float>, lds)
                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_factor<double>, lu_threads<double>, lds);
     else if (which == 1)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_newton_rhs, kBlock, lds);
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_newton_rhs, kRhsThreads, lds);
     else if (which == 2)
         e = prec == ABDF_PREC_FP32_LU
                 ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_newton_solve<float, false>, kBlock, lds)
@@ -1242,7 +1246,7 @@ hipError_t launch_factor(const Slots &s, const DeviceNet &n, int ring, int grid,
 hipError_t launch_newton_rhs(const Slots &s, const DeviceNet &n, int ring, int which, int grid, size_t lds,
                              hipStream_t st) {
     if (grid == 0) return hipSuccess;
-    hipLaunchKernelGGL(k_newton_rhs, dim3(grid), dim3(kBlock), lds, st, s, n, ring, which);
+    hipLaunchKernelGGL(k_newton_rhs, dim3(grid), dim3(kRhsThreads), lds, st, s, n, ring, which);
     return LAUNCH_CHECK();
 }
 
