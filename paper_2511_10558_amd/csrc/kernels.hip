@@ -521,6 +521,11 @@ __global__ void __launch_bounds__(kBlock) k_control(Slots s, int ring) {
                 cs.jac_refresh = 1;
                 cs.n_jac += 1;
                 sh[0] = 0.0;
+            } else if (s.lu_reuse > 0.0 && cs.c != cs.c_lu) {
+                // fresh Jacobian, factorisation kept from another c: retry the
+                // same step with the factorisation at the current c
+                cs.lu_valid = 0;
+                sh[0] = 0.0;
             } else if (s.prec == ABDF_PREC_FP32_LU && cs.lu_mode != kLu64) {
                 // the corrector failed with a fresh Jacobian and FP32 factors:
                 // the cell retries the same step with refined solves, then
