@@ -110,7 +110,7 @@ def run_serve(args):
         return srv.submit(cells.T, cells.n_H, cells.A_V, cells.zeta, cells.G0, cells.x0, cells.t_end)
 
     def one_pass(precision, arrivals):
-        with ab.Server(g, precision=precision, check_every=args.check_every) as srv:
+        with ab.Server(g, precision=precision, check_every=args.check_every, lu_reuse=args.lu_reuse) as srv:
             wid = [submit(srv, r.cells) for r in warm]
             got = 0
             while got < len(wid):
@@ -146,8 +146,11 @@ def run_serve(args):
            "unit": "cell-solves/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
            "config": {"workload": f"{args.network} serving: {len(reqs)} requests after 16 warm-up requests, "
                                   f"{n_cells} cells (1..1024 per request, mean {mean_cells:.1f}), t_end log-uniform "
-                                  "1e3..1e7 yr, rtol 1e-6 atol 1e-20", "requests": len(reqs), "cells": n_cells,
-                      "seed": args.seed}, "passes": {}}
+                                  "1e3..1e7 yr, rtol 1e-6 atol 1e-20"
+                                  + (f", factorisation kept while |c/c_lu - 1| <= {args.lu_reuse:g}"
+                                     if args.lu_reuse else ""),
+                      "requests": len(reqs), "cells": n_cells, "seed": args.seed, "lu_reuse": args.lu_reuse},
+           "passes": {}}
     for prec in args.serve_precisions.split(","):
         res = {}
         if args.rate > 0:

@@ -60,7 +60,7 @@ def main():
     out = ["# rocprofv3 kernel statistics: 500-species / 6000-reaction network, 4096 cells, FP64", "",
            "Command (repo root, on one MI355X):", "",
            "    rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o run -- "
-           "python3 bench.py --cells 4096 --steps 1 --warmup 0 --no-cpu-baseline --no-compare-fp32 --compare-reuse 0", "",
+           "python3 bench.py --cells 4096 --steps 1 --warmup 0 --no-cpu-baseline --no-compare-fp32 --no-compare-reuse", "",
            "| kernel | calls | total ms | average us | % |", "|---|---|---|---|---|"]
     for r in rows:
         if float(r["Percentage"]) < 0.01:
