@@ -147,9 +147,12 @@ def test_full_batch_sampled_against_oracle(ab, dev, name, seed):
     x, status, _ = solve_cells(ab, g, cells, dev)
     x32, status32, _ = solve_cells(ab, g, cells, dev, precision="fp32_lu")
     assert (status == 0).all() and (status32 == 0).all()
+    # W f = 0 and W (I - c J) = W, so the method keeps W x exactly in exact
+    # arithmetic; in FP64 the Newton solves' rounding lets it drift, and the
+    # oracle's own drift on this net200 batch reaches 1.2e-8 of sum |x| (cell 2840)
     W = net.conservation_matrix().astype(float)
     w0 = cells.x0 @ W.T
-    bound = 1e-12 * (np.abs(x) @ np.abs(W).T) + 1e-8 * np.abs(x).sum(axis=1, keepdims=True)
+    bound = 1e-12 * (np.abs(x) @ np.abs(W).T) + 1e-7 * np.abs(x).sum(axis=1, keepdims=True)
     assert np.all(np.abs(x @ W.T - w0) <= bound)
     sample = np.sort(np.random.default_rng(seed + 7).choice(4096, 3, replace=False))
     refs = oracle_cells(net, cells.subset(sample))
