@@ -38,7 +38,8 @@ struct SlotCtl {
     int32_t q, n_equal, status, phase, j_fresh, jac_refresh, landing, newton_iter;
     int32_t lu_valid, cell, m_last, lu_mode;   // FP32-LU engines: kLuPlain32, kLuRefined32 or kLu64
     int32_t n_steps, n_attempts, n_err_reject, n_newton_fail, n_rhs, n_jac, n_lu, n_newton_iter;
-    int32_t n_lu64, pad;                   // FP32-LU engines: factorisations done in FP64 after a fallback
+    int32_t n_lu64;                        // FP32-LU engines: factorisations done in FP64 after a fallback
+    int32_t jv_valid;                      // the slot's Jacobian nonzeros are those of the current x_J
 };
 
 // Device workspace for n slots of one network (all arrays slot-major).

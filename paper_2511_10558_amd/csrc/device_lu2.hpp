@@ -600,14 +600,19 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
 // perm in the solver).  b[NP] (LDS, FP64) is read, the
 // solution is left in y[NP] (LDS); t is 64 doubles of LDS scratch.  Factor
 // entries are widened to FP64; the arithmetic is FP64.
+// N (even, N <= NP) is the order of the padded matrix: its rows and columns
+// from N on are the identity's, in the matrix and so in its factors (no
+// pivot is taken from them before column N), and b is zero there; the
+// products then stop at N and y keeps its zeros past N.  N = NP for factors
+// of unknown padding.
 template <typename T>
 __device__ __forceinline__ void lu_solve_left(const T *__restrict__ A, const T *__restrict__ dinv, const int32_t *__restrict__ rowmap,
-                              const int32_t *__restrict__ bperm, int NP, const double *b, double *y, double *t) {
+                              const int32_t *__restrict__ bperm, int NP, int N, const double *b, double *y, double *t) {
     const int tid = threadIdx.x;
     const int lane16 = tid & 15, row16 = tid >> 4;   // 16 lanes per row, 16 rows per pass
     for (int i = tid; i < NP; i += kBlock) y[i] = b[bperm[i]];
     __syncthreads();
-    const int NB = (NP + kLuW - 1) / kLuW;
+    const int NB = (N + kLuW - 1) / kLuW;
     // t[rr] = y[r0 + rr] - A_row(r0 + rr)[c_begin, c_end) . vec for rr < W (rows through
     // rowmap); 16 lanes per row, each thread carries 4 rows so that 8 loads
     // per column pair are in flight.
@@ -640,20 +645,28 @@ __device__ __forceinline__ void lu_solve_left(const T *__restrict__ A, const T *
             if (lane16 == 0 && rr < W) t[rr] = y[r0 + rr] - a;
         }
     };
-    auto gemv_diag = [&](int r0, int W, const T *D) {
-        // D is a full 64 x 64 block: rows past W are read but not stored
+    // D is the 64 x 64 inverse of the block's unit lower (lower) or upper
+    // triangle.  Its other triangle is zero and is not read: a column on that
+    // side of the diagonal loads the diagonal entry instead (a cache line the
+    // row needs anyway) and contributes nothing.  Rows past W read row W - 1
+    // again and are not stored.
+    auto gemv_diag = [&](int r0, int W, const T *D, bool lower) {
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
         for (int c = 2 * lane16; c < W; c += 32) {
             const double t0 = t[c], t1 = t[c + 1];
             T a0[4], a1[4];
 #pragma unroll
             for (int p = 0; p < 4; ++p) {
-                const int rr = row16 + 16 * p;
-                a0[p] = D[rr * kLuW + c];
-                a1[p] = D[rr * kLuW + c + 1];
+                const int rr = min(row16 + 16 * p, W - 1);
+                a0[p] = D[rr * kLuW + (lower ? min(c, rr) : max(c, rr))];
+                a1[p] = D[rr * kLuW + (lower ? min(c + 1, rr) : max(c + 1, rr))];
             }
 #pragma unroll
-            for (int p = 0; p < 4; ++p) acc[p] += double(a0[p]) * t0 + double(a1[p]) * t1;
+            for (int p = 0; p < 4; ++p) {
+                const int rr = min(row16 + 16 * p, W - 1);
+                const bool u0 = lower ? c <= rr : c >= rr, u1 = lower ? c + 1 <= rr : c + 1 >= rr;
+                acc[p] += (u0 ? double(a0[p]) * t0 : 0.0) + (u1 ? double(a1[p]) * t1 : 0.0);
+            }
         }
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
@@ -664,17 +677,17 @@ __device__ __forceinline__ void lu_solve_left(const T *__restrict__ A, const T *
         }
     };
     for (int ib = 0; ib < NB; ++ib) {
-        const int r0 = ib * kLuW, W = min(kLuW, NP - r0);
+        const int r0 = ib * kLuW, W = min(kLuW, N - r0);
         gemv_off(r0, W, 0, r0, y);
         __syncthreads();
-        gemv_diag(r0, W, dinv + size_t(ib) * 2 * kLuW * kLuW);
+        gemv_diag(r0, W, dinv + size_t(ib) * 2 * kLuW * kLuW, true);
         __syncthreads();
     }
     for (int ib = NB - 1; ib >= 0; --ib) {
-        const int r0 = ib * kLuW, W = min(kLuW, NP - r0);
-        gemv_off(r0, W, r0 + W, NP, y);
+        const int r0 = ib * kLuW, W = min(kLuW, N - r0);
+        gemv_off(r0, W, r0 + W, N, y);
         __syncthreads();
-        gemv_diag(r0, W, dinv + size_t(ib) * 2 * kLuW * kLuW + kLuW * kLuW);
+        gemv_diag(r0, W, dinv + size_t(ib) * 2 * kLuW * kLuW + kLuW * kLuW, false);
         __syncthreads();
     }
 }

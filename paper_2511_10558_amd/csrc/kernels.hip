@@ -166,7 +166,7 @@ __device__ __forceinline__ void begin_attempt(const Slots &s, int slot, SlotCtl 
     }
     __syncthreads();
     if (threadIdx.x == 0) {
-        if (refresh) { cs.jac_refresh = 0; cs.lu_valid = 0; }
+        if (refresh) { cs.jac_refresh = 0; cs.lu_valid = 0; cs.jv_valid = 0; }
         cs.c = cs.h / gq;
         cs.phase = kIter;
         cs.newton_iter = 0;
@@ -305,19 +305,24 @@ __global__ void __launch_bounds__(lu_threads<T>) k_factor(Slots s, DeviceNet n, 
         const double c = s.ctl[slot].c;
         // x_J after the factorisation's own LDS; the Jacobian nonzeros go to the
         // slot's compact array and M = I - c J(x_J) is formed block column by
-        // block column as the factorisation gathers it
-        double *xs = reinterpret_cast<double *>(reinterpret_cast<unsigned char *>(smem) + lu2_lds_bytes<T>(NP));
-        for (int i = threadIdx.x; i < S; i += lu_threads<T>) xs[i] = s.xJ[size_t(slot) * S + i];
-        __syncthreads();
+        // block column as the factorisation gathers it.  A factorisation for a
+        // new c at the same x_J (modified Newton keeps J across steps) reuses
+        // the nonzeros already there.
         double *jv = s.jval + size_t(slot) * n.nnzJ;
-        jacobian_values<lu_threads<T>>(n, s.k + size_t(slot) * n.R, xs, jv);
-        __syncthreads();
+        if (!s.ctl[slot].jv_valid) {
+            double *xs = reinterpret_cast<double *>(reinterpret_cast<unsigned char *>(smem) + lu2_lds_bytes<T>(NP));
+            for (int i = threadIdx.x; i < S; i += lu_threads<T>) xs[i] = s.xJ[size_t(slot) * S + i];
+            __syncthreads();
+            jacobian_values<lu_threads<T>>(n, s.k + size_t(slot) * n.R, xs, jv);
+            __syncthreads();
+        }
         NewtonMatrixSource<T> src{n.jidx, jv, S, NP, c};
         lu_factor_left<T>(slot_lu<T>(s, slot), NP, s.perm + size_t(slot) * NP, slot_dinv<T>(s, slot), nullptr,
                           reinterpret_cast<unsigned char *>(smem), src);
         if (threadIdx.x == 0) {
             s.ctl[slot].c_lu = c;
             s.ctl[slot].lu_valid = 1;
+            s.ctl[slot].jv_valid = 1;
             s.ctl[slot].n_lu += 1;
             if (s.prec == ABDF_PREC_FP32_LU && sizeof(T) == sizeof(double)) s.ctl[slot].n_lu64 += 1;
         }
@@ -381,7 +386,8 @@ __device__ __forceinline__ void newton_solve_cell(const Slots &s, const DeviceNe
     const int32_t *perm = s.perm + size_t(slot) * NP;
     const T *A = slot_lu<T>(s, slot);
     const T *Di = slot_dinv<T>(s, slot);
-    lu_solve_left<T>(A, Di, perm, perm, NP, b, y, red);
+    const int N = min(NP, S + (S & 1));   // the padding past S is the identity's
+    lu_solve_left<T>(A, Di, perm, perm, NP, N, b, y, red);
     if (kRefine) {
         double *y2 = y + NP, *xs = y2 + NP, *drate = xs + S, *part = drate + n.R;
         const double c = s.ctl[slot].c_lu;
@@ -390,7 +396,7 @@ __device__ __forceinline__ void newton_solve_cell(const Slots &s, const DeviceNe
         cell_jvp(n, s.k + size_t(slot) * n.R, xs, y, drate, part, y2);   // y2 = J(x_J) y
         for (int i = threadIdx.x; i < NP; i += kBlock) b[i] = i < S ? rb[i] - (y[i] - c * y2[i]) : 0.0;
         __syncthreads();
-        lu_solve_left<T>(A, Di, perm, perm, NP, b, y2, red);
+        lu_solve_left<T>(A, Di, perm, perm, NP, N, b, y2, red);
         for (int i = threadIdx.x; i < NP; i += kBlock) y[i] = y[i] + y2[i];
         __syncthreads();
     }
@@ -821,6 +827,7 @@ __device__ __forceinline__ void adj_begin(const Slots &s, const DeviceNet &n, in
         cs.h = h;
         cs.q = q;
         cs.c = c;
+        cs.jv_valid = 0;   // x_J moved to the step's corrector point
         const int p = atomicAdd(&s.cnt[ring], 1);
         s.act[ring * s.nslots + p] = slot;
         const int pl = atomicAdd(&s.cnt[3 + ring], 1);
@@ -1131,8 +1138,8 @@ __global__ void __launch_bounds__(kBlock) k_lu_solve_only(int NP, int n, const d
     double *b = smem, *y = b + NP;
     for (int i = threadIdx.x; i < NP; i += kBlock) b[i] = i < n ? bvec[bi * n + i] : 0.0;
     __syncthreads();
-    lu_solve_left<double>(W + bi * NP * NP, dinv + bi * lu2_dinv_elems<double>(NP), nullptr, permW + bi * NP, NP, b,
-                          y, t);
+    lu_solve_left<double>(W + bi * NP * NP, dinv + bi * lu2_dinv_elems<double>(NP), nullptr, permW + bi * NP, NP, NP,
+                          b, y, t);
     for (int i = threadIdx.x; i < n; i += kBlock) bvec[bi * n + i] = y[i];
 }
 
