@@ -482,7 +482,8 @@ def main():
         roof = {"kernel": "k_control", "bound": "hbm", "achieved": round(ach, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None}
     rec = recorded_traffic()
-    if rec is not None and args.precision == "fp64":
+    # the counters were taken on one network in FP64; other workloads report none
+    if rec is not None and args.precision == "fp64" and rec.get("network") == args.network:
         if roof["kernel"] == "k_factor":
             roof["traffic"] = round(rec["k_factor_bytes_per_lu"] * n_lu / max(1, prof["factor"][0]))
         elif roof["kernel"] == "k_newton_solve":

@@ -126,7 +126,7 @@ def main():
     out += ["", f"Per factorisation (k_factor, assembly + LU): {per_lu/2**20:.2f} MiB of HBM traffic; "
                 f"per Newton solve (k_newton_solve): {per_it/2**20:.3f} MiB."]
     open(os.path.join(HERE, "kernel_stats_net500.md"), "w").write("\n".join(out) + "\n")
-    json.dump({"source_hash": source_hash(), "k_factor_bytes_per_lu": per_lu,
+    json.dump({"source_hash": source_hash(), "network": "net500", "k_factor_bytes_per_lu": per_lu,
                "k_newton_solve_bytes_per_iteration": per_it}, open(os.path.join(HERE, "traffic.json"), "w"),
               indent=1)
     print("\n".join(out))
