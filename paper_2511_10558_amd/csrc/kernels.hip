@@ -1138,8 +1138,9 @@ __global__ void __launch_bounds__(kBlock) k_lu_solve_only(int NP, int n, const d
     double *b = smem, *y = b + NP;
     for (int i = threadIdx.x; i < NP; i += kBlock) b[i] = i < n ? bvec[bi * n + i] : 0.0;
     __syncthreads();
-    lu_solve_left<double>(W + bi * NP * NP, dinv + bi * lu2_dinv_elems<double>(NP), nullptr, permW + bi * NP, NP, NP,
-                          b, y, t);
+    // the padding past n is the identity's (k_pad_in, k_copy_perm)
+    lu_solve_left<double>(W + bi * NP * NP, dinv + bi * lu2_dinv_elems<double>(NP), nullptr, permW + bi * NP, NP,
+                          min(NP, n + (n & 1)), b, y, t);
     for (int i = threadIdx.x; i < n; i += kBlock) bvec[bi * n + i] = y[i];
 }
 

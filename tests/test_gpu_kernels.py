@@ -119,8 +119,10 @@ def test_lu_factor_reports_zero_pivot(ab, dev):
     assert list(info.cpu().numpy()) == [0, 8]
 
 
-@pytest.mark.parametrize("n", [12, 200, 500])
+@pytest.mark.parametrize("n", [1, 12, 37, 64, 200, 500, 512])
 def test_lu_solve_matches_linalg(ab, dev, n):
+    # orders below, at and one short of the 16-padded size (odd n: the
+    # products stop one column into the identity padding)
     batch = 4
     A = _newton_like_matrices(n, batch, seed=100 + n)
     rng = np.random.default_rng(n)
