@@ -610,12 +610,13 @@ __device__ __forceinline__ void lu_solve_left(const T *__restrict__ A, const T *
                               const int32_t *__restrict__ bperm, int NP, int N, const double *b, double *y, double *t) {
     const int tid = threadIdx.x;
     const int lane16 = tid & 15, row16 = tid >> 4;   // 16 lanes per row, 16 rows per pass
+    constexpr int VW = 16 / int(sizeof(T));           // factor entries per 16-byte load
     for (int i = tid; i < NP; i += kBlock) y[i] = b[bperm[i]];
     __syncthreads();
     const int NB = (N + kLuW - 1) / kLuW;
     // t[rr] = y[r0 + rr] - A_row(r0 + rr)[c_begin, c_end) . vec for rr < W (rows through
-    // rowmap); 16 lanes per row, each thread carries 4 rows so that 8 loads
-    // per column pair are in flight.
+    // rowmap); 16 lanes per row, each thread carries 4 rows so that four
+    // 16-byte loads are in flight per step.
     auto gemv_off = [&](int r0, int W, int c_begin, int c_end, const double *vec) {
         // rows past W (last block) read row W - 1 again; their sums are not stored.
         // No load sits behind a condition, so all of them are in flight together.
@@ -626,16 +627,24 @@ __device__ __forceinline__ void lu_solve_left(const T *__restrict__ A, const T *
             rows[p] = A + size_t(rowmap ? rowmap[r0 + rr] : r0 + rr) * NP;
         }
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int c = c_begin + 2 * lane16; c < c_end; c += 32) {
-            const double y0 = vec[c], y1 = vec[c + 1];
-            T a0[4], a1[4];
+        // VW entries (16 bytes) per lane and load: c_begin is a multiple of 64
+        // and rows are 64-byte aligned.  FP32 entries past c_end (at most
+        // three, within the row) meet zeros of vec.
+        for (int c = c_begin + VW * lane16; c < c_end; c += 16 * VW) {
+            double yv[VW];
+#pragma unroll
+            for (int k = 0; k < VW; ++k) yv[k] = vec[c + k];
+            T a[4][VW];
+#pragma unroll
+            for (int p = 0; p < 4; ++p) __builtin_memcpy(a[p], __builtin_assume_aligned(rows[p] + c, 16), 16);
 #pragma unroll
             for (int p = 0; p < 4; ++p) {
-                a0[p] = rows[p][c];
-                a1[p] = rows[p][c + 1];
+                if constexpr (VW == 2)
+                    acc[p] += double(a[p][0]) * yv[0] + double(a[p][1]) * yv[1];
+                else
+                    acc[p] += (double(a[p][0]) * yv[0] + double(a[p][1]) * yv[1]) +
+                              (double(a[p][2]) * yv[2] + double(a[p][3]) * yv[3]);
             }
-#pragma unroll
-            for (int p = 0; p < 4; ++p) acc[p] += double(a0[p]) * y0 + double(a1[p]) * y1;
         }
 #pragma unroll
         for (int p = 0; p < 4; ++p) {
@@ -652,20 +661,31 @@ __device__ __forceinline__ void lu_solve_left(const T *__restrict__ A, const T *
     // again and are not stored.
     auto gemv_diag = [&](int r0, int W, const T *D, bool lower) {
         double acc[4] = {0.0, 0.0, 0.0, 0.0};
-        for (int c = 2 * lane16; c < W; c += 32) {
-            const double t0 = t[c], t1 = t[c + 1];
-            T a0[4], a1[4];
+        for (int c = VW * lane16; c < W; c += 16 * VW) {
+            double tv[VW];
+#pragma unroll
+            for (int k = 0; k < VW; ++k) tv[k] = c + k < W ? t[c + k] : 0.0;
+            // the 16 bytes holding the diagonal stand in for those on the zero side
+            T a[4][VW];
 #pragma unroll
             for (int p = 0; p < 4; ++p) {
-                const int rr = min(row16 + 16 * p, W - 1);
-                a0[p] = D[rr * kLuW + (lower ? min(c, rr) : max(c, rr))];
-                a1[p] = D[rr * kLuW + (lower ? min(c + 1, rr) : max(c + 1, rr))];
+                const int rr = min(row16 + 16 * p, W - 1), dq = rr & ~(VW - 1);
+                __builtin_memcpy(a[p], __builtin_assume_aligned(D + rr * kLuW + (lower ? min(c, dq) : max(c, dq)), 16),
+                                 16);
             }
 #pragma unroll
             for (int p = 0; p < 4; ++p) {
                 const int rr = min(row16 + 16 * p, W - 1);
-                const bool u0 = lower ? c <= rr : c >= rr, u1 = lower ? c + 1 <= rr : c + 1 >= rr;
-                acc[p] += (u0 ? double(a0[p]) * t0 : 0.0) + (u1 ? double(a1[p]) * t1 : 0.0);
+                double term[VW];
+#pragma unroll
+                for (int k = 0; k < VW; ++k) {
+                    const bool use = c + k < W && (lower ? c + k <= rr : c + k >= rr);
+                    term[k] = use ? double(a[p][k]) * tv[k] : 0.0;
+                }
+                if constexpr (VW == 2)
+                    acc[p] += term[0] + term[1];
+                else
+                    acc[p] += (term[0] + term[1]) + (term[2] + term[3]);
             }
         }
 #pragma unroll
