@@ -269,8 +269,7 @@ int Engine::newton_iterations(int which, hipStream_t st, std::string &err) {
         timer_end(which == kListNoFactor ? ABDF_PROF_RHS_SIDE : ABDF_PROF_RHS, t0, st);
         t0 = timer_begin(st);
         HIP_TRY(launch_newton_solve(s_, dn_, ring_, which, std::min(bound_, grid_solve_max_),
-                                    std::min(bound_, grid_solve_ref_max_), std::min(bound_, grid_solve64_max_),
-                                    lds_solve_, lds_solve32_, st));
+                                    std::min(bound_, grid_solve_ref_max_), lds_solve_, lds_solve32_, st));
         timer_end(which == kListNoFactor ? ABDF_PROF_NEWTON_SIDE : ABDF_PROF_NEWTON, t0, st);
     }
     return ABDF_OK;

@@ -462,20 +462,32 @@ __global__ void __launch_bounds__(kRhsThreads) k_newton_rhs(Slots s, DeviceNet n
     }
 }
 
-// Newton corrections of every listed slot still iterating (persistent); in an
-// FP32-LU engine each variant takes the slots of its factor mode.
+// Newton corrections of every listed slot still iterating (persistent).  In an
+// FP32-LU engine the plain FP32 variant also takes the slots whose factors are
+// FP64 (same LDS), so that they run beside the FP32 ones rather than in a
+// launch of their own; the refining variant takes its own slots.
 template <typename T, bool kRefine>
 __global__ void __launch_bounds__(kBlock) k_newton_solve(Slots s, DeviceNet n, int ring, int which) {
     extern __shared__ double smem[];
     __shared__ double red[kLuW + kWaves];
     __shared__ int decision;
     constexpr int32_t kMode = sizeof(T) == sizeof(double) ? kLu64 : (kRefine ? kLuRefined32 : kLuPlain32);
+    constexpr bool kTakes64 = sizeof(T) == sizeof(float) && !kRefine;
     int count;
     const int32_t *list = slot_list(s, which, ring, count);
     for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
         const int slot = list[idx];
         if (s.ctl[slot].phase != kIter) continue;
-        if (s.prec == ABDF_PREC_FP32_LU && s.ctl[slot].lu_mode != kMode) continue;
+        if (s.prec == ABDF_PREC_FP32_LU) {
+            const int32_t mode = s.ctl[slot].lu_mode;
+            if constexpr (kTakes64) {
+                if (mode == kLu64) {
+                    newton_solve_cell<double, false>(s, n, slot, smem, red, &decision);
+                    continue;
+                }
+            }
+            if (mode != kMode) continue;
+        }
         newton_solve_cell<T, kRefine>(s, n, slot, smem, red, &decision);
     }
 }
@@ -1271,7 +1283,7 @@ hipError_t launch_newton_fused(const Slots &s, const DeviceNet &n, int ring, int
 }
 
 hipError_t launch_newton_solve(const Slots &s, const DeviceNet &n, int ring, int which, int grid, int grid_ref,
-                               int grid64, size_t lds, size_t lds_ref, hipStream_t st) {
+                               size_t lds, size_t lds_ref, hipStream_t st) {
     if (grid == 0) return hipSuccess;
     if (s.prec == ABDF_PREC_FP32_LU) {
         hipLaunchKernelGGL((k_newton_solve<float, false>), dim3(grid), dim3(kBlock), lds, st, s, n, ring, which);
@@ -1279,11 +1291,9 @@ hipError_t launch_newton_solve(const Slots &s, const DeviceNet &n, int ring, int
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL((k_newton_solve<float, true>), dim3(grid_ref), dim3(kBlock), lds_ref, st, s, n, ring,
                            which);
-        e = LAUNCH_CHECK();
-        if (e != hipSuccess) return e;
+        return LAUNCH_CHECK();   // FP64-mode slots went with the plain FP32 variant
     }
-    hipLaunchKernelGGL((k_newton_solve<double, false>), dim3(s.prec == ABDF_PREC_FP32_LU ? grid64 : grid),
-                       dim3(kBlock), lds, st, s, n, ring, which);
+    hipLaunchKernelGGL((k_newton_solve<double, false>), dim3(grid), dim3(kBlock), lds, st, s, n, ring, which);
     return LAUNCH_CHECK();
 }
 

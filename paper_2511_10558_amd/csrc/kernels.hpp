@@ -81,7 +81,7 @@ hipError_t launch_newton_rhs(const Slots &s, const DeviceNet &n, int ring, int w
 hipError_t launch_newton_fused(const Slots &s, const DeviceNet &n, int ring, int which, int grid, size_t lds,
                                hipStream_t st);
 hipError_t launch_newton_solve(const Slots &s, const DeviceNet &n, int ring, int which, int grid, int grid_ref,
-                               int grid64, size_t lds, size_t lds_ref, hipStream_t st);
+                               size_t lds, size_t lds_ref, hipStream_t st);
 hipError_t launch_control(const Slots &s, int ring, int grid, hipStream_t st);
 hipError_t launch_harvest(const Slots &s, const HarvestArgs &h, hipStream_t st);
 
