@@ -9,6 +9,7 @@ import pytest
 
 import synth
 from oracle import bdf, chem
+from tests import tiny_nets
 from tests.gpu_util import device, rel_err_above, solve_cells, t
 
 pytestmark = pytest.mark.gpu
@@ -159,6 +160,50 @@ def test_full_batch_sampled_against_oracle(ab, dev, name, seed):
     for j, c in enumerate(sample):
         assert rel_err_above(x[c], refs[j].x) <= TOL, (c, rel_err_above(x[c], refs[j].x))
         assert rel_err_above(x32[c], refs[j].x) <= TOL, (c, rel_err_above(x32[c], refs[j].x))
+
+
+def _cells(net, cell, x0s, t_end):
+    n = len(x0s)
+    col = lambda v: np.full(n, float(v))
+    return synth.Cells(col(cell["T"]), col(cell["n_H"]), col(cell["A_V"]), col(cell["zeta"]), col(cell["G0"]),
+                       np.asarray(x0s, float), col(t_end))
+
+
+def test_association_closed_form_odd_order(ab, dev):
+    # A + B -> C (three species: the Newton solves run one column into the
+    # identity padding) against x_A(t) from the closed form of x_A' = -k x_A x_B
+    net = tiny_nets.association(1e-9)
+    cell = dict(T=30.0, n_H=1e4, A_V=1.0, zeta=1.3e-17, G0=1.0)
+    kp = chem.rate_coefficients(net, **cell)[0]       # already multiplied by n_H
+    pairs = [(3e-4, 1e-4), (1e-4, 1e-4), (1e-4, 5e-4)]
+    t_end = 3.0 / (kp * 5e-4)
+    g = ab.Network.from_text(net.to_text())
+    x, status, _ = solve_cells(ab, g, _cells(net, cell, [[a, b, 0.0] for a, b in pairs], t_end), dev,
+                               rtol=1e-10, atol=1e-30)
+    for c, (a0, b0) in enumerate(pairs):
+        assert status[c] == 0
+        d = a0 - b0
+        a = a0 / (1 + kp * a0 * t_end) if d == 0 else d / (1 - (b0 / a0) * np.exp(-kp * d * t_end))
+        np.testing.assert_allclose(x[c], [a, a - d, a0 - a], rtol=1e-8)
+
+
+def test_first_order_network_matches_matrix_exponential(ab, dev):
+    # nine species, one-body reactions only: x(t) = expm(t K) x0
+    import scipy.linalg as sla
+    net = tiny_nets.first_order()
+    cell = dict(T=20.0, n_H=1e3, A_V=0.5, zeta=1e-16, G0=1.0)
+    K = chem.cell_chemistry(net, cell).jac(np.zeros(net.n_species))
+    x0 = np.zeros(net.n_species)
+    x0[net.index("H2")] = 0.5
+    x0[net.index("CO")] = 1e-4
+    t_end = 1e6 * synth.YEAR_S
+    g = ab.Network.from_text(net.to_text())
+    x, status, _ = solve_cells(ab, g, _cells(net, cell, [x0, x0], t_end), dev, rtol=1e-10, atol=1e-30)
+    want = sla.expm(t_end * K) @ x0
+    m = want > 1e-12
+    for c in range(2):
+        assert status[c] == 0
+        np.testing.assert_allclose(x[c][m], want[m], rtol=1e-8)
 
 
 def test_largest_and_too_large_networks(ab, dev):
