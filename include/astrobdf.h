@@ -81,7 +81,9 @@ typedef struct abdf_options {
     int32_t max_steps;         /* step attempts per cell (default 100000) */
     int32_t precision;         /* ABDF_PREC_* (default FP64) */
     int32_t check_every;       /* step attempts between host polls of the running count (default 8) */
-    int32_t reserved0;
+    int32_t max_order;         /* highest BDF order the order selection may reach, 1..5;
+                                * 0 = 5 (default 5).  1 is the implicit Euler method
+                                * with the same error control. */
     uint64_t hbm_budget_bytes; /* bound on the library's device workspace, 0 = no bound */
     double newton_tol;         /* 0 = max(10 u / rtol, min(0.03, sqrt(rtol))) */
     double lu_reuse;           /* keep a cell's Newton-matrix factorisation while

@@ -168,8 +168,13 @@ def _newton(chem, lu, c, psi, x_p, scale, tol, stats):
 
 
 def solve(chem, x0, t_end, rtol=1e-6, atol=1e-20, max_steps=100000,
-          newton_tol=None, record=False) -> Result:
-    """Integrate dx/dt = f(x) from t = 0 to t_end with adaptive order and step."""
+          newton_tol=None, record=False, max_order=MAX_ORDER) -> Result:
+    """Integrate dx/dt = f(x) from t = 0 to t_end with adaptive order and step.
+
+    max_order (1..5) caps the order the order selection may reach; 1 leaves
+    the implicit Euler method under the same error and step control."""
+    if not 1 <= max_order <= MAX_ORDER:
+        raise ValueError("max_order must be in 1..5")
     x0 = np.asarray(x0, dtype=float)
     S = x0.shape[0]
     stats = Stats()
@@ -272,7 +277,7 @@ def solve(chem, x0, t_end, rtol=1e-6, atol=1e-20, max_steps=100000,
         if n_equal < q + 1:
             continue
         e_m = wrms(ERRC[q - 1] * D[q], scale_e) if q > 1 else np.inf
-        e_p = wrms(ERRC[q + 1] * D[q + 2], scale_e) if q < MAX_ORDER else np.inf
+        e_p = wrms(ERRC[q + 1] * D[q + 2], scale_e) if q < max_order else np.inf
         rhos = [_growth(e_m, q), _growth(err, q + 1), _growth(e_p, q + 2)]
         best = 1
         if rhos[0] > rhos[best]:

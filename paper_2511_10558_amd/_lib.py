@@ -18,7 +18,7 @@ class Options(ctypes.Structure):
         ("max_steps", ctypes.c_int32),
         ("precision", ctypes.c_int32),
         ("check_every", ctypes.c_int32),
-        ("reserved0", ctypes.c_int32),
+        ("max_order", ctypes.c_int32),
         ("hbm_budget_bytes", ctypes.c_uint64),
         ("newton_tol", ctypes.c_double),
         ("lu_reuse", ctypes.c_double),

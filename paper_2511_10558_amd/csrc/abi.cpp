@@ -74,6 +74,7 @@ abdf_status check_opts(const abdf_options &o) {
         return fail(ABDF_E_ARG, "unknown precision");
     if (o.newton_tol < 0.0 || !std::isfinite(o.newton_tol)) return fail(ABDF_E_ARG, "newton_tol must be >= 0");
     if (!(o.lu_reuse >= 0.0 && o.lu_reuse < 1.0)) return fail(ABDF_E_ARG, "lu_reuse must be in [0, 1)");
+    if (o.max_order < 0 || o.max_order > 5) return fail(ABDF_E_ARG, "max_order must be in 1..5 (0: 5)");
     return ABDF_OK;
 }
 
@@ -103,6 +104,7 @@ void abdf_options_default(abdf_options *opt) {
     opt->hbm_budget_bytes = 0;
     opt->newton_tol = 0.0;
     opt->lu_reuse = 0.0;
+    opt->max_order = 5;
 }
 
 const char *abdf_last_error(void) { return g_last_error.c_str(); }
@@ -175,6 +177,7 @@ abdf_status abdf_solve(const abdf_network *net, int64_t n_cells, const double *T
         if (nslots < 1) return fail(ABDF_E_BUDGET, "not even one cell fits in the workspace budget");
         abdf::Engine eng(net->host, *dn, o.precision, o.max_steps);
         eng.set_lu_reuse(o.lu_reuse);
+        eng.set_max_order(o.max_order);
         int r = eng.init(int(nslots), err);
         if (r != ABDF_OK) return fail(static_cast<abdf_status>(r), err);
         abdf::BatchIO io{n_cells, T, n_H, A_V, zeta, G0, x0, t_end, x_out, cell_status, stats};

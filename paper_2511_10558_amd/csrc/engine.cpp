@@ -180,6 +180,7 @@ int Engine::init(int nslots, std::string &err) {
     s_.act = static_cast<int32_t *>(act);
     s_.lul = static_cast<int32_t *>(lul);
     s_.lu_reuse = lu_reuse_;
+    s_.max_order = max_order_;
     s_.nol = static_cast<int32_t *>(nol);
     s_.fin = static_cast<int32_t *>(fin);
     s_.cnt = static_cast<int32_t *>(cnt);

@@ -53,6 +53,11 @@ class Engine {
     int init(int nslots, std::string &err);
     // relative change of c within which a slot keeps its factorisation (0: none)
     void set_lu_reuse(double v) { lu_reuse_ = v; s_.lu_reuse = v; }
+    // highest order the order selection may reach (1..5; 0 or out of range: 5)
+    void set_max_order(int q) {
+        max_order_ = (q >= 1 && q <= kMaxOrder) ? q : kMaxOrder;
+        s_.max_order = max_order_;
+    }
     // Bytes of device workspace per slot.
     static size_t bytes_per_slot(const DeviceNet &dn, int prec);
     // Solves every cell of io; returns an abdf_status.
@@ -101,6 +106,7 @@ class Engine {
     const DeviceNet &dn_;
     int prec_, max_steps_;
     double lu_reuse_ = 0.0;
+    int max_order_ = kMaxOrder;
     Slots s_{};
     void *base_ = nullptr;
     int32_t *d_admit_slots_ = nullptr;

@@ -670,7 +670,7 @@ __global__ void __launch_bounds__(kBlock) k_control(Slots s, int ring) {
     if (cs.n_equal >= q + 1) {
         if (threadIdx.x == 0) {
             const double e_m = q > 1 ? sqrt(sm / S) : INFINITY;
-            const double e_p = q < kMaxOrder ? sqrt(sp / S) : INFINITY;
+            const double e_p = q < s.max_order ? sqrt(sp / S) : INFINITY;
             const double r0 = growth(e_m, q), r1 = growth(err, q + 1), r2 = growth(e_p, q + 2);
             int best = 1;
             double rb = r1;

@@ -48,6 +48,7 @@ int Server::start(int nslots, std::string &err) {
     HIP_TRY(hipEventCreateWithFlags(&admit_done_, hipEventDisableTiming));
     eng_ = std::make_unique<Engine>(net_, dn_, opt_.solve.precision, opt_.solve.max_steps);
     eng_->set_lu_reuse(opt_.solve.lu_reuse);
+    eng_->set_max_order(opt_.solve.max_order);
     int rc = eng_->init(nslots, err);
     if (rc != ABDF_OK) return rc;
     const size_t n = size_t(nslots), S = size_t(dn_.S);

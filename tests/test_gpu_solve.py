@@ -206,6 +206,21 @@ def test_first_order_network_matches_matrix_exponential(ab, dev):
         np.testing.assert_allclose(x[c][m], want[m], rtol=1e-8)
 
 
+@pytest.mark.parametrize("name,n,max_order", [("small", 1, 1), ("net200", 3, 2)])
+def test_order_cap_matches_oracle(ab, dev, name, n, max_order):
+    # the order selection capped at max_order on both sides (1: implicit Euler)
+    net = synth.network_for_config(name)
+    cells = synth.single_cell(net) if n == 1 else synth.sample_cells(net, n, seed=2001)
+    g = ab.Network.from_text(net.to_text())
+    x, status, stats = solve_cells(ab, g, cells, dev, max_order=max_order)
+    for c in range(cells.n):
+        ref = bdf.solve(chem.cell_chemistry(net, cells.cell(c)), cells.x0[c], cells.t_end[c], 1e-6, 1e-20,
+                        max_order=max_order)
+        assert status[c] == 0 and ref.status == bdf.OK
+        assert stats["order"][c] <= max_order
+        assert rel_err_above(x[c], ref.x) <= TOL, (c, rel_err_above(x[c], ref.x))
+
+
 def test_largest_and_too_large_networks(ab, dev):
     # 512 species fill the factorisation's 512 x 512 tile exactly; 513 do not fit
     net = synth.large_network(512, 6000, seed=512)

@@ -72,6 +72,32 @@ def test_first_step_is_implicit_euler():
     assert x[1] == pytest.approx(1.0 - 1.0 / (1.0 + h * k), rel=1e-12)
 
 
+def test_order_cap_one_is_implicit_euler_throughout():
+    # max_order 1: every accepted step stays at order 1, and on the linear
+    # decay each step multiplies x_A by 1 / (1 + k h), so x_A(t_end) is the
+    # product over the recorded steps
+    net = tiny_nets.decay(2.0)
+    ch = chem.cell_chemistry(net, CELL)
+    k = ch.k[0]
+    res = bdf.solve(ch, np.array([1.0, 0.0]), 5.0 / k, 1e-6, 1e-20, record=True, max_order=1)
+    assert res.status == bdf.OK and len(res.history) > 10
+    assert all(q == 1 for (_h, q, _t, _x) in res.history)
+    want = np.prod([1.0 / (1.0 + k * h) for (h, _q, _t, _x) in res.history])
+    assert res.x[0] == pytest.approx(want, rel=1e-12)
+    assert res.x[1] == pytest.approx(1.0 - want, rel=1e-12)
+    # a cap of two on the 12-species network: orders stay <= 2, and an
+    # uncapped run reaches higher ones
+    small = synth.network_for_config("small")
+    cells = synth.single_cell(small)
+    chs = chem.cell_chemistry(small, cells.cell(0))
+    r2 = bdf.solve(chs, cells.x0[0], cells.t_end[0], 1e-6, 1e-20, record=True, max_order=2)
+    r5 = bdf.solve(chs, cells.x0[0], cells.t_end[0], 1e-6, 1e-20, record=True)
+    assert r2.status == bdf.OK and max(q for (_h, q, _t, _x) in r2.history) == 2
+    assert max(q for (_h, q, _t, _x) in r5.history) > 2
+    with pytest.raises(ValueError):
+        bdf.solve(ch, np.array([1.0, 0.0]), 1.0, max_order=6)
+
+
 def test_decay_matches_exponential():
     net = tiny_nets.decay(2.0)
     ch = chem.cell_chemistry(net, CELL)
