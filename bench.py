@@ -84,10 +84,9 @@ def recorded_traffic():
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
-    sys.path.insert(0, os.path.join(ROOT, "profiles"))
-    import summarize
+    from paper_2511_10558_amd import profile_summary
     rec = json.load(open(path))
-    return rec if rec.get("source_hash") == summarize.source_hash() else None
+    return rec if rec.get("source_hash") == profile_summary.source_hash() else None
 
 
 def run_serve(args):

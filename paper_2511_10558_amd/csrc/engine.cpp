@@ -14,12 +14,23 @@
 #include <cstring>
 #include <mutex>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "../../include/astrobdf.h"
 
 namespace abdf {
 
 namespace {
 size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+// A named host range for rocprofv3 --marker-trace (one library call each way
+// when no tool is attached).
+struct TraceRange {
+    explicit TraceRange(const char *name) { roctxRangePush(name); }
+    ~TraceRange() { roctxRangePop(); }
+    TraceRange(const TraceRange &) = delete;
+    TraceRange &operator=(const TraceRange &) = delete;
+};
 
 #define HIP_TRY(expr)                                                           \
     do {                                                                        \
@@ -228,6 +239,7 @@ double Engine::newton_tolerance(const abdf_options &opt) {
 
 int Engine::admit_cells(const AdmitArgs &a, hipStream_t st, std::string &err) {
     if (a.count <= 0) return ABDF_OK;
+    TraceRange tr("abdf admit");
     hipEvent_t t0 = timer_begin(st);
     HIP_TRY(launch_admit(s_, dn_, a, ring_, lds_admit_, st));
     timer_end(ABDF_PROF_ADMIT, t0, st);
@@ -285,6 +297,7 @@ constexpr int kSplitMinSlots = 32;
 // which the side stream's kernels fill.  Control waits for both streams.
 int Engine::attempt(hipStream_t st, std::string &err) {
     if (bound_ <= 0) return ABDF_OK;
+    TraceRange tr("abdf attempt");
     if (bound_ < kSplitMinSlots) {
         // a handful of cells: launch latency dominates, one stream
         hipEvent_t t0 = timer_begin(st);
@@ -325,6 +338,7 @@ int Engine::attempt(hipStream_t st, std::string &err) {
 }
 
 int Engine::sync_counts(hipStream_t st, int &nfin, std::string &err) {
+    TraceRange tr("abdf poll");
     HIP_TRY(hipMemcpyAsync(h_cnt_, s_.cnt, kCountSlots * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     flush_timers();
@@ -336,6 +350,7 @@ int Engine::sync_counts(hipStream_t st, int &nfin, std::string &err) {
 int Engine::harvest(HarvestArgs h, hipStream_t st, std::string &err) {
     const int nfin = h.count;
     if (nfin <= 0) return ABDF_OK;
+    TraceRange tr("abdf harvest");
     HIP_TRY(hipMemcpyAsync(h_fin_, s_.fin, nfin * sizeof(int32_t), hipMemcpyDeviceToHost, st));
     h.slots = s_.fin;
     hipEvent_t t0 = timer_begin(st);
@@ -347,6 +362,7 @@ int Engine::harvest(HarvestArgs h, hipStream_t st, std::string &err) {
 }
 
 int Engine::solve(const BatchIO &io, const abdf_options &opt, hipStream_t st, std::string &err) {
+    TraceRange tr("abdf solve");
     ring_ = 0;
     bound_ = 0;
     long long next = 0;
@@ -383,6 +399,7 @@ int Engine::solve(const BatchIO &io, const abdf_options &opt, hipStream_t st, st
 }
 
 int Engine::reverse(const AdjIO &io, int check_every, hipStream_t st, std::string &err) {
+    TraceRange tr("abdf reverse sweep");
     ring_ = 0;
     bound_ = 0;
     HIP_TRY(hipMemsetAsync(s_.cnt, 0, kCountSlots * sizeof(int32_t), st));
@@ -415,6 +432,7 @@ int Engine::reverse(const AdjIO &io, int check_every, hipStream_t st, std::strin
     int since = 0;
     while (true) {
         if (bound_ > 0) {
+            TraceRange ts("abdf reverse step");
             hipEvent_t t0 = timer_begin(st);
             HIP_TRY(launch_factor(s_, dn_, ring_, std::min(bound_, grid_factor_max_),
                                   std::min(bound_, grid_factor64_max_), lds_factor_, lds_factor32_, st));

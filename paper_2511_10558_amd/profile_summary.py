@@ -1,6 +1,7 @@
-"""Turns rocprofv3 CSV output into the short summaries kept in this folder.
+"""Turns rocprofv3 CSV output into the short summaries kept in profiles/.
 
-    python profiles/summarize.py TRACE_DIR FETCH_DIR WRITE_DIR FETCH_LOG
+    python -m paper_2511_10558_amd.profile_summary TRACE_DIR FETCH_DIR WRITE_DIR FETCH_LOG
+    python -m paper_2511_10558_amd.profile_summary --markers MARKER_DIR COMMAND
 
 TRACE_DIR holds run_kernel_stats.csv of a --kernel-trace --stats run;
 FETCH_DIR / WRITE_DIR hold run_counter_collection.csv of the FETCH_SIZE and
@@ -8,7 +9,10 @@ WRITE_SIZE passes of a bench run started with --calibrate-copy (one
 elementwise multiply of 32 Mi doubles: 256 MiB read, 256 MiB written);
 FETCH_LOG is that bench run's
 output line (for the number of factorisations).  Writes
-profiles/kernel_stats_net500.md and profiles/traffic.json.
+profiles/kernel_stats_net500.md and profiles/traffic.json.  With --markers,
+MARKER_DIR holds run_marker_api_trace.csv of a --marker-trace run (the
+library's host ranges) and COMMAND is the command that made it; writes
+profiles/markers_net500.md.
 """
 import csv
 import hashlib
@@ -18,6 +22,7 @@ import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
+PROFILES = os.path.join(ROOT, "profiles")
 KERNEL_SOURCES = ["paper_2511_10558_amd/csrc/device_lu2.hpp", "paper_2511_10558_amd/csrc/device_lu.hpp",
                   "paper_2511_10558_amd/csrc/device_chem.hpp", "paper_2511_10558_amd/csrc/kernels.hip",
                   "paper_2511_10558_amd/csrc/device_common.hpp"]
@@ -54,7 +59,31 @@ def counters(path):
     return per
 
 
+def markers(mdir, command):
+    """Host ranges of the library (count, total and mean duration) from a
+    rocprofv3 --marker-trace run."""
+    rows = list(csv.DictReader(open(os.path.join(mdir, "run_marker_api_trace.csv"))))
+    agg = {}
+    for r in rows:
+        name = r.get("Function") or r.get("Name") or ""
+        if not name.startswith("abdf"):
+            continue
+        dt = (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e6
+        n, tot = agg.get(name, (0, 0.0))
+        agg[name] = (n + 1, tot + dt)
+    out = ["# Host ranges of the library (rocprofv3 --marker-trace): 500-species network, 4096 cells, FP64", "",
+           "Command (repo root, on one MI355X):", "", "    " + command, "",
+           "| range | count | total ms | mean us |", "|---|---|---|---|"]
+    for name, (n, tot) in sorted(agg.items(), key=lambda kv: -kv[1][1]):
+        out.append(f"| {name} | {n} | {tot:.1f} | {1e3 * tot / n:.1f} |")
+    open(os.path.join(PROFILES, "markers_net500.md"), "w").write("\n".join(out) + "\n")
+    print("\n".join(out))
+
+
 def main():
+    if sys.argv[1] == "--markers":
+        markers(sys.argv[2], sys.argv[3])
+        return
     trace, fetch, write, flog = sys.argv[1:5]
     rows = list(csv.DictReader(open(os.path.join(trace, "run_kernel_stats.csv"))))
     out = ["# rocprofv3 kernel statistics: 500-species / 6000-reaction network, 4096 cells, FP64", "",
@@ -125,9 +154,9 @@ def main():
         max(1, work["newton_iterations"])
     out += ["", f"Per factorisation (k_factor, assembly + LU): {per_lu/2**20:.2f} MiB of HBM traffic; "
                 f"per Newton solve (k_newton_solve): {per_it/2**20:.3f} MiB."]
-    open(os.path.join(HERE, "kernel_stats_net500.md"), "w").write("\n".join(out) + "\n")
+    open(os.path.join(PROFILES, "kernel_stats_net500.md"), "w").write("\n".join(out) + "\n")
     json.dump({"source_hash": source_hash(), "network": "net500", "k_factor_bytes_per_lu": per_lu,
-               "k_newton_solve_bytes_per_iteration": per_it}, open(os.path.join(HERE, "traffic.json"), "w"),
+               "k_newton_solve_bytes_per_iteration": per_it}, open(os.path.join(PROFILES, "traffic.json"), "w"),
               indent=1)
     print("\n".join(out))
 
