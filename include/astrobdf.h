@@ -91,6 +91,10 @@ typedef struct abdf_options {
                                 * c_lu the value it was formed at, scaling each
                                 * correction by 2 / (1 + c / c_lu); 0 (default) =
                                 * refactor whenever c changes.  In [0, 1). */
+    double h0;                 /* first step size [s], > 0 replaces the starting-step
+                                * heuristic (still capped by t_end and h_max); 0 (default) =
+                                * heuristic */
+    double h_max;              /* upper bound on every step size [s]; 0 (default) = none */
 } abdf_options;
 
 /* Per-cell counters (written to a DEVICE array of n_cells structs). */

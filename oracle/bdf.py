@@ -168,11 +168,13 @@ def _newton(chem, lu, c, psi, x_p, scale, tol, stats):
 
 
 def solve(chem, x0, t_end, rtol=1e-6, atol=1e-20, max_steps=100000,
-          newton_tol=None, record=False, max_order=MAX_ORDER) -> Result:
+          newton_tol=None, record=False, max_order=MAX_ORDER, h0=0.0, h_max=0.0) -> Result:
     """Integrate dx/dt = f(x) from t = 0 to t_end with adaptive order and step.
 
     max_order (1..5) caps the order the order selection may reach; 1 leaves
-    the implicit Euler method under the same error and step control."""
+    the implicit Euler method under the same error and step control.  h0 > 0
+    replaces the starting-step heuristic's result; h_max > 0 bounds every step
+    (the starting step, and each increase chosen with the order)."""
     if not 1 <= max_order <= MAX_ORDER:
         raise ValueError("max_order must be in 1..5")
     x0 = np.asarray(x0, dtype=float)
@@ -188,6 +190,10 @@ def solve(chem, x0, t_end, rtol=1e-6, atol=1e-20, max_steps=100000,
     stats.n_rhs += 1
     h = initial_step(chem.f, x0, f0, t_end, rtol, atol)
     stats.n_rhs += 1
+    if h0 > 0.0:
+        h = min(h0, t_end)
+    if h_max > 0.0:
+        h = min(h, h_max)
     D = np.zeros((MAX_ORDER + 3, S))
     D[0] = x0
     D[1] = h * f0
@@ -286,6 +292,8 @@ def solve(chem, x0, t_end, rtol=1e-6, atol=1e-20, max_steps=100000,
             best = 2
         q = q + best - 1
         rho = min(MAX_FACTOR, safety * rhos[best])
+        if h_max > 0.0:
+            rho = min(rho, h_max / h)
         h = h * rho
         rescale(D, q, rho)
         n_equal = 0

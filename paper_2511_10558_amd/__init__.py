@@ -119,12 +119,14 @@ def default_options() -> Options:
 
 
 def make_options(rtol=1e-6, atol=1e-20, max_steps=100000, precision="fp64", check_every=8,
-                 hbm_budget_bytes=0, newton_tol=0.0, lu_reuse=0.0, max_order=5) -> Options:
+                 hbm_budget_bytes=0, newton_tol=0.0, lu_reuse=0.0, max_order=5, h0=0.0,
+                 h_max=0.0) -> Options:
     o = default_options()
     o.rtol, o.atol, o.max_steps = rtol, atol, max_steps
     o.precision = PREC[precision] if isinstance(precision, str) else int(precision)
     o.check_every, o.hbm_budget_bytes, o.newton_tol = check_every, hbm_budget_bytes, newton_tol
     o.lu_reuse, o.max_order = lu_reuse, max_order
+    o.h0, o.h_max = h0, h_max
     return o
 
 

@@ -22,6 +22,8 @@ class Options(ctypes.Structure):
         ("hbm_budget_bytes", ctypes.c_uint64),
         ("newton_tol", ctypes.c_double),
         ("lu_reuse", ctypes.c_double),
+        ("h0", ctypes.c_double),
+        ("h_max", ctypes.c_double),
     ]
 
 

@@ -75,6 +75,8 @@ abdf_status check_opts(const abdf_options &o) {
     if (o.newton_tol < 0.0 || !std::isfinite(o.newton_tol)) return fail(ABDF_E_ARG, "newton_tol must be >= 0");
     if (!(o.lu_reuse >= 0.0 && o.lu_reuse < 1.0)) return fail(ABDF_E_ARG, "lu_reuse must be in [0, 1)");
     if (o.max_order < 0 || o.max_order > 5) return fail(ABDF_E_ARG, "max_order must be in 1..5 (0: 5)");
+    if (!(o.h0 >= 0.0) || !std::isfinite(o.h0)) return fail(ABDF_E_ARG, "h0 must be finite and >= 0");
+    if (!(o.h_max >= 0.0) || !std::isfinite(o.h_max)) return fail(ABDF_E_ARG, "h_max must be finite and >= 0");
     return ABDF_OK;
 }
 
@@ -105,6 +107,8 @@ void abdf_options_default(abdf_options *opt) {
     opt->newton_tol = 0.0;
     opt->lu_reuse = 0.0;
     opt->max_order = 5;
+    opt->h0 = 0.0;
+    opt->h_max = 0.0;
 }
 
 const char *abdf_last_error(void) { return g_last_error.c_str(); }
@@ -178,6 +182,7 @@ abdf_status abdf_solve(const abdf_network *net, int64_t n_cells, const double *T
         abdf::Engine eng(net->host, *dn, o.precision, o.max_steps);
         eng.set_lu_reuse(o.lu_reuse);
         eng.set_max_order(o.max_order);
+        eng.set_step_bounds(o.h0, o.h_max);
         int r = eng.init(int(nslots), err);
         if (r != ABDF_OK) return fail(static_cast<abdf_status>(r), err);
         abdf::BatchIO io{n_cells, T, n_H, A_V, zeta, G0, x0, t_end, x_out, cell_status, stats};

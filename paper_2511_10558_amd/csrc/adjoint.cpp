@@ -86,6 +86,7 @@ int Tape::record(const BatchIO &io, const double *alpha, const abdf_options &opt
     eng_ = std::make_unique<Engine>(net_, dn_, opt.precision, opt.max_steps);
     eng_->set_lu_reuse(opt.lu_reuse);
     eng_->set_max_order(opt.max_order);
+    eng_->set_step_bounds(opt.h0, opt.h_max);
     int rc = eng_->init(int(nslots), err);
     if (rc != ABDF_OK) return rc;
     Slots &s = eng_->slots();

@@ -47,6 +47,8 @@ struct Slots {
     int nslots, S, R, NP, prec, max_steps;
     double lu_reuse;  // keep the factorisation while |c / c_lu - 1| <= lu_reuse (0: while c == c_lu)
     int max_order;    // highest order the order selection may reach (1..kMaxOrder)
+    double h0;        // first step (> 0 replaces the starting-step heuristic), seconds
+    double h_max;     // bound on every step (0: none), seconds
     SlotCtl *ctl;
     double *phi;      // [n][5]: T, n_H, A_V, zeta, G0
     double *k;        // [n][R]

@@ -192,6 +192,8 @@ int Engine::init(int nslots, std::string &err) {
     s_.lul = static_cast<int32_t *>(lul);
     s_.lu_reuse = lu_reuse_;
     s_.max_order = max_order_;
+    s_.h0 = h0_;
+    s_.h_max = h_max_;
     s_.nol = static_cast<int32_t *>(nol);
     s_.fin = static_cast<int32_t *>(fin);
     s_.cnt = static_cast<int32_t *>(cnt);

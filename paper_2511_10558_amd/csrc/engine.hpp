@@ -58,6 +58,13 @@ class Engine {
         max_order_ = (q >= 1 && q <= kMaxOrder) ? q : kMaxOrder;
         s_.max_order = max_order_;
     }
+    // first step (0: heuristic) and bound on every step (0: none), seconds
+    void set_step_bounds(double h0, double h_max) {
+        h0_ = h0;
+        h_max_ = h_max;
+        s_.h0 = h0;
+        s_.h_max = h_max;
+    }
     // Bytes of device workspace per slot.
     static size_t bytes_per_slot(const DeviceNet &dn, int prec);
     // Solves every cell of io; returns an abdf_status.
@@ -107,6 +114,7 @@ class Engine {
     int prec_, max_steps_;
     double lu_reuse_ = 0.0;
     int max_order_ = kMaxOrder;
+    double h0_ = 0.0, h_max_ = 0.0;
     Slots s_{};
     void *base_ = nullptr;
     int32_t *d_admit_slots_ = nullptr;

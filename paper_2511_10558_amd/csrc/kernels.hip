@@ -278,7 +278,8 @@ __global__ void __launch_bounds__(kBlock) k_admit(Slots s, DeviceNet n, AdmitArg
     const double d2 = sqrt(block_sum(s2, red) / S) / h0;
     const double mx = fmax(d1, d2);
     const double h1 = mx <= 1e-15 ? fmax(1e-6, h0 * 1e-3) : sqrt(0.01 / mx);
-    const double h = fmin(fmin(100.0 * h0, h1), cs.t_end);
+    double h = s.h0 > 0.0 ? fmin(s.h0, cs.t_end) : fmin(fmin(100.0 * h0, h1), cs.t_end);
+    if (s.h_max > 0.0) h = fmin(h, s.h_max);
     for (int i = threadIdx.x; i < S; i += kBlock) D[S + i] = h * f0[i];
     __syncthreads();
     if (threadIdx.x == 0) {
@@ -677,7 +678,8 @@ __global__ void __launch_bounds__(kBlock) k_control(Slots s, int ring) {
             if (r0 > rb) { best = 0; rb = r0; }
             if (r2 > rb) { best = 2; rb = r2; }
             cs.q = q + best - 1;
-            const double rho = fmin(kMaxFactor, safety * rb);
+            double rho = fmin(kMaxFactor, safety * rb);
+            if (s.h_max > 0.0) rho = fmin(rho, s.h_max / cs.h);
             cs.h = cs.h * rho;
             cs.n_equal = 0;
             if (s.lu_reuse == 0.0) cs.lu_valid = 0;   // else the change of c decides

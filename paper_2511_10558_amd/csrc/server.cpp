@@ -49,6 +49,7 @@ int Server::start(int nslots, std::string &err) {
     eng_ = std::make_unique<Engine>(net_, dn_, opt_.solve.precision, opt_.solve.max_steps);
     eng_->set_lu_reuse(opt_.solve.lu_reuse);
     eng_->set_max_order(opt_.solve.max_order);
+    eng_->set_step_bounds(opt_.solve.h0, opt_.solve.h_max);
     int rc = eng_->init(nslots, err);
     if (rc != ABDF_OK) return rc;
     const size_t n = size_t(nslots), S = size_t(dn_.S);

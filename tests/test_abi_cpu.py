@@ -38,7 +38,7 @@ def test_options_default_values():
     o = ab.default_options()
     assert o.rtol == 1e-6 and o.atol == 1e-20 and o.max_steps == 100000
     assert o.precision == 0 and o.check_every == 8 and o.hbm_budget_bytes == 0 and o.lu_reuse == 0.0
-    assert o.max_order == 5
+    assert o.max_order == 5 and o.h0 == 0.0 and o.h_max == 0.0
 
 
 @pytest.mark.parametrize("name", ["small", "net200", "net500"])
@@ -129,6 +129,10 @@ def test_null_and_invalid_arguments_without_gpu():
         o = ab.make_options(max_order=bad)
         assert L.abdf_solve(g.handle, 1, *([None] * 7), ctypes.byref(o), None, None, None, None) == 1
         assert b"max_order" in L.abdf_last_error()
+    for kw, word in ((dict(h0=-1.0), b"h0"), (dict(h_max=float("nan")), b"h_max"), (dict(h_max=-2.0), b"h_max")):
+        o = ab.make_options(**kw)
+        assert L.abdf_solve(g.handle, 1, *([None] * 7), ctypes.byref(o), None, None, None, None) == 1
+        assert word in L.abdf_last_error()
     o = ab.make_options(max_order=0)   # 0 stands for 5
     assert L.abdf_solve(g.handle, 0, *([None] * 7), ctypes.byref(o), None, None, None, None) == 0
     o = ab.make_options()

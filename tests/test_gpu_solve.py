@@ -221,6 +221,20 @@ def test_order_cap_matches_oracle(ab, dev, name, n, max_order):
         assert rel_err_above(x[c], ref.x) <= TOL, (c, rel_err_above(x[c], ref.x))
 
 
+def test_step_bounds_match_oracle(ab, dev):
+    # a given first step and a bound on every step, the same on both sides
+    net = synth.network_for_config("small")
+    cells = synth.single_cell(net)
+    h0, h_max = 1.0, float(cells.t_end[0]) / 300.0
+    g = ab.Network.from_text(net.to_text())
+    x, status, stats = solve_cells(ab, g, cells, dev, h0=h0, h_max=h_max)
+    ref = bdf.solve(chem.cell_chemistry(net, cells.cell(0)), cells.x0[0], cells.t_end[0], 1e-6, 1e-20,
+                    h0=h0, h_max=h_max)
+    assert status[0] == 0 and ref.status == bdf.OK
+    assert stats["n_steps"][0] >= 300 and stats["h"][0] <= h_max * (1 + 1e-12)
+    assert rel_err_above(x[0], ref.x) <= TOL, rel_err_above(x[0], ref.x)
+
+
 def test_largest_and_too_large_networks(ab, dev):
     # 512 species fill the factorisation's 512 x 512 tile exactly; 513 do not fit
     net = synth.large_network(512, 6000, seed=512)

@@ -98,6 +98,23 @@ def test_order_cap_one_is_implicit_euler_throughout():
         bdf.solve(ch, np.array([1.0, 0.0]), 1.0, max_order=6)
 
 
+def test_step_bounds():
+    # h0 is the first step taken, h_max bounds every step, and the solution is
+    # still the exponential to the tolerance's reach
+    net = tiny_nets.decay(2.0)
+    ch = chem.cell_chemistry(net, CELL)
+    k = ch.k[0]
+    t_end, h0, h_max = 5.0 / k, 1e-9 / k, 5.0 / (400 * k)
+    res = bdf.solve(ch, np.array([1.0, 0.0]), t_end, 1e-8, 1e-30, record=True, h0=h0, h_max=h_max)
+    assert res.status == bdf.OK
+    assert res.history[0][0] == h0
+    assert all(h <= h_max * (1 + 1e-12) for (h, _q, _t, _x) in res.history)
+    assert len(res.history) >= 400
+    np.testing.assert_allclose(res.x, [np.exp(-5.0), -np.expm1(-5.0)], rtol=1e-6)
+    free = bdf.solve(ch, np.array([1.0, 0.0]), t_end, 1e-8, 1e-30, record=True)
+    assert max(h for (h, _q, _t, _x) in free.history) > h_max
+
+
 def test_decay_matches_exponential():
     net = tiny_nets.decay(2.0)
     ch = chem.cell_chemistry(net, CELL)
