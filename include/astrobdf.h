@@ -95,6 +95,10 @@ typedef struct abdf_options {
                                 * heuristic (still capped by t_end and h_max); 0 (default) =
                                 * heuristic */
     double h_max;              /* upper bound on every step size [s]; 0 (default) = none */
+    const double *atol_species; /* DEVICE array of S absolute tolerances (one per species,
+                                 * each finite and >= 0) used in place of atol, or NULL
+                                 * (default).  Read when the call (or server) starts; the
+                                 * caller keeps ownership. */
 } abdf_options;
 
 /* Per-cell counters (written to a DEVICE array of n_cells structs). */

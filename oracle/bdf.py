@@ -171,7 +171,8 @@ def solve(chem, x0, t_end, rtol=1e-6, atol=1e-20, max_steps=100000,
           newton_tol=None, record=False, max_order=MAX_ORDER, h0=0.0, h_max=0.0) -> Result:
     """Integrate dx/dt = f(x) from t = 0 to t_end with adaptive order and step.
 
-    max_order (1..5) caps the order the order selection may reach; 1 leaves
+    atol is a scalar or one absolute tolerance per species.  max_order
+    (1..5) caps the order the order selection may reach; 1 leaves
     the implicit Euler method under the same error and step control.  h0 > 0
     replaces the starting-step heuristic's result; h_max > 0 bounds every step
     (the starting step, and each increase chosen with the order)."""
@@ -181,7 +182,9 @@ def solve(chem, x0, t_end, rtol=1e-6, atol=1e-20, max_steps=100000,
     S = x0.shape[0]
     stats = Stats()
     hist = [] if record else None
-    if not (np.all(np.isfinite(x0)) and np.isfinite(t_end) and t_end >= 0 and rtol > 0 and atol >= 0):
+    atol = np.asarray(atol, dtype=float) if np.ndim(atol) else float(atol)
+    if not (np.all(np.isfinite(x0)) and np.isfinite(t_end) and t_end >= 0 and rtol > 0
+            and np.all(np.isfinite(atol)) and np.all(np.asarray(atol) >= 0)):
         return Result(x0.copy(), BAD_INPUT, 0.0, stats, hist)
     if t_end == 0.0:
         return Result(x0.copy(), OK, 0.0, stats, hist)

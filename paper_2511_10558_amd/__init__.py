@@ -120,13 +120,22 @@ def default_options() -> Options:
 
 def make_options(rtol=1e-6, atol=1e-20, max_steps=100000, precision="fp64", check_every=8,
                  hbm_budget_bytes=0, newton_tol=0.0, lu_reuse=0.0, max_order=5, h0=0.0,
-                 h_max=0.0) -> Options:
+                 h_max=0.0, atol_species=None) -> Options:
+    """abdf_options.  atol_species: an FP64 device tensor of one absolute
+    tolerance per species (used in place of atol), kept referenced by the
+    returned options."""
     o = default_options()
     o.rtol, o.atol, o.max_steps = rtol, atol, max_steps
     o.precision = PREC[precision] if isinstance(precision, str) else int(precision)
     o.check_every, o.hbm_budget_bytes, o.newton_tol = check_every, hbm_budget_bytes, newton_tol
     o.lu_reuse, o.max_order = lu_reuse, max_order
     o.h0, o.h_max = h0, h_max
+    if atol_species is not None:
+        torch = _torch()
+        if atol_species.dtype != torch.float64 or atol_species.dim() != 1 or not atol_species.is_contiguous():
+            raise ValueError("atol_species must be a contiguous 1-D float64 tensor")
+        o.atol_species = ctypes.c_void_p(atol_species.data_ptr())
+        o._atol_species = atol_species   # keeps the array alive with the options
     return o
 
 

@@ -24,6 +24,7 @@ class Options(ctypes.Structure):
         ("lu_reuse", ctypes.c_double),
         ("h0", ctypes.c_double),
         ("h_max", ctypes.c_double),
+        ("atol_species", ctypes.c_void_p),
     ]
 
 

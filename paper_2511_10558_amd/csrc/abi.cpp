@@ -77,6 +77,7 @@ abdf_status check_opts(const abdf_options &o) {
     if (o.max_order < 0 || o.max_order > 5) return fail(ABDF_E_ARG, "max_order must be in 1..5 (0: 5)");
     if (!(o.h0 >= 0.0) || !std::isfinite(o.h0)) return fail(ABDF_E_ARG, "h0 must be finite and >= 0");
     if (!(o.h_max >= 0.0) || !std::isfinite(o.h_max)) return fail(ABDF_E_ARG, "h_max must be finite and >= 0");
+    if (o.atol_species) CHECK_DEV(o.atol_species, "atol_species");
     return ABDF_OK;
 }
 
@@ -109,6 +110,7 @@ void abdf_options_default(abdf_options *opt) {
     opt->max_order = 5;
     opt->h0 = 0.0;
     opt->h_max = 0.0;
+    opt->atol_species = nullptr;
 }
 
 const char *abdf_last_error(void) { return g_last_error.c_str(); }
@@ -180,10 +182,9 @@ abdf_status abdf_solve(const abdf_network *net, int64_t n_cells, const double *T
         const long long nslots = slot_count(*dn, o, n_cells);
         if (nslots < 1) return fail(ABDF_E_BUDGET, "not even one cell fits in the workspace budget");
         abdf::Engine eng(net->host, *dn, o.precision, o.max_steps);
-        eng.set_lu_reuse(o.lu_reuse);
-        eng.set_max_order(o.max_order);
-        eng.set_step_bounds(o.h0, o.h_max);
-        int r = eng.init(int(nslots), err);
+        int r = eng.set_options(o, err);
+        if (r != ABDF_OK) return fail(static_cast<abdf_status>(r), err);
+        r = eng.init(int(nslots), err);
         if (r != ABDF_OK) return fail(static_cast<abdf_status>(r), err);
         abdf::BatchIO io{n_cells, T, n_H, A_V, zeta, G0, x0, t_end, x_out, cell_status, stats};
         r = eng.solve(io, o, static_cast<hipStream_t>(stream), err);

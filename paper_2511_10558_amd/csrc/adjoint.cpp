@@ -84,10 +84,9 @@ int Tape::record(const BatchIO &io, const double *alpha, const abdf_options &opt
         return ABDF_E_NOMEM;
     }
     eng_ = std::make_unique<Engine>(net_, dn_, opt.precision, opt.max_steps);
-    eng_->set_lu_reuse(opt.lu_reuse);
-    eng_->set_max_order(opt.max_order);
-    eng_->set_step_bounds(opt.h0, opt.h_max);
-    int rc = eng_->init(int(nslots), err);
+    int rc = eng_->set_options(opt, err);
+    if (rc != ABDF_OK) return rc;
+    rc = eng_->init(int(nslots), err);
     if (rc != ABDF_OK) return rc;
     Slots &s = eng_->slots();
     s.tape_cap = cap;

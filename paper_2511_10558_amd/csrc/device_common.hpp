@@ -49,6 +49,7 @@ struct Slots {
     int max_order;    // highest order the order selection may reach (1..kMaxOrder)
     double h0;        // first step (> 0 replaces the starting-step heuristic), seconds
     double h_max;     // bound on every step (0: none), seconds
+    const double *atol_sp;   // [S] per-species absolute tolerances, or null (each cell's atol)
     SlotCtl *ctl;
     double *phi;      // [n][5]: T, n_H, A_V, zeta, G0
     double *k;        // [n][R]
@@ -80,6 +81,11 @@ struct Slots {
 };
 
 // The factor storage of a slot in element type T.
+// Absolute tolerance of species i in a slot's error and Newton weights.
+__device__ __forceinline__ double atol_of(const Slots &s, const SlotCtl &cs, int i) {
+    return s.atol_sp ? s.atol_sp[i] : cs.atol;
+}
+
 template <typename T>
 __device__ __forceinline__ T *slot_lu(const Slots &s, int slot) {
     return reinterpret_cast<T *>(static_cast<char *>(s.lu) + size_t(slot) * s.lu_stride);

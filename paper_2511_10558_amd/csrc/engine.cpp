@@ -136,12 +136,30 @@ size_t Engine::bytes_per_slot(const DeviceNet &dn, int prec) {
            NP * sizeof(int32_t) + 7 * sizeof(int32_t) + sizeof(long long);
 }
 
+int Engine::set_options(const abdf_options &o, std::string &err) {
+    set_lu_reuse(o.lu_reuse);
+    set_max_order(o.max_order);
+    set_step_bounds(o.h0, o.h_max);
+    atol_sp_.clear();
+    if (o.atol_species) {
+        atol_sp_.resize(size_t(dn_.S));
+        HIP_TRY(hipMemcpy(atol_sp_.data(), o.atol_species, atol_sp_.size() * sizeof(double), hipMemcpyDeviceToHost));
+        for (double v : atol_sp_)
+            if (!(v >= 0.0) || !std::isfinite(v)) {
+                err = "atol_species entries must be finite and >= 0";
+                atol_sp_.clear();
+                return ABDF_E_ARG;
+            }
+    }
+    return ABDF_OK;
+}
+
 int Engine::init(int nslots, std::string &err) {
     const size_t n = size_t(nslots), S = dn_.S, R = dn_.R, NP = dn_.NP;
     const size_t lu_stride = lu_bytes(int(NP), ABDF_PREC_FP64), dinv_stride = dinv_bytes(int(NP), ABDF_PREC_FP64);
     struct Part { void **dst; size_t bytes; };
     void *ctl, *phi, *k, *D, *x, *d, *psi, *scl, *xJ, *rb, *jval, *lu, *dinv, *perm, *act, *lul, *nol, *fin, *cnt,
-        *aslots, *acells;
+        *aslots, *acells, *atol_sp;
     Part parts[] = {
         {&ctl, n * sizeof(SlotCtl)}, {&phi, n * 5 * sizeof(double)}, {&k, n * R * sizeof(double)},
         {&D, n * kDRows * S * sizeof(double)}, {&x, n * S * sizeof(double)}, {&d, n * S * sizeof(double)},
@@ -150,7 +168,7 @@ int Engine::init(int nslots, std::string &err) {
         {&lu, n * lu_stride}, {&dinv, n * dinv_stride}, {&perm, n * NP * sizeof(int32_t)}, {&act, 3 * n * sizeof(int32_t)},
         {&lul, 3 * n * sizeof(int32_t)}, {&nol, 3 * n * sizeof(int32_t)}, {&fin, n * sizeof(int32_t)},
         {&cnt, kCountSlots * sizeof(int32_t)},
-        {&aslots, n * sizeof(int32_t)}, {&acells, n * sizeof(long long)},
+        {&aslots, n * sizeof(int32_t)}, {&acells, n * sizeof(long long)}, {&atol_sp, S * sizeof(double)},
     };
     size_t total = 0;
     for (auto &p : parts) total += align256(p.bytes);
@@ -194,6 +212,11 @@ int Engine::init(int nslots, std::string &err) {
     s_.max_order = max_order_;
     s_.h0 = h0_;
     s_.h_max = h_max_;
+    s_.atol_sp = nullptr;
+    if (!atol_sp_.empty()) {
+        HIP_TRY(hipMemcpy(atol_sp, atol_sp_.data(), S * sizeof(double), hipMemcpyHostToDevice));
+        s_.atol_sp = static_cast<const double *>(atol_sp);
+    }
     s_.nol = static_cast<int32_t *>(nol);
     s_.fin = static_cast<int32_t *>(fin);
     s_.cnt = static_cast<int32_t *>(cnt);

@@ -58,6 +58,9 @@ class Engine {
         max_order_ = (q >= 1 && q <= kMaxOrder) ? q : kMaxOrder;
         s_.max_order = max_order_;
     }
+    // The method options of o (reuse threshold, order cap, step bounds and the
+    // per-species absolute tolerances, read from the device now).  Before init.
+    int set_options(const abdf_options &o, std::string &err);
     // first step (0: heuristic) and bound on every step (0: none), seconds
     void set_step_bounds(double h0, double h_max) {
         h0_ = h0;
@@ -115,6 +118,7 @@ class Engine {
     double lu_reuse_ = 0.0;
     int max_order_ = kMaxOrder;
     double h0_ = 0.0, h_max_ = 0.0;
+    std::vector<double> atol_sp_;   // per-species absolute tolerances (empty: the scalar atol)
     Slots s_{};
     void *base_ = nullptr;
     int32_t *d_admit_slots_ = nullptr;

@@ -161,7 +161,7 @@ __device__ __forceinline__ void begin_attempt(const Slots &s, int slot, SlotCtl 
         x[i] = xp;
         d[i] = 0.0;
         psi[i] = ps;
-        scl[i] = cs.atol + cs.rtol * fabs(xp);
+        scl[i] = atol_of(s, cs, i) + cs.rtol * fabs(xp);
         if (refresh) xJ[i] = xp;
     }
     __syncthreads();
@@ -253,10 +253,10 @@ __global__ void __launch_bounds__(kBlock) k_admit(Slots s, DeviceNet n, AdmitArg
     }
     // starting step (Hairer, Norsett & Wanner, Solving ODEs I, Sec. II.4), order 1
     cell_rhs(n, k, xs, rate, part, f0);
-    const double rtol = cs.rtol, atol = cs.atol;
+    const double rtol = cs.rtol;
     double s0 = 0.0, s1 = 0.0;
     for (int i = threadIdx.x; i < S; i += kBlock) {
-        const double sc = atol + rtol * fabs(xs[i]);
+        const double sc = atol_of(s, cs, i) + rtol * fabs(xs[i]);
         s0 += (xs[i] / sc) * (xs[i] / sc);
         s1 += (f0[i] / sc) * (f0[i] / sc);
     }
@@ -271,7 +271,7 @@ __global__ void __launch_bounds__(kBlock) k_admit(Slots s, DeviceNet n, AdmitArg
     cell_rhs(n, k, x1, rate, part, f1);
     double s2 = 0.0;
     for (int i = threadIdx.x; i < S; i += kBlock) {
-        const double sc = atol + rtol * fabs(xs[i]);
+        const double sc = atol_of(s, cs, i) + rtol * fabs(xs[i]);
         const double v = (f1[i] - f0[i]) / sc;
         s2 += v * v;
     }
@@ -566,11 +566,11 @@ __global__ void __launch_bounds__(kBlock) k_control(Slots s, int ring) {
     }
     // converged: local error test
     const int q = cs.q;
-    const double rtol = cs.rtol, atol = cs.atol;
+    const double rtol = cs.rtol;
     const double eq = 1.0 / (q + 1);
     double acc = 0.0;
     for (int i = threadIdx.x; i < S; i += kBlock) {
-        const double sc = atol + rtol * fmax(fabs(D[i]), fabs(x[i]));
+        const double sc = atol_of(s, cs, i) + rtol * fmax(fabs(D[i]), fabs(x[i]));
         const double v = eq * d[i] / sc;
         acc += v * v;
     }
@@ -609,7 +609,7 @@ __global__ void __launch_bounds__(kBlock) k_control(Slots s, int ring) {
     double am = 0.0, ap = 0.0;
     bool nonfinite = false;
     for (int i = threadIdx.x; i < S; i += kBlock) {
-        const double sc = atol + rtol * fmax(fabs(D[i]), fabs(x[i]));
+        const double sc = atol_of(s, cs, i) + rtol * fmax(fabs(D[i]), fabs(x[i]));
         // rows 0..q+2 of the difference table, with every index static (masks
         // and selects instead of v[q + 1] etc.) so that v stays in registers
         double v[kDRows];

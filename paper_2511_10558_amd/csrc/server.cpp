@@ -47,10 +47,9 @@ int Server::start(int nslots, std::string &err) {
     HIP_TRY(hipStreamCreateWithFlags(&st_, hipStreamNonBlocking));
     HIP_TRY(hipEventCreateWithFlags(&admit_done_, hipEventDisableTiming));
     eng_ = std::make_unique<Engine>(net_, dn_, opt_.solve.precision, opt_.solve.max_steps);
-    eng_->set_lu_reuse(opt_.solve.lu_reuse);
-    eng_->set_max_order(opt_.solve.max_order);
-    eng_->set_step_bounds(opt_.solve.h0, opt_.solve.h_max);
-    int rc = eng_->init(nslots, err);
+    int rc = eng_->set_options(opt_.solve, err);
+    if (rc != ABDF_OK) return rc;
+    rc = eng_->init(nslots, err);
     if (rc != ABDF_OK) return rc;
     const size_t n = size_t(nslots), S = size_t(dn_.S);
     // one device block: admission inputs, slot and cell lists, harvested outputs

@@ -133,6 +133,11 @@ def test_null_and_invalid_arguments_without_gpu():
         o = ab.make_options(**kw)
         assert L.abdf_solve(g.handle, 1, *([None] * 7), ctypes.byref(o), None, None, None, None) == 1
         assert word in L.abdf_last_error()
+    o = ab.make_options()
+    host = (ctypes.c_double * 12)()
+    o.atol_species = ctypes.cast(host, ctypes.c_void_p)
+    assert L.abdf_solve(g.handle, 1, *([None] * 7), ctypes.byref(o), None, None, None, None) == 1
+    assert b"atol_species" in L.abdf_last_error()
     o = ab.make_options(max_order=0)   # 0 stands for 5
     assert L.abdf_solve(g.handle, 0, *([None] * 7), ctypes.byref(o), None, None, None, None) == 0
     o = ab.make_options()

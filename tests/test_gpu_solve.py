@@ -235,6 +235,31 @@ def test_step_bounds_match_oracle(ab, dev):
     assert rel_err_above(x[0], ref.x) <= TOL, rel_err_above(x[0], ref.x)
 
 
+def test_per_species_atol(ab, dev):
+    # one absolute tolerance per species: a constant vector is the scalar run
+    # bit for bit; seeded tolerances match the oracle given the same vector;
+    # a negative entry is refused
+    import torch
+    net = synth.network_for_config("net200")
+    cells = synth.sample_cells(net, 2, seed=2001)
+    g = ab.Network.from_text(net.to_text())
+    S = net.n_species
+    x_s, st_s, _ = solve_cells(ab, g, cells, dev)
+    const = torch.full((S,), 1e-20, dtype=torch.float64, device=dev)
+    x_c, st_c, _ = solve_cells(ab, g, cells, dev, atol_species=const)
+    assert (st_s == 0).all() and (st_c == 0).all() and np.array_equal(x_s, x_c)
+    av = np.exp(np.random.default_rng(77).uniform(np.log(1e-24), np.log(1e-16), S))
+    x_v, st_v, _ = solve_cells(ab, g, cells, dev, atol_species=t(av, dev))
+    for c in range(cells.n):
+        ref = bdf.solve(chem.cell_chemistry(net, cells.cell(c)), cells.x0[c], cells.t_end[c], 1e-6, av)
+        assert st_v[c] == 0 and ref.status == bdf.OK
+        assert rel_err_above(x_v[c], ref.x) <= TOL, rel_err_above(x_v[c], ref.x)
+    bad = t(np.where(np.arange(S) == 3, -1.0, 1e-20), dev)
+    with pytest.raises(ab.AbdfError) as e:
+        solve_cells(ab, g, cells, dev, atol_species=bad)
+    assert e.value.code == 1 and "atol_species" in str(e.value)
+
+
 def test_largest_and_too_large_networks(ab, dev):
     # 512 species fill the factorisation's 512 x 512 tile exactly; 513 do not fit
     net = synth.large_network(512, 6000, seed=512)

@@ -115,6 +115,22 @@ def test_step_bounds():
     assert max(h for (h, _q, _t, _x) in free.history) > h_max
 
 
+def test_per_species_atol():
+    # a vector of the scalar everywhere is the scalar run exactly; a huge atol on
+    # B leaves the control to A, whose value stays the exponential
+    net = tiny_nets.decay(2.0)
+    ch = chem.cell_chemistry(net, CELL)
+    k = ch.k[0]
+    x0 = np.array([1.0, 0.0])
+    a = bdf.solve(ch, x0, 5.0 / k, 1e-8, 1e-30)
+    b = bdf.solve(ch, x0, 5.0 / k, 1e-8, np.array([1e-30, 1e-30]))
+    assert np.array_equal(a.x, b.x) and a.stats.n_attempts == b.stats.n_attempts
+    c = bdf.solve(ch, x0, 5.0 / k, 1e-8, np.array([1e-30, 1.0]))
+    assert c.status == bdf.OK
+    assert c.x[0] == pytest.approx(np.exp(-5.0), rel=1e-6)
+    assert bdf.solve(ch, x0, 5.0 / k, 1e-8, np.array([1e-30, -1.0])).status == bdf.BAD_INPUT
+
+
 def test_decay_matches_exponential():
     net = tiny_nets.decay(2.0)
     ch = chem.cell_chemistry(net, CELL)
