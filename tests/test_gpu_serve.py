@@ -67,6 +67,24 @@ def test_served_results_equal_batch_results_bitwise(ab, dev, net200):
         assert np.array_equal(c["stats"]["n_steps"], stb["n_steps"])
 
 
+def test_served_results_follow_the_method_options(ab, dev, net200):
+    # the server applies the solve options (order cap, step bounds) exactly as
+    # the batch entry point does
+    g = ab.Network.from_text(net200.to_text())
+    reqs = _stream(net200, [(21, 3, 1e5), (22, 4, 1e6)])
+    opts = dict(max_order=2, h0=10.0, h_max=1e11)
+    with ab.Server(g, **opts) as srv:
+        ids = [_submit(srv, c) for c in reqs]
+        done = _drain(srv, len(ids))
+    for rid, cells in zip(ids, reqs):
+        c = done[rid]
+        assert c["n_failed"] == 0
+        xb, sb, stb = solve_cells(ab, g, cells, dev, **opts)
+        assert (c["status"] == sb).all() and (stb["order"] <= 2).all()
+        assert np.array_equal(c["x"], xb)
+        assert np.array_equal(c["stats"]["n_steps"], stb["n_steps"])
+
+
 def test_result_alone_equals_result_in_the_mix(ab, dev, net200):
     g = ab.Network.from_text(net200.to_text())
     probe = synth.sample_cells(net200, 9, seed=21, t_end_yr=2e5)
