@@ -408,6 +408,9 @@ class Server:
             for k, v in opts.items():
                 if k == "precision":
                     v = PREC[v] if isinstance(v, str) else int(v)
+                if k == "atol_species" and v is not None:
+                    o.atol_species = make_options(atol_species=v).atol_species   # read at creation
+                    continue
                 setattr(o, k, v)
         so.max_slots, so.max_queued_cells = max_slots, max_queued_cells
         self._net = net           # the network must outlive the server

@@ -83,6 +83,15 @@ def test_served_results_follow_the_method_options(ab, dev, net200):
         assert (c["status"] == sb).all() and (stb["order"] <= 2).all()
         assert np.array_equal(c["x"], xb)
         assert np.array_equal(c["stats"]["n_steps"], stb["n_steps"])
+    # per-species absolute tolerances, read when the server is created
+    import torch
+    av = torch.tensor(np.exp(np.random.default_rng(5).uniform(np.log(1e-22), np.log(1e-18), net200.n_species)),
+                      dtype=torch.float64, device=dev)
+    with ab.Server(g, atol_species=av) as srv:
+        rid = _submit(srv, reqs[0])
+        c = _drain(srv, 1)[rid]
+    xb, sb, _ = solve_cells(ab, g, reqs[0], dev, atol_species=av)
+    assert (c["status"] == sb).all() and np.array_equal(c["x"], xb)
 
 
 def test_result_alone_equals_result_in_the_mix(ab, dev, net200):
