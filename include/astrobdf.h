@@ -128,13 +128,16 @@ const char *abdf_last_error(void);
  * common format, from which the incidence matrix is built).  Text format:
  *   astrobdf-network 1
  *   name <word>
+ *   [albedo <omega>]                                  (optional, in [0, 1), default 0)
  *   elements <E> <symbol>...
  *   species <S>
  *   <i> <name> <charge> <count of each element>      (S lines)
  *   reactions <R>
  *   <r> <type> <nr> <r1> <r2> <np> <p1> <p2> <p3> <alpha> <beta> <gamma>   (R lines)
  *   end
- * type: 0 two-body, 1 cosmic ray, 2 photo; unused reactant/product slots are -1.
+ * type: 0 two-body, 1 cosmic ray, 2 photo, 3 photoreaction by cosmic-ray-induced
+ * photons, k = alpha (T/300)^beta gamma zeta / (1 - omega) with gamma the
+ * reaction's efficiency (paper App. B.1); unused reactant/product slots are -1.
  * Every reaction must conserve each element and the charge exactly (integer
  * check); otherwise ABDF_E_NONCONSERVING names the reaction.  The handle is
  * owned by the library, immutable after loading and safe to share between

@@ -12,7 +12,7 @@ from __future__ import annotations
 import numpy as np
 import scipy.sparse as sp
 
-TWO_BODY, COSMIC_RAY, PHOTO = 0, 1, 2
+TWO_BODY, COSMIC_RAY, PHOTO, CR_PHOTON = 0, 1, 2, 3
 
 
 def rate_coefficients(net, T, n_H, A_V, zeta, G0) -> np.ndarray:
@@ -21,6 +21,8 @@ def rate_coefficients(net, T, n_H, A_V, zeta, G0) -> np.ndarray:
     two-body  (Sec. 2, Kooij-Arrhenius): alpha (T/300)^beta exp(-gamma/T), times n_H
     cosmic ray (Sec. 2, direct ionisation): alpha zeta
     photo     (App. B.1): alpha G0 exp(-gamma A_V), G0 being the UV field F_UV
+    cosmic-ray-induced photons (App. B.1): alpha (T/300)^beta E zeta / (1 - omega),
+              E the efficiency (the gamma field), omega the network's dust albedo
     """
     k = np.empty(net.n_reactions)
     for r in range(net.n_reactions):
@@ -32,6 +34,8 @@ def rate_coefficients(net, T, n_H, A_V, zeta, G0) -> np.ndarray:
             k[r] = a * zeta
         elif t == PHOTO:
             k[r] = a * G0 * np.exp(-g * A_V)
+        elif t == CR_PHOTON:
+            k[r] = a * (T / 300.0) ** b * g * zeta / (1.0 - net.albedo)
         else:
             raise ValueError(f"unknown reaction type {t}")
     return k
@@ -49,6 +53,8 @@ def log_rate_derivatives(net, T, n_H, A_V, zeta, G0) -> np.ndarray:
     cosmic ray: log k = log alpha + log zeta -> d/dzeta = 1/zeta
     photo:      log k = log alpha + log G0 - gamma A_V
                 -> d/dA_V = -gamma, d/dG0 = 1/G0
+    CR photons: log k = log alpha + beta log(T/300) + log E + log zeta - log(1 - omega)
+                -> d/dT = beta/T, d/dzeta = 1/zeta
     """
     D = np.zeros((net.n_reactions, 5))
     for r in range(net.n_reactions):
@@ -62,6 +68,9 @@ def log_rate_derivatives(net, T, n_H, A_V, zeta, G0) -> np.ndarray:
         elif t == PHOTO:
             D[r, 2] = -g
             D[r, 4] = 1.0 / G0
+        elif t == CR_PHOTON:
+            D[r, 0] = b / T
+            D[r, 3] = 1.0 / zeta
         else:
             raise ValueError(f"unknown reaction type {t}")
     return D

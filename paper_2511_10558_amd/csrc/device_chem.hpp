@@ -8,7 +8,9 @@
 namespace abdf {
 
 // k_r for one cell (paper Sec. 2 Kooij-Arrhenius and direct cosmic-ray forms,
-// App. B.1 photo form); two-body coefficients carry the factor n_H of the
+// App. B.1 photo form and the cosmic-ray-induced photon form
+// alpha (T/300)^beta E zeta / (1 - omega), E the reaction's efficiency kept in
+// its gamma field, omega the network's dust albedo); two-body coefficients carry the factor n_H of the
 // fractional-abundance state.  Written to global memory, coalesced over r.
 __device__ inline void cell_rates(const DeviceNet &n, const double *phi, double *k) {
     const double T = phi[0], nH = phi[1], Av = phi[2], zeta = phi[3], G0 = phi[4];
@@ -19,6 +21,7 @@ __device__ inline void cell_rates(const DeviceNet &n, const double *phi, double 
         double v;
         if (t == kTwoBody) v = a * pow(T300, n.beta[r]) * exp(-n.gamma[r] / T) * nH;
         else if (t == kCosmicRay) v = a * zeta;
+        else if (t == kCrPhoton) v = a * pow(T300, n.beta[r]) * (n.gamma[r] / (1.0 - n.albedo)) * zeta;
         else v = a * G0 * exp(-n.gamma[r] * Av);
         k[r] = v;
     }

@@ -1033,6 +1033,9 @@ __global__ void __launch_bounds__(kBlock) k_phys_grad(DeviceNet n, PhysArgs p, c
             sN += gr / nH;
         } else if (t == kCosmicRay) {
             sZ += gr / zeta;
+        } else if (t == kCrPhoton) {
+            sT += gr * n.beta[r] / T;
+            sZ += gr / zeta;
         } else {
             sA += -n.gamma[r] * gr;
             sG += gr / G0;

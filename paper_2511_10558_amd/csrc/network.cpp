@@ -58,7 +58,13 @@ int HostNetwork::parse(const char *text, size_t len, std::string &err) {
         return ABDF_E_PARSE;
     }
     if (!expect_word(t, "name") || !t.get(name)) { err = "missing name"; return ABDF_E_PARSE; }
-    if (!expect_word(t, "elements") || !t.get(E) || E < 1 || E > 32) { err = "bad elements line"; return ABDF_E_PARSE; }
+    std::string word;
+    if (!t.get(word)) { err = "bad elements line"; return ABDF_E_PARSE; }
+    if (word == "albedo") {
+        if (!t.get(albedo) || !(albedo >= 0.0 && albedo < 1.0)) { err = "albedo must be in [0, 1)"; return ABDF_E_PARSE; }
+        if (!t.get(word)) { err = "bad elements line"; return ABDF_E_PARSE; }
+    }
+    if (word != "elements" || !t.get(E) || E < 1 || E > 32) { err = "bad elements line"; return ABDF_E_PARSE; }
     elements.resize(E);
     for (int e = 0; e < E; ++e)
         if (!t.get(elements[e])) { err = "bad elements line"; return ABDF_E_PARSE; }
@@ -91,7 +97,7 @@ int HostNetwork::parse(const char *text, size_t len, std::string &err) {
         bool ok = t.get(idx) && idx == r && t.get(rtype[r]) && t.get(nr) && t.get(a[0]) && t.get(a[1]) &&
                   t.get(np) && t.get(p[0]) && t.get(p[1]) && t.get(p[2]) && t.get(alpha[r]) &&
                   t.get(beta[r]) && t.get(gamma[r]);
-        if (!ok || nr < 1 || nr > 2 || np < 1 || np > 3 || rtype[r] < 0 || rtype[r] > 2) {
+        if (!ok || nr < 1 || nr > 2 || np < 1 || np > 3 || rtype[r] < 0 || rtype[r] > 3) {
             err = "bad reaction record " + std::to_string(r);
             return ABDF_E_PARSE;
         }
@@ -274,6 +280,7 @@ const DeviceNet *HostNetwork::device_tables(std::string &err) const {
     auto chk = [&](hipError_t x) { if (e == hipSuccess) e = x; };
     chk(upload(&d->rx_ab, ab));
     chk(upload(&d->rx_type, rtype));
+    d->albedo = albedo;
     chk(upload(&d->alpha, alpha));
     chk(upload(&d->beta, beta));
     chk(upload(&d->gamma, gamma));

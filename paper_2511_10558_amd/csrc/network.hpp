@@ -12,12 +12,14 @@ namespace abdf {
 constexpr int kTwoBody = 0;
 constexpr int kCosmicRay = 1;
 constexpr int kPhoto = 2;
+constexpr int kCrPhoton = 3;   // photoreaction by cosmic-ray-induced photons
 constexpr int kRhsSegment = 32;   // CSR entries summed by one thread before the per-species pass
 
 // Device copies of the network tables (one per HIP device).
 struct DeviceNet {
     int device = -1;
     int S = 0, R = 0, NP = 0;
+    double albedo = 0.0;           // dust albedo of the cosmic-ray-induced photon rate
     // per reaction
     int32_t *rx_ab = nullptr;      // reactant a in low 16 bits, b in high 16 bits (0xffff: none)
     int32_t *rx_type = nullptr;
@@ -48,6 +50,7 @@ struct DeviceNet {
 
 struct HostNetwork {
     std::string name;
+    double albedo = 0.0;                  // dust grain albedo (optional "albedo" line), in [0, 1)
     std::vector<std::string> elements;
     std::vector<std::string> species;
     std::vector<int32_t> charge;          // [S]

@@ -16,6 +16,7 @@ from .network import (  # noqa: F401
     TWO_BODY,
     COSMIC_RAY,
     PHOTO,
+    CR_PHOTON,
 )
 from .cells import (  # noqa: F401
     YEAR_S,

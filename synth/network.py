@@ -36,7 +36,8 @@ N_ELEM = len(ELEMENTS)
 TWO_BODY = 0
 COSMIC_RAY = 1
 PHOTO = 2
-RTYPE_NAMES = {TWO_BODY: "two_body", COSMIC_RAY: "cosmic_ray", PHOTO: "photo"}
+CR_PHOTON = 3   # photoreaction by cosmic-ray-induced photons
+RTYPE_NAMES = {TWO_BODY: "two_body", COSMIC_RAY: "cosmic_ray", PHOTO: "photo", CR_PHOTON: "cr_photon"}
 
 # packed composition key: one base-32 digit per element, one for charge+1 per species
 _BASE = 32
@@ -49,12 +50,13 @@ class Network:
     species: list
     comp: np.ndarray       # (S, 6) int64 element counts
     charge: np.ndarray     # (S,) int64
-    rtype: np.ndarray      # (R,) int32, TWO_BODY / COSMIC_RAY / PHOTO
+    rtype: np.ndarray      # (R,) int32, TWO_BODY / COSMIC_RAY / PHOTO / CR_PHOTON
     reactants: np.ndarray  # (R, 2) int32, ascending, -1 padded
     products: np.ndarray   # (R, 3) int32, ascending, -1 padded at the end
     alpha: np.ndarray      # (R,) float64
     beta: np.ndarray       # (R,) float64
     gamma: np.ndarray      # (R,) float64
+    albedo: float = 0.0    # dust albedo of the cosmic-ray-induced photon rate
 
     @property
     def n_species(self) -> int:
@@ -75,6 +77,8 @@ class Network:
         out = io.StringIO()
         out.write("astrobdf-network 1\n")
         out.write(f"name {self.name}\n")
+        if self.albedo != 0.0 or (np.asarray(self.rtype) == CR_PHOTON).any():
+            out.write(f"albedo {float(self.albedo)!r}\n")
         out.write(f"elements {N_ELEM} {' '.join(ELEMENTS)}\n")
         out.write(f"species {self.n_species}\n")
         for i, s in enumerate(self.species):
@@ -454,7 +458,7 @@ def network_for_config(name: str) -> Network:
     return _CACHE[name]
 
 
-def make_network(name, species, reactions) -> Network:
+def make_network(name, species, reactions, albedo=0.0) -> Network:
     """Explicit network.  species: [(name, {element: count}, charge)];
     reactions: [(rtype, [reactant names], [product names], alpha, beta, gamma)].
     Raises ValueError if a reaction does not conserve every element and charge."""
@@ -477,4 +481,4 @@ def make_network(name, species, reactions) -> Network:
         rea[r, : len(ri)] = ri
         pro[r, : len(pi)] = pi
         al[r], be[r], ga[r] = a, b, g
-    return Network(name, names, comp, charge, rtype, rea, pro, al, be, ga)
+    return Network(name, names, comp, charge, rtype, rea, pro, al, be, ga, albedo)

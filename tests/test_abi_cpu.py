@@ -52,6 +52,21 @@ def test_generated_networks_load(name):
     assert g.species_name(-1) is None and g.species_name(net.n_species) is None
 
 
+def test_cosmic_ray_photon_type_and_albedo_line():
+    from tests import tiny_nets
+    net = tiny_nets.four_types(albedo=0.6)
+    text = net.to_text()
+    assert "albedo 0.6" in text
+    g = ab.Network.from_text(text)
+    assert g.n_species == net.n_species and g.n_reactions == 10
+    for bad in ("albedo 1.0", "albedo -0.1", "albedo x"):
+        with pytest.raises(ab.AbdfError) as e:
+            ab.Network.from_text(text.replace("albedo 0.6", bad))
+        assert e.value.code == 2
+    # networks without the line keep their text (and an albedo of 0)
+    assert "albedo" not in synth.network_for_config("small").to_text()
+
+
 def test_network_file_load_and_missing_file(tmp_path):
     net = synth.network_for_config("small")
     p = tmp_path / "n.txt"

@@ -38,6 +38,30 @@ def test_rates_match_oracle(ab, dev, name):
         np.testing.assert_allclose(k[c], ref, rtol=1e-13, atol=0)
 
 
+def test_four_rate_laws_match_oracle(ab, dev):
+    # two-body, cosmic-ray, photo and cosmic-ray-induced photon rates, then the
+    # physical-parameter gradient contraction, and a solve of the network
+    from tests import tiny_nets
+    net = tiny_nets.four_types(albedo=0.6)
+    g = ab.Network.from_text(net.to_text())
+    cells = synth.sample_cells(net, 9, seed=4)
+    args = [t(v, dev) for v in (cells.T, cells.n_H, cells.A_V, cells.zeta, cells.G0)]
+    k = ab.rates(g, *args).cpu().numpy()
+    gl = np.random.default_rng(8).normal(size=(cells.n, net.n_reactions))
+    gphi = ab.phys_gradient(g, *args, t(gl, dev)).cpu().numpy()
+    for c in range(cells.n):
+        np.testing.assert_allclose(k[c], chem.rate_coefficients(net, **cells.cell(c)), rtol=1e-13, atol=0)
+        want = chem.phys_gradient(net, cells.cell(c), gl[c])
+        np.testing.assert_allclose(gphi[c], want, rtol=1e-12, atol=1e-12 * np.abs(want).max())
+    from tests.gpu_util import rel_err_above, solve_cells
+    from oracle import bdf
+    x, status, _ = solve_cells(ab, g, cells, dev)
+    for c in range(3):
+        ref = bdf.solve(chem.cell_chemistry(net, cells.cell(c)), cells.x0[c], cells.t_end[c], 1e-6, 1e-20)
+        assert status[c] == 0 and ref.status == bdf.OK
+        assert rel_err_above(x[c], ref.x) <= 1e-4
+
+
 @pytest.mark.parametrize("name", ["small", "net200", "net500"])
 def test_rhs_matches_oracle(ab, dev, name):
     net = synth.network_for_config(name)

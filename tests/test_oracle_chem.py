@@ -167,3 +167,32 @@ def test_log_rate_derivatives_match_central_differences():
     two, cr, ph = (net.rtype == t for t in (synth.TWO_BODY, synth.COSMIC_RAY, synth.PHOTO))
     assert np.all(D[cr][:, [0, 1, 2, 4]] == 0) and np.all(D[ph][:, [0, 1, 3]] == 0)
     assert np.all(D[two][:, 2:] == 0)
+
+
+def test_cosmic_ray_photon_rates():
+    # photorates by cosmic-ray-induced photons scale with zeta and (T/300)^beta,
+    # are independent of n_H, A_V and G0, and grow as 1 / (1 - albedo); their
+    # log-derivatives match central differences
+    from tests import tiny_nets
+    net = tiny_nets.four_types(albedo=0.6)
+    crp = net.rtype == synth.CR_PHOTON
+    assert crp.sum() == 3
+    k0 = chem.rate_coefficients(net, **CELL)
+    moved = dict(CELL, n_H=3 * CELL["n_H"], A_V=CELL["A_V"] + 2.0, G0=5.0)
+    assert np.array_equal(chem.rate_coefficients(net, **moved)[crp], k0[crp])
+    k2 = chem.rate_coefficients(net, **dict(CELL, zeta=2 * CELL["zeta"]))
+    np.testing.assert_allclose(k2[crp], 2 * k0[crp], rtol=1e-15)
+    kt = chem.rate_coefficients(net, **dict(CELL, T=2 * CELL["T"]))
+    np.testing.assert_allclose(kt[crp] / k0[crp], 2.0 ** net.beta[crp], rtol=1e-14)
+    dark = tiny_nets.four_types(albedo=0.0)
+    np.testing.assert_allclose(k0[crp] / chem.rate_coefficients(dark, **CELL)[crp], 1 / 0.4, rtol=1e-15)
+    D = chem.log_rate_derivatives(net, **CELL)
+    for j, name in enumerate(chem.PHYS_PARAMS):
+        step = 1e-5 * (abs(CELL[name]) if CELL[name] != 0 else 1.0)
+        up, dn = dict(CELL), dict(CELL)
+        up[name] += step
+        dn[name] -= step
+        fd = (np.log(chem.rate_coefficients(net, **up)) - np.log(chem.rate_coefficients(net, **dn))) / (2 * step)
+        scale = max(np.abs(D[:, j]).max(), 1e-300)
+        assert np.all(np.abs(fd - D[:, j]) <= 1e-7 * scale + 1e-12 * np.abs(fd)), name
+    assert np.all(D[crp][:, [1, 2, 4]] == 0)

@@ -1,6 +1,6 @@
 """Tiny hand-built networks with closed-form behaviour, used as pins."""
 import synth
-from synth import COSMIC_RAY, PHOTO, TWO_BODY
+from synth import COSMIC_RAY, CR_PHOTON, PHOTO, TWO_BODY
 
 
 def decay(alpha=2.0):
@@ -47,3 +47,22 @@ def first_order():
         (PHOTO, ["H2+"], ["H", "H+"], 1e-10, 0, 1.0),
     ]
     return synth.make_network("first-order", sp, rx)
+
+
+def four_types(albedo=0.6):
+    """All four rate laws, cosmic-ray-induced photodissociation among them."""
+    sp = [("e-", {}, -1), ("H", {"H": 1}, 0), ("H2", {"H": 2}, 0), ("H+", {"H": 1}, 1), ("CO", {"C": 1, "O": 1}, 0),
+          ("C", {"C": 1}, 0), ("O", {"O": 1}, 0), ("C+", {"C": 1}, 1), ("OH", {"H": 1, "O": 1}, 0)]
+    rx = [
+        (TWO_BODY, ["H", "H"], ["H2"], 3e-17, 0.5, 0.0),
+        (TWO_BODY, ["C", "O"], ["CO"], 1e-10, -0.2, 20.0),
+        (TWO_BODY, ["O", "H"], ["OH"], 5e-11, 0.3, 10.0),
+        (TWO_BODY, ["C+", "e-"], ["C"], 2e-12, -0.6, 0.0),
+        (COSMIC_RAY, ["H"], ["H+", "e-"], 0.46, 0.0, 0.0),
+        (PHOTO, ["CO"], ["C", "O"], 2e-10, 0.0, 3.5),
+        (PHOTO, ["C"], ["C+", "e-"], 3e-10, 0.0, 3.0),
+        (CR_PHOTON, ["CO"], ["C", "O"], 1.0, 0.5, 105.0),
+        (CR_PHOTON, ["OH"], ["O", "H"], 1.3, 0.0, 509.0),
+        (CR_PHOTON, ["C"], ["C+", "e-"], 1.0, 0.0, 1020.0),
+    ]
+    return synth.make_network("four-types", sp, rx, albedo=albedo)
