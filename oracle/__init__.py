@@ -15,7 +15,7 @@ bdf     variable-order, variable-step BDF (quasi-constant step size,
         discrete forward sensitivities.
 steady  steady state of the rate equations by damped Newton with the
         conservation laws substituted for dependent rows.
-brute   fixed-step 2-stage Gauss-Legendre reference integrator.
+brute   fixed-step 3-stage Radau IIA reference integrator with step halving.
 
 Pins: every function here is checked by ``tests/test_oracle_*.py`` against
 closed forms, invariants, library routines or brute force; see the pin table

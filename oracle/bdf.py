@@ -87,8 +87,9 @@ def rescale(D, q, rho):
 
 
 def wrms(v, scale):
-    """Weighted root-mean-square norm sqrt(mean((v/scale)^2))."""
-    return float(np.sqrt(np.mean((v / scale) ** 2)))
+    """Weighted root-mean-square norm sqrt(mean(|v/scale|^2)) (|.| the modulus
+    for the complex iterates of complex-step replays)."""
+    return float(np.sqrt(np.mean(np.abs(v / scale) ** 2)))
 
 
 def initial_step(f, x0, f0, t_span, rtol, atol):
@@ -191,6 +192,9 @@ def solve(chem, x0, t_end, rtol=1e-6, atol=1e-20, max_steps=100000,
     tol = newton_tolerance(rtol) if newton_tol is None else newton_tol
     f0 = chem.f(x0)
     stats.n_rhs += 1
+    if not np.all(np.isfinite(f0)):
+        # rates overflow at the initial state: no step can be taken
+        return Result(x0.copy(), NONFINITE, 0.0, stats, hist)
     h = initial_step(chem.f, x0, f0, t_end, rtol, atol)
     stats.n_rhs += 1
     if h0 > 0.0:
@@ -310,18 +314,27 @@ def replay(chem, x0, history, newton_atol=1e-12, rtol=1e-6, atol=1e-20,
            sens_dfdp=None, max_newton=50):
     """Frozen-sequence BDF: the accepted (h, q) sequence of a recorded run, each
     corrector solved by full Newton until the weighted correction norm is below
-    `newton_atol`.  This is the discrete map whose exact derivative the adjoint
-    computes.
+    `newton_atol` (or `max_newton` iterations).  This is the discrete map whose
+    exact derivative the adjoint computes.
+
+    The arithmetic follows the coefficients' type: FP64; complex (a rate
+    coefficient perturbed by i h gives the complex-step derivative of the map,
+    Im L / h, free of cancellation); or np.longdouble (x86 extended precision:
+    the state, residuals and difference tables are carried with a 64-bit
+    significand while each Newton correction is solved in FP64, so the
+    iteration converges to the extended-precision corrector solution).
 
     sens_dfdp(x) -> (S x P) array of d f / d p: if given, the discrete forward
     sensitivities S = dx/dp are carried along (difference array D_S with the
     structure of D, rescaled with it; each step solves
     (I - c J(x_{n+1})) S_{n+1} = S_p - psi_S + c df/dp(x_{n+1})).
     Returns x_end, or (x_end, S_end) with sensitivities."""
-    x0 = np.asarray(x0, dtype=float)
+    work = np.result_type(np.asarray(chem.k).dtype, np.float64)
+    lin = np.complex128 if np.issubdtype(work, np.complexfloating) else np.float64
+    x0 = np.asarray(x0).astype(work)
     S = x0.shape[0]
     I = np.eye(S)
-    D = np.zeros((MAX_ORDER + 3, S))
+    D = np.zeros((MAX_ORDER + 3, S), dtype=work)
     D[0] = x0
     h0 = history[0][0]
     D[1] = h0 * chem.f(x0)
@@ -345,7 +358,7 @@ def replay(chem, x0, history, newton_atol=1e-12, rtol=1e-6, atol=1e-20,
         x = x_p.copy()
         for _ in range(max_newton):
             g = x - x_p - c * chem.f(x) + psi
-            delta = np.linalg.solve(I - c * chem.jac(x), -g)
+            delta = np.linalg.solve((I - c * chem.jac(x)).astype(lin), (-g).astype(lin))
             x = x + delta
             if wrms(delta, scale) <= newton_atol:
                 break

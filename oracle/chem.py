@@ -76,6 +76,46 @@ def log_rate_derivatives(net, T, n_H, A_V, zeta, G0) -> np.ndarray:
     return D
 
 
+def rate_parameter_derivatives(net, T, n_H, A_V, zeta, G0) -> np.ndarray:
+    """dk_r / dphi_j (R x 5) for phi = (T, n_H, A_V, zeta, G0), differentiating
+    the rate laws of rate_coefficients term by term:
+
+    two-body:   k = alpha (T/300)^beta exp(-gamma/T) n_H
+                -> dk/dT = k (beta/T + gamma/T^2), dk/dn_H = alpha (T/300)^beta exp(-gamma/T)
+    cosmic ray: k = alpha zeta -> dk/dzeta = alpha
+    photo:      k = alpha G0 exp(-gamma A_V)
+                -> dk/dA_V = -gamma k, dk/dG0 = alpha exp(-gamma A_V)
+    CR photons: k = alpha (T/300)^beta E zeta / (1 - omega)
+                -> dk/dT = k beta / T, dk/dzeta = alpha (T/300)^beta E / (1 - omega)
+
+    Nothing is divided by zeta or G0, so the derivatives stay exact where a
+    cell has zeta = 0 or G0 = 0 (those reactions then have k = 0)."""
+    k = rate_coefficients(net, T, n_H, A_V, zeta, G0)
+    D = np.zeros((net.n_reactions, 5))
+    for r in range(net.n_reactions):
+        a, b, g = net.alpha[r], net.beta[r], net.gamma[r]
+        t = net.rtype[r]
+        if t == TWO_BODY:
+            D[r, 0] = k[r] * (b / T + g / T ** 2)
+            D[r, 1] = a * (T / 300.0) ** b * np.exp(-g / T)
+        elif t == COSMIC_RAY:
+            D[r, 3] = a
+        elif t == PHOTO:
+            D[r, 2] = -g * k[r]
+            D[r, 4] = a * np.exp(-g * A_V)
+        elif t == CR_PHOTON:
+            D[r, 0] = k[r] * b / T
+            D[r, 3] = a * (T / 300.0) ** b * g / (1.0 - net.albedo)
+        else:
+            raise ValueError(f"unknown reaction type {t}")
+    return D
+
+
+def phys_gradient_from_rate_gradient(net, cell: dict, g_k) -> np.ndarray:
+    """dL/dphi (5) of one cell from its dL/dk (R): sum_r dL/dk_r dk_r/dphi."""
+    return rate_parameter_derivatives(net, **cell).T @ np.asarray(g_k, dtype=float)
+
+
 def phys_gradient(net, cell: dict, g_log_alpha) -> np.ndarray:
     """dL/dphi (5) of one cell from its dL/dlog alpha (R).  The parameters enter
     the rate equations only through the coefficients k_r = alpha_r h_r(phi), so
@@ -108,18 +148,22 @@ def reaction_rates(net, k, x) -> np.ndarray:
 
 
 def rate_derivative(net, k, x) -> sp.csr_matrix:
-    """d rate_r / d x_j (R x S) for rates of mass-action form."""
-    rows, cols, vals = [], [], []
-    for r in range(net.n_reactions):
-        a, b = net.reactants[r]
-        if b < 0:
-            rows.append(r); cols.append(a); vals.append(k[r])
-        elif a == b:
-            rows.append(r); cols.append(a); vals.append(2.0 * k[r] * x[a])
-        else:
-            rows.append(r); cols.append(a); vals.append(k[r] * x[b])
-            rows.append(r); cols.append(b); vals.append(k[r] * x[a])
-    return sp.csr_matrix((vals, (rows, cols)), shape=(net.n_reactions, net.n_species))
+    """d rate_r / d x_j (R x S) for rates of mass-action form: k_r for one
+    reactant, 2 k_r x_a for A + A, and k_r x_b (at column a), k_r x_a (at column
+    b) for A + B.  The entries are built with whole-array operations; their
+    values and order are those of a loop over reactions."""
+    R = net.n_reactions
+    a, b = net.reactants[:, 0], net.reactants[:, 1]
+    one, same, pair = b < 0, (b >= 0) & (a == b), (b >= 0) & (a != b)
+    rr = np.arange(R)
+    # per reaction up to two entries: (r, a, v_a) and, for A + B, (r, b, v_b)
+    va = np.where(one, k, np.where(same, 2.0 * k * x[np.where(same, a, 0)], k * x[np.where(pair, b, 0)]))
+    vb = k * x[np.where(pair, a, 0)]
+    rows = np.concatenate([rr, rr[pair]])
+    cols = np.concatenate([a, b[pair]])
+    vals = np.concatenate([va, vb[pair]])
+    order = np.argsort(np.concatenate([2 * rr, 2 * rr[pair] + 1]), kind="stable")
+    return sp.csr_matrix((vals[order], (rows[order], cols[order])), shape=(R, net.n_species))
 
 
 class Chemistry:
@@ -127,7 +171,10 @@ class Chemistry:
 
     def __init__(self, net, k):
         self.net = net
-        self.k = np.asarray(k, dtype=float)
+        # real coefficients in FP64 (or extended precision when given as
+        # np.longdouble); complex ones are kept for complex-step derivatives
+        k = np.asarray(k)
+        self.k = k.astype(np.result_type(k.dtype, np.float64))
         self.nu = stoichiometry(net)
 
     def f(self, x) -> np.ndarray:

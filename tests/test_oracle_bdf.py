@@ -230,3 +230,107 @@ def test_recorded_history_holds_the_accepted_states():
     for h, q, t_rec, _x in res.history[:-1]:
         t += h
         assert t_rec == pytest.approx(t, rel=1e-12)
+
+
+def _hnw_linear(y0, lam, sc, t_span):
+    """The starting step of Hairer, Norsett & Wanner (Solving ODEs I, Sec. II.4,
+    order p = 1) for y' = lam y, written with the exact derivatives of the linear
+    problem: y' = lam y0, y'' = lam^2 y0 (the algorithm estimates the latter by a
+    difference quotient over one explicit Euler step, which is exact here up to
+    rounding)."""
+    rms = lambda v: np.sqrt(np.mean((v / sc) ** 2))
+    d0, d1, d2 = rms(y0), rms(lam * y0), rms(lam ** 2 * y0)
+    h0 = 1e-6 if (d0 < 1e-5 or d1 < 1e-5) else 0.01 * d0 / d1
+    h0 = min(h0, t_span)
+    h1 = max(1e-6, 1e-3 * h0) if max(d1, d2) <= 1e-15 else (0.01 / max(d1, d2)) ** 0.5
+    return min(100.0 * h0, h1, t_span), d0, d1, d2, h0
+
+
+@pytest.mark.parametrize("case", ["curvature", "cap_100_h0", "t_span", "tiny_state", "no_motion"])
+def test_initial_step_on_linear_problem(case):
+    # each case makes a different term of the starting-step rule decide
+    y0 = np.array([1.0, 2.0, 3.0])
+    rtol, atol, t_span = 1e-3, 0.0, 1e9
+    lam = np.array([-1e3, -2e3, -3e3])
+    if case == "cap_100_h0":        # weights dominated by atol: d0 = 1e-3, |lam| = 5
+        y0, atol, rtol, lam = np.full(3, 1e-9), 1e-6, 1e-12, np.full(3, -5.0)
+    elif case == "t_span":
+        t_span = 1e-7
+    elif case == "tiny_state":      # d0 < 1e-5: h0 = 1e-6
+        y0, atol = np.full(3, 1e-12), 1e-6
+    elif case == "no_motion":       # f = 0
+        lam = np.zeros(3)
+    sc = atol + rtol * np.abs(y0)
+    f = lambda y: lam * y
+    h = bdf.initial_step(f, y0, f(y0), t_span, rtol, atol)
+    want, d0, d1, d2, h0 = _hnw_linear(y0, lam, sc, t_span)
+    assert h == pytest.approx(want, rel=1e-12)
+    if case == "curvature":
+        # the defining condition of the order-1 rule: h^2 max(d1, d2) = 0.01
+        assert d2 > d1 and h < 100 * h0
+        assert h * h * max(d1, d2) == pytest.approx(0.01, rel=1e-12)
+    elif case == "cap_100_h0":
+        assert h == pytest.approx(100.0 * 0.01 * d0 / d1, rel=1e-12)
+        assert h * h * max(d1, d2) < 0.01
+    elif case == "t_span":
+        assert h == t_span
+    elif case == "tiny_state":
+        assert d0 < 1e-5 and h0 == 1e-6
+    else:
+        assert h == 1e-6
+
+
+def test_oracle_conservation_drift_on_connected_networks():
+    # W f = 0 and W (I - c J) = W, so W x is conserved in exact arithmetic; the
+    # oracle's FP64 LAPACK solves at the condition numbers of the connected
+    # 200-species network (up to ~1e7) let it drift.  This measures that drift
+    # on the cells behind the conservation bars of the GPU tests: cell 2840 of
+    # the seeded 4096-cell batch (the largest drift found in that batch) and the
+    # cells of the small-batch parity test.  The GPU bars are set above the
+    # oracle's own: 1e-12 sum_i |W_ei x_i| + 1e-8 |x|_1 for the small batches,
+    # 1e-7 |x|_1 over the 4096-cell batch.
+    from threadpoolctl import threadpool_limits
+    net = synth.network_for_config("net200")
+    W = net.conservation_matrix().astype(float)
+
+    def drift(cells, c):
+        with threadpool_limits(1):
+            r = bdf.solve(chem.cell_chemistry(net, cells.cell(c)), cells.x0[c], cells.t_end[c], 1e-6, 1e-20)
+        assert r.status == bdf.OK
+        return float(np.max(np.abs(W @ r.x - W @ cells.x0[c]))) / np.abs(r.x).sum(), r.x
+
+    big = synth.sample_cells(net, 4096, seed=2001, t_end_yr=1e6)
+    d2840, x = drift(big, 2840)
+    # far above 1e-12 of the conserved totals, and within the GPU's batch bar
+    assert 1e-9 < d2840 < 1e-7 / 4
+    assert np.max(np.abs(W @ x - W @ big.x0[2840]) / (np.abs(W) @ np.abs(x))) > 1e-9
+    small = synth.sample_cells(net, 6, seed=2001)
+    for c in range(small.n):
+        d, x = drift(small, c)
+        assert d <= 1e-8, (c, d)
+
+
+def test_finite_time_blow_up_ends_with_step_too_small():
+    # A + B -> C from x_A = x_B = a0 < 0 (abundances are never clipped): x_A' =
+    # -k' x_A^2 has x_A(t) = a0 / (1 + k' a0 t), which blows up at t* = 1 / (k' |a0|).
+    # The step control shrinks h towards t* until h < 10 u t: STEP_TOO_SMALL,
+    # with the blow-up time the solution implies, t + 1 / (k' |x_A|), at t*
+    net = tiny_nets.association(1e-9)
+    ch = chem.cell_chemistry(net, dict(T=300.0, n_H=1e4, A_V=0.0, zeta=1e-17, G0=1.0))
+    kp, a0 = ch.k[0], -1e-4
+    t_star = 1.0 / (kp * abs(a0))
+    r = bdf.solve(ch, np.array([a0, a0, 0.0]), 2 * t_star, 1e-6, 1e-20)
+    assert r.status == bdf.STEP_TOO_SMALL
+    assert r.stats.h < 10 * bdf.U_ROUND * r.t
+    assert abs(r.t - t_star) <= 1e-4 * t_star and r.t < t_star
+    assert abs(r.t + 1.0 / (kp * abs(r.x[0])) - t_star) <= 1e-4 * t_star
+    assert r.x[0] == r.x[1] and abs(r.x[2] + r.x[0] - a0) <= 1e-12 * abs(r.x[0])
+
+
+def test_rates_overflowing_at_the_initial_state_end_as_nonfinite():
+    net = tiny_nets.association(1e-9)
+    ch = chem.cell_chemistry(net, dict(T=300.0, n_H=1e4, A_V=0.0, zeta=1e-17, G0=1.0))
+    x0 = np.array([1e200, 1e200, 0.0])
+    with np.errstate(over="ignore", invalid="ignore"):
+        r = bdf.solve(ch, x0, 1e10, 1e-6, 1e-20)
+    assert r.status == bdf.NONFINITE and r.t == 0.0 and np.array_equal(r.x, x0)

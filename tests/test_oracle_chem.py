@@ -196,3 +196,34 @@ def test_cosmic_ray_photon_rates():
         scale = max(np.abs(D[:, j]).max(), 1e-300)
         assert np.all(np.abs(fd - D[:, j]) <= 1e-7 * scale + 1e-12 * np.abs(fd)), name
     assert np.all(D[crp][:, [1, 2, 4]] == 0)
+
+
+@pytest.mark.parametrize("where", ["generic", "zeta0", "G00"])
+def test_rate_parameter_derivatives_match_central_differences(where):
+    # dk/dphi of every law against central differences of k itself, including
+    # cells where zeta = 0 or G0 = 0 switch a family of reactions off (k is
+    # linear in zeta and in G0, so there the difference quotient is exact up to
+    # rounding); where k != 0 it equals k d log k / dphi
+    from tests import tiny_nets
+    net = tiny_nets.four_types(albedo=0.3)
+    cell = dict(CELL, zeta=0.0) if where == "zeta0" else dict(CELL, G0=0.0) if where == "G00" else dict(CELL)
+    D = chem.rate_parameter_derivatives(net, **cell)
+    for j, name in enumerate(chem.PHYS_PARAMS):
+        step = 1e-5 * (abs(cell[name]) if cell[name] != 0 else 1.0)
+        up, dn = dict(cell), dict(cell)
+        up[name] += step
+        dn[name] -= step
+        fd = (chem.rate_coefficients(net, **up) - chem.rate_coefficients(net, **dn)) / (2 * step)
+        scale = max(np.abs(D[:, j]).max(), 1e-300)
+        assert np.all(np.abs(fd - D[:, j]) <= 1e-7 * scale + 1e-12 * np.abs(fd)), name
+    k = chem.rate_coefficients(net, **cell)
+    on = k != 0
+    L = chem.log_rate_derivatives(net, **cell) if where == "generic" else None
+    if L is not None:
+        np.testing.assert_allclose(D[on], k[on, None] * L[on], rtol=1e-14, atol=0)
+    if where == "zeta0":
+        cr = np.isin(net.rtype, [synth.COSMIC_RAY, synth.CR_PHOTON])
+        assert np.all(k[cr] == 0) and np.all(D[cr, 3] > 0)
+    if where == "G00":
+        ph = net.rtype == synth.PHOTO
+        assert np.all(k[ph] == 0) and np.all(D[ph, 4] > 0)
