@@ -3,7 +3,10 @@
 One step = one full solve of a batch of cells of the 500-species /
 6000-reaction network from t = 0 to t_end (rates, starting step, every BDF
 step attempt with its Newton-matrix factorisations, Newton iterations and
-step control), inputs resident in HBM.  Prints one JSON line.
+step control), inputs resident in HBM.  After the timed steps the default run
+also serves a Poisson request stream on the same network in both precision
+forms (throughput with p50/p99 latency) and times the right-hand-side kernel
+on its own.  Prints one JSON line.
 
     python bench.py [--steps K] [--warmup W] [--cells C] [--precision fp64|fp32_lu]
 """
@@ -36,11 +39,22 @@ def _oracle_cell(args):
     return i, r.status, r.x
 
 
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(net_name, cells, n_sample):
     """The oracle, untuned, one cell per single-threaded process on the host
-    cores.  Called before anything touches the GPU, so the worker processes are
-    forked from a process without GPU state.  Returns the baseline record and
-    the oracle's abundances of the sampled cells."""
+    cores (at most 16 processes).  Called before anything touches the GPU, so
+    the worker processes are forked from a process without GPU state.  Returns
+    the baseline record and the oracle's abundances of the sampled cells."""
     procs = max(1, min(os.cpu_count() or 1, 16, n_sample))
     import synth  # noqa: F401  (warm the network cache before forking)
     synth.network_for_config(net_name)
@@ -56,8 +70,9 @@ def cpu_baseline(net_name, cells, n_sample):
     wall = time.perf_counter() - t0
     ok = sum(1 for s, _ in res if s == 0)
     rec = {"value": ok / wall, "unit": "cell-solves/s", "cores": procs, "kind": "oracle",
-           "sample": f"first {n_sample} cells of the timed batch, one single-threaded process per cell, "
-                     f"wall {wall:.1f} s"}
+           "cpu_model": cpu_model(), "host_cpus": os.cpu_count(),
+           "sample": f"first {n_sample} cells of the timed batch, {procs} single-threaded processes "
+                     f"(one cell per task), wall {wall:.1f} s"}
     return rec, np.array([x for _, x in res])
 
 
@@ -89,17 +104,15 @@ def recorded_traffic():
     return rec if rec.get("source_hash") == profile_summary.source_hash() else None
 
 
-def run_serve(args):
-    """Serving workload: Poisson arrivals of requests of 1..1024 cells with
-    horizons log-uniform in 1e3..1e7 yr on one server.  A closed-loop pass
-    (every request queued at once) gives the saturated throughput; the
-    open-loop pass offers 0.8 of it (unless --rate is given) and yields the
-    latency percentiles."""
+def serve_stream(args, net, g, n_requests, precisions):
+    """Poisson arrivals of requests of 1..1024 cells with horizons log-uniform
+    in 1e3..1e7 yr on one server per precision form.  A closed-loop pass (every
+    request queued at once) gives the saturated throughput; the open-loop pass
+    offers 0.8 of it (unless --rate is given) and yields the latency
+    percentiles.  Returns the record of every pass."""
     import paper_2511_10558_amd as ab
     import synth
-    net = synth.network_for_config(args.network)
-    g = ab.Network.from_text(net.to_text())
-    reqs = synth.request_stream(net, args.requests, seed=args.seed, rate_per_s=1.0)
+    reqs = synth.request_stream(net, n_requests, seed=args.seed, rate_per_s=1.0)
     warm = synth.request_stream(net, 16, seed=args.seed + 1, rate_per_s=1.0)
     unit_arrivals = np.array([r.arrival_s for r in reqs])
     n_cells = sum(r.cells.n for r in reqs)
@@ -108,7 +121,7 @@ def run_serve(args):
     def submit(srv, cells):
         return srv.submit(cells.T, cells.n_H, cells.A_V, cells.zeta, cells.G0, cells.x0, cells.t_end)
 
-    def one_pass(precision, arrivals):
+    def one_pass(precision, arrivals, label):
         with ab.Server(g, precision=precision, check_every=args.check_every, lu_reuse=args.lu_reuse) as srv:
             wid = [submit(srv, r.cells) for r in warm]
             got = 0
@@ -120,9 +133,9 @@ def run_serve(args):
             last_note = 0.0
             while len(done) < len(reqs):
                 now = srv.clock() - t0
-                if now - last_note > 20.0:
+                if now - last_note > 15.0:
                     last_note = now
-                    print(f"[serve] {precision}: {now:.0f} s, {i} submitted, {len(done)} complete",
+                    print(f"[serve] {precision} {label}: {now:.0f} s, {i} submitted, {len(done)} complete",
                           file=sys.stderr, flush=True)
                 while i < len(reqs) and arrivals[i] <= now:
                     ids[submit(srv, reqs[i].cells)] = i
@@ -141,35 +154,78 @@ def run_serve(args):
                 "mean_latency_s": round(float(lat.mean()), 4), "failed_cells": int(failed),
                 "slots": int(info1["slots"]), "mean_occupied_slots": round(busy / t_end, 1)}
 
-    out = {"metric": "served cell-solves/sec (Poisson request stream, 500-sp net) with p50/p99 latency",
-           "unit": "cell-solves/s", "n_gpus": 1, "higher_is_better": True, "data": "synthetic",
-           "config": {"workload": f"{args.network} serving: {len(reqs)} requests after 16 warm-up requests, "
-                                  f"{n_cells} cells (1..1024 per request, mean {mean_cells:.1f}), t_end log-uniform "
-                                  "1e3..1e7 yr, rtol 1e-6 atol 1e-20"
-                                  + (f", factorisation kept while |c/c_lu - 1| <= {args.lu_reuse:g}"
-                                     if args.lu_reuse else ""),
-                      "requests": len(reqs), "cells": n_cells, "seed": args.seed, "lu_reuse": args.lu_reuse},
-           "passes": {}}
-    for prec in args.serve_precisions.split(","):
-        res = {}
-        if args.rate > 0:
-            rate = args.rate
-        else:
-            closed = one_pass(prec, np.zeros(len(reqs)))
-            res["closed_loop"] = closed
-            rate = 0.8 * closed["cell_solves_per_s"] / mean_cells
-        res["open_loop"] = one_pass(prec, unit_arrivals / rate)
-        res["arrival_rate_req_per_s"] = round(rate, 4)
-        out["passes"][prec] = res
+    out = {"workload": f"{args.network} serving: {len(reqs)} Poisson requests after 16 warm-up requests, "
+                       f"{n_cells} cells (1..1024 per request, mean {mean_cells:.1f}), t_end log-uniform "
+                       "1e3..1e7 yr, rtol 1e-6 atol 1e-20"
+                       + (f", factorisation kept while |c/c_lu - 1| <= {args.lu_reuse:g}" if args.lu_reuse else ""),
+           "requests": len(reqs), "cells": n_cells, "seed": args.seed, "lu_reuse": args.lu_reuse, "passes": {}}
+    # closed loops first; then every form is offered the same open-loop stream,
+    # at 0.8 of the first form's saturated throughput, so that their latencies
+    # compare at equal load
+    rate = args.rate
+    for prec in precisions:
+        out["passes"][prec] = {}
+        if args.rate <= 0:
+            closed = one_pass(prec, np.zeros(len(reqs)), "closed loop")
+            out["passes"][prec]["closed_loop"] = closed
+            if rate <= 0:
+                rate = 0.8 * closed["cell_solves_per_s"] / mean_cells
+    out["arrival_rate_req_per_s"] = round(rate, 4)
+    for prec in precisions:
+        res = out["passes"][prec]
+        res["open_loop"] = one_pass(prec, unit_arrivals / rate, "open loop")
         print(f"[serve] {prec}: {json.dumps(res)}", file=sys.stderr, flush=True)
-    first = out["passes"][args.serve_precisions.split(",")[0]]["open_loop"]
-    out["value"] = first["cell_solves_per_s"]
-    out["p50_latency_s"], out["p99_latency_s"] = first["p50_latency_s"], first["p99_latency_s"]
     if "fp64" in out["passes"] and "fp32_lu" in out["passes"]:
         a, b = out["passes"]["fp64"], out["passes"]["fp32_lu"]
-        key = "closed_loop" if "closed_loop" in a else "open_loop"
-        out["fp32_lu_speedup_saturated"] = round(b[key]["cell_solves_per_s"] / a[key]["cell_solves_per_s"], 4)
+        if "closed_loop" in a:
+            out["fp32_lu_speedup_saturated"] = round(b["closed_loop"]["cell_solves_per_s"] /
+                                                     a["closed_loop"]["cell_solves_per_s"], 4)
+        out["fp32_lu_p50_ratio_same_load"] = round(b["open_loop"]["p50_latency_s"] / a["open_loop"]["p50_latency_s"], 4)
+        out["fp32_lu_p99_ratio_same_load"] = round(b["open_loop"]["p99_latency_s"] / a["open_loop"]["p99_latency_s"], 4)
+    return out
+
+
+def run_serve(args):
+    """Serving workload on its own (--workload serve)."""
+    import paper_2511_10558_amd as ab
+    import synth
+    net = synth.network_for_config(args.network)
+    g = ab.Network.from_text(net.to_text())
+    rec = serve_stream(args, net, g, args.requests, args.serve_precisions.split(","))
+    first = rec["passes"][args.serve_precisions.split(",")[0]]["open_loop"]
+    out = {"metric": "served cell-solves/sec (Poisson request stream, 500-sp net) with p50/p99 latency",
+           "value": first["cell_solves_per_s"], "unit": "cell-solves/s", "n_gpus": 1, "higher_is_better": True,
+           "data": "synthetic", "p50_latency_s": first["p50_latency_s"], "p99_latency_s": first["p99_latency_s"],
+           "config": {"workload": rec.pop("workload"), "requests": rec["requests"], "cells": rec["cells"],
+                      "seed": rec["seed"], "lu_reuse": rec["lu_reuse"]},
+           **{k: v for k, v in rec.items() if k not in ("requests", "cells", "seed", "lu_reuse")}}
     print(json.dumps(out))
+
+
+def rhs_standalone(net, g, inp, n_rep=20):
+    """The right-hand-side kernel on its own (abdf_rhs over the batch's cells,
+    rates from abdf_rates, abundances x0): algorithmic bytes (x and k read, f
+    written) per average launch, timed with HIP events on the launch stream."""
+    import torch
+    import paper_2511_10558_amd as ab
+    k = ab.rates(g, *inp[:5])
+    x = inp[5]
+    C = x.shape[0]
+    ab.rhs(g, k, x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(n_rep):
+        ab.rhs(g, k, x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / n_rep
+    byt = C * (2 * net.n_species + net.n_reactions) * 8
+    ach = byt / (ms * 1e-3) / 1e9
+    return {"kernel": "k_rhs_only (abdf_rhs, standalone)", "bound": "hbm", "achieved": round(ach, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+            "cells": C, "avg_launch_ms": round(ms, 4),
+            "work": f"(2 S + R) x 8 B = {(2 * net.n_species + net.n_reactions) * 8} B per cell-evaluation"}
 
 
 def run_adjoint(args):
@@ -200,8 +256,7 @@ def run_adjoint(args):
     print(f"[bench] recorded forward: {t1 - t0:.1f} s", file=sys.stderr, flush=True)
     dLdx = torch.zeros_like(x)
     dLdx[:, targets] = 1.0 / x[:, targets]
-    gsum, gcell, _ = tape.adjoint(dLdx, per_cell=True)
-    gphi = ab.phys_gradient(g, *inp[:5], gcell)      # dL/d(T, n_H, A_V, zeta, G0) per cell
+    gsum, gcell, _, gphi = tape.adjoint(dLdx, per_cell=True, phys_grad=True)   # gphi: dL/d(T, n_H, A_V, zeta, G0)
     torch.cuda.synchronize()
     t2 = time.perf_counter()
     ab.profile_enable(False)
@@ -229,7 +284,7 @@ def run_adjoint(args):
         xs, _ = ab.solve(g, *sub)
         d = torch.zeros_like(xs)
         d[:, gt] = 1.0 / xs[:, gt]
-        _, _, _, gc, _ = ab.solve_adjoint(g, *sub, d, per_cell=True)
+        _, _, _, gc, _, gpc = ab.solve_adjoint(g, *sub, d, per_cell=True, phys_grad=True)
         gc = gc.cpu().numpy()
 
         def err(gv, ref, top):
@@ -255,7 +310,7 @@ def run_adjoint(args):
         pg = json.load(open(phys_path)) if os.path.exists(phys_path) else None
         if pg is not None and pg["targets"] == gold["targets"]:
             m = len(pg["cells"])
-            gp = ab.phys_gradient(g, *[v[:m] for v in sub[:5]], torch.as_tensor(gc[:m], device=dev)).cpu().numpy()
+            gp = gpc[:m].cpu().numpy()
             e_ps, e_pf, e_po = [], [], []
             for c, r in enumerate(pg["cells"]):
                 # phi_j dL/dphi_j (dL/dA_V for the extinction): one dimensionless scale
@@ -361,6 +416,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--workload", default="batch", choices=["batch", "serve", "adjoint", "single", "ceilings"])
     ap.add_argument("--requests", type=int, default=256, help="serve: requests after the warm-up")
+    ap.add_argument("--batch-serve-requests", type=int, default=96,
+                    help="requests of the serving pass that follows the batch steps (0: none)")
     ap.add_argument("--rate", type=float, default=0.0, help="serve: arrival rate [requests/s]; 0 = 0.8 x saturation")
     ap.add_argument("--serve-precisions", default="fp64,fp32_lu")
     ap.add_argument("--check-every", type=int, default=4)
@@ -373,7 +430,7 @@ def main():
     ap.add_argument("--t-end-yr", type=float, default=1e6)
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32_lu"])
     ap.add_argument("--seed", type=int, default=3001)
-    ap.add_argument("--cpu-sample", type=int, default=16)
+    ap.add_argument("--cpu-sample", type=int, default=64)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--lu-reuse", type=float, default=0.3,
                     help="keep a factorisation while |c/c_lu - 1| <= this (0: refactor whenever c changes)")
@@ -496,7 +553,8 @@ def main():
     # the Newton kernels come from the rocprofv3 summary, not from these spans.
 
     out = {
-        "metric": f"cell-solves/sec to t_end at rtol 1e-6, {S}-sp net",
+        "metric": ("cell-solves/sec to t_end at rtol 1e-6, 500-sp net; p50/p99 latency; FP32-LU vs FP64"
+                   if args.network == "net500" else f"cell-solves/sec to t_end at rtol 1e-6, {S}-sp net"),
         "value": round(value, 3),
         "unit": "cell-solves/s",
         "n_gpus": 1,
@@ -549,6 +607,19 @@ def main():
                                  "cells_ok": okr, "ratio_to_value": round((okr / wr) / value, 4),
                                  "factorisations": int(sr["n_lu"].sum()),
                                  "max_rel_dev_from_headline_gpu": max_rel_err(xr.cpu().numpy(), x64)}
+    out["roofline_rhs"] = rhs_standalone(net, g, inp)
+    progress(f"standalone right-hand side: {out['roofline_rhs']['achieved']} GB/s")
+    if args.batch_serve_requests > 0 and args.network == "net500":
+        # the serving half of the metric: p50/p99 latency, FP32-LU against FP64
+        rec = serve_stream(args, net, g, args.batch_serve_requests, ["fp64", "fp32_lu"])
+        p64, p32 = rec["passes"]["fp64"]["open_loop"], rec["passes"]["fp32_lu"]["open_loop"]
+        out["p50_latency_s"], out["p99_latency_s"] = p64["p50_latency_s"], p64["p99_latency_s"]
+        out["serving"] = rec
+        out["serving"]["summary"] = {
+            "fp64": {"served_cell_solves_per_s": p64["cell_solves_per_s"], "p50_s": p64["p50_latency_s"],
+                     "p99_s": p64["p99_latency_s"]},
+            "fp32_lu": {"served_cell_solves_per_s": p32["cell_solves_per_s"], "p50_s": p32["p50_latency_s"],
+                        "p99_s": p32["p99_latency_s"]}}
     if cpu_rec is not None:
         n = len(xo)
         out["cpu_baseline"] = cpu_rec

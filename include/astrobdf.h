@@ -293,15 +293,21 @@ abdf_status abdf_solve_record(const abdf_network *net, int64_t n_cells,
                               abdf_tape **tape, void *stream);
 
 /* Reverse sweep of a tape for dL_dx = dL/dx(t_end) (DEVICE [n_cells][S]).
+ * The sweep accumulates dL/dk_r, the gradient with respect to each cell's rate
+ * coefficients; since k_r is linear in alpha_r, dL/dlog alpha_r = k_r dL/dk_r.
  * Outputs (DEVICE, each may be NULL):
  *   dL_dlog_alpha      [R]          summed over cells, in cell order
  *   dL_dlog_alpha_cell [n_cells][R] per cell
  *   dL_dx0             [n_cells][S]
+ *   dL_dphi            [n_cells][5] per cell, columns T, n_H, A_V, zeta, G0:
+ *                      sum_r dL/dk_r dk_r/dphi with the derivatives of the
+ *                      rate laws written out (no division by zeta or G0, so
+ *                      the columns are exact where zeta = 0 or G0 = 0)
  * Cells whose forward status was not ABDF_CELL_OK contribute zeros.  A tape
  * may be swept any number of times.  Errors: ABDF_E_ARG, ABDF_E_NOMEM,
  * ABDF_E_DEVICE. */
 abdf_status abdf_tape_adjoint(abdf_tape *tape, const double *dL_dx, double *dL_dlog_alpha,
-                              double *dL_dlog_alpha_cell, double *dL_dx0, void *stream);
+                              double *dL_dlog_alpha_cell, double *dL_dx0, double *dL_dphi, void *stream);
 
 /* Device bytes held by the tape's checkpoint (inputs, alpha, steps). */
 int64_t abdf_tape_bytes(const abdf_tape *tape);
@@ -315,7 +321,7 @@ abdf_status abdf_solve_adjoint(const abdf_network *net, int64_t n_cells,
                                const abdf_options *opt, const double *dL_dx,
                                double *x_out, int32_t *cell_status,
                                double *dL_dlog_alpha, double *dL_dlog_alpha_cell, double *dL_dx0,
-                               abdf_cell_stats *stats, void *stream);
+                               double *dL_dphi, abdf_cell_stats *stats, void *stream);
 
 /* Gradients with respect to each cell's physical parameters, from the per-cell
  * gradients with respect to log alpha (dL_dlog_alpha_cell of
@@ -330,6 +336,10 @@ abdf_status abdf_solve_adjoint(const abdf_network *net, int64_t n_cells,
  * solve's inputs.  dL_dphi: DEVICE [n_cells][5], columns T, n_H, A_V, zeta,
  * G0; the sums over reactions run in reaction order per thread, then in a
  * fixed tree, so results are deterministic.  Asynchronous on the stream.
+ * A cell with zeta = 0 (G0 = 0) has k_r = 0 for its cosmic-ray (photo)
+ * reactions, so dL/dlog alpha_r carries nothing of their zeta (G0) derivative:
+ * that column is then not finite.  The dL_dphi output of abdf_tape_adjoint,
+ * formed from dL/dk, is exact there.
  * Errors: ABDF_E_ARG (null or non-device pointers, n_cells out of range),
  * ABDF_E_DEVICE. */
 abdf_status abdf_phys_gradient(const abdf_network *net, int64_t n_cells,

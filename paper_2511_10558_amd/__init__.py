@@ -197,17 +197,19 @@ class Tape:
     def nbytes(self) -> int:
         return int(_lib.lib().abdf_tape_bytes(self._h))
 
-    def adjoint(self, dL_dx, per_cell=False, x0_grad=False):
-        """(dL/dlog alpha [R], dL/dlog alpha per cell [C, R] or None, dL/dx0 [C, S] or None)."""
+    def adjoint(self, dL_dx, per_cell=False, x0_grad=False, phys_grad=False):
+        """(dL/dlog alpha [R], dL/dlog alpha per cell [C, R] or None, dL/dx0 [C, S] or None,
+        dL/d(T, n_H, A_V, zeta, G0) per cell [C, 5] or None)."""
         torch = _torch()
         C, S, R = self.n_cells, self._net.n_species, self._net.n_reactions
         g = torch.empty((R,), dtype=torch.float64, device=self._dev)
         gc = torch.empty((C, R), dtype=torch.float64, device=self._dev) if per_cell else None
         dx0 = torch.empty((C, S), dtype=torch.float64, device=self._dev) if x0_grad else None
+        dphi = torch.empty((C, 5), dtype=torch.float64, device=self._dev) if phys_grad else None
         p = lambda t: ctypes.c_void_p(t.data_ptr() if t is not None else None)
         _check(_lib.lib().abdf_tape_adjoint(self._h, _ptr(dL_dx.contiguous(), torch.float64, (C, S), "dL_dx"),
-                                            p(g), p(gc), p(dx0), _stream()))
-        return g, gc, dx0
+                                            p(g), p(gc), p(dx0), p(dphi), _stream()))
+        return g, gc, dx0, dphi
 
     def free(self):
         h = getattr(self, "_h", None)
@@ -245,8 +247,9 @@ def solve_record(net: Network, T, n_H, A_V, zeta, G0, x0, t_end, *, alpha=None, 
 
 
 def solve_adjoint(net: Network, T, n_H, A_V, zeta, G0, x0, t_end, dL_dx, *, alpha=None,
-                  options: Options | None = None, per_cell=False, x0_grad=False, **opts):
-    """One call: (x_out, status, dL/dlog alpha [R], per cell [C, R] or None, dL/dx0 or None)."""
+                  options: Options | None = None, per_cell=False, x0_grad=False, phys_grad=False, **opts):
+    """One call: (x_out, status, dL/dlog alpha [R], per cell [C, R] or None, dL/dx0 or None,
+    dL/d(T, n_H, A_V, zeta, G0) per cell [C, 5] or None)."""
     torch = _torch()
     C, args = _cell_args(net, T, n_H, A_V, zeta, G0, x0, t_end)
     S, R = net.n_species, net.n_reactions
@@ -257,12 +260,13 @@ def solve_adjoint(net: Network, T, n_H, A_V, zeta, G0, x0, t_end, dL_dx, *, alph
     g = torch.empty((R,), dtype=torch.float64, device=x0.device)
     gc = torch.empty((C, R), dtype=torch.float64, device=x0.device) if per_cell else None
     dx0 = torch.empty((C, S), dtype=torch.float64, device=x0.device) if x0_grad else None
+    dphi = torch.empty((C, 5), dtype=torch.float64, device=x0.device) if phys_grad else None
     p = lambda t: ctypes.c_void_p(t.data_ptr() if t is not None else None)
     _check(_lib.lib().abdf_solve_adjoint(net.handle, C, *args, a, ctypes.byref(o),
                                          _ptr(dL_dx.contiguous(), torch.float64, (C, S), "dL_dx"),
-                                         p(x_out), p(status), p(g), p(gc), p(dx0), ctypes.c_void_p(None),
+                                         p(x_out), p(status), p(g), p(gc), p(dx0), p(dphi), ctypes.c_void_p(None),
                                          _stream()))
-    return x_out, status, g, gc, dx0
+    return x_out, status, g, gc, dx0, dphi
 
 
 PHYS_PARAMS = ("T", "n_H", "A_V", "zeta", "G0")
@@ -270,7 +274,9 @@ PHYS_PARAMS = ("T", "n_H", "A_V", "zeta", "G0")
 
 def phys_gradient(net: Network, T, n_H, A_V, zeta, G0, dL_dlog_alpha_cell):
     """dL/dphi [C, 5] (columns T, n_H, A_V, zeta, G0) from the per-cell
-    gradients with respect to log alpha [C, R] (abdf_phys_gradient)."""
+    gradients with respect to log alpha [C, R] (abdf_phys_gradient).  Where a
+    cell has zeta = 0 or G0 = 0 that column is not recoverable from log-alpha
+    gradients; Tape.adjoint(..., phys_grad=True) is exact there."""
     torch = _torch()
     C = T.shape[0]
     args = [_ptr(v, torch.float64, (C,), nm) for v, nm in
@@ -287,8 +293,8 @@ def _autograd_function():
     class SolveFunction(torch.autograd.Function):
         """x(t_end) as a differentiable function of log alpha [R], x0 [C, S] and
         the cells' physical parameters T, n_H, A_V, zeta, G0 [C]; the backward
-        pass is the discrete adjoint of the recorded solve (parameters through
-        abdf_phys_gradient)."""
+        pass is the discrete adjoint of the recorded solve.  Cells that did not
+        reach t_end (status other than ok) have no gradient: backward raises."""
 
         @staticmethod
         def forward(ctx, log_alpha, x0, net, T, n_H, A_V, zeta, G0, t_end, options, max_tape_steps):
@@ -297,16 +303,22 @@ def _autograd_function():
             x, status, tape = solve_record(net, *phys, x0.detach().contiguous(), t_end,
                                            alpha=alpha, options=options, max_tape_steps=max_tape_steps)
             ctx.tape, ctx.net, ctx.phys = tape, net, phys
+            ctx.failed = status.ne(0)
             ctx.mark_non_differentiable(status)
             return x, status
 
         @staticmethod
         def backward(ctx, gx, _gstatus):
+            n_failed = int(ctx.failed.sum().item())
+            if n_failed:
+                first = int(torch.nonzero(ctx.failed)[0, 0].item())
+                raise AbdfError(1, f"{n_failed} cell(s) did not reach t_end (first: cell {first}); the adjoint "
+                                   "differentiates completed solves only (a larger max_tape_steps avoids tape_full)")
             need_phys = any(ctx.needs_input_grad[3:8])
-            g, gc, dx0 = ctx.tape.adjoint(gx.contiguous(), per_cell=need_phys, x0_grad=ctx.needs_input_grad[1])
+            g, _, dx0, gphi = ctx.tape.adjoint(gx.contiguous(), x0_grad=ctx.needs_input_grad[1],
+                                               phys_grad=need_phys)
             gp = [None] * 5
             if need_phys:
-                gphi = phys_gradient(ctx.net, *ctx.phys, gc)
                 gp = [gphi[:, j].clone() if ctx.needs_input_grad[3 + j] else None for j in range(5)]
             return (g, dx0, None, *gp, None, None, None)
 

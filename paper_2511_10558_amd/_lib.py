@@ -101,11 +101,11 @@ SIGNATURES = {
     "abdf_solve_record": (ctypes.c_int, [c_void_p, ctypes.c_int64] + [c_void_p] * 8 +
                           [ctypes.POINTER(Options), ctypes.c_int32, c_void_p, c_void_p, c_void_p,
                            ctypes.POINTER(c_void_p), c_void_p]),
-    "abdf_tape_adjoint": (ctypes.c_int, [c_void_p] * 6),
+    "abdf_tape_adjoint": (ctypes.c_int, [c_void_p] * 7),
     "abdf_tape_bytes": (ctypes.c_int64, [c_void_p]),
     "abdf_tape_free": (None, [c_void_p]),
     "abdf_solve_adjoint": (ctypes.c_int, [c_void_p, ctypes.c_int64] + [c_void_p] * 8 +
-                           [ctypes.POINTER(Options)] + [c_void_p] * 8),
+                           [ctypes.POINTER(Options)] + [c_void_p] * 9),
     "abdf_server_options_default": (None, [ctypes.POINTER(ServerOptions)]),
     "abdf_server_create": (ctypes.c_int, [c_void_p, ctypes.POINTER(ServerOptions), ctypes.POINTER(c_void_p)]),
     "abdf_server_submit": (ctypes.c_int, [c_void_p, ctypes.POINTER(Request), ctypes.POINTER(ctypes.c_uint64)]),

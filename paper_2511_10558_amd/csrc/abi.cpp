@@ -256,15 +256,16 @@ abdf_status abdf_solve_record(const abdf_network *net, int64_t n_cells, const do
 }
 
 abdf_status abdf_tape_adjoint(abdf_tape *tape, const double *dL_dx, double *dL_dlog_alpha,
-                              double *dL_dlog_alpha_cell, double *dL_dx0, void *stream) {
+                              double *dL_dlog_alpha_cell, double *dL_dx0, double *dL_dphi, void *stream) {
     if (!tape) return fail(ABDF_E_ARG, "null tape");
     CHECK_DEV(dL_dx, "dL_dx");
     if (dL_dlog_alpha) CHECK_DEV(dL_dlog_alpha, "dL_dlog_alpha");
     if (dL_dlog_alpha_cell) CHECK_DEV(dL_dlog_alpha_cell, "dL_dlog_alpha_cell");
     if (dL_dx0) CHECK_DEV(dL_dx0, "dL_dx0");
+    if (dL_dphi) CHECK_DEV(dL_dphi, "dL_dphi");
     try {
         std::string err;
-        int r = tape->impl->adjoint(dL_dx, dL_dlog_alpha, dL_dlog_alpha_cell, dL_dx0,
+        int r = tape->impl->adjoint(dL_dx, dL_dlog_alpha, dL_dlog_alpha_cell, dL_dx0, dL_dphi,
                                     static_cast<hipStream_t>(stream), err);
         if (r != ABDF_OK) return fail(static_cast<abdf_status>(r), err);
         return ok();
@@ -281,12 +282,13 @@ abdf_status abdf_solve_adjoint(const abdf_network *net, int64_t n_cells, const d
                                const double *A_V, const double *zeta, const double *G0, const double *x0,
                                const double *t_end, const double *alpha, const abdf_options *opt,
                                const double *dL_dx, double *x_out, int32_t *cell_status, double *dL_dlog_alpha,
-                               double *dL_dlog_alpha_cell, double *dL_dx0, abdf_cell_stats *stats, void *stream) {
+                               double *dL_dlog_alpha_cell, double *dL_dx0, double *dL_dphi, abdf_cell_stats *stats,
+                               void *stream) {
     abdf_tape *tape = nullptr;
     abdf_status rc = abdf_solve_record(net, n_cells, T, n_H, A_V, zeta, G0, x0, t_end, alpha, opt, 0, x_out,
                                        cell_status, stats, &tape, stream);
     if (rc != ABDF_OK) return rc;
-    rc = abdf_tape_adjoint(tape, dL_dx, dL_dlog_alpha, dL_dlog_alpha_cell, dL_dx0, stream);
+    rc = abdf_tape_adjoint(tape, dL_dx, dL_dlog_alpha, dL_dlog_alpha_cell, dL_dx0, dL_dphi, stream);
     abdf_tape_free(tape);
     return rc;
 }
@@ -444,11 +446,11 @@ abdf_status abdf_newton_matrix(const abdf_network *net, int64_t n_cells, const d
     const abdf::DeviceNet *dn = net->host.device_tables(err);
     if (!dn) return fail(ABDF_E_DEVICE, err);
     hipStream_t st = static_cast<hipStream_t>(stream);
-    double *W = nullptr;
-    HIP_OR_FAIL(hipMalloc(reinterpret_cast<void **>(&W), size_t(n_cells) * dn->NP * dn->NP * sizeof(double)));
-    hipError_t e = abdf::launch_newton_matrix(*dn, n_cells, k, x, c, M_out, W, st);
+    double *jv = nullptr;
+    HIP_OR_FAIL(hipMalloc(reinterpret_cast<void **>(&jv), size_t(n_cells) * std::max(dn->nnzJ, 1) * sizeof(double)));
+    hipError_t e = abdf::launch_newton_matrix(*dn, n_cells, k, x, c, M_out, jv, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
-    (void)hipFree(W);
+    (void)hipFree(jv);
     if (e != hipSuccess) return fail(ABDF_E_DEVICE, hipGetErrorString(e));
     return ok();
 }

@@ -103,19 +103,19 @@ int Tape::record(const BatchIO &io, const double *alpha, const abdf_options &opt
     return ABDF_OK;
 }
 
-int Tape::adjoint(const double *dLdx, double *g_sum, double *g_cell, double *dx0, hipStream_t st,
+int Tape::adjoint(const double *dLdx, double *g_sum, double *g_cell, double *dx0, double *dphi, hipStream_t st,
                   std::string &err) {
     const size_t R = size_t(dn_.R);
     double *gc = g_cell;
     void *tmp = nullptr;
-    if (!gc) {
+    if (!gc && g_sum) {
         if (hipMalloc(&tmp, std::max<size_t>(1, size_t(C_) * R * 8)) != hipSuccess) {
             err = "per-cell gradient scratch";
             return ABDF_E_NOMEM;
         }
         gc = static_cast<double *>(tmp);
     }
-    AdjIO io{C_, phi_, dLdx, status_, gc, dx0};
+    AdjIO io{C_, phi_, dLdx, status_, gc, dx0, dphi};
     int rc = eng_->reverse(io, opt_.check_every, st, err);
     hipError_t e = hipSuccess;
     if (rc == ABDF_OK && g_sum) e = launch_grad_sum(gc, C_, int(R), g_sum, st);

@@ -24,7 +24,8 @@ class Tape {
     int record(const BatchIO &io, const double *alpha, const abdf_options &opt, int cap, hipStream_t st,
                std::string &err);
     // Reverse sweep for the loss gradient dLdx [C][S]; any output may be null.
-    int adjoint(const double *dLdx, double *g_sum, double *g_cell, double *dx0, hipStream_t st, std::string &err);
+    int adjoint(const double *dLdx, double *g_sum, double *g_cell, double *dx0, double *dphi, hipStream_t st,
+                std::string &err);
     size_t bytes() const { return bytes_; }
     long long cells() const { return C_; }
 

@@ -116,8 +116,8 @@ __device__ __forceinline__ void cell_jvp(const DeviceNet &n, const double *__res
 }
 
 // The Jacobian nonzeros J_e(x) of one cell into jv[nnzJ] (global, written
-// coalesced): the terms of each nonzero summed in the order of
-// assemble_newton_matrix.  x in LDS, k in global memory.  Cooperative.
+// coalesced): each nonzero's terms summed in the order of its term list.  x in
+// LDS, k in global memory.  Cooperative.
 template <int NT>
 __device__ __forceinline__ void jacobian_values(const DeviceNet &n, const double *__restrict__ k, const double *x,
                                                 double *jv) {
@@ -156,8 +156,8 @@ __device__ __forceinline__ void jacobian_values(const DeviceNet &n, const double
 }
 
 // Entries of M = I - c J of one cell where the factorisation gathers them:
-// the dense map gives the nonzero of (i, j) (same value as
-// assemble_newton_matrix stores); rows and columns beyond S are the identity's.
+// the dense map gives the nonzero of (i, j); rows and columns beyond S are the
+// identity's.
 template <typename T>
 struct NewtonMatrixSource {
     const int32_t *jidx;   // [NP][NP] entry of J at (i, j), -1 where J is structurally zero
@@ -172,57 +172,5 @@ struct NewtonMatrixSource {
         return T((i == j ? 1.0 : 0.0) + (e >= 0 ? -c * jvv : 0.0));
     }
 };
-
-// One row i of M = I - c J(x) into rowbuf[NP] (LDS, owned by the calling wave),
-// then to the matrix row in global memory as T.  Rows i >= S are identity.
-template <typename T>
-__device__ __forceinline__ void newton_matrix_row(const DeviceNet &n, const double *__restrict__ k, const double *x,
-                                         double c, int i, double *rowbuf, T *Mrow) {
-    const int lane = threadIdx.x & 63;
-    for (int j = lane; j < n.NP; j += 64) rowbuf[j] = 0.0;
-    __builtin_amdgcn_wave_barrier();
-    if (i < n.S) {
-        for (int e = n.jrow_ptr[i] + lane; e < n.jrow_ptr[i + 1]; e += 64) {
-            double v = 0.0;
-            for (int t = n.jterm_ptr[e]; t < n.jterm_ptr[e + 1]; ++t) {
-                const int w = n.jt_rx_other[t];
-                const int other = (w & 0xffff) - 1;
-                double term = n.jt_coef[t] * k[w >> 16];
-                if (other >= 0) term *= x[other];
-                v += term;
-            }
-            rowbuf[n.jcol[e]] = -c * v;
-        }
-    }
-    __builtin_amdgcn_wave_barrier();
-    for (int j = lane; j < n.NP; j += 64) Mrow[j] = T((j == i ? 1.0 : 0.0) + rowbuf[j]);
-    __builtin_amdgcn_wave_barrier();
-}
-
-// M = I - c J(x) for one cell into the NP x NP row-major matrix A (global, T),
-// by all NT threads of the workgroup: an identity pass over the whole matrix,
-// then one independent gather per nonzero of J.  x in LDS.  Contains a
-// workgroup barrier between the passes.
-template <typename T, int NT>
-__device__ __forceinline__ void assemble_newton_matrix(const DeviceNet &n, const double *__restrict__ k,
-                                                       const double *x, double c, T *A) {
-    const int NP = n.NP;
-    const size_t total = size_t(NP) * NP;
-    for (size_t e = threadIdx.x; e < total; e += NT) A[e] = T((e / NP) == (e % NP) ? 1.0 : 0.0);
-    __syncthreads();
-    for (int e = threadIdx.x; e < n.nnzJ; e += NT) {
-        double v = 0.0;
-        for (int t = n.jterm_ptr[e]; t < n.jterm_ptr[e + 1]; ++t) {
-            const int w = n.jt_rx_other[t];
-            const int other = (w & 0xffff) - 1;
-            double term = n.jt_coef[t] * k[w >> 16];
-            if (other >= 0) term *= x[other];
-            v += term;
-        }
-        const int i = n.jrow[e], j = n.jcol[e];
-        A[size_t(i) * NP + j] = T((i == j ? 1.0 : 0.0) + (-c * v));
-    }
-    __syncthreads();
-}
 
 }  // namespace abdf

@@ -478,9 +478,9 @@ int Engine::reverse(const AdjIO &io, int check_every, hipStream_t st, std::strin
             if (rc != ABDF_OK) return rc;
             if (nfin > 0) {
                 HIP_TRY(hipMemcpyAsync(h_fin_, s_.fin, nfin * sizeof(int32_t), hipMemcpyDeviceToHost, st));
-                AdjHarvestArgs h{nfin, s_.fin, io.g_cell, io.dx0};
+                AdjHarvestArgs h{nfin, s_.fin, io.g_cell, io.dx0, io.dphi};
                 hipEvent_t t0 = timer_begin(st);
-                HIP_TRY(launch_adj_harvest(s_, h, st));
+                HIP_TRY(launch_adj_harvest(s_, dn_, h, st));
                 timer_end(ABDF_PROF_HARVEST, t0, st);
                 HIP_TRY(hipStreamSynchronize(st));
                 for (int i = 0; i < nfin; ++i) free_.push_back(h_fin_[i]);

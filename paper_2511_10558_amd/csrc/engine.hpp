@@ -30,8 +30,9 @@ struct AdjIO {
     const double *phi;        // [n][5]
     const double *dLdx;       // [n][S]
     const int32_t *status;    // [n] forward outcome
-    double *g_cell;           // [n][R] gradient with respect to log alpha per cell
+    double *g_cell;           // [n][R] gradient with respect to log alpha per cell, or null
     double *dx0;              // [n][S] or null
+    double *dphi;             // [n][5] gradient with respect to T, n_H, A_V, zeta, G0, or null
 };
 
 // Process-wide kernel timers (abdf_profile_*).

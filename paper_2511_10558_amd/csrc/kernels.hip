@@ -253,6 +253,19 @@ __global__ void __launch_bounds__(kBlock) k_admit(Slots s, DeviceNet n, AdmitArg
     }
     // starting step (Hairer, Norsett & Wanner, Solving ODEs I, Sec. II.4), order 1
     cell_rhs(n, k, xs, rate, part, f0);
+    {
+        // rates that overflow at the initial state leave no step to take
+        bool nf = false;
+        for (int i = threadIdx.x; i < S; i += kBlock) nf |= !isfinite(f0[i]);
+        if (block_any(nf, red)) {
+            if (threadIdx.x == 0) cs.n_rhs = 1;
+            __syncthreads();
+            finish_slot(s, slot, cs, ABDF_CELL_NONFINITE);
+            __syncthreads();
+            if (threadIdx.x == 0) s.ctl[slot] = cs;
+            return;
+        }
+    }
     const double rtol = cs.rtol;
     double s0 = 0.0, s1 = 0.0;
     for (int i = threadIdx.x; i < S; i += kBlock) {
@@ -735,16 +748,21 @@ __global__ void __launch_bounds__(kBlock) k_harvest(Slots s, HarvestArgs h) {
 //   corrector           mu = M^{-T} lambda_d with M = I - c J(x_{n+1}) factored afresh,
 //                       solved as lambda_xp = mu - lambda_d = M^{-T} c J^T lambda_d
 //   predictor           lambda_j += lambda_xp (j <= q), lambda_j -= gamma_j / gamma_q mu (1 <= j <= q)
-//   parameters          dL/dlog alpha_r += c rate_r(x_{n+1}) (nu_r . mu)
+//   parameters          dL/dk_r += c x_a x_b (nu_r . mu)   (x at x_{n+1}, x_b only for two reactants)
 //   step-size change    lambda_{0..q} <- (R(rho) U) lambda when (h, q) changed from step n-1
 // and finally, for D_0 = x_0 and D_1 = h_0 f(x_0):
-//   dL/dlog alpha_r += h_0 rate_r(x_0) (nu_r . lambda_1),  dL/dx_0 = lambda_0 + h_0 J(x_0)^T lambda_1.
+//   dL/dk_r += h_0 x_a x_b (nu_r . lambda_1) at x_0,  dL/dx_0 = lambda_0 + h_0 J(x_0)^T lambda_1.
+// The sweep accumulates the gradient with respect to the rate coefficients;
+// dL/dlog alpha_r = k_r dL/dk_r (k_r is linear in alpha_r) and the gradient with
+// respect to a cell's physical parameters, sum_r dL/dk_r dk_r/dphi, are formed
+// when the cell finishes.  Neither divides by a parameter, so both stay finite
+// where G0 = 0 or zeta = 0 switches a family of reactions off.
 
-// rate_r(x) = k_r x_a (x_b) from the packed reactant pair
-__device__ __forceinline__ double mass_action(const DeviceNet &n, const double *k, const double *xs, int r) {
+// x_a (x_b): the abundance factor of rate_r = k_r x_a (x_b), from the packed reactant pair
+__device__ __forceinline__ double reactant_product(const DeviceNet &n, const double *xs, int r) {
     const int ab = n.rx_ab[r];
     const int a = ab & 0xffff, b = (ab >> 16) & 0xffff;
-    double v = k[r] * xs[a];
+    double v = xs[a];
     if (b != 0xffff) v *= xs[b];
     return v;
 }
@@ -868,7 +886,7 @@ __device__ __forceinline__ void adj_finish(const Slots &s, const DeviceNet &n, i
             l1[i] = L[S + i];
         }
         __syncthreads();
-        for (int r = threadIdx.x; r < R; r += kBlock) g[r] += h0 * mass_action(n, k, xs, r) * nu_dot(n, l1, r);
+        for (int r = threadIdx.x; r < R; r += kBlock) g[r] += h0 * reactant_product(n, xs, r) * nu_dot(n, l1, r);
         __syncthreads();
         // dL/dx0 = lambda_0 + h0 J(x0)^T lambda_1 (dx0 first holds the second term)
         jac_transpose_apply(n, k, xs, l1, w, h0, dx0, S);
@@ -974,9 +992,8 @@ __global__ void __launch_bounds__(kBlock) k_adj_step(Slots s, DeviceNet n, int r
         for (int j = 1; j <= q; ++j) L[j * S + i] = L[j * S + i] + (lxp - gr[j] * m);
     }
     __syncthreads();
-    const double *k = s.k + size_t(slot) * R;
     double *g = s.g + size_t(slot) * R;
-    for (int r = threadIdx.x; r < R; r += kBlock) g[r] += c * mass_action(n, k, xs, r) * nu_dot(n, ms, r);
+    for (int r = threadIdx.x; r < R; r += kBlock) g[r] += c * reactant_product(n, xs, r) * nu_dot(n, ms, r);
     __syncthreads();
     const int m = cs.n_steps - 1;
     if (m > 0) {
@@ -993,17 +1010,63 @@ __global__ void __launch_bounds__(kBlock) k_adj_step(Slots s, DeviceNet n, int r
         adj_finish(s, n, slot, cs, 1, smem);
 }
 
-// Copies the gradients of finished reverse slots to per-cell arrays.
-__global__ void __launch_bounds__(kBlock) k_adj_harvest(Slots s, AdjHarvestArgs h) {
+// dk_r / dphi_j of one reaction for phi = (T, n_H, A_V, zeta, G0) (paper Sec. 2
+// Kooij-Arrhenius and direct cosmic-ray laws, App. B.1 photo and cosmic-ray-
+// induced photon laws), written without dividing by zeta or G0: the
+// cosmic-ray and photo coefficients are linear in them.
+__device__ __forceinline__ void rate_param_derivs(const DeviceNet &n, int r, const double *phi, double k,
+                                                  double d[5]) {
+    const double T = phi[0], nH = phi[1], Av = phi[2];
+    const int t = n.rx_type[r];
+    d[0] = d[1] = d[2] = d[3] = d[4] = 0.0;
+    if (t == kTwoBody) {
+        d[0] = k * (n.beta[r] + n.gamma[r] / T) / T;
+        d[1] = k / nH;
+    } else if (t == kCosmicRay) {
+        d[3] = n.alpha[r];
+    } else if (t == kCrPhoton) {
+        d[0] = k * n.beta[r] / T;
+        d[3] = n.alpha[r] * pow(T / 300.0, n.beta[r]) * (n.gamma[r] / (1.0 - n.albedo));
+    } else {
+        d[2] = -n.gamma[r] * k;
+        d[4] = n.alpha[r] * exp(-n.gamma[r] * Av);
+    }
+}
+
+// Copies the gradients of finished reverse slots to per-cell arrays: dL/dlog
+// alpha_r = k_r dL/dk_r, dL/dx_0, and dL/dphi = sum_r dL/dk_r dk_r/dphi
+// (per-thread sums in reaction order, then a fixed tree).
+__global__ void __launch_bounds__(kBlock) k_adj_harvest(Slots s, DeviceNet n, AdjHarvestArgs h) {
+    __shared__ double red[kWaves];
     const int idx = blockIdx.x;
     if (idx == 0 && threadIdx.x == 0) s.cnt[6] = 0;
     if (idx >= h.count) return;
     const int slot = h.slots[idx];
     const long long cell = s.ctl[slot].cell;
     const int S = s.S, R = s.R;
-    for (int r = threadIdx.x; r < R; r += kBlock) h.g_cell[size_t(cell) * R + r] = s.g[size_t(slot) * R + r];
+    const double *gk = s.g + size_t(slot) * R, *k = s.k + size_t(slot) * R, *phi = s.phi + size_t(slot) * 5;
+    // a cell whose forward solve failed contributes zeros (its coefficients
+    // may not even be finite, e.g. for a non-physical temperature)
+    const bool ok = s.ctl[slot].status == ABDF_CELL_OK;
+    if (h.g_cell)
+        for (int r = threadIdx.x; r < R; r += kBlock) h.g_cell[size_t(cell) * R + r] = ok ? k[r] * gk[r] : 0.0;
     if (h.dx0)
         for (int i = threadIdx.x; i < S; i += kBlock) h.dx0[size_t(cell) * S + i] = s.x[size_t(slot) * S + i];
+    if (h.dphi) {
+        double acc[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+        for (int r = ok ? int(threadIdx.x) : R; r < R; r += kBlock) {
+            double d[5];
+            rate_param_derivs(n, r, phi, k[r], d);
+            const double g = gk[r];
+#pragma unroll
+            for (int j = 0; j < 5; ++j) acc[j] += g * d[j];
+        }
+#pragma unroll
+        for (int j = 0; j < 5; ++j) {
+            const double v = block_sum(acc[j], red);
+            if (threadIdx.x == 0) h.dphi[size_t(cell) * 5 + j] = v;
+        }
+    }
 }
 
 // out[r] = sum over cells of g_cell[c][r], cells in order.
@@ -1077,19 +1140,25 @@ __global__ void __launch_bounds__(kBlock) k_rhs_only(DeviceNet n, const double *
     cell_rhs(n, k + size_t(c) * n.R, xs, rate, part, f + size_t(c) * n.S);
 }
 
-// Writes the unpadded S x S Newton matrix of each cell, assembled by the same
-// code as the solver's factor kernel (into a padded work matrix W).
+// Writes the unpadded S x S Newton matrix of each cell through the solver's
+// own path: the Jacobian nonzeros at x (jacobian_values, into the scratch jv of
+// nnzJ doubles per cell), then every entry as NewtonMatrixSource yields it to
+// the factorisation's gather.
 __global__ void __launch_bounds__(kAsmThreads) k_newton_matrix_only(DeviceNet n, const double *k, const double *x,
-                                                                  const double *cvec, double *W, double *M) {
+                                                                  const double *cvec, double *jv, double *M) {
     extern __shared__ double smem[];
     const long long c = blockIdx.x;
     double *xs = smem;
     for (int i = threadIdx.x; i < n.S; i += kAsmThreads) xs[i] = x[size_t(c) * n.S + i];
     __syncthreads();
-    double *Wc = W + size_t(c) * n.NP * n.NP;
-    assemble_newton_matrix<double, kAsmThreads>(n, k + size_t(c) * n.R, xs, cvec[c], Wc);
-    for (size_t e = threadIdx.x; e < size_t(n.S) * n.S; e += kAsmThreads)
-        M[size_t(c) * n.S * n.S + e] = Wc[(e / n.S) * n.NP + e % n.S];
+    double *jvc = jv + size_t(c) * max(n.nnzJ, 1);
+    jacobian_values<kAsmThreads>(n, k + size_t(c) * n.R, xs, jvc);
+    __syncthreads();
+    const NewtonMatrixSource<double> src{n.jidx, jvc, n.S, n.NP, cvec[c]};
+    for (size_t e = threadIdx.x; e < size_t(n.S) * n.S; e += kAsmThreads) {
+        const int i = int(e / n.S), j = int(e % n.S);
+        M[size_t(c) * n.S * n.S + e] = src.value(src.handle(i, j), i, j);
+    }
 }
 
 // Copies an n x n matrix into the padded NP x NP work matrix (identity padding) and back.
@@ -1332,8 +1401,8 @@ hipError_t launch_adj_step(const Slots &s, const DeviceNet &n, int ring, int gri
     return LAUNCH_CHECK();
 }
 
-hipError_t launch_adj_harvest(const Slots &s, const AdjHarvestArgs &h, hipStream_t st) {
-    hipLaunchKernelGGL(k_adj_harvest, dim3(h.count > 0 ? h.count : 1), dim3(kBlock), 0, st, s, h);
+hipError_t launch_adj_harvest(const Slots &s, const DeviceNet &n, const AdjHarvestArgs &h, hipStream_t st) {
+    hipLaunchKernelGGL(k_adj_harvest, dim3(h.count > 0 ? h.count : 1), dim3(kBlock), 0, st, s, n, h);
     return LAUNCH_CHECK();
 }
 
@@ -1360,9 +1429,9 @@ hipError_t launch_rhs(const DeviceNet &n, long long cells, const double *k, cons
 }
 
 hipError_t launch_newton_matrix(const DeviceNet &n, long long cells, const double *k, const double *x,
-                                const double *c, double *M, double *W, hipStream_t st) {
+                                const double *c, double *M, double *jv, hipStream_t st) {
     const size_t lds = sizeof(double) * size_t(n.S);
-    hipLaunchKernelGGL(k_newton_matrix_only, dim3(cells), dim3(kAsmThreads), lds, st, n, k, x, c, W, M);
+    hipLaunchKernelGGL(k_newton_matrix_only, dim3(cells), dim3(kAsmThreads), lds, st, n, k, x, c, jv, M);
     return LAUNCH_CHECK();
 }
 

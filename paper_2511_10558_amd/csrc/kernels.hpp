@@ -45,8 +45,9 @@ struct AdjArgs {
 struct AdjHarvestArgs {
     int count;
     const int32_t *slots;
-    double *g_cell;             // [cells][R]
+    double *g_cell;             // [cells][R] dL/dlog alpha, or null
     double *dx0;                // [cells][S] or null
+    double *dphi;               // [cells][5] dL/d(T, n_H, A_V, zeta, G0), or null
 };
 
 struct PhysArgs {
@@ -88,7 +89,7 @@ hipError_t launch_harvest(const Slots &s, const HarvestArgs &h, hipStream_t st);
 hipError_t launch_adj_admit(const Slots &s, const DeviceNet &n, const AdjArgs &a, int ring, size_t lds, hipStream_t st);
 hipError_t launch_adj_solve(const Slots &s, int ring, int grid, size_t lds, hipStream_t st);
 hipError_t launch_adj_step(const Slots &s, const DeviceNet &n, int ring, int grid, size_t lds, hipStream_t st);
-hipError_t launch_adj_harvest(const Slots &s, const AdjHarvestArgs &h, hipStream_t st);
+hipError_t launch_adj_harvest(const Slots &s, const DeviceNet &n, const AdjHarvestArgs &h, hipStream_t st);
 hipError_t launch_grad_sum(const double *g_cell, long long cells, int R, double *out, hipStream_t st);
 // dL/dphi [cells][5] (T, n_H, A_V, zeta, G0) from per-cell dL/dlog alpha [cells][R].
 hipError_t launch_phys_grad(const DeviceNet &n, const PhysArgs &p, long long cells, const double *g_cell,
@@ -98,8 +99,9 @@ inline size_t adj_solve_lds(const DeviceNet &n) { return sizeof(double) * (2 * s
 
 hipError_t launch_rates(const DeviceNet &n, const PhysArgs &p, long long cells, double *k, hipStream_t st);
 hipError_t launch_rhs(const DeviceNet &n, long long cells, const double *k, const double *x, double *f, hipStream_t st);
+// jv: scratch of cells * max(nnzJ, 1) doubles (the Jacobian nonzeros)
 hipError_t launch_newton_matrix(const DeviceNet &n, long long cells, const double *k, const double *x,
-                                const double *c, double *M, double *W, hipStream_t st);
+                                const double *c, double *M, double *jv, hipStream_t st);
 hipError_t launch_lu_factor(int n, int NP, long long batch, double *A, void *W, int32_t *permW, int32_t *perm,
                             void *dinv, int32_t *info, int prec, hipStream_t st);
 hipError_t launch_lu_solve(int n, int NP, long long batch, const double *LU, const int32_t *perm, double *b,

@@ -190,7 +190,7 @@ def test_adjoint_entry_points_reject_null_arguments():
     # no tape pointer
     rc = L.abdf_solve_record(g.handle, 1, *([nul] * 8), ctypes.byref(o), 0, nul, nul, nul, None, nul)
     assert rc == 1
-    assert L.abdf_tape_adjoint(nul, nul, nul, nul, nul, nul) == 1
+    assert L.abdf_tape_adjoint(nul, nul, nul, nul, nul, nul, nul) == 1
     assert L.abdf_tape_bytes(nul) == 0
     L.abdf_tape_free(nul)
     # host pointers are not device pointers

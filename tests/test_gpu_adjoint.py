@@ -53,7 +53,7 @@ def cells_for(net, cell, x0, t_end):
 
 def adjoint(ab, g, cells, dLdx, dev, **kw):
     args = [t(v, dev) for v in (cells.T, cells.n_H, cells.A_V, cells.zeta, cells.G0, cells.x0, cells.t_end)]
-    x, st, gs, gc, dx0 = ab.solve_adjoint(g, *args, t(dLdx, dev), per_cell=True, x0_grad=True, **kw)
+    x, st, gs, gc, dx0, _ = ab.solve_adjoint(g, *args, t(dLdx, dev), per_cell=True, x0_grad=True, **kw)
     return (x.cpu().numpy(), st.cpu().numpy(), gs.cpu().numpy(), gc.cpu().numpy(), dx0.cpu().numpy())
 
 
@@ -188,7 +188,7 @@ def test_autograd_function_matches_solve_adjoint(ab, dev):
     alpha = torch.exp(log_alpha.detach())
     dLdx = torch.zeros_like(x)
     dLdx[:, targets] = 1.0 / x.detach()[:, targets]
-    x2, _, gs, _, dx0 = ab.solve_adjoint(g, *phys, x0.detach(), t(cells.t_end, dev), dLdx, alpha=alpha,
+    x2, _, gs, _, dx0, _ = ab.solve_adjoint(g, *phys, x0.detach(), t(cells.t_end, dev), dLdx, alpha=alpha,
                                          x0_grad=True)
     assert torch.equal(x2, x.detach())
     assert torch.equal(log_alpha.grad, gs)
@@ -206,10 +206,10 @@ def test_tape_is_linear_in_the_loss_gradient_and_reusable(ab, dev):
     assert tape.nbytes > 0
     rng = np.random.default_rng(3)
     a, b = rng.normal(size=(2, 4, net.n_species))
-    ga, gca, da = tape.adjoint(t(a, dev), per_cell=True, x0_grad=True)
-    gb, _, db = tape.adjoint(t(b, dev), x0_grad=True)
-    gab, _, dab = tape.adjoint(t(a + b, dev), x0_grad=True)
-    ga2, _, _ = tape.adjoint(t(a, dev))
+    ga, gca, da, _ = tape.adjoint(t(a, dev), per_cell=True, x0_grad=True)
+    gb, _, db, _ = tape.adjoint(t(b, dev), x0_grad=True)
+    gab, _, dab, _ = tape.adjoint(t(a + b, dev), x0_grad=True)
+    ga2, _, _, _ = tape.adjoint(t(a, dev))
     assert torch_equal(ga, ga2)
     scale = max(float(ga.abs().max()), float(gb.abs().max()))
     assert float((gab - ga - gb).abs().max()) <= 1e-10 * scale

@@ -14,7 +14,7 @@ import pytest
 import scipy.linalg as sla
 
 import synth
-from oracle import chem
+from oracle import bdf, chem
 from tests import tiny_nets
 from tests.gpu_util import device, solve_cells, t
 from tests.test_gpu_adjoint import adjoint, cells_for, grad_ok, log_loss_grad, oracle_log_gradient
@@ -121,11 +121,13 @@ def test_autograd_reaches_the_physical_parameters(ab, dev):
     dLdx[:, targets] = 1.0 / x.detach()[:, targets]
     plain = [p.detach() for p in phys]
     # the same solve through the one-call entry point, with alpha = exp(log alpha) as the function uses
-    _, _, _, gc, _ = ab.solve_adjoint(g, *plain, t(cells.x0, dev), t(cells.t_end, dev), dLdx,
-                                      alpha=torch.exp(log_alpha), per_cell=True)
-    want = ab.phys_gradient(g, *plain, gc)
+    _, _, _, gc, _, want = ab.solve_adjoint(g, *plain, t(cells.x0, dev), t(cells.t_end, dev), dLdx,
+                                            alpha=torch.exp(log_alpha), per_cell=True, phys_grad=True)
     for j, p in enumerate(phys):
         assert torch.equal(p.grad, want[:, j])
+    # the contraction of the log-alpha gradients gives the same values up to rounding
+    via_alpha = ab.phys_gradient(g, *plain, gc)
+    assert torch.allclose(via_alpha, want, rtol=1e-12, atol=0)
 
 
 PHYS_GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "phys_net500.json")
@@ -155,3 +157,69 @@ def test_net500_matches_oracle_sensitivities_and_central_differences(ab, dev):
         scale = np.maximum(np.abs(fd), 1e-3 * np.abs(sens).max())
         own = np.abs(sens - fd) / scale
         assert np.all(np.abs(gv - fd) / scale <= np.maximum(1e-3, 2.0 * own))
+
+
+def oracle_phys_gradient(net, cells, c, targets, rtol=1e-6, atol=1e-20):
+    """dL/dphi of the oracle's frozen map by forward sensitivities with
+    df/dphi_j = nu . (dk/dphi_j x_a x_b), the rate laws differentiated directly."""
+    cell = cells.cell(c)
+    ch = chem.cell_chemistry(net, cell)
+    res = bdf.solve(ch, cells.x0[c], cells.t_end[c], rtol, atol, record=True)
+    Dk = chem.rate_parameter_derivatives(net, **cell)
+    nu = chem.stoichiometry(net)
+    dfdp = lambda y: np.column_stack([nu @ chem.reaction_rates(net, Dk[:, j], y) for j in range(5)])
+    x, S = bdf.replay(ch, cells.x0[c], res.history, max_newton=8, sens_dfdp=dfdp)
+    return (S[targets] / x[targets, None]).sum(axis=0)
+
+
+@pytest.mark.parametrize("where", ["zeta0", "G00"])
+def test_gradient_exact_where_zeta_or_G0_vanish(ab, dev, where):
+    # zeta = 0 (G0 = 0) switches the cosmic-ray (photo) reactions off: their k
+    # and log-alpha gradients vanish, yet dL/dzeta (dL/dG0) is finite.  The
+    # sweep's dL/dk gives it exactly; checked entry by entry against the
+    # oracle's forward sensitivities with the rate laws differentiated directly
+    import torch
+    net = tiny_nets.four_types(albedo=0.3)
+    g = ab.Network.from_text(net.to_text())
+    cells = synth.sample_cells(net, 2, seed=141, t_end_yr=1e5)
+    col = 3 if where == "zeta0" else 4
+    (cells.zeta if where == "zeta0" else cells.G0)[:] = 0.0
+    xg, st, _ = solve_cells(ab, g, cells, dev)
+    assert (st == 0).all()
+    targets = np.flatnonzero((xg > 1e-12).all(axis=0))
+    args = [t(v, dev) for v in (cells.T, cells.n_H, cells.A_V, cells.zeta, cells.G0, cells.x0, cells.t_end)]
+    _, st, _, _, _, dphi = ab.solve_adjoint(g, *args, t(log_loss_grad(xg, targets), dev), phys_grad=True)
+    assert (st.cpu().numpy() == 0).all()
+    dphi = dphi.cpu().numpy()
+    assert np.all(np.isfinite(dphi))
+    for c in range(cells.n):
+        ref = oracle_phys_gradient(net, cells, c, targets)
+        assert ref[col] != 0.0
+        for j in range(5):
+            if ref[j] == 0.0:
+                assert dphi[c, j] == 0.0, (c, j)
+            else:
+                assert abs(dphi[c, j] - ref[j]) <= 1e-3 * abs(ref[j]), (c, j, dphi[c, j], ref[j])
+    # the autograd function takes the same path
+    phys = [v.clone().requires_grad_(True) for v in args[:5]]
+    log_alpha = torch.tensor(np.log(net.alpha), dtype=torch.float64, device=dev)
+    x, st2 = ab.solve_diff(g, *phys, args[5], args[6], log_alpha)
+    torch.log(x[:, targets]).sum().backward()
+    assert torch.isfinite(phys[col].grad).all()
+    np.testing.assert_allclose(phys[col].grad.cpu().numpy(), dphi[:, col], rtol=1e-12, atol=0)
+
+
+def test_autograd_refuses_cells_that_did_not_finish(ab, dev):
+    # a cell that ends with tape_full (more accepted steps than the tape holds)
+    # has no gradient: the backward pass raises instead of returning zeros
+    import torch
+    net = synth.network_for_config("small")
+    g = ab.Network.from_text(net.to_text())
+    cells = synth.sample_cells(net, 2, seed=131, t_end_yr=3e4)
+    log_alpha = torch.tensor(np.log(net.alpha), dtype=torch.float64, device=dev, requires_grad=True)
+    args = [t(v, dev) for v in (cells.T, cells.n_H, cells.A_V, cells.zeta, cells.G0, cells.x0, cells.t_end)]
+    x, st = ab.solve_diff(g, *args[:5], args[5], args[6], log_alpha, max_tape_steps=5)
+    assert (st.cpu().numpy() == 5).all()
+    with pytest.raises(ab.AbdfError) as e:
+        x[:, 0].sum().backward()
+    assert "did not reach t_end" in str(e.value)

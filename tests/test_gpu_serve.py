@@ -179,3 +179,39 @@ def test_fp32_lu_server(ab, dev, net200):
         c = _drain(srv, 1)[rid]
     xb, sb, _ = solve_cells(ab, g, cells, dev, precision="fp32_lu")
     assert np.array_equal(c["x"], xb) and (c["status"] == 0).all()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32_lu"])
+def test_net500_result_alone_equals_result_in_a_large_mix(ab, dev, precision):
+    # The served configuration: the 500-species network, the benchmark's
+    # factorisation policy, a pool of 96 slots kept full by overlapping
+    # requests (at 32 or more occupied slots an attempt runs on two streams,
+    # residual and correction kernels apart; alone, the probe's 4 cells run on
+    # one stream with every Newton iteration in one fused launch).  The probe's
+    # results are bitwise the same both ways and match the oracle
+    net = synth.network_for_config("net500")
+    g = ab.Network.from_text(net.to_text())
+    opts = dict(precision=precision, lu_reuse=0.3)
+    probe = synth.sample_cells(net, 4, seed=91, t_end_yr=3e5)
+    with ab.Server(g, **opts) as srv:
+        pid0 = _submit(srv, probe)
+        a = _drain(srv, 1)[pid0]
+    others = _stream(net, [(92, 80, 1e6), (93, 50, 1e5), (94, 60, 3e5), (95, 30, 1e6)])
+    with ab.Server(g, max_slots=96, **opts) as srv:
+        ids = [_submit(srv, others[0]), _submit(srv, others[1])]
+        time.sleep(0.05)
+        pid = _submit(srv, probe)
+        ids += [_submit(srv, others[2]), _submit(srv, others[3])]
+        done = _drain(srv, 5, timeout_s=300.0)
+        info = srv.info()
+    m = done[pid]
+    assert (a["status"] == 0).all() and (m["status"] == 0).all()
+    assert m["t_first_admit"] < max(done[r]["t_done"] for r in ids)      # it ran beside the others
+    assert np.array_equal(m["x"], a["x"]), "served result differs alone and in the mix"
+    assert np.array_equal(m["stats"]["n_attempts"], a["stats"]["n_attempts"])
+    assert info["slots"] == 96 and info["completed_cells"] == 4 + sum(c.n for c in others)
+    for rid in ids:
+        assert (done[rid]["status"] == 0).all()
+    for i in range(2):
+        ref = bdf.solve(chem.cell_chemistry(net, probe.cell(i)), probe.x0[i], probe.t_end[i], 1e-6, 1e-20)
+        assert rel_err_above(m["x"][i], ref.x) <= 1e-4, (i, rel_err_above(m["x"][i], ref.x))

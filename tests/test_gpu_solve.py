@@ -62,7 +62,8 @@ def test_batched_cells_match_oracle(ab, dev, name, n, seed):
         assert err <= TOL, (c, err, int(stats["n_steps"][c]), refs[c].stats.n_steps)
         # conservation: 1e-12 of each conserved quantity's terms, plus the drift
         # that FP64 Newton solves at condition numbers up to ~1e7 leave on these
-        # connected networks (the oracle itself drifts by up to ~5e-10 of |x|_1)
+        # connected networks (the oracle's own drift on these cells stays below
+        # 1e-8 of |x|_1; tests/test_oracle_bdf.py measures it)
         w0 = W @ cells.x0[c]
         bound = 1e-12 * (np.abs(W) @ np.abs(x[c])) + 1e-8 * np.abs(x[c]).sum()
         assert np.all(np.abs(W @ x[c] - w0) <= bound)
@@ -137,26 +138,36 @@ def test_fp32_lu_form_matches_oracle(ab, dev):
     assert np.all(st64["n_lu_fp64"] == st64["n_lu"])
 
 
-@pytest.mark.parametrize("name,seed", [("net500", 3001), ("net200", 2001)])
-def test_full_batch_sampled_against_oracle(ab, dev, name, seed):
-    # the 4096-cell batch the benchmark times, in its launch configuration: every
-    # cell finishes and conserves elements and charge; seeded cells spread over
-    # the batch match the oracle, in FP64 and in the FP32-LU form
+@pytest.mark.parametrize("name,seed,lu_reuse", [("net500", 3001, 0.3), ("net200", 2001, 0.0)])
+def test_full_batch_sampled_against_oracle(ab, dev, name, seed, lu_reuse):
+    # The 4096-cell batch the benchmark times, in its launch configuration (the
+    # 500-species batch at the benchmark's factorisation policy): every cell
+    # finishes and conserves elements and charge; seeded cells spread over the
+    # batch, solved again on their own, are bitwise the same (alone: fewer than
+    # 32 occupied slots, one stream, every Newton iteration in one fused launch;
+    # in the batch: two streams, residual and correction kernels apart) and
+    # match the oracle, in FP64 and in the FP32-LU form
     net = synth.network_for_config(name)
     cells = synth.sample_cells(net, 4096, seed=seed, t_end_yr=1e6)
     g = ab.Network.from_text(net.to_text())
-    x, status, _ = solve_cells(ab, g, cells, dev)
-    x32, status32, _ = solve_cells(ab, g, cells, dev, precision="fp32_lu")
+    x, status, _ = solve_cells(ab, g, cells, dev, lu_reuse=lu_reuse)
+    x32, status32, _ = solve_cells(ab, g, cells, dev, precision="fp32_lu", lu_reuse=lu_reuse)
     assert (status == 0).all() and (status32 == 0).all()
     # W f = 0 and W (I - c J) = W, so the method keeps W x exactly in exact
-    # arithmetic; in FP64 the Newton solves' rounding lets it drift, and the
-    # oracle's own drift on this net200 batch reaches 1.2e-8 of sum |x| (cell 2840)
+    # arithmetic; in FP64 the Newton solves' rounding lets it drift.  The
+    # oracle's own drift on the net200 batch reaches 1.2e-8 of sum |x| (cell
+    # 2840; tests/test_oracle_bdf.py measures it): the bar is 1e-7 of sum |x|
     W = net.conservation_matrix().astype(float)
     w0 = cells.x0 @ W.T
     bound = 1e-12 * (np.abs(x) @ np.abs(W).T) + 1e-7 * np.abs(x).sum(axis=1, keepdims=True)
     assert np.all(np.abs(x @ W.T - w0) <= bound)
     sample = np.sort(np.random.default_rng(seed + 7).choice(4096, 3, replace=False))
-    refs = oracle_cells(net, cells.subset(sample))
+    sub = cells.subset(sample)
+    for prec, xb in (("fp64", x), ("fp32_lu", x32)):
+        alone, st_a, _ = solve_cells(ab, g, sub, dev, precision=prec, lu_reuse=lu_reuse)
+        assert (st_a == 0).all()
+        assert np.array_equal(alone, xb[sample]), (prec, "alone differs from the same cells in the batch")
+    refs = oracle_cells(net, sub)
     for j, c in enumerate(sample):
         assert rel_err_above(x[c], refs[j].x) <= TOL, (c, rel_err_above(x[c], refs[j].x))
         assert rel_err_above(x32[c], refs[j].x) <= TOL, (c, rel_err_above(x32[c], refs[j].x))
@@ -293,3 +304,27 @@ def test_factorisation_reuse_across_small_c_changes(ab, dev):
         assert rel_err_above(x1[c], refs[c].x) <= TOL
     with pytest.raises(ab.AbdfError):
         solve_cells(ab, g, cells, dev, lu_reuse=1.0)
+
+
+def test_failure_codes_match_the_oracle(ab, dev):
+    # finite-time blow-up from negative abundances (x_A' = -k' x_A^2, a0 < 0)
+    # ends with STEP_TOO_SMALL near t* = 1 / (k' |a0|); rates overflowing at the
+    # initial state end as NONFINITE before any step; the same codes as the oracle
+    net = tiny_nets.association(1e-9)
+    cell = dict(T=300.0, n_H=1e4, A_V=0.0, zeta=1e-17, G0=1.0)
+    kp, a0 = chem.rate_coefficients(net, **cell)[0], -1e-4
+    t_star = 1.0 / (kp * abs(a0))
+    g = ab.Network.from_text(net.to_text())
+    x0s = [[a0, a0, 0.0], [1e200, 1e200, 0.0], [1e-4, 2e-4, 0.0]]
+    x, status, stats = solve_cells(ab, g, _cells(net, cell, x0s, 2 * t_star), dev)
+    ch = chem.cell_chemistry(net, cell)
+    with np.errstate(over="ignore", invalid="ignore"):
+        refs = [bdf.solve(ch, np.array(v), 2 * t_star, 1e-6, 1e-20) for v in x0s]
+    assert [r.status for r in refs] == [bdf.STEP_TOO_SMALL, bdf.NONFINITE, bdf.OK]
+    assert list(status) == [r.status for r in refs]
+    tg = stats["t"][0]
+    assert stats["h"][0] < 10 * bdf.U_ROUND * tg
+    assert abs(tg - t_star) <= 1e-4 * t_star and tg < t_star
+    assert abs(tg + 1.0 / (kp * abs(x[0, 0])) - t_star) <= 1e-4 * t_star
+    assert stats["t"][1] == 0.0 and stats["n_steps"][1] == 0 and np.array_equal(x[1], x0s[1])
+    assert rel_err_above(x[2], refs[2].x) <= TOL
