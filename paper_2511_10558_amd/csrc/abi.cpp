@@ -81,14 +81,19 @@ abdf_status check_opts(const abdf_options &o) {
     return ABDF_OK;
 }
 
-// Slots that fit in the budget and in 85% of the free device memory (at most `want`).
-long long slot_count(const abdf::DeviceNet &dn, const abdf_options &o, long long want, size_t extra_per_slot = 0) {
+// Slots that fit in the budget and in 85% of the device memory free (plus,
+// for an engine that takes the network's cached workspace, the cached bytes),
+// at most `want`.
+long long slot_count(const abdf::HostNetwork &net, const abdf::DeviceNet &dn, const abdf_options &o, long long want,
+                     size_t extra_per_slot = 0, bool uses_cache = false) {
     const size_t per = abdf::Engine::bytes_per_slot(dn, o.precision) + extra_per_slot;
     long long n = want;
     if (o.hbm_budget_bytes > 0) n = std::min<long long>(n, (long long)(o.hbm_budget_bytes / per));
     size_t free_b = 0, total_b = 0;
-    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b > 0)
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess && free_b > 0) {
+        if (uses_cache) free_b += net.cached_workspace_bytes(dn.device);
         n = std::min<long long>(n, (long long)(0.85 * double(free_b) / double(per)));
+    }
     return n;
 }
 
@@ -179,12 +184,12 @@ abdf_status abdf_solve(const abdf_network *net, int64_t n_cells, const double *T
         std::string err;
         const abdf::DeviceNet *dn = net->host.device_tables(err);
         if (!dn) return fail(ABDF_E_DEVICE, err);
-        const long long nslots = slot_count(*dn, o, n_cells);
+        const long long nslots = slot_count(net->host, *dn, o, n_cells, 0, /*uses_cache=*/true);
         if (nslots < 1) return fail(ABDF_E_BUDGET, "not even one cell fits in the workspace budget");
         abdf::Engine eng(net->host, *dn, o.precision, o.max_steps);
         int r = eng.set_options(o, err);
         if (r != ABDF_OK) return fail(static_cast<abdf_status>(r), err);
-        r = eng.init(int(nslots), err);
+        r = eng.init(int(nslots), err, /*cache_workspace=*/true);
         if (r != ABDF_OK) return fail(static_cast<abdf_status>(r), err);
         abdf::BatchIO io{n_cells, T, n_H, A_V, zeta, G0, x0, t_end, x_out, cell_status, stats};
         r = eng.solve(io, o, static_cast<hipStream_t>(stream), err);
@@ -315,7 +320,7 @@ abdf_status abdf_server_create(const abdf_network *net, const abdf_server_option
         if (!dn) return fail(ABDF_E_DEVICE, err);
         // staging per slot: admission inputs (8 + S doubles), outputs (S doubles, status, stats)
         const size_t staging = (8 + 2 * size_t(dn->S)) * sizeof(double) + 16 + sizeof(abdf_cell_stats);
-        long long nslots = slot_count(*dn, o.solve, o.max_slots > 0 ? o.max_slots : INT32_MAX, staging);
+        long long nslots = slot_count(net->host, *dn, o.solve, o.max_slots > 0 ? o.max_slots : INT32_MAX, staging);
         if (nslots < 1) return fail(ABDF_E_BUDGET, "not even one cell fits in the workspace budget");
         int dev = 0;
         HIP_OR_FAIL(hipGetDevice(&dev));

@@ -115,7 +115,12 @@ Engine::~Engine() {
         event_pool_.push_back(p.b);
     }
     for (hipEvent_t e : event_pool_) (void)hipEventDestroy(e);
-    if (base_) (void)hipFree(base_);
+    if (base_) {
+        if (cached_)
+            net_.keep_workspace(dn_.device, base_, base_bytes_);
+        else
+            (void)hipFree(base_);
+    }
     if (h_cnt_) (void)hipHostFree(h_cnt_);
     if (h_fin_) (void)hipHostFree(h_fin_);
     if (h_admit_slots_) (void)hipHostFree(h_admit_slots_);
@@ -136,99 +141,109 @@ size_t Engine::bytes_per_slot(const DeviceNet &dn, int prec) {
            NP * sizeof(int32_t) + 7 * sizeof(int32_t) + sizeof(long long);
 }
 
-int Engine::set_options(const abdf_options &o, std::string &err) {
+int Engine::set_options(const abdf_options &o, std::string &err, double *atol_host) {
     set_lu_reuse(o.lu_reuse);
     set_max_order(o.max_order);
     set_step_bounds(o.h0, o.h_max);
-    atol_sp_.clear();
+    atol_sp_ = nullptr;
     if (o.atol_species) {
-        atol_sp_.resize(size_t(dn_.S));
-        HIP_TRY(hipMemcpy(atol_sp_.data(), o.atol_species, atol_sp_.size() * sizeof(double), hipMemcpyDeviceToHost));
-        for (double v : atol_sp_)
-            if (!(v >= 0.0) || !std::isfinite(v)) {
+        if (dn_.S > kMaxSpecies) {
+            err = "network too large";
+            return ABDF_E_ARG;
+        }
+        double *h = atol_host;
+        if (!h) {
+            atol_store_.resize(size_t(dn_.S));
+            h = atol_store_.data();
+        }
+        HIP_TRY(hipMemcpy(h, o.atol_species, size_t(dn_.S) * sizeof(double), hipMemcpyDeviceToHost));
+        for (int i = 0; i < dn_.S; ++i)
+            if (!(h[i] >= 0.0) || !std::isfinite(h[i])) {
                 err = "atol_species entries must be finite and >= 0";
-                atol_sp_.clear();
                 return ABDF_E_ARG;
             }
+        atol_sp_ = h;
     }
     return ABDF_OK;
 }
 
-int Engine::init(int nslots, std::string &err) {
-    const size_t n = size_t(nslots), S = dn_.S, R = dn_.R, NP = dn_.NP;
-    const size_t lu_stride = lu_bytes(int(NP), ABDF_PREC_FP64), dinv_stride = dinv_bytes(int(NP), ABDF_PREC_FP64);
-    struct Part { void **dst; size_t bytes; };
-    void *ctl, *phi, *k, *D, *x, *d, *psi, *scl, *xJ, *rb, *jval, *lu, *dinv, *perm, *act, *lul, *nol, *fin, *cnt,
-        *aslots, *acells, *atol_sp;
-    Part parts[] = {
-        {&ctl, n * sizeof(SlotCtl)}, {&phi, n * 5 * sizeof(double)}, {&k, n * R * sizeof(double)},
-        {&D, n * kDRows * S * sizeof(double)}, {&x, n * S * sizeof(double)}, {&d, n * S * sizeof(double)},
-        {&psi, n * S * sizeof(double)}, {&scl, n * S * sizeof(double)}, {&xJ, n * S * sizeof(double)},
-        {&rb, n * S * sizeof(double)}, {&jval, n * size_t(std::max(dn_.nnzJ, 1)) * sizeof(double)},
-        {&lu, n * lu_stride}, {&dinv, n * dinv_stride}, {&perm, n * NP * sizeof(int32_t)}, {&act, 3 * n * sizeof(int32_t)},
-        {&lul, 3 * n * sizeof(int32_t)}, {&nol, 3 * n * sizeof(int32_t)}, {&fin, n * sizeof(int32_t)},
-        {&cnt, kCountSlots * sizeof(int32_t)},
-        {&aslots, n * sizeof(int32_t)}, {&acells, n * sizeof(long long)}, {&atol_sp, S * sizeof(double)},
-    };
-    size_t total = 0;
-    for (auto &p : parts) total += align256(p.bytes);
-    hipError_t e = hipMalloc(&base_, total);
-    if (e != hipSuccess) {
-        base_ = nullptr;
-        err = "device workspace of " + std::to_string(total) + " bytes: " + hipGetErrorString(e);
-        return ABDF_E_NOMEM;
+namespace {
+// The slot arrays of n slots in the order init lays them out (each part
+// 256-byte aligned).
+struct Layout {
+    size_t bytes[22];
+    static constexpr int kParts = 22;
+    Layout(const DeviceNet &dn, size_t n) {
+        const size_t S = dn.S, R = dn.R, NP = dn.NP;
+        const size_t lu_stride = lu_bytes(int(NP), ABDF_PREC_FP64), dinv_stride = dinv_bytes(int(NP), ABDF_PREC_FP64);
+        const size_t b[kParts] = {
+            n * sizeof(SlotCtl), n * 5 * sizeof(double), n * R * sizeof(double), n * kDRows * S * sizeof(double),
+            n * S * sizeof(double), n * S * sizeof(double), n * S * sizeof(double), n * S * sizeof(double),
+            n * S * sizeof(double), n * S * sizeof(double), n * size_t(std::max(dn.nnzJ, 1)) * sizeof(double),
+            n * lu_stride, n * dinv_stride, n * NP * sizeof(int32_t), 3 * n * sizeof(int32_t),
+            3 * n * sizeof(int32_t), 3 * n * sizeof(int32_t), n * sizeof(int32_t), kCountSlots * sizeof(int32_t),
+            n * sizeof(int32_t), n * sizeof(long long), S * sizeof(double)};
+        for (int i = 0; i < kParts; ++i) bytes[i] = b[i];
     }
+    size_t total() const {
+        size_t t = 0;
+        for (size_t b : bytes) t += align256(b);
+        return t;
+    }
+};
+}  // namespace
+
+size_t Engine::workspace_bytes(const DeviceNet &dn, long long n) { return Layout(dn, size_t(n)).total(); }
+
+// Points the slot arrays into base (workspace_bytes(nslots) bytes) and sets
+// the launch shapes.
+int Engine::layout(int nslots, void *base, std::string &err) {
+    const size_t n = size_t(nslots), S = dn_.S, NP = dn_.NP;
+    const Layout lay(dn_, n);
+    void *part[Layout::kParts];
     size_t off = 0;
-    for (auto &p : parts) {
-        *p.dst = static_cast<char *>(base_) + off;
-        off += align256(p.bytes);
+    for (int i = 0; i < Layout::kParts; ++i) {
+        part[i] = static_cast<char *>(base) + off;
+        off += align256(lay.bytes[i]);
     }
-    HIP_TRY(hipMemset(cnt, 0, kCountSlots * sizeof(int32_t)));
     s_.nslots = nslots;
     s_.S = dn_.S;
     s_.R = dn_.R;
     s_.NP = dn_.NP;
     s_.prec = prec_;
     s_.max_steps = max_steps_;
-    s_.ctl = static_cast<SlotCtl *>(ctl);
-    s_.phi = static_cast<double *>(phi);
-    s_.k = static_cast<double *>(k);
-    s_.D = static_cast<double *>(D);
-    s_.x = static_cast<double *>(x);
-    s_.d = static_cast<double *>(d);
-    s_.psi = static_cast<double *>(psi);
-    s_.scl = static_cast<double *>(scl);
-    s_.xJ = static_cast<double *>(xJ);
-    s_.rb = static_cast<double *>(rb);
-    s_.jval = static_cast<double *>(jval);
-    s_.lu = lu;
-    s_.dinv = dinv;
-    s_.lu_stride = lu_stride;
-    s_.dinv_stride = dinv_stride;
-    s_.perm = static_cast<int32_t *>(perm);
-    s_.act = static_cast<int32_t *>(act);
-    s_.lul = static_cast<int32_t *>(lul);
+    s_.ctl = static_cast<SlotCtl *>(part[0]);
+    s_.phi = static_cast<double *>(part[1]);
+    s_.k = static_cast<double *>(part[2]);
+    s_.D = static_cast<double *>(part[3]);
+    s_.x = static_cast<double *>(part[4]);
+    s_.d = static_cast<double *>(part[5]);
+    s_.psi = static_cast<double *>(part[6]);
+    s_.scl = static_cast<double *>(part[7]);
+    s_.xJ = static_cast<double *>(part[8]);
+    s_.rb = static_cast<double *>(part[9]);
+    s_.jval = static_cast<double *>(part[10]);
+    s_.lu = part[11];
+    s_.dinv = part[12];
+    s_.lu_stride = lu_bytes(int(NP), ABDF_PREC_FP64);
+    s_.dinv_stride = dinv_bytes(int(NP), ABDF_PREC_FP64);
+    s_.perm = static_cast<int32_t *>(part[13]);
+    s_.act = static_cast<int32_t *>(part[14]);
+    s_.lul = static_cast<int32_t *>(part[15]);
+    s_.nol = static_cast<int32_t *>(part[16]);
+    s_.fin = static_cast<int32_t *>(part[17]);
+    s_.cnt = static_cast<int32_t *>(part[18]);
+    d_admit_slots_ = static_cast<int32_t *>(part[19]);
+    d_admit_cells_ = static_cast<long long *>(part[20]);
     s_.lu_reuse = lu_reuse_;
     s_.max_order = max_order_;
     s_.h0 = h0_;
     s_.h_max = h_max_;
     s_.atol_sp = nullptr;
-    if (!atol_sp_.empty()) {
-        HIP_TRY(hipMemcpy(atol_sp, atol_sp_.data(), S * sizeof(double), hipMemcpyHostToDevice));
-        s_.atol_sp = static_cast<const double *>(atol_sp);
+    if (atol_sp_) {
+        HIP_TRY(hipMemcpy(part[21], atol_sp_, S * sizeof(double), hipMemcpyHostToDevice));
+        s_.atol_sp = static_cast<const double *>(part[21]);
     }
-    s_.nol = static_cast<int32_t *>(nol);
-    s_.fin = static_cast<int32_t *>(fin);
-    s_.cnt = static_cast<int32_t *>(cnt);
-    d_admit_slots_ = static_cast<int32_t *>(aslots);
-    d_admit_cells_ = static_cast<long long *>(acells);
-    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&h_cnt_), kCountSlots * sizeof(int32_t), hipHostMallocDefault));
-    HIP_TRY(hipStreamCreateWithFlags(&side_, hipStreamNonBlocking));
-    HIP_TRY(hipEventCreateWithFlags(&ev_lists_, hipEventDisableTiming));
-    HIP_TRY(hipEventCreateWithFlags(&ev_side_, hipEventDisableTiming));
-    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&h_fin_), n * sizeof(int32_t), hipHostMallocDefault));
-    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&h_admit_slots_), n * sizeof(int32_t), hipHostMallocDefault));
-    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&h_admit_cells_), n * sizeof(long long), hipHostMallocDefault));
     lds_admit_ = admit_lds(dn_);
     lds_factor_ = factor_lds(dn_, ABDF_PREC_FP64);
     lds_factor32_ = factor_lds(dn_, ABDF_PREC_FP32_LU);
@@ -252,8 +267,38 @@ int Engine::init(int nslots, std::string &err) {
     grid_solve_max_ = f32 ? cus * resident_per_cu(2, prec_, lds_solve_) : grid_solve64_max_;
     grid_solve_ref_max_ = cus * resident_per_cu(4, prec_, lds_solve32_);
     grid_adj_solve_max_ = cus * resident_per_cu(3, prec_, adj_solve_lds(dn_));
-    free_.clear();
-    for (int i = nslots - 1; i >= 0; --i) free_.push_back(i);
+    n_free_ = 0;
+    for (int i = nslots - 1; i >= 0; --i) free_[n_free_++] = i;
+    (void)n;
+    return ABDF_OK;
+}
+
+int Engine::init(int nslots, std::string &err, bool cache_workspace) {
+    const size_t n = size_t(nslots);
+    const size_t total = workspace_bytes(dn_, nslots);
+    cached_ = cache_workspace;
+    base_ = cached_ ? net_.take_workspace(dn_.device, total, &base_bytes_) : nullptr;
+    if (!base_) {
+        hipError_t e = hipMalloc(&base_, total);
+        if (e != hipSuccess) {
+            base_ = nullptr;
+            err = "device workspace of " + std::to_string(total) + " bytes: " + hipGetErrorString(e);
+            return ABDF_E_NOMEM;
+        }
+        base_bytes_ = total;
+    }
+    free_store_.resize(n);
+    free_ = free_store_.data();
+    int rc = layout(nslots, base_, err);
+    if (rc != ABDF_OK) return rc;
+    HIP_TRY(hipMemset(s_.cnt, 0, kCountSlots * sizeof(int32_t)));
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&h_cnt_), kCountSlots * sizeof(int32_t), hipHostMallocDefault));
+    HIP_TRY(hipStreamCreateWithFlags(&side_, hipStreamNonBlocking));
+    HIP_TRY(hipEventCreateWithFlags(&ev_lists_, hipEventDisableTiming));
+    HIP_TRY(hipEventCreateWithFlags(&ev_side_, hipEventDisableTiming));
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&h_fin_), n * sizeof(int32_t), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&h_admit_slots_), n * sizeof(int32_t), hipHostMallocDefault));
+    HIP_TRY(hipHostMalloc(reinterpret_cast<void **>(&h_admit_cells_), n * sizeof(long long), hipHostMallocDefault));
     return ABDF_OK;
 }
 
@@ -273,7 +318,7 @@ int Engine::admit_cells(const AdmitArgs &a, hipStream_t st, std::string &err) {
 }
 
 int Engine::admit(const BatchIO &io, const abdf_options &opt, long long &next, hipStream_t st, std::string &err) {
-    const long long want = std::min<long long>(static_cast<long long>(free_.size()), io.n_cells - next);
+    const long long want = std::min<long long>(static_cast<long long>(n_free_), io.n_cells - next);
     if (want <= 0) return ABDF_OK;
     for (long long i = 0; i < want; ++i) {
         h_admit_slots_[i] = take_slot();
@@ -382,7 +427,7 @@ int Engine::harvest(HarvestArgs h, hipStream_t st, std::string &err) {
     HIP_TRY(launch_harvest(s_, h, st));
     timer_end(ABDF_PROF_HARVEST, t0, st);
     HIP_TRY(hipStreamSynchronize(st));
-    for (int i = 0; i < nfin; ++i) free_.push_back(h_fin_[i]);
+    for (int i = 0; i < nfin; ++i) free_[n_free_++] = h_fin_[i];
     return ABDF_OK;
 }
 
@@ -436,7 +481,7 @@ int Engine::reverse(const AdjIO &io, int check_every, hipStream_t st, std::strin
     check_every = std::max(1, check_every);
     long long next = 0;
     auto admit_rev = [&]() -> int {
-        const long long want = std::min<long long>(static_cast<long long>(free_.size()), io.n_cells - next);
+        const long long want = std::min<long long>(static_cast<long long>(n_free_), io.n_cells - next);
         if (want <= 0) return ABDF_OK;
         for (long long i = 0; i < want; ++i) {
             h_admit_slots_[i] = take_slot();
@@ -483,7 +528,7 @@ int Engine::reverse(const AdjIO &io, int check_every, hipStream_t st, std::strin
                 HIP_TRY(launch_adj_harvest(s_, dn_, h, st));
                 timer_end(ABDF_PROF_HARVEST, t0, st);
                 HIP_TRY(hipStreamSynchronize(st));
-                for (int i = 0; i < nfin; ++i) free_.push_back(h_fin_[i]);
+                for (int i = 0; i < nfin; ++i) free_[n_free_++] = h_fin_[i];
             }
             rc = admit_rev();
             if (rc != ABDF_OK) return rc;

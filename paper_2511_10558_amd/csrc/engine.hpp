@@ -35,6 +35,8 @@ struct AdjIO {
     double *dphi;             // [n][5] gradient with respect to T, n_H, A_V, zeta, G0, or null
 };
 
+constexpr int kMaxSpecies = 512;   // the factorisation holds at most this order
+
 // Process-wide kernel timers (abdf_profile_*).
 struct Profiler {
     static bool on();
@@ -50,8 +52,12 @@ class Engine {
   public:
     Engine(const HostNetwork &net, const DeviceNet &dn, int prec, int max_steps);
     ~Engine();
-    // Allocates room for up to `nslots` slots; returns an abdf_status.
-    int init(int nslots, std::string &err);
+    // Allocates room for up to `nslots` slots; returns an abdf_status.  With
+    // cache_workspace the device workspace is taken from the network's cache
+    // on this device when large enough and returned to it by the destructor.
+    int init(int nslots, std::string &err, bool cache_workspace = false);
+    // Device bytes of the workspace of n slots (as init lays it out).
+    static size_t workspace_bytes(const DeviceNet &dn, long long n);
     // relative change of c within which a slot keeps its factorisation (0: none)
     void set_lu_reuse(double v) { lu_reuse_ = v; s_.lu_reuse = v; }
     // highest order the order selection may reach (1..5; 0 or out of range: 5)
@@ -60,8 +66,9 @@ class Engine {
         s_.max_order = max_order_;
     }
     // The method options of o (reuse threshold, order cap, step bounds and the
-    // per-species absolute tolerances, read from the device now).  Before init.
-    int set_options(const abdf_options &o, std::string &err);
+    // per-species absolute tolerances, read from the device now into atol_host,
+    // kMaxSpecies doubles, or into storage of the engine's own when null).  Before init.
+    int set_options(const abdf_options &o, std::string &err, double *atol_host = nullptr);
     // first step (0: heuristic) and bound on every step (0: none), seconds
     void set_step_bounds(double h0, double h_max) {
         h0_ = h0;
@@ -79,14 +86,10 @@ class Engine {
 
     // Building blocks of a driver loop (batch solve, server, adjoint).
     int nslots() const { return s_.nslots; }
-    int free_count() const { return int(free_.size()); }
+    int free_count() const { return n_free_; }
     // Slots on the current attempt list (an upper bound until the next sync_counts).
     int running() const { return bound_; }
-    int take_slot() {
-        const int v = free_.back();
-        free_.pop_back();
-        return v;
-    }
+    int take_slot() { return free_[--n_free_]; }
     // Admits a.count cells into the slots a.slots (taken with take_slot).
     int admit_cells(const AdmitArgs &a, hipStream_t st, std::string &err);
     // One step attempt of every running slot.
@@ -119,9 +122,13 @@ class Engine {
     double lu_reuse_ = 0.0;
     int max_order_ = kMaxOrder;
     double h0_ = 0.0, h_max_ = 0.0;
-    std::vector<double> atol_sp_;   // per-species absolute tolerances (empty: the scalar atol)
+    std::vector<double> atol_store_;   // per-species absolute tolerances when the engine owns them
+    const double *atol_sp_ = nullptr;  // host copy of the per-species tolerances, or null (scalar atol)
     Slots s_{};
+    bool cached_ = false;              // the workspace goes back to the network's cache
     void *base_ = nullptr;
+    size_t base_bytes_ = 0;
+    int layout(int nslots, void *base, std::string &err);
     int32_t *d_admit_slots_ = nullptr;
     long long *d_admit_cells_ = nullptr;
     int32_t *h_cnt_ = nullptr;          // pinned [kCountSlots]
@@ -130,7 +137,9 @@ class Engine {
     int32_t *h_fin_ = nullptr;          // pinned [nslots]
     int32_t *h_admit_slots_ = nullptr;  // pinned [nslots]
     long long *h_admit_cells_ = nullptr;
-    std::vector<int32_t> free_;
+    std::vector<int32_t> free_store_;  // free-slot stack when the engine owns it
+    int32_t *free_ = nullptr;
+    int n_free_ = 0;
     int ring_ = 0;
     int bound_ = 0;
     // LDS and persistent grid sizes; the *64 / unsuffixed FP64 values serve the

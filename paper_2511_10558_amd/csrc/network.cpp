@@ -35,6 +35,14 @@ bool expect_word(Tok &t, const char *w) {
 }  // namespace
 
 HostNetwork::~HostNetwork() {
+    for (size_t i = 0; i < spare.size(); ++i) {
+        if (!spare[i].ptr) continue;
+        int prev = 0;
+        if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(int(i)) == hipSuccess) {
+            (void)hipFree(spare[i].ptr);
+            (void)hipSetDevice(prev);
+        }
+    }
     for (DeviceNet *d : dev) {
         if (!d) continue;
         int prev = 0;
@@ -252,6 +260,53 @@ hipError_t upload(T **dst, const std::vector<T> &src) {
     return e;
 }
 }  // namespace
+
+const DeviceNet *HostNetwork::device_tables_present(int devid) const {
+    std::lock_guard<std::mutex> lock(mu);
+    return devid >= 0 && devid < int(dev.size()) ? dev[devid] : nullptr;
+}
+
+void *HostNetwork::take_workspace(int devid, size_t bytes, size_t *got) const {
+    void *drop = nullptr, *p = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        if (devid < 0 || devid >= int(spare.size()) || !spare[devid].ptr) return nullptr;
+        if (spare[devid].bytes >= bytes) {
+            p = spare[devid].ptr;
+            *got = spare[devid].bytes;
+        } else {
+            drop = spare[devid].ptr;   // too small: released, so that a larger one can be allocated
+        }
+        spare[devid] = Block{};
+    }
+    if (drop) (void)hipFree(drop);
+    return p;
+}
+
+void HostNetwork::keep_workspace(int devid, void *ptr, size_t bytes) const {
+    void *drop = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(mu);
+        if (devid < 0) {
+            drop = ptr;
+        } else {
+            if (int(spare.size()) <= devid) spare.resize(devid + 1);
+            Block &b = spare[devid];
+            if (bytes > b.bytes) {
+                drop = b.ptr;
+                b = Block{ptr, bytes};
+            } else {
+                drop = ptr;
+            }
+        }
+    }
+    if (drop) (void)hipFree(drop);
+}
+
+size_t HostNetwork::cached_workspace_bytes(int devid) const {
+    std::lock_guard<std::mutex> lock(mu);
+    return devid >= 0 && devid < int(spare.size()) ? spare[devid].bytes : 0;
+}
 
 const DeviceNet *HostNetwork::device_tables(std::string &err) const {
     int devid = 0;

@@ -71,6 +71,9 @@ struct HostNetwork {
     // per-device uploads, created on first use
     mutable std::mutex mu;
     mutable std::vector<DeviceNet *> dev;
+    // one solver workspace per device kept between calls (the largest returned)
+    struct Block { void *ptr = nullptr; size_t bytes = 0; };
+    mutable std::vector<Block> spare;
 
     ~HostNetwork();
     // Parses the text format; on failure returns an abdf_status code and sets err.
@@ -79,6 +82,16 @@ struct HostNetwork {
     void finalize();
     // Device tables for the current HIP device (uploaded once); nullptr + err on failure.
     const DeviceNet *device_tables(std::string &err) const;
+    // The tables of device devid if already uploaded, else nullptr (uploads nothing).
+    const DeviceNet *device_tables_present(int devid) const;
+    // A cached workspace of at least `bytes` on device devid (removed from the
+    // cache; its size in *got), or nullptr (a smaller cached one is freed).
+    void *take_workspace(int devid, size_t bytes, size_t *got) const;
+    // Returns a workspace to the cache, which keeps the larger of it and the
+    // one it holds and frees the other.
+    void keep_workspace(int devid, void *ptr, size_t bytes) const;
+    // Bytes cached on device devid.
+    size_t cached_workspace_bytes(int devid) const;
 };
 
 }  // namespace abdf
