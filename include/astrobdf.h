@@ -172,6 +172,33 @@ abdf_status abdf_solve(const abdf_network *net, int64_t n_cells,
                        double *x_out, int32_t *cell_status, abdf_cell_stats *stats,
                        void *stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid device allocation): abdf_solve with the
+ * same arguments, results and errors, that calls no hipMalloc, hipFree or
+ * other allocating routine.  Its workspace is a 64 MiB device array built into
+ * the library (each device the library runs on holds its own copy until the
+ * process ends) and static host buffers; it holds as many slots as fit there
+ * (e.g. 24 cells of the 500-species network, ~100 of the 200-species one, at
+ * most 4096), bounded further by opt->hbm_budget_bytes, and admits further
+ * cells as slots free up.  Attempts run on `stream` alone.
+ * Requirements and limits:
+ *  - the network's device tables must already be on the current device (any
+ *    other solving call with this network on this device uploads them);
+ *    otherwise ABDF_E_ARG;
+ *  - ABDF_E_BUDGET when not even one cell's workspace fits in 64 MiB (or in
+ *    opt->hbm_budget_bytes when that is smaller);
+ *  - every call on one device shares that device's array and host buffers,
+ *    which keep the last call's contents (the call clears what must start at
+ *    zero): calls that overlap on one device race and must be serialised by
+ *    the caller. */
+abdf_status abdf_solve_noalloc(const abdf_network *net, int64_t n_cells,
+                               const double *T, const double *n_H, const double *A_V,
+                               const double *zeta, const double *G0,
+                               const double *x0, const double *t_end,
+                               const abdf_options *opt,
+                               double *x_out, int32_t *cell_status, abdf_cell_stats *stats,
+                               void *stream);
+
 /* ---------------------------------------------------------------- serving --
  * A request server with continuous batching (one per network and device).
  * Requests of any number of cells, each with its own horizon, are queued on

@@ -151,8 +151,10 @@ def stats_to_numpy(buf) -> np.ndarray:
 
 
 def solve(net: Network, T, n_H, A_V, zeta, G0, x0, t_end, *, options: Options | None = None,
-          with_stats=False, **opts):
-    """Integrates every cell to its t_end.  Returns (x_out, status[, stats])."""
+          with_stats=False, noalloc=False, **opts):
+    """Integrates every cell to its t_end.  Returns (x_out, status[, stats]).
+    noalloc: through abdf_solve_noalloc, the entry point that allocates
+    nothing on the device (the outputs here are still torch tensors)."""
     torch = _torch()
     C, S = x0.shape
     f64 = torch.float64
@@ -168,9 +170,9 @@ def solve(net: Network, T, n_H, A_V, zeta, G0, x0, t_end, *, options: Options | 
     if with_stats:
         st = torch.zeros((max(C, 1) * ctypes.sizeof(CellStats),), dtype=torch.uint8, device=x0.device)
         st_ptr = ctypes.c_void_p(st.data_ptr())
-    _check(_lib.lib().abdf_solve(net.handle, C, *args, ctypes.byref(o),
-                                 ctypes.c_void_p(x_out.data_ptr()), ctypes.c_void_p(status.data_ptr()),
-                                 st_ptr, _stream()))
+    entry = _lib.lib().abdf_solve_noalloc if noalloc else _lib.lib().abdf_solve
+    _check(entry(net.handle, C, *args, ctypes.byref(o),
+                 ctypes.c_void_p(x_out.data_ptr()), ctypes.c_void_p(status.data_ptr()), st_ptr, _stream()))
     if with_stats:
         return x_out, status, stats_to_numpy(st)[:C]
     return x_out, status

@@ -88,6 +88,8 @@ SIGNATURES = {
     "abdf_network_species_name": (ctypes.c_char_p, [c_void_p, ctypes.c_int32]),
     "abdf_solve": (ctypes.c_int, [c_void_p, ctypes.c_int64] + [c_void_p] * 7 +
                    [ctypes.POINTER(Options), c_void_p, c_void_p, c_void_p, c_void_p]),
+    "abdf_solve_noalloc": (ctypes.c_int, [c_void_p, ctypes.c_int64] + [c_void_p] * 7 +
+                           [ctypes.POINTER(Options), c_void_p, c_void_p, c_void_p, c_void_p]),
     "abdf_rates": (ctypes.c_int, [c_void_p, ctypes.c_int64] + [c_void_p] * 6 + [c_void_p]),
     "abdf_phys_gradient": (ctypes.c_int, [c_void_p, ctypes.c_int64] + [c_void_p] * 7 + [c_void_p]),
     "abdf_rhs": (ctypes.c_int, [c_void_p, ctypes.c_int64, c_void_p, c_void_p, c_void_p, c_void_p]),

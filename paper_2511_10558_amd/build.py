@@ -7,7 +7,7 @@ from concurrent.futures import ThreadPoolExecutor
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 SOURCES = ["csrc/kernels.hip", "csrc/engine.cpp", "csrc/network.cpp", "csrc/server.cpp", "csrc/adjoint.cpp",
-           "csrc/abi.cpp"]
+           "csrc/abi.cpp", "csrc/noalloc.hip"]
 FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-pthread",
     # keep the compiler from forming packed FP32 instructions

@@ -18,6 +18,7 @@
 #include "network.hpp"
 #include "server.hpp"
 #include "adjoint.hpp"
+#include "noalloc.hpp"
 
 struct abdf_network {
     abdf::HostNetwork host;
@@ -200,6 +201,61 @@ abdf_status abdf_solve(const abdf_network *net, int64_t n_cells, const double *T
     } catch (const std::exception &e) {
         return fail(ABDF_E_DEVICE, e.what());
     }
+}
+
+abdf_status abdf_solve_noalloc(const abdf_network *net, int64_t n_cells, const double *T, const double *n_H,
+                               const double *A_V, const double *zeta, const double *G0, const double *x0,
+                               const double *t_end, const abdf_options *opt, double *x_out, int32_t *cell_status,
+                               abdf_cell_stats *stats, void *stream) {
+    if (!net) return fail(ABDF_E_ARG, "null network");
+    if (n_cells < 0 || n_cells > INT32_MAX) return fail(ABDF_E_ARG, "n_cells out of range");
+    abdf_options o;
+    if (opt) o = *opt; else abdf_options_default(&o);
+    abdf_status rc = check_opts(o);
+    if (rc != ABDF_OK) return rc;
+    if (n_cells == 0) return ok();
+    CHECK_DEV(T, "T");
+    CHECK_DEV(n_H, "n_H");
+    CHECK_DEV(A_V, "A_V");
+    CHECK_DEV(zeta, "zeta");
+    CHECK_DEV(G0, "G0");
+    CHECK_DEV(x0, "x0");
+    CHECK_DEV(t_end, "t_end");
+    CHECK_DEV(x_out, "x_out");
+    CHECK_DEV(cell_status, "cell_status");
+    if (stats) CHECK_DEV(stats, "stats");
+    int dev = 0;
+    HIP_OR_FAIL(hipGetDevice(&dev));
+    const abdf::DeviceNet *dn = net->host.device_tables_present(dev);
+    if (!dn)
+        return fail(ABDF_E_ARG, "the network's tables are not on this device yet (they are uploaded by the first "
+                                "call of any other solving entry point with this network on this device)");
+    std::string err;
+    void *scratch = nullptr;
+    abdf::HostBuffers hb{};
+    int r = abdf::noalloc_workspace(dev, &scratch, &hb, err);
+    if (r != ABDF_OK) return fail(static_cast<abdf_status>(r), err);
+    // as many slots as the scratch array, its host buffers and the budget hold
+    const size_t cap = o.hbm_budget_bytes > 0 ? std::min<size_t>(o.hbm_budget_bytes, abdf::kNoAllocScratchBytes)
+                                              : abdf::kNoAllocScratchBytes;
+    long long nslots = std::min<long long>(n_cells, hb.max_slots);
+    const size_t per = abdf::Engine::bytes_per_slot(*dn, o.precision);
+    nslots = std::min<long long>(nslots, (long long)(cap / per) + 1);
+    while (nslots > 0 && abdf::Engine::workspace_bytes(*dn, nslots) > cap) --nslots;
+    if (nslots < 1)
+        return fail(ABDF_E_BUDGET, "one cell of this network needs " +
+                                       std::to_string(abdf::Engine::workspace_bytes(*dn, 1)) +
+                                       " bytes of workspace, more than the " + std::to_string(cap) +
+                                       " bytes the no-allocation entry point may use");
+    abdf::Engine eng(net->host, *dn, o.precision, o.max_steps);
+    r = eng.set_options(o, err, hb.atol);
+    if (r != ABDF_OK) return fail(static_cast<abdf_status>(r), err);
+    r = eng.init_external(int(nslots), scratch, cap, hb, err);
+    if (r != ABDF_OK) return fail(static_cast<abdf_status>(r), err);
+    abdf::BatchIO io{n_cells, T, n_H, A_V, zeta, G0, x0, t_end, x_out, cell_status, stats};
+    r = eng.solve(io, o, static_cast<hipStream_t>(stream), err);
+    if (r != ABDF_OK) return fail(static_cast<abdf_status>(r), err);
+    return ok();
 }
 
 namespace {

@@ -66,7 +66,7 @@ void Profiler::read(int64_t *launches, double *ms, bool reset) {
 }
 
 hipEvent_t Engine::timer_begin(hipStream_t st) {
-    if (!Profiler::on()) return nullptr;
+    if (ext_ || !Profiler::on()) return nullptr;
     hipEvent_t e = nullptr;
     if (!event_pool_.empty()) {
         e = event_pool_.back();
@@ -115,6 +115,7 @@ Engine::~Engine() {
         event_pool_.push_back(p.b);
     }
     for (hipEvent_t e : event_pool_) (void)hipEventDestroy(e);
+    if (ext_) return;   // nothing below was allocated
     if (base_) {
         if (cached_)
             net_.keep_workspace(dn_.device, base_, base_bytes_);
@@ -302,6 +303,27 @@ int Engine::init(int nslots, std::string &err, bool cache_workspace) {
     return ABDF_OK;
 }
 
+int Engine::init_external(int nslots, void *base, size_t bytes, const HostBuffers &hb, std::string &err) {
+    ext_ = true;
+    if (nslots < 1 || nslots > hb.max_slots || workspace_bytes(dn_, nslots) > bytes) {
+        err = "slot count beyond the external workspace";
+        return ABDF_E_ARG;
+    }
+    base_ = base;
+    base_bytes_ = bytes;
+    free_ = hb.free_list;
+    h_cnt_ = hb.cnt;
+    h_fin_ = hb.fin;
+    h_admit_slots_ = hb.admit_slots;
+    h_admit_cells_ = hb.admit_cells;
+    return layout(nslots, base, err);
+}
+
+int Engine::reset_counts(hipStream_t st, std::string &err) {
+    HIP_TRY(launch_fill_i32(s_.cnt, 0, kCountSlots, st));
+    return ABDF_OK;
+}
+
 double Engine::newton_tolerance(const abdf_options &opt) {
     return opt.newton_tol > 0 ? opt.newton_tol
                               : std::max(10.0 * kURound / opt.rtol, std::min(0.03, std::sqrt(opt.rtol)));
@@ -368,7 +390,7 @@ constexpr int kSplitMinSlots = 32;
 int Engine::attempt(hipStream_t st, std::string &err) {
     if (bound_ <= 0) return ABDF_OK;
     TraceRange tr("abdf attempt");
-    if (bound_ < kSplitMinSlots) {
+    if (bound_ < kSplitMinSlots || !side_) {
         // a handful of cells: launch latency dominates, one stream
         hipEvent_t t0 = timer_begin(st);
         HIP_TRY(launch_factor(s_, dn_, ring_, std::min(bound_, grid_factor_max_),
@@ -436,6 +458,11 @@ int Engine::solve(const BatchIO &io, const abdf_options &opt, hipStream_t st, st
     ring_ = 0;
     bound_ = 0;
     long long next = 0;
+    if (ext_) {
+        // the external workspace keeps the previous call's contents
+        int rc0 = reset_counts(st, err);
+        if (rc0 != ABDF_OK) return rc0;
+    }
     const int check_every = std::max(1, opt.check_every);
     int rc = admit(io, opt, next, st, err);
     if (rc != ABDF_OK) return rc;

@@ -35,6 +35,17 @@ struct AdjIO {
     double *dphi;             // [n][5] gradient with respect to T, n_H, A_V, zeta, G0, or null
 };
 
+// Host buffers of an engine that allocates nothing itself: the caller keeps
+// them (static storage) and they hold up to max_slots slots.
+struct HostBuffers {
+    int32_t *cnt;            // [kCountSlots]
+    int32_t *fin;            // [max_slots]
+    int32_t *admit_slots;    // [max_slots]
+    long long *admit_cells;  // [max_slots]
+    int32_t *free_list;      // [max_slots]
+    double *atol;            // [kMaxSpecies] per-species absolute tolerances
+    int max_slots;
+};
 constexpr int kMaxSpecies = 512;   // the factorisation holds at most this order
 
 // Process-wide kernel timers (abdf_profile_*).
@@ -56,6 +67,11 @@ class Engine {
     // cache_workspace the device workspace is taken from the network's cache
     // on this device when large enough and returned to it by the destructor.
     int init(int nslots, std::string &err, bool cache_workspace = false);
+    // Lays out `nslots` slots in caller-provided device memory (`bytes` at
+    // `base`) with the host buffers `hb`, allocating nothing: no side stream,
+    // no events, no kernel timers; the counters are cleared by a kernel on the
+    // solve's stream.  Returns an abdf_status.
+    int init_external(int nslots, void *base, size_t bytes, const HostBuffers &hb, std::string &err);
     // Device bytes of the workspace of n slots (as init lays it out).
     static size_t workspace_bytes(const DeviceNet &dn, long long n);
     // relative change of c within which a slot keeps its factorisation (0: none)
@@ -125,9 +141,11 @@ class Engine {
     std::vector<double> atol_store_;   // per-species absolute tolerances when the engine owns them
     const double *atol_sp_ = nullptr;  // host copy of the per-species tolerances, or null (scalar atol)
     Slots s_{};
+    bool ext_ = false;                 // workspace and host buffers belong to the caller
     bool cached_ = false;              // the workspace goes back to the network's cache
     void *base_ = nullptr;
     size_t base_bytes_ = 0;
+    int reset_counts(hipStream_t st, std::string &err);
     int layout(int nslots, void *base, std::string &err);
     int32_t *d_admit_slots_ = nullptr;
     long long *d_admit_cells_ = nullptr;

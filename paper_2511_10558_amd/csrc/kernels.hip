@@ -1280,7 +1280,19 @@ __global__ void k_selftest(int *bad) {
     atomicAdd(bad, nb);
 }
 
+// v[0..n) = value (counters cleared by a kernel rather than a memset node)
+__global__ void k_fill_i32(int32_t *v, int32_t value, int n) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) v[i] = value;
+}
+
 // ------------------------------------------------------------- launchers --
+
+hipError_t launch_fill_i32(int32_t *v, int32_t value, int n, hipStream_t st) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_i32, dim3((n + 255) / 256), dim3(256), 0, st, v, value, n);
+    return hipGetLastError();
+}
 
 size_t lu_work_lds(int NP, int prec) {
     return prec == ABDF_PREC_FP32_LU ? lu2_lds_bytes<float>(NP) : lu2_lds_bytes<double>(NP);

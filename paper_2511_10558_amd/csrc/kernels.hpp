@@ -113,6 +113,7 @@ size_t lu_bytes(int NP, int prec);
 // solve (4) kernel.
 int resident_per_cu(int which, int prec, size_t lds);
 hipError_t launch_selftest(int *bad, hipStream_t st);
+hipError_t launch_fill_i32(int32_t *v, int32_t value, int n, hipStream_t st);
 size_t lu_work_lds(int NP, int prec);
 
 // Largest dynamic LDS one workgroup may use on the device.
