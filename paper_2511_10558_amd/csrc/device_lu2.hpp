@@ -20,9 +20,17 @@
 //     block column, staged through LDS), then the rows below block i are
 //     updated C -= L_{:,i} U_ij on the matrix cores, L read from memory;
 //  3. the panel (rows >= 64j) is factored in 16-column sub-panels, one thread
-//     per row: arg-max pivot search (ties to the smaller logical row, as
+//     per row.  First on the diagonal: one wave factors the sub-panel's 16 x 16
+//     diagonal block without row exchanges (lane k holds row k, the pivot row
+//     broadcast from its lane), then every other row eliminates against those
+//     U rows with no exchange between waves; this is accepted when every
+//     multiplier of the sub-panel is at most kPivotThreshold in magnitude
+//     (threshold pivoting, u = 1 / kPivotThreshold: the diagonal entry is at
+//     least u times the largest candidate of its column).  Otherwise the
+//     sub-panel is factored again from its saved entries with partial
+//     pivoting: arg-max pivot search (ties to the smaller logical row, as
 //     LAPACK's idamax), scaling and rank-1 update; rows keep their positions
-//     and only their logical labels change; after each sub-panel the rest of
+//     and only their logical labels change.  After each sub-panel the rest of
 //     the block column is updated on the matrix cores;
 //  4. the inverses of the diagonal block's triangles are formed and stored,
 //     and the block column is written back through perm.
@@ -35,6 +43,11 @@ namespace abdf {
 
 constexpr int kLuW = 64;          // block-column width
 constexpr int kLuMaxNP = 512;     // one thread per row in the panel
+// Largest multiplier with which a sub-panel keeps its diagonal pivots.  On the
+// Newton matrices I - c J of the chemistry networks fewer than 1% of the
+// sub-panels exceed it (at large c, late in an integration); the factors'
+// backward error stays at the level of partial pivoting there.
+constexpr double kPivotThreshold = 4.0;
 
 // Workgroup shape of the factorisation per element type.  FP64: 8 waves of
 // 256 VGPRs, each wave holding four row tiles of the block column.  FP32: 16
@@ -90,7 +103,9 @@ __host__ __device__ constexpr size_t lu2_lds_bytes(int NP) {
     return 5 * size_t(NP) * sizeof(int32_t)                        // perm, sto, pos_log, log_pos, pidx
            + kLuW * sizeof(int32_t)                                // piv_pos
            + 2 * lu_waves<T> * (sizeof(double) + sizeof(int32_t))     // arg-max partials, double-buffered
-           + 2 * lu_waves<T> * kCrowLd * sizeof(T) + 16               // candidate pivot rows, double-buffered
+           + 16 + 18 * sizeof(int32_t)                                // row flags; diagonal positions, flag
+           + 2 * lu_waves<T> * kCrowLd * sizeof(T)                    // candidate pivot rows, double-buffered
+           + 16 * kCrowLd * sizeof(T)                                 // factored diagonal block
            + lu2_work_elems<T>(NP) * sizeof(T) + 64;
 }
 
@@ -239,8 +254,11 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
     int32_t *redi = reinterpret_cast<int32_t *>(redv + 2 * lu_waves<T>);
     int32_t *rwave = redi + 2 * lu_waves<T>;                        // [2] wave holding logical row r;
                                                                  // [2] first zero pivot (1-based) or INT_MAX
-    T *crow = reinterpret_cast<T *>(rwave + 4);                  // [2][waves][kCrowLd] candidate rows
-    T *work = crow + 2 * lu_waves<T> * kCrowLd;
+    int32_t *dpos = rwave + 4;                                   // [16] positions of the diagonal pivot rows
+    int32_t *spec_bad = dpos + 16;                               // [2] the diagonal pivots were refused
+    T *crow = reinterpret_cast<T *>(dpos + 18);                  // [2][waves][kCrowLd] candidate rows
+    T *Db = crow + 2 * lu_waves<T> * kCrowLd;                    // [16][kCrowLd] factored diagonal block
+    T *work = Db + 16 * kCrowLd;
     T *Cb = work;                                          // [64][kLdb]   (left-looking, inverses)
     T *Ub = Cb + kLuW * kLdb;                              // [64][kLdb]
     T *Xb = Ub + kLuW * kLdb;                              // [64][kLdb]
@@ -248,6 +266,7 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
     T *U12 = P + size_t(NP) * kPanLd;                      // [16][kU12Ld]
 
     for (int i = tid; i < NP; i += lu_threads<T>) perm[i] = i;
+    if (tid < 16) dpos[tid] = 0;      // every position read from it stays in the panel
     if (tid == 0) rwave[2] = 0x7fffffff;
     __syncthreads();
 
@@ -353,35 +372,152 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
         //    positions; pivoting assigns logical rows to positions.
 #pragma unroll 1
         for (int sp = 0; sp < CTj; ++sp) {
-            // (a) the sub-panel's column tile to LDS, one row per position
+            // (a) the sub-panel's column tile to LDS, one row per position (the
+            //     accumulators keep it until (c), so it can be written again)
+            auto panel_to_lds = [&]() {
 #pragma unroll
-            for (int s = 0; s < lu_slots<T>; ++s) {
-                const int rt = wave + lu_waves<T> * s;
-                if (rt >= 4 * j && rt < RT)
+                for (int s = 0; s < lu_slots<T>; ++s) {
+                    const int rt = wave + lu_waves<T> * s;
+                    if (rt >= 4 * j && rt < RT)
 #pragma unroll
-                    for (int v = 0; v < 4; ++v) {
-                        T val = acc[s][0][v];
+                        for (int v = 0; v < 4; ++v) {
+                            T val = acc[s][0][v];
 #pragma unroll
-                        for (int ct = 1; ct < 4; ++ct)
-                            if (ct == sp) val = acc[s][ct][v];
-                        P[(16 * rt + M::row(lane, v)) * kPanLd + lc] = val;
-                    }
-            }
-            __syncthreads();
+                            for (int ct = 1; ct < 4; ++ct)
+                                if (ct == sp) val = acc[s][ct][v];
+                            P[(16 * rt + M::row(lane, v)) * kPanLd + lc] = val;
+                        }
+                }
+            };
+            panel_to_lds();
             // (b) one thread per position factors the 16 columns.  Each
-            //     thread knows the logical row of its position (mylog); the
-            //     winner of the pivot search among a wave's lanes publishes
-            //     its row, so one barrier per column suffices.
+            //     thread knows the logical row of its position (mylog).
             const int q = tid;
             bool active = q >= c0 && q < NP && pidx[q] < 0;
             const bool participated = active;
-            // a wave without unpivoted rows only takes part in the barriers
+            int mylog = active ? pos_log[q] : 0x7fffffff;
+            // (b1) diagonal pivots: the rows of logical index rb .. rb + 15
+            const int rb = c0 + 16 * sp;
+            const bool is_diag = active && mylog >= rb && mylog < rb + 16;
+            if (tid == 0) spec_bad[0] = 0;
+            if (is_diag) dpos[mylog - rb] = q;
+            __syncthreads();
+            if (wave == 0) {
+                // the 16 x 16 diagonal block in Db, lane l holding entries
+                // (i, j) = (l / 4 + 16 t / 4 ... ) of rows i = 4 t + l / 16 and
+                // column j = l % 16 (t = 0..3); column c: every entry below
+                // row c takes its multiplier or its update from row c, then
+                // the wave's writes complete before the next column reads
+                const int jj = lane & 15;
+#pragma unroll
+                for (int t = 0; t < 4; ++t) {
+                    const int i = 4 * t + (lane >> 4);
+                    Db[i * kCrowLd + jj] = P[dpos[i] * kPanLd + jj];
+                }
+                bool bad = false;
+#pragma unroll
+                for (int c = 0; c < 16; ++c) {
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                    // a pivot below the smallest normal number refuses the diagonal
+                    // (partial pivoting then forms such multipliers by division)
+                    const T piv = Db[c * kCrowLd + c];
+                    const bool normal = fabs(piv) >= std::numeric_limits<T>::min();
+                    const T rinv = T(1) / (normal ? piv : T(1));
+                    const T ucj = Db[c * kCrowLd + jj];
+                    T a[4], l[4];
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const int i = 4 * t + (lane >> 4);
+                        a[t] = Db[i * kCrowLd + jj];
+                        l[t] = Db[i * kCrowLd + c] * rinv;
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                    __builtin_amdgcn_wave_barrier();
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                    bad |= !normal;
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) {
+                        const int i = 4 * t + (lane >> 4);
+                        if (i > c) {
+                            if (jj == c) {
+                                bad |= !(fabs(l[t]) <= T(kPivotThreshold));
+                                Db[i * kCrowLd + jj] = l[t];
+                            } else if (jj > c) {
+                                Db[i * kCrowLd + jj] = a[t] - l[t] * ucj;
+                            }
+                        }
+                    }
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                if (lane < 16) Db[lane * kCrowLd + 16] = T(1) / Db[lane * kCrowLd + lane];   // used only when every pivot is normal
+                if (__ballot(bad) != 0 && lane == 0) spec_bad[0] = 1;
+            }
+            __syncthreads();
+            // (b2) every other unpivoted row against the diagonal block's U
+            //      rows (the elimination of the partial-pivoting loop below
+            //      with its pivots fixed, so no exchange between waves), the
+            //      result written over the row in LDS; the diagonal rows take
+            //      their factored entries
+            {
+                bool bad = false;
+                if (active && !is_diag) {
+                    T x[16];
+#pragma unroll
+                    for (int c = 0; c < 16; ++c) x[c] = P[q * kPanLd + c];
+#pragma unroll
+                    for (int c = 0; c < 16; ++c) {
+                        const T *urow = Db + c * kCrowLd;
+                        const T l = x[c] * urow[16];
+                        bad |= !(fabs(l) <= T(kPivotThreshold));
+                        x[c] = l;
+#pragma unroll
+                        for (int cb = c + 1; cb < 16; cb += 4) {
+                            T uv[4];
+#pragma unroll
+                            for (int u = 0; u < 4; ++u)
+                                if (cb + u < 16) uv[u] = urow[cb + u];
+#pragma unroll
+                            for (int u = 0; u < 4; ++u)
+                                if (cb + u < 16) x[cb + u] -= l * uv[u];
+                        }
+                        // the U rows are the same for every row: keep the
+                        // scheduler from hoisting all their loads at once
+                        __builtin_amdgcn_sched_barrier(0);
+                    }
+#pragma unroll
+                    for (int c = 0; c < 16; ++c) P[q * kPanLd + c] = x[c];
+                } else if (is_diag) {
+                    const int k = mylog - rb;
+#pragma unroll
+                    for (int c = 0; c < 16; ++c) P[q * kPanLd + c] = Db[k * kCrowLd + c];
+                }
+                if (__ballot(bad) != 0 && lane == 0) spec_bad[0] = 1;
+            }
+            __syncthreads();
+            if (spec_bad[0] == 0) {
+                // accepted: the diagonal rows are the pivots, labels unchanged
+                if (is_diag) {
+                    pidx[q] = 16 * sp + (mylog - rb);
+                    piv_pos[16 * sp + (mylog - rb)] = q;
+                }
+                __syncthreads();
+            } else {
+            // (b3) refused: the sub-panel again from the accumulators, with
+            //      partial pivoting.  The winner of the pivot search among a
+            //      wave's lanes publishes its row, so one barrier per column
+            //      suffices.  A wave without unpivoted rows only takes part in
+            //      the barriers.
+            panel_to_lds();
+            __syncthreads();
             const bool busy = __ballot(active) != 0;
             if (!busy && lane == 0) {
                 redv[wave] = -1.0;
                 redv[lu_waves<T> + wave] = -1.0;
             }
-            int mylog = active ? pos_log[q] : 0x7fffffff;
             T x[16];
 #pragma unroll
             for (int c = 0; c < 16; ++c) x[c] = active ? P[q * kPanLd + c] : T(0);
@@ -483,6 +619,7 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
                 pos_log[q] = mylog;
             }
             __syncthreads();
+            }   // partial pivoting
             // (c) back to the accumulators
 #pragma unroll
             for (int s = 0; s < lu_slots<T>; ++s) {
@@ -556,6 +693,9 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
                 __syncthreads();
             }
         }
+        // the last sub-panel's rows are read back from P before the staging
+        // buffer below (which shares P's memory) is written
+        __syncthreads();
         for (int q2 = tid; q2 < NP; q2 += lu_threads<T>)
             if (q2 >= c0) perm[pos_log[q2]] = sto[q2];
         // 4. diagonal block (logical rows c0 .. c0 + Wj - 1) to LDS, its
