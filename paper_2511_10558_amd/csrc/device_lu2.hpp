@@ -109,6 +109,15 @@ __host__ __device__ constexpr size_t lu2_lds_bytes(int NP) {
            + lu2_work_elems<T>(NP) * sizeof(T) + 64;
 }
 
+// Orders one wave's LDS accesses before and after this point as written: the
+// LDS executes a wave's instructions in issue order, so a value one lane
+// writes is seen by every lane of the wave that reads it later; only the
+// compiler must be kept from moving the accesses (no instruction is emitted).
+__device__ __forceinline__ void wave_lds_order() {
+    __builtin_amdgcn_wave_barrier();
+    asm volatile("" ::: "memory");
+}
+
 // Elements of the per-matrix inverse diagonal blocks.
 template <typename T>
 __host__ __device__ constexpr size_t lu2_dinv_elems(int NP) {
@@ -403,11 +412,10 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
             if (is_diag) dpos[mylog - rb] = q;
             __syncthreads();
             if (wave == 0) {
-                // the 16 x 16 diagonal block in Db, lane l holding entries
-                // (i, j) = (l / 4 + 16 t / 4 ... ) of rows i = 4 t + l / 16 and
-                // column j = l % 16 (t = 0..3); column c: every entry below
-                // row c takes its multiplier or its update from row c, then
-                // the wave's writes complete before the next column reads
+                // the 16 x 16 diagonal block in Db, lane l holding the entries
+                // of rows i = 4 t + l / 16 (t = 0..3) in column j = l % 16;
+                // column c: every entry below row c takes its multiplier or
+                // its update from row c, read before any lane writes
                 const int jj = lane & 15;
 #pragma unroll
                 for (int t = 0; t < 4; ++t) {
@@ -417,9 +425,7 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
                 bool bad = false;
 #pragma unroll
                 for (int c = 0; c < 16; ++c) {
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                    wave_lds_order();
                     // a pivot below the smallest normal number refuses the diagonal
                     // (partial pivoting then forms such multipliers by division)
                     const T piv = Db[c * kCrowLd + c];
@@ -433,9 +439,7 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
                         a[t] = Db[i * kCrowLd + jj];
                         l[t] = Db[i * kCrowLd + c] * rinv;
                     }
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                    __builtin_amdgcn_wave_barrier();
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                    wave_lds_order();
                     bad |= !normal;
 #pragma unroll
                     for (int t = 0; t < 4; ++t) {
@@ -450,9 +454,7 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
                         }
                     }
                 }
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
-                __builtin_amdgcn_wave_barrier();
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+                wave_lds_order();
                 if (lane < 16) Db[lane * kCrowLd + 16] = T(1) / Db[lane * kCrowLd + lane];   // used only when every pivot is normal
                 if (__ballot(bad) != 0 && lane == 0) spec_bad[0] = 1;
             }
