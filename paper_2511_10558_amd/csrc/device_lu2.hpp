@@ -290,28 +290,38 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
             pidx[q] = -1;
         }
         acc_t acc[lu_slots<T>][4];
-        // 1. gather the block column (positions = logical rows at this point),
-        //    a row tile at a time: its 16 handles, then its 16 values.  Tiles
-        //    outside the matrix read column c0 + lc of row 0 and are zeroed.
+        // 1. gather the block column (positions = logical rows at this point):
+        //    every row tile's 16 handles first, then all values, so that each
+        //    lane has all its index loads in flight together and then all its
+        //    value loads (the accumulators are not live yet).  Tiles outside
+        //    the matrix read column c0 + lc of row 0 and are zeroed.
+        {
+            int32_t hnd[lu_slots<T>][4][4];
+            int srow[lu_slots<T>][4];
 #pragma unroll
-        for (int s = 0; s < lu_slots<T>; ++s) {
-            const int rt = wave + lu_waves<T> * s;
-            int32_t hnd[4][4];
-            int srow[4];
+            for (int s = 0; s < lu_slots<T>; ++s) {
+                const int rt = wave + lu_waves<T> * s;
 #pragma unroll
-            for (int v = 0; v < 4; ++v) srow[v] = rt < RT ? perm[16 * rt + M::row(lane, v)] : 0;
+                for (int v = 0; v < 4; ++v) srow[s][v] = rt < RT ? perm[16 * rt + M::row(lane, v)] : 0;
+            }
 #pragma unroll
-            for (int ct = 0; ct < 4; ++ct)
+            for (int s = 0; s < lu_slots<T>; ++s)
 #pragma unroll
-                for (int v = 0; v < 4; ++v)
-                    hnd[ct][v] = src.handle(srow[v], c0 + 16 * (ct < CTj ? ct : 0) + lc);
+                for (int ct = 0; ct < 4; ++ct)
 #pragma unroll
-            for (int ct = 0; ct < 4; ++ct)
+                    for (int v = 0; v < 4; ++v)
+                        hnd[s][ct][v] = src.handle(srow[s][v], c0 + 16 * (ct < CTj ? ct : 0) + lc);
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const T val = src.value(hnd[ct][v], srow[v], c0 + 16 * ct + lc);
-                    acc[s][ct][v] = (rt < RT && ct < CTj) ? val : T(0);
-                }
+            for (int s = 0; s < lu_slots<T>; ++s) {
+                const int rt = wave + lu_waves<T> * s;
+#pragma unroll
+                for (int ct = 0; ct < 4; ++ct)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const T val = src.value(hnd[s][ct][v], srow[s][v], c0 + 16 * ct + lc);
+                        acc[s][ct][v] = (rt < RT && ct < CTj) ? val : T(0);
+                    }
+            }
         }
         // 2. updates from the earlier block columns
         for (int i = 0; i < j; ++i) {
@@ -330,35 +340,43 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
             }
             __syncthreads();
             const T *Li = dinv + size_t(i) * 2 * kLuW * kLuW;   // inverse of the unit-lower block i
+            {
+                // the 16 tiles of U_ij = inv(L_ii) C_i, spread over all waves
+                constexpr int TPW = 16 / lu_waves<T>;
+                const int t0 = wave * TPW, tr = t0 >> 2;
+                v4 a[4];
+#pragma unroll
+                for (int kk = 0; kk < 4; ++kk)
+                    a[kk] = *reinterpret_cast<const v4 *>(Li + (16 * tr + lc) * kLuW + 16 * kk + 4 * g);
+#pragma unroll
+                for (int k = 0; k < TPW; ++k) {
+                    const int ct = (t0 + k) & 3;
+                    if (ct < CTj) {
+                        acc_t u = acc_t{0, 0, 0, 0};
+#pragma unroll
+                        for (int kk = 0; kk < 4; ++kk)
+#pragma unroll
+                            for (int e = 0; e < 4; ++e)
+                                u = M::mma(a[kk][e], Cb[(16 * kk + 4 * g + e) * kLdb + 16 * ct + lc], u);
+#pragma unroll
+                        for (int v = 0; v < 4; ++v) Ub[(16 * tr + M::row(lane, v)) * kLdb + 16 * ct + lc] = u[v];
+                    }
+                }
+            }
+            __syncthreads();
+            // the rows of block i take their tiles of U_ij; the rows below are
+            // updated C -= L_{:,i} U_ij
 #pragma unroll
             for (int s = 0; s < lu_slots<T>; ++s) {
                 const int rt = wave + lu_waves<T> * s;
                 if (rt >= 4 * i && rt < 4 * i + 4) {
                     const int tr = rt - 4 * i;
-                    v4 a[4];
 #pragma unroll
-                    for (int kk = 0; kk < 4; ++kk)
-                        a[kk] = *reinterpret_cast<const v4 *>(Li + (16 * tr + lc) * kLuW + 16 * kk + 4 * g);
+                    for (int ct = 0; ct < 4; ++ct)
+                        if (ct < CTj)
 #pragma unroll
-                    for (int ct = 0; ct < 4; ++ct) {
-                        if (ct < CTj) {
-                            acc_t u = acc_t{0, 0, 0, 0};
-#pragma unroll
-                            for (int kk = 0; kk < 4; ++kk)
-#pragma unroll
-                                for (int e = 0; e < 4; ++e)
-                                    u = M::mma(a[kk][e], Cb[(16 * kk + 4 * g + e) * kLdb + 16 * ct + lc], u);
-                            acc[s][ct] = u;
-#pragma unroll
-                            for (int v = 0; v < 4; ++v) Ub[(16 * tr + M::row(lane, v)) * kLdb + 16 * ct + lc] = u[v];
-                        }
-                    }
+                            for (int v = 0; v < 4; ++v) acc[s][ct][v] = Ub[(16 * tr + M::row(lane, v)) * kLdb + 16 * ct + lc];
                 }
-            }
-            __syncthreads();
-#pragma unroll
-            for (int s = 0; s < lu_slots<T>; ++s) {
-                const int rt = wave + lu_waves<T> * s;
                 if (rt >= 4 * (i + 1) && rt < RT) {
                     const T *Lrow = A + size_t(perm[16 * rt + lc]) * NP + r0;
                     v4 a[4];
