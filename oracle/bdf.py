@@ -92,8 +92,10 @@ def wrms(v, scale):
     return float(np.sqrt(np.mean(np.abs(v / scale) ** 2)))
 
 
-def initial_step(f, x0, f0, t_span, rtol, atol):
-    """Starting step of Hairer, Norsett & Wanner (Solving ODEs I, Sec. II.4) for order 1."""
+def initial_step(f, x0, f0, t_span, rtol, atol, ft=None):
+    """Starting step of Hairer, Norsett & Wanner (Solving ODEs I, Sec. II.4) for order 1.
+    ft(t, x), if given, is the right-hand side at time t (for the trial
+    evaluation at t = h0); otherwise f(x)."""
     scale = atol + rtol * np.abs(x0)
     d0 = wrms(x0, scale)
     d1 = wrms(f0, scale)
@@ -102,7 +104,7 @@ def initial_step(f, x0, f0, t_span, rtol, atol):
     else:
         h0 = 0.01 * d0 / d1
     h0 = min(h0, t_span)
-    f1 = f(x0 + h0 * f0)
+    f1 = ft(h0, x0 + h0 * f0) if ft is not None else f(x0 + h0 * f0)
     d2 = wrms(f1 - f0, scale) / h0
     if max(d1, d2) <= 1e-15:
         h1 = max(1e-6, h0 * 1e-3)
@@ -172,6 +174,12 @@ def solve(chem, x0, t_end, rtol=1e-6, atol=1e-20, max_steps=100000,
           newton_tol=None, record=False, max_order=MAX_ORDER, h0=0.0, h_max=0.0) -> Result:
     """Integrate dx/dt = f(x) from t = 0 to t_end with adaptive order and step.
 
+    chem provides f and jac; if it also provides at(t), the rate
+    coefficients depend on time: every step attempt from t to t + h uses those
+    at t + h (the corrector equation is evaluated there), the Jacobian is taken
+    at the attempt where it is refreshed, and the starting step's trial
+    evaluation at t = h0.
+
     atol is a scalar or one absolute tolerance per species.  max_order
     (1..5) caps the order the order selection may reach; 1 leaves
     the implicit Euler method under the same error and step control.  h0 > 0
@@ -182,6 +190,8 @@ def solve(chem, x0, t_end, rtol=1e-6, atol=1e-20, max_steps=100000,
     x0 = np.asarray(x0, dtype=float)
     S = x0.shape[0]
     stats = Stats()
+    at = getattr(chem, "at", None)
+    chem_at = at if at is not None else (lambda t: chem)
     hist = [] if record else None
     atol = np.asarray(atol, dtype=float) if np.ndim(atol) else float(atol)
     if not (np.all(np.isfinite(x0)) and np.isfinite(t_end) and t_end >= 0 and rtol > 0
@@ -190,12 +200,14 @@ def solve(chem, x0, t_end, rtol=1e-6, atol=1e-20, max_steps=100000,
     if t_end == 0.0:
         return Result(x0.copy(), OK, 0.0, stats, hist)
     tol = newton_tolerance(rtol) if newton_tol is None else newton_tol
-    f0 = chem.f(x0)
+    ch0 = chem_at(0.0)
+    f0 = ch0.f(x0)
     stats.n_rhs += 1
     if not np.all(np.isfinite(f0)):
         # rates overflow at the initial state: no step can be taken
         return Result(x0.copy(), NONFINITE, 0.0, stats, hist)
-    h = initial_step(chem.f, x0, f0, t_end, rtol, atol)
+    h = initial_step(ch0.f, x0, f0, t_end, rtol, atol,
+                     ft=(lambda t, y: chem_at(t).f(y)) if at is not None else None)
     stats.n_rhs += 1
     if h0 > 0.0:
         h = min(h0, t_end)
@@ -207,7 +219,7 @@ def solve(chem, x0, t_end, rtol=1e-6, atol=1e-20, max_steps=100000,
     q = 1
     n_equal = 0
     t = 0.0
-    J = chem.jac(x0)
+    J = ch0.jac(x0)
     stats.n_jac += 1
     j_fresh = True
     lu, c_lu = None, None
@@ -238,16 +250,17 @@ def solve(chem, x0, t_end, rtol=1e-6, atol=1e-20, max_steps=100000,
             psi = psi + GAMMA[j] * D[j]
         psi = psi / GAMMA[q]
         c = h / GAMMA[q]
+        ch = chem_at(t + h)
         if lu is None or c != c_lu:
             lu = sla.lu_factor(I - c * J)
             c_lu = c
             stats.n_lu += 1
         scale = atol + rtol * np.abs(x_p)
-        converged, m, x_new, d = _newton(chem, lu, c, psi, x_p, scale, tol, stats)
+        converged, m, x_new, d = _newton(ch, lu, c, psi, x_p, scale, tol, stats)
         if not converged:
             stats.n_newton_fail += 1
             if not j_fresh:
-                J = chem.jac(x_p)
+                J = ch.jac(x_p)
                 stats.n_jac += 1
                 j_fresh = True
                 lu = None

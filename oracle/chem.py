@@ -169,13 +169,13 @@ def rate_derivative(net, k, x) -> sp.csr_matrix:
 class Chemistry:
     """f(x) = nu . rate(x) and J(x) = nu . d rate / dx for one cell's coefficients."""
 
-    def __init__(self, net, k):
+    def __init__(self, net, k, nu=None):
         self.net = net
         # real coefficients in FP64 (or extended precision when given as
         # np.longdouble); complex ones are kept for complex-step derivatives
         k = np.asarray(k)
         self.k = k.astype(np.result_type(k.dtype, np.float64))
-        self.nu = stoichiometry(net)
+        self.nu = stoichiometry(net) if nu is None else nu
 
     def f(self, x) -> np.ndarray:
         return self.nu @ reaction_rates(self.net, self.k, x)
@@ -190,3 +190,30 @@ class Chemistry:
 
 def cell_chemistry(net, cell: dict) -> Chemistry:
     return Chemistry(net, rate_coefficients(net, **cell))
+
+
+class TrajectoryChemistry:
+    """A cell whose physical conditions change along a trajectory: an expanding
+    flow with phi_j(t) = phi_j(0) (1 + t / t_c)^(-p_j) for each of
+    phi = (T, n_H, A_V, zeta, G0).  A wind moving out at constant speed has
+    radius r = r0 (1 + t / t_c), density n_H ~ r^-2 and radial extinction
+    A_V ~ r^-1 (p = 2 and 1); the paper's outflow study (App. A) integrates the
+    chemistry along such trajectories.  t_c <= 0 keeps phi constant.  at(t) is
+    the Chemistry of the rate coefficients at time t (paper Sec. 2 and
+    App. B.1 rate laws at phi(t))."""
+
+    def __init__(self, net, cell: dict, t_c: float, exponents):
+        self.net = net
+        self.cell = dict(cell)
+        self.t_c = float(t_c)
+        self.p = np.asarray(exponents, dtype=float)
+        self.nu = stoichiometry(net)
+
+    def phi(self, t: float) -> dict:
+        if self.t_c <= 0.0:
+            return dict(self.cell)
+        s = 1.0 + t / self.t_c
+        return {name: self.cell[name] * s ** (-pj) for name, pj in zip(PHYS_PARAMS, self.p)}
+
+    def at(self, t: float) -> Chemistry:
+        return Chemistry(self.net, rate_coefficients(self.net, **self.phi(t)), nu=self.nu)

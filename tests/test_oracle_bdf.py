@@ -334,3 +334,77 @@ def test_rates_overflowing_at_the_initial_state_end_as_nonfinite():
     with np.errstate(over="ignore", invalid="ignore"):
         r = bdf.solve(ch, x0, 1e10, 1e-6, 1e-20)
     assert r.status == bdf.NONFINITE and r.t == 0.0 and np.array_equal(r.x, x0)
+
+
+def _expansion_integral(t, t_c, p):
+    """int_0^t (1 + s / t_c)^(-p) ds."""
+    if p == 1.0:
+        return t_c * np.log1p(t / t_c)
+    return t_c * ((1.0 + t / t_c) ** (1.0 - p) - 1.0) / (1.0 - p)
+
+
+@pytest.mark.parametrize("p", [0.5, 1.0, 1.5, 2.0])
+def test_decay_under_falling_ionisation_rate(p):
+    # A -> B by cosmic rays with zeta(t) = zeta0 (1 + t / t_c)^(-p):
+    # x_A(t) = exp(-alpha zeta0 int_0^t (1 + s / t_c)^(-p) ds)
+    net = tiny_nets.decay(2.0)
+    cell = dict(T=30.0, n_H=1e4, A_V=1.0, zeta=1.3e-17, G0=1.0)
+    k0 = 2.0 * cell["zeta"]
+    t_end = 3.0 / k0
+    t_c = 0.5 * t_end
+    ch = chem.TrajectoryChemistry(net, cell, t_c, [0.0, 0.0, 0.0, p, 0.0])
+    r = bdf.solve(ch, np.array([1.0, 0.0]), t_end, 1e-10, 1e-30)
+    want = np.exp(-k0 * _expansion_integral(t_end, t_c, p))
+    assert r.status == bdf.OK
+    np.testing.assert_allclose(r.x, [want, 1.0 - want], rtol=1e-7)
+
+
+def test_association_under_expanding_density():
+    # A + B -> C, two-body coefficient k n_H with n_H(t) = n_H0 (1 + t/t_c)^-2:
+    # for a0 = b0, 1/a - 1/a0 = k n_H0 int_0^t (1 + s/t_c)^-2 ds
+    net = tiny_nets.association(1e-9)
+    cell = dict(T=30.0, n_H=1e4, A_V=1.0, zeta=1.3e-17, G0=1.0)
+    kp = chem.rate_coefficients(net, **cell)[0]
+    a0 = 2e-4
+    t_end = 5.0 / (kp * a0)
+    t_c = 0.3 * t_end
+    ch = chem.TrajectoryChemistry(net, cell, t_c, [0.0, 2.0, 1.0, 0.0, 0.0])
+    r = bdf.solve(ch, np.array([a0, a0, 0.0]), t_end, 1e-10, 1e-30)
+    a = a0 / (1.0 + a0 * kp * _expansion_integral(t_end, t_c, 2.0))
+    assert r.status == bdf.OK
+    np.testing.assert_allclose(r.x, [a, a, a0 - a], rtol=1e-7)
+
+
+def test_constant_trajectory_is_the_autonomous_solve():
+    # t_c = 0 (and all exponents 0) leave the conditions constant: the same
+    # steps and the same result bit for bit as the autonomous solve
+    net = synth.network_for_config("small")
+    cells = synth.single_cell(net)
+    cell = cells.cell(0)
+    ref = bdf.solve(chem.cell_chemistry(net, cell), cells.x0[0], cells.t_end[0], 1e-6, 1e-20)
+    for t_c, p in ((0.0, [0.7, 2.0, 1.0, 0.0, 0.0]), (1e10, [0.0] * 5)):
+        r = bdf.solve(chem.TrajectoryChemistry(net, cell, t_c, p), cells.x0[0], cells.t_end[0], 1e-6, 1e-20)
+        assert np.array_equal(r.x, ref.x) and r.stats.n_steps == ref.stats.n_steps
+    tr = chem.TrajectoryChemistry(net, cell, 1e10, [0.7, 2.0, 1.0, 0.5, 0.0])
+    ph = tr.phi(1e10)
+    assert ph["T"] == pytest.approx(cell["T"] * 2 ** -0.7) and ph["n_H"] == pytest.approx(cell["n_H"] / 4)
+    assert ph["G0"] == cell["G0"] and tr.phi(0.0) == cell
+
+
+def test_initial_step_takes_the_trial_evaluation_at_h0():
+    # y' = lam(t) y with lam(t) = lam0 (1 + t / tau)^-2: the trial evaluation
+    # of the starting-step rule is f(h0, y0 + h0 f0) = lam(h0) (1 + h0 lam0) y0,
+    # so d2 = |lam(h0) (1 + h0 lam0) - lam0| d0 / h0 exactly (up to rounding)
+    y0 = np.array([1.0, 2.0, 3.0])
+    rtol, atol = 1e-3, 0.0
+    lam0, tau = -2e3, 1e-4
+    lam = lambda t: lam0 * (1.0 + t / tau) ** -2
+    sc = atol + rtol * np.abs(y0)
+    rms = lambda v: np.sqrt(np.mean((v / sc) ** 2))
+    d0, d1 = rms(y0), rms(lam0 * y0)
+    h0 = 0.01 * d0 / d1
+    d2 = abs(lam(h0) * (1.0 + h0 * lam0) - lam0) * d0 / h0
+    want = min(100 * h0, (0.01 / max(d1, d2)) ** 0.5, 1e9)
+    h = bdf.initial_step(lambda y: lam0 * y, y0, lam0 * y0, 1e9, rtol, atol, ft=lambda t, y: lam(t) * y)
+    assert h == pytest.approx(want, rel=1e-12)
+    assert h != pytest.approx(bdf.initial_step(lambda y: lam0 * y, y0, lam0 * y0, 1e9, rtol, atol), rel=1e-3)
