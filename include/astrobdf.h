@@ -99,6 +99,16 @@ typedef struct abdf_options {
                                  * each finite and >= 0) used in place of atol, or NULL
                                  * (default).  Read when the call (or server) starts; the
                                  * caller keeps ownership. */
+    const double *phi_tc;      /* DEVICE array [n_cells] of expansion times t_c [s] (each
+                                * finite and >= 0; 0 = constant conditions), or NULL
+                                * (default: every cell's conditions are constant).  A cell
+                                * with t_c > 0 follows phi_j(t) = phi_j(0) (1 + t/t_c)^(-p_j)
+                                * for phi = (T, n_H, A_V, zeta, G0), p = phi_exp (an
+                                * expanding flow, the outflow setting of paper App. A);
+                                * each step attempt from t to t + h takes the rate
+                                * coefficients at t + h.  abdf_solve and abdf_solve_noalloc
+                                * only (ABDF_E_ARG elsewhere). */
+    double phi_exp[5];         /* the exponents p_j (finite; default 0) */
 } abdf_options;
 
 /* Per-cell counters (written to a DEVICE array of n_cells structs). */

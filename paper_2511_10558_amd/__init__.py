@@ -120,10 +120,12 @@ def default_options() -> Options:
 
 def make_options(rtol=1e-6, atol=1e-20, max_steps=100000, precision="fp64", check_every=8,
                  hbm_budget_bytes=0, newton_tol=0.0, lu_reuse=0.0, max_order=5, h0=0.0,
-                 h_max=0.0, atol_species=None) -> Options:
+                 h_max=0.0, atol_species=None, phi_tc=None, phi_exp=None) -> Options:
     """abdf_options.  atol_species: an FP64 device tensor of one absolute
-    tolerance per species (used in place of atol), kept referenced by the
-    returned options."""
+    tolerance per species (used in place of atol); phi_tc: an FP64 device
+    tensor of one expansion time per cell (conditions phi_j(0) (1 + t/t_c)^-p_j,
+    p = phi_exp, five exponents for T, n_H, A_V, zeta, G0).  Tensors are kept
+    referenced by the returned options."""
     o = default_options()
     o.rtol, o.atol, o.max_steps = rtol, atol, max_steps
     o.precision = PREC[precision] if isinstance(precision, str) else int(precision)
@@ -136,6 +138,17 @@ def make_options(rtol=1e-6, atol=1e-20, max_steps=100000, precision="fp64", chec
             raise ValueError("atol_species must be a contiguous 1-D float64 tensor")
         o.atol_species = ctypes.c_void_p(atol_species.data_ptr())
         o._atol_species = atol_species   # keeps the array alive with the options
+    if phi_tc is not None:
+        torch = _torch()
+        if phi_tc.dtype != torch.float64 or phi_tc.dim() != 1 or not phi_tc.is_contiguous():
+            raise ValueError("phi_tc must be a contiguous 1-D float64 tensor")
+        o.phi_tc = ctypes.c_void_p(phi_tc.data_ptr())
+        o._phi_tc = phi_tc
+    if phi_exp is not None:
+        if len(phi_exp) != 5:
+            raise ValueError("phi_exp holds five exponents (T, n_H, A_V, zeta, G0)")
+        for j, v in enumerate(phi_exp):
+            o.phi_exp[j] = float(v)
     return o
 
 

@@ -25,6 +25,8 @@ class Options(ctypes.Structure):
         ("h0", ctypes.c_double),
         ("h_max", ctypes.c_double),
         ("atol_species", ctypes.c_void_p),
+        ("phi_tc", ctypes.c_void_p),
+        ("phi_exp", ctypes.c_double * 5),
     ]
 
 

@@ -79,6 +79,9 @@ abdf_status check_opts(const abdf_options &o) {
     if (!(o.h0 >= 0.0) || !std::isfinite(o.h0)) return fail(ABDF_E_ARG, "h0 must be finite and >= 0");
     if (!(o.h_max >= 0.0) || !std::isfinite(o.h_max)) return fail(ABDF_E_ARG, "h_max must be finite and >= 0");
     if (o.atol_species) CHECK_DEV(o.atol_species, "atol_species");
+    if (o.phi_tc) CHECK_DEV(o.phi_tc, "phi_tc");
+    for (double p : o.phi_exp)
+        if (!std::isfinite(p)) return fail(ABDF_E_ARG, "phi_exp entries must be finite");
     return ABDF_OK;
 }
 
@@ -117,6 +120,8 @@ void abdf_options_default(abdf_options *opt) {
     opt->h0 = 0.0;
     opt->h_max = 0.0;
     opt->atol_species = nullptr;
+    opt->phi_tc = nullptr;
+    for (double &p : opt->phi_exp) p = 0.0;
 }
 
 const char *abdf_last_error(void) { return g_last_error.c_str(); }
@@ -295,6 +300,7 @@ abdf_status abdf_solve_record(const abdf_network *net, int64_t n_cells, const do
     rc = check_opts(o);
     if (rc != ABDF_OK) return rc;
     if (o.precision != ABDF_PREC_FP64) return fail(ABDF_E_ARG, "recording solves use FP64 factorisations");
+    if (o.phi_tc) return fail(ABDF_E_ARG, "recording solves take constant conditions (phi_tc must be NULL)");
     if (max_tape_steps < 0) return fail(ABDF_E_ARG, "max_tape_steps must be >= 0");
     if (alpha) CHECK_DEV(alpha, "alpha");
     try {
@@ -370,6 +376,7 @@ abdf_status abdf_server_create(const abdf_network *net, const abdf_server_option
     if (rc != ABDF_OK) return rc;
     if (o.max_slots < 0 || o.max_slots > INT32_MAX || o.max_queued_cells < 0)
         return fail(ABDF_E_ARG, "max_slots or max_queued_cells out of range");
+    if (o.solve.phi_tc) return fail(ABDF_E_ARG, "served requests take constant conditions (phi_tc must be NULL)");
     try {
         std::string err;
         const abdf::DeviceNet *dn = net->host.device_tables(err);

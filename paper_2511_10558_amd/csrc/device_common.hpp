@@ -35,6 +35,7 @@ constexpr int32_t kLu64 = 2;
 
 struct SlotCtl {
     double t, h, t_end, c, c_lu, eta_old, rtol, atol, newton_tol, err;
+    double tc;        // expansion time of the conditions (0: constant)
     int32_t q, n_equal, status, phase, j_fresh, jac_refresh, landing, newton_iter;
     int32_t lu_valid, cell, m_last, lu_mode;   // FP32-LU engines: kLuPlain32, kLuRefined32 or kLu64
     int32_t n_steps, n_attempts, n_err_reject, n_newton_fail, n_rhs, n_jac, n_lu, n_newton_iter;
@@ -49,6 +50,8 @@ struct Slots {
     int max_order;    // highest order the order selection may reach (1..kMaxOrder)
     double h0;        // first step (> 0 replaces the starting-step heuristic), seconds
     double h_max;     // bound on every step (0: none), seconds
+    int tvar;         // cells may have time-dependent conditions (SlotCtl::tc > 0)
+    double phi_exp[5];  // phi_j(t) = phi_j(0) (1 + t / tc)^(-phi_exp[j])
     const double *atol_sp;   // [S] per-species absolute tolerances, or null (each cell's atol)
     SlotCtl *ctl;
     double *phi;      // [n][5]: T, n_H, A_V, zeta, G0

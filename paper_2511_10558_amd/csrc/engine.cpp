@@ -146,6 +146,10 @@ int Engine::set_options(const abdf_options &o, std::string &err, double *atol_ho
     set_lu_reuse(o.lu_reuse);
     set_max_order(o.max_order);
     set_step_bounds(o.h0, o.h_max);
+    tvar_ = o.phi_tc != nullptr;
+    for (int j = 0; j < 5; ++j) phi_exp_[j] = o.phi_exp[j];
+    s_.tvar = tvar_;
+    for (int j = 0; j < 5; ++j) s_.phi_exp[j] = phi_exp_[j];
     atol_sp_ = nullptr;
     if (o.atol_species) {
         if (dn_.S > kMaxSpecies) {
@@ -240,6 +244,8 @@ int Engine::layout(int nslots, void *base, std::string &err) {
     s_.max_order = max_order_;
     s_.h0 = h0_;
     s_.h_max = h_max_;
+    s_.tvar = tvar_;
+    for (int j = 0; j < 5; ++j) s_.phi_exp[j] = phi_exp_[j];
     s_.atol_sp = nullptr;
     if (atol_sp_) {
         HIP_TRY(hipMemcpy(part[21], atol_sp_, S * sizeof(double), hipMemcpyHostToDevice));
@@ -362,6 +368,7 @@ int Engine::admit(const BatchIO &io, const abdf_options &opt, long long &next, h
     a.rtol = opt.rtol;
     a.atol = opt.atol;
     a.newton_tol = newton_tolerance(opt);
+    a.tc = opt.phi_tc;
     // the pinned admission buffers are rewritten only after the next poll's synchronisation
     next += want;
     return admit_cells(a, st, err);
@@ -405,7 +412,7 @@ int Engine::attempt(hipStream_t st, std::string &err) {
             if (rc != ABDF_OK) return rc;
         }
         t0 = timer_begin(st);
-        HIP_TRY(launch_control(s_, ring_, bound_, st));
+        HIP_TRY(launch_control(s_, dn_, ring_, bound_, st));
         timer_end(ABDF_PROF_CONTROL, t0, st);
         ring_ = (ring_ + 1) % 3;
         return ABDF_OK;
@@ -423,7 +430,7 @@ int Engine::attempt(hipStream_t st, std::string &err) {
     if (rc != ABDF_OK) return rc;
     HIP_TRY(hipStreamWaitEvent(st, ev_side_, 0));
     t0 = timer_begin(st);
-    HIP_TRY(launch_control(s_, ring_, bound_, st));
+    HIP_TRY(launch_control(s_, dn_, ring_, bound_, st));
     timer_end(ABDF_PROF_CONTROL, t0, st);
     ring_ = (ring_ + 1) % 3;
     return ABDF_OK;

@@ -138,6 +138,8 @@ class Engine {
     double lu_reuse_ = 0.0;
     int max_order_ = kMaxOrder;
     double h0_ = 0.0, h_max_ = 0.0;
+    int tvar_ = 0;
+    double phi_exp_[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     std::vector<double> atol_store_;   // per-species absolute tolerances when the engine owns them
     const double *atol_sp_ = nullptr;  // host copy of the per-species tolerances, or null (scalar atol)
     Slots s_{};

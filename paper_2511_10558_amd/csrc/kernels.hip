@@ -99,10 +99,24 @@ __device__ inline void finish_slot(const Slots &s, int slot, SlotCtl &cs, int st
     }
 }
 
+// The conditions of a slot at time t into out[5] (LDS, thread 0): an
+// expanding flow, phi_j(t) = phi_j(0) (1 + t / tc)^(-p_j), constant for tc = 0.
+__device__ __forceinline__ void phi_at(const Slots &s, int slot, double tc, double t, double *out) {
+    if (threadIdx.x == 0) {
+        const double *p0 = s.phi + size_t(slot) * 5;
+        const double sc = 1.0 + t / tc;
+#pragma unroll
+        for (int j = 0; j < 5; ++j) out[j] = tc > 0.0 ? p0[j] * pow(sc, -s.phi_exp[j]) : p0[j];
+    }
+}
+
 // Starts the next step attempt of a running slot whose cs (LDS) is current:
 // checks limits, lands on t_end, forms the predictor and queues the slot.
-// Writes cs back to global memory.
-__device__ __forceinline__ void begin_attempt(const Slots &s, int slot, SlotCtl &cs, int ring, double *RU, double *sh) {
+// With time-dependent conditions the slot's rate coefficients become those
+// at the attempt's end, t + h (phit: 5 doubles of LDS).  Writes cs back to
+// global memory.
+__device__ __forceinline__ void begin_attempt(const Slots &s, const DeviceNet &n, int slot, SlotCtl &cs, int ring,
+                                              double *RU, double *sh, double *phit) {
     const int S = s.S;
     double *D = s.D + size_t(slot) * kDRows * S;
     if (threadIdx.x == 0) {
@@ -138,6 +152,11 @@ __device__ __forceinline__ void begin_attempt(const Slots &s, int slot, SlotCtl 
     }
     const int q = cs.q;
     if (sh[0] != 0.0) rescale_D(D, S, q, sh[0], RU);
+    if (s.tvar && cs.tc > 0.0) {
+        phi_at(s, slot, cs.tc, cs.t + cs.h, phit);
+        __syncthreads();
+        cell_rates(n, phit, s.k + size_t(slot) * n.R);
+    }
     const double gq = bdf_gamma(q);
     double gam[kMaxOrder + 1];
 #pragma unroll
@@ -192,7 +211,7 @@ __device__ __forceinline__ void begin_attempt(const Slots &s, int slot, SlotCtl 
 __global__ void __launch_bounds__(kBlock) k_admit(Slots s, DeviceNet n, AdmitArgs a, int ring) {
     extern __shared__ double smem[];
     __shared__ SlotCtl cs;
-    __shared__ double RU[36], red[kWaves], sh[2];
+    __shared__ double RU[36], red[kWaves], sh[2], phit[5];
     const int idx = blockIdx.x;
     if (idx >= a.count) return;
     const int slot = a.slots[idx];
@@ -220,6 +239,7 @@ __global__ void __launch_bounds__(kBlock) k_admit(Slots s, DeviceNet n, AdmitArg
         z.j_fresh = 1;
         z.lu_valid = 0;
         z.cell = int32_t(cell);
+        z.tc = a.tc ? a.tc[cell] : 0.0;
         cs = z;
     }
     bool bad = false;
@@ -235,7 +255,8 @@ __global__ void __launch_bounds__(kBlock) k_admit(Slots s, DeviceNet n, AdmitArg
     const double T = phi[0], nH = phi[1], Av = phi[2], zeta = phi[3], G0 = phi[4];
     bad |= !(isfinite(T) && T > 0.0 && isfinite(nH) && nH > 0.0 && isfinite(Av) && isfinite(zeta) &&
              zeta >= 0.0 && isfinite(G0) && G0 >= 0.0 && isfinite(cs.t_end) && cs.t_end >= 0.0 &&
-             isfinite(cs.rtol) && cs.rtol > 0.0 && isfinite(cs.atol) && cs.atol >= 0.0);
+             isfinite(cs.rtol) && cs.rtol > 0.0 && isfinite(cs.atol) && cs.atol >= 0.0 && isfinite(cs.tc) &&
+             cs.tc >= 0.0);
     bad = block_any(bad, red);
     if (bad) {
         finish_slot(s, slot, cs, ABDF_CELL_BAD_INPUT);
@@ -280,6 +301,12 @@ __global__ void __launch_bounds__(kBlock) k_admit(Slots s, DeviceNet n, AdmitArg
     // x1 = x0 + h0 f0 (kept in f1 as scratch, then f1 = f(x1))
     double *x1 = f1 + S;
     for (int i = threadIdx.x; i < S; i += kBlock) x1[i] = xs[i] + h0 * f0[i];
+    if (s.tvar && cs.tc > 0.0) {
+        // the trial evaluation at t = h0
+        phi_at(s, slot, cs.tc, h0, phit);
+        __syncthreads();
+        cell_rates(n, phit, k);
+    }
     __syncthreads();
     cell_rhs(n, k, x1, rate, part, f1);
     double s2 = 0.0;
@@ -301,7 +328,7 @@ __global__ void __launch_bounds__(kBlock) k_admit(Slots s, DeviceNet n, AdmitArg
         cs.n_jac = 1;
     }
     __syncthreads();
-    begin_attempt(s, slot, cs, ring, RU, sh);
+    begin_attempt(s, n, slot, cs, ring, RU, sh, phit);
 }
 
 // Forms M = I - c J(x_J) for every queued slot and factors it (one workgroup
@@ -527,9 +554,9 @@ __global__ void __launch_bounds__(kBlock) k_newton_fused(Slots s, DeviceNet n, i
 }
 
 // Acts on the outcome of every active slot's attempt and starts its next one.
-__global__ void __launch_bounds__(kBlock) k_control(Slots s, int ring) {
+__global__ void __launch_bounds__(kBlock) k_control(Slots s, DeviceNet n, int ring) {
     __shared__ SlotCtl cs;
-    __shared__ double RU[36], red[kWaves], sh[4];
+    __shared__ double RU[36], red[kWaves], sh[4], phit[5];
     const int next = (ring + 1) % 3;
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         const int old = (ring + 2) % 3;
@@ -574,7 +601,7 @@ __global__ void __launch_bounds__(kBlock) k_control(Slots s, int ring) {
         }
         __syncthreads();
         if (sh[0] != 0.0) rescale_D(D, S, cs.q, 0.5, RU);
-        begin_attempt(s, slot, cs, next, RU, sh + 2);
+        begin_attempt(s, n, slot, cs, next, RU, sh + 2, phit);
         return;
     }
     // converged: local error test
@@ -605,7 +632,7 @@ __global__ void __launch_bounds__(kBlock) k_control(Slots s, int ring) {
             if (s.lu_reuse == 0.0) cs.lu_valid = 0;   // else the change of c decides
         }
         rescale_D(D, S, q, rho, RU);
-        begin_attempt(s, slot, cs, next, RU, sh + 2);
+        begin_attempt(s, n, slot, cs, next, RU, sh + 2, phit);
         return;
     }
     // accept: update the differences, collect the order-selection norms, and
@@ -701,7 +728,7 @@ __global__ void __launch_bounds__(kBlock) k_control(Slots s, int ring) {
         __syncthreads();
         rescale_D(D, S, cs.q, sh[0], RU);
     }
-    begin_attempt(s, slot, cs, next, RU, sh + 2);
+    begin_attempt(s, n, slot, cs, next, RU, sh + 2, phit);
 }
 
 // Copies results of finished slots to the caller's arrays.
@@ -1383,8 +1410,8 @@ hipError_t launch_newton_solve(const Slots &s, const DeviceNet &n, int ring, int
     return LAUNCH_CHECK();
 }
 
-hipError_t launch_control(const Slots &s, int ring, int grid, hipStream_t st) {
-    hipLaunchKernelGGL(k_control, dim3(grid > 0 ? grid : 1), dim3(kBlock), 0, st, s, ring);
+hipError_t launch_control(const Slots &s, const DeviceNet &n, int ring, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(k_control, dim3(grid > 0 ? grid : 1), dim3(kBlock), 0, st, s, n, ring);
     return LAUNCH_CHECK();
 }
 

@@ -21,6 +21,7 @@ struct AdmitArgs {
     const double *rtol_c, *atol_c;  // per-cell tolerances [cells], or null for rtol / atol
     double rtol, atol;
     double newton_tol;          // > 0: used as is; 0: from each cell's rtol
+    const double *tc;           // [cells] expansion times of the conditions, or null (constant)
 };
 
 struct HarvestArgs {
@@ -83,7 +84,7 @@ hipError_t launch_newton_fused(const Slots &s, const DeviceNet &n, int ring, int
                                hipStream_t st);
 hipError_t launch_newton_solve(const Slots &s, const DeviceNet &n, int ring, int which, int grid, int grid_ref,
                                size_t lds, size_t lds_ref, hipStream_t st);
-hipError_t launch_control(const Slots &s, int ring, int grid, hipStream_t st);
+hipError_t launch_control(const Slots &s, const DeviceNet &n, int ring, int grid, hipStream_t st);
 hipError_t launch_harvest(const Slots &s, const HarvestArgs &h, hipStream_t st);
 
 hipError_t launch_adj_admit(const Slots &s, const DeviceNet &n, const AdjArgs &a, int ring, size_t lds, hipStream_t st);

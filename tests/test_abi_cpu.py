@@ -39,6 +39,7 @@ def test_options_default_values():
     assert o.rtol == 1e-6 and o.atol == 1e-20 and o.max_steps == 100000
     assert o.precision == 0 and o.check_every == 8 and o.hbm_budget_bytes == 0 and o.lu_reuse == 0.0
     assert o.max_order == 5 and o.h0 == 0.0 and o.h_max == 0.0
+    assert o.phi_tc is None and list(o.phi_exp) == [0.0] * 5
 
 
 @pytest.mark.parametrize("name", ["small", "net200", "net500"])

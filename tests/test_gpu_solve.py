@@ -328,3 +328,68 @@ def test_failure_codes_match_the_oracle(ab, dev):
     assert abs(tg + 1.0 / (kp * abs(x[0, 0])) - t_star) <= 1e-4 * t_star
     assert stats["t"][1] == 0.0 and stats["n_steps"][1] == 0 and np.array_equal(x[1], x0s[1])
     assert rel_err_above(x[2], refs[2].x) <= TOL
+
+
+def _expansion_integral(t, t_c, p):
+    return t_c * np.log1p(t / t_c) if p == 1.0 else t_c * ((1.0 + t / t_c) ** (1.0 - p) - 1.0) / (1.0 - p)
+
+
+def test_trajectory_closed_forms(ab, dev):
+    # conditions along an expanding flow, phi_j(0) (1 + t/t_c)^-p_j:
+    # A -> B under zeta(t) (x_A = exp(-alpha int zeta dt)) and A + B -> C under
+    # n_H(t) (1/a - 1/a0 = k n_H0 int (1 + s/t_c)^-2 ds)
+    import torch
+    cell = dict(T=30.0, n_H=1e4, A_V=1.0, zeta=1.3e-17, G0=1.0)
+    net = tiny_nets.decay(2.0)
+    g = ab.Network.from_text(net.to_text())
+    k0 = 2.0 * cell["zeta"]
+    t_end = 3.0 / k0
+    tcs = np.array([0.5, 0.5, 0.1]) * t_end
+    for p in (1.0, 1.5):
+        tc = torch.tensor(tcs, dtype=torch.float64, device=dev)
+        x, status, _ = solve_cells(ab, g, _cells(net, cell, [[1.0, 0.0]] * 3, t_end), dev, rtol=1e-10, atol=1e-30,
+                                   phi_tc=tc, phi_exp=[0.0, 0.0, 0.0, p, 0.0])
+        for c in range(3):
+            want = np.exp(-k0 * _expansion_integral(t_end, tcs[c], p))
+            assert status[c] == 0
+            np.testing.assert_allclose(x[c], [want, 1.0 - want], rtol=1e-7)
+    net = tiny_nets.association(1e-9)
+    g = ab.Network.from_text(net.to_text())
+    kp, a0 = chem.rate_coefficients(net, **cell)[0], 2e-4
+    t_end = 5.0 / (kp * a0)
+    tc = torch.tensor([0.3 * t_end], dtype=torch.float64, device=dev)
+    x, status, _ = solve_cells(ab, g, _cells(net, cell, [[a0, a0, 0.0]], t_end), dev, rtol=1e-10, atol=1e-30,
+                               phi_tc=tc, phi_exp=[0.0, 2.0, 1.0, 0.0, 0.0])
+    a = a0 / (1.0 + a0 * kp * _expansion_integral(t_end, 0.3 * t_end, 2.0))
+    assert status[0] == 0
+    np.testing.assert_allclose(x[0], [a, a, a0 - a], rtol=1e-7)
+
+
+def test_trajectory_cells_match_the_oracle(ab, dev):
+    # 200-species cells along an outflow (T ~ r^-0.7, n_H ~ r^-2, A_V ~ r^-1,
+    # r = 1 + t/t_c) against the oracle's TrajectoryChemistry; a cell with
+    # t_c = 0 in the same batch is bitwise the plain solve
+    import torch
+    net = synth.network_for_config("net200")
+    cells = synth.sample_cells(net, 4, seed=2101, t_end_yr=1e5)
+    tcs = np.array([3e3, 3e4, 0.0, 1e5]) * synth.YEAR_S
+    exps = [0.7, 2.0, 1.0, 0.0, 0.0]
+    g = ab.Network.from_text(net.to_text())
+    x, status, stats = solve_cells(ab, g, cells, dev, phi_tc=torch.tensor(tcs, dtype=torch.float64, device=dev),
+                                   phi_exp=exps)
+    plain, _, _ = solve_cells(ab, g, cells.subset([2]), dev)
+    assert np.array_equal(x[2], plain[0])
+    for c in (0, 1, 3):
+        ref = bdf.solve(chem.TrajectoryChemistry(net, cells.cell(c), tcs[c], exps), cells.x0[c], cells.t_end[c],
+                        1e-6, 1e-20)
+        assert status[c] == 0 and ref.status == bdf.OK
+        assert rel_err_above(x[c], ref.x) <= TOL, (c, rel_err_above(x[c], ref.x))
+        assert abs(int(stats["n_steps"][c]) - ref.stats.n_steps) <= 0.05 * ref.stats.n_steps + 2
+    # trajectories are refused where they are not supported, and bad expansion times fail the cell
+    tc = torch.tensor(tcs, dtype=torch.float64, device=dev)
+    args = [t(v, dev) for v in (cells.T, cells.n_H, cells.A_V, cells.zeta, cells.G0, cells.x0, cells.t_end)]
+    with pytest.raises(ab.AbdfError):
+        ab.solve_record(g, *args, phi_tc=tc, phi_exp=exps)
+    bad = torch.tensor([-1.0, np.nan, 0.0, 1e10], dtype=torch.float64, device=dev)
+    _, st_bad, _ = solve_cells(ab, g, cells, dev, phi_tc=bad, phi_exp=exps)
+    assert list(st_bad[:2]) == [4, 4] and st_bad[2] == 0
