@@ -13,6 +13,8 @@ chem    rate coefficients (paper Sec. 2 Kooij-Arrhenius and cosmic-ray forms,
 bdf     variable-order, variable-step BDF (quasi-constant step size,
         backward-difference form) for one cell, with frozen-sequence replay and
         discrete forward sensitivities.
+esdirk  Kvaerno's seven-stage 5(4) ESDIRK (the paper's integrator, Sec. 4)
+        for one cell, on the same Newton iteration as bdf.
 steady  steady state of the rate equations by damped Newton with the
         conservation laws substituted for dependent rows.
 brute   fixed-step 3-stage Radau IIA reference integrator with step halving.

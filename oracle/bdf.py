@@ -92,10 +92,11 @@ def wrms(v, scale):
     return float(np.sqrt(np.mean(np.abs(v / scale) ** 2)))
 
 
-def initial_step(f, x0, f0, t_span, rtol, atol, ft=None):
-    """Starting step of Hairer, Norsett & Wanner (Solving ODEs I, Sec. II.4) for order 1.
-    ft(t, x), if given, is the right-hand side at time t (for the trial
-    evaluation at t = h0); otherwise f(x)."""
+def initial_step(f, x0, f0, t_span, rtol, atol, ft=None, order=1):
+    """Starting step of Hairer, Norsett & Wanner (Solving ODEs I, Sec. II.4) for
+    a method of the given order (1: BDF's first step; 5: the fifth-order
+    Runge-Kutta method).  ft(t, x), if given, is the right-hand side at time t
+    (for the trial evaluation at t = h0); otherwise f(x)."""
     scale = atol + rtol * np.abs(x0)
     d0 = wrms(x0, scale)
     d1 = wrms(f0, scale)
@@ -109,7 +110,7 @@ def initial_step(f, x0, f0, t_span, rtol, atol, ft=None):
     if max(d1, d2) <= 1e-15:
         h1 = max(1e-6, h0 * 1e-3)
     else:
-        h1 = (0.01 / max(d1, d2)) ** 0.5
+        h1 = (0.01 / max(d1, d2)) ** (1.0 / (order + 1))
     return min(100.0 * h0, h1, t_span)
 
 
@@ -144,12 +145,12 @@ class Result:
     history: list | None = None   # accepted (h, q, t_new, x_new) when recorded
 
 
-def _newton(chem, lu, c, psi, x_p, scale, tol, stats):
+def _newton(chem, lu, c, psi, x_p, scale, tol, stats, maxiter=NEWTON_MAXITER):
     """Modified Newton on d = c f(x_p + d) - psi with the factor of I - cJ."""
     d = np.zeros_like(x_p)
     x = x_p.copy()
     eta_old = None
-    for m in range(1, NEWTON_MAXITER + 1):
+    for m in range(1, maxiter + 1):
         fx = chem.f(x)
         stats.n_rhs += 1
         stats.n_newton_iter += 1
@@ -159,7 +160,7 @@ def _newton(chem, lu, c, psi, x_p, scale, tol, stats):
         eta = wrms(delta, scale)
         theta = None if eta_old is None else eta / eta_old
         if theta is not None and (
-            theta >= 1.0 or theta ** (NEWTON_MAXITER - m) / (1.0 - theta) * eta > tol
+            theta >= 1.0 or theta ** (maxiter - m) / (1.0 - theta) * eta > tol
         ):
             return False, m, x, d
         x = x + delta
@@ -167,7 +168,7 @@ def _newton(chem, lu, c, psi, x_p, scale, tol, stats):
         if eta == 0.0 or (theta is not None and theta / (1.0 - theta) * eta < tol):
             return True, m, x, d
         eta_old = eta
-    return False, NEWTON_MAXITER, x, d
+    return False, maxiter, x, d
 
 
 def solve(chem, x0, t_end, rtol=1e-6, atol=1e-20, max_steps=100000,
