@@ -3,13 +3,19 @@
 first cells of its seeded batch.
 
 Loss L = sum over 10 target species of log x_s(t_end).  For each cell the
-oracle's own accepted (h, q) sequence is frozen (its recorded run) and the
-file holds, for 50 seeded reactions r:
-  sens: dL/dlog alpha_r from the oracle's discrete forward sensitivities
-  fd:   central differences of the frozen map with step 1e-6 in log alpha_r,
-        for the first N_FD of them (seeded order)
+oracle's own accepted (h, q) sequence is frozen (its recorded run), each
+corrector solved exactly, and the file holds, for 50 seeded reactions r, three
+independent values of dL/dlog alpha_r of that map:
+  sens: the oracle's discrete forward sensitivities (FP64)
+  cs:   the complex-step derivative Im L(log alpha_r + i h) / h, h = 1e-30
+        (Squire & Trapp, SIAM Review 40, 1998): no difference is formed, so
+        no cancellation
+  fd:   central differences with step 1e-6 in log alpha_r, each replay run
+        in x86 extended precision (64-bit significand) with Newton iterated
+        until the weighted correction is below 1e-12, so that the rounding
+        noise the map amplifies stays far below the difference quotient
 Only the oracle is called.  Run from the repository root:
-    python tests/golden/make_adjoint_golden.py [--cells 2] [--procs 8]
+    python tests/golden/make_adjoint_golden.py [--cells 2] [--procs 7]
 """
 from __future__ import annotations
 
@@ -18,6 +24,7 @@ import json
 import multiprocessing as mp
 import os
 import sys
+import time
 
 import numpy as np
 
@@ -29,9 +36,11 @@ from oracle import bdf, chem  # noqa: E402
 
 N_CELLS_BATCH = 256
 SEED_CELLS, SEED_TARGETS, SEED_REACTIONS = 5001, 5002, 5003
-N_TARGETS, N_REACTIONS, N_FD = 10, 50, 20
-DELTA = 1e-6
-MAX_NEWTON = 4        # full Newton from the predictor reaches rounding level within these
+N_TARGETS, N_REACTIONS = 10, 50
+DELTA = 1e-6          # central-difference step in log alpha
+H_CS = 1e-30          # complex step
+NEWTON_FP64 = 5       # full Newton from the predictor: FP64 iterates reach the rounding floor within 3
+NEWTON_EXT = 50       # extended precision: iterated until the weighted correction is below 1e-12
 OUT = os.path.join(os.path.dirname(os.path.abspath(__file__)), "adjoint_net500.json")
 
 _state = {}
@@ -53,13 +62,19 @@ def _init(n_cells):
     _state["setup"] = _setup(n_cells)
 
 
-def _fd_task(args):
-    c, r, sign = args
+def _task(args):
+    kind, c, r, sign = args
     net, cells, runs = _state["setup"]
-    ch = chem.cell_chemistry(net, cells.cell(c))
-    k = ch.k.copy()
-    k[r] *= np.exp(sign * DELTA)
-    return bdf.replay(chem.Chemistry(net, k), cells.x0[c], runs[c].history, max_newton=MAX_NEWTON)
+    k = chem.cell_chemistry(net, cells.cell(c)).k
+    if kind == "fd":
+        k = k.astype(np.longdouble)
+        k[r] *= np.exp(np.longdouble(sign * DELTA))
+        x = bdf.replay(chem.Chemistry(net, k), cells.x0[c], runs[c].history, max_newton=NEWTON_EXT)
+    else:
+        k = k.astype(np.complex128)
+        k[r] *= np.exp(1j * H_CS)
+        x = bdf.replay(chem.Chemistry(net, k), cells.x0[c], runs[c].history, max_newton=NEWTON_FP64)
+    return (kind, c, r, sign), x
 
 
 def _sens_task(args):
@@ -67,46 +82,53 @@ def _sens_task(args):
     net, cells, runs = _state["setup"]
     ch = chem.cell_chemistry(net, cells.cell(c))
     rs = np.asarray(reactions)
-    x, S = bdf.replay(ch, cells.x0[c], runs[c].history, max_newton=MAX_NEWTON,
+    x, S = bdf.replay(ch, cells.x0[c], runs[c].history, max_newton=NEWTON_FP64,
                       sens_dfdp=lambda y: ch.df_dlogalpha(y)[:, rs].toarray())
-    return x, S
+    return ("sens", c, -1, 0), (x, S)
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--cells", type=int, default=2)
-    ap.add_argument("--procs", type=int, default=8)
+    ap.add_argument("--procs", type=int, default=7)
     args = ap.parse_args()
     net, cells, runs = _setup(args.cells)
     xs = np.array([r.x for r in runs])
     # targets: species above 1e-12 in every cell at t_end
     eligible = np.flatnonzero((xs > 1e-12).all(axis=0))
     targets = np.sort(np.random.default_rng(SEED_TARGETS).choice(eligible, N_TARGETS, replace=False))
-    drawn = np.random.default_rng(SEED_REACTIONS).choice(net.n_reactions, N_REACTIONS, replace=False)
-    reactions = np.sort(drawn)
-    fd_reactions = np.sort(drawn[:N_FD])
+    reactions = np.sort(np.random.default_rng(SEED_REACTIONS).choice(net.n_reactions, N_REACTIONS, replace=False))
+    tasks = [("fd", c, int(r), s) for c in range(args.cells) for r in reactions for s in (1, -1)]
+    tasks += [("cs", c, int(r), 0) for c in range(args.cells) for r in reactions]
+    res = {}
+    t0 = time.time()
     with mp.get_context("fork").Pool(args.procs, initializer=_init, initargs=(args.cells,)) as pool:
-        sens = pool.map(_sens_task, [(c, reactions.tolist()) for c in range(args.cells)])
-        tasks = [(c, int(r), s) for c in range(args.cells) for r in fd_reactions for s in (1, -1)]
-        fd_x = pool.map(_fd_task, tasks)
+        for key, val in pool.imap_unordered(_sens_task, [(c, reactions.tolist()) for c in range(args.cells)]):
+            res[key] = val
+        for n, (key, val) in enumerate(pool.imap_unordered(_task, tasks)):
+            res[key] = val
+            print(f"{n + 1}/{len(tasks)} replays at {time.time() - t0:.0f} s", flush=True)
     out = {"workload": "net500 differentiation: 500 species / 6000 reactions, t_end 1e6 yr, rtol 1e-6, atol 1e-20",
            "seeds": {"cells": SEED_CELLS, "targets": SEED_TARGETS, "reactions": SEED_REACTIONS},
-           "batch_cells": N_CELLS_BATCH, "fd_step_log_alpha": DELTA, "max_newton": MAX_NEWTON,
-           "targets": targets.tolist(), "reactions": reactions.tolist(), "fd_reactions": fd_reactions.tolist(),
-           "cells": []}
-    it = iter(fd_x)
+           "batch_cells": N_CELLS_BATCH, "fd_step_log_alpha": DELTA, "complex_step": H_CS,
+           "newton_fp64": NEWTON_FP64, "newton_extended": NEWTON_EXT,
+           "targets": targets.tolist(), "reactions": reactions.tolist(), "cells": []}
     for c in range(args.cells):
-        x, S = sens[c]
+        x, S = res[("sens", c, -1, 0)]
         g_sens = (S[targets] / x[targets, None]).sum(axis=0)
-        g_fd = []
-        for _ in fd_reactions:
-            xp, xm = next(it), next(it)
+        g_fd, g_cs = [], []
+        for r in reactions:
+            xp, xm = res[("fd", c, int(r), 1)], res[("fd", c, int(r), -1)]
             g_fd.append(float(np.sum(np.log(xp[targets]) - np.log(xm[targets])) / (2 * DELTA)))
+            xc = res[("cs", c, int(r), 0)]
+            g_cs.append(float(np.sum(np.log(xc[targets])).imag / H_CS))
+        g_fd, g_cs = np.array(g_fd), np.array(g_cs)
+        top = np.abs(g_sens).max()
         out["cells"].append({"index": c, "n_steps": runs[c].stats.n_steps, "x_end_targets": x[targets].tolist(),
-                             "sens": g_sens.tolist(), "fd": g_fd})
-        sel = np.searchsorted(reactions, fd_reactions)
-        print(f"cell {c}: steps {runs[c].stats.n_steps}, max |sens - fd| / max |sens| = "
-              f"{np.max(np.abs(g_sens[sel] - np.array(g_fd))) / np.max(np.abs(g_sens)):.2e}")
+                             "sens": g_sens.tolist(), "cs": g_cs.tolist(), "fd": g_fd.tolist()})
+        print(f"cell {c}: steps {runs[c].stats.n_steps}, max |g| {top:.3e}; over max |g|: "
+              f"|sens - cs| {np.max(np.abs(g_sens - g_cs)) / top:.2e}, |fd - cs| {np.max(np.abs(g_fd - g_cs)) / top:.2e}, "
+              f"|fd - sens| {np.max(np.abs(g_fd - g_sens)) / top:.2e}")
     with open(OUT, "w") as f:
         json.dump(out, f, indent=1)
     print("wrote", OUT)

@@ -157,17 +157,17 @@ def test_net500_matches_oracle_sensitivities_and_central_differences(ab, dev):
     xg, _, _ = solve_cells(ab, g, cells, dev)
     x, st, gs, gc, _ = adjoint(ab, g, cells, log_loss_grad(xg, targets), dev)
     assert (st == 0).all()
-    fd_r = np.array(gold["fd_reactions"])
-    sel = np.searchsorted(reactions, fd_r)
     for c, rec in enumerate(gold["cells"]):
-        sens, fd = np.array(rec["sens"]), np.array(rec["fd"])
-        assert grad_ok(gc[c, reactions], sens) <= 1e-3
-        # central differences of the frozen map carry rounding noise that the map
-        # amplifies; entry by entry the bar is the larger of 1e-3 and the
-        # oracle's own disagreement between its differences and sensitivities
-        scale = np.maximum(np.abs(fd), 1e-3 * np.abs(sens).max())
-        own = np.abs(sens[sel] - fd) / scale
-        assert np.all(np.abs(gc[c, fd_r] - fd) / scale <= np.maximum(1e-3, 2.0 * own))
+        sens, cs, fd = np.array(rec["sens"]), np.array(rec["cs"]), np.array(rec["fd"])
+        # each reference of the golden file: the oracle's forward sensitivities,
+        # the complex-step derivative of its frozen map and central differences
+        # of that map replayed in extended precision (they agree to 1e-6 of the
+        # largest entry); the GPU gradient within 1e-3 of each, entry by entry
+        # over all 50 reactions, relative to the entry with a floor of 1e-3 of
+        # the largest
+        for ref in (sens, cs, fd):
+            assert grad_ok(gc[c, reactions], ref) <= 1e-3
+        assert np.all(np.isfinite(gc[c]))
     assert np.allclose(gs, gc.sum(axis=0), rtol=1e-12, atol=0)
 
 
