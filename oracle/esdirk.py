@@ -16,7 +16,8 @@ One step from (t_n, x_n) with step h, F_j = f(Y_j), G_j = h F_j:
         step's last stage, FSAL)
   Y_i = x_n + sum_{j<i} A[i, j] G_j + gamma h f(Y_i),   i = 2..7,
 each implicit stage solved by the modified Newton iteration of the BDF oracle
-(bdf._newton: the same rate tests and tolerance) on M = I - h gamma J(x_n),
+(bdf._newton: the same rate tests and tolerance, at most NEWTON_MAXITER = 10
+iterations) on M = I - h gamma J(x_n),
 with J and the factorisation formed once per step attempt and Y_{i-1} as the
 stage's starting point.  A converged stage gives G_i from its own equation,
 G_i = (Y_i - x_n - sum_{j<i} A[i, j] G_j) / gamma, so no extra evaluation of f
@@ -45,6 +46,10 @@ ORDER = 5
 SAFETY = 0.9
 MIN_FACTOR = 0.2
 MAX_FACTOR = 10.0
+# Newton iterations per stage: with the BDF corrector's 4, half the attempts on
+# the networks' cells end in a corrector failure while the error estimate would
+# allow the step; 10 leaves almost none
+NEWTON_MAXITER = 10
 
 
 def tableau():
@@ -73,7 +78,7 @@ C = A.sum(axis=1)
 E = A[6] - A[5]          # weights of the error estimate Y_7 - Y_6
 
 
-def step(chem, x, F1, h, lu, tol, rtol, atol, stats, maxiter=bdf.NEWTON_MAXITER):
+def step(chem, x, F1, h, lu, tol, rtol, atol, stats, maxiter=NEWTON_MAXITER):
     """One step attempt from x with stage derivative F1 = f(x) and the factor
     `lu` of I - h gamma J.  Returns (ok, x_new, G, err_vec): ok False when a
     stage's corrector failed; G[j] = h F_{j+1}; err_vec = Y_7 - Y_6."""
