@@ -73,6 +73,26 @@ enum {
     ABDF_PREC_FP32_LU = 1
 };
 
+/* Integration method (abdf_options.method).
+ *   ABDF_METHOD_BDF: variable-order (1..5), variable-step BDF in the
+ *     quasi-constant-step backward-difference form (the stiff integrator of
+ *     the paper's Sec. 1).
+ *   ABDF_METHOD_ESDIRK5: Kvaerno's seven-stage ESDIRK of order 5 with an
+ *     embedded order-4 estimate (the integrator of the paper's Sec. 4;
+ *     Kvaerno, BIT 44, 2004): explicit first stage, six implicit stages with
+ *     the one Newton matrix I - 0.26 h J(x_n) per step attempt, each stage
+ *     solved by the same modified Newton iteration as a BDF corrector from the
+ *     previous stage's value; error Y_7 - Y_6; step factor
+ *     min(10, max(0.2, 0.9 err^(-1/5))), no growth right after a rejection,
+ *     h / 2 after a corrector failure.  abdf_solve and abdf_solve_noalloc
+ *     only; max_order is ignored, lu_reuse must be 0 and phi_tc NULL.  Per-cell
+ *     counters: n_attempts step attempts, n_lu one factorisation per attempt,
+ *     order 5. */
+enum {
+    ABDF_METHOD_BDF = 0,
+    ABDF_METHOD_ESDIRK5 = 1
+};
+
 typedef struct abdf_network abdf_network;
 
 typedef struct abdf_options {
@@ -109,6 +129,8 @@ typedef struct abdf_options {
                                 * coefficients at t + h.  abdf_solve and abdf_solve_noalloc
                                 * only (ABDF_E_ARG elsewhere). */
     double phi_exp[5];         /* the exponents p_j (finite; default 0) */
+    int32_t method;            /* ABDF_METHOD_* (default BDF) */
+    int32_t reserved;          /* 0 */
 } abdf_options;
 
 /* Per-cell counters (written to a DEVICE array of n_cells structs). */

@@ -14,6 +14,7 @@ from . import _lib
 from ._lib import CellStats, LibraryMissing, Options  # noqa: F401
 
 PREC = {"fp64": 0, "fp32_lu": 1}
+METHOD = {"bdf": 0, "esdirk5": 1}
 CELL_STATUS = {0: "ok", 1: "step_too_small", 2: "max_steps", 3: "nonfinite", 4: "bad_input", 5: "tape_full"}
 STATUS_NAMES = {0: "OK", 1: "E_ARG", 2: "E_PARSE", 3: "E_NONCONSERVING", 4: "E_IO", 5: "E_DEVICE",
                 6: "E_BUDGET", 7: "E_NOMEM", 8: "E_BUSY"}
@@ -120,18 +121,20 @@ def default_options() -> Options:
 
 def make_options(rtol=1e-6, atol=1e-20, max_steps=100000, precision="fp64", check_every=8,
                  hbm_budget_bytes=0, newton_tol=0.0, lu_reuse=0.0, max_order=5, h0=0.0,
-                 h_max=0.0, atol_species=None, phi_tc=None, phi_exp=None) -> Options:
+                 h_max=0.0, atol_species=None, phi_tc=None, phi_exp=None, method="bdf") -> Options:
     """abdf_options.  atol_species: an FP64 device tensor of one absolute
     tolerance per species (used in place of atol); phi_tc: an FP64 device
     tensor of one expansion time per cell (conditions phi_j(0) (1 + t/t_c)^-p_j,
-    p = phi_exp, five exponents for T, n_H, A_V, zeta, G0).  Tensors are kept
-    referenced by the returned options."""
+    p = phi_exp, five exponents for T, n_H, A_V, zeta, G0).  method: "bdf" or
+    "esdirk5" (ABDF_METHOD_*).  Tensors are kept referenced by the returned
+    options."""
     o = default_options()
     o.rtol, o.atol, o.max_steps = rtol, atol, max_steps
     o.precision = PREC[precision] if isinstance(precision, str) else int(precision)
     o.check_every, o.hbm_budget_bytes, o.newton_tol = check_every, hbm_budget_bytes, newton_tol
     o.lu_reuse, o.max_order = lu_reuse, max_order
     o.h0, o.h_max = h0, h_max
+    o.method = METHOD[method] if isinstance(method, str) else int(method)
     if atol_species is not None:
         torch = _torch()
         if atol_species.dtype != torch.float64 or atol_species.dim() != 1 or not atol_species.is_contiguous():

@@ -27,6 +27,8 @@ class Options(ctypes.Structure):
         ("atol_species", ctypes.c_void_p),
         ("phi_tc", ctypes.c_void_p),
         ("phi_exp", ctypes.c_double * 5),
+        ("method", ctypes.c_int32),
+        ("reserved", ctypes.c_int32),
     ]
 
 

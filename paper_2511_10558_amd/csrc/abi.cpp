@@ -73,6 +73,11 @@ abdf_status check_opts(const abdf_options &o) {
     if (o.max_steps < 1) return fail(ABDF_E_ARG, "max_steps must be >= 1");
     if (o.precision != ABDF_PREC_FP64 && o.precision != ABDF_PREC_FP32_LU)
         return fail(ABDF_E_ARG, "unknown precision");
+    if (o.method != ABDF_METHOD_BDF && o.method != ABDF_METHOD_ESDIRK5) return fail(ABDF_E_ARG, "unknown method");
+    if (o.method == ABDF_METHOD_ESDIRK5) {
+        if (o.lu_reuse != 0.0) return fail(ABDF_E_ARG, "the ESDIRK method factors every step attempt (lu_reuse must be 0)");
+        if (o.phi_tc) return fail(ABDF_E_ARG, "the ESDIRK method takes constant conditions (phi_tc must be NULL)");
+    }
     if (o.newton_tol < 0.0 || !std::isfinite(o.newton_tol)) return fail(ABDF_E_ARG, "newton_tol must be >= 0");
     if (!(o.lu_reuse >= 0.0 && o.lu_reuse < 1.0)) return fail(ABDF_E_ARG, "lu_reuse must be in [0, 1)");
     if (o.max_order < 0 || o.max_order > 5) return fail(ABDF_E_ARG, "max_order must be in 1..5 (0: 5)");
@@ -122,6 +127,7 @@ void abdf_options_default(abdf_options *opt) {
     opt->atol_species = nullptr;
     opt->phi_tc = nullptr;
     for (double &p : opt->phi_exp) p = 0.0;
+    opt->method = ABDF_METHOD_BDF;
 }
 
 const char *abdf_last_error(void) { return g_last_error.c_str(); }
@@ -301,6 +307,7 @@ abdf_status abdf_solve_record(const abdf_network *net, int64_t n_cells, const do
     if (rc != ABDF_OK) return rc;
     if (o.precision != ABDF_PREC_FP64) return fail(ABDF_E_ARG, "recording solves use FP64 factorisations");
     if (o.phi_tc) return fail(ABDF_E_ARG, "recording solves take constant conditions (phi_tc must be NULL)");
+    if (o.method != ABDF_METHOD_BDF) return fail(ABDF_E_ARG, "recording solves (the adjoint) use the BDF method");
     if (max_tape_steps < 0) return fail(ABDF_E_ARG, "max_tape_steps must be >= 0");
     if (alpha) CHECK_DEV(alpha, "alpha");
     try {
@@ -377,6 +384,7 @@ abdf_status abdf_server_create(const abdf_network *net, const abdf_server_option
     if (o.max_slots < 0 || o.max_slots > INT32_MAX || o.max_queued_cells < 0)
         return fail(ABDF_E_ARG, "max_slots or max_queued_cells out of range");
     if (o.solve.phi_tc) return fail(ABDF_E_ARG, "served requests take constant conditions (phi_tc must be NULL)");
+    if (o.solve.method != ABDF_METHOD_BDF) return fail(ABDF_E_ARG, "the server uses the BDF method");
     try {
         std::string err;
         const abdf::DeviceNet *dn = net->host.device_tables(err);

@@ -12,7 +12,8 @@ constexpr int kBlock = 256;          // threads per workgroup in every per-cell 
 constexpr int kWaves = kBlock / 64;
 constexpr int kMaxOrder = 5;
 constexpr int kDRows = kMaxOrder + 3;  // difference rows 0..q+2 at q = 5
-constexpr int kNewtonMaxIter = 4;
+constexpr int kNewtonMaxIter = 4;     // BDF corrector iterations per attempt
+constexpr int kRkNewtonMaxIter = 10;  // ESDIRK iterations per stage
 constexpr double kURound = 2.220446049250313e-16;  // 2^-52
 constexpr double kMinFactor = 0.2;
 constexpr double kMaxFactor = 10.0;
@@ -41,6 +42,8 @@ struct SlotCtl {
     int32_t n_steps, n_attempts, n_err_reject, n_newton_fail, n_rhs, n_jac, n_lu, n_newton_iter;
     int32_t n_lu64;                        // FP32-LU engines: factorisations done in FP64 after a fallback
     int32_t jv_valid;                      // the slot's Jacobian nonzeros are those of the current x_J
+    int32_t stage;                         // ESDIRK: the stage being solved (2..7)
+    int32_t rejected;                      // ESDIRK: the last attempt was rejected (no growth on the next accept)
 };
 
 // Device workspace for n slots of one network (all arrays slot-major).
@@ -50,13 +53,15 @@ struct Slots {
     int max_order;    // highest order the order selection may reach (1..kMaxOrder)
     double h0;        // first step (> 0 replaces the starting-step heuristic), seconds
     double h_max;     // bound on every step (0: none), seconds
+    int method;       // ABDF_METHOD_BDF or ABDF_METHOD_ESDIRK5
+    int newton_maxiter;  // Newton iterations per corrector (kNewtonMaxIter or kRkNewtonMaxIter)
     int tvar;         // cells may have time-dependent conditions (SlotCtl::tc > 0)
     double phi_exp[5];  // phi_j(t) = phi_j(0) (1 + t / tc)^(-phi_exp[j])
     const double *atol_sp;   // [S] per-species absolute tolerances, or null (each cell's atol)
     SlotCtl *ctl;
     double *phi;      // [n][5]: T, n_H, A_V, zeta, G0
     double *k;        // [n][R]
-    double *D;        // [n][kDRows][S]
+    double *D;        // [n][kDRows][S]: BDF differences; ESDIRK: x_n, F_1, G_2..G_7
     double *x;        // [n][S] Newton iterate
     double *d;        // [n][S] accumulated correction
     double *psi;      // [n][S]

@@ -146,6 +146,9 @@ int Engine::set_options(const abdf_options &o, std::string &err, double *atol_ho
     set_lu_reuse(o.lu_reuse);
     set_max_order(o.max_order);
     set_step_bounds(o.h0, o.h_max);
+    method_ = o.method;
+    s_.method = method_;
+    s_.newton_maxiter = method_ == ABDF_METHOD_ESDIRK5 ? kRkNewtonMaxIter : kNewtonMaxIter;
     tvar_ = o.phi_tc != nullptr;
     for (int j = 0; j < 5; ++j) phi_exp_[j] = o.phi_exp[j];
     s_.tvar = tvar_;
@@ -244,6 +247,8 @@ int Engine::layout(int nslots, void *base, std::string &err) {
     s_.max_order = max_order_;
     s_.h0 = h0_;
     s_.h_max = h_max_;
+    s_.method = method_;
+    s_.newton_maxiter = method_ == ABDF_METHOD_ESDIRK5 ? kRkNewtonMaxIter : kNewtonMaxIter;
     s_.tvar = tvar_;
     for (int j = 0; j < 5; ++j) s_.phi_exp[j] = phi_exp_[j];
     s_.atol_sp = nullptr;
@@ -375,7 +380,7 @@ int Engine::admit(const BatchIO &io, const abdf_options &opt, long long &next, h
 }
 
 int Engine::newton_iterations(int which, hipStream_t st, std::string &err) {
-    for (int m = 0; m < kNewtonMaxIter; ++m) {
+    for (int m = 0; m < s_.newton_maxiter; ++m) {
         hipEvent_t t0 = timer_begin(st);
         HIP_TRY(launch_newton_rhs(s_, dn_, ring_, which, std::min(bound_, grid_newton_max_), lds_newton_, st));
         timer_end(which == kListNoFactor ? ABDF_PROF_RHS_SIDE : ABDF_PROF_RHS, t0, st);
@@ -385,6 +390,11 @@ int Engine::newton_iterations(int which, hipStream_t st, std::string &err) {
         timer_end(which == kListNoFactor ? ABDF_PROF_NEWTON_SIDE : ABDF_PROF_NEWTON, t0, st);
     }
     return ABDF_OK;
+}
+
+hipError_t Engine::control(hipStream_t st) {
+    return method_ == ABDF_METHOD_ESDIRK5 ? launch_control_rk(s_, ring_, bound_, st)
+                                          : launch_control(s_, dn_, ring_, bound_, st);
 }
 
 // Below this many occupied slots an attempt runs on one stream.
@@ -412,7 +422,7 @@ int Engine::attempt(hipStream_t st, std::string &err) {
             if (rc != ABDF_OK) return rc;
         }
         t0 = timer_begin(st);
-        HIP_TRY(launch_control(s_, dn_, ring_, bound_, st));
+        HIP_TRY(control(st));
         timer_end(ABDF_PROF_CONTROL, t0, st);
         ring_ = (ring_ + 1) % 3;
         return ABDF_OK;
@@ -430,7 +440,7 @@ int Engine::attempt(hipStream_t st, std::string &err) {
     if (rc != ABDF_OK) return rc;
     HIP_TRY(hipStreamWaitEvent(st, ev_side_, 0));
     t0 = timer_begin(st);
-    HIP_TRY(launch_control(s_, dn_, ring_, bound_, st));
+    HIP_TRY(control(st));
     timer_end(ABDF_PROF_CONTROL, t0, st);
     ring_ = (ring_ + 1) % 3;
     return ABDF_OK;

@@ -108,7 +108,7 @@ class Engine {
     int take_slot() { return free_[--n_free_]; }
     // Admits a.count cells into the slots a.slots (taken with take_slot).
     int admit_cells(const AdmitArgs &a, hipStream_t st, std::string &err);
-    // One step attempt of every running slot.
+    // One step attempt of every running slot (ESDIRK: one stage).
     int attempt(hipStream_t st, std::string &err);
     // Waits for the stream and reads the running and finished counts.
     int sync_counts(hipStream_t st, int &nfin, std::string &err);
@@ -131,6 +131,7 @@ class Engine {
   private:
     int admit(const BatchIO &io, const abdf_options &opt, long long &next, hipStream_t st, std::string &err);
     int newton_iterations(int which, hipStream_t st, std::string &err);
+    hipError_t control(hipStream_t st);   // the method's control kernel
 
     const HostNetwork &net_;
     const DeviceNet &dn_;
@@ -138,6 +139,7 @@ class Engine {
     double lu_reuse_ = 0.0;
     int max_order_ = kMaxOrder;
     double h0_ = 0.0, h_max_ = 0.0;
+    int method_ = 0;   // ABDF_METHOD_*
     int tvar_ = 0;
     double phi_exp_[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     std::vector<double> atol_store_;   // per-species absolute tolerances when the engine owns them

@@ -204,6 +204,107 @@ __device__ __forceinline__ void begin_attempt(const Slots &s, const DeviceNet &n
     }
 }
 
+// ----------------------------------------------------------------- ESDIRK --
+//
+// Kvaerno's seven-stage ESDIRK 5(4) (BIT Numer. Math. 44, 2004): explicit
+// first stage, diagonal gamma = 0.26, stiffly accurate pair (c_6 = c_7 = 1).
+// One stage of every slot per pass of the attempt loop: stage 2 of an attempt
+// queues the factorisation of I - h gamma J(x_n), stages 3..7 reuse it.  The
+// slot's D rows hold x_n (0), F_1 = f(x_n) (1) and G_i = h f(Y_i) (2..7).
+
+constexpr int kRkStages = 7;
+constexpr double kRkGamma = 0.26;
+__constant__ double kRkA[kRkStages][kRkStages] = {
+    {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0},
+    {0.26, 0.26, 0.0, 0.0, 0.0, 0.0, 0.0},
+    {0.13, 0.84033320996790809, 0.26, 0.0, 0.0, 0.0, 0.0},
+    {0.22371961478320505, 0.47675532319799699, -0.06470895363112615, 0.26, 0.0, 0.0, 0.0},
+    {0.16648564323248321, 0.10450018841591720, 0.03631482272098715, -0.13090704451073998, 0.26, 0.0, 0.0},
+    {0.13855640231268224, 0.0, -0.04245337201752043, 0.02446657898003141, 0.61943039072480676, 0.26, 0.0},
+    {0.13659751177640291, 0.0, -0.05496908796538376, -0.04118626728321046, 0.62993304899016403,
+     0.06962479448202728, 0.26}};
+
+// Starts stage cs.stage (2..7) of a running slot whose cs (LDS) is current.
+// Stage 2 opens a step attempt: the step budget, the step-size floor and the
+// landing on t_end are checked, and after an accepted step the Jacobian point
+// moves to x_n.  The stage starts from Y_{i-1} (x_n for stage 2) with
+// psi = Y_{i-1} - x_n - sum_{j<i} a_ij G_j and weights atol + rtol |Y_{i-1}|,
+// so that the corrector kernels solve Y_i = x_n + sum_j a_ij G_j + h gamma f(Y_i)
+// as a BDF corrector with c = h gamma.  Writes cs back to global memory.
+__device__ __forceinline__ void begin_stage_rk(const Slots &s, int slot, SlotCtl &cs, int ring) {
+    const int S = s.S;
+    const int stage = cs.stage;
+    if (threadIdx.x == 0 && stage == 2) {
+        int st = kRunning;
+        if (cs.n_attempts >= s.max_steps) {
+            st = ABDF_CELL_MAX_STEPS;
+        } else {
+            cs.n_attempts += 1;
+            if (cs.h < 10.0 * kURound * fabs(cs.t)) {
+                st = ABDF_CELL_STEP_TOO_SMALL;
+            } else {
+                cs.landing = 0;
+                if (cs.t + cs.h >= cs.t_end) {
+                    cs.h = cs.t_end - cs.t;
+                    cs.landing = 1;
+                }
+            }
+        }
+        cs.status = st;
+    }
+    __syncthreads();
+    if (cs.status != kRunning) {
+        finish_slot(s, slot, cs, cs.status);
+        __syncthreads();
+        if (threadIdx.x == 0) s.ctl[slot] = cs;
+        return;
+    }
+    const double *D = s.D + size_t(slot) * kDRows * S;
+    double *x = s.x + size_t(slot) * S, *d = s.d + size_t(slot) * S, *psi = s.psi + size_t(slot) * S;
+    double *scl = s.scl + size_t(slot) * S, *xJ = s.xJ + size_t(slot) * S;
+    const bool first = stage == 2;
+    const bool refresh = first && cs.jac_refresh != 0;
+    const double h = cs.h;
+    const double *a = kRkA[stage - 1];
+    for (int i = threadIdx.x; i < S; i += kBlock) {
+        const double xn = D[i];
+        double sum = a[0] * (h * D[S + i]);
+        for (int j = 2; j < stage; ++j) sum = sum + a[j - 1] * D[j * S + i];
+        const double xp = first ? xn : x[i];
+        x[i] = xp;
+        d[i] = 0.0;
+        psi[i] = (xp - xn) - sum;
+        scl[i] = atol_of(s, cs, i) + cs.rtol * fabs(xp);
+        if (refresh) xJ[i] = xn;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const double c = h * kRkGamma;
+        if (refresh) {
+            cs.jac_refresh = 0;
+            cs.jv_valid = 0;
+            cs.lu_valid = 0;
+            cs.n_jac += 1;
+        }
+        if (first && c != cs.c_lu) cs.lu_valid = 0;
+        cs.c = c;
+        cs.phase = kIter;
+        cs.newton_iter = 0;
+        cs.eta_old = 0.0;
+        const int p = atomicAdd(&s.cnt[ring], 1);
+        s.act[ring * s.nslots + p] = slot;
+        if (!cs.lu_valid) {
+            const int pl = atomicAdd(&s.cnt[3 + ring], 1);
+            s.lul[ring * s.nslots + pl] = slot;
+        } else {
+            const int pn = atomicAdd(&s.cnt[7 + ring], 1);
+            s.nol[ring * s.nslots + pn] = slot;
+        }
+        s.ctl[slot] = cs;
+    }
+}
+
+
 // --------------------------------------------------------------- kernels --
 
 // Admits cells into slots: copies inputs, rates, starting step, difference
@@ -234,7 +335,8 @@ __global__ void __launch_bounds__(kBlock) k_admit(Slots s, DeviceNet n, AdmitArg
         z.atol = a.atol_c ? a.atol_c[cell] : a.atol;
         z.newton_tol = a.newton_tol > 0.0 ? a.newton_tol
                                           : fmax(10.0 * kURound / z.rtol, fmin(0.03, sqrt(z.rtol)));
-        z.q = 1;
+        z.q = s.method == ABDF_METHOD_ESDIRK5 ? 5 : 1;
+        z.stage = 2;
         z.status = kRunning;
         z.j_fresh = 1;
         z.lu_valid = 0;
@@ -272,7 +374,9 @@ __global__ void __launch_bounds__(kBlock) k_admit(Slots s, DeviceNet n, AdmitArg
         if (threadIdx.x == 0) s.ctl[slot] = cs;
         return;
     }
-    // starting step (Hairer, Norsett & Wanner, Solving ODEs I, Sec. II.4), order 1
+    // starting step (Hairer, Norsett & Wanner, Solving ODEs I, Sec. II.4), for
+    // the method's order: 1 (BDF's first step) or 5 (ESDIRK)
+    const bool rk = s.method == ABDF_METHOD_ESDIRK5;
     cell_rhs(n, k, xs, rate, part, f0);
     {
         // rates that overflow at the initial state leave no step to take
@@ -317,10 +421,10 @@ __global__ void __launch_bounds__(kBlock) k_admit(Slots s, DeviceNet n, AdmitArg
     }
     const double d2 = sqrt(block_sum(s2, red) / S) / h0;
     const double mx = fmax(d1, d2);
-    const double h1 = mx <= 1e-15 ? fmax(1e-6, h0 * 1e-3) : sqrt(0.01 / mx);
+    const double h1 = mx <= 1e-15 ? fmax(1e-6, h0 * 1e-3) : (rk ? pow(0.01 / mx, 1.0 / 6.0) : sqrt(0.01 / mx));
     double h = s.h0 > 0.0 ? fmin(s.h0, cs.t_end) : fmin(fmin(100.0 * h0, h1), cs.t_end);
     if (s.h_max > 0.0) h = fmin(h, s.h_max);
-    for (int i = threadIdx.x; i < S; i += kBlock) D[S + i] = h * f0[i];
+    for (int i = threadIdx.x; i < S; i += kBlock) D[S + i] = rk ? f0[i] : h * f0[i];
     __syncthreads();
     if (threadIdx.x == 0) {
         cs.h = h;
@@ -328,7 +432,10 @@ __global__ void __launch_bounds__(kBlock) k_admit(Slots s, DeviceNet n, AdmitArg
         cs.n_jac = 1;
     }
     __syncthreads();
-    begin_attempt(s, n, slot, cs, ring, RU, sh, phit);
+    if (rk)
+        begin_stage_rk(s, slot, cs, ring);
+    else
+        begin_attempt(s, n, slot, cs, ring, RU, sh, phit);
 }
 
 // Forms M = I - c J(x_J) for every queued slot and factors it (one workgroup
@@ -465,10 +572,10 @@ __device__ __forceinline__ void newton_solve_cell(const Slots &s, const DeviceNe
         double theta = -1.0;
         if (m > 1) {
             theta = eta / g.eta_old;
-            fail = theta >= 1.0 || pow(theta, double(kNewtonMaxIter - m)) / (1.0 - theta) * eta > tol;
+            fail = theta >= 1.0 || pow(theta, double(s.newton_maxiter - m)) / (1.0 - theta) * eta > tol;
         }
         if (!fail) conv = eta == 0.0 || (m > 1 && theta / (1.0 - theta) * eta < tol);
-        if (!fail && !conv && m == kNewtonMaxIter) fail = true;
+        if (!fail && !conv && m == s.newton_maxiter) fail = true;
         g.n_newton_iter += 1;
         g.newton_iter = m;
         g.m_last = m;
@@ -544,7 +651,7 @@ __global__ void __launch_bounds__(kBlock) k_newton_fused(Slots s, DeviceNet n, i
     const int32_t *list = slot_list(s, which, ring, count);
     for (int idx = blockIdx.x; idx < count; idx += gridDim.x) {
         const int slot = list[idx];
-        for (int m = 0; m < kNewtonMaxIter; ++m) {
+        for (int m = 0; m < s.newton_maxiter; ++m) {
             if (s.ctl[slot].phase != kIter) break;
             newton_rhs_cell<kBlock>(s, n, slot, smem, red);
             if (s.ctl[slot].phase != kIter) break;
@@ -729,6 +836,117 @@ __global__ void __launch_bounds__(kBlock) k_control(Slots s, DeviceNet n, int ri
         rescale_D(D, S, cs.q, sh[0], RU);
     }
     begin_attempt(s, n, slot, cs, next, RU, sh + 2, phit);
+}
+
+// Acts on the stage every active slot has just solved and starts its next
+// stage: a converged stage stores G_i = (psi + d) / gamma (its own equation
+// gives h f(Y_i)); after stage 7 the error test Y_7 - Y_6 decides the step.
+__global__ void __launch_bounds__(kBlock) k_control_rk(Slots s, int ring) {
+    __shared__ SlotCtl cs;
+    __shared__ double red[kWaves];
+    const int next = (ring + 1) % 3;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        const int old = (ring + 2) % 3;
+        s.cnt[old] = 0;
+        s.cnt[3 + old] = 0;
+        s.cnt[7 + old] = 0;
+    }
+    const int idx = blockIdx.x;
+    if (idx >= s.cnt[ring]) return;
+    const int slot = s.act[ring * s.nslots + idx];
+    const int S = s.S;
+    if (threadIdx.x == 0) cs = s.ctl[slot];
+    __syncthreads();
+    double *D = s.D + size_t(slot) * kDRows * S;
+    const double *x = s.x + size_t(slot) * S, *d = s.d + size_t(slot) * S, *psi = s.psi + size_t(slot) * S;
+    if (cs.phase == kFailed) {
+        if (threadIdx.x == 0) {
+            cs.n_newton_fail += 1;
+            if (s.prec == ABDF_PREC_FP32_LU && cs.lu_mode != kLu64) {
+                // FP32 factors: the same step again with refined solves, then
+                // with FP64 factors
+                cs.lu_mode += 1;
+                if (cs.lu_mode == kLu64) cs.lu_valid = 0;
+            } else {
+                cs.h = 0.5 * cs.h;
+                cs.rejected = 1;
+            }
+            cs.stage = 2;
+        }
+        __syncthreads();
+        begin_stage_rk(s, slot, cs, next);
+        return;
+    }
+    const int stage = cs.stage;
+    for (int i = threadIdx.x; i < S; i += kBlock) D[stage * S + i] = (psi[i] + d[i]) / kRkGamma;
+    if (stage < kRkStages) {
+        __syncthreads();
+        if (threadIdx.x == 0) cs.stage = stage + 1;
+        __syncthreads();
+        begin_stage_rk(s, slot, cs, next);
+        return;
+    }
+    // error estimate Y_7 - Y_6 = sum_j (a_7j - a_6j) G_j, weights from x_n and Y_7
+    const double h = cs.h, rtol = cs.rtol;
+    double acc = 0.0;
+    for (int i = threadIdx.x; i < S; i += kBlock) {
+        double e = (kRkA[6][0] - kRkA[5][0]) * (h * D[S + i]);
+        for (int j = 2; j <= kRkStages; ++j) e = e + (kRkA[6][j - 1] - kRkA[5][j - 1]) * D[j * S + i];
+        const double sc = atol_of(s, cs, i) + rtol * fmax(fabs(D[i]), fabs(x[i]));
+        const double v = e / sc;
+        acc += v * v;
+    }
+    const double err = sqrt(block_sum(acc, red) / S);
+    if (!isfinite(err)) {
+        finish_slot(s, slot, cs, ABDF_CELL_NONFINITE);
+        __syncthreads();
+        if (threadIdx.x == 0) s.ctl[slot] = cs;
+        return;
+    }
+    if (err > 1.0) {
+        if (threadIdx.x == 0) {
+            cs.n_err_reject += 1;
+            cs.h = cs.h * fmax(kMinFactor, 0.9 * pow(err, -0.2));
+            cs.rejected = 1;
+            cs.stage = 2;
+        }
+        __syncthreads();
+        begin_stage_rk(s, slot, cs, next);
+        return;
+    }
+    // accept: x_{n+1} = Y_7, and F_1 of the next step is G_7 / h
+    bool nonfinite = false;
+    for (int i = threadIdx.x; i < S; i += kBlock) {
+        const double xi = x[i];
+        D[i] = xi;
+        D[S + i] = D[kRkStages * S + i] / h;
+        nonfinite |= !isfinite(xi);
+    }
+    nonfinite = block_any(nonfinite, red);
+    if (threadIdx.x == 0) {
+        cs.t = cs.landing ? cs.t_end : cs.t + h;
+        cs.n_steps += 1;
+        cs.jac_refresh = 1;
+    }
+    __syncthreads();
+    if (nonfinite || cs.landing) {
+        finish_slot(s, slot, cs, nonfinite ? ABDF_CELL_NONFINITE : ABDF_CELL_OK);
+        __syncthreads();
+        if (threadIdx.x == 0) s.ctl[slot] = cs;
+        return;
+    }
+    if (threadIdx.x == 0) {
+        double fac = err == 0.0 ? kMaxFactor : fmin(kMaxFactor, fmax(kMinFactor, 0.9 * pow(err, -0.2)));
+        if (cs.rejected) {
+            fac = fmin(1.0, fac);
+            cs.rejected = 0;
+        }
+        cs.h = h * fac;
+        if (s.h_max > 0.0) cs.h = fmin(cs.h, s.h_max);
+        cs.stage = 2;
+    }
+    __syncthreads();
+    begin_stage_rk(s, slot, cs, next);
 }
 
 // Copies results of finished slots to the caller's arrays.
@@ -1408,6 +1626,11 @@ hipError_t launch_newton_solve(const Slots &s, const DeviceNet &n, int ring, int
     }
     hipLaunchKernelGGL((k_newton_solve<double, false>), dim3(grid), dim3(kBlock), lds, st, s, n, ring, which);
     return LAUNCH_CHECK();
+}
+
+hipError_t launch_control_rk(const Slots &s, int ring, int grid, hipStream_t st) {
+    k_control_rk<<<grid, kBlock, 0, st>>>(s, ring);
+    return hipGetLastError();
 }
 
 hipError_t launch_control(const Slots &s, const DeviceNet &n, int ring, int grid, hipStream_t st) {

@@ -85,6 +85,8 @@ hipError_t launch_newton_fused(const Slots &s, const DeviceNet &n, int ring, int
 hipError_t launch_newton_solve(const Slots &s, const DeviceNet &n, int ring, int which, int grid, int grid_ref,
                                size_t lds, size_t lds_ref, hipStream_t st);
 hipError_t launch_control(const Slots &s, const DeviceNet &n, int ring, int grid, hipStream_t st);
+// ESDIRK: the next stage (or the step decision) of every active slot
+hipError_t launch_control_rk(const Slots &s, int ring, int grid, hipStream_t st);
 hipError_t launch_harvest(const Slots &s, const HarvestArgs &h, hipStream_t st);
 
 hipError_t launch_adj_admit(const Slots &s, const DeviceNet &n, const AdjArgs &a, int ring, size_t lds, hipStream_t st);

@@ -206,3 +206,32 @@ def test_adjoint_entry_points_reject_null_arguments():
     assert L.abdf_phys_gradient(g.handle, -1, *([nul] * 7), nul) == 1
     assert L.abdf_phys_gradient(g.handle, 1, *([hp] * 7), nul) == 1
     assert L.abdf_phys_gradient(g.handle, 0, *([nul] * 7), nul) == 0
+
+
+def test_method_option_checks_without_gpu():
+    import ctypes
+    L = ab._lib.lib()
+    g = ab.Network.from_text(synth.network_for_config("small").to_text())
+    none7 = [None] * 7
+    assert ab.default_options().method == 0
+    o = ab.make_options(method=7)
+    assert L.abdf_solve(g.handle, 1, *none7, ctypes.byref(o), None, None, None, None) == 1
+    assert b"unknown method" in L.abdf_last_error()
+    # the ESDIRK method factors every attempt and takes constant conditions
+    o = ab.make_options(method="esdirk5", lu_reuse=0.3)
+    assert L.abdf_solve(g.handle, 1, *none7, ctypes.byref(o), None, None, None, None) == 1
+    assert b"lu_reuse" in L.abdf_last_error()
+    o = ab.make_options(method="esdirk5")
+    host = (ctypes.c_double * 4)()
+    o.phi_tc = ctypes.cast(host, ctypes.c_void_p)
+    assert L.abdf_solve(g.handle, 1, *none7, ctypes.byref(o), None, None, None, None) == 1
+    assert b"ESDIRK" in L.abdf_last_error()
+    o = ab.make_options(method="esdirk5")
+    assert L.abdf_solve(g.handle, 0, *none7, ctypes.byref(o), None, None, None, None) == 0
+    # the server runs the BDF method
+    so = ab._lib.ServerOptions()
+    L.abdf_server_options_default(ctypes.byref(so))
+    so.solve.method = 1
+    srv = ctypes.c_void_p()
+    assert L.abdf_server_create(g.handle, ctypes.byref(so), ctypes.byref(srv)) == 1
+    assert b"BDF" in L.abdf_last_error() and not srv.value
