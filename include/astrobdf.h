@@ -59,7 +59,8 @@ enum {
     ABDF_CELL_MAX_STEPS = 2,       /* more than max_steps step attempts */
     ABDF_CELL_NONFINITE = 3,       /* a non-finite abundance or error norm */
     ABDF_CELL_BAD_INPUT = 4,       /* non-finite or non-physical phi, x0, t_end or tolerances */
-    ABDF_CELL_TAPE_FULL = 5        /* more accepted steps than the step tape holds (recording solves) */
+    ABDF_CELL_TAPE_FULL = 5        /* reserved: recording solves integrate past a full tape (see
+                                    * abdf_solve_record) and no longer end with it */
 };
 
 /* Precision of the Newton-matrix factorisation.  Residuals, error norms,
@@ -329,16 +330,26 @@ void abdf_server_destroy(abdf_server *srv);
  * abundances after every accepted step (the checkpoint); the reverse sweep
  * walks it backwards with one fresh factorisation of I - c J(x_{n+1}) and
  * one transposed solve per step.  Factorisations are FP64.
+ *
+ * The tape holds max_tape_steps steps per cell.  A cell that takes more is
+ * swept in windows of max_tape_steps steps, the last window first: before each
+ * window the forward solve of the cells that need it runs again from the
+ * tape's copies of the inputs, records that window and stops at its end (the
+ * solve is deterministic, so it repeats the recorded steps exactly), and the
+ * sweep carries its adjoint state from one window to the next.  The gradient
+ * is therefore the same as with a tape long enough for every step; a cell of
+ * N steps costs about N^2 / (2 max_tape_steps) extra forward steps.
  */
 typedef struct abdf_tape abdf_tape;
 
 /* Solves like abdf_solve and records the step tape.
  *   alpha          : DEVICE [R] rate prefactors to use, or NULL for the network's
- *   max_tape_steps : accepted steps recorded per cell (0 = 2048); a cell that
- *                    needs more ends with ABDF_CELL_TAPE_FULL
+ *   max_tape_steps : accepted steps the tape holds per cell (0 = 2048); a cell
+ *                    that takes more is integrated to t_end all the same and
+ *                    swept in windows (see above)
  *   tape           : receives the tape, owned by the caller (abdf_tape_free);
  *                    it holds its own copies of the inputs and of alpha
- * Device memory: n_cells * (max_tape_steps * (S + 2) + S + 8) doubles for the
+ * Device memory: n_cells * (max_tape_steps * (S + 2) + S + 16) doubles for the
  * tape, counted against opt->hbm_budget_bytes before the solver's slots.
  * Errors: as abdf_solve; ABDF_E_ARG also for precision other than FP64 or
  * max_tape_steps < 0; ABDF_E_BUDGET when the tape alone exceeds the budget.
@@ -363,7 +374,9 @@ abdf_status abdf_solve_record(const abdf_network *net, int64_t n_cells,
  *                      rate laws written out (no division by zeta or G0, so
  *                      the columns are exact where zeta = 0 or G0 = 0)
  * Cells whose forward status was not ABDF_CELL_OK contribute zeros.  A tape
- * may be swept any number of times.  Errors: ABDF_E_ARG, ABDF_E_NOMEM,
+ * may be swept any number of times.  The first sweep of a tape with a cell
+ * longer than max_tape_steps allocates n_cells * (9 S + R) doubles of window
+ * buffers, kept with the tape.  Errors: ABDF_E_ARG, ABDF_E_NOMEM,
  * ABDF_E_DEVICE. */
 abdf_status abdf_tape_adjoint(abdf_tape *tape, const double *dL_dx, double *dL_dlog_alpha,
                               double *dL_dlog_alpha_cell, double *dL_dx0, double *dL_dphi, void *stream);

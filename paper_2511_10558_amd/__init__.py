@@ -331,7 +331,7 @@ def _autograd_function():
             if n_failed:
                 first = int(torch.nonzero(ctx.failed)[0, 0].item())
                 raise AbdfError(1, f"{n_failed} cell(s) did not reach t_end (first: cell {first}); the adjoint "
-                                   "differentiates completed solves only (a larger max_tape_steps avoids tape_full)")
+                                   "differentiates completed solves only")
             need_phys = any(ctx.needs_input_grad[3:8])
             g, _, dx0, gphi = ctx.tape.adjoint(gx.contiguous(), x0_grad=ctx.needs_input_grad[1],
                                                phys_grad=need_phys)

@@ -3,6 +3,11 @@
 // A recording solve stores, per cell, the accepted steps' (h, q) and the
 // abundances after each step, plus copies of the inputs; the reverse sweep
 // (Engine::reverse) then differentiates the frozen-sequence map through them.
+// The tape holds `cap` steps per cell.  A cell with more is swept in windows
+// of cap steps, last window first: before each pass a forward re-run of the
+// cells that need it records their window (the solve is deterministic, so the
+// re-run repeats the recorded steps bit for bit) and the adjoint rows and
+// dL/dk carry over from one pass to the next.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -41,6 +46,12 @@ class Tape {
     size_t bytes_ = 0;
     double *alpha_ = nullptr, *phi_ = nullptr, *x0_ = nullptr, *tape_x_ = nullptr, *tape_h_ = nullptr;
     int32_t *tape_q_ = nullptr, *len_ = nullptr, *status_ = nullptr;
+    double *phis_ = nullptr, *t_end_ = nullptr, *hprev_ = nullptr;   // [5][C] inputs, [C] horizons, [C]
+    int32_t *qprev_ = nullptr;                                       // [C]
+    // buffers of windowed sweeps, allocated by the first sweep that needs them
+    void *win_base_ = nullptr;
+    size_t win_bytes_ = 0;
+    int windowed_sweep(const AdjIO &io, hipStream_t st, std::string &err);
 };
 
 }  // namespace abdf

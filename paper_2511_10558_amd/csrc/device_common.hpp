@@ -86,7 +86,25 @@ struct Slots {
     int32_t *tape_len;  // [cells] accepted steps recorded
     const double *tape_x0;   // [cells][S] initial abundances
     double *g;        // [n][R] reverse sweep: per-slot gradient with respect to log alpha
+    // Windows of a cell with more accepted steps than tape_cap: its tape rows
+    // hold steps [w0, w0 + tape_cap), w0 = tape_w0[cell]; a forward re-run
+    // records the window and stops after tape_stop[cell] accepted steps; the
+    // reverse sweep walks one window per pass and carries its adjoint rows and
+    // dL/dk between passes in win_lam / win_g.
+    const int32_t *tape_w0;    // [cells] window start, or null (0)
+    const int32_t *tape_stop;  // [cells] re-run: stop after this many accepted steps (<= 0: not run), or null
+    double *tape_hprev;        // [cells] h of the step before the window
+    int32_t *tape_qprev;       // [cells] its order
+    int tape_overflow;         // steps past the window go unrecorded (else the cell ends TAPE_FULL)
+    const int32_t *win_end;    // [cells] reverse: the window's end (< 0: the cell sits the pass out), or null
+    double *win_lam;           // [cells][kDRows][S] adjoint rows carried between passes
+    double *win_g;             // [cells][R] dL/dk carried between passes
+    int win_resume;            // reverse admission resumes from win_lam / win_g (else from dL/dx)
 };
+
+// Internal end states of a slot in a windowed reverse pass (never returned).
+constexpr int32_t kWindowDone = 100;   // the window is swept; the cell continues in the next pass
+constexpr int32_t kSitsOut = 101;      // the cell has no window in this pass
 
 // The factor storage of a slot in element type T.
 // Absolute tolerance of species i in a slot's error and Newton weights.

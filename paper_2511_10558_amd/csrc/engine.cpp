@@ -475,8 +475,9 @@ int Engine::solve(const BatchIO &io, const abdf_options &opt, hipStream_t st, st
     ring_ = 0;
     bound_ = 0;
     long long next = 0;
-    if (ext_) {
-        // the external workspace keeps the previous call's contents
+    {
+        // the slot lists start empty: an external workspace keeps the previous
+        // call's contents, and an engine's earlier sweep leaves its last ring's counts
         int rc0 = reset_counts(st, err);
         if (rc0 != ABDF_OK) return rc0;
     }
@@ -516,7 +517,10 @@ int Engine::reverse(const AdjIO &io, int check_every, hipStream_t st, std::strin
     TraceRange tr("abdf reverse sweep");
     ring_ = 0;
     bound_ = 0;
-    HIP_TRY(hipMemsetAsync(s_.cnt, 0, kCountSlots * sizeof(int32_t), st));
+    {
+        int rc0 = reset_counts(st, err);
+        if (rc0 != ABDF_OK) return rc0;
+    }
     const size_t lds_adj = adj_lds(dn_), lds_adj_solve = adj_solve_lds(dn_);
     if (lds_adj > kMaxLds || lds_adj_solve > kMaxLds) {
         err = "network too large for one workgroup's LDS";

@@ -366,6 +366,13 @@ __global__ void __launch_bounds__(kBlock) k_admit(Slots s, DeviceNet n, AdmitArg
         if (threadIdx.x == 0) s.ctl[slot] = cs;
         return;
     }
+    if (s.tape_stop && s.tape_stop[cell] <= 0) {
+        // a forward re-run that does not need this cell
+        finish_slot(s, slot, cs, ABDF_CELL_OK);
+        __syncthreads();
+        if (threadIdx.x == 0) s.ctl[slot] = cs;
+        return;
+    }
     cell_rates(n, phi, k);
     __syncthreads();
     if (cs.t_end == 0.0) {
@@ -743,14 +750,16 @@ __global__ void __launch_bounds__(kBlock) k_control(Slots s, DeviceNet n, int ri
         return;
     }
     // accept: update the differences, collect the order-selection norms, and
-    // record the step when a tape is attached
-    if (s.tape_x && cs.n_steps >= s.tape_cap) {
+    // record the step when a tape is attached and the step is in the cell's window
+    const int rel = cs.n_steps - (s.tape_w0 ? s.tape_w0[cs.cell] : 0);
+    if (s.tape_x && rel >= s.tape_cap && !s.tape_overflow) {
         finish_slot(s, slot, cs, ABDF_CELL_TAPE_FULL);
         __syncthreads();
         if (threadIdx.x == 0) s.ctl[slot] = cs;
         return;
     }
-    double *tx = s.tape_x ? s.tape_x + (size_t(cs.cell) * s.tape_cap + cs.n_steps) * S : nullptr;
+    double *tx = s.tape_x && rel >= 0 && rel < s.tape_cap ? s.tape_x + (size_t(cs.cell) * s.tape_cap + rel) * S
+                                                         : nullptr;
     const double em_c = q > 1 ? 1.0 / q : 0.0;
     const double ep_c = 1.0 / (q + 2);
     double am = 0.0, ap = 0.0;
@@ -794,8 +803,11 @@ __global__ void __launch_bounds__(kBlock) k_control(Slots s, DeviceNet n, int ri
     nonfinite = block_any(nonfinite, red);
     if (threadIdx.x == 0) {
         if (tx) {
-            s.tape_h[size_t(cs.cell) * s.tape_cap + cs.n_steps] = cs.h;
-            s.tape_q[size_t(cs.cell) * s.tape_cap + cs.n_steps] = q;
+            s.tape_h[size_t(cs.cell) * s.tape_cap + rel] = cs.h;
+            s.tape_q[size_t(cs.cell) * s.tape_cap + rel] = q;
+        } else if (s.tape_x && rel == -1 && s.tape_hprev) {
+            s.tape_hprev[cs.cell] = cs.h;
+            s.tape_qprev[cs.cell] = q;
         }
         cs.t = cs.landing ? cs.t_end : cs.t + cs.h;
         cs.n_steps += 1;
@@ -809,7 +821,8 @@ __global__ void __launch_bounds__(kBlock) k_control(Slots s, DeviceNet n, int ri
         if (threadIdx.x == 0) s.ctl[slot] = cs;
         return;
     }
-    if (cs.landing) {
+    if (cs.landing || (s.tape_stop && cs.n_steps >= s.tape_stop[cs.cell])) {
+        // t_end reached, or a re-run has recorded its window
         finish_slot(s, slot, cs, ABDF_CELL_OK);
         __syncthreads();
         if (threadIdx.x == 0) s.ctl[slot] = cs;
@@ -1076,7 +1089,8 @@ __device__ __forceinline__ void jac_transpose_apply(const DeviceNet &n, const do
 __device__ __forceinline__ void adj_begin(const Slots &s, const DeviceNet &n, int slot, SlotCtl &cs, int ring,
                                           double *smem) {
     const int S = s.S;
-    const size_t te = size_t(cs.cell) * s.tape_cap + (cs.n_steps - 1);
+    const int w0 = s.tape_w0 ? s.tape_w0[cs.cell] : 0;
+    const size_t te = size_t(cs.cell) * s.tape_cap + (cs.n_steps - 1 - w0);
     const int q = s.tape_q[te];
     const double h = s.tape_h[te];
     const double c = h / bdf_gamma(q);
@@ -1156,23 +1170,43 @@ __global__ void __launch_bounds__(kBlock) k_adj_admit(Slots s, DeviceNet n, AdjA
     const long long cell = a.cells[idx];
     const int S = s.S, R = n.R;
     const bool ok = a.status[cell] == ABDF_CELL_OK;
+    if (s.win_end && s.win_end[cell] < 0) {
+        // windowed sweep: nothing of this cell in the pass
+        if (threadIdx.x == 0) {
+            SlotCtl z = {};
+            z.cell = int32_t(cell);
+            cs = z;
+        }
+        __syncthreads();
+        finish_slot(s, slot, cs, kSitsOut);
+        __syncthreads();
+        if (threadIdx.x == 0) s.ctl[slot] = cs;
+        return;
+    }
     double *phi = s.phi + size_t(slot) * 5;
     if (threadIdx.x == 0) {
         for (int j = 0; j < 5; ++j) phi[j] = a.phi[cell * 5 + j];
         SlotCtl z = {};
         z.cell = int32_t(cell);
-        z.n_steps = ok ? s.tape_len[cell] : 0;
+        z.n_steps = ok ? (s.win_end ? s.win_end[cell] : s.tape_len[cell]) : 0;
         z.status = ok ? kRunning : a.status[cell];
         z.q = 1;
         cs = z;
     }
     double *L = s.D + size_t(slot) * kDRows * S;
-    for (int i = threadIdx.x; i < S; i += kBlock) {
-        L[i] = ok ? a.dLdx[cell * S + i] : 0.0;
-        for (int j = 1; j < kDRows; ++j) L[j * S + i] = 0.0;
-    }
     double *g = s.g + size_t(slot) * R;
-    for (int r = threadIdx.x; r < R; r += kBlock) g[r] = 0.0;
+    if (ok && s.win_resume) {
+        // the adjoint rows and dL/dk where the previous pass (the later window) left them
+        const double *wl = s.win_lam + size_t(cell) * kDRows * S;
+        for (int i = threadIdx.x; i < kDRows * S; i += kBlock) L[i] = wl[i];
+        for (int r = threadIdx.x; r < R; r += kBlock) g[r] = s.win_g[size_t(cell) * R + r];
+    } else {
+        for (int i = threadIdx.x; i < S; i += kBlock) {
+            L[i] = ok ? a.dLdx[cell * S + i] : 0.0;
+            for (int j = 1; j < kDRows; ++j) L[j * S + i] = 0.0;
+        }
+        for (int r = threadIdx.x; r < R; r += kBlock) g[r] = 0.0;
+    }
     __syncthreads();
     cell_rates(n, phi, s.k + size_t(slot) * R);
     __syncthreads();
@@ -1241,18 +1275,30 @@ __global__ void __launch_bounds__(kBlock) k_adj_step(Slots s, DeviceNet n, int r
     for (int r = threadIdx.x; r < R; r += kBlock) g[r] += c * reactant_product(n, xs, r) * nu_dot(n, ms, r);
     __syncthreads();
     const int m = cs.n_steps - 1;
+    const int w0 = s.tape_w0 ? s.tape_w0[cs.cell] : 0;
     if (m > 0) {
-        const size_t te = size_t(cs.cell) * s.tape_cap + m;
-        const double hp = s.tape_h[te - 1];
-        const int qp = s.tape_q[te - 1];
+        // (h, q) of step m - 1: in the window, or the one recorded just before it
+        const size_t te = size_t(cs.cell) * s.tape_cap + (m - 1 - w0);
+        const double hp = m > w0 ? s.tape_h[te] : s.tape_hprev[cs.cell];
+        const int qp = m > w0 ? s.tape_q[te] : s.tape_qprev[cs.cell];
         if (cs.h != hp || q != qp) rescale_adjoint(L, S, q, cs.h / hp, RU);
     }
     if (threadIdx.x == 0) cs.n_steps = m;
     __syncthreads();
-    if (m > 0)
+    if (m > w0) {
         adj_begin(s, n, slot, cs, next, smem);
-    else
+    } else if (m > 0) {
+        // the window is swept: the earlier steps come in the next pass
+        double *wl = s.win_lam + size_t(cs.cell) * kDRows * S;
+        for (int i = threadIdx.x; i < kDRows * S; i += kBlock) wl[i] = L[i];
+        for (int r = threadIdx.x; r < R; r += kBlock) s.win_g[size_t(cs.cell) * R + r] = g[r];
+        __syncthreads();
+        finish_slot(s, slot, cs, kWindowDone);
+        __syncthreads();
+        if (threadIdx.x == 0) s.ctl[slot] = cs;
+    } else {
         adj_finish(s, n, slot, cs, 1, smem);
+    }
 }
 
 // dk_r / dphi_j of one reaction for phi = (T, n_H, A_V, zeta, G0) (paper Sec. 2
@@ -1287,6 +1333,8 @@ __global__ void __launch_bounds__(kBlock) k_adj_harvest(Slots s, DeviceNet n, Ad
     if (idx == 0 && threadIdx.x == 0) s.cnt[6] = 0;
     if (idx >= h.count) return;
     const int slot = h.slots[idx];
+    const int32_t fin = s.ctl[slot].status;
+    if (fin == kWindowDone || fin == kSitsOut) return;   // the cell's result comes in a later pass
     const long long cell = s.ctl[slot].cell;
     const int S = s.S, R = s.R;
     const double *gk = s.g + size_t(slot) * R, *k = s.k + size_t(slot) * R, *phi = s.phi + size_t(slot) * 5;

@@ -159,14 +159,18 @@ def test_net500_matches_oracle_sensitivities_and_central_differences(ab, dev):
     assert (st == 0).all()
     for c, rec in enumerate(gold["cells"]):
         sens, cs, fd = np.array(rec["sens"]), np.array(rec["cs"]), np.array(rec["fd"])
-        # each reference of the golden file: the oracle's forward sensitivities,
+        top = np.abs(cs).max()
+        # the references of the golden file: the oracle's forward sensitivities,
         # the complex-step derivative of its frozen map and central differences
-        # of that map replayed in extended precision (they agree to 1e-6 of the
-        # largest entry); the GPU gradient within 1e-3 of each, entry by entry
-        # over all 50 reactions, relative to the entry with a floor of 1e-3 of
-        # the largest
+        # of that map replayed in extended precision.  The differences stay
+        # within 1.5e-6 of the largest entry of the complex-step values (1.2e-6
+        # measured), which bounds what any entry-wise comparison can resolve;
+        # the GPU also differentiates its own step sequence, which differs from
+        # the oracle's at the tolerance (rtol 1e-6).  Bar, entry by entry over
+        # all 50 reactions: 1e-3 of the entry plus 2e-6 of the largest
+        assert np.max(np.abs(fd - cs)) <= 1.5e-6 * top and np.max(np.abs(sens - cs)) <= 1e-7 * top
         for ref in (sens, cs, fd):
-            assert grad_ok(gc[c, reactions], ref) <= 1e-3
+            assert np.all(np.abs(gc[c, reactions] - ref) <= 1e-3 * np.abs(ref) + 2e-6 * top)
         assert np.all(np.isfinite(gc[c]))
     assert np.allclose(gs, gc.sum(axis=0), rtol=1e-12, atol=0)
 
@@ -238,11 +242,38 @@ def test_failed_and_empty_cells_contribute_nothing(ab, dev):
     assert np.array_equal(alone[3][0], gc[0]) and np.array_equal(alone[4][0], dx0[0])
 
 
-def test_tape_capacity_is_reported(ab, dev):
-    net = synth.network_for_config("small")
-    g = ab.Network.from_text(net.to_text())
-    cells = synth.sample_cells(net, 2, seed=95, t_end_yr=1e5)
-    args = [t(v, dev) for v in (cells.T, cells.n_H, cells.A_V, cells.zeta, cells.G0, cells.x0, cells.t_end)]
-    x, st, tape = ab.solve_record(g, *args, max_tape_steps=5)
-    assert (st.cpu().numpy() == 5).all()
+def _record_and_sweep(ab, g, args, dLdx, cap, sweeps=1):
+    import torch
+    x, st, tape = ab.solve_record(g, *args, max_tape_steps=cap)
+    outs = [tape.adjoint(dLdx, per_cell=True, x0_grad=True, phys_grad=True) for _ in range(sweeps)]
+    torch.cuda.synchronize()
     tape.free()
+    return x.cpu().numpy(), st.cpu().numpy(), [[v.cpu().numpy() for v in o] for o in outs]
+
+
+@pytest.mark.parametrize("name,n,seed,t_end_yr,cap", [("small", 3, 95, 1e5, 7), ("net200", 40, 96, 1e6, 150)])
+def test_cells_longer_than_the_tape_are_swept_in_windows(ab, dev, name, n, seed, t_end_yr, cap):
+    # a tape far shorter than the cells' step counts: the forward solve still
+    # reaches t_end, and the windowed sweep (forward re-runs of each window,
+    # the adjoint state carried between windows) gives bitwise the gradients
+    # of a tape that holds every step, sweep after sweep.  The batch mixes in a
+    # cell with no steps (t_end = 0) and one with bad input (zero gradients);
+    # the 40-cell batch runs the two-stream attempts in its re-runs
+    net = synth.network_for_config(name)
+    g = ab.Network.from_text(net.to_text())
+    cells = synth.sample_cells(net, n, seed=seed, t_end_yr=t_end_yr)
+    cells.t_end[1] = 0.0
+    cells.T[2] = -5.0
+    args = [t(v, dev) for v in (cells.T, cells.n_H, cells.A_V, cells.zeta, cells.G0, cells.x0, cells.t_end)]
+    dLdx = t(np.random.default_rng(seed).normal(size=cells.x0.shape), dev)
+    xf, sf, (gf,) = _record_and_sweep(ab, g, args, dLdx, 100000)
+    xw, sw, gw = _record_and_sweep(ab, g, args, dLdx, cap, sweeps=2)
+    assert sf[2] == 4 and sf[1] == 0 and (np.delete(sf, 2) == 0).all()
+    assert np.array_equal(sw, sf) and np.array_equal(xw, xf)
+    _, _, tp, stats = ab.solve_record(g, *args, max_tape_steps=cap, with_stats=True)
+    tp.free()
+    assert stats["n_steps"].max() > 3 * cap          # several windows
+    for run in gw:
+        for a, b in zip(run, gf):
+            assert np.array_equal(a, b)
+    assert not gw[0][1][2].any()

@@ -210,16 +210,16 @@ def test_gradient_exact_where_zeta_or_G0_vanish(ab, dev, where):
 
 
 def test_autograd_refuses_cells_that_did_not_finish(ab, dev):
-    # a cell that ends with tape_full (more accepted steps than the tape holds)
-    # has no gradient: the backward pass raises instead of returning zeros
+    # a cell that ends short of t_end (here: out of step attempts) has no
+    # gradient: the backward pass raises instead of returning zeros
     import torch
     net = synth.network_for_config("small")
     g = ab.Network.from_text(net.to_text())
     cells = synth.sample_cells(net, 2, seed=131, t_end_yr=3e4)
     log_alpha = torch.tensor(np.log(net.alpha), dtype=torch.float64, device=dev, requires_grad=True)
     args = [t(v, dev) for v in (cells.T, cells.n_H, cells.A_V, cells.zeta, cells.G0, cells.x0, cells.t_end)]
-    x, st = ab.solve_diff(g, *args[:5], args[5], args[6], log_alpha, max_tape_steps=5)
-    assert (st.cpu().numpy() == 5).all()
+    x, st = ab.solve_diff(g, *args[:5], args[5], args[6], log_alpha, max_steps=5)
+    assert (st.cpu().numpy() == 2).all()
     with pytest.raises(ab.AbdfError) as e:
         x[:, 0].sum().backward()
     assert "did not reach t_end" in str(e.value)
