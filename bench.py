@@ -439,6 +439,8 @@ def main():
                     help="skip the run with the other factorisation policy (0 if --lu-reuse > 0, else 0.3)")
     ap.add_argument("--no-compare-fp32", dest="compare_fp32", action="store_false",
                     help="skip the FP32-LU run of the same batch")
+    ap.add_argument("--method", default="bdf", choices=["bdf", "esdirk5"],
+                    help="integrator of the timed solve (the ESDIRK runs with lu_reuse 0)")
     ap.add_argument("--no-compare-esdirk", dest="compare_esdirk", action="store_false",
                     help="skip the ESDIRK solve of the same batch")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -474,7 +476,8 @@ def main():
     g = ab.Network.from_text(net.to_text())
     t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float64, device=dev)
     inp = [t(cells.T), t(cells.n_H), t(cells.A_V), t(cells.zeta), t(cells.G0), t(cells.x0), t(cells.t_end)]
-    opts = ab.make_options(rtol=1e-6, atol=1e-20, precision=args.precision, lu_reuse=args.lu_reuse)
+    opts = ab.make_options(rtol=1e-6, atol=1e-20, precision=args.precision,
+                           lu_reuse=args.lu_reuse if args.method == "bdf" else 0.0, method=args.method)
 
     if args.calibrate_copy:
         src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device=dev)
@@ -571,8 +574,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.network}: {S} species / {R} reactions, batch of {args.cells} cells, "
                                f"t_end {args.t_end_yr:g} yr, rtol 1e-6 atol 1e-20, {args.precision} Newton LU"
-                               + (f", factorisation kept while |c/c_lu - 1| <= {args.lu_reuse:g}" if args.lu_reuse else ""),
+                               + (f", factorisation kept while |c/c_lu - 1| <= {args.lu_reuse:g}"
+                                  if args.lu_reuse and args.method == "bdf" else "")
+                               + (", Kvaerno 5(4) ESDIRK" if args.method == "esdirk5" else ""),
                    "cells": args.cells, "species": S, "reactions": R, "precision": args.precision,
+                   "method": args.method,
                    "parallelism": "one GPU, cells across workgroups"},
         "work": {"cells_ok": ok, "factorisations": int(n_lu), "newton_iterations": int(n_newton),
                  "step_attempts": int(n_att)},
@@ -594,7 +600,7 @@ def main():
         out["fp32_lu"] = {"value": round(ok32 / w32, 3), "unit": "cell-solves/s", "cells_ok": ok32,
                           "speedup_vs_fp64": round((ok32 / w32) / value, 4),
                           "max_rel_dev_from_fp64_gpu": max_rel_err(x32.cpu().numpy(), x64)}
-    if args.compare_reuse:
+    if args.compare_reuse and args.method == "bdf":
         # the same batch with the other factorisation policy: refactor whenever c
         # changes (the oracle's), or keep factorisations across small changes of c
         other = 0.0 if args.lu_reuse > 0 else 0.3
@@ -610,7 +616,7 @@ def main():
                                  "cells_ok": okr, "ratio_to_value": round((okr / wr) / value, 4),
                                  "factorisations": int(sr["n_lu"].sum()),
                                  "max_rel_dev_from_headline_gpu": max_rel_err(xr.cpu().numpy(), x64)}
-    if args.compare_esdirk and args.precision == "fp64":
+    if args.compare_esdirk and args.precision == "fp64" and args.method == "bdf":
         # the same batch integrated with Kvaerno's 5(4) ESDIRK (FP64 factors,
         # one factorisation per step attempt)
         o_rk = ab.make_options(rtol=1e-6, atol=1e-20, precision="fp64", method="esdirk5")

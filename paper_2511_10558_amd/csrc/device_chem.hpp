@@ -29,26 +29,34 @@ __device__ inline void cell_rates(const DeviceNet &n, const double *phi, double 
 
 // out_i = sum_r nu_ir v_r for per-reaction values v (LDS): each species' row of
 // the stoichiometry in segments of up to 32 entries (part[n_seg], LDS), then
-// the segments of a species in order.  Deterministic.
-// A segment's entries are loaded eight at a time before any is used, so the
-// loads are in flight together; the sum still runs entry by entry in order.
+// the segments of a species in order.  Deterministic: a segment's entries are
+// summed in order from zero whichever lane takes it.
+// Each wave takes groups of 64 segments in the layout of DeviceNet::sg_ent, so
+// that its loads of the j-th entries of its lanes' segments are adjacent
+// (one or two cache lines instead of 64).  The entries are loaded eight at a
+// time before any is used, so the loads are in flight together.
 template <int NT = kBlock>
 __device__ __forceinline__ void species_gather(const DeviceNet &n, const double *v, double *part, double *out) {
-    for (int s = threadIdx.x; s < n.n_seg; s += NT) {
-        const int e0 = n.seg_beg[s], e1 = n.seg_beg[s + 1];
+    constexpr int kB = 8;
+    const int lane = threadIdx.x & 63;
+    for (int g = threadIdx.x >> 6; g < n.n_sgroup; g += NT / 64) {
+        const int meta = n.sg_lane[g * 64 + lane];
+        const int L = n.sg_len[g];
+        const int mine = meta < 0 ? 0 : (meta & 63);
+        const int32_t *ent = n.sg_ent + n.sg_base[g] + lane;
         double acc = 0.0;
-        for (int eb = e0; eb < e1; eb += 8) {
-            int w[8];
+        for (int jb = 0; jb < L; jb += kB) {
+            int w[kB];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) w[u] = eb + u < e1 ? n.f_ent[eb + u] : 4;   // 4: coefficient 0, entry 0
-            double vv[8];
+            for (int u = 0; u < kB; ++u) w[u] = jb + u < mine ? ent[(jb + u) * 64] : 4;   // 4: coefficient 0, entry 0
+            double vv[kB];
 #pragma unroll
-            for (int u = 0; u < 8; ++u) vv[u] = v[w[u] >> 3];
+            for (int u = 0; u < kB; ++u) vv[u] = v[w[u] >> 3];
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
-                if (eb + u < e1) acc += double((w[u] & 7) - 4) * vv[u];
+            for (int u = 0; u < kB; ++u)
+                if (jb + u < mine) acc += double((w[u] & 7) - 4) * vv[u];
         }
-        part[s] = acc;
+        if (meta >= 0) part[meta >> 6] = acc;
     }
     __syncthreads();
     for (int i = threadIdx.x; i < n.S; i += NT) {
@@ -62,21 +70,23 @@ __device__ __forceinline__ void species_gather(const DeviceNet &n, const double 
 // f = nu . rate(x) for one cell.  x in LDS; k in global memory (one coalesced
 // pass); rate[R] and part[n_seg] are LDS scratch; f may be LDS or global.
 // Deterministic: every sum runs in a fixed order.
-template <int NT = kBlock>
+// kWide: more loads in flight per thread, for kernels with registers to spare.
+template <int NT = kBlock, bool kWide = false>
 __device__ __forceinline__ void cell_rhs(const DeviceNet &n, const double *__restrict__ k, const double *x,
                                 double *rate, double *part, double *f) {
-    // four reactions per thread per pass, their loads issued before any use
-    for (int r0 = threadIdx.x; r0 < n.R; r0 += 4 * NT) {
-        int ab[4];
-        double kr[4];
+    // kU reactions per thread per pass, their loads issued before any use
+    constexpr int kU = kWide ? 6 : 4;
+    for (int r0 = threadIdx.x; r0 < n.R; r0 += kU * NT) {
+        int ab[kU];
+        double kr[kU];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kU; ++u) {
             const int r = r0 + u * NT;
             ab[u] = r < n.R ? n.rx_ab[r] : 0;
             kr[u] = r < n.R ? k[r] : 0.0;
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < kU; ++u) {
             const int r = r0 + u * NT;
             const int a = ab[u] & 0xffff, b = (ab[u] >> 16) & 0xffff;
             double v = kr[u] * x[a];

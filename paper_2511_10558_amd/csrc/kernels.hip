@@ -603,8 +603,8 @@ __device__ __forceinline__ void newton_solve_cell(const Slots &s, const DeviceNe
 
 // Newton residuals of every listed slot still iterating (persistent), with
 // kRhsThreads per slot: the residual's LDS (the rates) allows two workgroups per
-// CU, so each takes more waves.
-constexpr int kRhsThreads = 512;
+// CU, so each takes sixteen waves and the CU runs its full 32.
+constexpr int kRhsThreads = 1024;
 __global__ void __launch_bounds__(kRhsThreads) k_newton_rhs(Slots s, DeviceNet n, int ring, int which) {
     extern __shared__ double smem[];
     __shared__ double red[kRhsThreads / 64];
@@ -1424,13 +1424,14 @@ __global__ void __launch_bounds__(kBlock) k_rates_only(DeviceNet n, PhysArgs p, 
     cell_rates(n, phi, k_out + size_t(c) * n.R);
 }
 
-__global__ void __launch_bounds__(kBlock) k_rhs_only(DeviceNet n, const double *k, const double *x, double *f) {
+__global__ void __launch_bounds__(kRhsThreads) __attribute__((amdgpu_waves_per_eu(8)))
+k_rhs_only(DeviceNet n, const double *k, const double *x, double *f) {
     extern __shared__ double smem[];
     const long long c = blockIdx.x;
     double *xs = smem, *rate = xs + n.S, *part = rate + n.R;
-    for (int i = threadIdx.x; i < n.S; i += kBlock) xs[i] = x[size_t(c) * n.S + i];
+    for (int i = threadIdx.x; i < n.S; i += kRhsThreads) xs[i] = x[size_t(c) * n.S + i];
     __syncthreads();
-    cell_rhs(n, k + size_t(c) * n.R, xs, rate, part, f + size_t(c) * n.S);
+    cell_rhs<kRhsThreads, true>(n, k + size_t(c) * n.R, xs, rate, part, f + size_t(c) * n.S);
 }
 
 // Writes the unpadded S x S Newton matrix of each cell through the solver's
@@ -1734,7 +1735,7 @@ hipError_t launch_rates(const DeviceNet &n, const PhysArgs &p, long long cells, 
 
 hipError_t launch_rhs(const DeviceNet &n, long long cells, const double *k, const double *x, double *f, hipStream_t st) {
     const size_t lds = sizeof(double) * (size_t(n.S) + n.R + n.n_seg);
-    hipLaunchKernelGGL(k_rhs_only, dim3(cells), dim3(kBlock), lds, st, n, k, x, f);
+    hipLaunchKernelGGL(k_rhs_only, dim3(cells), dim3(kRhsThreads), lds, st, n, k, x, f);
     return LAUNCH_CHECK();
 }
 

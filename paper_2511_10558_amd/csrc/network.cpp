@@ -48,7 +48,7 @@ HostNetwork::~HostNetwork() {
         int prev = 0;
         if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(d->device) == hipSuccess) {
             void *ptrs[] = {d->rx_ab, d->rx_type, d->alpha, d->beta, d->gamma, d->seg_ptr, d->seg_beg,
-                            d->f_ent, d->jrow_ptr, d->jcol, d->jrow, d->jterm_ptr, d->jt_rx_other, d->jt_coef,
+                            d->f_ent, d->sg_base, d->sg_len, d->sg_lane, d->sg_ent, d->jrow_ptr, d->jcol, d->jrow, d->jterm_ptr, d->jt_rx_other, d->jt_coef,
                             d->rnu_ptr, d->rnu_ent, d->dcol_ptr, d->dcol_ent, d->dcol_coef, d->jidx};
             for (void *p : ptrs)
                 if (p) (void)hipFree(p);
@@ -179,6 +179,32 @@ void HostNetwork::finalize() {
     }
     seg_ptr[S] = int32_t(seg_beg.size());
     seg_beg.push_back(int32_t(f_ent.size()));
+    {
+        // wave layout of the segments (see DeviceNet::sg_ent)
+        const int nseg = int(seg_beg.size()) - 1;
+        std::vector<int> order(static_cast<size_t>(nseg));
+        for (int i = 0; i < nseg; ++i) order[size_t(i)] = i;
+        auto len = [&](int q) { return seg_beg[size_t(q) + 1] - seg_beg[size_t(q)]; };
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return len(a) > len(b); });
+        const int ng = (nseg + 63) / 64;
+        sg_base.assign(size_t(ng), 0);
+        sg_len.assign(size_t(ng), 0);
+        sg_lane.assign(size_t(ng) * 64, -1);
+        sg_ent.clear();
+        for (int g = 0; g < ng; ++g) {
+            int L = 0;
+            for (int l = 0; l < 64 && g * 64 + l < nseg; ++l) L = std::max(L, len(order[size_t(g * 64 + l)]));
+            sg_base[size_t(g)] = int32_t(sg_ent.size());
+            sg_len[size_t(g)] = L;
+            sg_ent.resize(sg_ent.size() + size_t(L) * 64, 4);
+            for (int l = 0; l < 64 && g * 64 + l < nseg; ++l) {
+                const int q = order[size_t(g * 64 + l)];
+                sg_lane[size_t(g) * 64 + l] = (q << 6) | len(q);
+                for (int j = 0; j < len(q); ++j)
+                    sg_ent[size_t(sg_base[size_t(g)]) + size_t(j) * 64 + l] = f_ent[size_t(seg_beg[size_t(q)] + j)];
+            }
+        }
+    }
 
     // Jacobian terms: d rate_r / d x_j of a mass-action rate
     struct Term { int j, r, other; double coef; };
@@ -342,6 +368,10 @@ const DeviceNet *HostNetwork::device_tables(std::string &err) const {
     chk(upload(&d->seg_ptr, seg_ptr));
     chk(upload(&d->seg_beg, seg_beg));
     chk(upload(&d->f_ent, f_ent));
+    chk(upload(&d->sg_base, sg_base));
+    chk(upload(&d->sg_len, sg_len));
+    chk(upload(&d->sg_lane, sg_lane));
+    chk(upload(&d->sg_ent, sg_ent));
     chk(upload(&d->jrow_ptr, jrow_ptr));
     chk(upload(&d->jcol, jcol));
     chk(upload(&d->jrow, jrow));
@@ -355,6 +385,7 @@ const DeviceNet *HostNetwork::device_tables(std::string &err) const {
     chk(upload(&d->dcol_coef, dcol_coef));
     chk(upload(&d->jidx, jidx));
     d->n_seg = int32_t(seg_beg.size()) - 1;
+    d->n_sgroup = int32_t(sg_base.size());
     d->nnzJ = int32_t(jcol.size());
     d->nterm = int32_t(jt_coef.size());
     if (e != hipSuccess) {

@@ -29,6 +29,14 @@ struct DeviceNet {
     int32_t *seg_ptr = nullptr;    // [S+1] first segment of each species
     int32_t *seg_beg = nullptr;    // [n_seg+1] first entry of each segment (entries are contiguous)
     int32_t *f_ent = nullptr;      // packed entry: reaction index << 3 | (nu + 4)
+    // the same segments laid out for a wave: sorted by length (longest first)
+    // and taken 64 at a time; entry j of the 64 segments of group g sits at
+    // sg_ent[sg_base[g] + 64 j + lane], so a wave's loads of entry j are adjacent
+    int32_t n_sgroup = 0;
+    int32_t *sg_base = nullptr;    // [n_sgroup] first entry of the group
+    int32_t *sg_len = nullptr;     // [n_sgroup] longest segment of the group
+    int32_t *sg_lane = nullptr;    // [64 n_sgroup] segment << 6 | its length, -1 for no segment
+    int32_t *sg_ent = nullptr;     // packed entries as f_ent, 4 (coefficient 0) in the padding
     // Jacobian: nonzeros of J grouped by row, each with its list of terms
     int32_t *jrow_ptr = nullptr;   // [S+1]
     int32_t *jcol = nullptr;       // [nnzJ]
@@ -63,6 +71,7 @@ struct HostNetwork {
     // derived (built by finalize())
     int S = 0, R = 0, E = 0, NP = 0;
     std::vector<int32_t> seg_ptr, seg_beg, f_ent;
+    std::vector<int32_t> sg_base, sg_len, sg_lane, sg_ent;
     std::vector<int32_t> jrow_ptr, jcol, jrow, jterm_ptr, jt_rx_other;
     std::vector<double> jt_coef;
     std::vector<int32_t> rnu_ptr, rnu_ent, dcol_ptr, dcol_ent, jidx;
