@@ -473,12 +473,13 @@ enum {
      * spans include the time spent waiting for compute units it holds. */
     ABDF_PROF_RHS_SIDE = 8,
     ABDF_PROF_NEWTON_SIDE = 9,
-    ABDF_PROF_KINDS = 10
+    ABDF_PROF_RHS_EVAL = 10,  /* abdf_rhs: the right-hand-side kernel on its own */
+    ABDF_PROF_KINDS = 11
 };
 
 typedef struct abdf_profile {
-    int64_t launches[10];   /* kernel launches per family */
-    double ms[10];          /* summed launch durations [ms] per family */
+    int64_t launches[11];   /* kernel launches per family */
+    double ms[11];          /* summed launch durations [ms] per family */
 } abdf_profile;
 
 /* Turns the timers on (nonzero) or off. */

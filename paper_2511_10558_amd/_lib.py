@@ -73,11 +73,11 @@ class ServerInfo(ctypes.Structure):
 
 
 class Profile(ctypes.Structure):
-    _fields_ = [("launches", ctypes.c_int64 * 10), ("ms", ctypes.c_double * 10)]
+    _fields_ = [("launches", ctypes.c_int64 * 11), ("ms", ctypes.c_double * 11)]
 
 
 PROFILE_KINDS = ("admit", "factor", "newton", "control", "harvest", "rhs", "adj_solve", "adj_step", "rhs_side",
-                 "newton_side")
+                 "newton_side", "rhs_eval")
 
 # name -> (restype, argtypes); mirrors include/astrobdf.h
 SIGNATURES = {

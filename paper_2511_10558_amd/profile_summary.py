@@ -1,18 +1,25 @@
 """Turns rocprofv3 CSV output into the short summaries kept in profiles/.
 
-    python -m paper_2511_10558_amd.profile_summary TRACE_DIR FETCH_DIR WRITE_DIR FETCH_LOG
+    python -m paper_2511_10558_amd.profile_summary TRACE_DIR FETCH_DIR WRITE_DIR FETCH_LOG [TRACE_LOG]
     python -m paper_2511_10558_amd.profile_summary --markers MARKER_DIR COMMAND
+    python -m paper_2511_10558_amd.profile_summary --mfma MFMA_DIR MFMA_LOG COMMAND
+    python -m paper_2511_10558_amd.profile_summary --trace TRACE_DIR LOG NAME TITLE COMMAND
 
 TRACE_DIR holds run_kernel_stats.csv of a --kernel-trace --stats run;
 FETCH_DIR / WRITE_DIR hold run_counter_collection.csv of the FETCH_SIZE and
 WRITE_SIZE passes of a bench run started with --calibrate-copy (one
 elementwise multiply of 32 Mi doubles: 256 MiB read, 256 MiB written);
 FETCH_LOG is that bench run's
-output line (for the number of factorisations).  Writes
+output line (for the number of factorisations); TRACE_LOG, if given, the
+traced run's output (its standalone right-hand-side figure).  Writes
 profiles/kernel_stats_net500.md and profiles/traffic.json.  With --markers,
 MARKER_DIR holds run_marker_api_trace.csv of a --marker-trace run (the
 library's host ranges) and COMMAND is the command that made it; writes
-profiles/markers_net500.md.
+profiles/markers_net500.md.  With --mfma, MFMA_DIR holds run_counter_collection.csv
+of a run with the counters SQ_VALU_MFMA_BUSY_CYCLES, SQ_BUSY_CU_CYCLES,
+SQ_INSTS_VALU_MFMA_MOPS_F64 and SQ_WAVE_CYCLES and MFMA_LOG that run's bench
+line; writes profiles/mfma_net500.md.  With --trace, a kernel-statistics table
+of another run goes to profiles/NAME.md.
 """
 import csv
 import hashlib
@@ -80,16 +87,78 @@ def markers(mdir, command):
     print("\n".join(out))
 
 
+def mfma(mdir, mlog, command):
+    """Per-kernel MFMA counters: executed FP64 MFMA work (SQ_INSTS_VALU_MFMA_MOPS_F64
+    counts 512 flops each) per factorisation against the algorithmic 2/3 n^3,
+    and MFMA busy cycles against CU busy cycles."""
+    agg, calls = {}, {}
+    for r in csv.DictReader(open(os.path.join(mdir, "run_counter_collection.csv"))):
+        k = short(r["Kernel_Name"])
+        d = agg.setdefault(k, {})
+        d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        if r["Counter_Name"] == "SQ_BUSY_CU_CYCLES":
+            calls[k] = calls.get(k, 0) + 1
+    line = json.loads([l for l in open(mlog) if l.startswith("{")][-1])
+    n_lu = line["work"]["factorisations"]
+    S = line["config"]["species"]
+    out = ["# MFMA counters: 500-species / 6000-reaction network, 512 cells, FP64", "",
+           "Command (repo root, on one MI355X):", "", "    " + command, "",
+           "| kernel | dispatches | SQ_INSTS_VALU_MFMA_MOPS_F64 | SQ_VALU_MFMA_BUSY_CYCLES | SQ_BUSY_CU_CYCLES | "
+           "SQ_WAVE_CYCLES |", "|---|---|---|---|---|---|"]
+    for k, d in sorted(agg.items(), key=lambda kv: -kv[1].get("SQ_BUSY_CU_CYCLES", 0.0)):
+        if d.get("SQ_BUSY_CU_CYCLES", 0.0) < 1e6:
+            continue
+        out.append(f"| {k} | {calls.get(k, 0)} | {d.get('SQ_INSTS_VALU_MFMA_MOPS_F64', 0):.4g} | "
+                   f"{d.get('SQ_VALU_MFMA_BUSY_CYCLES', 0):.4g} | {d.get('SQ_BUSY_CU_CYCLES', 0):.4g} | "
+                   f"{d.get('SQ_WAVE_CYCLES', 0):.4g} |")
+    f = agg.get("k_factor<double>", {})
+    executed = f.get("SQ_INSTS_VALU_MFMA_MOPS_F64", 0.0) * 512 / max(1, n_lu)
+    out += ["", f"k_factor<double>: {n_lu} factorisations; MFMA work executed per factorisation "
+                f"{executed:.4g} flop (MOPS x 512) against the algorithmic 2/3 n^3 = {2 / 3 * S ** 3:.4g} "
+                f"({executed / (2 / 3 * S ** 3):.3f}x: the padding to 512 rows and the diagonal-block inverses).",
+            f"MFMA busy / CU busy cycles: {f.get('SQ_VALU_MFMA_BUSY_CYCLES', 0) / max(1, f.get('SQ_BUSY_CU_CYCLES', 1)):.3f}"
+            " (both summed over the device as the counters report them)."]
+    open(os.path.join(PROFILES, "mfma_net500.md"), "w").write("\n".join(out) + "\n")
+    print("\n".join(out))
+
+
+def trace_table(tdir, log, name, title, command):
+    rows = list(csv.DictReader(open(os.path.join(tdir, "run_kernel_stats.csv"))))
+    line = json.loads([l for l in open(log) if l.startswith("{")][-1])
+    out = [f"# {title}", "", "Command (repo root, on one MI355X):", "", "    " + command, "",
+           "| kernel | calls | total ms | average us | % |", "|---|---|---|---|---|"]
+    for r in rows:
+        if float(r["Percentage"]) < 0.01:
+            continue
+        out.append(f"| {short(r['Name'])} | {r['Calls']} | {float(r['TotalDurationNs'])/1e6:.1f} | "
+                   f"{float(r['AverageNs'])/1e3:.1f} | {float(r['Percentage']):.2f} |")
+    out += ["", f"Bench line of the run: {line['value']} {line['unit']}, {line['ms_per_step']} ms per solve; "
+                f"work {json.dumps(line['work'])}."]
+    if "roofline_rhs" in line:
+        rr = line["roofline_rhs"]
+        out.append(f"Standalone right-hand side (k_rhs_only): {rr['achieved']} GB/s of algorithmic traffic "
+                   f"({rr['work']}), {rr['avg_launch_ms']} ms per launch over {rr['cells']} cells.")
+    open(os.path.join(PROFILES, name + ".md"), "w").write("\n".join(out) + "\n")
+    print("\n".join(out))
+
+
 def main():
     if sys.argv[1] == "--markers":
         markers(sys.argv[2], sys.argv[3])
+        return
+    if sys.argv[1] == "--mfma":
+        mfma(sys.argv[2], sys.argv[3], sys.argv[4])
+        return
+    if sys.argv[1] == "--trace":
+        trace_table(*sys.argv[2:7])
         return
     trace, fetch, write, flog = sys.argv[1:5]
     rows = list(csv.DictReader(open(os.path.join(trace, "run_kernel_stats.csv"))))
     out = ["# rocprofv3 kernel statistics: 500-species / 6000-reaction network, 4096 cells, FP64", "",
            "Command (repo root, on one MI355X):", "",
            "    rocprofv3 --kernel-trace --stats --output-format csv -d <dir> -o run -- "
-           "python3 bench.py --cells 4096 --steps 1 --warmup 0 --no-cpu-baseline --no-compare-fp32 --no-compare-reuse", "",
+           "python3 bench.py --cells 4096 --steps 1 --warmup 0 --no-cpu-baseline --no-compare-fp32 "
+           "--no-compare-reuse --no-compare-esdirk --batch-serve-requests 0", "",
            "| kernel | calls | total ms | average us | % |", "|---|---|---|---|---|"]
     for r in rows:
         if float(r["Percentage"]) < 0.01:
@@ -130,6 +199,15 @@ def main():
         out.append(f"| {k} | {q} | {n} | {tot / 1e6:.1f} | {tot / n / 1e3:.1f} |")
     out += ["", f"GPU busy (union of all kernel spans): {busy / 1e6:.1f} ms, of which k_factor "
                 f"{sum(t for (k, q), (n, t) in perq.items() if k.startswith('k_factor')) / 1e6:.1f} ms."]
+    if len(sys.argv) > 5:
+        tl = json.loads([l for l in open(sys.argv[5]) if l.startswith("{")][-1])
+        out += ["", f"Bench line of the traced run: {tl['value']} {tl['unit']}, {tl['ms_per_step']} ms per solve, "
+                    f"work {json.dumps(tl['work'])}."]
+        if "roofline_rhs" in tl:
+            rr = tl["roofline_rhs"]
+            out.append(f"Standalone right-hand side (k_rhs_only, the 21 launches above, timed by HIP events "
+                       f"in the same run): {rr['achieved']} GB/s of algorithmic traffic ({rr['work']}), "
+                       f"{rr['avg_launch_ms']} ms per launch over {rr['cells']} cells, {rr['frac']} of 8 TB/s.")
     f = counters(fetch)
     w = counters(write)
     cf = COPY_BYTES / (f["reference multiply"][1] * 1024.0)
