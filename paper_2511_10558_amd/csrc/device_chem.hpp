@@ -166,20 +166,29 @@ __device__ __forceinline__ void jacobian_values(const DeviceNet &n, const double
 }
 
 // Entries of M = I - c J of one cell where the factorisation gathers them:
-// the dense map gives the nonzero of (i, j); rows and columns beyond S are the
-// identity's.
+// the 64-column words of the Jacobian's pattern give the nonzero of (i, j)
+// (one word and one base per row and block column, shared by the lanes of a
+// row); rows and columns beyond S are the identity's.
 template <typename T>
 struct NewtonMatrixSource {
-    const int32_t *jidx;   // [NP][NP] entry of J at (i, j), -1 where J is structurally zero
-    const double *jv;      // the entries' values (at least one)
-    int S, NP;
+    const uint64_t *jmask;   // [NP][nbw] pattern words
+    const int32_t *jbase;    // [NP][nbw] index of the first nonzero of each word
+    int nbw;
+    const double *jv;        // the entries' values
     double c;
-    // Entries are read in two passes, every index first and then every value,
-    // so that no load waits behind a condition on an earlier one.
-    __device__ __forceinline__ int32_t handle(int i, int j) const { return jidx[size_t(i) * NP + j]; }
-    __device__ __forceinline__ T value(int32_t e, int i, int j) const {
-        const double jvv = jv[e < 0 ? 0 : e];
-        return T((i == j ? 1.0 : 0.0) + (e >= 0 ? -c * jvv : 0.0));
+    // Entries are read in two passes, every row's word first and then every
+    // value, so that no load waits behind a condition on an earlier one;
+    // structural zeros load nothing.
+    struct Row { uint64_t m; int32_t base; };
+    __device__ __forceinline__ Row row(int i, int c0) const {
+        const size_t w = size_t(i) * nbw + (c0 >> 6);
+        return {jmask[w], jbase[w]};
+    }
+    __device__ __forceinline__ T entry(const Row &w, int i, int j) const {
+        const int bit = j & 63;
+        const bool nz = (w.m >> bit) & 1ull;
+        const double jvv = nz ? jv[w.base + __popcll(w.m & ((1ull << bit) - 1ull))] : 0.0;
+        return T((i == j ? 1.0 : 0.0) - c * jvv);
     }
 };
 

@@ -228,15 +228,17 @@ __device__ __forceinline__ void diag_inverses(const T *Cb, int W, T *D, T *Xb, T
 }
 
 // Entries of the matrix to factor as stored in A (storage row, column).  A
-// source yields an entry in two steps, handle(row, col) and then
-// value(handle, row, col), so that the gather can issue every handle load of a
-// tile before the value loads that depend on them.
+// source yields an entry in two steps: row(r, c0), what the lanes of row r
+// need for the 64 columns from c0 (a multiple of 64), and entry(that, r, col),
+// so that the gather can issue every row's loads before the entry loads that
+// depend on them.
 template <typename T>
 struct DenseSource {
     const T *A;
     int NP;
-    __device__ __forceinline__ int32_t handle(int row, int col) const { return row * NP + col; }
-    __device__ __forceinline__ T value(int32_t h, int, int) const { return A[h]; }
+    struct Row { int32_t off; };
+    __device__ __forceinline__ Row row(int r, int) const { return {r * NP}; }
+    __device__ __forceinline__ T entry(const Row &w, int, int col) const { return A[w.off + col]; }
 };
 
 // Factors the matrix whose entries src yields (read once, when its block
@@ -291,12 +293,12 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
         }
         acc_t acc[lu_slots<T>][4];
         // 1. gather the block column (positions = logical rows at this point):
-        //    every row tile's 16 handles first, then all values, so that each
-        //    lane has all its index loads in flight together and then all its
-        //    value loads (the accumulators are not live yet).  Tiles outside
-        //    the matrix read column c0 + lc of row 0 and are zeroed.
+        //    what each of the lane's rows needs first, then every entry, so
+        //    that each lane has all its row loads in flight together and then
+        //    all its entry loads (the accumulators are not live yet).  Tiles
+        //    outside the matrix read column c0 + lc of row 0 and are zeroed.
         {
-            int32_t hnd[lu_slots<T>][4][4];
+            typename Src::Row rw[lu_slots<T>][4];
             int srow[lu_slots<T>][4];
 #pragma unroll
             for (int s = 0; s < lu_slots<T>; ++s) {
@@ -307,10 +309,7 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
 #pragma unroll
             for (int s = 0; s < lu_slots<T>; ++s)
 #pragma unroll
-                for (int ct = 0; ct < 4; ++ct)
-#pragma unroll
-                    for (int v = 0; v < 4; ++v)
-                        hnd[s][ct][v] = src.handle(srow[s][v], c0 + 16 * (ct < CTj ? ct : 0) + lc);
+                for (int v = 0; v < 4; ++v) rw[s][v] = src.row(srow[s][v], c0);
 #pragma unroll
             for (int s = 0; s < lu_slots<T>; ++s) {
                 const int rt = wave + lu_waves<T> * s;
@@ -318,7 +317,7 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
                 for (int ct = 0; ct < 4; ++ct)
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        const T val = src.value(hnd[s][ct][v], srow[s][v], c0 + 16 * ct + lc);
+                        const T val = src.entry(rw[s][v], srow[s][v], c0 + 16 * (ct < CTj ? ct : 0) + lc);
                         acc[s][ct][v] = (rt < RT && ct < CTj) ? val : T(0);
                     }
             }

@@ -471,7 +471,7 @@ __global__ void __launch_bounds__(lu_threads<T>) k_factor(Slots s, DeviceNet n, 
             jacobian_values<lu_threads<T>>(n, s.k + size_t(slot) * n.R, xs, jv);
             __syncthreads();
         }
-        NewtonMatrixSource<T> src{n.jidx, jv, S, NP, c};
+        NewtonMatrixSource<T> src{n.jmask, n.jbase, n.nbw, jv, c};
         lu_factor_left<T>(slot_lu<T>(s, slot), NP, s.perm + size_t(slot) * NP, slot_dinv<T>(s, slot), nullptr,
                           reinterpret_cast<unsigned char *>(smem), src);
         if (threadIdx.x == 0) {
@@ -1448,10 +1448,10 @@ __global__ void __launch_bounds__(kAsmThreads) k_newton_matrix_only(DeviceNet n,
     double *jvc = jv + size_t(c) * max(n.nnzJ, 1);
     jacobian_values<kAsmThreads>(n, k + size_t(c) * n.R, xs, jvc);
     __syncthreads();
-    const NewtonMatrixSource<double> src{n.jidx, jvc, n.S, n.NP, cvec[c]};
+    const NewtonMatrixSource<double> src{n.jmask, n.jbase, n.nbw, jvc, cvec[c]};
     for (size_t e = threadIdx.x; e < size_t(n.S) * n.S; e += kAsmThreads) {
         const int i = int(e / n.S), j = int(e % n.S);
-        M[size_t(c) * n.S * n.S + e] = src.value(src.handle(i, j), i, j);
+        M[size_t(c) * n.S * n.S + e] = src.entry(src.row(i, j & ~63), i, j);
     }
 }
 

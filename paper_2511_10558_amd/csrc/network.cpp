@@ -10,6 +10,7 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <sstream>
@@ -49,7 +50,8 @@ HostNetwork::~HostNetwork() {
         if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(d->device) == hipSuccess) {
             void *ptrs[] = {d->rx_ab, d->rx_type, d->alpha, d->beta, d->gamma, d->seg_ptr, d->seg_beg,
                             d->f_ent, d->sg_base, d->sg_len, d->sg_lane, d->sg_ent, d->jrow_ptr, d->jcol, d->jrow, d->jterm_ptr, d->jt_rx_other, d->jt_coef,
-                            d->rnu_ptr, d->rnu_ent, d->dcol_ptr, d->dcol_ent, d->dcol_coef, d->jidx};
+                            d->rnu_ptr, d->rnu_ent, d->dcol_ptr, d->dcol_ent, d->dcol_coef, d->jidx,
+                            d->jmask, d->jbase};
             for (void *p : ptrs)
                 if (p) (void)hipFree(p);
             (void)hipSetDevice(prev);
@@ -274,6 +276,24 @@ void HostNetwork::finalize() {
     dcol_ptr[S] = int32_t(dcol_ent.size());
     jidx.assign(size_t(NP) * NP, -1);
     for (size_t e = 0; e < jcol.size(); ++e) jidx[size_t(jrow[e]) * NP + jcol[e]] = int32_t(e);
+    const int nbw = (NP + 63) / 64;
+    jmask.assign(size_t(NP) * nbw, 0);
+    jbase.assign(size_t(NP) * nbw, 0);
+    for (int i = 0; i < NP; ++i) {
+        int32_t next = i < S ? jrow_ptr[i] : 0;
+        for (int b = 0; b < nbw; ++b) {
+            jbase[size_t(i) * nbw + b] = next;
+            uint64_t m = 0;
+            for (int c = 0; c < 64 && 64 * b + c < NP; ++c)
+                if (jidx[size_t(i) * NP + 64 * b + c] >= 0) {
+                    // the numbering the word encodes is the map's
+                    if (jidx[size_t(i) * NP + 64 * b + c] != next) std::abort();
+                    m |= uint64_t(1) << c;
+                    ++next;
+                }
+            jmask[size_t(i) * nbw + b] = m;
+        }
+    }
 }
 
 namespace {
@@ -384,6 +404,9 @@ const DeviceNet *HostNetwork::device_tables(std::string &err) const {
     chk(upload(&d->dcol_ent, dcol_ent));
     chk(upload(&d->dcol_coef, dcol_coef));
     chk(upload(&d->jidx, jidx));
+    chk(upload(&d->jmask, jmask));
+    chk(upload(&d->jbase, jbase));
+    d->nbw = (NP + 63) / 64;
     d->n_seg = int32_t(seg_beg.size()) - 1;
     d->n_sgroup = int32_t(sg_base.size());
     d->nnzJ = int32_t(jcol.size());

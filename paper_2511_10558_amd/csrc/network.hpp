@@ -54,6 +54,13 @@ struct DeviceNet {
     double *dcol_coef = nullptr;
     // dense map (i, j) -> index of the Jacobian nonzero, -1 where J_ij = 0 structurally [NP][NP]
     int32_t *jidx = nullptr;
+    // the same map in 64-column words: bit c of jmask[i][b] is set when J has a
+    // nonzero at (i, 64 b + c); jbase[i][b] is the index of the row's first
+    // nonzero at or after column 64 b (nonzeros are numbered row by row, columns
+    // ascending), so the index of (i, j) is jbase + the set bits below j
+    int32_t nbw = 0;               // words per row, ceil(NP / 64)
+    uint64_t *jmask = nullptr;     // [NP][nbw]
+    int32_t *jbase = nullptr;      // [NP][nbw]
 };
 
 struct HostNetwork {
@@ -74,7 +81,8 @@ struct HostNetwork {
     std::vector<int32_t> sg_base, sg_len, sg_lane, sg_ent;
     std::vector<int32_t> jrow_ptr, jcol, jrow, jterm_ptr, jt_rx_other;
     std::vector<double> jt_coef;
-    std::vector<int32_t> rnu_ptr, rnu_ent, dcol_ptr, dcol_ent, jidx;
+    std::vector<int32_t> rnu_ptr, rnu_ent, dcol_ptr, dcol_ent, jidx, jbase;
+    std::vector<uint64_t> jmask;
     std::vector<double> dcol_coef;
 
     // per-device uploads, created on first use
