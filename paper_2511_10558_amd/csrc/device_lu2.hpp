@@ -429,48 +429,45 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
             if (is_diag) dpos[mylog - rb] = q;
             __syncthreads();
             if (wave == 0) {
-                // the 16 x 16 diagonal block in Db, lane l holding the entries
-                // of rows i = 4 t + l / 16 (t = 0..3) in column j = l % 16;
-                // column c: every entry below row c takes its multiplier or
-                // its update from row c, read before any lane writes
-                const int jj = lane & 15;
+                // the 16 x 16 diagonal block in registers, lane l holding the
+                // entries of rows i = 4 t + l / 16 (t = 0..3) in column j = l % 16;
+                // column c: every entry below row c takes its multiplier or its
+                // update from row c, each lane reading the values it needs from
+                // the lanes that hold them (cross-lane shuffles) before it
+                // changes its own; the factored block then goes to Db
+                const int jj = lane & 15, gg = lane >> 4;
+                T a[4];
 #pragma unroll
-                for (int t = 0; t < 4; ++t) {
-                    const int i = 4 * t + (lane >> 4);
-                    Db[i * kCrowLd + jj] = P[dpos[i] * kPanLd + jj];
-                }
+                for (int t = 0; t < 4; ++t) a[t] = P[dpos[4 * t + gg] * kPanLd + jj];
                 bool bad = false;
 #pragma unroll
                 for (int c = 0; c < 16; ++c) {
-                    wave_lds_order();
+                    const int tc = c >> 2, gc = c & 3;
                     // a pivot below the smallest normal number refuses the diagonal
                     // (partial pivoting then forms such multipliers by division)
-                    const T piv = Db[c * kCrowLd + c];
+                    const T piv = __shfl(a[tc], 16 * gc + c);
                     const bool normal = fabs(piv) >= std::numeric_limits<T>::min();
                     const T rinv = T(1) / (normal ? piv : T(1));
-                    const T ucj = Db[c * kCrowLd + jj];
-                    T a[4], l[4];
+                    const T ucj = __shfl(a[tc], 16 * gc + jj);
+                    T l[4];
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        const int i = 4 * t + (lane >> 4);
-                        a[t] = Db[i * kCrowLd + jj];
-                        l[t] = Db[i * kCrowLd + c] * rinv;
-                    }
-                    wave_lds_order();
+                    for (int t = 0; t < 4; ++t) l[t] = __shfl(a[t], 16 * gg + c) * rinv;
                     bad |= !normal;
 #pragma unroll
                     for (int t = 0; t < 4; ++t) {
-                        const int i = 4 * t + (lane >> 4);
+                        const int i = 4 * t + gg;
                         if (i > c) {
                             if (jj == c) {
                                 bad |= !(fabs(l[t]) <= T(kPivotThreshold));
-                                Db[i * kCrowLd + jj] = l[t];
+                                a[t] = l[t];
                             } else if (jj > c) {
-                                Db[i * kCrowLd + jj] = a[t] - l[t] * ucj;
+                                a[t] = a[t] - l[t] * ucj;
                             }
                         }
                     }
                 }
+#pragma unroll
+                for (int t = 0; t < 4; ++t) Db[(4 * t + gg) * kCrowLd + jj] = a[t];
                 wave_lds_order();
                 if (lane < 16) Db[lane * kCrowLd + 16] = T(1) / Db[lane * kCrowLd + lane];   // used only when every pivot is normal
                 if (__ballot(bad) != 0 && lane == 0) spec_bad[0] = 1;
