@@ -227,6 +227,16 @@ __device__ __forceinline__ void diag_inverses(const T *Cb, int W, T *D, T *Xb, T
     for (int e = h; e < 64 * 64; e += HALF) D[(upper ? kLuW * kLuW : 0) + e] = Z[(e >> 6) * kLdb + (e & 63)];
 }
 
+// The value v of lane src (a constant of the unrolled loops), on every lane.
+__device__ __forceinline__ double lane_value(double v, int src) {
+    const int lo = __builtin_amdgcn_readlane(__double2loint(v), src);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(v), src);
+    return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float lane_value(float v, int src) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
+}
+
 // Entries of the matrix to factor as stored in A (storage row, column).  A
 // source yields an entry in two steps: row(r, c0), what the lanes of row r
 // need for the 64 columns from c0 (a multiple of 64), and entry(that, r, col),
@@ -429,47 +439,80 @@ __device__ __forceinline__ void lu_factor_left(T *__restrict__ A, int NP, int32_
             if (is_diag) dpos[mylog - rb] = q;
             __syncthreads();
             if (wave == 0) {
-                // the 16 x 16 diagonal block in registers, lane l holding the
-                // entries of rows i = 4 t + l / 16 (t = 0..3) in column j = l % 16;
-                // column c: every entry below row c takes its multiplier or its
-                // update from row c, each lane reading the values it needs from
-                // the lanes that hold them (cross-lane shuffles) before it
-                // changes its own; the factored block then goes to Db
-                const int jj = lane & 15, gg = lane >> 4;
-                T a[4];
-#pragma unroll
-                for (int t = 0; t < 4; ++t) a[t] = P[dpos[4 * t + gg] * kPanLd + jj];
+                // the 16 x 16 diagonal block in registers; column c: every entry
+                // below row c takes its multiplier or its update from row c,
+                // each lane reading what it needs from the lanes that hold it
+                // before it changes its own; the factored block then goes to Db.
+                // A pivot below the smallest normal number refuses the diagonal
+                // (partial pivoting then forms such multipliers by division).
                 bool bad = false;
+                if constexpr (sizeof(T) == sizeof(float)) {
+                    // FP32: lane i < 16 holds row i; the pivot and the rest of
+                    // row c reach every lane by readlane
+                    T a[16];
+                    const bool row_lane = lane < 16;
 #pragma unroll
-                for (int c = 0; c < 16; ++c) {
-                    const int tc = c >> 2, gc = c & 3;
-                    // a pivot below the smallest normal number refuses the diagonal
-                    // (partial pivoting then forms such multipliers by division)
-                    const T piv = __shfl(a[tc], 16 * gc + c);
-                    const bool normal = fabs(piv) >= std::numeric_limits<T>::min();
-                    const T rinv = T(1) / (normal ? piv : T(1));
-                    const T ucj = __shfl(a[tc], 16 * gc + jj);
-                    T l[4];
+                    for (int c = 0; c < 16; ++c) a[c] = P[dpos[row_lane ? lane : 0] * kPanLd + c];
+                    T uii = T(1);
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) l[t] = __shfl(a[t], 16 * gg + c) * rinv;
-                    bad |= !normal;
+                    for (int c = 0; c < 16; ++c) {
+                        const T piv = lane_value(a[c], c);
+                        const bool normal = fabs(piv) >= std::numeric_limits<T>::min();
+                        const T rinv = T(1) / (normal ? piv : T(1));
+                        if (lane == c) uii = a[c];
+                        const bool below = row_lane && lane > c;
+                        const T l = a[c] * rinv;
+                        bad |= !normal;
+                        bad |= below && !(fabs(l) <= T(kPivotThreshold));
 #pragma unroll
-                    for (int t = 0; t < 4; ++t) {
-                        const int i = 4 * t + gg;
-                        if (i > c) {
-                            if (jj == c) {
-                                bad |= !(fabs(l[t]) <= T(kPivotThreshold));
-                                a[t] = l[t];
-                            } else if (jj > c) {
-                                a[t] = a[t] - l[t] * ucj;
+                        for (int j = c + 1; j < 16; ++j) {
+                            const T ucj = lane_value(a[j], c);
+                            if (below) a[j] = a[j] - l * ucj;
+                        }
+                        if (below) a[c] = l;
+                    }
+                    if (row_lane) {
+#pragma unroll
+                        for (int c = 0; c < 16; ++c) Db[lane * kCrowLd + c] = a[c];
+                        Db[lane * kCrowLd + 16] = T(1) / uii;   // used only when every pivot is normal
+                    }
+                } else {
+                    // FP64 (fewer registers): lane l holds the entries of rows
+                    // i = 4 t + l / 16 (t = 0..3) in column j = l % 16, read by
+                    // shuffles
+                    const int jj = lane & 15, gg = lane >> 4;
+                    T a[4];
+#pragma unroll
+                    for (int t = 0; t < 4; ++t) a[t] = P[dpos[4 * t + gg] * kPanLd + jj];
+#pragma unroll
+                    for (int c = 0; c < 16; ++c) {
+                        const int tc = c >> 2, gc = c & 3;
+                        const T piv = __shfl(a[tc], 16 * gc + c);
+                        const bool normal = fabs(piv) >= std::numeric_limits<T>::min();
+                        const T rinv = T(1) / (normal ? piv : T(1));
+                        const T ucj = __shfl(a[tc], 16 * gc + jj);
+                        T l[4];
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) l[t] = __shfl(a[t], 16 * gg + c) * rinv;
+                        bad |= !normal;
+#pragma unroll
+                        for (int t = 0; t < 4; ++t) {
+                            const int i = 4 * t + gg;
+                            if (i > c) {
+                                if (jj == c) {
+                                    bad |= !(fabs(l[t]) <= T(kPivotThreshold));
+                                    a[t] = l[t];
+                                } else if (jj > c) {
+                                    a[t] = a[t] - l[t] * ucj;
+                                }
                             }
                         }
                     }
-                }
 #pragma unroll
-                for (int t = 0; t < 4; ++t) Db[(4 * t + gg) * kCrowLd + jj] = a[t];
-                wave_lds_order();
-                if (lane < 16) Db[lane * kCrowLd + 16] = T(1) / Db[lane * kCrowLd + lane];   // used only when every pivot is normal
+                    for (int t = 0; t < 4; ++t) Db[(4 * t + gg) * kCrowLd + jj] = a[t];
+                    wave_lds_order();
+                    if (lane < 16) Db[lane * kCrowLd + 16] = T(1) / Db[lane * kCrowLd + lane];   // used only when every pivot is normal
+                }
                 if (__ballot(bad) != 0 && lane == 0) spec_bad[0] = 1;
             }
             __syncthreads();
