@@ -145,14 +145,8 @@ class Result:
     history: list | None = None   # accepted (h, q, t_new, x_new) when recorded
 
 
-def _newton(chem, lu, c, psi, x_p, scale, tol, stats, maxiter=NEWTON_MAXITER, rate=None):
-    """Modified Newton on d = c f(x_p + d) - psi with the factor of I - cJ.
-
-    rate: None, or a one-element list carrying the contraction-rate estimate
-    across correctors: each iteration m > 1 sets it to max(0.3 rate, theta_m)
-    (the decay floor of the rate estimate of CVODE's corrector test), a failed
-    corrector resets it to 1, and the first iteration's convergence test uses
-    it in place of theta (so a corrector may converge after one iteration)."""
+def _newton(chem, lu, c, psi, x_p, scale, tol, stats, maxiter=NEWTON_MAXITER):
+    """Modified Newton on d = c f(x_p + d) - psi with the factor of I - cJ."""
     d = np.zeros_like(x_p)
     x = x_p.copy()
     eta_old = None
@@ -168,25 +162,17 @@ def _newton(chem, lu, c, psi, x_p, scale, tol, stats, maxiter=NEWTON_MAXITER, ra
         if theta is not None and (
             theta >= 1.0 or theta ** (maxiter - m) / (1.0 - theta) * eta > tol
         ):
-            if rate is not None:
-                rate[0] = 1.0
             return False, m, x, d
         x = x + delta
         d = d + delta
-        if rate is not None and theta is not None:
-            rate[0] = max(0.3 * rate[0], theta)
-        r = theta if theta is not None else (rate[0] if rate is not None else None)
-        if eta == 0.0 or (r is not None and r < 1.0 and r / (1.0 - r) * eta < tol):
+        if eta == 0.0 or (theta is not None and theta / (1.0 - theta) * eta < tol):
             return True, m, x, d
         eta_old = eta
-    if rate is not None:
-        rate[0] = 1.0
     return False, maxiter, x, d
 
 
 def solve(chem, x0, t_end, rtol=1e-6, atol=1e-20, max_steps=100000,
-          newton_tol=None, record=False, max_order=MAX_ORDER, h0=0.0, h_max=0.0,
-          rate_carry=False) -> Result:
+          newton_tol=None, record=False, max_order=MAX_ORDER, h0=0.0, h_max=0.0) -> Result:
     """Integrate dx/dt = f(x) from t = 0 to t_end with adaptive order and step.
 
     chem provides f and jac; if it also provides at(t), the rate
@@ -199,9 +185,7 @@ def solve(chem, x0, t_end, rtol=1e-6, atol=1e-20, max_steps=100000,
     (1..5) caps the order the order selection may reach; 1 leaves
     the implicit Euler method under the same error and step control.  h0 > 0
     replaces the starting-step heuristic's result; h_max > 0 bounds every step
-    (the starting step, and each increase chosen with the order).  rate_carry
-    carries the corrector's contraction-rate estimate from one corrector to
-    the next (see _newton), starting at 1."""
+    (the starting step, and each increase chosen with the order)."""
     if not 1 <= max_order <= MAX_ORDER:
         raise ValueError("max_order must be in 1..5")
     x0 = np.asarray(x0, dtype=float)
@@ -242,7 +226,6 @@ def solve(chem, x0, t_end, rtol=1e-6, atol=1e-20, max_steps=100000,
     lu, c_lu = None, None
     status = OK
     I = np.eye(S)
-    rate = [1.0] if rate_carry else None
     while True:
         if stats.n_attempts >= max_steps:
             status = MAX_STEPS
@@ -274,7 +257,7 @@ def solve(chem, x0, t_end, rtol=1e-6, atol=1e-20, max_steps=100000,
             c_lu = c
             stats.n_lu += 1
         scale = atol + rtol * np.abs(x_p)
-        converged, m, x_new, d = _newton(ch, lu, c, psi, x_p, scale, tol, stats, rate=rate)
+        converged, m, x_new, d = _newton(ch, lu, c, psi, x_p, scale, tol, stats)
         if not converged:
             stats.n_newton_fail += 1
             if not j_fresh:

@@ -408,44 +408,3 @@ def test_initial_step_takes_the_trial_evaluation_at_h0():
     h = bdf.initial_step(lambda y: lam0 * y, y0, lam0 * y0, 1e9, rtol, atol, ft=lambda t, y: lam(t) * y)
     assert h == pytest.approx(want, rel=1e-12)
     assert h != pytest.approx(bdf.initial_step(lambda y: lam0 * y, y0, lam0 * y0, 1e9, rtol, atol), rel=1e-3)
-
-
-def test_carried_newton_rate():
-    # With the rate carried across correctors, a linear problem (x' = -k x with
-    # its exact Jacobian: each corrector's second correction is zero up to
-    # rounding, theta ~ 0) soon converges after one iteration per step, and the
-    # solution still meets the closed form; without the option a corrector
-    # takes two iterations (theta needs two corrections) unless its first
-    # correction is exactly zero (late, at equilibrium)
-    net = tiny_nets.decay(2.0)
-    ch = chem.cell_chemistry(net, CELL)
-    k = ch.k[0]
-    plain = bdf.solve(ch, np.array([1.0, 0.0]), 20.0 / k, 1e-10, 1e-30)
-    carry = bdf.solve(ch, np.array([1.0, 0.0]), 20.0 / k, 1e-10, 1e-30, rate_carry=True)
-    assert plain.stats.n_newton_iter >= 1.9 * plain.stats.n_attempts
-    assert carry.stats.n_newton_iter < 1.25 * carry.stats.n_attempts
-    for r in (plain, carry):
-        assert r.status == bdf.OK
-        np.testing.assert_allclose(r.x, [np.exp(-20.0), -np.expm1(-20.0)], rtol=1e-7)
-    # a nonlinear closed form at the production tolerance
-    net = tiny_nets.association(1e-9)
-    ch = chem.cell_chemistry(net, CELL)
-    kp, a0, b0 = ch.k[0], 3e-4, 1e-4
-    t = 3.0 / (kp * a0)
-    r = bdf.solve(ch, np.array([a0, b0, 0.0]), t, 1e-10, 1e-30, rate_carry=True)
-    d = a0 - b0
-    a = d / (1 - (b0 / a0) * np.exp(-kp * d * t))
-    np.testing.assert_allclose(r.x, [a, a - d, a0 - a], rtol=1e-8)
-    # the rate estimate: decays by at most 0.3 per iteration, resets on failure
-    st = bdf.Stats()
-    lin = chem.cell_chemistry(tiny_nets.decay(2.0), CELL)
-    J = lin.jac(np.array([1.0, 0.0]))
-    lu = sla.lu_factor(np.eye(2) - 0.1 / lin.k[0] * J)
-    rate = [1.0]
-    ok, m, _x, _d = bdf._newton(lin, lu, 0.1 / lin.k[0], np.zeros(2), np.array([1.0, 0.0]), np.full(2, 1e-8),
-                                1e-3, st, rate=rate)
-    assert ok and m == 2 and rate[0] == pytest.approx(0.3)
-    rate = [0.5]
-    ok, m, _x, _d = bdf._newton(lin, lu, 0.1 / lin.k[0], np.zeros(2), np.array([1.0, 0.0]), np.full(2, 1e-8),
-                                1e-3, st, maxiter=1, rate=rate)
-    assert not ok and rate[0] == 1.0
