@@ -126,12 +126,13 @@ __host__ __device__ constexpr size_t lu2_dinv_elems(int NP) {
 
 // Inverses of the unit-lower and the upper triangle of the W x W diagonal block
 // held in LDS (leading dimension kLdb), written to D[0] and D[1] (64 x 64
-// row-major, global).  The first half of the threads forms inv(L), the second
-// inv(U), block-recursively on 16 x 16 blocks: the diagonal blocks by
-// substitution (one lane per column), then the off-diagonal blocks level by level,
+// row-major, global), block-recursively on 16 x 16 blocks: the diagonal
+// blocks by substitution (the first half of the threads for inv(L), the second
+// for inv(U), one lane per column), then the off-diagonal blocks level by
+// level on the matrix cores, one wave per block,
 // X_ij = -X_ii sum_k L_ik X_kj (lower) and Y_ij = -Y_ii sum_k U_ik Y_kj (upper).
-// Xb, Yb: 64 x kLdb LDS outputs; Tb: 2 x 768 LDS scratch.  Every thread of
-// the workgroup must call this (it contains barriers).
+// Xb, Yb: 64 x kLdb LDS outputs; Tb: 1536 elements of LDS scratch.  Every
+// thread of the workgroup must call this (it contains barriers).
 template <typename T>
 __device__ __forceinline__ void diag_inverses(const T *Cb, int W, T *D, T *Xb, T *Yb, T *Tb) {
     constexpr int HALF = lu_threads<T> / 2;
@@ -181,48 +182,51 @@ __device__ __forceinline__ void diag_inverses(const T *Cb, int W, T *D, T *Xb, T
         }
     }
     __syncthreads();
-    // off-diagonal blocks, by distance from the diagonal
-    for (int d = 1; d < nb; ++d) {
-        const int cnt = (nb - d) * 256;
-        for (int e = h; e < cnt; e += HALF) {
-            const int bi = e >> 8, r = (e >> 4) & 15, c = e & 15;
-            // lower: block (bi + d, bi), sum over columns 16 bi .. 16 (bi + d) - 1;
-            // upper: block (bi, bi + d), sum over columns 16 (bi + 1) .. 16 (bi + d) + 15;
-            // d blocks of 16 terms either way, in ascending order
-            const int i = upper ? bi : bi + d, jb = upper ? bi + d : bi;
-            const int mb = upper ? 16 * (bi + 1) : 16 * bi;
-            const T *crow_i = Cb + (16 * i + r) * kLdb;
-            const T *zcol = Z + 16 * jb + c;
-            double acc = 0.0;
-            for (int kb = 0; kb < d; ++kb) {
-                const int m0 = mb + 16 * kb;
-                T cv[16], zv[16];
+    // off-diagonal blocks, by distance from the diagonal, one wave per block on
+    // the matrix cores: the sum over the blocks between, then the product with
+    // the diagonal block's inverse (lower X_ij = -X_ii sum_{k=j..i-1} L_ik X_kj,
+    // upper Y_ij = -Y_ii sum_{k=i+1..j} U_ik Y_kj)
+    {
+        using Mt = Mfma<T>;
+        using acc_t = typename Mt::acc_t;
+        const int wave = tid >> 6, lane = tid & 63, lr = lane & 15, lg = lane >> 4;
+        for (int d = 1; d < nb; ++d) {
+            if (wave < 2 * (nb - d)) {
+                const bool up = wave >= nb - d;
+                const int bi = up ? wave - (nb - d) : wave;
+                const int i = up ? bi : bi + d, jb = up ? bi + d : bi;
+                const int k0 = up ? i + 1 : jb;
+                T *Zt = up ? Yb : Xb;
+                acc_t acc = acc_t{0, 0, 0, 0};
+                for (int kb = 0; kb < d; ++kb) {
+                    const int k = k0 + kb;
 #pragma unroll
-                for (int mm = 0; mm < 16; ++mm) {
-                    cv[mm] = crow_i[m0 + mm];
-                    zv[mm] = zcol[(m0 + mm) * kLdb];
+                    for (int st = 0; st < 4; ++st)
+                        acc = Mt::mma(Cb[(16 * i + lr) * kLdb + 16 * k + 4 * st + lg],
+                                      Zt[(16 * k + 4 * st + lg) * kLdb + 16 * jb + lr], acc);
+                }
+                acc_t acc2 = acc_t{0, 0, 0, 0};
+                if constexpr (sizeof(T) == sizeof(double)) {
+                    // the accumulator's register st holds rows 4 st + lane / 16:
+                    // the B operand of step st as it stands
+#pragma unroll
+                    for (int st = 0; st < 4; ++st)
+                        acc2 = Mt::mma(Zt[(16 * i + lr) * kLdb + 16 * i + 4 * st + lg], acc[st], acc2);
+                } else {
+                    T *Ts = Tb + 256 * wave;
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) Ts[Mt::row(lane, v) * 16 + lr] = acc[v];
+                    wave_lds_order();
+#pragma unroll
+                    for (int st = 0; st < 4; ++st)
+                        acc2 = Mt::mma(Zt[(16 * i + lr) * kLdb + 16 * i + 4 * st + lg], Ts[(4 * st + lg) * 16 + lr],
+                                       acc2);
                 }
 #pragma unroll
-                for (int mm = 0; mm < 16; ++mm) acc += double(cv[mm]) * double(zv[mm]);
+                for (int v = 0; v < 4; ++v) Zt[(16 * i + Mt::row(lane, v)) * kLdb + 16 * jb + lr] = -acc2[v];
             }
-            Tz[e] = T(acc);
+            __syncthreads();
         }
-        __syncthreads();
-        for (int e = h; e < cnt; e += HALF) {
-            const int bi = e >> 8, r = (e >> 4) & 15, c = e & 15;
-            const int i = upper ? bi : bi + d, jb = upper ? bi + d : bi;
-            T zv[16], tv[16];
-#pragma unroll
-            for (int m = 0; m < 16; ++m) {
-                zv[m] = Z[(16 * i + r) * kLdb + 16 * i + m];
-                tv[m] = Tz[(bi << 8) + (m << 4) + c];
-            }
-            double acc = 0.0;
-#pragma unroll
-            for (int m = 0; m < 16; ++m) acc += double(zv[m]) * double(tv[m]);
-            Z[(16 * i + r) * kLdb + 16 * jb + c] = T(-acc);
-        }
-        __syncthreads();
     }
     for (int e = h; e < 64 * 64; e += HALF) D[(upper ? kLuW * kLuW : 0) + e] = Z[(e >> 6) * kLdb + (e & 63)];
 }
