@@ -200,13 +200,17 @@ def test_gradient_exact_where_zeta_or_G0_vanish(ab, dev, where):
                 assert dphi[c, j] == 0.0, (c, j)
             else:
                 assert abs(dphi[c, j] - ref[j]) <= 1e-3 * abs(ref[j]), (c, j, dphi[c, j], ref[j])
-    # the autograd function takes the same path
+    # the autograd function takes the same path: with the same rate
+    # prefactors (exp(log alpha) differs from alpha in the last bit) the
+    # same gradient
     phys = [v.clone().requires_grad_(True) for v in args[:5]]
     log_alpha = torch.tensor(np.log(net.alpha), dtype=torch.float64, device=dev)
     x, st2 = ab.solve_diff(g, *phys, args[5], args[6], log_alpha)
     torch.log(x[:, targets]).sum().backward()
     assert torch.isfinite(phys[col].grad).all()
-    np.testing.assert_allclose(phys[col].grad.cpu().numpy(), dphi[:, col], rtol=1e-12, atol=0)
+    _, _, _, _, _, dphi_same = ab.solve_adjoint(g, *args, t(log_loss_grad(x.detach().cpu().numpy(), targets), dev),
+                                               alpha=torch.exp(log_alpha), phys_grad=True)
+    np.testing.assert_allclose(phys[col].grad.cpu().numpy(), dphi_same[:, col].cpu().numpy(), rtol=1e-12, atol=0)
 
 
 def test_autograd_refuses_cells_that_did_not_finish(ab, dev):
