@@ -501,7 +501,7 @@ abdf_status abdf_rhs(const abdf_network *net, int64_t n_cells, const double *k, 
     std::string err;
     const abdf::DeviceNet *dn = net->host.device_tables(err);
     if (!dn) return fail(ABDF_E_DEVICE, err);
-    if (sizeof(double) * (size_t(dn->S) + dn->R + dn->n_seg) > abdf::kMaxLds)
+    if (sizeof(double) * (size_t(dn->S) + dn->R) > abdf::kMaxLds)
         return fail(ABDF_E_ARG, "network too large for one workgroup's LDS");
     hipStream_t st = static_cast<hipStream_t>(stream);
     // with the timers on, the launch alone is bracketed by events

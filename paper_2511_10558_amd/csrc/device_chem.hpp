@@ -27,22 +27,21 @@ __device__ inline void cell_rates(const DeviceNet &n, const double *phi, double 
     }
 }
 
-// out_i = sum_r nu_ir v_r for per-reaction values v (LDS): each species' row of
-// the stoichiometry in segments of up to 32 entries (part[n_seg], LDS), then
-// the segments of a species in order.  Deterministic: a segment's entries are
-// summed in order from zero whichever lane takes it.
-// Each wave takes groups of 64 segments in the layout of DeviceNet::sg_ent, so
-// that its loads of the j-th entries of its lanes' segments are adjacent
-// (one or two cache lines instead of 64).  The entries are loaded eight at a
-// time before any is used, so the loads are in flight together.
+// out_i = sum_r nu_ir v_r for per-reaction values v (LDS), in the wave layout
+// of DeviceNet::sg_ent: each wave takes groups of 64 lanes; a lane sums its
+// entries in order from zero, then the lanes of each species are added
+// pairwise within the wave and the species' first lane writes out_i.
+// Deterministic: the order of every sum is fixed by the layout, whichever
+// wave takes a group.  The entries are loaded eight at a time before any is
+// used, so the loads are in flight together.  Ends with a barrier.
 template <int NT = kBlock>
-__device__ __forceinline__ void species_gather(const DeviceNet &n, const double *v, double *part, double *out) {
+__device__ __forceinline__ void species_gather(const DeviceNet &n, const double *v, double *out) {
     constexpr int kB = 8;
     const int lane = threadIdx.x & 63;
     for (int g = threadIdx.x >> 6; g < n.n_sgroup; g += NT / 64) {
-        const int meta = n.sg_lane[g * 64 + lane];
-        const int L = n.sg_len[g];
-        const int mine = meta < 0 ? 0 : (meta & 63);
+        const int mine = n.sg_lane[g * 64 + lane];
+        const int lw = n.sg_len[g];
+        const int L = lw & 0xffffff, steps = lw >> 24;
         const int32_t *ent = n.sg_ent + n.sg_base[g] + lane;
         double acc = 0.0;
         for (int jb = 0; jb < L; jb += kB) {
@@ -56,24 +55,26 @@ __device__ __forceinline__ void species_gather(const DeviceNet &n, const double 
             for (int u = 0; u < kB; ++u)
                 if (jb + u < mine) acc += double((w[u] & 7) - 4) * vv[u];
         }
-        if (meta >= 0) part[meta >> 6] = acc;
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < n.S; i += NT) {
-        double acc = 0.0;
-        for (int s = n.seg_ptr[i]; s < n.seg_ptr[i + 1]; ++s) acc += part[s];
-        out[i] = acc;
+        // the species' lanes pairwise; steps is the same for the whole wave
+        const int red = n.sg_red[g * 64 + lane];
+        const int q = red < 0 ? 0 : (red >> 7) & 127, m = red < 0 ? 1 : red & 127;
+        for (int t = 0; t < steps; ++t) {
+            const int off = 1 << t;
+            const double o = __shfl_down(acc, off);
+            if ((q & (2 * off - 1)) == 0 && q + off < m) acc += o;
+        }
+        if (red >= 0 && q == 0) out[red >> 14] = acc;
     }
     __syncthreads();
 }
 
 // f = nu . rate(x) for one cell.  x in LDS; k in global memory (one coalesced
-// pass); rate[R] and part[n_seg] are LDS scratch; f may be LDS or global.
+// pass); rate[R] is LDS scratch; f may be LDS or global.
 // Deterministic: every sum runs in a fixed order.
 // kWide: more loads in flight per thread, for kernels with registers to spare.
 template <int NT = kBlock, bool kWide = false>
 __device__ __forceinline__ void cell_rhs(const DeviceNet &n, const double *__restrict__ k, const double *x,
-                                double *rate, double *part, double *f) {
+                                double *rate, double *f) {
     // kU reactions per thread per pass, their loads issued before any use
     constexpr int kU = kWide ? 6 : 4;
     for (int r0 = threadIdx.x; r0 < n.R; r0 += kU * NT) {
@@ -95,15 +96,15 @@ __device__ __forceinline__ void cell_rhs(const DeviceNet &n, const double *__res
         }
     }
     __syncthreads();
-    species_gather<NT>(n, rate, part, f);
+    species_gather<NT>(n, rate, f);
 }
 
 // J(x) y = nu . (d rate / dx) y for one cell: per reaction
 // k_r (y_a x_b + x_a y_b) (k_r y_a for one reactant; the same expression gives
 // 2 k_r x_a y_a for A + A), then the species sums of cell_rhs.  x, y in LDS;
-// drate[R], part[n_seg] LDS scratch.
+// drate[R] LDS scratch.
 __device__ __forceinline__ void cell_jvp(const DeviceNet &n, const double *__restrict__ k, const double *x,
-                                         const double *y, double *drate, double *part, double *out) {
+                                         const double *y, double *drate, double *out) {
     for (int r0 = threadIdx.x; r0 < n.R; r0 += 4 * kBlock) {
         int ab[4];
         double kr[4];
@@ -122,7 +123,7 @@ __device__ __forceinline__ void cell_jvp(const DeviceNet &n, const double *__res
         }
     }
     __syncthreads();
-    species_gather(n, drate, part, out);
+    species_gather(n, drate, out);
 }
 
 // The Jacobian nonzeros J_e(x) of one cell into jv[nnzJ] (global, written

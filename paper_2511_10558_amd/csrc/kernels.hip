@@ -321,8 +321,7 @@ __global__ void __launch_bounds__(kBlock) k_admit(Slots s, DeviceNet n, AdmitArg
     double *xs = smem;
     double *f0 = xs + S;
     double *rate = f0 + S;
-    double *part = rate + n.R;
-    double *f1 = part + n.n_seg;
+    double *f1 = rate + n.R;
     double *phi = s.phi + size_t(slot) * 5;
     double *k = s.k + size_t(slot) * n.R;
     double *D = s.D + size_t(slot) * kDRows * S;
@@ -384,7 +383,7 @@ __global__ void __launch_bounds__(kBlock) k_admit(Slots s, DeviceNet n, AdmitArg
     // starting step (Hairer, Norsett & Wanner, Solving ODEs I, Sec. II.4), for
     // the method's order: 1 (BDF's first step) or 5 (ESDIRK)
     const bool rk = s.method == ABDF_METHOD_ESDIRK5;
-    cell_rhs(n, k, xs, rate, part, f0);
+    cell_rhs(n, k, xs, rate, f0);
     {
         // rates that overflow at the initial state leave no step to take
         bool nf = false;
@@ -419,7 +418,7 @@ __global__ void __launch_bounds__(kBlock) k_admit(Slots s, DeviceNet n, AdmitArg
         cell_rates(n, phit, k);
     }
     __syncthreads();
-    cell_rhs(n, k, x1, rate, part, f1);
+    cell_rhs(n, k, x1, rate, f1);
     double s2 = 0.0;
     for (int i = threadIdx.x; i < S; i += kBlock) {
         const double sc = atol_of(s, cs, i) + rtol * fabs(xs[i]);
@@ -487,21 +486,20 @@ __global__ void __launch_bounds__(lu_threads<T>) k_factor(Slots s, DeviceNet n, 
 
 // Newton residual r = c f(x) - psi - d of one slot still iterating.  A
 // non-finite f ends the attempt as a corrector failure.  Cooperative; ends with
-// a barrier.  LDS: xs [S], rate [R], part [n_seg], f [S]; red [kWaves].
+// a barrier.  LDS: xs [S], rate [R], f [S]; red [kWaves].
 template <int NT>
 __device__ __forceinline__ void newton_rhs_cell(const Slots &s, const DeviceNet &n, int slot, double *smem,
                                                 double *red) {
     const int S = s.S;
     double *xs = smem;
     double *rate = xs + S;
-    double *part = rate + n.R;
-    double *f = part + n.n_seg;
+    double *f = rate + n.R;
     const double *x = s.x + size_t(slot) * S, *d = s.d + size_t(slot) * S, *psi = s.psi + size_t(slot) * S;
     double *rb = s.rb + size_t(slot) * S;
     const double c = s.ctl[slot].c;
     for (int i = threadIdx.x; i < S; i += NT) xs[i] = x[i];
     __syncthreads();
-    cell_rhs<NT>(n, s.k + size_t(slot) * n.R, xs, rate, part, f);
+    cell_rhs<NT>(n, s.k + size_t(slot) * n.R, xs, rate, f);
     bool nonfinite = false;
     for (int i = threadIdx.x; i < S; i += NT) {
         nonfinite |= !isfinite(f[i]);
@@ -526,7 +524,7 @@ __device__ __forceinline__ void newton_rhs_cell(const Slots &s, const DeviceNet 
 // The refining variant (FP32 factors after a corrector failure) refines once in FP64:
 // Delta += M^{-1} (r - (Delta - c J(x_J) Delta)), J applied through the
 // network's Jacobian term lists.  Cooperative; ends with a barrier.
-// LDS: b, y [NP] (refining: y2 [NP], xs [S], drate [R], part [n_seg]);
+// LDS: b, y [NP] (refining: y2 [NP], xs [S], drate [R]);
 // red [kLuW + kWaves]; decision: one shared int.
 template <typename T, bool kRefine>
 __device__ __forceinline__ void newton_solve_cell(const Slots &s, const DeviceNet &n, int slot, double *smem,
@@ -544,11 +542,11 @@ __device__ __forceinline__ void newton_solve_cell(const Slots &s, const DeviceNe
     const int N = min(NP, S + (S & 1));   // the padding past S is the identity's
     lu_solve_left<T>(A, Di, perm, perm, NP, N, b, y, red);
     if (kRefine) {
-        double *y2 = y + NP, *xs = y2 + NP, *drate = xs + S, *part = drate + n.R;
+        double *y2 = y + NP, *xs = y2 + NP, *drate = xs + S;
         const double c = s.ctl[slot].c_lu;
         for (int i = threadIdx.x; i < S; i += kBlock) xs[i] = s.xJ[size_t(slot) * S + i];
         __syncthreads();
-        cell_jvp(n, s.k + size_t(slot) * n.R, xs, y, drate, part, y2);   // y2 = J(x_J) y
+        cell_jvp(n, s.k + size_t(slot) * n.R, xs, y, drate, y2);   // y2 = J(x_J) y
         for (int i = threadIdx.x; i < NP; i += kBlock) b[i] = i < S ? rb[i] - (y[i] - c * y2[i]) : 0.0;
         __syncthreads();
         lu_solve_left<T>(A, Di, perm, perm, NP, N, b, y2, red);
@@ -605,7 +603,8 @@ __device__ __forceinline__ void newton_solve_cell(const Slots &s, const DeviceNe
 // kRhsThreads per slot: the residual's LDS (the rates) allows two workgroups per
 // CU, so each takes sixteen waves and the CU runs its full 32.
 constexpr int kRhsThreads = 1024;
-__global__ void __launch_bounds__(kRhsThreads) k_newton_rhs(Slots s, DeviceNet n, int ring, int which) {
+__global__ void __launch_bounds__(kRhsThreads) __attribute__((amdgpu_waves_per_eu(8)))
+k_newton_rhs(Slots s, DeviceNet n, int ring, int which) {
     extern __shared__ double smem[];
     __shared__ double red[kRhsThreads / 64];
     int count;
@@ -1428,10 +1427,10 @@ __global__ void __launch_bounds__(kRhsThreads) __attribute__((amdgpu_waves_per_e
 k_rhs_only(DeviceNet n, const double *k, const double *x, double *f) {
     extern __shared__ double smem[];
     const long long c = blockIdx.x;
-    double *xs = smem, *rate = xs + n.S, *part = rate + n.R;
+    double *xs = smem, *rate = xs + n.S;
     for (int i = threadIdx.x; i < n.S; i += kRhsThreads) xs[i] = x[size_t(c) * n.S + i];
     __syncthreads();
-    cell_rhs<kRhsThreads, true>(n, k + size_t(c) * n.R, xs, rate, part, f + size_t(c) * n.S);
+    cell_rhs<kRhsThreads, true>(n, k + size_t(c) * n.R, xs, rate, f + size_t(c) * n.S);
 }
 
 // Writes the unpadded S x S Newton matrix of each cell through the solver's
@@ -1734,7 +1733,7 @@ hipError_t launch_rates(const DeviceNet &n, const PhysArgs &p, long long cells, 
 }
 
 hipError_t launch_rhs(const DeviceNet &n, long long cells, const double *k, const double *x, double *f, hipStream_t st) {
-    const size_t lds = sizeof(double) * (size_t(n.S) + n.R + n.n_seg);
+    const size_t lds = sizeof(double) * (size_t(n.S) + n.R);
     hipLaunchKernelGGL(k_rhs_only, dim3(cells), dim3(kRhsThreads), lds, st, n, k, x, f);
     return LAUNCH_CHECK();
 }

@@ -56,15 +56,15 @@ struct PhysArgs {
 };
 
 // LDS bytes per kernel for a network
-inline size_t admit_lds(const DeviceNet &n) { return sizeof(double) * (4 * size_t(n.S) + n.R + n.n_seg); }
+inline size_t admit_lds(const DeviceNet &n) { return sizeof(double) * (4 * size_t(n.S) + n.R); }
 inline size_t newton_lds(const DeviceNet &n) {
-    return sizeof(double) * (2 * size_t(n.S) + n.R + n.n_seg);
+    return sizeof(double) * (2 * size_t(n.S) + n.R);
 }
 inline size_t solve_lds(const DeviceNet &n) { return sizeof(double) * 2 * size_t(n.NP); }
 // the refining FP32 variant also holds the second solution, x_J and the
 // scratch of the Jacobian-vector product
 inline size_t solve_lds32(const DeviceNet &n) {
-    return sizeof(double) * (3 * size_t(n.NP) + n.S + n.R + n.n_seg);
+    return sizeof(double) * (3 * size_t(n.NP) + n.S + n.R);
 }
 size_t factor_lds(const DeviceNet &n, int prec);
 

@@ -48,8 +48,8 @@ HostNetwork::~HostNetwork() {
         if (!d) continue;
         int prev = 0;
         if (hipGetDevice(&prev) == hipSuccess && hipSetDevice(d->device) == hipSuccess) {
-            void *ptrs[] = {d->rx_ab, d->rx_type, d->alpha, d->beta, d->gamma, d->seg_ptr, d->seg_beg,
-                            d->f_ent, d->sg_base, d->sg_len, d->sg_lane, d->sg_ent, d->jrow_ptr, d->jcol, d->jrow, d->jterm_ptr, d->jt_rx_other, d->jt_coef,
+            void *ptrs[] = {d->rx_ab, d->rx_type, d->alpha, d->beta, d->gamma, d->sg_base, d->sg_len,
+                            d->sg_lane, d->sg_red, d->sg_ent, d->jrow_ptr, d->jcol, d->jrow, d->jterm_ptr, d->jt_rx_other, d->jt_coef,
                             d->rnu_ptr, d->rnu_ent, d->dcol_ptr, d->dcol_ent, d->dcol_coef, d->jidx,
                             d->jmask, d->jbase};
             for (void *p : ptrs)
@@ -162,48 +162,68 @@ void HostNetwork::finalize() {
         for (int j = 0; j < 2; ++j)
             if (react[size_t(r) * 2 + j] >= 0) nu[react[size_t(r) * 2 + j]][r] -= 1;
     }
-    // right-hand side entries, each species' row cut into segments
-    seg_ptr.assign(S + 1, 0);
-    seg_beg.clear();
-    f_ent.clear();
-    for (int i = 0; i < S; ++i) {
-        seg_ptr[i] = int32_t(seg_beg.size());
-        int in_seg = kRhsSegment;
-        for (auto &kv : nu[i]) {
-            if (kv.second == 0) continue;
-            if (in_seg == kRhsSegment) {
-                seg_beg.push_back(int32_t(f_ent.size()));
-                in_seg = 0;
-            }
-            f_ent.push_back((kv.first << 3) | (kv.second + 4));
-            ++in_seg;
-        }
-    }
-    seg_ptr[S] = int32_t(seg_beg.size());
-    seg_beg.push_back(int32_t(f_ent.size()));
+    // right-hand side: each species' nonzero entries, reactions ascending,
+    // packed as reaction << 3 | (nu + 4)
+    std::vector<std::vector<int32_t>> ent(S);
+    for (int i = 0; i < S; ++i)
+        for (auto &kv : nu[i])
+            if (kv.second != 0) ent[size_t(i)].push_back((kv.first << 3) | (kv.second + 4));
     {
-        // wave layout of the segments (see DeviceNet::sg_ent)
-        const int nseg = int(seg_beg.size()) - 1;
-        std::vector<int> order(static_cast<size_t>(nseg));
-        for (int i = 0; i < nseg; ++i) order[size_t(i)] = i;
-        auto len = [&](int q) { return seg_beg[size_t(q) + 1] - seg_beg[size_t(q)]; };
-        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return len(a) > len(b); });
-        const int ng = (nseg + 63) / 64;
-        sg_base.assign(size_t(ng), 0);
-        sg_len.assign(size_t(ng), 0);
-        sg_lane.assign(size_t(ng) * 64, -1);
+        // wave layout (DeviceNet::sg_ent): species i takes m_i consecutive
+        // lanes of one group, its entries split as evenly as they go
+        const size_t nS = static_cast<size_t>(S);
+        std::vector<int> m(nS), len(nS), order(nS);
+        for (int i = 0; i < S; ++i) {
+            const int ni = int(ent[size_t(i)].size());
+            m[size_t(i)] = std::max(1, std::min(64, (ni + kRhsSegment - 1) / kRhsSegment));
+            len[size_t(i)] = (ni + m[size_t(i)] - 1) / m[size_t(i)];
+            order[size_t(i)] = i;
+        }
+        // longest lanes first, each species into the first group with room:
+        // a group's loop runs as long as its first species' lanes
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+            return len[size_t(a)] != len[size_t(b)] ? len[size_t(a)] > len[size_t(b)] : m[size_t(a)] > m[size_t(b)];
+        });
+        std::vector<int> used;
+        std::vector<std::vector<int>> members;
+        for (int i : order) {
+            size_t g = 0;
+            while (g < used.size() && used[g] + m[size_t(i)] > 64) ++g;
+            if (g == used.size()) {
+                used.push_back(0);
+                members.emplace_back();
+            }
+            members[g].push_back(i);
+            used[g] += m[size_t(i)];
+        }
+        const size_t ng = used.size();
+        sg_base.assign(ng, 0);
+        sg_len.assign(ng, 0);
+        sg_lane.assign(ng * 64, 0);
+        sg_red.assign(ng * 64, -1);
         sg_ent.clear();
-        for (int g = 0; g < ng; ++g) {
-            int L = 0;
-            for (int l = 0; l < 64 && g * 64 + l < nseg; ++l) L = std::max(L, len(order[size_t(g * 64 + l)]));
-            sg_base[size_t(g)] = int32_t(sg_ent.size());
-            sg_len[size_t(g)] = L;
+        for (size_t g = 0; g < ng; ++g) {
+            int L = 0, mm = 1, steps = 0;
+            for (int i : members[g]) {
+                L = std::max(L, len[size_t(i)]);
+                mm = std::max(mm, m[size_t(i)]);
+            }
+            while ((1 << steps) < mm) ++steps;
+            sg_base[g] = int32_t(sg_ent.size());
+            sg_len[g] = L | (steps << 24);
             sg_ent.resize(sg_ent.size() + size_t(L) * 64, 4);
-            for (int l = 0; l < 64 && g * 64 + l < nseg; ++l) {
-                const int q = order[size_t(g * 64 + l)];
-                sg_lane[size_t(g) * 64 + l] = (q << 6) | len(q);
-                for (int j = 0; j < len(q); ++j)
-                    sg_ent[size_t(sg_base[size_t(g)]) + size_t(j) * 64 + l] = f_ent[size_t(seg_beg[size_t(q)] + j)];
+            int lane = 0;
+            for (int i : members[g]) {
+                const std::vector<int32_t> &e = ent[size_t(i)];
+                const int ni = int(e.size()), mi = m[size_t(i)], base = ni / mi, extra = ni % mi;
+                size_t next = 0;
+                for (int q = 0; q < mi; ++q, ++lane) {
+                    const int lq = base + (q < extra ? 1 : 0);
+                    sg_lane[g * 64 + size_t(lane)] = lq;
+                    sg_red[g * 64 + size_t(lane)] = (i << 14) | (q << 7) | mi;
+                    for (int j = 0; j < lq; ++j)
+                        sg_ent[size_t(sg_base[g]) + size_t(j) * 64 + size_t(lane)] = e[next++];
+                }
             }
         }
     }
@@ -385,12 +405,10 @@ const DeviceNet *HostNetwork::device_tables(std::string &err) const {
     chk(upload(&d->alpha, alpha));
     chk(upload(&d->beta, beta));
     chk(upload(&d->gamma, gamma));
-    chk(upload(&d->seg_ptr, seg_ptr));
-    chk(upload(&d->seg_beg, seg_beg));
-    chk(upload(&d->f_ent, f_ent));
     chk(upload(&d->sg_base, sg_base));
     chk(upload(&d->sg_len, sg_len));
     chk(upload(&d->sg_lane, sg_lane));
+    chk(upload(&d->sg_red, sg_red));
     chk(upload(&d->sg_ent, sg_ent));
     chk(upload(&d->jrow_ptr, jrow_ptr));
     chk(upload(&d->jcol, jcol));
@@ -407,7 +425,6 @@ const DeviceNet *HostNetwork::device_tables(std::string &err) const {
     chk(upload(&d->jmask, jmask));
     chk(upload(&d->jbase, jbase));
     d->nbw = (NP + 63) / 64;
-    d->n_seg = int32_t(seg_beg.size()) - 1;
     d->n_sgroup = int32_t(sg_base.size());
     d->nnzJ = int32_t(jcol.size());
     d->nterm = int32_t(jt_coef.size());

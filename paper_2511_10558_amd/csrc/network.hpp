@@ -13,7 +13,7 @@ constexpr int kTwoBody = 0;
 constexpr int kCosmicRay = 1;
 constexpr int kPhoto = 2;
 constexpr int kCrPhoton = 3;   // photoreaction by cosmic-ray-induced photons
-constexpr int kRhsSegment = 32;   // CSR entries summed by one thread before the per-species pass
+constexpr int kRhsSegment = 32;   // right-hand-side entries summed by one lane before the species' lanes combine
 
 // Device copies of the network tables (one per HIP device).
 struct DeviceNet {
@@ -24,19 +24,20 @@ struct DeviceNet {
     int32_t *rx_ab = nullptr;      // reactant a in low 16 bits, b in high 16 bits (0xffff: none)
     int32_t *rx_type = nullptr;
     double *alpha = nullptr, *beta = nullptr, *gamma = nullptr;
-    // right-hand side: species rows split into segments of <= kRhsSegment entries
-    int32_t n_seg = 0;
-    int32_t *seg_ptr = nullptr;    // [S+1] first segment of each species
-    int32_t *seg_beg = nullptr;    // [n_seg+1] first entry of each segment (entries are contiguous)
-    int32_t *f_ent = nullptr;      // packed entry: reaction index << 3 | (nu + 4)
-    // the same segments laid out for a wave: sorted by length (longest first)
-    // and taken 64 at a time; entry j of the 64 segments of group g sits at
-    // sg_ent[sg_base[g] + 64 j + lane], so a wave's loads of entry j are adjacent
+    // right-hand side f_i = sum_r nu_ir rate_r in the layout of a wave: species
+    // i's nonzero entries (reactions ascending) are split over m_i =
+    // min(64, ceil(n_i / kRhsSegment)) consecutive lanes of one group of 64
+    // lanes (at least one lane per species); entry j of the lanes of group g
+    // sits at sg_ent[sg_base[g] + 64 j + lane], so a wave's loads of entry j
+    // are adjacent.  A lane sums its entries in order, then the lanes of a
+    // species are added pairwise (lane 2t takes lane 2t+1, then 4t takes
+    // 4t+2, ...) and the species' first lane holds f_i.
     int32_t n_sgroup = 0;
     int32_t *sg_base = nullptr;    // [n_sgroup] first entry of the group
-    int32_t *sg_len = nullptr;     // [n_sgroup] longest segment of the group
-    int32_t *sg_lane = nullptr;    // [64 n_sgroup] segment << 6 | its length, -1 for no segment
-    int32_t *sg_ent = nullptr;     // packed entries as f_ent, 4 (coefficient 0) in the padding
+    int32_t *sg_len = nullptr;     // [n_sgroup] longest lane | pairwise steps (ceil log2 of the widest species) << 24
+    int32_t *sg_lane = nullptr;    // [64 n_sgroup] entries of the lane
+    int32_t *sg_red = nullptr;     // [64 n_sgroup] species << 14 | lane within the species << 7 | m_i; -1 unused
+    int32_t *sg_ent = nullptr;     // packed entries reaction << 3 | (nu + 4); 4 (coefficient 0) in the padding
     // Jacobian: nonzeros of J grouped by row, each with its list of terms
     int32_t *jrow_ptr = nullptr;   // [S+1]
     int32_t *jcol = nullptr;       // [nnzJ]
@@ -77,8 +78,7 @@ struct HostNetwork {
 
     // derived (built by finalize())
     int S = 0, R = 0, E = 0, NP = 0;
-    std::vector<int32_t> seg_ptr, seg_beg, f_ent;
-    std::vector<int32_t> sg_base, sg_len, sg_lane, sg_ent;
+    std::vector<int32_t> sg_base, sg_len, sg_lane, sg_red, sg_ent;
     std::vector<int32_t> jrow_ptr, jcol, jrow, jterm_ptr, jt_rx_other;
     std::vector<double> jt_coef;
     std::vector<int32_t> rnu_ptr, rnu_ent, dcol_ptr, dcol_ent, jidx, jbase;

@@ -80,6 +80,27 @@ def test_rhs_matches_oracle(ab, dev, name):
         assert np.all(np.abs(f[c] - ref) <= bound + 1e-300)
 
 
+def test_rhs_of_a_species_wider_than_a_wave(ab, dev):
+    # H takes part in 2100 reactions: 64 lanes of 33 entries, more than
+    # kRhsSegment per lane; Z in none, so its f is exactly zero
+    from tests import tiny_nets
+    net = tiny_nets.hub()
+    g = ab.Network.from_text(net.to_text())
+    rng = np.random.default_rng(15)
+    conds = [dict(T=T, n_H=1e4, A_V=2.0, zeta=1.3e-17, G0=1.0) for T in (10.0, 30.0, 100.0, 300.0, 1000.0)]
+    x = np.exp(rng.uniform(np.log(1e-8), 0.0, (len(conds), net.n_species)))
+    K = np.array([chem.rate_coefficients(net, **cd) for cd in conds])
+    f = ab.rhs(g, t(K, dev), t(x, dev)).cpu().numpy()
+    absnu = abs(chem.stoichiometry(net))
+    z = net.species.index("Z")
+    assert np.all(f[:, z] == 0.0)
+    for c in range(len(conds)):
+        ref = chem.Chemistry(net, K[c]).f(x[c])
+        bound = 16 * EPS * (absnu @ chem.reaction_rates(net, K[c], x[c]))
+        assert np.all(np.abs(f[c] - ref) <= bound + 1e-300)
+        assert f[c, 0] < 0 and abs(f[c, 0] - ref[0]) <= bound[0]
+
+
 @pytest.mark.parametrize("name", ["small", "net200", "net500"])
 def test_newton_matrix_matches_oracle(ab, dev, name):
     net = synth.network_for_config(name)

@@ -66,3 +66,13 @@ def four_types(albedo=0.6):
         (CR_PHOTON, ["C"], ["C+", "e-"], 1.0, 0.0, 1020.0),
     ]
     return synth.make_network("four-types", sp, rx, albedo=albedo)
+
+
+def hub(n_rx=2100, n_iso=40):
+    """One species (H) in n_rx two-body reactions H + A_i -> B_j, more than a
+    wave's 64 lanes of 32 entries hold, and one species (Z) in none."""
+    sp = ([("H", {"H": 1}, 0), ("Z", {"O": 1}, 0)] + [(f"A{i}", {"C": 1}, 0) for i in range(n_iso)]
+          + [(f"B{i}", {"C": 1, "H": 1}, 0) for i in range(n_iso)])
+    rx = [(TWO_BODY, ["H", f"A{j % n_iso}"], [f"B{(j // n_iso) % n_iso}"], 1e-10 * (1.0 + 0.37 * (j % 7)),
+           0.1 * (j % 3), 5.0 * (j % 5)) for j in range(n_rx)]
+    return synth.make_network("hub", sp, rx)
