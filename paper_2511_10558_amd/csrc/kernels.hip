@@ -1433,6 +1433,141 @@ k_rhs_only(DeviceNet n, const double *k, const double *x, double *f) {
     cell_rhs<kRhsThreads, true>(n, k + size_t(c) * n.R, xs, rate, f + size_t(c) * n.S);
 }
 
+// The standalone right-hand side, streaming: each workgroup walks the cells
+// blockIdx.x, blockIdx.x + gridDim.x, ...  The reactant pairs and each wave's
+// lane groups of the species sums (two 16-bit entries a register) stay in
+// registers for the whole launch, so the sums read LDS only; the next cell's
+// k and x are loaded into registers while the current cell's sums run, so
+// their memory latency hides behind the LDS work.  The lanes sum the entries
+// of species_gather in the same order, with the padding read from a zero
+// after the rates instead of being skipped (it adds +0), so no entry needs a
+// test.  LDS: rate [R], a zero, x [S], a one (the second factor of a
+// one-reactant rate).  A resident entry is the rate's byte offset | nu in 3
+// bits, two's complement.  Requires S <= kRhsStreamThreads, R < 8191, at
+// most kGPW * 8 lane groups of at most kRhsResidentLen entries, and R <= kKU
+// * kRhsStreamThreads (launch_rhs checks; other networks take k_rhs_only).
+constexpr int kRhsStreamThreads = 512;
+template <int kKU, int kGPW>
+__global__ void __launch_bounds__(kRhsStreamThreads) __attribute__((amdgpu_waves_per_eu(4)))
+k_rhs_stream(DeviceNet n, long long C, const double *__restrict__ k, const double *__restrict__ x,
+             double *__restrict__ f) {
+    constexpr int NT = kRhsStreamThreads, NW = NT / 64, kE = kRhsResidentLen / 2;
+    constexpr int kB = kGPW * kKU >= 16 ? 4 : 8;   // LDS reads in flight per lane, as registers allow
+    extern __shared__ double smem[];
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int S = n.S, R = n.R;
+    double *rate = smem, *xs = smem + R + 1;
+    // reactant pairs as LDS byte offsets into xs (the one at xs[S] for none)
+    uint32_t ab[kKU];
+#pragma unroll
+    for (int u = 0; u < kKU; ++u) {
+        const int r = tid + u * NT;
+        const int w = r < R ? n.rx_ab[r] : 0;
+        const int a = w & 0xffff, b = (w >> 16) & 0xffff;
+        ab[u] = uint32_t(a * 8) | (uint32_t(b == 0xffff ? S : b) * 8u << 16);
+    }
+    uint32_t ent[kGPW][kE];
+    int red[kGPW], L[kGPW], steps[kGPW];
+    const uint32_t pad = uint32_t(R) << 3 | 1u;   // +1 times the zero after the rates
+#pragma unroll
+    for (int gi = 0; gi < kGPW; ++gi) {
+        const int g = wave + gi * NW;
+        const bool has = g < n.n_sgroup;
+        const int mine = has ? n.sg_lane[g * 64 + lane] : 0;
+        red[gi] = has ? n.sg_red[g * 64 + lane] : -1;
+        const int lw = has ? __builtin_amdgcn_readfirstlane(n.sg_len[g]) : 0;
+        L[gi] = lw & 0xffffff;
+        steps[gi] = lw >> 24;
+        auto conv = [](int32_t w) { return uint32_t(w & ~7) | (uint32_t((w & 7) - 4) & 7u); };
+        if (L[gi] > 0) {
+            // every load in flight at once: indexes past the group's longest
+            // lane are clamped to its last row and their values discarded
+            const int32_t *e = n.sg_ent + n.sg_base[g] + lane;
+            int32_t v[kRhsResidentLen];
+#pragma unroll
+            for (int j = 0; j < kRhsResidentLen; ++j) v[j] = e[min(j, L[gi] - 1) * 64];
+#pragma unroll
+            for (int j = 0; j < kE; ++j) {
+                const uint32_t lo = 2 * j < mine ? conv(v[2 * j]) : pad;
+                const uint32_t hi = 2 * j + 1 < mine ? conv(v[2 * j + 1]) : pad;
+                ent[gi][j] = lo | (hi << 16);
+            }
+        } else {
+#pragma unroll
+            for (int j = 0; j < kE; ++j) ent[gi][j] = pad | (pad << 16);
+        }
+    }
+    if (tid == 0) {
+        rate[R] = 0.0;
+        xs[S] = 1.0;
+    }
+    long long c = blockIdx.x;
+    double kr[kKU], xr = 0.0;
+    if (c < C) {
+#pragma unroll
+        for (int u = 0; u < kKU; ++u) kr[u] = tid + u * NT < R ? k[size_t(c) * R + tid + u * NT] : 0.0;
+        if (tid < S) xr = x[size_t(c) * S + tid];
+    }
+    const char *xb = reinterpret_cast<const char *>(xs);
+    const char *rb = reinterpret_cast<const char *>(rate);
+    for (; c < C; c += gridDim.x) {
+        const long long cn = c + gridDim.x;
+        const bool more = cn < C;
+        if (tid < S) xs[tid] = xr;
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kKU; ++u) {
+            const int r = tid + u * NT;
+            const double xa = *reinterpret_cast<const double *>(xb + (ab[u] & 0xffffu));
+            const double xc = *reinterpret_cast<const double *>(xb + (ab[u] >> 16));
+            if (r < R) rate[r] = kr[u] * xa * xc;
+        }
+        __syncthreads();
+        if (more) {
+#pragma unroll
+            for (int u = 0; u < kKU; ++u)
+                if (tid + u * NT < R) kr[u] = k[size_t(cn) * R + tid + u * NT];
+            if (tid < S) xr = x[size_t(cn) * S + tid];
+        }
+        double *fc = f + size_t(c) * S;
+        // the entries are opaque to the compiler from one cell to the next, so
+        // that it keeps them packed instead of hoisting what it derives from
+        // them (offsets, coefficients) out of the cell loop into registers
+#pragma unroll
+        for (int gi = 0; gi < kGPW; ++gi)
+#pragma unroll
+            for (int j = 0; j < kE; ++j) asm volatile("" : "+v"(ent[gi][j]));
+#pragma unroll
+        for (int gi = 0; gi < kGPW; ++gi) {
+            if (L[gi] == 0) continue;
+            double acc = 0.0;
+#pragma unroll
+            for (int jb = 0; jb < kRhsResidentLen; jb += kB) {
+                if (jb < L[gi]) {   // the same for the whole wave
+                    double vv[kB], cf[kB];
+#pragma unroll
+                    for (int u = 0; u < kB; ++u) {
+                        const int j = jb + u, sh = 16 * (j & 1);
+                        const uint32_t w = ent[gi][j >> 1];
+                        vv[u] = *reinterpret_cast<const double *>(rb + ((w >> sh) & 0xfff8u));
+                        cf[u] = double(int32_t(w << (29 - sh)) >> 29);
+                    }
+#pragma unroll
+                    for (int u = 0; u < kB; ++u) acc += cf[u] * vv[u];
+                }
+            }
+            const int q = red[gi] < 0 ? 0 : (red[gi] >> 7) & 127, m = red[gi] < 0 ? 1 : red[gi] & 127;
+            for (int t = 0; t < steps[gi]; ++t) {
+                const int off = 1 << t;
+                const double o = __shfl_down(acc, off);
+                if ((q & (2 * off - 1)) == 0 && q + off < m) acc += o;
+            }
+            if (red[gi] >= 0 && q == 0) fc[red[gi] >> 14] = acc;
+        }
+        __syncthreads();
+    }
+}
+
 // Writes the unpadded S x S Newton matrix of each cell through the solver's
 // own path: the Jacobian nonzeros at x (jacobian_values, into the scratch jv of
 // nnzJ doubles per cell), then every entry as NewtonMatrixSource yields it to
@@ -1732,8 +1867,41 @@ hipError_t launch_rates(const DeviceNet &n, const PhysArgs &p, long long cells, 
     return LAUNCH_CHECK();
 }
 
+template <int kKU, int kGPW>
+static hipError_t launch_rhs_stream(const DeviceNet &n, long long cells, const double *k, const double *x, double *f,
+                                    size_t lds, hipStream_t st) {
+    int dev = 0, ncu = 0, nb = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e == hipSuccess)
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rhs_stream<kKU, kGPW>, kRhsStreamThreads, lds);
+    if (e != hipSuccess) return e;
+    const long long grid = std::min<long long>(cells, std::max(1LL, (long long)nb * ncu));
+    hipLaunchKernelGGL((k_rhs_stream<kKU, kGPW>), dim3(unsigned(grid)), dim3(kRhsStreamThreads), lds, st, n, cells, k,
+                       x, f);
+    return LAUNCH_CHECK();
+}
+
 hipError_t launch_rhs(const DeviceNet &n, long long cells, const double *k, const double *x, double *f, hipStream_t st) {
     const size_t lds = sizeof(double) * (size_t(n.S) + n.R);
+    constexpr int NW = kRhsStreamThreads / 64;
+    const int ku = (n.R + kRhsStreamThreads - 1) / kRhsStreamThreads;
+    if (n.S <= kRhsStreamThreads && n.R < 8191 && n.sg_maxlen <= kRhsResidentLen) {
+        const size_t lds = sizeof(double) * (size_t(n.S) + n.R + 2);
+        if (n.n_sgroup <= NW) {
+            if (ku <= 2) return launch_rhs_stream<2, 1>(n, cells, k, x, f, lds, st);
+            if (ku <= 4) return launch_rhs_stream<4, 1>(n, cells, k, x, f, lds, st);
+            if (ku <= 8) return launch_rhs_stream<8, 1>(n, cells, k, x, f, lds, st);
+            if (ku <= 12) return launch_rhs_stream<12, 1>(n, cells, k, x, f, lds, st);
+            return launch_rhs_stream<16, 1>(n, cells, k, x, f, lds, st);
+        }
+        if (n.n_sgroup <= 2 * NW && ku <= 12) {
+            if (ku <= 2) return launch_rhs_stream<2, 2>(n, cells, k, x, f, lds, st);
+            if (ku <= 4) return launch_rhs_stream<4, 2>(n, cells, k, x, f, lds, st);
+            if (ku <= 8) return launch_rhs_stream<8, 2>(n, cells, k, x, f, lds, st);
+            return launch_rhs_stream<12, 2>(n, cells, k, x, f, lds, st);
+        }
+    }
     hipLaunchKernelGGL(k_rhs_only, dim3(cells), dim3(kRhsThreads), lds, st, n, k, x, f);
     return LAUNCH_CHECK();
 }

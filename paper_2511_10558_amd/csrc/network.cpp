@@ -12,12 +12,95 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <sstream>
 
 #include "../../include/astrobdf.h"
 
 namespace abdf {
+
+namespace {
+
+// Orders the entries of each lane of a group (the lane's sum runs in this
+// order) so that the rates the lanes read at the same step fall in different
+// LDS banks where the entries allow.  Lanes are taken sixteen at a time (at
+// 128 bytes a clock, a 64-lane read of doubles is served sixteen lanes at a
+// time) and a rate's bank is its index mod 16 (two of 32 four-byte banks per
+// double).  Step by step, a maximum matching
+// of the lanes still holding entries to distinct banks (lanes with the most
+// entries left first, banks with the most entries left tried first) picks
+// one entry per lane; a lane left unmatched takes the entry whose bank is
+// least used at that step.
+void order_for_banks(std::vector<std::vector<int32_t>> &lanes) {
+    constexpr int Q = 16, NB = 16;
+    auto bank = [](int32_t e) { return (e >> 3) % NB; };
+    for (size_t q0 = 0; q0 < lanes.size(); q0 += Q) {
+        std::vector<std::vector<int32_t>> rem(lanes.begin() + long(q0), lanes.begin() + long(q0 + Q)), out(Q);
+        size_t L = 0;
+        for (auto &v : rem) L = std::max(L, v.size());
+        for (size_t j = 0; j < L; ++j) {
+            int deg[NB] = {}, match_b[NB], match_l[Q], mult[NB] = {};
+            std::fill(match_b, match_b + NB, -1);
+            std::fill(match_l, match_l + Q, -1);
+            for (auto &v : rem)
+                for (int32_t e : v) ++deg[bank(e)];
+            std::vector<int> act;
+            for (int l = 0; l < Q; ++l)
+                if (!rem[size_t(l)].empty()) act.push_back(l);
+            std::vector<int> by_need = act;
+            std::stable_sort(by_need.begin(), by_need.end(),
+                             [&](int a, int b) { return rem[size_t(a)].size() > rem[size_t(b)].size(); });
+            // augmenting paths (Kuhn); a lane's banks tried most loaded first
+            auto options = [&](int l) {
+                std::vector<int> o;
+                bool has[NB] = {};
+                for (int32_t e : rem[size_t(l)]) has[bank(e)] = true;
+                for (int b = 0; b < NB; ++b)
+                    if (has[b]) o.push_back(b);
+                std::stable_sort(o.begin(), o.end(), [&](int a, int b) { return deg[a] > deg[b]; });
+                return o;
+            };
+            std::vector<std::vector<int>> opts(Q);
+            for (int l : act) opts[size_t(l)] = options(l);
+            std::vector<char> seen(NB);
+            std::function<bool(int)> augment = [&](int l) {
+                for (int b : opts[size_t(l)]) {
+                    if (seen[size_t(b)]) continue;
+                    seen[size_t(b)] = 1;
+                    if (match_b[b] < 0 || augment(match_b[b])) {
+                        match_b[b] = l;
+                        match_l[l] = b;
+                        return true;
+                    }
+                }
+                return false;
+            };
+            for (int l : by_need) {
+                std::fill(seen.begin(), seen.end(), 0);
+                augment(l);
+            }
+            for (int l : act) {
+                std::vector<int32_t> &v = rem[size_t(l)];
+                size_t pick = 0;
+                if (match_l[l] >= 0) {
+                    while (bank(v[pick]) != match_l[l]) ++pick;
+                } else {
+                    for (size_t t = 1; t < v.size(); ++t) {
+                        const int bt = bank(v[t]), bp = bank(v[pick]);
+                        if (mult[bt] < mult[bp] || (mult[bt] == mult[bp] && deg[bt] > deg[bp])) pick = t;
+                    }
+                }
+                ++mult[bank(v[pick])];
+                out[size_t(l)].push_back(v[pick]);
+                v.erase(v.begin() + long(pick));
+            }
+        }
+        for (int l = 0; l < Q; ++l) lanes[q0 + size_t(l)] = out[size_t(l)];
+    }
+}
+
+}  // namespace
 
 namespace {
 
@@ -172,29 +255,43 @@ void HostNetwork::finalize() {
         // wave layout (DeviceNet::sg_ent): species i takes m_i consecutive
         // lanes of one group, its entries split as evenly as they go
         const size_t nS = static_cast<size_t>(S);
-        std::vector<int> m(nS), len(nS), order(nS);
-        for (int i = 0; i < S; ++i) {
-            const int ni = int(ent[size_t(i)].size());
-            m[size_t(i)] = std::max(1, std::min(64, (ni + kRhsSegment - 1) / kRhsSegment));
-            len[size_t(i)] = (ni + m[size_t(i)] - 1) / m[size_t(i)];
-            order[size_t(i)] = i;
-        }
-        // longest lanes first, each species into the first group with room:
-        // a group's loop runs as long as its first species' lanes
-        std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
-            return len[size_t(a)] != len[size_t(b)] ? len[size_t(a)] > len[size_t(b)] : m[size_t(a)] > m[size_t(b)];
-        });
-        std::vector<int> used;
+        std::vector<int> m(nS), len(nS), order(nS), used;
         std::vector<std::vector<int>> members;
-        for (int i : order) {
-            size_t g = 0;
-            while (g < used.size() && used[g] + m[size_t(i)] > 64) ++g;
-            if (g == used.size()) {
-                used.push_back(0);
-                members.emplace_back();
+        auto pack = [&](int seg) {
+            for (int i = 0; i < S; ++i) {
+                const int ni = int(ent[size_t(i)].size());
+                m[size_t(i)] = std::max(1, std::min(64, (ni + seg - 1) / seg));
+                len[size_t(i)] = (ni + m[size_t(i)] - 1) / m[size_t(i)];
+                order[size_t(i)] = i;
             }
-            members[g].push_back(i);
-            used[g] += m[size_t(i)];
+            // longest lanes first, each species into the first group with
+            // room: a group's loop runs as long as its first species' lanes
+            std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+                return len[size_t(a)] != len[size_t(b)] ? len[size_t(a)] > len[size_t(b)] : m[size_t(a)] > m[size_t(b)];
+            });
+            used.clear();
+            members.clear();
+            for (int i : order) {
+                size_t g = 0;
+                while (g < used.size() && used[g] + m[size_t(i)] > 64) ++g;
+                if (g == used.size()) {
+                    used.push_back(0);
+                    members.emplace_back();
+                }
+                members[g].push_back(i);
+                used[g] += m[size_t(i)];
+            }
+        };
+        // lanes of kRhsSegment entries, or longer ones (up to kRhsResidentLen)
+        // where that brings the groups down to kRhsResidentGroups, the most the
+        // streaming right-hand side keeps in registers
+        for (int seg = kRhsSegment;; seg += 2) {
+            pack(seg);
+            if (used.size() <= size_t(kRhsResidentGroups)) break;
+            if (seg + 2 > kRhsResidentLen) {
+                pack(kRhsSegment);
+                break;
+            }
         }
         const size_t ng = used.size();
         sg_base.assign(ng, 0);
@@ -212,6 +309,7 @@ void HostNetwork::finalize() {
             sg_base[g] = int32_t(sg_ent.size());
             sg_len[g] = L | (steps << 24);
             sg_ent.resize(sg_ent.size() + size_t(L) * 64, 4);
+            std::vector<std::vector<int32_t>> lanes(64);
             int lane = 0;
             for (int i : members[g]) {
                 const std::vector<int32_t> &e = ent[size_t(i)];
@@ -221,10 +319,13 @@ void HostNetwork::finalize() {
                     const int lq = base + (q < extra ? 1 : 0);
                     sg_lane[g * 64 + size_t(lane)] = lq;
                     sg_red[g * 64 + size_t(lane)] = (i << 14) | (q << 7) | mi;
-                    for (int j = 0; j < lq; ++j)
-                        sg_ent[size_t(sg_base[g]) + size_t(j) * 64 + size_t(lane)] = e[next++];
+                    lanes[size_t(lane)].assign(e.begin() + long(next), e.begin() + long(next + size_t(lq)));
+                    next += size_t(lq);
                 }
             }
+            order_for_banks(lanes);
+            for (size_t l = 0; l < 64; ++l)
+                for (size_t j = 0; j < lanes[l].size(); ++j) sg_ent[size_t(sg_base[g]) + j * 64 + l] = lanes[l][j];
         }
     }
 
@@ -426,6 +527,8 @@ const DeviceNet *HostNetwork::device_tables(std::string &err) const {
     chk(upload(&d->jbase, jbase));
     d->nbw = (NP + 63) / 64;
     d->n_sgroup = int32_t(sg_base.size());
+    d->sg_maxlen = 0;
+    for (int32_t w : sg_len) d->sg_maxlen = std::max(d->sg_maxlen, w & 0xffffff);
     d->nnzJ = int32_t(jcol.size());
     d->nterm = int32_t(jt_coef.size());
     if (e != hipSuccess) {

@@ -14,6 +14,8 @@ constexpr int kCosmicRay = 1;
 constexpr int kPhoto = 2;
 constexpr int kCrPhoton = 3;   // photoreaction by cosmic-ray-induced photons
 constexpr int kRhsSegment = 32;   // right-hand-side entries summed by one lane before the species' lanes combine
+constexpr int kRhsResidentGroups = 16;   // lane groups the streaming right-hand side holds in registers
+constexpr int kRhsResidentLen = 40;      // the longest lane it holds
 
 // Device copies of the network tables (one per HIP device).
 struct DeviceNet {
@@ -26,13 +28,16 @@ struct DeviceNet {
     double *alpha = nullptr, *beta = nullptr, *gamma = nullptr;
     // right-hand side f_i = sum_r nu_ir rate_r in the layout of a wave: species
     // i's nonzero entries (reactions ascending) are split over m_i =
-    // min(64, ceil(n_i / kRhsSegment)) consecutive lanes of one group of 64
+    // min(64, ceil(n_i / segment)) consecutive lanes of one group of 64
     // lanes (at least one lane per species); entry j of the lanes of group g
     // sits at sg_ent[sg_base[g] + 64 j + lane], so a wave's loads of entry j
     // are adjacent.  A lane sums its entries in order, then the lanes of a
     // species are added pairwise (lane 2t takes lane 2t+1, then 4t takes
     // 4t+2, ...) and the species' first lane holds f_i.
+    // Lanes hold up to kRhsSegment entries, or up to kRhsResidentLen when that
+    // brings the groups down to kRhsResidentGroups.
     int32_t n_sgroup = 0;
+    int32_t sg_maxlen = 0;         // longest lane of any group
     int32_t *sg_base = nullptr;    // [n_sgroup] first entry of the group
     int32_t *sg_len = nullptr;     // [n_sgroup] longest lane | pairwise steps (ceil log2 of the widest species) << 24
     int32_t *sg_lane = nullptr;    // [64 n_sgroup] entries of the lane

@@ -101,6 +101,34 @@ def test_rhs_of_a_species_wider_than_a_wave(ab, dev):
         assert f[c, 0] < 0 and abs(f[c, 0] - ref[0]) <= bound[0]
 
 
+@pytest.mark.parametrize("name,n", [("net200", 1100), ("net500", 1500)])
+def test_rhs_batch_streams_cells(ab, dev, name, n):
+    # more cells than resident workgroups, so each workgroup takes several in
+    # turn (the next one's inputs loading while the current one's sums run):
+    # sampled rows match the oracle, every row conserves the elements, and a
+    # row equals the same cell evaluated alone, bit for bit
+    net = synth.network_for_config(name)
+    g = ab.Network.from_text(net.to_text())
+    rng = np.random.default_rng(17)
+    # the coefficients are any positive numbers to the right-hand side
+    K = np.exp(rng.uniform(np.log(1e-14), np.log(1e-2), (n, net.n_reactions)))
+    x = np.exp(rng.uniform(np.log(1e-20), 0.0, (n, net.n_species)))
+    Kd = t(K, dev)
+    f = ab.rhs(g, Kd, t(x, dev)).cpu().numpy()
+    absnu = abs(chem.stoichiometry(net))
+    sample = np.unique(np.concatenate([[0, 1, n - 1], rng.choice(n, 21, replace=False)]))
+    for c in sample:
+        ref = chem.Chemistry(net, K[c]).f(x[c])
+        bound = 16 * EPS * (absnu @ chem.reaction_rates(net, K[c], x[c]))
+        assert np.all(np.abs(f[c] - ref) <= bound + 1e-300), c
+    W = net.conservation_matrix().astype(float)
+    scale = np.array([absnu @ chem.reaction_rates(net, K[c], x[c]) for c in range(n)])
+    assert np.all(np.abs(f @ W.T) <= 32 * EPS * (scale @ np.abs(W).T) + 1e-300)
+    for c in sample[:4]:
+        alone = ab.rhs(g, Kd[c:c + 1], t(x[c:c + 1], dev)).cpu().numpy()
+        assert np.array_equal(alone[0], f[c]), c
+
+
 @pytest.mark.parametrize("name", ["small", "net200", "net500"])
 def test_newton_matrix_matches_oracle(ab, dev, name):
     net = synth.network_for_config(name)
