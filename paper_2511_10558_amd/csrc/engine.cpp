@@ -275,7 +275,7 @@ int Engine::layout(int nslots, void *base, std::string &err) {
     grid_factor64_max_ = cus * resident_per_cu(0, ABDF_PREC_FP64, lds_factor_);
     grid_solve64_max_ = cus * resident_per_cu(2, ABDF_PREC_FP64, lds_solve_);
     grid_factor_max_ = f32 ? cus * resident_per_cu(0, prec_, lds_factor32_) : grid_factor64_max_;
-    grid_newton_max_ = cus * resident_per_cu(1, prec_, lds_newton_);
+    grid_newton_max_ = cus * newton_rhs_resident_per_cu(dn_, prec_, lds_newton_);
     grid_solve_max_ = f32 ? cus * resident_per_cu(2, prec_, lds_solve_) : grid_solve64_max_;
     grid_solve_ref_max_ = cus * resident_per_cu(4, prec_, lds_solve32_);
     grid_adj_solve_max_ = cus * resident_per_cu(3, prec_, adj_solve_lds(dn_));

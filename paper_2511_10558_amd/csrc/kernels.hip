@@ -616,6 +616,223 @@ k_newton_rhs(Slots s, DeviceNet n, int ring, int which) {
     }
 }
 
+// Streaming right-hand sides (k_rhs_stream, k_newton_rhs_stream): a
+// workgroup of kRhsStreamThreads evaluates one cell after another, and each
+// thread keeps for the whole launch its reactant pairs and its wave's lane
+// groups of the species sums (two 16-bit entries a register), so the sums read
+// LDS only and the next cell's inputs can be in flight while they run.  The
+// lanes sum the entries of species_gather in the same order; the padding
+// reads a -0.0 placed after the rates instead of being skipped (adding -0.0
+// changes no sum, signed zeros included), so no entry needs a test, and a
+// one-reactant rate takes a 1.0 placed after x as its second factor.
+// LDS: rate [R], -0.0, x [S], 1.0.  A resident entry is the rate's byte offset
+// | nu in 3 bits, two's complement.  Requires S <= kRhsStreamThreads, R <
+// 8191, at most kGPW * 8 lane groups of at most kRhsResidentLen entries, and R
+// <= kKU * kRhsStreamThreads (rhs_stream_shape checks).
+constexpr int kRhsStreamThreads = 512;
+template <int kKU, int kGPW>
+struct RhsResident {
+    static constexpr int NT = kRhsStreamThreads, NW = NT / 64, kE = kRhsResidentLen / 2;
+    static constexpr int kB = kGPW * kKU >= 16 ? 4 : 8;   // LDS reads in flight per lane, as registers allow
+    uint32_t ab[kKU];
+    uint32_t ent[kGPW][kE];
+    int red[kGPW], L[kGPW], steps[kGPW];
+
+    __device__ __forceinline__ static size_t lds_doubles(const DeviceNet &n) { return size_t(n.S) + n.R + 2; }
+
+    // reactant pairs as LDS byte offsets into x (the 1.0 at x[S] for none)
+    __device__ __forceinline__ void load_pairs(const DeviceNet &n) {
+#pragma unroll
+        for (int u = 0; u < kKU; ++u) {
+            const int r = threadIdx.x + u * NT;
+            const int w = r < n.R ? n.rx_ab[r] : 0;
+            const int a = w & 0xffff, b = (w >> 16) & 0xffff;
+            ab[u] = uint32_t(a * 8) | (uint32_t(b == 0xffff ? n.S : b) * 8u << 16);
+        }
+    }
+
+    __device__ __forceinline__ void load(const DeviceNet &n) {
+        const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+        const int R = n.R;
+        load_pairs(n);
+        const uint32_t pad = uint32_t(R) << 3 | 1u;   // +1 times the -0.0 after the rates
+        auto conv = [](int32_t w) { return uint32_t(w & ~7) | (uint32_t((w & 7) - 4) & 7u); };
+#pragma unroll
+        for (int gi = 0; gi < kGPW; ++gi) {
+            const int g = wave + gi * NW;
+            const bool has = g < n.n_sgroup;
+            const int mine = has ? n.sg_lane[g * 64 + lane] : 0;
+            red[gi] = has ? n.sg_red[g * 64 + lane] : -1;
+            const int lw = has ? __builtin_amdgcn_readfirstlane(n.sg_len[g]) : 0;
+            L[gi] = lw & 0xffffff;
+            steps[gi] = lw >> 24;
+            if (L[gi] > 0) {
+                // every load in flight at once: indexes past the group's
+                // longest lane are clamped to its last row, their values unused
+                const int32_t *e = n.sg_ent + n.sg_base[g] + lane;
+                int32_t v[kRhsResidentLen];
+#pragma unroll
+                for (int j = 0; j < kRhsResidentLen; ++j) v[j] = e[min(j, L[gi] - 1) * 64];
+#pragma unroll
+                for (int j = 0; j < kE; ++j) {
+                    const uint32_t lo = 2 * j < mine ? conv(v[2 * j]) : pad;
+                    const uint32_t hi = 2 * j + 1 < mine ? conv(v[2 * j + 1]) : pad;
+                    ent[gi][j] = lo | (hi << 16);
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < kE; ++j) ent[gi][j] = pad | (pad << 16);
+            }
+        }
+    }
+
+    __device__ __forceinline__ static void init_lds(const DeviceNet &n, double *smem) {
+        if (threadIdx.x == 0) {
+            smem[n.R] = -0.0;
+            smem[n.R + 1 + n.S] = 1.0;
+        }
+    }
+
+    // rate[r] = k_r x_a x_b for this thread's reactions (x in LDS)
+    __device__ __forceinline__ void rates(const DeviceNet &n, const double (&kr)[kKU], double *smem) const {
+        const char *xb = reinterpret_cast<const char *>(smem + n.R + 1);
+#pragma unroll
+        for (int u = 0; u < kKU; ++u) {
+            const int r = threadIdx.x + u * NT;
+            const double xa = *reinterpret_cast<const double *>(xb + (ab[u] & 0xffffu));
+            const double xc = *reinterpret_cast<const double *>(xb + (ab[u] >> 16));
+            if (r < n.R) smem[r] = kr[u] * xa * xc;
+        }
+    }
+
+    // out_i = sum_r nu_ir rate_r, written by each species' first lane
+    __device__ __forceinline__ void sums(const DeviceNet &n, const double *smem, double *out) {
+        // the entries are opaque to the compiler from one cell to the next,
+        // so that it keeps them packed instead of hoisting what it derives from
+        // them (offsets, coefficients) out of the cell loop into registers
+#pragma unroll
+        for (int gi = 0; gi < kGPW; ++gi)
+#pragma unroll
+            for (int j = 0; j < kE; ++j) asm volatile("" : "+v"(ent[gi][j]));
+        const char *rb = reinterpret_cast<const char *>(smem);
+#pragma unroll
+        for (int gi = 0; gi < kGPW; ++gi) {
+            if (L[gi] == 0) continue;
+            double acc = 0.0;
+#pragma unroll
+            for (int jb = 0; jb < kRhsResidentLen; jb += kB) {
+                if (jb < L[gi]) {   // the same for the whole wave
+                    double vv[kB], cf[kB];
+#pragma unroll
+                    for (int u = 0; u < kB; ++u) {
+                        const int j = jb + u, sh = 16 * (j & 1);
+                        const uint32_t w = ent[gi][j >> 1];
+                        vv[u] = *reinterpret_cast<const double *>(rb + ((w >> sh) & 0xfff8u));
+                        cf[u] = double(int32_t(w << (29 - sh)) >> 29);
+                    }
+#pragma unroll
+                    for (int u = 0; u < kB; ++u) acc += cf[u] * vv[u];
+                }
+            }
+            const int q = red[gi] < 0 ? 0 : (red[gi] >> 7) & 127, m = red[gi] < 0 ? 1 : red[gi] & 127;
+            for (int t = 0; t < steps[gi]; ++t) {
+                const int off = 1 << t;
+                const double o = __shfl_down(acc, off);
+                if ((q & (2 * off - 1)) == 0 && q + off < m) acc += o;
+            }
+            if (red[gi] >= 0 && q == 0) out[red[gi] >> 14] = acc;
+        }
+    }
+};
+
+// Newton residuals of every listed slot still iterating, streaming: the
+// workgroup first collects, NT list positions at a time, the slots of its
+// positions (blockIdx.x, blockIdx.x + gridDim.x, ...) still iterating, then
+// evaluates them one after another with the next slot's k and x loading while
+// the current one's sums run.  Per slot the same arithmetic as newton_rhs_cell.
+// LDS: the RhsResident layout, then f [S].
+template <int kKU, int kGPW>
+__global__ void __launch_bounds__(kRhsStreamThreads) __attribute__((amdgpu_waves_per_eu(4)))
+k_newton_rhs_stream(Slots s, DeviceNet n, int ring, int which) {
+    using RR = RhsResident<kKU, kGPW>;
+    constexpr int NT = kRhsStreamThreads;
+    extern __shared__ double smem[];
+    __shared__ int todo[NT];
+    __shared__ int ntodo;
+    const int tid = threadIdx.x;
+    const int S = n.S, R = n.R;
+    int count;
+    const int32_t *list = slot_list(s, which, ring, count);
+    RR rr;
+    rr.load(n);
+    RR::init_lds(n, smem);
+    double *xs = smem + R + 1, *f = xs + S + 1;
+    const long long stride = (long long)gridDim.x * NT;
+    for (long long base = blockIdx.x; base < count; base += stride) {
+        if (tid == 0) ntodo = 0;
+        __syncthreads();
+        {
+            const long long p = base + (long long)tid * gridDim.x;
+            if (p < count) {
+                const int slot = list[p];
+                if (s.ctl[slot].phase == kIter) todo[atomicAdd(&ntodo, 1)] = slot;
+            }
+        }
+        __syncthreads();
+        const int nt = ntodo;
+        double kr[kKU], xr = 0.0;
+        if (nt > 0) {
+            const int slot = todo[0];
+#pragma unroll
+            for (int u = 0; u < kKU; ++u) kr[u] = tid + u * NT < R ? s.k[size_t(slot) * R + tid + u * NT] : 0.0;
+            if (tid < S) xr = s.x[size_t(slot) * S + tid];
+        }
+        for (int j = 0; j < nt; ++j) {
+            const int slot = todo[j];
+            const double c = s.ctl[slot].c;
+            if (tid < S) xs[tid] = xr;
+            __syncthreads();
+            rr.rates(n, kr, smem);
+            __syncthreads();
+            double psi_i = 0.0, d_i = 0.0;
+            if (tid < S) {
+                psi_i = s.psi[size_t(slot) * S + tid];
+                d_i = s.d[size_t(slot) * S + tid];
+            }
+            if (j + 1 < nt) {
+                const int nx = todo[j + 1];
+#pragma unroll
+                for (int u = 0; u < kKU; ++u)
+                    if (tid + u * NT < R) kr[u] = s.k[size_t(nx) * R + tid + u * NT];
+                if (tid < S) xr = s.x[size_t(nx) * S + tid];
+            }
+            rr.sums(n, smem, f);
+            // the pairs are reloaded (from cache) for the next slot rather than
+            // held through the sums, where registers are scarcest
+            rr.load_pairs(n);
+            __syncthreads();
+            bool nonfinite = false;
+            if (tid < S) {
+                const double fv = f[tid];
+                nonfinite = !isfinite(fv);
+                s.rb[size_t(slot) * S + tid] = c * fv - psi_i - d_i;
+            }
+            nonfinite = __syncthreads_or(nonfinite) != 0;
+            if (tid == 0) {
+                SlotCtl &g = s.ctl[slot];
+                g.n_rhs += 1;
+                if (nonfinite) {
+                    g.n_newton_iter += 1;
+                    g.newton_iter += 1;
+                    g.m_last = g.newton_iter;
+                    g.phase = kFailed;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
 // Newton corrections of every listed slot still iterating (persistent).  In an
 // FP32-LU engine the plain FP32 variant also takes the slots whose factors are
 // FP64 (same LDS), so that they run beside the FP32 ones rather than in a
@@ -1434,73 +1651,21 @@ k_rhs_only(DeviceNet n, const double *k, const double *x, double *f) {
 }
 
 // The standalone right-hand side, streaming: each workgroup walks the cells
-// blockIdx.x, blockIdx.x + gridDim.x, ...  The reactant pairs and each wave's
-// lane groups of the species sums (two 16-bit entries a register) stay in
-// registers for the whole launch, so the sums read LDS only; the next cell's
-// k and x are loaded into registers while the current cell's sums run, so
-// their memory latency hides behind the LDS work.  The lanes sum the entries
-// of species_gather in the same order, with the padding read from a zero
-// after the rates instead of being skipped (it adds +0), so no entry needs a
-// test.  LDS: rate [R], a zero, x [S], a one (the second factor of a
-// one-reactant rate).  A resident entry is the rate's byte offset | nu in 3
-// bits, two's complement.  Requires S <= kRhsStreamThreads, R < 8191, at
-// most kGPW * 8 lane groups of at most kRhsResidentLen entries, and R <= kKU
-// * kRhsStreamThreads (launch_rhs checks; other networks take k_rhs_only).
-constexpr int kRhsStreamThreads = 512;
+// blockIdx.x, blockIdx.x + gridDim.x, ...; the next cell's k and x are loaded
+// into registers while the current cell's sums run (RhsResident).
 template <int kKU, int kGPW>
 __global__ void __launch_bounds__(kRhsStreamThreads) __attribute__((amdgpu_waves_per_eu(4)))
 k_rhs_stream(DeviceNet n, long long C, const double *__restrict__ k, const double *__restrict__ x,
              double *__restrict__ f) {
-    constexpr int NT = kRhsStreamThreads, NW = NT / 64, kE = kRhsResidentLen / 2;
-    constexpr int kB = kGPW * kKU >= 16 ? 4 : 8;   // LDS reads in flight per lane, as registers allow
+    using RR = RhsResident<kKU, kGPW>;
+    constexpr int NT = kRhsStreamThreads;
     extern __shared__ double smem[];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    const int tid = threadIdx.x;
     const int S = n.S, R = n.R;
-    double *rate = smem, *xs = smem + R + 1;
-    // reactant pairs as LDS byte offsets into xs (the one at xs[S] for none)
-    uint32_t ab[kKU];
-#pragma unroll
-    for (int u = 0; u < kKU; ++u) {
-        const int r = tid + u * NT;
-        const int w = r < R ? n.rx_ab[r] : 0;
-        const int a = w & 0xffff, b = (w >> 16) & 0xffff;
-        ab[u] = uint32_t(a * 8) | (uint32_t(b == 0xffff ? S : b) * 8u << 16);
-    }
-    uint32_t ent[kGPW][kE];
-    int red[kGPW], L[kGPW], steps[kGPW];
-    const uint32_t pad = uint32_t(R) << 3 | 1u;   // +1 times the zero after the rates
-#pragma unroll
-    for (int gi = 0; gi < kGPW; ++gi) {
-        const int g = wave + gi * NW;
-        const bool has = g < n.n_sgroup;
-        const int mine = has ? n.sg_lane[g * 64 + lane] : 0;
-        red[gi] = has ? n.sg_red[g * 64 + lane] : -1;
-        const int lw = has ? __builtin_amdgcn_readfirstlane(n.sg_len[g]) : 0;
-        L[gi] = lw & 0xffffff;
-        steps[gi] = lw >> 24;
-        auto conv = [](int32_t w) { return uint32_t(w & ~7) | (uint32_t((w & 7) - 4) & 7u); };
-        if (L[gi] > 0) {
-            // every load in flight at once: indexes past the group's longest
-            // lane are clamped to its last row and their values discarded
-            const int32_t *e = n.sg_ent + n.sg_base[g] + lane;
-            int32_t v[kRhsResidentLen];
-#pragma unroll
-            for (int j = 0; j < kRhsResidentLen; ++j) v[j] = e[min(j, L[gi] - 1) * 64];
-#pragma unroll
-            for (int j = 0; j < kE; ++j) {
-                const uint32_t lo = 2 * j < mine ? conv(v[2 * j]) : pad;
-                const uint32_t hi = 2 * j + 1 < mine ? conv(v[2 * j + 1]) : pad;
-                ent[gi][j] = lo | (hi << 16);
-            }
-        } else {
-#pragma unroll
-            for (int j = 0; j < kE; ++j) ent[gi][j] = pad | (pad << 16);
-        }
-    }
-    if (tid == 0) {
-        rate[R] = 0.0;
-        xs[S] = 1.0;
-    }
+    RR rr;
+    rr.load(n);
+    RR::init_lds(n, smem);
+    double *xs = smem + R + 1;
     long long c = blockIdx.x;
     double kr[kKU], xr = 0.0;
     if (c < C) {
@@ -1508,62 +1673,19 @@ k_rhs_stream(DeviceNet n, long long C, const double *__restrict__ k, const doubl
         for (int u = 0; u < kKU; ++u) kr[u] = tid + u * NT < R ? k[size_t(c) * R + tid + u * NT] : 0.0;
         if (tid < S) xr = x[size_t(c) * S + tid];
     }
-    const char *xb = reinterpret_cast<const char *>(xs);
-    const char *rb = reinterpret_cast<const char *>(rate);
     for (; c < C; c += gridDim.x) {
         const long long cn = c + gridDim.x;
-        const bool more = cn < C;
         if (tid < S) xs[tid] = xr;
         __syncthreads();
-#pragma unroll
-        for (int u = 0; u < kKU; ++u) {
-            const int r = tid + u * NT;
-            const double xa = *reinterpret_cast<const double *>(xb + (ab[u] & 0xffffu));
-            const double xc = *reinterpret_cast<const double *>(xb + (ab[u] >> 16));
-            if (r < R) rate[r] = kr[u] * xa * xc;
-        }
+        rr.rates(n, kr, smem);
         __syncthreads();
-        if (more) {
+        if (cn < C) {
 #pragma unroll
             for (int u = 0; u < kKU; ++u)
                 if (tid + u * NT < R) kr[u] = k[size_t(cn) * R + tid + u * NT];
             if (tid < S) xr = x[size_t(cn) * S + tid];
         }
-        double *fc = f + size_t(c) * S;
-        // the entries are opaque to the compiler from one cell to the next, so
-        // that it keeps them packed instead of hoisting what it derives from
-        // them (offsets, coefficients) out of the cell loop into registers
-#pragma unroll
-        for (int gi = 0; gi < kGPW; ++gi)
-#pragma unroll
-            for (int j = 0; j < kE; ++j) asm volatile("" : "+v"(ent[gi][j]));
-#pragma unroll
-        for (int gi = 0; gi < kGPW; ++gi) {
-            if (L[gi] == 0) continue;
-            double acc = 0.0;
-#pragma unroll
-            for (int jb = 0; jb < kRhsResidentLen; jb += kB) {
-                if (jb < L[gi]) {   // the same for the whole wave
-                    double vv[kB], cf[kB];
-#pragma unroll
-                    for (int u = 0; u < kB; ++u) {
-                        const int j = jb + u, sh = 16 * (j & 1);
-                        const uint32_t w = ent[gi][j >> 1];
-                        vv[u] = *reinterpret_cast<const double *>(rb + ((w >> sh) & 0xfff8u));
-                        cf[u] = double(int32_t(w << (29 - sh)) >> 29);
-                    }
-#pragma unroll
-                    for (int u = 0; u < kB; ++u) acc += cf[u] * vv[u];
-                }
-            }
-            const int q = red[gi] < 0 ? 0 : (red[gi] >> 7) & 127, m = red[gi] < 0 ? 1 : red[gi] & 127;
-            for (int t = 0; t < steps[gi]; ++t) {
-                const int off = 1 << t;
-                const double o = __shfl_down(acc, off);
-                if ((q & (2 * off - 1)) == 0 && q + off < m) acc += o;
-            }
-            if (red[gi] >= 0 && q == 0) fc[red[gi] >> 14] = acc;
-        }
+        rr.sums(n, smem, f + size_t(c) * S);
         __syncthreads();
     }
 }
@@ -1730,6 +1852,26 @@ size_t factor_lds(const DeviceNet &n, int prec) {
     return lu_work_lds(n.NP, prec) + sizeof(double) * size_t(n.S);   // factorisation, then x_J
 }
 
+// The streaming right-hand sides' instantiation for a network: lanes groups
+// per wave (1 or 2) and reactions per thread (ku), or false when the network
+// does not fit them.
+static bool rhs_stream_shape(const DeviceNet &n, int &ku, int &gpw) {
+    constexpr int NW = kRhsStreamThreads / 64;
+    if (n.S > kRhsStreamThreads || n.R >= 8191 || n.sg_maxlen > kRhsResidentLen || n.n_sgroup > 2 * NW) return false;
+    gpw = n.n_sgroup <= NW ? 1 : 2;
+    const int need = (n.R + kRhsStreamThreads - 1) / kRhsStreamThreads;
+    ku = need <= 2 ? 2 : need <= 4 ? 4 : need <= 8 ? 8 : need <= 12 ? 12 : 16;
+    return !(gpw == 2 && ku > 12);   // <16, 2> would spill
+}
+
+#define ABDF_RHS_STREAM_PICK(K)                                                                              \
+    (gpw == 1 ? (ku == 2 ? (const void *)&K<2, 1> : ku == 4 ? (const void *)&K<4, 1> : ku == 8 ? (const void *)&K<8, 1> \
+                 : ku == 12 ? (const void *)&K<12, 1> : (const void *)&K<16, 1>)                                         \
+              : (ku == 2 ? (const void *)&K<2, 2> : ku == 4 ? (const void *)&K<4, 2> : ku == 8 ? (const void *)&K<8, 2> \
+                 : (const void *)&K<12, 2>))
+
+static size_t newton_rhs_stream_lds(const DeviceNet &n) { return sizeof(double) * (2 * size_t(n.S) + n.R + 2); }
+
 int resident_per_cu(int which, int prec, size_t lds) {
     int nb = 0;
     hipError_t e;
@@ -1785,8 +1927,26 @@ hipError_t launch_factor(const Slots &s, const DeviceNet &n, int ring, int grid,
 hipError_t launch_newton_rhs(const Slots &s, const DeviceNet &n, int ring, int which, int grid, size_t lds,
                              hipStream_t st) {
     if (grid == 0) return hipSuccess;
+    int ku = 0, gpw = 0;
+    if (rhs_stream_shape(n, ku, gpw)) {
+        Slots ss = s;
+        DeviceNet nn = n;
+        int rr = ring, ww = which;
+        void *args[] = {&ss, &nn, &rr, &ww};
+        return hipLaunchKernel(ABDF_RHS_STREAM_PICK(k_newton_rhs_stream), dim3(grid), dim3(kRhsStreamThreads), args,
+                               newton_rhs_stream_lds(n), st);
+    }
     hipLaunchKernelGGL(k_newton_rhs, dim3(grid), dim3(kRhsThreads), lds, st, s, n, ring, which);
     return LAUNCH_CHECK();
+}
+
+int newton_rhs_resident_per_cu(const DeviceNet &n, int prec, size_t lds) {
+    int ku = 0, gpw = 0;
+    if (!rhs_stream_shape(n, ku, gpw)) return resident_per_cu(1, prec, lds);
+    int nb = 0;
+    const hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, ABDF_RHS_STREAM_PICK(k_newton_rhs_stream),
+                                                                      kRhsStreamThreads, newton_rhs_stream_lds(n));
+    return (e == hipSuccess && nb > 0) ? nb : 1;
 }
 
 hipError_t launch_newton_fused(const Slots &s, const DeviceNet &n, int ring, int which, int grid, size_t lds,
@@ -1867,41 +2027,25 @@ hipError_t launch_rates(const DeviceNet &n, const PhysArgs &p, long long cells, 
     return LAUNCH_CHECK();
 }
 
-template <int kKU, int kGPW>
-static hipError_t launch_rhs_stream(const DeviceNet &n, long long cells, const double *k, const double *x, double *f,
-                                    size_t lds, hipStream_t st) {
-    int dev = 0, ncu = 0, nb = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-    if (e == hipSuccess)
-        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_rhs_stream<kKU, kGPW>, kRhsStreamThreads, lds);
-    if (e != hipSuccess) return e;
-    const long long grid = std::min<long long>(cells, std::max(1LL, (long long)nb * ncu));
-    hipLaunchKernelGGL((k_rhs_stream<kKU, kGPW>), dim3(unsigned(grid)), dim3(kRhsStreamThreads), lds, st, n, cells, k,
-                       x, f);
-    return LAUNCH_CHECK();
-}
-
 hipError_t launch_rhs(const DeviceNet &n, long long cells, const double *k, const double *x, double *f, hipStream_t st) {
-    const size_t lds = sizeof(double) * (size_t(n.S) + n.R);
-    constexpr int NW = kRhsStreamThreads / 64;
-    const int ku = (n.R + kRhsStreamThreads - 1) / kRhsStreamThreads;
-    if (n.S <= kRhsStreamThreads && n.R < 8191 && n.sg_maxlen <= kRhsResidentLen) {
+    int ku = 0, gpw = 0;
+    if (rhs_stream_shape(n, ku, gpw)) {
         const size_t lds = sizeof(double) * (size_t(n.S) + n.R + 2);
-        if (n.n_sgroup <= NW) {
-            if (ku <= 2) return launch_rhs_stream<2, 1>(n, cells, k, x, f, lds, st);
-            if (ku <= 4) return launch_rhs_stream<4, 1>(n, cells, k, x, f, lds, st);
-            if (ku <= 8) return launch_rhs_stream<8, 1>(n, cells, k, x, f, lds, st);
-            if (ku <= 12) return launch_rhs_stream<12, 1>(n, cells, k, x, f, lds, st);
-            return launch_rhs_stream<16, 1>(n, cells, k, x, f, lds, st);
-        }
-        if (n.n_sgroup <= 2 * NW && ku <= 12) {
-            if (ku <= 2) return launch_rhs_stream<2, 2>(n, cells, k, x, f, lds, st);
-            if (ku <= 4) return launch_rhs_stream<4, 2>(n, cells, k, x, f, lds, st);
-            if (ku <= 8) return launch_rhs_stream<8, 2>(n, cells, k, x, f, lds, st);
-            return launch_rhs_stream<12, 2>(n, cells, k, x, f, lds, st);
-        }
+        const void *fn = ABDF_RHS_STREAM_PICK(k_rhs_stream);
+        int dev = 0, ncu = 0, nb = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kRhsStreamThreads, lds);
+        if (e != hipSuccess) return e;
+        const long long grid = std::min<long long>(cells, std::max(1LL, (long long)nb * ncu));
+        DeviceNet nn = n;
+        long long C = cells;
+        const double *kk = k, *xx = x;
+        double *ff = f;
+        void *args[] = {&nn, &C, &kk, &xx, &ff};
+        return hipLaunchKernel(fn, dim3(unsigned(grid)), dim3(kRhsStreamThreads), args, lds, st);
     }
+    const size_t lds = sizeof(double) * (size_t(n.S) + n.R);
     hipLaunchKernelGGL(k_rhs_only, dim3(cells), dim3(kRhsThreads), lds, st, n, k, x, f);
     return LAUNCH_CHECK();
 }

@@ -115,6 +115,9 @@ size_t lu_bytes(int NP, int prec);
 // Newton solve (2), transposed adjoint solve (3) or refining FP32 Newton
 // solve (4) kernel.
 int resident_per_cu(int which, int prec, size_t lds);
+// Workgroups per CU of the kernel launch_newton_rhs runs for this network
+// (lds: the LDS of the non-streaming kernel, used when it is that one).
+int newton_rhs_resident_per_cu(const DeviceNet &n, int prec, size_t lds);
 hipError_t launch_selftest(int *bad, hipStream_t st);
 hipError_t launch_fill_i32(int32_t *v, int32_t value, int n, hipStream_t st);
 size_t lu_work_lds(int NP, int prec);
