@@ -205,8 +205,9 @@ def run_serve(args):
 def rhs_standalone(net, g, inp, n_rep=20):
     """The right-hand-side kernel on its own (abdf_rhs over the batch's cells,
     rates from abdf_rates, abundances x0): algorithmic bytes (x and k read, f
-    written) per average launch, each launch bracketed by HIP events on its
-    stream inside the library (the rhs_eval timer family)."""
+    written) per average launch, each launch's start and end recorded as HIP
+    events by its own dispatch inside the library (the rhs_eval timer
+    family)."""
     import torch
     import paper_2511_10558_amd as ab
     k = ab.rates(g, *inp[:5])
@@ -223,7 +224,8 @@ def rhs_standalone(net, g, inp, n_rep=20):
     ms = total_ms / max(1, launches)
     byt = C * (2 * net.n_species + net.n_reactions) * 8
     ach = byt / (ms * 1e-3) / 1e9
-    return {"kernel": "k_rhs_only (abdf_rhs, standalone)", "bound": "hbm", "achieved": round(ach, 1),
+    # every network bench.py offers fits the streaming kernel
+    return {"kernel": "k_rhs_stream (abdf_rhs, standalone)", "bound": "hbm", "achieved": round(ach, 1),
             "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
             "cells": C, "avg_launch_ms": round(ms, 4),
             "work": f"(2 S + R) x 8 B = {(2 * net.n_species + net.n_reactions) * 8} B per cell-evaluation"}

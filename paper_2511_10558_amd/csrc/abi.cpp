@@ -504,16 +504,17 @@ abdf_status abdf_rhs(const abdf_network *net, int64_t n_cells, const double *k, 
     if (sizeof(double) * (size_t(dn->S) + dn->R) > abdf::kMaxLds)
         return fail(ABDF_E_ARG, "network too large for one workgroup's LDS");
     hipStream_t st = static_cast<hipStream_t>(stream);
-    // with the timers on, the launch alone is bracketed by events
+    abdf::RhsPlan plan;
+    hipError_t e = abdf::plan_rhs(*dn, n_cells, plan);
+    if (e != hipSuccess) return fail(ABDF_E_DEVICE, std::string("abdf_rhs: ") + hipGetErrorString(e));
+    // with the timers on, the dispatch records events at the kernel's start and end
     hipEvent_t ev[2] = {nullptr, nullptr};
-    if (abdf::Profiler::on() && (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess ||
-                                 hipEventRecord(ev[0], st) != hipSuccess)) {
-        for (hipEvent_t e : ev)
-            if (e) (void)hipEventDestroy(e);
+    if (abdf::Profiler::on() && (hipEventCreate(&ev[0]) != hipSuccess || hipEventCreate(&ev[1]) != hipSuccess)) {
+        for (hipEvent_t evt : ev)
+            if (evt) (void)hipEventDestroy(evt);
         ev[0] = ev[1] = nullptr;
     }
-    hipError_t e = abdf::launch_rhs(*dn, n_cells, k, x, f_out, st);
-    if (e == hipSuccess && ev[0]) e = hipEventRecord(ev[1], st);
+    e = abdf::launch_rhs_planned(plan, *dn, n_cells, k, x, f_out, st, ev[0], ev[1]);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e == hipSuccess && ev[0]) {
         float ms = 0.f;

@@ -2027,27 +2027,38 @@ hipError_t launch_rates(const DeviceNet &n, const PhysArgs &p, long long cells, 
     return LAUNCH_CHECK();
 }
 
-hipError_t launch_rhs(const DeviceNet &n, long long cells, const double *k, const double *x, double *f, hipStream_t st) {
+hipError_t plan_rhs(const DeviceNet &n, long long cells, RhsPlan &p) {
     int ku = 0, gpw = 0;
+    p = RhsPlan{};
     if (rhs_stream_shape(n, ku, gpw)) {
-        const size_t lds = sizeof(double) * (size_t(n.S) + n.R + 2);
-        const void *fn = ABDF_RHS_STREAM_PICK(k_rhs_stream);
+        p.fn = ABDF_RHS_STREAM_PICK(k_rhs_stream);
+        p.lds = sizeof(double) * (size_t(n.S) + n.R + 2);
+        p.threads = kRhsStreamThreads;
         int dev = 0, ncu = 0, nb = 0;
         hipError_t e = hipGetDevice(&dev);
         if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
-        if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, kRhsStreamThreads, lds);
+        if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, p.fn, kRhsStreamThreads, p.lds);
         if (e != hipSuccess) return e;
-        const long long grid = std::min<long long>(cells, std::max(1LL, (long long)nb * ncu));
-        DeviceNet nn = n;
-        long long C = cells;
-        const double *kk = k, *xx = x;
-        double *ff = f;
-        void *args[] = {&nn, &C, &kk, &xx, &ff};
-        return hipLaunchKernel(fn, dim3(unsigned(grid)), dim3(kRhsStreamThreads), args, lds, st);
+        p.grid = std::min<long long>(cells, std::max(1LL, (long long)nb * ncu));
+        return hipSuccess;
     }
-    const size_t lds = sizeof(double) * (size_t(n.S) + n.R);
-    hipLaunchKernelGGL(k_rhs_only, dim3(cells), dim3(kRhsThreads), lds, st, n, k, x, f);
-    return LAUNCH_CHECK();
+    p.fn = reinterpret_cast<const void *>(&k_rhs_only);
+    p.lds = sizeof(double) * (size_t(n.S) + n.R);
+    p.threads = kRhsThreads;
+    p.grid = cells;
+    return hipSuccess;
+}
+
+hipError_t launch_rhs_planned(const RhsPlan &p, const DeviceNet &n, long long cells, const double *k, const double *x,
+                              double *f, hipStream_t st, hipEvent_t start, hipEvent_t stop) {
+    DeviceNet nn = n;
+    long long C = cells;
+    const double *kk = k, *xx = x;
+    double *ff = f;
+    void *args_only[] = {&nn, &kk, &xx, &ff};
+    void *args_stream[] = {&nn, &C, &kk, &xx, &ff};
+    void **args = p.fn == reinterpret_cast<const void *>(&k_rhs_only) ? args_only : args_stream;
+    return hipExtLaunchKernel(p.fn, dim3(unsigned(p.grid)), dim3(p.threads), args, p.lds, st, start, stop, 0);
 }
 
 hipError_t launch_newton_matrix(const DeviceNet &n, long long cells, const double *k, const double *x,

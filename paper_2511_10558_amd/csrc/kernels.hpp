@@ -101,7 +101,19 @@ inline size_t adj_lds(const DeviceNet &n) { return sizeof(double) * (2 * size_t(
 inline size_t adj_solve_lds(const DeviceNet &n) { return sizeof(double) * (2 * size_t(n.NP) + 5 * 64 + 64 * 65); }
 
 hipError_t launch_rates(const DeviceNet &n, const PhysArgs &p, long long cells, double *k, hipStream_t st);
-hipError_t launch_rhs(const DeviceNet &n, long long cells, const double *k, const double *x, double *f, hipStream_t st);
+// The standalone right-hand side: the kernel and grid for a batch (host
+// queries only), then its launch.
+struct RhsPlan {
+    const void *fn = nullptr;
+    long long grid = 0;
+    int threads = 0;
+    size_t lds = 0;
+};
+hipError_t plan_rhs(const DeviceNet &n, long long cells, RhsPlan &p);
+// start, stop: events (or null) the dispatch itself records at the kernel's
+// start and end.
+hipError_t launch_rhs_planned(const RhsPlan &p, const DeviceNet &n, long long cells, const double *k, const double *x,
+                              double *f, hipStream_t st, hipEvent_t start = nullptr, hipEvent_t stop = nullptr);
 // jv: scratch of cells * max(nnzJ, 1) doubles (the Jacobian nonzeros)
 hipError_t launch_newton_matrix(const DeviceNet &n, long long cells, const double *k, const double *x,
                                 const double *c, double *M, double *jv, hipStream_t st);

@@ -136,7 +136,7 @@ def trace_table(tdir, log, name, title, command):
                 f"work {json.dumps(line['work'])}."]
     if "roofline_rhs" in line:
         rr = line["roofline_rhs"]
-        out.append(f"Standalone right-hand side (k_rhs_only): {rr['achieved']} GB/s of algorithmic traffic "
+        out.append(f"Standalone right-hand side ({rr['kernel'].split()[0]}): {rr['achieved']} GB/s of algorithmic traffic "
                    f"({rr['work']}), {rr['avg_launch_ms']} ms per launch over {rr['cells']} cells.")
     open(os.path.join(PROFILES, name + ".md"), "w").write("\n".join(out) + "\n")
     print("\n".join(out))
@@ -205,7 +205,7 @@ def main():
                     f"work {json.dumps(tl['work'])}."]
         if "roofline_rhs" in tl:
             rr = tl["roofline_rhs"]
-            out.append(f"Standalone right-hand side (k_rhs_only, the 21 launches above, timed by HIP events "
+            out.append(f"Standalone right-hand side ({rr['kernel'].split()[0]}, the 21 launches above, timed by HIP events "
                        f"in the same run): {rr['achieved']} GB/s of algorithmic traffic ({rr['work']}), "
                        f"{rr['avg_launch_ms']} ms per launch over {rr['cells']} cells, {rr['frac']} of 8 TB/s.")
     f = counters(fetch)
