@@ -625,10 +625,13 @@ k_newton_rhs(Slots s, DeviceNet n, int ring, int which) {
 // reads a -0.0 placed after the rates instead of being skipped (adding -0.0
 // changes no sum, signed zeros included), so no entry needs a test, and a
 // one-reactant rate takes a 1.0 placed after x as its second factor.
-// LDS: rate [R], -0.0, x [S], 1.0.  A resident entry is the rate's byte offset
-// | nu in 3 bits, two's complement.  Requires S <= kRhsStreamThreads, R <
-// 8191, at most kGPW * 8 lane groups of at most kRhsResidentLen entries, and R
-// <= kKU * kRhsStreamThreads (rhs_stream_shape checks).
+// LDS: rate [R], -0.0, x [S], 1.0, from the start of the dynamic block.  A
+// resident entry is the rate's LDS address | nu in 3 bits, two's complement,
+// so the sums read LDS at the entry's own address (the kernels have no static
+// LDS, so the dynamic block starts at address 0 and every address fits 16
+// bits).  Requires S <= kRhsStreamThreads, R < 8191, at most kGPW * 8 lane
+// groups of at most kRhsResidentLen entries, and R <= kKU * kRhsStreamThreads
+// (rhs_stream_shape checks).
 constexpr int kRhsStreamThreads = 512;
 template <int kKU, int kGPW>
 struct RhsResident {
@@ -651,12 +654,14 @@ struct RhsResident {
         }
     }
 
-    __device__ __forceinline__ void load(const DeviceNet &n) {
+    __device__ __forceinline__ void load(const DeviceNet &n, const double *smem) {
         const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
         const int R = n.R;
         load_pairs(n);
-        const uint32_t pad = uint32_t(R) << 3 | 1u;   // +1 times the -0.0 after the rates
-        auto conv = [](int32_t w) { return uint32_t(w & ~7) | (uint32_t((w & 7) - 4) & 7u); };
+        // the LDS address of rate[0]
+        const uint32_t lds0 = uint32_t(size_t((const __attribute__((address_space(3))) char *)smem));
+        const uint32_t pad = (lds0 + uint32_t(R) * 8u) | 1u;   // +1 times the -0.0 after the rates
+        auto conv = [lds0](int32_t w) { return (lds0 + uint32_t(w & ~7)) | (uint32_t((w & 7) - 4) & 7u); };
 #pragma unroll
         for (int gi = 0; gi < kGPW; ++gi) {
             const int g = wave + gi * NW;
@@ -714,7 +719,6 @@ struct RhsResident {
         for (int gi = 0; gi < kGPW; ++gi)
 #pragma unroll
             for (int j = 0; j < kE; ++j) asm volatile("" : "+v"(ent[gi][j]));
-        const char *rb = reinterpret_cast<const char *>(smem);
 #pragma unroll
         for (int gi = 0; gi < kGPW; ++gi) {
             if (L[gi] == 0) continue;
@@ -727,7 +731,7 @@ struct RhsResident {
                     for (int u = 0; u < kB; ++u) {
                         const int j = jb + u, sh = 16 * (j & 1);
                         const uint32_t w = ent[gi][j >> 1];
-                        vv[u] = *reinterpret_cast<const double *>(rb + ((w >> sh) & 0xfff8u));
+                        vv[u] = *(const __attribute__((address_space(3))) double *)size_t((w >> sh) & 0xfff8u);
                         cf[u] = double(int32_t(w << (29 - sh)) >> 29);
                     }
 #pragma unroll
@@ -750,23 +754,23 @@ struct RhsResident {
 // positions (blockIdx.x, blockIdx.x + gridDim.x, ...) still iterating, then
 // evaluates them one after another with the next slot's k and x loading while
 // the current one's sums run.  Per slot the same arithmetic as newton_rhs_cell.
-// LDS: the RhsResident layout, then f [S].
+// LDS: the RhsResident layout, then f [S], then the list of slots to evaluate
+// [NT], its length and a non-finite flag (no static LDS: see RhsResident).
 template <int kKU, int kGPW>
 __global__ void __launch_bounds__(kRhsStreamThreads) __attribute__((amdgpu_waves_per_eu(4)))
 k_newton_rhs_stream(Slots s, DeviceNet n, int ring, int which) {
     using RR = RhsResident<kKU, kGPW>;
     constexpr int NT = kRhsStreamThreads;
     extern __shared__ double smem[];
-    __shared__ int todo[NT];
-    __shared__ int ntodo;
     const int tid = threadIdx.x;
     const int S = n.S, R = n.R;
     int count;
     const int32_t *list = slot_list(s, which, ring, count);
     RR rr;
-    rr.load(n);
+    rr.load(n, smem);
     RR::init_lds(n, smem);
     double *xs = smem + R + 1, *f = xs + S + 1;
+    int *todo = reinterpret_cast<int *>(f + S), &ntodo = todo[NT], &bad = todo[NT + 1];
     const long long stride = (long long)gridDim.x * NT;
     for (long long base = blockIdx.x; base < count; base += stride) {
         if (tid == 0) ntodo = 0;
@@ -790,6 +794,7 @@ k_newton_rhs_stream(Slots s, DeviceNet n, int ring, int which) {
         for (int j = 0; j < nt; ++j) {
             const int slot = todo[j];
             const double c = s.ctl[slot].c;
+            if (tid == 0) bad = 0;
             if (tid < S) xs[tid] = xr;
             __syncthreads();
             rr.rates(n, kr, smem);
@@ -811,17 +816,16 @@ k_newton_rhs_stream(Slots s, DeviceNet n, int ring, int which) {
             // held through the sums, where registers are scarcest
             rr.load_pairs(n);
             __syncthreads();
-            bool nonfinite = false;
             if (tid < S) {
                 const double fv = f[tid];
-                nonfinite = !isfinite(fv);
+                if (!isfinite(fv)) bad = 1;
                 s.rb[size_t(slot) * S + tid] = c * fv - psi_i - d_i;
             }
-            nonfinite = __syncthreads_or(nonfinite) != 0;
-            if (tid == 0) {
+            __syncthreads();
+            if (tid == 0) {   // only thread 0 reads the flag: it clears it next
                 SlotCtl &g = s.ctl[slot];
                 g.n_rhs += 1;
-                if (nonfinite) {
+                if (bad) {
                     g.n_newton_iter += 1;
                     g.newton_iter += 1;
                     g.m_last = g.newton_iter;
@@ -1663,7 +1667,7 @@ k_rhs_stream(DeviceNet n, long long C, const double *__restrict__ k, const doubl
     const int tid = threadIdx.x;
     const int S = n.S, R = n.R;
     RR rr;
-    rr.load(n);
+    rr.load(n, smem);
     RR::init_lds(n, smem);
     double *xs = smem + R + 1;
     long long c = blockIdx.x;
@@ -1870,7 +1874,9 @@ static bool rhs_stream_shape(const DeviceNet &n, int &ku, int &gpw) {
               : (ku == 2 ? (const void *)&K<2, 2> : ku == 4 ? (const void *)&K<4, 2> : ku == 8 ? (const void *)&K<8, 2> \
                  : (const void *)&K<12, 2>))
 
-static size_t newton_rhs_stream_lds(const DeviceNet &n) { return sizeof(double) * (2 * size_t(n.S) + n.R + 2); }
+static size_t newton_rhs_stream_lds(const DeviceNet &n) {
+    return sizeof(double) * (2 * size_t(n.S) + n.R + 2) + sizeof(int) * (kRhsStreamThreads + 2);
+}
 
 int resident_per_cu(int which, int prec, size_t lds) {
     int nb = 0;
