@@ -330,6 +330,28 @@ def test_failure_codes_match_the_oracle(ab, dev):
     assert rel_err_above(x[2], refs[2].x) <= TOL
 
 
+def test_failure_codes_in_a_two_stream_batch(ab, dev):
+    # the cells of test_failure_codes_match_the_oracle, twelve copies each: 36
+    # slots run the two-stream attempt (streaming residual beside the
+    # factorisation), where a corrector that meets a non-finite residual fails
+    # through the residual kernel's own flag; every copy ends as its cell
+    # does alone (fused path), bit for bit
+    net = tiny_nets.association(1e-9)
+    cell = dict(T=300.0, n_H=1e4, A_V=0.0, zeta=1e-17, G0=1.0)
+    kp, a0 = chem.rate_coefficients(net, **cell)[0], -1e-4
+    t_star = 1.0 / (kp * abs(a0))
+    g = ab.Network.from_text(net.to_text())
+    base = [[a0, a0, 0.0], [1e200, 1e200, 0.0], [1e-4, 2e-4, 0.0]]
+    alone_x, alone_s, alone_st = solve_cells(ab, g, _cells(net, cell, base, 2 * t_star), dev)
+    assert list(alone_s) == [bdf.STEP_TOO_SMALL, bdf.NONFINITE, bdf.OK]
+    x, status, stats = solve_cells(ab, g, _cells(net, cell, base * 12, 2 * t_star), dev)
+    for c in range(36):
+        j = c % 3
+        assert status[c] == alone_s[j]
+        assert np.array_equal(x[c], alone_x[j])
+        assert stats["n_steps"][c] == alone_st["n_steps"][j] and stats["t"][c] == alone_st["t"][j]
+
+
 def _expansion_integral(t, t_c, p):
     return t_c * np.log1p(t / t_c) if p == 1.0 else t_c * ((1.0 + t / t_c) ** (1.0 - p) - 1.0) / (1.0 - p)
 
