@@ -80,11 +80,14 @@ def test_rhs_matches_oracle(ab, dev, name):
         assert np.all(np.abs(f[c] - ref) <= bound + 1e-300)
 
 
-def test_rhs_of_a_species_wider_than_a_wave(ab, dev):
-    # H takes part in 2100 reactions: 64 lanes of 33 entries, more than
-    # kRhsSegment per lane; Z in none, so its f is exactly zero
+@pytest.mark.parametrize("n_rx", [2100, 3000])
+def test_rhs_of_a_species_wider_than_a_wave(ab, dev, n_rx):
+    # H takes part in n_rx reactions: 64 lanes of 33 (47) entries, more than
+    # kRhsSegment per lane; at 47 the lanes are too long to be held in
+    # registers, so the per-cell kernel runs instead of the streaming one.
+    # Z takes part in none, so its f is exactly zero
     from tests import tiny_nets
-    net = tiny_nets.hub()
+    net = tiny_nets.hub(n_rx)
     g = ab.Network.from_text(net.to_text())
     rng = np.random.default_rng(15)
     conds = [dict(T=T, n_H=1e4, A_V=2.0, zeta=1.3e-17, G0=1.0) for T in (10.0, 30.0, 100.0, 300.0, 1000.0)]

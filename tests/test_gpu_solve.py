@@ -288,6 +288,33 @@ def test_largest_and_too_large_networks(ab, dev):
     assert e.value.code == 1 and "too large" in str(e.value)
 
 
+def test_network_outside_the_streaming_kernels(ab, dev):
+    # a species in 3000 reactions makes lanes too long for the streaming
+    # right-hand sides, so the solver's residual runs in the per-cell kernel:
+    # 40 cells (the two-stream attempt) match the oracle and two of them
+    # solved alone (one stream, fused Newton) bit for bit
+    net = tiny_nets.hub(3000)
+    g = ab.Network.from_text(net.to_text())
+    rng = np.random.default_rng(3000)
+    n = 40
+    x0 = np.zeros((n, net.n_species))
+    x0[:, net.species.index("H")] = 10 ** rng.uniform(-5, -3, n)
+    x0[:, net.species.index("Z")] = 1e-5
+    for i in range(40):
+        x0[:, net.species.index(f"A{i}")] = 10 ** rng.uniform(-7, -5, n)
+    col = lambda lo, hi: 10 ** rng.uniform(lo, hi, n)
+    cells = synth.Cells(col(1, 2.5), col(3, 5), col(0, 1), col(-17.3, -16.3), col(-0.5, 0.5), x0,
+                        np.full(n, 1e5 * 3.15576e7))
+    x, status, _ = solve_cells(ab, g, cells, dev)
+    assert (status == 0).all()
+    sample = np.array([4, 31])
+    sub = cells.subset(sample)
+    alone, st_a, _ = solve_cells(ab, g, sub, dev)
+    assert (st_a == 0).all() and np.array_equal(alone, x[sample])
+    for j, r in enumerate(oracle_cells(net, sub)):
+        assert r.status == bdf.OK and rel_err_above(alone[j], r.x) <= TOL
+
+
 def test_factorisation_reuse_across_small_c_changes(ab, dev):
     # keeping a factorisation while |c / c_lu - 1| <= 0.3 (corrections scaled by
     # 2 / (1 + c / c_lu)) changes the Newton iteration, not its fixed point: the
