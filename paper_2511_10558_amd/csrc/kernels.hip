@@ -641,8 +641,6 @@ struct RhsResident {
     uint32_t ent[kGPW][kE];
     int red[kGPW], L[kGPW], steps[kGPW];
 
-    __device__ __forceinline__ static size_t lds_doubles(const DeviceNet &n) { return size_t(n.S) + n.R + 2; }
-
     // reactant pairs as LDS byte offsets into x (the 1.0 at x[S] for none)
     __device__ __forceinline__ void load_pairs(const DeviceNet &n) {
 #pragma unroll
