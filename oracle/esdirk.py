@@ -18,8 +18,10 @@ One step from (t_n, x_n) with step h, F_j = f(Y_j), G_j = h F_j:
 each implicit stage solved by the modified Newton iteration of the BDF oracle
 (bdf._newton: the same rate tests and tolerance, at most NEWTON_MAXITER = 10
 iterations) on M = I - h gamma J(x_n),
-with J and the factorisation formed once per step attempt and Y_{i-1} as the
-stage's starting point.  A converged stage gives G_i from its own equation,
+with J and the factorisation formed once per step attempt.  A stage starts
+from its own equation with the previous stage's G in place of G_i,
+Y_i^0 = x_n + sum_{j<i} A[i, j] G_j + gamma G_{i-1}.  A converged stage gives
+G_i from its own equation,
 G_i = (Y_i - x_n - sum_{j<i} A[i, j] G_j) / gamma, so no extra evaluation of f
 is made; x_{n+1} = Y_7 and the next step's F_1 = G_7 / h.
 
@@ -89,9 +91,10 @@ def step(chem, x, F1, h, lu, tol, rtol, atol, stats, maxiter=NEWTON_MAXITER):
         s = np.zeros_like(x)
         for j in range(i):
             s = s + A[i, j] * G[j]
-        psi = y_prev - x - s
-        scale = atol + rtol * np.abs(y_prev)
-        conv, _m, y, d = bdf._newton(chem, lu, c, psi, y_prev, scale, tol, stats, maxiter=maxiter)
+        start = x + s + GAMMA * G[i - 1]
+        psi = start - x - s
+        scale = atol + rtol * np.abs(start)
+        conv, _m, y, d = bdf._newton(chem, lu, c, psi, start, scale, tol, stats, maxiter=maxiter)
         if not conv:
             return False, None, G, None
         G.append((psi + d) / GAMMA)

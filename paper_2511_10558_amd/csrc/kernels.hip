@@ -227,8 +227,9 @@ __constant__ double kRkA[kRkStages][kRkStages] = {
 // Starts stage cs.stage (2..7) of a running slot whose cs (LDS) is current.
 // Stage 2 opens a step attempt: the step budget, the step-size floor and the
 // landing on t_end are checked, and after an accepted step the Jacobian point
-// moves to x_n.  The stage starts from Y_{i-1} (x_n for stage 2) with
-// psi = Y_{i-1} - x_n - sum_{j<i} a_ij G_j and weights atol + rtol |Y_{i-1}|,
+// moves to x_n.  The stage starts from Y_i^0 = x_n + sum_{j<i} a_ij G_j +
+// gamma G_{i-1} (its own equation with the previous stage's G, G_1 = h F_1)
+// with psi = Y_i^0 - x_n - sum_{j<i} a_ij G_j and weights atol + rtol |Y_i^0|,
 // so that the corrector kernels solve Y_i = x_n + sum_j a_ij G_j + h gamma f(Y_i)
 // as a BDF corrector with c = h gamma.  Writes cs back to global memory.
 __device__ __forceinline__ void begin_stage_rk(const Slots &s, int slot, SlotCtl &cs, int ring) {
@@ -267,10 +268,14 @@ __device__ __forceinline__ void begin_stage_rk(const Slots &s, int slot, SlotCtl
     const double h = cs.h;
     const double *a = kRkA[stage - 1];
     for (int i = threadIdx.x; i < S; i += kBlock) {
+        // the stage starts from its own equation with the previous stage's G
+        // in place of its own: x_n + sum_{j<i} a_ij G_j + gamma G_{i-1}
         const double xn = D[i];
-        double sum = a[0] * (h * D[S + i]);
+        const double g1 = h * D[S + i];
+        double sum = a[0] * g1;
         for (int j = 2; j < stage; ++j) sum = sum + a[j - 1] * D[j * S + i];
-        const double xp = first ? xn : x[i];
+        const double gprev = first ? g1 : D[(stage - 1) * S + i];
+        const double xp = (xn + sum) + kRkGamma * gprev;
         x[i] = xp;
         d[i] = 0.0;
         psi[i] = (xp - xn) - sum;
