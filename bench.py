@@ -202,7 +202,7 @@ def run_serve(args):
     print(json.dumps(out))
 
 
-def rhs_standalone(net, g, inp, n_rep=20):
+def rhs_standalone(net, g, inp, net_name, n_rep=20):
     """The right-hand-side kernel on its own (abdf_rhs over the batch's cells,
     rates from abdf_rates, abundances x0): algorithmic bytes (x and k read, f
     written) per average launch, each launch's start and end recorded as HIP
@@ -224,11 +224,19 @@ def rhs_standalone(net, g, inp, n_rep=20):
     ms = total_ms / max(1, launches)
     byt = C * (2 * net.n_species + net.n_reactions) * 8
     ach = byt / (ms * 1e-3) / 1e9
+    # HBM bytes per launch from the counter passes, when they were taken on
+    # this network with the current kernels
+    rec = recorded_traffic()
+    traffic = None
+    if rec is not None and "k_rhs_bytes_per_cell" in rec and rec.get("network") == net_name:
+        traffic = round(rec["k_rhs_bytes_per_cell"] * C)
     # every network bench.py offers fits the streaming kernel
     return {"kernel": "k_rhs_stream (abdf_rhs, standalone)", "bound": "hbm", "achieved": round(ach, 1),
-            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": None,
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4), "traffic": traffic,
             "cells": C, "avg_launch_ms": round(ms, 4),
-            "work": f"(2 S + R) x 8 B = {(2 * net.n_species + net.n_reactions) * 8} B per cell-evaluation"}
+            "work": f"(2 S + R) x 8 B = {(2 * net.n_species + net.n_reactions) * 8} B per cell-evaluation",
+            **({"traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)"}
+               if traffic is not None else {})}
 
 
 def run_adjoint(args):
@@ -642,7 +650,7 @@ def main():
                           "k_factor_tflops": round(nk_lu * lu_flop / max(1e-9, pk["factor"][1] * 1e-3) / 1e12, 3),
                           "kernels": {k: {"launches": v[0], "ms": round(v[1], 3)} for k, v in pk.items()},
                           "max_rel_dev_from_bdf_gpu": max_rel_err(xk.cpu().numpy(), x64)}
-    out["roofline_rhs"] = rhs_standalone(net, g, inp)
+    out["roofline_rhs"] = rhs_standalone(net, g, inp, args.network)
     progress(f"standalone right-hand side: {out['roofline_rhs']['achieved']} GB/s")
     if args.batch_serve_requests > 0 and args.network == "net500":
         # the serving half of the metric: p50/p99 latency, FP32-LU against FP64

@@ -241,10 +241,19 @@ def main():
         max(1, work["newton_iterations"])
     out += ["", f"Per factorisation (k_factor, assembly + LU): {per_lu/2**20:.2f} MiB of HBM traffic; "
                 f"per Newton solve (k_newton_solve): {per_it/2**20:.3f} MiB."]
+    rec = {"source_hash": source_hash(), "network": "net500", "k_factor_bytes_per_lu": per_lu,
+           "k_newton_solve_bytes_per_iteration": per_it}
+    # the standalone right-hand side: its launches cover the run's whole batch
+    cells = json.loads(line)["config"]["cells"]
+    rhs = [(k, n) for k, (n, _) in f.items() if k.startswith("k_rhs_stream") or k.startswith("k_rhs_only")]
+    if rhs:
+        k, n = rhs[0]
+        per_cell = traffic[k] / (n * cells)
+        rec["k_rhs_bytes_per_cell"] = per_cell
+        out.append(f"Standalone right-hand side ({k}): {per_cell / 1e3:.1f} kB of HBM traffic per cell-evaluation "
+                   f"({n} launches over {cells} cells).")
     open(os.path.join(PROFILES, "kernel_stats_net500.md"), "w").write("\n".join(out) + "\n")
-    json.dump({"source_hash": source_hash(), "network": "net500", "k_factor_bytes_per_lu": per_lu,
-               "k_newton_solve_bytes_per_iteration": per_it}, open(os.path.join(PROFILES, "traffic.json"), "w"),
-              indent=1)
+    json.dump(rec, open(os.path.join(PROFILES, "traffic.json"), "w"), indent=1)
     print("\n".join(out))
 
 
